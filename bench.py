@@ -1,0 +1,177 @@
+"""Throughput of the fused difference-free CPF-LBM step on one MI355X.
+
+Workload: Rayleigh-Taylor instability on a 128 x 512 x 128 lattice
+(8,388,608 nodes), heavy fluid on top (At = 0.5), single-mode perturbation
+of amplitude 0.05 Lx, Re = 256, W = 4, sigma = 5e-5, periodic in x and z,
+no-slip walls in y, Courant number 0.997; FP32 collision with the
+populations stored in HBM as FP16 deviations (synthetic initial fields).
+A step is one fused launch (propagation, moments, both collisions, store)
+over the whole lattice; the reported value is MLUPS = nodes x steps /
+(seconds x 1e6), timed with HIP events on the solver's stream with the state
+resident in HBM. The same run also reports the FP32-storage rate.
+
+Prints ONE JSON line (see the keys below).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline; surrogate-vs-LBM speedup at φ L2 err ≤1e-2"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2407_12263_amd/csrc/lbm_kernels.hpp", "paper_2407_12263_amd/csrc/lbm.hip"]
+COUNTERS_FILE = "profiles/step_kernel_rayleigh_taylor_128x512x128_fp16.counters.txt"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(launch_bytes_alg: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, COUNTERS_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_solver(sol, steps: int, warmup: int):
+    import torch
+    sol.step(warmup)
+    torch.cuda.synchronize()
+    stream = sol.stream
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        start.record(stream)
+        sol.step(steps)
+        end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / 1e3  # seconds
+
+
+def cpu_baseline(w, steps: int = 2):
+    """The FP64 CPU oracle, untuned, on the full lattice of the same workload
+    for a few steps (bounded sample); returns (MLUPS, threads, seconds)."""
+    import oracle
+    oracle.build(force=False)
+    P = oracle.OracleParams(**w.params())
+    o = oracle.Oracle(P, w.phi0, w.u0, w.p0)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    threads = oracle.num_threads()
+    del o
+    return w.N * steps / dt / 1e6, threads, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--storage", default="fp16", choices=["fp16", "bf16", "fp32", "fp64"])
+    ap.add_argument("--secondary", default="fp32", help="comma list of extra storage modes")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the step would shard by z-slabs with one halo exchange per step)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2407_12263_amd import inputs, lbm
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    lbm.load_library()
+
+    w = inputs.rayleigh_taylor()  # 128 x 512 x 128, Re = 256, At = 0.5
+    results = {}
+    modes = [args.storage] + [m for m in args.secondary.split(",") if m and m != args.storage]
+    for mode in modes:
+        print(f"[bench] {w.name} storage={mode} warmup={args.warmup} steps={args.steps}",
+              file=sys.stderr, flush=True)
+        sol = lbm.Solver(dict(w.params(), precision=mode), w.phi0, w.u0, w.p0)
+        secs = time_solver(sol, args.steps, args.warmup)
+        d = sol.diagnostics()
+        ok = all(map(lambda v: v == v, [d["sum_phi"], d["umax"]]))
+        results[mode] = dict(seconds=secs, ms_per_step=secs * 1e3 / args.steps,
+                             mlups=w.N * args.steps / secs / 1e6, finite=ok,
+                             sum_phi=d["sum_phi"], umax=d["umax"])
+        del sol
+        torch.cuda.synchronize()
+
+    main_r = results[args.storage]
+    bpl = lbm.BYTES_PER_LU[args.storage]
+    launch_bytes = bpl * w.N
+    launch_s = main_r["seconds"] / args.steps
+    achieved = launch_bytes / launch_s / 1e9
+    traffic = measured_traffic(launch_bytes)
+    line = {
+        "metric": METRIC,
+        "value": round(main_r["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_r["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name} rayleigh-taylor At=0.5 Re=256 W=4 c=0.997",
+                   "grid": [w.nx, w.ny, w.nz], "nodes": w.N, "storage": args.storage,
+                   "walls": "y", "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes_per_launch": launch_bytes,
+                     "kernel": "step_kernel (fused propagate+moments+collide+store)"},
+        "secondary": {m: {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 5),
+                          "hbm_frac": round(lbm.BYTES_PER_LU[m] * w.N / (r["seconds"] / args.steps)
+                                            / 1e9 / HBM_PEAK_GBS, 4)}
+                      for m, r in results.items() if m != args.storage},
+        "checks": {m: {"finite": r["finite"], "sum_phi": r["sum_phi"], "umax": r["umax"]}
+                   for m, r in results.items()},
+    }
+    if not args.no_cpu_baseline:
+        print(f"[bench] cpu baseline: oracle FP64, {args.cpu_steps} steps on the full lattice",
+              file=sys.stderr, flush=True)
+        mlups, threads, dt = cpu_baseline(w, args.cpu_steps)
+        line["cpu_baseline"] = {"value": round(mlups, 3), "unit": "MLUPS", "cores": threads,
+                                "kind": "oracle",
+                                "sample": f"{args.cpu_steps} steps of the full {w.nx}x{w.ny}x{w.nz} "
+                                          f"lattice in FP64 ({dt:.1f} s)"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

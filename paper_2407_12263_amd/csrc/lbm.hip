@@ -1,0 +1,466 @@
+// lbm.hip -- host side of the C ABI declared in include/lbm.h.
+//
+// The context holds two ping-pong population buffers A, B carved from the
+// caller's workspace. The state "at time t" is the post-collision buffer
+// cur, whose propagation gives the post-propagation PDFs at t + 1; the other
+// buffer still holds what the last step read, so the moments at t are
+// obtained by propagating it again (or, right after lbm_init / lbm_set_pdfs,
+// by reading it in place, since it then holds the post-propagation PDFs at t).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "lbm.h"
+#include "lbm_kernels.hpp"
+
+using namespace cpf;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+size_t elem_bytes(int precision) {
+    switch (precision) {
+        case LBM_FP64: return 8;
+        case LBM_FP32: return 4;
+        default: return 2;
+    }
+}
+
+bool is16(int precision) {
+    return precision == LBM_FP32_FP16STORE || precision == LBM_FP32_BF16STORE;
+}
+
+struct Layout {
+    size_t pdf_bytes;      // one field (19 N values)
+    size_t phis_bytes;     // N floats (16-bit storage) or 0
+    size_t buf_bytes;      // f + g + phis of one ping-pong buffer
+    size_t partial_bytes;  // NSUM doubles per reduction block
+    size_t result_bytes;
+    size_t flag_bytes;
+    size_t total;
+};
+
+Layout layout_of(const lbm_params *P) {
+    Layout L;
+    const size_t N = (size_t)P->nx * P->ny * P->nz;
+    const size_t nblocks = (N + kBlock - 1) / kBlock;
+    L.pdf_bytes = align_up(19 * N * elem_bytes(P->precision));
+    L.phis_bytes = is16(P->precision) ? align_up(N * sizeof(float)) : 0;
+    L.buf_bytes = 2 * L.pdf_bytes + L.phis_bytes;
+    L.partial_bytes = align_up(nblocks * NSUM * sizeof(double));
+    L.result_bytes = align_up(NSUM * sizeof(double));
+    L.flag_bytes = kAlign;
+    L.total = 2 * L.buf_bytes + L.partial_bytes + L.result_bytes + L.flag_bytes;
+    return L;
+}
+
+int validate(const lbm_params *P) {
+    if (!P) return LBM_EINVAL;
+    if (P->nx < 1 || P->ny < 1 || P->nz < 1) return LBM_EINVAL;
+    const double N = (double)P->nx * P->ny * P->nz;
+    if (19.0 * N >= 2147483647.0) return LBM_EINVAL;
+    if (P->precision < LBM_FP64 || P->precision > LBM_FP32_BF16STORE) return LBM_EINVAL;
+    const int nn[3] = {P->nx, P->ny, P->nz};
+    for (int a = 0; a < 3; ++a) {
+        if (P->wall[a] != 0 && P->wall[a] != 1) return LBM_EINVAL;
+        if (P->wall[a] && nn[a] < 2) return LBM_EINVAL;
+    }
+    for (int k = 0; k < 2; ++k)
+        if (P->store_log2[k] < -24 || P->store_log2[k] > 24) return LBM_EINVAL;
+    if (P->check_every < 0) return LBM_EINVAL;
+    auto fin = [](double x) { return std::isfinite(x); };
+    if (!(fin(P->courant) && P->courant > 0.0 && P->courant <= 1.0)) return LBM_EINVAL;
+    if (!(fin(P->rho1) && fin(P->rho2) && P->rho1 > 0.0 && P->rho2 > 0.0)) return LBM_EINVAL;
+    if (!(fin(P->tau_rho1) && fin(P->tau_rho2) && P->tau_rho1 > 0.0 && P->tau_rho2 > 0.0))
+        return LBM_EINVAL;
+    if (!(fin(P->tau_phi) && P->tau_phi > 0.0)) return LBM_EINVAL;
+    if (!(fin(P->sigma) && P->sigma >= 0.0)) return LBM_EINVAL;
+    if (!(fin(P->delta) && P->delta > 0.0)) return LBM_EINVAL;
+    if (!(fin(P->G[0]) && fin(P->G[1]) && fin(P->G[2]))) return LBM_EINVAL;
+    if (!(fin(P->k1_eps) && P->k1_eps >= 0.0)) return LBM_EINVAL;
+    if (!fin(P->p_ref)) return LBM_EINVAL;
+    return LBM_OK;
+}
+
+template <class R>
+DevParams<R> make_params(const lbm_params *P) {
+    DevParams<R> d;
+    d.nx = P->nx;
+    d.ny = P->ny;
+    d.nz = P->nz;
+    d.N = P->nx * P->ny * P->nz;
+    for (int a = 0; a < 3; ++a) d.wall[a] = P->wall[a];
+    const double c = P->courant, cs2 = c * c / 3.0;
+    const double eta1 = P->rho1 * cs2 * P->tau_rho1, eta2 = P->rho2 * cs2 * P->tau_rho2;
+    d.c = R(c);
+    d.h = R(0.5 * c * (1.0 - c));
+    d.cs2 = R(cs2);
+    d.inv_cs2 = R(1.0 / cs2);
+    d.half_inv_cs4 = R(0.5 / (cs2 * cs2));
+    d.rho2 = R(P->rho2);
+    d.drho = R(P->rho1 - P->rho2);
+    d.eta2 = R(eta2);
+    d.deta = R(eta1 - eta2);
+    d.omega_g = R(1.0 / (P->tau_phi + 0.5));
+    d.tau_phi_c = R(P->tau_phi * c);
+    d.tau_phi_cs2 = R(P->tau_phi * cs2);
+    d.inv_tp = R(1.0 / ((P->tau_phi + 0.5) * cs2));
+    d.sigma = R(P->sigma);
+    d.four_over_delta = R(4.0 / P->delta);
+    for (int a = 0; a < 3; ++a) d.G[a] = R(P->G[a]);
+    d.k1_eps = R(P->k1_eps);
+    d.rho0 = R(P->p_ref / cs2);
+    d.scale_f = R(std::ldexp(1.0, P->store_log2[0]));
+    d.iscale_f = R(std::ldexp(1.0, -P->store_log2[0]));
+    d.scale_g = R(std::ldexp(1.0, P->store_log2[1]));
+    d.iscale_g = R(std::ldexp(1.0, -P->store_log2[1]));
+    return d;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_params P;
+    Layout L;
+    hipStream_t stream;
+    char *ws;
+    char *buf[2];
+    double *partials;
+    double *result;
+    int *flag;
+    int cur;            // buffer holding the post-collision state
+    bool prev_local;    // the other buffer holds post-propagation PDFs at t
+    int64_t t;
+    int status;
+    int nblocks;
+};
+
+namespace {
+
+template <class St>
+Buf<St> buf_of(lbm_ctx *c, int k) {
+    Buf<St> b;
+    b.f = (typename St::T *)c->buf[k];
+    b.g = (typename St::T *)(c->buf[k] + c->L.pdf_bytes);
+    b.phis = c->L.phis_bytes ? (float *)(c->buf[k] + 2 * c->L.pdf_bytes) : nullptr;
+    return b;
+}
+
+template <class St>
+CBuf<St> cbuf_of(lbm_ctx *c, int k) {
+    Buf<St> b = buf_of<St>(c, k);
+    return CBuf<St>{b.f, b.g, b.phis};
+}
+
+int check_launch(lbm_ctx *c) {
+    if (hipGetLastError() != hipSuccess) {
+        if (c) c->status = LBM_EDEVICE;
+        return LBM_EDEVICE;
+    }
+    return LBM_OK;
+}
+
+template <class St, Mode M, bool W>
+void launch_step(lbm_ctx *c, int src, int dst) {
+    using R = typename St::R;
+    const DevParams<R> P = make_params<R>(&c->P);
+    hipLaunchKernelGGL((step_kernel<St, M, W>), dim3(c->nblocks), dim3(kBlock), 0, c->stream,
+                       cbuf_of<St>(c, src), buf_of<St>(c, dst), P);
+}
+
+template <class St, Mode M>
+void launch_step_w(lbm_ctx *c, int src, int dst) {
+    const bool walls = c->P.wall[0] || c->P.wall[1] || c->P.wall[2];
+    if (walls) launch_step<St, M, true>(c, src, dst);
+    else launch_step<St, M, false>(c, src, dst);
+}
+
+template <class St>
+void step_dispatch(lbm_ctx *c, Mode m, int src, int dst) {
+    switch (m) {
+        case LOCAL: launch_step_w<St, LOCAL>(c, src, dst); break;
+        case SHIFT: launch_step_w<St, SHIFT>(c, src, dst); break;
+        default: launch_step_w<St, LW>(c, src, dst); break;
+    }
+}
+
+void step_any(lbm_ctx *c, Mode m, int src, int dst) {
+    switch (c->P.precision) {
+        case LBM_FP64: step_dispatch<SF64>(c, m, src, dst); break;
+        case LBM_FP32: step_dispatch<SF32>(c, m, src, dst); break;
+        case LBM_FP32_FP16STORE: step_dispatch<SH16>(c, m, src, dst); break;
+        default: step_dispatch<SB16>(c, m, src, dst); break;
+    }
+}
+
+Mode prop_mode(const lbm_ctx *c) { return c->P.courant == 1.0 ? SHIFT : LW; }
+
+template <class St, Mode M, bool W>
+void launch_moments(lbm_ctx *c, const FieldOut &o) {
+    using R = typename St::R;
+    const DevParams<R> P = make_params<R>(&c->P);
+    hipLaunchKernelGGL((moments_kernel<St, M, W>), dim3(c->nblocks), dim3(kBlock), 0, c->stream,
+                       cbuf_of<St>(c, c->cur ^ 1), P, o);
+}
+
+template <class St, Mode M>
+void moments_w(lbm_ctx *c, const FieldOut &o) {
+    const bool walls = c->P.wall[0] || c->P.wall[1] || c->P.wall[2];
+    if (walls) launch_moments<St, M, true>(c, o);
+    else launch_moments<St, M, false>(c, o);
+}
+
+template <class St>
+void moments_dispatch(lbm_ctx *c, const FieldOut &o) {
+    if (c->prev_local) moments_w<St, LOCAL>(c, o);
+    else if (prop_mode(c) == SHIFT) moments_w<St, SHIFT>(c, o);
+    else moments_w<St, LW>(c, o);
+}
+
+void moments_any(lbm_ctx *c, const FieldOut &o) {
+    switch (c->P.precision) {
+        case LBM_FP64: moments_dispatch<SF64>(c, o); break;
+        case LBM_FP32: moments_dispatch<SF32>(c, o); break;
+        case LBM_FP32_FP16STORE: moments_dispatch<SH16>(c, o); break;
+        default: moments_dispatch<SB16>(c, o); break;
+    }
+}
+
+template <class St>
+void launch_init(lbm_ctx *c, const double *phi0, const double *u0, const double *p0, int dst) {
+    using R = typename St::R;
+    const DevParams<double> PD = make_params<double>(&c->P);
+    const DevParams<R> PR = make_params<R>(&c->P);
+    const bool walls = c->P.wall[0] || c->P.wall[1] || c->P.wall[2];
+    if (walls)
+        hipLaunchKernelGGL((init_kernel<St, true>), dim3(c->nblocks), dim3(kBlock), 0, c->stream,
+                           phi0, u0, p0, PD, PR, buf_of<St>(c, dst), c->flag);
+    else
+        hipLaunchKernelGGL((init_kernel<St, false>), dim3(c->nblocks), dim3(kBlock), 0, c->stream,
+                           phi0, u0, p0, PD, PR, buf_of<St>(c, dst), c->flag);
+}
+
+void init_any(lbm_ctx *c, const double *phi0, const double *u0, const double *p0, int dst) {
+    switch (c->P.precision) {
+        case LBM_FP64: launch_init<SF64>(c, phi0, u0, p0, dst); break;
+        case LBM_FP32: launch_init<SF32>(c, phi0, u0, p0, dst); break;
+        case LBM_FP32_FP16STORE: launch_init<SH16>(c, phi0, u0, p0, dst); break;
+        default: launch_init<SB16>(c, phi0, u0, p0, dst); break;
+    }
+}
+
+template <class St>
+void launch_load(lbm_ctx *c, const double *f, const double *g, int dst) {
+    using R = typename St::R;
+    const DevParams<R> P = make_params<R>(&c->P);
+    hipLaunchKernelGGL((load_kernel<St>), dim3(c->nblocks), dim3(kBlock), 0, c->stream, f, g, P,
+                       buf_of<St>(c, dst));
+}
+
+void load_any(lbm_ctx *c, const double *f, const double *g, int dst) {
+    switch (c->P.precision) {
+        case LBM_FP64: launch_load<SF64>(c, f, g, dst); break;
+        case LBM_FP32: launch_load<SF32>(c, f, g, dst); break;
+        case LBM_FP32_FP16STORE: launch_load<SH16>(c, f, g, dst); break;
+        default: launch_load<SB16>(c, f, g, dst); break;
+    }
+}
+
+// Runs the diagnostics reduction of the state at t into c->result (device).
+int reduce_diag(lbm_ctx *c, const double *phi_ref) {
+    FieldOut o{};
+    o.phi_ref = phi_ref;
+    o.partials = c->partials;
+    moments_any(c, o);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kBlock), 0, c->stream,
+                       (const double *)c->partials, c->nblocks, c->result);
+    return check_launch(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+void lbm_lattice(int32_t e[57], double t[19]) {
+    for (int i = 0; i < 19; ++i) {
+        e[3 * i + 0] = Lat::EX[i];
+        e[3 * i + 1] = Lat::EY[i];
+        e[3 * i + 2] = Lat::EZ[i];
+        const int cl = Lat::cls(i);
+        t[i] = cl == 0 ? 1.0 / 3.0 : (cl == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+}
+
+int lbm_workspace_bytes(const lbm_params *P, size_t *bytes) {
+    if (!bytes) return LBM_EINVAL;
+    const int rc = validate(P);
+    if (rc != LBM_OK) return rc;
+    *bytes = layout_of(P).total;
+    return LBM_OK;
+}
+
+int lbm_init(const lbm_params *P, void *d_workspace, size_t bytes, void *stream,
+             const double *d_phi0, const double *d_u0, const double *d_p0, lbm_ctx **out) {
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    int rc = validate(P);
+    if (rc != LBM_OK) return rc;
+    if (!d_workspace || !d_phi0) return LBM_EINVAL;
+    if (((uintptr_t)d_workspace) % kAlign != 0) return LBM_EINVAL;
+    const Layout L = layout_of(P);
+    if (bytes < L.total) return LBM_ENOMEM;
+
+    lbm_ctx *c = new (std::nothrow) lbm_ctx;
+    if (!c) return LBM_ENOMEM;
+    std::memset(c, 0, sizeof(*c));
+    c->P = *P;
+    c->L = L;
+    c->stream = (hipStream_t)stream;
+    c->ws = (char *)d_workspace;
+    c->buf[0] = c->ws;
+    c->buf[1] = c->ws + L.buf_bytes;
+    c->partials = (double *)(c->ws + 2 * L.buf_bytes);
+    c->result = (double *)(c->ws + 2 * L.buf_bytes + L.partial_bytes);
+    c->flag = (int *)(c->ws + 2 * L.buf_bytes + L.partial_bytes + L.result_bytes);
+    const size_t N = (size_t)P->nx * P->ny * P->nz;
+    c->nblocks = (int)((N + kBlock - 1) / kBlock);
+    c->status = LBM_OK;
+
+    hipLaunchKernelGGL(clear_int_kernel, dim3(1), dim3(1), 0, c->stream, c->flag);
+    // post-propagation PDFs at t = 0 into buffer 1, collide into buffer 0
+    init_any(c, d_phi0, d_u0, d_p0, 1);
+    step_any(c, LOCAL, 1, 0);
+    c->cur = 0;
+    c->prev_local = true;
+    c->t = 0;
+    int bad = 0;
+    if (check_launch(c) != LBM_OK ||
+        hipMemcpyAsync(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        delete c;
+        return LBM_EDEVICE;
+    }
+    if (bad) {
+        delete c;
+        return LBM_EINVAL;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int64_t n) {
+    if (!c || n < 0) return LBM_EINVAL;
+    if (c->status != LBM_OK) return LBM_ESTATE;
+    const Mode m = prop_mode(c);
+    for (int64_t k = 0; k < n; ++k) {
+        step_any(c, m, c->cur, c->cur ^ 1);
+        c->cur ^= 1;
+        c->prev_local = false;
+        c->t += 1;
+        if (c->P.check_every > 0 && c->t % c->P.check_every == 0) {
+            if (reduce_diag(c, nullptr) != LBM_OK) return LBM_EDEVICE;
+            double r[NSUM];
+            if (hipMemcpyAsync(r, c->result, sizeof(r), hipMemcpyDeviceToHost, c->stream) !=
+                    hipSuccess ||
+                hipStreamSynchronize(c->stream) != hipSuccess) {
+                c->status = LBM_EDEVICE;
+                return LBM_EDEVICE;
+            }
+            const double cs = c->P.courant / std::sqrt(3.0);
+            bool ok = true;
+            for (int k2 = 0; k2 < NSUM; ++k2) ok = ok && std::isfinite(r[k2]);
+            if (!ok || r[6] >= cs) {
+                c->status = LBM_EUNSTABLE;
+                return LBM_EUNSTABLE;
+            }
+        }
+    }
+    return check_launch(c);
+}
+
+int lbm_fields(lbm_ctx *c, void *d_phi, void *d_u, void *d_p, int32_t dtype) {
+    if (!c || (dtype != 0 && dtype != 1)) return LBM_EINVAL;
+    if (c->status == LBM_EDEVICE) return LBM_ESTATE;
+    FieldOut o{};
+    o.phi = d_phi;
+    o.u = d_u;
+    o.p = d_p;
+    o.dtype = dtype;
+    moments_any(c, o);
+    return check_launch(c);
+}
+
+int lbm_diagnostics(lbm_ctx *c, const double *d_phi_ref, lbm_diag *out) {
+    if (!c || !out) return LBM_EINVAL;
+    if (c->status == LBM_EDEVICE) return LBM_ESTATE;
+    if (reduce_diag(c, d_phi_ref) != LBM_OK) return LBM_EDEVICE;
+    double r[NSUM];
+    if (hipMemcpyAsync(r, c->result, sizeof(r), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        c->status = LBM_EDEVICE;
+        return LBM_EDEVICE;
+    }
+    out->step = c->t;
+    out->sum_phi = r[0];
+    out->mass = r[1];
+    out->mom[0] = r[2];
+    out->mom[1] = r[3];
+    out->mom[2] = r[4];
+    out->ekin = r[5];
+    out->umax = r[6];
+    out->phi_min = r[7];
+    out->phi_max = r[8];
+    for (int a = 0; a < 3; ++a) {
+        out->com[a] = r[9 + a];
+        out->phiu[a] = r[12 + a];
+    }
+    out->l2_num = r[15];
+    out->l2_den = r[16];
+    return LBM_OK;
+}
+
+int lbm_get_pdfs(lbm_ctx *c, double *d_f, double *d_g) {
+    if (!c || !d_f || !d_g) return LBM_EINVAL;
+    if (c->status == LBM_EDEVICE) return LBM_ESTATE;
+    FieldOut o{};
+    o.pdf_f = d_f;
+    o.pdf_g = d_g;
+    moments_any(c, o);
+    return check_launch(c);
+}
+
+int lbm_set_pdfs(lbm_ctx *c, const double *d_f, const double *d_g) {
+    if (!c || !d_f || !d_g) return LBM_EINVAL;
+    if (c->status == LBM_EDEVICE) return LBM_ESTATE;
+    const int prev = c->cur ^ 1;
+    load_any(c, d_f, d_g, prev);
+    step_any(c, LOCAL, prev, c->cur);
+    c->prev_local = true;
+    c->status = LBM_OK;
+    return check_launch(c);
+}
+
+int64_t lbm_time(const lbm_ctx *c) { return c ? c->t : -1; }
+
+void lbm_destroy(lbm_ctx *c) { delete c; }
+
+const char *lbm_strerror(int status) {
+    switch (status) {
+        case LBM_OK: return "ok";
+        case LBM_EINVAL: return "invalid argument";
+        case LBM_ENOMEM: return "workspace too small";
+        case LBM_EDEVICE: return "HIP device error";
+        case LBM_EUNSTABLE: return "simulation became unstable";
+        case LBM_ESTATE: return "context is in an error state";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,734 @@
+// lbm_kernels.hpp -- HIP kernels (gfx950) of the fused difference-free
+// conservative phase-field LBM step (Zhao, Patel & Lee, arXiv 2407.12263).
+//
+// One thread per lattice node, one pass per step: each thread pulls the
+// Lax-Wendroff taps of its 2 x 19 populations from the post-collision
+// buffer, recovers phi, u, K1, n, grad(phi), p in registers, collides both
+// populations and writes 2 x 19 post-collision values. The only non-local
+// operation is the propagation; the interface normal and grad(phi) come from
+// the node's own K1 (Sec. 2.3), so no neighbour field is ever differenced.
+//
+// Precision policies: FP64; FP32; FP32 compute with 16-bit storage of the
+// deviations f_i - t_i rho0 and g_i - t_i phi_s scaled by 2^k (FP16 or
+// BF16, round-to-nearest-even) plus the FP32 per-node phi_s chosen so that the
+// stored g of a node sums exactly (to FP32 rounding) to the collided phi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+namespace cpf {
+
+// ---------------------------------------------------------------- lattice
+// D3Q19: rest, 6 axis vectors, 12 edge vectors; weights 1/3, 1/18, 1/36.
+struct Lat {
+    static constexpr int EX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int EY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int EZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr int OPP[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+    static constexpr int cls(int i) { return EX[i] * EX[i] + EY[i] * EY[i] + EZ[i] * EZ[i]; }
+};
+
+template <class R>
+__device__ __forceinline__ constexpr R wgt(int cls) {
+    return cls == 0 ? R(1) / R(3) : (cls == 1 ? R(1) / R(18) : R(1) / R(36));
+}
+
+template <int B, int E, class F>
+__device__ __forceinline__ void unroll(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        unroll<B + 1, E>(f);
+    }
+}
+
+// sum_i v_i * e^_ia with compile-time integer components
+template <int A, class R>
+__device__ __forceinline__ R first_moment(const R (&v)[19]) {
+    R s = R(0);
+    unroll<1, 19>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int e = A == 0 ? Lat::EX[i] : (A == 1 ? Lat::EY[i] : Lat::EZ[i]);
+        if constexpr (e > 0) s += v[i];
+        if constexpr (e < 0) s -= v[i];
+    });
+    return s;
+}
+
+// e^_i . v for a compile-time direction
+template <int i, class R>
+__device__ __forceinline__ R edot(const R (&v)[3]) {
+    constexpr int ex = Lat::EX[i], ey = Lat::EY[i], ez = Lat::EZ[i];
+    R s = R(0);
+    bool first = true;
+    auto add = [&](int e, R x) {
+        if (e == 0) return;
+        R t = e > 0 ? x : -x;
+        s = first ? t : s + t;
+        first = false;
+    };
+    add(ex, v[0]);
+    add(ey, v[1]);
+    add(ez, v[2]);
+    return s;
+}
+
+// ------------------------------------------------------------ parameters
+template <class R>
+struct DevParams {
+    int nx, ny, nz, N;
+    int wall[3];
+    R c, h;                  // Courant number, c(1-c)/2
+    R cs2, inv_cs2, half_inv_cs4;
+    R rho2, drho;            // rho = rho2 + drho*phi
+    R eta2, deta;            // eta = eta2 + deta*phi
+    R omega_g, tau_phi_c;    // 1/(tau_phi+1/2), tau_phi*c
+    R tau_phi_cs2, inv_tp;   // tau_phi*cs2, 1/((tau_phi+1/2) cs2)
+    R sigma, four_over_delta;
+    R G[3];
+    R k1_eps;
+    R rho0;                  // p_ref/cs2: gauge of the 16-bit f storage
+    R scale_f, iscale_f, scale_g, iscale_g;
+};
+
+// ---------------------------------------------------------- storage types
+struct SF64 { using R = double; using T = double; static constexpr bool DEV = false; };
+struct SF32 { using R = float;  using T = float;  static constexpr bool DEV = false; };
+struct SH16 { using R = float;  using T = _Float16; static constexpr bool DEV = true; };
+struct SB16 { using R = float;  using T = uint16_t; static constexpr bool DEV = true; };
+
+template <class St>
+__device__ __forceinline__ typename St::R decode(typename St::T v) {
+    if constexpr (std::is_same_v<St, SB16>) {
+        return __uint_as_float(uint32_t(v) << 16);
+    } else {
+        return typename St::R(v);
+    }
+}
+
+template <class St>
+__device__ __forceinline__ typename St::T encode(typename St::R x) {
+    if constexpr (std::is_same_v<St, SB16>) {
+        // round to nearest even (finite inputs)
+        uint32_t u = __float_as_uint(x);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return uint16_t(u >> 16);
+    } else {
+        return typename St::T(x);
+    }
+}
+
+template <class St>
+struct Buf {
+    typename St::T *f;   // 19 planes of N
+    typename St::T *g;   // 19 planes of N
+    float *phis;         // N (16-bit storage only)
+};
+
+template <class St>
+struct CBuf {
+    const typename St::T *f;
+    const typename St::T *g;
+    const float *phis;
+};
+
+// ------------------------------------------------------- node geometry
+struct Site {
+    int n;
+    int X[3];            // x-1, x, x+1 (wrapped)
+    int Y[3];            // (y-1)*nx, y*nx, (y+1)*nx (wrapped)
+    int Z[3];            // likewise times nx*ny
+    bool lo[3], hi[3];   // node on the first / last layer of a wall axis
+
+    template <int dx, int dy, int dz>
+    __device__ __forceinline__ int at() const { return X[dx + 1] + Y[dy + 1] + Z[dz + 1]; }
+};
+
+template <class R>
+__device__ __forceinline__ Site make_site(const DevParams<R> &P, int n) {
+    Site s;
+    s.n = n;
+    const int nxy = P.nx * P.ny;
+    const int z = n / nxy;
+    const int r = n - z * nxy;
+    const int y = r / P.nx;
+    const int x = r - y * P.nx;
+    s.X[1] = x;
+    s.X[0] = x == 0 ? P.nx - 1 : x - 1;
+    s.X[2] = x == P.nx - 1 ? 0 : x + 1;
+    s.Y[1] = y * P.nx;
+    s.Y[0] = (y == 0 ? P.ny - 1 : y - 1) * P.nx;
+    s.Y[2] = (y == P.ny - 1 ? 0 : y + 1) * P.nx;
+    s.Z[1] = z * nxy;
+    s.Z[0] = (z == 0 ? P.nz - 1 : z - 1) * nxy;
+    s.Z[2] = (z == P.nz - 1 ? 0 : z + 1) * nxy;
+    const int c[3] = {x, y, z};
+    const int nn[3] = {P.nx, P.ny, P.nz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s.lo[a] = P.wall[a] && c[a] == 0;
+        s.hi[a] = P.wall[a] && c[a] == nn[a] - 1;
+    }
+    return s;
+}
+
+// x - s*e^_i lies beyond a wall (s = +1: upstream, s = -1: downstream)
+template <int i, int sgn>
+__device__ __forceinline__ bool beyond_wall(const Site &s) {
+    constexpr int e[3] = {sgn * Lat::EX[i], sgn * Lat::EY[i], sgn * Lat::EZ[i]};
+    bool b = false;
+    if constexpr (e[0] > 0) b = b || s.lo[0];
+    if constexpr (e[0] < 0) b = b || s.hi[0];
+    if constexpr (e[1] > 0) b = b || s.lo[1];
+    if constexpr (e[1] < 0) b = b || s.hi[1];
+    if constexpr (e[2] > 0) b = b || s.lo[2];
+    if constexpr (e[2] < 0) b = b || s.hi[2];
+    return b;
+}
+
+// ------------------------------------------------------------ propagation
+enum Mode { LOCAL = 0, SHIFT = 1, LW = 2 };
+
+// Reads population i (f or g) at node index m, as a value of the field.
+template <class St, bool IS_G>
+struct Reader {
+    using R = typename St::R;
+    const typename St::T *plane0;
+    const float *phis;
+    int N;
+    R rho0, iscale;
+
+    template <int i>
+    __device__ __forceinline__ R get(int m, R phis_m) const {
+        const typename St::T v = plane0[(size_t)i * N + m];
+        if constexpr (St::DEV) {
+            constexpr R t = wgt<R>(Lat::cls(i));
+            const R base = IS_G ? t * phis_m : t * rho0;
+            return fma(iscale, decode<St>(v), base);
+        } else {
+            return R(v);
+        }
+    }
+};
+
+// Lax-Wendroff propagation of one population in flux form (Sec. 2.2):
+//   out = a0 + [flux in through x - e/2] - [flux out through x + e/2],
+//   flux(x + e/2) = c a(x) + h (a(x+e) - a(x)),   h = c(1-c)/2,
+// which equals the printed three-point form in the interior and sums to zero
+// over the lattice in floating point too (each face flux is computed
+// bit-identically by both of its nodes). A face beyond a wall takes the
+// node itself as its far value and returns its outgoing flux into the
+// opposite population (halfway bounce-back at c = 1).
+template <Mode M, bool WALLS, class St, bool IS_G, int i>
+__device__ __forceinline__ typename St::R pull(const Reader<St, IS_G> &rd, const Site &s,
+                                               const DevParams<typename St::R> &P,
+                                               const typename St::R (&ph)[19]) {
+    using R = typename St::R;
+    constexpr int ex = Lat::EX[i], ey = Lat::EY[i], ez = Lat::EZ[i];
+    constexpr int o = Lat::OPP[i];
+    if constexpr (M == LOCAL || i == 0) {
+        return rd.template get<i>(s.n, ph[0]);
+    } else if constexpr (M == SHIFT) {
+        const R am = rd.template get<i>(s.template at<-ex, -ey, -ez>(), ph[o]);
+        if constexpr (WALLS) {
+            if (beyond_wall<i, 1>(s)) return rd.template get<o>(s.n, ph[0]);
+        }
+        return am;
+    } else {
+        const R a0 = rd.template get<i>(s.n, ph[0]);
+        const R am = rd.template get<i>(s.template at<-ex, -ey, -ez>(), ph[o]);
+        const R ap = rd.template get<i>(s.template at<ex, ey, ez>(), ph[i]);
+        R fout = fma(P.h, ap - a0, P.c * a0);
+        R fin = fma(P.h, a0 - am, P.c * am);
+        if constexpr (WALLS) {
+            if (beyond_wall<i, -1>(s)) fout = P.c * a0;
+            if (beyond_wall<i, 1>(s)) fin = P.c * rd.template get<o>(s.n, ph[0]);
+        }
+        return a0 + (fin - fout);
+    }
+}
+
+// Gathers the post-propagation f and g of one node.
+template <Mode M, bool WALLS, class St>
+__device__ __forceinline__ void gather(const CBuf<St> &src, const Site &s,
+                                       const DevParams<typename St::R> &P,
+                                       typename St::R (&fb)[19], typename St::R (&gb)[19]) {
+    using R = typename St::R;
+    R ph[19];  // phi_s at the stencil nodes x + e^_i (16-bit storage only)
+    if constexpr (St::DEV) {
+        unroll<0, 19>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (M == LOCAL) {
+                if constexpr (i == 0) ph[0] = src.phis[s.n];
+                else ph[i] = R(0);
+            } else {
+                ph[i] = src.phis[s.template at<Lat::EX[i], Lat::EY[i], Lat::EZ[i]>()];
+            }
+        });
+    } else {
+        unroll<0, 19>([&](auto I) { ph[decltype(I)::value] = R(0); });
+    }
+    const Reader<St, false> rf{src.f, src.phis, P.N, P.rho0, P.iscale_f};
+    const Reader<St, true> rg{src.g, src.phis, P.N, P.rho0, P.iscale_g};
+    unroll<0, 19>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        fb[i] = pull<M, WALLS, St, false, i>(rf, s, P, ph);
+        gb[i] = pull<M, WALLS, St, true, i>(rg, s, P, ph);
+    });
+}
+
+// --------------------------------------------------------------- moments
+template <class R>
+struct Macro {
+    R phi, rho, omega_f;
+    R u[3];
+    R p;
+    R n[3];
+    R gnorm;      // |grad phi|
+    R gradrho[3];
+    R S[3];
+};
+
+// Moments of the post-propagation PDFs (Sec. 2.2 Eqs. 11-12, Sec. 2.3
+// Eqs. 15, 17-19): phi = sum g, rho(phi), u = (sum f e + rho G/2)/rho,
+// K1 = sum g e - phi u, n = -K1/|K1| (0 where |K1| <= k1_eps),
+// S = 4 phi (1 - phi)/delta n, grad(phi) = (tau cs2 S - K1)/((tau + 1/2) cs2),
+// grad(rho) = (rho1 - rho2) grad(phi), p = cs2 sum f + cs2/2 u.grad(rho).
+template <class R>
+__device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)[19],
+                                            const R (&gb)[19]) {
+    Macro<R> m;
+    R phi = gb[0], sf = fb[0];
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        phi += gb[i];
+        sf += fb[i];
+    }
+    m.phi = phi;
+    m.rho = fma(P.drho, phi, P.rho2);
+    const R eta = fma(P.deta, phi, P.eta2);
+    const R irho = R(1) / m.rho;
+    // omega_f = 1/(tau_rho + 1/2), tau_rho = eta/(rho cs2)
+    m.omega_f = R(1) / fma(eta * irho, P.inv_cs2, R(0.5));
+    const R jx = first_moment<0>(fb), jy = first_moment<1>(fb), jz = first_moment<2>(fb);
+    m.u[0] = fma(P.c, jx, R(0.5) * m.rho * P.G[0]) * irho;
+    m.u[1] = fma(P.c, jy, R(0.5) * m.rho * P.G[1]) * irho;
+    m.u[2] = fma(P.c, jz, R(0.5) * m.rho * P.G[2]) * irho;
+    const R K[3] = {fma(P.c, first_moment<0>(gb), -phi * m.u[0]),
+                    fma(P.c, first_moment<1>(gb), -phi * m.u[1]),
+                    fma(P.c, first_moment<2>(gb), -phi * m.u[2])};
+    const R k = sqrt(fma(K[0], K[0], fma(K[1], K[1], K[2] * K[2])));
+    const bool has_n = k > P.k1_eps;
+    const R rk = has_n ? R(1) / k : R(0);
+    const R s = P.four_over_delta * phi * (R(1) - phi);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        m.n[a] = -K[a] * rk;
+        m.S[a] = s * m.n[a];
+    }
+    // |grad phi|: with n = -K1/|K1|, grad phi = n (tau cs2 s + |K1|)/((tau+1/2)cs2)
+    m.gnorm = has_n ? fabs(fma(P.tau_phi_cs2, s, k)) * P.inv_tp : k * P.inv_tp;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        m.gradrho[a] = P.drho * fma(P.tau_phi_cs2, m.S[a], -K[a]) * P.inv_tp;
+    const R ug = fma(m.u[0], m.gradrho[0], fma(m.u[1], m.gradrho[1], m.u[2] * m.gradrho[2]));
+    m.p = P.cs2 * fma(R(0.5), ug, sf);
+    return m;
+}
+
+// ------------------------------------------------------------- collision
+// Equilibria and forcing of direction i, each divided by t_i:
+//   feq/t  = p/cs2 + rho poly - Pi_s:(e e - cs2 I)/(2 cs4)      (Eq. 8, minus)
+//   F/t    = poly (e - u).grad(rho)                             (App. A, S_i)
+//          + [(e - u)/cs2 + (e.u) e/cs4].(rho G)                (Eq. 7, R_i)
+//   geq/t  = phi (1 + poly) + tau_phi e.S                       (Eq. 14)
+// with poly = e.u/cs2 + (e.u)^2/(2 cs4) - u^2/(2 cs2), so Gamma_i = t_i (1 + poly).
+template <class R>
+struct NodeCoef {
+    R cu[3];          // c u
+    R cgr[3];         // c grad(rho)
+    R crG[3];         // c rho G
+    R tS[3];          // tau_phi c S
+    R a3;             // u^2/(2 cs2)
+    R ug, uG;         // u.grad(rho), u.(rho G)
+    R A0[3];          // p/cs2 - Pi_s:(e e - cs2 I)/(2cs4) minus the (e.n)^2 part, per speed class
+    R kpsi;           // sigma |grad phi| c^2/(2 cs4): coefficient of (e^.n)^2
+};
+
+template <class R>
+__device__ __forceinline__ NodeCoef<R> node_coef(const DevParams<R> &P, const Macro<R> &m) {
+    NodeCoef<R> q;
+    R rG[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        rG[a] = m.rho * P.G[a];
+        q.cu[a] = P.c * m.u[a];
+        q.cgr[a] = P.c * m.gradrho[a];
+        q.crG[a] = P.c * rG[a];
+        q.tS[a] = P.tau_phi_c * m.S[a];
+    }
+    const R uu = fma(m.u[0], m.u[0], fma(m.u[1], m.u[1], m.u[2] * m.u[2]));
+    q.a3 = R(0.5) * uu * P.inv_cs2;
+    q.ug = fma(m.u[0], m.gradrho[0], fma(m.u[1], m.gradrho[1], m.u[2] * m.gradrho[2]));
+    q.uG = fma(m.u[0], rG[0], fma(m.u[1], rG[1], m.u[2] * rG[2]));
+    const R nn = fma(m.n[0], m.n[0], fma(m.n[1], m.n[1], m.n[2] * m.n[2]));
+    // Pi_s:(e e - cs2 I)/(2cs4) = ps [c^2 |e^|^2 - c^2 (e^.n)^2 - cs2 (3 - |n|^2)]
+    const R ps = P.sigma * m.gnorm * P.half_inv_cs4;
+    const R c2 = P.c * P.c;
+    q.kpsi = ps * c2;
+    const R base = fma(m.p, P.inv_cs2, ps * P.cs2 * (R(3) - nn));
+    q.A0[0] = base;
+    q.A0[1] = base - q.kpsi;
+    q.A0[2] = base - R(2) * q.kpsi;
+    return q;
+}
+
+template <class R>
+struct Collided {
+    R f[19];
+    R g[19];
+};
+
+// f* = f - omega_f (f - feq + F/2) + F ;  g* = g - omega_g (g - geq)   (Eqs. 10, 16)
+template <class R>
+__device__ __forceinline__ void collide(const DevParams<R> &P, const Macro<R> &m,
+                                        const NodeCoef<R> &q, R (&fb)[19], R (&gb)[19]) {
+    const R of = m.omega_f, cf = R(1) - R(0.5) * of, rf = R(1) - of;
+    const R og = P.omega_g, rg = R(1) - og;
+    unroll<0, 19>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int cl = Lat::cls(i);
+        constexpr R t = wgt<R>(cl);
+        R poly, A, B, Gq;
+        if constexpr (i == 0) {
+            poly = -q.a3;
+            A = fma(m.rho, poly, q.A0[0]);
+            B = -poly * q.ug - q.uG * P.inv_cs2;
+            Gq = fma(m.phi, poly, m.phi);
+        } else {
+            const R eu = edot<i>(q.cu);
+            const R en = edot<i>(m.n);
+            const R eg = edot<i>(q.cgr);
+            const R eG = edot<i>(q.crG);
+            const R es = edot<i>(q.tS);
+            poly = fma(eu, fma(eu, P.half_inv_cs4, P.inv_cs2), -q.a3);
+            A = fma(m.rho, poly, fma(q.kpsi * en, en, q.A0[cl]));
+            B = fma(poly, eg - q.ug, fma(eG - q.uG, P.inv_cs2, R(2) * P.half_inv_cs4 * eu * eG));
+            Gq = fma(m.phi, poly, m.phi + es);
+        }
+        fb[i] = fma(rf, fb[i], t * fma(of, A, cf * B));
+        gb[i] = fma(rg, gb[i], og * t * Gq);
+    });
+}
+
+// ---------------------------------------------------------------- store
+template <class St>
+__device__ __forceinline__ void store(const Buf<St> &dst, int n,
+                                      const DevParams<typename St::R> &P,
+                                      const typename St::R (&fs)[19],
+                                      const typename St::R (&gs)[19]) {
+    using R = typename St::R;
+    const size_t N = (size_t)P.N;
+    if constexpr (!St::DEV) {
+        unroll<0, 19>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            dst.f[i * N + n] = fs[i];
+            dst.g[i * N + n] = gs[i];
+        });
+    } else {
+        R phi_a = gs[0];
+#pragma unroll
+        for (int i = 1; i < 19; ++i) phi_a += gs[i];
+        R resid = R(0);
+        unroll<0, 19>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr R t = wgt<R>(Lat::cls(i));
+            const typename St::T hf = encode<St>(P.scale_f * (fs[i] - t * P.rho0));
+            const R dg = fma(-t, phi_a, gs[i]);
+            const typename St::T hg = encode<St>(P.scale_g * dg);
+            resid += fma(-P.iscale_g, decode<St>(hg), dg);
+            dst.f[i * N + n] = hf;
+            dst.g[i * N + n] = hg;
+        });
+        // sum_i (t_i phi_s + 2^-k h_i) = sum_i g*_i: the storage rounding of g
+        // is absorbed by phi_s, so the node keeps its phase mass
+        dst.phis[n] = phi_a + resid;
+    }
+}
+
+// ---------------------------------------------------------------- kernels
+// Fused step: propagate (mode M) from src, moments, collide, store to dst.
+template <class St, Mode M, bool WALLS>
+__global__ void __launch_bounds__(256) step_kernel(CBuf<St> src, Buf<St> dst,
+                                                   DevParams<typename St::R> P) {
+    using R = typename St::R;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= P.N) return;
+    const Site s = make_site(P, n);
+    R fb[19], gb[19];
+    gather<M, WALLS, St>(src, s, P, fb, gb);
+    const Macro<R> m = moments(P, fb, gb);
+    const NodeCoef<R> q = node_coef(P, m);
+    collide(P, m, q, fb, gb);
+    store<St>(dst, n, P, fb, gb);
+}
+
+// Number of FP64 partial sums per block in the diagnostics reduction.
+constexpr int NSUM = 17;
+// layout: 0 sum_phi 1 mass 2-4 mom 5 ekin 6 umax(max) 7 phi_min(min)
+//         8 phi_max(max) 9-11 com 12-14 phiu 15 l2_num 16 l2_den
+
+struct FieldOut {
+    void *phi, *u, *p;
+    int dtype;                 // 0 double, 1 float
+    double *pdf_f, *pdf_g;     // FP64 post-propagation PDFs (or NULL)
+    const double *phi_ref;     // for the L2 entries (or NULL)
+    double *partials;          // NSUM per block (or NULL)
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Moments of the state at t (propagation mode M from the previous buffer):
+// fields, FP64 PDFs and/or per-block FP64 partial sums of the diagnostics.
+template <class St, Mode M, bool WALLS>
+__global__ void __launch_bounds__(256) moments_kernel(CBuf<St> src, DevParams<typename St::R> P,
+                                                      FieldOut out) {
+    using R = typename St::R;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = n < P.N;
+    double acc[NSUM];
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) acc[k] = 0.0;
+    acc[6] = 0.0;
+    acc[7] = 1e300;
+    acc[8] = -1e300;
+    if (live) {
+        const Site s = make_site(P, n);
+        R fb[19], gb[19];
+        gather<M, WALLS, St>(src, s, P, fb, gb);
+        const Macro<R> m = moments(P, fb, gb);
+        const size_t N = (size_t)P.N;
+        if (out.phi) {
+            if (out.dtype == 0) ((double *)out.phi)[n] = m.phi;
+            else ((float *)out.phi)[n] = (float)m.phi;
+        }
+        if (out.u) {
+            for (int a = 0; a < 3; ++a) {
+                if (out.dtype == 0) ((double *)out.u)[a * N + n] = m.u[a];
+                else ((float *)out.u)[a * N + n] = (float)m.u[a];
+            }
+        }
+        if (out.p) {
+            if (out.dtype == 0) ((double *)out.p)[n] = m.p;
+            else ((float *)out.p)[n] = (float)m.p;
+        }
+        if (out.pdf_f) {
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                out.pdf_f[i * N + n] = fb[i];
+                out.pdf_g[i * N + n] = gb[i];
+            }
+        }
+        if (out.partials) {
+            const double phi = m.phi, rho = m.rho;
+            const double ux = m.u[0], uy = m.u[1], uz = m.u[2];
+            const double uu = ux * ux + uy * uy + uz * uz;
+            const int z = n / (P.nx * P.ny);
+            const int y = (n - z * P.nx * P.ny) / P.nx;
+            const int x = n - (z * P.ny + y) * P.nx;
+            acc[0] = phi;
+            acc[1] = rho * phi;
+            acc[2] = rho * ux;
+            acc[3] = rho * uy;
+            acc[4] = rho * uz;
+            acc[5] = 0.5 * rho * uu;
+            acc[6] = sqrt(uu);
+            acc[7] = phi;
+            acc[8] = phi;
+            acc[9] = phi * x;
+            acc[10] = phi * y;
+            acc[11] = phi * z;
+            acc[12] = phi * ux;
+            acc[13] = phi * uy;
+            acc[14] = phi * uz;
+            if (out.phi_ref) {
+                const double r = out.phi_ref[n];
+                acc[15] = (phi - r) * (phi - r);
+                acc[16] = r * r;
+            }
+        }
+    }
+    if (out.partials) {
+        // deterministic block reduction: wave shuffles, then waves in order
+        __shared__ double red[4][NSUM];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k) {
+            double v = acc[k];
+            v = (k == 6 || k == 8) ? wave_max(v) : (k == 7 ? wave_min(v) : wave_sum(v));
+            if (lane == 0) red[wv][k] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < NSUM) {
+            const int k = threadIdx.x;
+            double v = red[0][k];
+            for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+                const double x = red[w][k];
+                v = (k == 6 || k == 8) ? fmax(v, x) : (k == 7 ? fmin(v, x) : v + x);
+            }
+            out.partials[(size_t)blockIdx.x * NSUM + k] = v;
+        }
+    }
+}
+
+// Final reduction of the per-block partials (one block, fixed order).
+__global__ void __launch_bounds__(256) reduce_partials_kernel(const double *partials, int nblocks,
+                                                              double *result) {
+    __shared__ double red[4][NSUM];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = 0; k < NSUM; ++k) {
+        const bool mx = (k == 6 || k == 8), mn = (k == 7);
+        double v = mx ? -1e300 : (mn ? 1e300 : 0.0);
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+            const double x = partials[(size_t)b * NSUM + k];
+            v = mx ? fmax(v, x) : (mn ? fmin(v, x) : v + x);
+        }
+        v = mx ? wave_max(v) : (mn ? wave_min(v) : wave_sum(v));
+        if (lane == 0) red[wv][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NSUM) {
+        const int k = threadIdx.x;
+        const bool mx = (k == 6 || k == 8), mn = (k == 7);
+        double v = red[0][k];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+            const double x = red[w][k];
+            v = mx ? fmax(v, x) : (mn ? fmin(v, x) : v + x);
+        }
+        result[k] = v;
+    }
+}
+
+// Initial state (at t = 0, post-propagation) from phi0, u0, p0 (FP64):
+// f = f_eq - F/2, g = g_eq - (tau_phi + 1/2) t_i e_i.grad(phi0), with
+// grad(phi0) = 3 sum_i t_i e^_i [phi0(x + e^_i) - phi0(x - e^_i)]/2 (a
+// neighbour beyond a wall takes the node's own value). Computed in FP64 and
+// rounded once to the storage precision. Sets *bad if an input is
+// non-finite or phi0 lies outside [-0.5, 1.5].
+template <class St, bool WALLS>
+__global__ void __launch_bounds__(256) init_kernel(const double *phi0, const double *u0,
+                                                   const double *p0, DevParams<double> P,
+                                                   DevParams<typename St::R> PR, Buf<St> dst,
+                                                   int *bad) {
+    using R = typename St::R;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= P.N) return;
+    const Site s = make_site(P, n);
+    const size_t N = (size_t)P.N;
+    const double ph0 = phi0[n];
+    double g[3] = {0.0, 0.0, 0.0};
+    unroll<1, 19>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int ex = Lat::EX[i], ey = Lat::EY[i], ez = Lat::EZ[i];
+        constexpr double t = wgt<double>(Lat::cls(i));
+        double vp = phi0[s.template at<ex, ey, ez>()];
+        double vm = phi0[s.template at<-ex, -ey, -ez>()];
+        if constexpr (WALLS) {
+            if (beyond_wall<i, -1>(s)) vp = ph0;
+            if (beyond_wall<i, 1>(s)) vm = ph0;
+        }
+        const double d = 0.5 * (vp - vm) * t;
+        g[0] += ex * d;
+        g[1] += ey * d;
+        g[2] += ez * d;
+    });
+#pragma unroll
+    for (int a = 0; a < 3; ++a) g[a] *= 3.0;
+
+    Macro<double> m;
+    m.phi = ph0;
+    m.rho = fma(P.drho, ph0, P.rho2);
+    m.omega_f = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) m.u[a] = u0 ? u0[a * N + n] : 0.0;
+    m.p = p0 ? p0[n] : 0.0;
+    const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    const double s4 = P.four_over_delta * ph0 * (1.0 - ph0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        m.n[a] = gn > 0.0 ? g[a] / gn : 0.0;
+        m.S[a] = s4 * m.n[a];
+        m.gradrho[a] = P.drho * g[a];
+    }
+    m.gnorm = gn;
+    if (!(isfinite(ph0) && isfinite(m.p) && isfinite(m.u[0]) && isfinite(m.u[1]) &&
+          isfinite(m.u[2]) && ph0 >= -0.5 && ph0 <= 1.5))
+        atomicOr(bad, 1);
+
+    const NodeCoef<double> q = node_coef(P, m);
+    R fo[19], go[19];
+    unroll<0, 19>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int cl = Lat::cls(i);
+        constexpr double t = wgt<double>(cl);
+        double poly, A, B, Gq, eg0;
+        if constexpr (i == 0) {
+            poly = -q.a3;
+            A = fma(m.rho, poly, q.A0[0]);
+            B = -poly * q.ug - q.uG * P.inv_cs2;
+            Gq = fma(m.phi, poly, m.phi);
+            eg0 = 0.0;
+        } else {
+            const double eu = edot<i>(q.cu);
+            const double en = edot<i>(m.n);
+            const double eg = edot<i>(q.cgr);
+            const double eG = edot<i>(q.crG);
+            const double es = edot<i>(q.tS);
+            poly = fma(eu, fma(eu, P.half_inv_cs4, P.inv_cs2), -q.a3);
+            A = fma(m.rho, poly, fma(q.kpsi * en, en, q.A0[cl]));
+            B = fma(poly, eg - q.ug, fma(eG - q.uG, P.inv_cs2, 2.0 * P.half_inv_cs4 * eu * eG));
+            Gq = fma(m.phi, poly, m.phi + es);
+            eg0 = P.c * edot<i>(g);
+        }
+        fo[i] = R(t * (A - 0.5 * B));
+        go[i] = R(t * (Gq - (P.omega_g > 0 ? 1.0 / P.omega_g : 0.0) * eg0));
+    });
+    store<St>(dst, n, PR, fo, go);
+}
+
+// Loads FP64 post-propagation PDFs into the storage format (restart).
+template <class St>
+__global__ void __launch_bounds__(256) load_kernel(const double *f, const double *g,
+                                                   DevParams<typename St::R> P, Buf<St> dst) {
+    using R = typename St::R;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= P.N) return;
+    const size_t N = (size_t)P.N;
+    R fo[19], go[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        fo[i] = R(f[i * N + n]);
+        go[i] = R(g[i * N + n]);
+    }
+    store<St>(dst, n, P, fo, go);
+}
+
+__global__ void clear_int_kernel(int *p) { *p = 0; }
+
+}  // namespace cpf

@@ -1,0 +1,42 @@
+"""Shared helpers of the GPU tests: run the HIP library and the oracle on the
+same seeded workload, and map PDFs between the two lattice orders."""
+import sys
+
+import numpy as np
+
+import oracle
+from paper_2407_12263_amd import lbm
+
+
+def say(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def order_maps():
+    """perm such that gpu[i] = oracle[perm[i]]."""
+    eg, _ = lbm.lbm_lattice()
+    eo, _ = oracle.lattice()
+    perm = [next(k for k in range(19) if tuple(eo[k]) == tuple(eg[i])) for i in range(19)]
+    inv = [perm.index(k) for k in range(19)]
+    return np.array(perm), np.array(inv)
+
+
+def oracle_run(w, steps, **over):
+    prm = w.params()
+    prm.update(over)
+    o = oracle.Oracle(oracle.OracleParams(**prm), w.phi0, w.u0, w.p0)
+    o.step(steps)
+    return o
+
+
+def gpu_solver(w, precision, **over):
+    prm = w.params()
+    prm.update(over)
+    prm["precision"] = precision
+    return lbm.Solver(prm, w.phi0, w.u0, w.p0)
+
+
+def gpu_fields(sol):
+    phi, u, p = sol.fields()
+    return phi.cpu().numpy(), u.cpu().numpy(), p.cpu().numpy()

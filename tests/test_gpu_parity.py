@@ -1,0 +1,219 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 CPU oracle.
+
+Tolerances: FP64 max|dphi| <= 1e-12 and FP32 <= 1e-5 after 100 steps on the
+static droplet (32^3, R = 8, W = 4, tau_f = 0.8, M = 0.02, sigma = 1e-3),
+FP16/BF16 storage <= 2e-3 with relative phase-mass drift <= 1e-6 per 10^4
+steps. Trajectories of the scheme amplify rounding differences in some
+configurations (interface regions where grad(phi) vanishes, walls under
+acceleration); there the oracle's own response to a 1e-15 perturbation
+bounds the horizon of a trajectory comparison, and the step map itself is
+compared from identical states (one-step parity), which no amplification
+can affect.
+"""
+import numpy as np
+import pytest
+
+from paper_2407_12263_amd import inputs
+
+from gpu_common import gpu_fields, gpu_solver, oracle_run, order_maps, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2407_12263_amd import lbm
+    lbm.load_library()
+
+
+def _cmp(w, precision, steps, tol_phi, tol_u=None, tol_p=None, **over):
+    say(f"[parity] {w.name} {precision} steps={steps} over={over}")
+    o = oracle_run(w, steps, **over)
+    sol = gpu_solver(w, precision, **over)
+    sol.step(steps)
+    phi, u, p = gpu_fields(sol)
+    po, uo, qo = o.fields()
+    e_phi = np.abs(phi - po).max()
+    e_u = np.abs(u - uo).max()
+    e_p = np.abs(p - qo).max()
+    say(f"   max|dphi|={e_phi:.3e} max|du|={e_u:.3e} max|dp|={e_p:.3e}")
+    assert e_phi <= tol_phi, e_phi
+    if tol_u is not None:
+        assert e_u <= tol_u, e_u
+    if tol_p is not None:
+        assert e_p <= tol_p, e_p
+    return sol, o
+
+
+# ------------------------------------------------- the headline tolerances
+
+def test_fp64_static_droplet_100_steps():
+    _cmp(inputs.static_droplet(), "fp64", 100, 1e-12, 1e-14, 1e-14)
+
+
+def test_fp32_static_droplet_100_steps():
+    _cmp(inputs.static_droplet(), "fp32", 100, 1e-5, 1e-6, 1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_16bit_storage_static_droplet_100_steps(prec):
+    _cmp(inputs.static_droplet(), prec, 100, 2e-3)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_phase_mass_drift_10k_steps(prec):
+    """Relative drift of sum(phi) over 10^4 steps on the static droplet."""
+    w = inputs.static_droplet()
+    say(f"[mass] {w.name} {prec} 10000 steps")
+    sol = gpu_solver(w, prec)
+    m0 = float(w.phi0.sum())
+    d0 = sol.diagnostics()
+    sol.step(10000)
+    d1 = sol.diagnostics()
+    drift = abs(d1["sum_phi"] - m0) / m0
+    say(f"   sum_phi(0)={d0['sum_phi']:.12e} sum_phi(1e4)={d1['sum_phi']:.12e} drift={drift:.2e}")
+    assert drift <= 1e-6
+
+
+# ----------------------------------------------------- other workloads
+
+SMALL = {
+    "rt": lambda: inputs.rayleigh_taylor(nx=32, ny=128, nz=16),
+    "bubble": lambda: inputs.rising_bubble(nx=32, ny=32, nz=64, R=8, zc=20, g=2e-5),
+    "tg": lambda: inputs.taylor_green_breakup(n=32),
+    "ragged": lambda: inputs.static_droplet(n=13, R=3.5, ny=7, nz=9, sigma=2e-3),
+    "slab": lambda: inputs.static_droplet(n=1, R=4.0, ny=1, nz=64, sigma=2e-3,
+                                          center=(0.0, 0.0, 32.0)),
+}
+
+
+@pytest.mark.parametrize("name,steps", [("bubble", 100), ("tg", 100), ("rt", 10),
+                                        ("ragged", 50), ("slab", 100)])
+def test_fp64_trajectory(name, steps):
+    _cmp(SMALL[name](), "fp64", steps, 1e-12, 1e-13, 1e-13)
+
+
+@pytest.mark.parametrize("name", ["bubble", "tg"])
+def test_fp32_trajectory(name):
+    _cmp(SMALL[name](), "fp32", 100, 1e-5)
+
+
+def test_fp64_exact_streaming_c1():
+    _cmp(inputs.static_droplet(courant=1.0), "fp64", 20, 1e-12, 1e-13, 1e-13)
+
+
+def test_fp64_walls_all_faces_small_box():
+    w = inputs.rising_bubble(nx=6, ny=5, nz=12, R=2.0, zc=6.0, g=1e-4)
+    _cmp(w, "fp64", 50, 1e-12, 1e-13, 1e-13)
+
+
+@pytest.mark.parametrize("name", ["rt", "bubble", "tg", "ragged"])
+@pytest.mark.parametrize("courant", [0.997, 1.0])
+def test_one_step_parity_from_oracle_state(name, courant):
+    """The GPU step map equals the oracle's: both advance the oracle's state
+    at t = 30 by one step."""
+    w = SMALL[name]().with_(courant=courant)
+    say(f"[one-step] {w.name} c={courant}")
+    perm, _ = order_maps()
+    o = oracle_run(w, 30)
+    f, g = o.pdfs()
+    sol = gpu_solver(w, "fp64")
+    sol.set_pdfs(f[perm], g[perm])
+    # moments of the loaded state agree before stepping
+    phi0, u0, p0 = gpu_fields(sol)
+    po, uo, qo = o.fields()
+    assert np.abs(phi0 - po).max() < 1e-14
+    o.step(1)
+    sol.step(1)
+    phi, u, p = gpu_fields(sol)
+    po, uo, qo = o.fields()
+    fg, gg = sol.get_pdfs()
+    fo, go = o.pdfs()
+    e = [np.abs(phi - po).max(), np.abs(u - uo).max(), np.abs(p - qo).max(),
+         np.abs(fg.cpu().numpy() - fo[perm]).max(), np.abs(gg.cpu().numpy() - go[perm]).max()]
+    say("   " + " ".join(f"{x:.2e}" for x in e))
+    assert max(e) < 1e-14
+
+
+# ------------------------------------------------ state, outputs, errors
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-15), ("fp32", 1e-6), ("fp16", 2e-3),
+                                      ("bf16", 2e-3)])
+def test_initial_moments_return_inputs(prec, tol):
+    w = inputs.taylor_green_breakup(n=32)
+    say(f"[init] {w.name} {prec}")
+    sol = gpu_solver(w, prec)
+    phi, u, p = gpu_fields(sol)
+    assert np.abs(phi - w.phi0).max() < tol
+    assert np.abs(u - w.u0).max() < tol * 0.1
+    assert np.abs(p - w.p0).max() < tol * 0.1
+
+
+def test_diagnostics_match_oracle():
+    w = inputs.static_droplet()
+    say(f"[diag] {w.name} fp64")
+    o = oracle_run(w, 100)
+    sol = gpu_solver(w, "fp64")
+    sol.step(100)
+    d = sol.diagnostics(w.phi0)
+    do = o.diag(w.phi0)
+    assert d["step"] == 100
+    assert abs(d["sum_phi"] - do["sum_phi"]) < 1e-12 * do["sum_phi"]
+    assert abs(d["mass"] - do["mass"]) < 1e-12 * do["mass"]
+    assert abs(d["ekin"] - do["ekin"]) < 1e-9 * do["ekin"]
+    assert abs(d["umax"] - do["umax"]) < 1e-9 * do["umax"]
+    assert abs(d["phi_min"] - do["phi_min"]) < 1e-12
+    assert abs(d["phi_max"] - do["phi_max"]) < 1e-12
+    for a, k in enumerate("xyz"):
+        assert abs(d["com"][a] - do["com" + k]) < 1e-12 * do["com" + k]
+        assert abs(d["mom"][a] - do["mom" + k]) < 1e-14 * w.N
+    assert abs(d["l2_num"] - do["l2_num"]) < 1e-9 * do["l2_num"]
+    assert abs(d["l2_den"] - do["l2_den"]) < 1e-12 * do["l2_den"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_checkpoint_restart_bitwise(prec):
+    """200 steps straight equal 100 steps, get_pdfs / set_pdfs, 100 steps."""
+    w = SMALL["tg"]()
+    say(f"[restart] {w.name} {prec}")
+    a = gpu_solver(w, prec)
+    a.step(200)
+    b = gpu_solver(w, prec)
+    b.step(100)
+    f, g = b.get_pdfs()
+    c = gpu_solver(w, prec)
+    c.set_pdfs(f, g)
+    c.step(100)
+    pa = a.fields()[0].cpu().numpy()
+    pc = c.fields()[0].cpu().numpy()
+    assert np.array_equal(pa, pc)
+
+
+def test_invalid_initial_field_rejected():
+    from paper_2407_12263_amd import lbm
+    w = inputs.static_droplet(n=8, R=2.0)
+    phi = w.phi0.copy()
+    phi[1, 2, 3] = np.nan
+    say("[errors] NaN in phi0")
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Solver(dict(w.params(), precision="fp32"), phi)
+    assert ei.value.status == lbm.LBM_EINVAL
+
+
+def test_instability_check_reports():
+    """A velocity above the sound speed is caught by the periodic check."""
+    from paper_2407_12263_amd import lbm
+    w = inputs.static_droplet(n=8, R=2.0)
+    u0 = np.zeros((3,) + w.shape)
+    u0[0] = 0.9
+    say("[errors] supersonic initial velocity with check_every=1")
+    sol = lbm.Solver(dict(w.params(), precision="fp32", check_every=1), w.phi0, u0)
+    with pytest.raises(lbm.LbmError) as ei:
+        sol.step(5)
+    assert ei.value.status == lbm.LBM_EUNSTABLE
+    with pytest.raises(lbm.LbmError) as ei:
+        sol.step(1)
+    assert ei.value.status == lbm.LBM_ESTATE
