@@ -63,7 +63,8 @@ typedef enum {
 } lbm_precision;
 
 typedef struct {
-    int32_t nx, ny, nz;        /* lattice size; N = nx*ny*nz, 19*N < 2^31     */
+    int32_t nx, ny, nz;        /* lattice size; N = nx*ny*nz, 19*N < 2^31 and */
+                               /* 19*N*bytes per value < 2^32                 */
     int32_t precision;         /* lbm_precision                               */
     int32_t wall[3];           /* per axis: 0 periodic, 1 no-slip walls on    */
                                /* both faces (halfway between nodes; neutral  */

@@ -20,10 +20,15 @@ using namespace cpf;
 
 namespace {
 
-constexpr int kBlock = 256;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// one block per TILE_X x TILE_Y tile of one z-plane
+size_t num_tiles(const lbm_params *P) {
+    const size_t ntx = (P->nx + TILE_X - 1) / TILE_X, nty = (P->ny + TILE_Y - 1) / TILE_Y;
+    return ntx * nty * (size_t)P->nz;
+}
 
 size_t elem_bytes(int precision) {
     switch (precision) {
@@ -50,7 +55,7 @@ struct Layout {
 Layout layout_of(const lbm_params *P) {
     Layout L;
     const size_t N = (size_t)P->nx * P->ny * P->nz;
-    const size_t nblocks = (N + kBlock - 1) / kBlock;
+    const size_t nblocks = num_tiles(P);
     L.pdf_bytes = align_up(19 * N * elem_bytes(P->precision));
     L.phis_bytes = is16(P->precision) ? align_up(N * sizeof(float)) : 0;
     L.buf_bytes = 2 * L.pdf_bytes + L.phis_bytes;
@@ -67,6 +72,8 @@ int validate(const lbm_params *P) {
     const double N = (double)P->nx * P->ny * P->nz;
     if (19.0 * N >= 2147483647.0) return LBM_EINVAL;
     if (P->precision < LBM_FP64 || P->precision > LBM_FP32_BF16STORE) return LBM_EINVAL;
+    // every population field is addressed through one 32-bit buffer range
+    if (19.0 * N * (double)elem_bytes(P->precision) >= 4294967295.0) return LBM_EINVAL;
     const int nn[3] = {P->nx, P->ny, P->nz};
     for (int a = 0; a < 3; ++a) {
         if (P->wall[a] != 0 && P->wall[a] != 1) return LBM_EINVAL;
@@ -97,10 +104,17 @@ DevParams<R> make_params(const lbm_params *P) {
     d.nz = P->nz;
     d.N = P->nx * P->ny * P->nz;
     for (int a = 0; a < 3; ++a) d.wall[a] = P->wall[a];
+    d.ntx = (P->nx + TILE_X - 1) / TILE_X;
+    d.nty = (P->ny + TILE_Y - 1) / TILE_Y;
+    d.ntiles = d.ntx * d.nty * P->nz;
+    d.xq = d.ntiles / 8;
+    d.xr = d.ntiles % 8;
     const double c = P->courant, cs2 = c * c / 3.0;
     const double eta1 = P->rho1 * cs2 * P->tau_rho1, eta2 = P->rho2 * cs2 * P->tau_rho2;
     d.c = R(c);
     d.h = R(0.5 * c * (1.0 - c));
+    d.lwA = R(0.5 * c * (1.0 + c));
+    d.lwD = R(-0.5 * c * (1.0 - c));
     d.cs2 = R(cs2);
     d.inv_cs2 = R(1.0 / cs2);
     d.half_inv_cs4 = R(0.5 / (cs2 * cs2));
@@ -171,7 +185,7 @@ template <class St, Mode M, bool W>
 void launch_step(lbm_ctx *c, int src, int dst) {
     using R = typename St::R;
     const DevParams<R> P = make_params<R>(&c->P);
-    hipLaunchKernelGGL((step_kernel<St, M, W>), dim3(c->nblocks), dim3(kBlock), 0, c->stream,
+    hipLaunchKernelGGL((step_kernel<St, M, W>), dim3(c->nblocks), dim3(BLOCK), 0, c->stream,
                        cbuf_of<St>(c, src), buf_of<St>(c, dst), P);
 }
 
@@ -206,7 +220,7 @@ template <class St, Mode M, bool W>
 void launch_moments(lbm_ctx *c, const FieldOut &o) {
     using R = typename St::R;
     const DevParams<R> P = make_params<R>(&c->P);
-    hipLaunchKernelGGL((moments_kernel<St, M, W>), dim3(c->nblocks), dim3(kBlock), 0, c->stream,
+    hipLaunchKernelGGL((moments_kernel<St, M, W>), dim3(c->nblocks), dim3(BLOCK), 0, c->stream,
                        cbuf_of<St>(c, c->cur ^ 1), P, o);
 }
 
@@ -240,10 +254,10 @@ void launch_init(lbm_ctx *c, const double *phi0, const double *u0, const double 
     const DevParams<R> PR = make_params<R>(&c->P);
     const bool walls = c->P.wall[0] || c->P.wall[1] || c->P.wall[2];
     if (walls)
-        hipLaunchKernelGGL((init_kernel<St, true>), dim3(c->nblocks), dim3(kBlock), 0, c->stream,
+        hipLaunchKernelGGL((init_kernel<St, true>), dim3(c->nblocks), dim3(BLOCK), 0, c->stream,
                            phi0, u0, p0, PD, PR, buf_of<St>(c, dst), c->flag);
     else
-        hipLaunchKernelGGL((init_kernel<St, false>), dim3(c->nblocks), dim3(kBlock), 0, c->stream,
+        hipLaunchKernelGGL((init_kernel<St, false>), dim3(c->nblocks), dim3(BLOCK), 0, c->stream,
                            phi0, u0, p0, PD, PR, buf_of<St>(c, dst), c->flag);
 }
 
@@ -260,7 +274,7 @@ template <class St>
 void launch_load(lbm_ctx *c, const double *f, const double *g, int dst) {
     using R = typename St::R;
     const DevParams<R> P = make_params<R>(&c->P);
-    hipLaunchKernelGGL((load_kernel<St>), dim3(c->nblocks), dim3(kBlock), 0, c->stream, f, g, P,
+    hipLaunchKernelGGL((load_kernel<St>), dim3(c->nblocks), dim3(BLOCK), 0, c->stream, f, g, P,
                        buf_of<St>(c, dst));
 }
 
@@ -279,7 +293,7 @@ int reduce_diag(lbm_ctx *c, const double *phi_ref) {
     o.phi_ref = phi_ref;
     o.partials = c->partials;
     moments_any(c, o);
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kBlock), 0, c->stream,
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, c->stream,
                        (const double *)c->partials, c->nblocks, c->result);
     return check_launch(c);
 }
@@ -329,8 +343,7 @@ int lbm_init(const lbm_params *P, void *d_workspace, size_t bytes, void *stream,
     c->partials = (double *)(c->ws + 2 * L.buf_bytes);
     c->result = (double *)(c->ws + 2 * L.buf_bytes + L.partial_bytes);
     c->flag = (int *)(c->ws + 2 * L.buf_bytes + L.partial_bytes + L.result_bytes);
-    const size_t N = (size_t)P->nx * P->ny * P->nz;
-    c->nblocks = (int)((N + kBlock - 1) / kBlock);
+    c->nblocks = (int)num_tiles(P);
     c->status = LBM_OK;
 
     hipLaunchKernelGGL(clear_int_kernel, dim3(1), dim3(1), 0, c->stream, c->flag);

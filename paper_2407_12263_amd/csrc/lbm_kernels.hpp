@@ -8,6 +8,15 @@
 // operation is the propagation; the interface normal and grad(phi) come from
 // the node's own K1 (Sec. 2.3), so no neighbour field is ever differenced.
 //
+// Memory access: structure-of-arrays planes (population i of all nodes is
+// contiguous, x fastest), read and written with buffer instructions whose
+// plane offset i*N*size is a scalar register and whose per-lane offset is
+// one of the 19 stencil-node offsets computed once per thread, so no vector
+// instruction is spent on addresses. A block is a 64 x 4 tile of one z-plane
+// (a wavefront is one 64-node x-row: every load is a coalesced row segment);
+// tiles are handed to the 8 XCDs in contiguous runs so that the y- and
+// z-neighbour rows a tile re-reads sit in the same L2.
+//
 // Precision policies: FP64; FP32; FP32 compute with 16-bit storage of the
 // deviations f_i - t_i rho0 and g_i - t_i phi_s scaled by 2^k (FP16 or
 // BF16, round-to-nearest-even) plus the FP32 per-node phi_s chosen so that the
@@ -86,11 +95,16 @@ __device__ __forceinline__ R edot(const R (&v)[3]) {
 }
 
 // ------------------------------------------------------------ parameters
+constexpr int TILE_X = 64, TILE_Y = 4, BLOCK = TILE_X * TILE_Y;
+
 template <class R>
 struct DevParams {
     int nx, ny, nz, N;
     int wall[3];
+    int ntx, nty, ntiles;    // tiles of TILE_X x TILE_Y nodes in a z-plane, all planes
+    int xq, xr;              // ntiles = 8 xq + xr (XCD runs)
     R c, h;                  // Courant number, c(1-c)/2
+    R lwA, lwD;              // Lax-Wendroff weights of x-e and x+e: c(1+c)/2, -c(1-c)/2
     R cs2, inv_cs2, half_inv_cs4;
     R rho2, drho;            // rho = rho2 + drho*phi
     R eta2, deta;            // eta = eta2 + deta*phi
@@ -144,43 +158,88 @@ struct CBuf {
     const float *phis;
 };
 
+// ------------------------------------------------------- buffer access
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+// Raw buffer over [p, p + bytes); accesses beyond it read 0 and write nothing.
+// Word 3 is the gfx9-family raw-buffer configuration.
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+template <class T>
+__device__ __forceinline__ T bload(rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 8) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    } else if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void bstore(T v, rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 8) {
+        using V2 = unsigned int __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, soff, 0);
+    } else if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff, 0);
+    }
+}
+
 // ------------------------------------------------------- node geometry
 struct Site {
-    int n;
-    int X[3];            // x-1, x, x+1 (wrapped)
-    int Y[3];            // (y-1)*nx, y*nx, (y+1)*nx (wrapped)
-    int Z[3];            // likewise times nx*ny
+    int x, y, z;
+    bool valid;
+    uint32_t n;          // node index
+    uint32_t nb[19];     // index of node x + e^_j (wrapped), nb[0] = n
     bool lo[3], hi[3];   // node on the first / last layer of a wall axis
-
-    template <int dx, int dy, int dz>
-    __device__ __forceinline__ int at() const { return X[dx + 1] + Y[dy + 1] + Z[dz + 1]; }
+    bool wall;           // lo or hi on some axis
 };
 
+// Block -> tile: workgroups go round-robin to the 8 XCDs; XCD k takes the
+// contiguous run of tiles [start_k, start_k + count_k), so neighbouring tiles
+// (and the z-planes above and below) share an L2.
 template <class R>
-__device__ __forceinline__ Site make_site(const DevParams<R> &P, int n) {
+__device__ __forceinline__ Site make_site(const DevParams<R> &P) {
     Site s;
-    s.n = n;
-    const int nxy = P.nx * P.ny;
-    const int z = n / nxy;
-    const int r = n - z * nxy;
-    const int y = r / P.nx;
-    const int x = r - y * P.nx;
-    s.X[1] = x;
-    s.X[0] = x == 0 ? P.nx - 1 : x - 1;
-    s.X[2] = x == P.nx - 1 ? 0 : x + 1;
-    s.Y[1] = y * P.nx;
-    s.Y[0] = (y == 0 ? P.ny - 1 : y - 1) * P.nx;
-    s.Y[2] = (y == P.ny - 1 ? 0 : y + 1) * P.nx;
-    s.Z[1] = z * nxy;
-    s.Z[0] = (z == 0 ? P.nz - 1 : z - 1) * nxy;
-    s.Z[2] = (z == P.nz - 1 ? 0 : z + 1) * nxy;
+    const uint32_t b = blockIdx.x;
+    const uint32_t xcd = b & 7u, slot = b >> 3;
+    const uint32_t q = (uint32_t)P.xq, r = (uint32_t)P.xr;
+    const uint32_t t = (xcd < r ? xcd * (q + 1u) : r * (q + 1u) + (xcd - r) * q) + slot;
+    const uint32_t ntx = (uint32_t)P.ntx, nty = (uint32_t)P.nty;
+    const uint32_t tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+    s.x = (int)(tx * TILE_X + (threadIdx.x % TILE_X));
+    s.y = (int)(ty * TILE_Y + (threadIdx.x / TILE_X));
+    s.z = (int)tz;
+    s.valid = s.x < P.nx && s.y < P.ny && s.z < P.nz;
+    const int x = s.valid ? s.x : 0, y = s.valid ? s.y : 0, z = s.valid ? s.z : 0;
+    const uint32_t nx = P.nx, nxy = (uint32_t)P.nx * P.ny;
+    const uint32_t X[3] = {uint32_t(x == 0 ? P.nx - 1 : x - 1), uint32_t(x),
+                           uint32_t(x == P.nx - 1 ? 0 : x + 1)};
+    const uint32_t Y[3] = {uint32_t(y == 0 ? P.ny - 1 : y - 1) * nx, uint32_t(y) * nx,
+                           uint32_t(y == P.ny - 1 ? 0 : y + 1) * nx};
+    const uint32_t Z[3] = {uint32_t(z == 0 ? P.nz - 1 : z - 1) * nxy, uint32_t(z) * nxy,
+                           uint32_t(z == P.nz - 1 ? 0 : z + 1) * nxy};
+    unroll<0, 19>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        s.nb[j] = X[Lat::EX[j] + 1] + Y[Lat::EY[j] + 1] + Z[Lat::EZ[j] + 1];
+    });
+    s.n = s.nb[0];
     const int c[3] = {x, y, z};
     const int nn[3] = {P.nx, P.ny, P.nz};
+    s.wall = false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         s.lo[a] = P.wall[a] && c[a] == 0;
         s.hi[a] = P.wall[a] && c[a] == nn[a] - 1;
+        s.wall = s.wall || s.lo[a] || s.hi[a];
     }
+    s.wall = s.wall && s.valid;
     return s;
 }
 
@@ -201,91 +260,147 @@ __device__ __forceinline__ bool beyond_wall(const Site &s) {
 // ------------------------------------------------------------ propagation
 enum Mode { LOCAL = 0, SHIFT = 1, LW = 2 };
 
-// Reads population i (f or g) at node index m, as a value of the field.
-template <class St, bool IS_G>
-struct Reader {
-    using R = typename St::R;
-    const typename St::T *plane0;
-    const float *phis;
-    int N;
-    R rho0, iscale;
-
-    template <int i>
-    __device__ __forceinline__ R get(int m, R phis_m) const {
-        const typename St::T v = plane0[(size_t)i * N + m];
-        if constexpr (St::DEV) {
-            constexpr R t = wgt<R>(Lat::cls(i));
-            const R base = IS_G ? t * phis_m : t * rho0;
-            return fma(iscale, decode<St>(v), base);
-        } else {
-            return R(v);
-        }
-    }
+template <class St>
+struct Src {
+    rsrc_t f, g, phis;
+    uint32_t plane;      // bytes of one population plane (N * sizeof(T))
 };
 
-// Lax-Wendroff propagation of one population in flux form (Sec. 2.2):
-//   out = a0 + [flux in through x - e/2] - [flux out through x + e/2],
-//   flux(x + e/2) = c a(x) + h (a(x+e) - a(x)),   h = c(1-c)/2,
-// which equals the printed three-point form in the interior and sums to zero
-// over the lattice in floating point too (each face flux is computed
-// bit-identically by both of its nodes). A face beyond a wall takes the
-// node itself as its far value and returns its outgoing flux into the
-// opposite population (halfway bounce-back at c = 1).
-template <Mode M, bool WALLS, class St, bool IS_G, int i>
-__device__ __forceinline__ typename St::R pull(const Reader<St, IS_G> &rd, const Site &s,
-                                               const DevParams<typename St::R> &P,
-                                               const typename St::R (&ph)[19]) {
-    using R = typename St::R;
-    constexpr int ex = Lat::EX[i], ey = Lat::EY[i], ez = Lat::EZ[i];
-    constexpr int o = Lat::OPP[i];
-    if constexpr (M == LOCAL || i == 0) {
-        return rd.template get<i>(s.n, ph[0]);
-    } else if constexpr (M == SHIFT) {
-        const R am = rd.template get<i>(s.template at<-ex, -ey, -ez>(), ph[o]);
-        if constexpr (WALLS) {
-            if (beyond_wall<i, 1>(s)) return rd.template get<o>(s.n, ph[0]);
-        }
-        return am;
-    } else {
-        const R a0 = rd.template get<i>(s.n, ph[0]);
-        const R am = rd.template get<i>(s.template at<-ex, -ey, -ez>(), ph[o]);
-        const R ap = rd.template get<i>(s.template at<ex, ey, ez>(), ph[i]);
-        R fout = fma(P.h, ap - a0, P.c * a0);
-        R fin = fma(P.h, a0 - am, P.c * am);
-        if constexpr (WALLS) {
-            if (beyond_wall<i, -1>(s)) fout = P.c * a0;
-            if (beyond_wall<i, 1>(s)) fin = P.c * rd.template get<o>(s.n, ph[0]);
-        }
-        return a0 + (fin - fout);
-    }
+template <class St>
+__device__ __forceinline__ Src<St> make_src(const CBuf<St> &b, const DevParams<typename St::R> &P) {
+    Src<St> s;
+    const uint32_t plane = (uint32_t)P.N * (uint32_t)sizeof(typename St::T);
+    s.plane = plane;
+    s.f = make_rsrc(b.f, 19u * plane);
+    s.g = make_rsrc(b.g, 19u * plane);
+    s.phis = make_rsrc(b.phis, St::DEV ? (uint32_t)P.N * 4u : 0u);
+    return s;
 }
 
-// Gathers the post-propagation f and g of one node.
+// raw stored value of population i at stencil node j
+template <class St, int i>
+__device__ __forceinline__ typename St::R raw(rsrc_t r, const Src<St> &src, const Site &s, int j) {
+    using T = typename St::T;
+    const T v = bload<T>(r, s.nb[j] * (uint32_t)sizeof(T), (uint32_t)i * src.plane);
+    if constexpr (St::DEV) return decode<St>(v);
+    else return typename St::R(v);
+}
+
+// Lax-Wendroff step of one population from its three taps (Sec. 2.2):
+// a0 - c[a0 - am] - c(1-c)/2 [ap - 2 a0 + am] = a0 + A (am - a0) + D (ap - a0).
+template <class R>
+__device__ __forceinline__ R lw3(const DevParams<R> &P, R am, R a0, R ap) {
+    return fma(P.lwA, am - a0, fma(P.lwD, ap - a0, a0));
+}
+
+// Same step in flux form next to a wall: out = a0 + [in flux] - [out flux],
+// flux(x + e/2) = c a(x) + h (a(x+e) - a(x)), h = c(1-c)/2; a face beyond a
+// wall takes the node itself as its far value and returns its outgoing flux
+// into the opposite population (halfway bounce-back at c = 1).
+template <class R>
+__device__ __forceinline__ R lw_wall(const DevParams<R> &P, R am, R a0, R ap, R aopp,
+                                     bool up_solid, bool dn_solid) {
+    const R fout = dn_solid ? P.c * a0 : fma(P.h, ap - a0, P.c * a0);
+    const R fin = up_solid ? P.c * aopp : fma(P.h, a0 - am, P.c * am);
+    return a0 + (fin - fout);
+}
+
+// Gathers the post-propagation f and g of one node. WALLS selects the
+// wall-aware path (used only by wavefronts that contain a wall node).
 template <Mode M, bool WALLS, class St>
-__device__ __forceinline__ void gather(const CBuf<St> &src, const Site &s,
+__device__ __forceinline__ void gather(const Src<St> &src, const Site &s,
                                        const DevParams<typename St::R> &P,
                                        typename St::R (&fb)[19], typename St::R (&gb)[19]) {
     using R = typename St::R;
-    R ph[19];  // phi_s at the stencil nodes x + e^_i (16-bit storage only)
+    R ph[19];  // phi_s at the stencil nodes x + e^_j (16-bit storage only)
     if constexpr (St::DEV) {
-        unroll<0, 19>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            if constexpr (M == LOCAL) {
-                if constexpr (i == 0) ph[0] = src.phis[s.n];
-                else ph[i] = R(0);
+        unroll<0, 19>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            if constexpr (M == LOCAL && j > 0) {
+                ph[j] = R(0);
             } else {
-                ph[i] = src.phis[s.template at<Lat::EX[i], Lat::EY[i], Lat::EZ[i]>()];
+                ph[j] = bload<float>(src.phis, s.nb[j] * 4u, 0u);
             }
         });
-    } else {
-        unroll<0, 19>([&](auto I) { ph[decltype(I)::value] = R(0); });
     }
-    const Reader<St, false> rf{src.f, src.phis, P.N, P.rho0, P.iscale_f};
-    const Reader<St, true> rg{src.g, src.phis, P.N, P.rho0, P.iscale_g};
     unroll<0, 19>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        fb[i] = pull<M, WALLS, St, false, i>(rf, s, P, ph);
-        gb[i] = pull<M, WALLS, St, true, i>(rg, s, P, ph);
+        constexpr int o = Lat::OPP[i];
+        constexpr R t = wgt<R>(Lat::cls(i));
+        if constexpr (M == LOCAL || i == 0) {
+            const R hf = raw<St, i>(src.f, src, s, 0);
+            const R hg = raw<St, i>(src.g, src, s, 0);
+            if constexpr (St::DEV) {
+                fb[i] = fma(P.iscale_f, hf, t * P.rho0);
+                gb[i] = fma(P.iscale_g, hg, t * ph[0]);
+            } else {
+                fb[i] = hf;
+                gb[i] = hg;
+            }
+        } else if constexpr (!WALLS) {
+            const R fm = raw<St, i>(src.f, src, s, o);
+            const R gm = raw<St, i>(src.g, src, s, o);
+            if constexpr (M == SHIFT) {
+                if constexpr (St::DEV) {
+                    fb[i] = fma(P.iscale_f, fm, t * P.rho0);
+                    gb[i] = fma(P.iscale_g, gm, t * ph[o]);
+                } else {
+                    fb[i] = fm;
+                    gb[i] = gm;
+                }
+            } else {
+                const R f0 = raw<St, i>(src.f, src, s, 0);
+                const R fp = raw<St, i>(src.f, src, s, i);
+                const R g0 = raw<St, i>(src.g, src, s, 0);
+                const R gp = raw<St, i>(src.g, src, s, i);
+                if constexpr (St::DEV) {
+                    // propagate the stored deviations and the phi_s bases apart
+                    fb[i] = fma(P.iscale_f, lw3(P, fm, f0, fp), t * P.rho0);
+                    gb[i] = fma(P.iscale_g, lw3(P, gm, g0, gp), t * lw3(P, ph[o], ph[0], ph[i]));
+                } else {
+                    fb[i] = lw3(P, fm, f0, fp);
+                    gb[i] = lw3(P, gm, g0, gp);
+                }
+            }
+        } else {
+            // wall-aware: the wall-free result for nodes whose taps are all
+            // inside, the flux form with bounce-back for populations that
+            // cross a wall face (full values of the taps and of the opposite
+            // population at the node)
+            const bool up = beyond_wall<i, 1>(s), dn = beyond_wall<i, -1>(s);
+            const R hfm = raw<St, i>(src.f, src, s, o), hgm = raw<St, i>(src.g, src, s, o);
+            const R hfo = raw<St, o>(src.f, src, s, 0), hgo = raw<St, o>(src.g, src, s, 0);
+            auto full_f = [&](R h) -> R {
+                if constexpr (St::DEV) return fma(P.iscale_f, h, t * P.rho0);
+                else return h;
+            };
+            auto full_g = [&](R h, R phs) -> R {
+                if constexpr (St::DEV) return fma(P.iscale_g, h, t * phs);
+                else return h;
+            };
+            if constexpr (M == SHIFT) {
+                fb[i] = up ? full_f(hfo) : full_f(hfm);
+                gb[i] = up ? full_g(hgo, ph[0]) : full_g(hgm, ph[o]);
+            } else {
+                const R hf0 = raw<St, i>(src.f, src, s, 0), hfp = raw<St, i>(src.f, src, s, i);
+                const R hg0 = raw<St, i>(src.g, src, s, 0), hgp = raw<St, i>(src.g, src, s, i);
+                R ff, gg;
+                if constexpr (St::DEV) {
+                    ff = fma(P.iscale_f, lw3(P, hfm, hf0, hfp), t * P.rho0);
+                    gg = fma(P.iscale_g, lw3(P, hgm, hg0, hgp), t * lw3(P, ph[o], ph[0], ph[i]));
+                } else {
+                    ff = lw3(P, hfm, hf0, hfp);
+                    gg = lw3(P, hgm, hg0, hgp);
+                }
+                if (up || dn) {
+                    ff = lw_wall(P, full_f(hfm), full_f(hf0), full_f(hfp), full_f(hfo), up, dn);
+                    gg = lw_wall(P, full_g(hgm, ph[o]), full_g(hg0, ph[0]), full_g(hgp, ph[i]),
+                                 full_g(hgo, ph[0]), up, dn);
+                }
+                fb[i] = ff;
+                gb[i] = gg;
+            }
+        }
     });
 }
 
@@ -438,19 +553,38 @@ __device__ __forceinline__ void collide(const DevParams<R> &P, const Macro<R> &m
     });
 }
 
+
 // ---------------------------------------------------------------- store
 template <class St>
-__device__ __forceinline__ void store(const Buf<St> &dst, int n,
+struct Dst {
+    rsrc_t f, g, phis;
+    uint32_t plane;
+};
+
+template <class St>
+__device__ __forceinline__ Dst<St> make_dst(const Buf<St> &b, const DevParams<typename St::R> &P) {
+    Dst<St> d;
+    const uint32_t plane = (uint32_t)P.N * (uint32_t)sizeof(typename St::T);
+    d.plane = plane;
+    d.f = make_rsrc(b.f, 19u * plane);
+    d.g = make_rsrc(b.g, 19u * plane);
+    d.phis = make_rsrc(b.phis, St::DEV ? (uint32_t)P.N * 4u : 0u);
+    return d;
+}
+
+template <class St>
+__device__ __forceinline__ void store(const Dst<St> &dst, uint32_t n,
                                       const DevParams<typename St::R> &P,
                                       const typename St::R (&fs)[19],
                                       const typename St::R (&gs)[19]) {
     using R = typename St::R;
-    const size_t N = (size_t)P.N;
+    using T = typename St::T;
+    const uint32_t voff = n * (uint32_t)sizeof(T);
     if constexpr (!St::DEV) {
         unroll<0, 19>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            dst.f[i * N + n] = fs[i];
-            dst.g[i * N + n] = gs[i];
+            bstore<T>(T(fs[i]), dst.f, voff, (uint32_t)i * dst.plane);
+            bstore<T>(T(gs[i]), dst.g, voff, (uint32_t)i * dst.plane);
         });
     } else {
         R phi_a = gs[0];
@@ -460,34 +594,40 @@ __device__ __forceinline__ void store(const Buf<St> &dst, int n,
         unroll<0, 19>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr R t = wgt<R>(Lat::cls(i));
-            const typename St::T hf = encode<St>(P.scale_f * (fs[i] - t * P.rho0));
+            const T hf = encode<St>(P.scale_f * (fs[i] - t * P.rho0));
             const R dg = fma(-t, phi_a, gs[i]);
-            const typename St::T hg = encode<St>(P.scale_g * dg);
+            const T hg = encode<St>(P.scale_g * dg);
             resid += fma(-P.iscale_g, decode<St>(hg), dg);
-            dst.f[i * N + n] = hf;
-            dst.g[i * N + n] = hg;
+            bstore<T>(hf, dst.f, voff, (uint32_t)i * dst.plane);
+            bstore<T>(hg, dst.g, voff, (uint32_t)i * dst.plane);
         });
         // sum_i (t_i phi_s + 2^-k h_i) = sum_i g*_i: the storage rounding of g
         // is absorbed by phi_s, so the node keeps its phase mass
-        dst.phis[n] = phi_a + resid;
+        bstore<float>(phi_a + resid, dst.phis, n * 4u, 0u);
     }
 }
 
 // ---------------------------------------------------------------- kernels
 // Fused step: propagate (mode M) from src, moments, collide, store to dst.
+// Wavefronts without a wall node take the wall-free propagation.
 template <class St, Mode M, bool WALLS>
-__global__ void __launch_bounds__(256) step_kernel(CBuf<St> src, Buf<St> dst,
-                                                   DevParams<typename St::R> P) {
+__global__ void __launch_bounds__(BLOCK) step_kernel(CBuf<St> src, Buf<St> dst,
+                                                     DevParams<typename St::R> P) {
     using R = typename St::R;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= P.N) return;
-    const Site s = make_site(P, n);
+    const Site s = make_site(P);
+    if (!s.valid) return;
+    const Src<St> in = make_src(src, P);
     R fb[19], gb[19];
-    gather<M, WALLS, St>(src, s, P, fb, gb);
+    if constexpr (WALLS) {
+        if (__any(s.wall)) gather<M, true, St>(in, s, P, fb, gb);
+        else gather<M, false, St>(in, s, P, fb, gb);
+    } else {
+        gather<M, false, St>(in, s, P, fb, gb);
+    }
     const Macro<R> m = moments(P, fb, gb);
     const NodeCoef<R> q = node_coef(P, m);
     collide(P, m, q, fb, gb);
-    store<St>(dst, n, P, fb, gb);
+    store<St>(make_dst(dst, P), s.n, P, fb, gb);
 }
 
 // Number of FP64 partial sums per block in the diagnostics reduction.
@@ -522,23 +662,22 @@ __device__ __forceinline__ double wave_min(double v) {
 // Moments of the state at t (propagation mode M from the previous buffer):
 // fields, FP64 PDFs and/or per-block FP64 partial sums of the diagnostics.
 template <class St, Mode M, bool WALLS>
-__global__ void __launch_bounds__(256) moments_kernel(CBuf<St> src, DevParams<typename St::R> P,
-                                                      FieldOut out) {
+__global__ void __launch_bounds__(BLOCK) moments_kernel(CBuf<St> src, DevParams<typename St::R> P,
+                                                        FieldOut out) {
     using R = typename St::R;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = n < P.N;
+    const Site s = make_site(P);
     double acc[NSUM];
 #pragma unroll
     for (int k = 0; k < NSUM; ++k) acc[k] = 0.0;
-    acc[6] = 0.0;
     acc[7] = 1e300;
     acc[8] = -1e300;
-    if (live) {
-        const Site s = make_site(P, n);
+    if (s.valid) {
+        const Src<St> in = make_src(src, P);
         R fb[19], gb[19];
-        gather<M, WALLS, St>(src, s, P, fb, gb);
+        if (WALLS && __any(s.wall)) gather<M, WALLS, St>(in, s, P, fb, gb);
+        else gather<M, false, St>(in, s, P, fb, gb);
         const Macro<R> m = moments(P, fb, gb);
-        const size_t N = (size_t)P.N;
+        const size_t N = (size_t)P.N, n = s.n;
         if (out.phi) {
             if (out.dtype == 0) ((double *)out.phi)[n] = m.phi;
             else ((float *)out.phi)[n] = (float)m.phi;
@@ -564,9 +703,6 @@ __global__ void __launch_bounds__(256) moments_kernel(CBuf<St> src, DevParams<ty
             const double phi = m.phi, rho = m.rho;
             const double ux = m.u[0], uy = m.u[1], uz = m.u[2];
             const double uu = ux * ux + uy * uy + uz * uz;
-            const int z = n / (P.nx * P.ny);
-            const int y = (n - z * P.nx * P.ny) / P.nx;
-            const int x = n - (z * P.ny + y) * P.nx;
             acc[0] = phi;
             acc[1] = rho * phi;
             acc[2] = rho * ux;
@@ -576,9 +712,9 @@ __global__ void __launch_bounds__(256) moments_kernel(CBuf<St> src, DevParams<ty
             acc[6] = sqrt(uu);
             acc[7] = phi;
             acc[8] = phi;
-            acc[9] = phi * x;
-            acc[10] = phi * y;
-            acc[11] = phi * z;
+            acc[9] = phi * s.x;
+            acc[10] = phi * s.y;
+            acc[11] = phi * s.z;
             acc[12] = phi * ux;
             acc[13] = phi * uy;
             acc[14] = phi * uz;
@@ -591,7 +727,7 @@ __global__ void __launch_bounds__(256) moments_kernel(CBuf<St> src, DevParams<ty
     }
     if (out.partials) {
         // deterministic block reduction: wave shuffles, then waves in order
-        __shared__ double red[4][NSUM];
+        __shared__ double red[BLOCK / 64][NSUM];
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
         for (int k = 0; k < NSUM; ++k) {
@@ -603,7 +739,7 @@ __global__ void __launch_bounds__(256) moments_kernel(CBuf<St> src, DevParams<ty
         if (threadIdx.x < NSUM) {
             const int k = threadIdx.x;
             double v = red[0][k];
-            for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+            for (int w = 1; w < BLOCK / 64; ++w) {
                 const double x = red[w][k];
                 v = (k == 6 || k == 8) ? fmax(v, x) : (k == 7 ? fmin(v, x) : v + x);
             }
@@ -647,23 +783,22 @@ __global__ void __launch_bounds__(256) reduce_partials_kernel(const double *part
 // rounded once to the storage precision. Sets *bad if an input is
 // non-finite or phi0 lies outside [-0.5, 1.5].
 template <class St, bool WALLS>
-__global__ void __launch_bounds__(256) init_kernel(const double *phi0, const double *u0,
-                                                   const double *p0, DevParams<double> P,
-                                                   DevParams<typename St::R> PR, Buf<St> dst,
-                                                   int *bad) {
+__global__ void __launch_bounds__(BLOCK) init_kernel(const double *phi0, const double *u0,
+                                                     const double *p0, DevParams<double> P,
+                                                     DevParams<typename St::R> PR, Buf<St> dst,
+                                                     int *bad) {
     using R = typename St::R;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= P.N) return;
-    const Site s = make_site(P, n);
-    const size_t N = (size_t)P.N;
+    const Site s = make_site(P);
+    if (!s.valid) return;
+    const size_t N = (size_t)P.N, n = s.n;
     const double ph0 = phi0[n];
     double g[3] = {0.0, 0.0, 0.0};
     unroll<1, 19>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int ex = Lat::EX[i], ey = Lat::EY[i], ez = Lat::EZ[i];
         constexpr double t = wgt<double>(Lat::cls(i));
-        double vp = phi0[s.template at<ex, ey, ez>()];
-        double vm = phi0[s.template at<-ex, -ey, -ez>()];
+        double vp = phi0[s.nb[i]];
+        double vm = phi0[s.nb[Lat::OPP[i]]];
         if constexpr (WALLS) {
             if (beyond_wall<i, -1>(s)) vp = ph0;
             if (beyond_wall<i, 1>(s)) vm = ph0;
@@ -722,26 +857,26 @@ __global__ void __launch_bounds__(256) init_kernel(const double *phi0, const dou
             eg0 = P.c * edot<i>(g);
         }
         fo[i] = R(t * (A - 0.5 * B));
-        go[i] = R(t * (Gq - (P.omega_g > 0 ? 1.0 / P.omega_g : 0.0) * eg0));
+        go[i] = R(t * (Gq - (1.0 / P.omega_g) * eg0));
     });
-    store<St>(dst, n, PR, fo, go);
+    store<St>(make_dst(dst, PR), s.n, PR, fo, go);
 }
 
 // Loads FP64 post-propagation PDFs into the storage format (restart).
 template <class St>
-__global__ void __launch_bounds__(256) load_kernel(const double *f, const double *g,
-                                                   DevParams<typename St::R> P, Buf<St> dst) {
+__global__ void __launch_bounds__(BLOCK) load_kernel(const double *f, const double *g,
+                                                     DevParams<typename St::R> P, Buf<St> dst) {
     using R = typename St::R;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= P.N) return;
-    const size_t N = (size_t)P.N;
+    const Site s = make_site(P);
+    if (!s.valid) return;
+    const size_t N = (size_t)P.N, n = s.n;
     R fo[19], go[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
         fo[i] = R(f[i * N + n]);
         go[i] = R(g[i * N + n]);
     }
-    store<St>(dst, n, P, fo, go);
+    store<St>(make_dst(dst, P), s.n, P, fo, go);
 }
 
 __global__ void clear_int_kernel(int *p) { *p = 0; }
