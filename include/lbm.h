@@ -73,7 +73,11 @@ typedef struct {
                                /* deviations (ignored otherwise); |k| <= 24   */
     int32_t check_every;       /* lbm_step checks finiteness and |u| < c_s    */
                                /* every this many steps (0: never)            */
-    int32_t reserved;
+    int32_t mass_fix_every;    /* FP64 phase-mass bookkeeping: every this     */
+                               /* many steps the total of phi is measured in  */
+                               /* FP64 and the drift from sum(phi0) is put    */
+                               /* back on the interface, weighted by          */
+                               /* phi(1 - phi), at the next step (0: never)   */
     double courant;            /* c in (0, 1]; the paper uses 0.997; 1 gives  */
                                /* exact streaming                             */
     double rho1, rho2;         /* density of the phi = 1 and phi = 0 phases   */
@@ -84,7 +88,7 @@ typedef struct {
     double delta;              /* interface thickness (> 0)                   */
     double G[3];               /* body acceleration                           */
     double k1_eps;             /* normal n = -K1/|K1| where |K1| > k1_eps,    */
-                               /* n = 0 otherwise (>= 0; default 1e-6)        */
+                               /* n = 0 otherwise (>= 0; 1e-5 recommended)    */
     double p_ref;              /* pressure gauge of the 16-bit f storage      */
 } lbm_params;
 

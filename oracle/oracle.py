@@ -62,7 +62,7 @@ class OracleParams:
     delta: float = 4.0
     G: tuple = (0.0, 0.0, 0.0)
     normal_fd: int = 0
-    k1_eps: float = 1e-6
+    k1_eps: float = 1e-5
 
     def to_c(self) -> _Params:
         p = _Params()

@@ -10,6 +10,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -24,9 +25,37 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// one block per TILE_X x TILE_Y tile of one z-plane
-size_t num_tiles(const lbm_params *P) {
-    const size_t ntx = (P->nx + TILE_X - 1) / TILE_X, nty = (P->ny + TILE_Y - 1) / TILE_Y;
+// Launch shape: one 256-thread block per tile of 2^tx_log2 x (256 >> tx_log2)
+// nodes of one z-plane. The tile spans whole x-rows up to 256 nodes (a
+// wavefront reads 64 contiguous nodes of a row, and a row's periodic wrap
+// stays inside the tile); tiles are dispatched in XCD runs of a z-banded
+// order (see make_site). LBM_TILE_X_LOG2, LBM_TILE_ORDER and LBM_TILE_BAND
+// override the choice (tuning only; every choice gives the same results).
+struct TileCfg {
+    int tx_log2, order, band;
+};
+
+int env_int(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    return v && *v ? std::atoi(v) : dflt;
+}
+
+TileCfg tile_cfg(const lbm_params *P) {
+    TileCfg t;
+    int l = 0;
+    while ((1 << l) < P->nx && l < 8) ++l;
+    t.tx_log2 = env_int("LBM_TILE_X_LOG2", l);
+    if (t.tx_log2 < 0 || t.tx_log2 > 8) t.tx_log2 = l;
+    t.order = env_int("LBM_TILE_ORDER", 2);
+    if (t.order < 0 || t.order > 2) t.order = 2;
+    t.band = env_int("LBM_TILE_BAND", 8);
+    if (t.band < 1) t.band = 8;
+    return t;
+}
+
+size_t num_tiles(const lbm_params *P, const TileCfg &t) {
+    const size_t tw = (size_t)1 << t.tx_log2, th = (size_t)BLOCK >> t.tx_log2;
+    const size_t ntx = (P->nx + tw - 1) / tw, nty = (P->ny + th - 1) / th;
     return ntx * nty * (size_t)P->nz;
 }
 
@@ -49,20 +78,25 @@ struct Layout {
     size_t partial_bytes;  // NSUM doubles per reduction block
     size_t result_bytes;
     size_t flag_bytes;
+    size_t mf_bytes;
     size_t total;
 };
 
 Layout layout_of(const lbm_params *P) {
     Layout L;
     const size_t N = (size_t)P->nx * P->ny * P->nz;
-    const size_t nblocks = num_tiles(P);
+    // the reduction partials are sized for the largest tile count any launch
+    // shape can give (tile width 1)
+    TileCfg narrow{0, 0, 1};
+    const size_t nblocks = num_tiles(P, narrow);
     L.pdf_bytes = align_up(19 * N * elem_bytes(P->precision));
     L.phis_bytes = is16(P->precision) ? align_up(N * sizeof(float)) : 0;
     L.buf_bytes = 2 * L.pdf_bytes + L.phis_bytes;
     L.partial_bytes = align_up(nblocks * NSUM * sizeof(double));
     L.result_bytes = align_up(NSUM * sizeof(double));
     L.flag_bytes = kAlign;
-    L.total = 2 * L.buf_bytes + L.partial_bytes + L.result_bytes + L.flag_bytes;
+    L.mf_bytes = kAlign;  // M0, coef
+    L.total = 2 * L.buf_bytes + L.partial_bytes + L.result_bytes + L.flag_bytes + L.mf_bytes;
     return L;
 }
 
@@ -81,7 +115,7 @@ int validate(const lbm_params *P) {
     }
     for (int k = 0; k < 2; ++k)
         if (P->store_log2[k] < -24 || P->store_log2[k] > 24) return LBM_EINVAL;
-    if (P->check_every < 0) return LBM_EINVAL;
+    if (P->check_every < 0 || P->mass_fix_every < 0) return LBM_EINVAL;
     auto fin = [](double x) { return std::isfinite(x); };
     if (!(fin(P->courant) && P->courant > 0.0 && P->courant <= 1.0)) return LBM_EINVAL;
     if (!(fin(P->rho1) && fin(P->rho2) && P->rho1 > 0.0 && P->rho2 > 0.0)) return LBM_EINVAL;
@@ -97,16 +131,19 @@ int validate(const lbm_params *P) {
 }
 
 template <class R>
-DevParams<R> make_params(const lbm_params *P) {
+DevParams<R> make_params(const lbm_params *P, const TileCfg &tc) {
     DevParams<R> d;
     d.nx = P->nx;
     d.ny = P->ny;
     d.nz = P->nz;
     d.N = P->nx * P->ny * P->nz;
     for (int a = 0; a < 3; ++a) d.wall[a] = P->wall[a];
-    d.ntx = (P->nx + TILE_X - 1) / TILE_X;
-    d.nty = (P->ny + TILE_Y - 1) / TILE_Y;
+    d.tx_log2 = tc.tx_log2;
+    d.ntx = (P->nx + (1 << tc.tx_log2) - 1) >> tc.tx_log2;
+    d.nty = (P->ny + (BLOCK >> tc.tx_log2) - 1) / (BLOCK >> tc.tx_log2);
     d.ntiles = d.ntx * d.nty * P->nz;
+    d.order = tc.order;
+    d.band = tc.band < d.nty ? tc.band : d.nty;
     d.xq = d.ntiles / 8;
     d.xr = d.ntiles % 8;
     const double c = P->courant, cs2 = c * c / 3.0;
@@ -149,6 +186,9 @@ struct lbm_ctx {
     double *partials;
     double *result;
     int *flag;
+    double *mf;         // M0, coef of the phase-mass bookkeeping
+    bool mf_pending;    // the next step applies coef
+    TileCfg tc;
     int cur;            // buffer holding the post-collision state
     bool prev_local;    // the other buffer holds post-propagation PDFs at t
     int64_t t;
@@ -182,35 +222,36 @@ int check_launch(lbm_ctx *c) {
 }
 
 template <class St, Mode M, bool W>
-void launch_step(lbm_ctx *c, int src, int dst) {
+void launch_step(lbm_ctx *c, int src, int dst, const MassFix &mf) {
     using R = typename St::R;
-    const DevParams<R> P = make_params<R>(&c->P);
+    const DevParams<R> P = make_params<R>(&c->P, c->tc);
     hipLaunchKernelGGL((step_kernel<St, M, W>), dim3(c->nblocks), dim3(BLOCK), 0, c->stream,
-                       cbuf_of<St>(c, src), buf_of<St>(c, dst), P);
+                       cbuf_of<St>(c, src), buf_of<St>(c, dst), P, mf);
 }
 
 template <class St, Mode M>
-void launch_step_w(lbm_ctx *c, int src, int dst) {
+void launch_step_w(lbm_ctx *c, int src, int dst, const MassFix &mf) {
     const bool walls = c->P.wall[0] || c->P.wall[1] || c->P.wall[2];
-    if (walls) launch_step<St, M, true>(c, src, dst);
-    else launch_step<St, M, false>(c, src, dst);
+    if (walls) launch_step<St, M, true>(c, src, dst, mf);
+    else launch_step<St, M, false>(c, src, dst, mf);
 }
 
 template <class St>
-void step_dispatch(lbm_ctx *c, Mode m, int src, int dst) {
+void step_dispatch(lbm_ctx *c, Mode m, int src, int dst, const MassFix &mf) {
     switch (m) {
-        case LOCAL: launch_step_w<St, LOCAL>(c, src, dst); break;
-        case SHIFT: launch_step_w<St, SHIFT>(c, src, dst); break;
-        default: launch_step_w<St, LW>(c, src, dst); break;
+        case LOCAL: launch_step_w<St, LOCAL>(c, src, dst, mf); break;
+        case SHIFT: launch_step_w<St, SHIFT>(c, src, dst, mf); break;
+        default: launch_step_w<St, LW>(c, src, dst, mf); break;
     }
 }
 
-void step_any(lbm_ctx *c, Mode m, int src, int dst) {
+void step_any(lbm_ctx *c, Mode m, int src, int dst, int mf_mode = 0) {
+    const MassFix mf{mf_mode, c->partials, c->mf + 1};
     switch (c->P.precision) {
-        case LBM_FP64: step_dispatch<SF64>(c, m, src, dst); break;
-        case LBM_FP32: step_dispatch<SF32>(c, m, src, dst); break;
-        case LBM_FP32_FP16STORE: step_dispatch<SH16>(c, m, src, dst); break;
-        default: step_dispatch<SB16>(c, m, src, dst); break;
+        case LBM_FP64: step_dispatch<SF64>(c, m, src, dst, mf); break;
+        case LBM_FP32: step_dispatch<SF32>(c, m, src, dst, mf); break;
+        case LBM_FP32_FP16STORE: step_dispatch<SH16>(c, m, src, dst, mf); break;
+        default: step_dispatch<SB16>(c, m, src, dst, mf); break;
     }
 }
 
@@ -219,7 +260,7 @@ Mode prop_mode(const lbm_ctx *c) { return c->P.courant == 1.0 ? SHIFT : LW; }
 template <class St, Mode M, bool W>
 void launch_moments(lbm_ctx *c, const FieldOut &o) {
     using R = typename St::R;
-    const DevParams<R> P = make_params<R>(&c->P);
+    const DevParams<R> P = make_params<R>(&c->P, c->tc);
     hipLaunchKernelGGL((moments_kernel<St, M, W>), dim3(c->nblocks), dim3(BLOCK), 0, c->stream,
                        cbuf_of<St>(c, c->cur ^ 1), P, o);
 }
@@ -250,15 +291,15 @@ void moments_any(lbm_ctx *c, const FieldOut &o) {
 template <class St>
 void launch_init(lbm_ctx *c, const double *phi0, const double *u0, const double *p0, int dst) {
     using R = typename St::R;
-    const DevParams<double> PD = make_params<double>(&c->P);
-    const DevParams<R> PR = make_params<R>(&c->P);
+    const DevParams<double> PD = make_params<double>(&c->P, c->tc);
+    const DevParams<R> PR = make_params<R>(&c->P, c->tc);
     const bool walls = c->P.wall[0] || c->P.wall[1] || c->P.wall[2];
     if (walls)
         hipLaunchKernelGGL((init_kernel<St, true>), dim3(c->nblocks), dim3(BLOCK), 0, c->stream,
-                           phi0, u0, p0, PD, PR, buf_of<St>(c, dst), c->flag);
+                           phi0, u0, p0, PD, PR, buf_of<St>(c, dst), c->flag, c->partials);
     else
         hipLaunchKernelGGL((init_kernel<St, false>), dim3(c->nblocks), dim3(BLOCK), 0, c->stream,
-                           phi0, u0, p0, PD, PR, buf_of<St>(c, dst), c->flag);
+                           phi0, u0, p0, PD, PR, buf_of<St>(c, dst), c->flag, c->partials);
 }
 
 void init_any(lbm_ctx *c, const double *phi0, const double *u0, const double *p0, int dst) {
@@ -273,7 +314,7 @@ void init_any(lbm_ctx *c, const double *phi0, const double *u0, const double *p0
 template <class St>
 void launch_load(lbm_ctx *c, const double *f, const double *g, int dst) {
     using R = typename St::R;
-    const DevParams<R> P = make_params<R>(&c->P);
+    const DevParams<R> P = make_params<R>(&c->P, c->tc);
     hipLaunchKernelGGL((load_kernel<St>), dim3(c->nblocks), dim3(BLOCK), 0, c->stream, f, g, P,
                        buf_of<St>(c, dst));
 }
@@ -343,12 +384,18 @@ int lbm_init(const lbm_params *P, void *d_workspace, size_t bytes, void *stream,
     c->partials = (double *)(c->ws + 2 * L.buf_bytes);
     c->result = (double *)(c->ws + 2 * L.buf_bytes + L.partial_bytes);
     c->flag = (int *)(c->ws + 2 * L.buf_bytes + L.partial_bytes + L.result_bytes);
-    c->nblocks = (int)num_tiles(P);
+    c->mf = (double *)(c->ws + 2 * L.buf_bytes + L.partial_bytes + L.result_bytes + L.flag_bytes);
+    c->tc = tile_cfg(P);
+    c->nblocks = (int)num_tiles(P, c->tc);
+    c->mf_pending = false;
     c->status = LBM_OK;
 
     hipLaunchKernelGGL(clear_int_kernel, dim3(1), dim3(1), 0, c->stream, c->flag);
     // post-propagation PDFs at t = 0 into buffer 1, collide into buffer 0
     init_any(c, d_phi0, d_u0, d_p0, 1);
+    // M0 = sum phi0 (FP64), the target of the phase-mass bookkeeping
+    hipLaunchKernelGGL(massfix_kernel, dim3(1), dim3(256), 0, c->stream,
+                       (const double *)c->partials, c->nblocks, c->mf, c->mf + 1, 1);
     step_any(c, LOCAL, 1, 0);
     c->cur = 0;
     c->prev_local = true;
@@ -372,8 +419,17 @@ int lbm_step(lbm_ctx *c, int64_t n) {
     if (!c || n < 0) return LBM_EINVAL;
     if (c->status != LBM_OK) return LBM_ESTATE;
     const Mode m = prop_mode(c);
+    const int mfe = c->P.mass_fix_every;
     for (int64_t k = 0; k < n; ++k) {
-        step_any(c, m, c->cur, c->cur ^ 1);
+        int mf_mode = c->mf_pending ? 2 : 0;
+        if (mfe > 0 && (c->t + 1) % mfe == 0) mf_mode |= 1;
+        step_any(c, m, c->cur, c->cur ^ 1, mf_mode);
+        c->mf_pending = false;
+        if (mf_mode & 1) {
+            hipLaunchKernelGGL(massfix_kernel, dim3(1), dim3(256), 0, c->stream,
+                               (const double *)c->partials, c->nblocks, c->mf, c->mf + 1, 0);
+            c->mf_pending = true;
+        }
         c->cur ^= 1;
         c->prev_local = false;
         c->t += 1;
@@ -454,7 +510,12 @@ int lbm_set_pdfs(lbm_ctx *c, const double *d_f, const double *d_g) {
     if (c->status == LBM_EDEVICE) return LBM_ESTATE;
     const int prev = c->cur ^ 1;
     load_any(c, d_f, d_g, prev);
-    step_any(c, LOCAL, prev, c->cur);
+    // collide in place of a step; the loaded state's sum of phi becomes the
+    // target of the phase-mass bookkeeping
+    step_any(c, LOCAL, prev, c->cur, 1);
+    hipLaunchKernelGGL(massfix_kernel, dim3(1), dim3(256), 0, c->stream,
+                       (const double *)c->partials, c->nblocks, c->mf, c->mf + 1, 1);
+    c->mf_pending = false;
     c->prev_local = true;
     c->status = LBM_OK;
     return check_launch(c);

@@ -95,13 +95,18 @@ __device__ __forceinline__ R edot(const R (&v)[3]) {
 }
 
 // ------------------------------------------------------------ parameters
-constexpr int TILE_X = 64, TILE_Y = 4, BLOCK = TILE_X * TILE_Y;
+// A block is 256 threads covering a tile of 2^tx_log2 x (256 >> tx_log2) nodes
+// of one z-plane.
+constexpr int BLOCK = 256;
 
 template <class R>
 struct DevParams {
     int nx, ny, nz, N;
     int wall[3];
-    int ntx, nty, ntiles;    // tiles of TILE_X x TILE_Y nodes in a z-plane, all planes
+    int tx_log2;             // tile width 2^tx_log2, tile height 256 >> tx_log2
+    int ntx, nty, ntiles;    // tiles per row, per column, in total
+    int order;               // 0: tile = block id; 1: XCD runs; 2: XCD runs of z-banded order
+    int band;                // tile-rows per band (order 2)
     int xq, xr;              // ntiles = 8 xq + xr (XCD runs)
     R c, h;                  // Courant number, c(1-c)/2
     R lwA, lwD;              // Lax-Wendroff weights of x-e and x+e: c(1+c)/2, -c(1-c)/2
@@ -201,20 +206,43 @@ struct Site {
     bool wall;           // lo or hi on some axis
 };
 
-// Block -> tile: workgroups go round-robin to the 8 XCDs; XCD k takes the
-// contiguous run of tiles [start_k, start_k + count_k), so neighbouring tiles
-// (and the z-planes above and below) share an L2.
+// Block -> tile. Workgroups are dispatched round-robin to the 8 XCDs; with
+// order >= 1, XCD k takes the contiguous run of logical tiles
+// [start_k, start_k + count_k), so neighbouring tiles share its L2. Logical
+// tiles run x fastest, then (order 1) y, then z, or (order 2) y within a band
+// of `band` tile-rows, then z, then the band: the z-neighbour planes a tile
+// re-reads are then only a band's width of tiles away.
 template <class R>
 __device__ __forceinline__ Site make_site(const DevParams<R> &P) {
     Site s;
     const uint32_t b = blockIdx.x;
-    const uint32_t xcd = b & 7u, slot = b >> 3;
-    const uint32_t q = (uint32_t)P.xq, r = (uint32_t)P.xr;
-    const uint32_t t = (xcd < r ? xcd * (q + 1u) : r * (q + 1u) + (xcd - r) * q) + slot;
-    const uint32_t ntx = (uint32_t)P.ntx, nty = (uint32_t)P.nty;
-    const uint32_t tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
-    s.x = (int)(tx * TILE_X + (threadIdx.x % TILE_X));
-    s.y = (int)(ty * TILE_Y + (threadIdx.x / TILE_X));
+    uint32_t t = b;
+    if (P.order >= 1) {
+        const uint32_t xcd = b & 7u, slot = b >> 3;
+        const uint32_t q = (uint32_t)P.xq, r = (uint32_t)P.xr;
+        t = (xcd < r ? xcd * (q + 1u) : r * (q + 1u) + (xcd - r) * q) + slot;
+    }
+    const uint32_t ntx = (uint32_t)P.ntx, nty = (uint32_t)P.nty, nz = (uint32_t)P.nz;
+    const uint32_t tx = t % ntx, rr = t / ntx;
+    uint32_t ty, tz;
+    if (P.order == 2) {
+        const uint32_t bw = (uint32_t)P.band, full = nty / bw, per_band = bw * nz;
+        if (rr < full * per_band) {
+            const uint32_t k = rr / per_band, w = rr - k * per_band;
+            tz = w / bw;
+            ty = k * bw + (w - tz * bw);
+        } else {
+            const uint32_t rem = nty - full * bw, w = rr - full * per_band;
+            tz = w / rem;
+            ty = full * bw + (w - tz * rem);
+        }
+    } else {
+        ty = rr % nty;
+        tz = rr / nty;
+    }
+    const uint32_t lx = threadIdx.x & ((1u << P.tx_log2) - 1u), ly = threadIdx.x >> P.tx_log2;
+    s.x = (int)((tx << P.tx_log2) + lx);
+    s.y = (int)(ty * (uint32_t)(BLOCK >> P.tx_log2) + ly);
     s.z = (int)tz;
     s.valid = s.x < P.nx && s.y < P.ny && s.z < P.nz;
     const int x = s.valid ? s.x : 0, y = s.valid ? s.y : 0, z = s.valid ? s.z : 0;
@@ -608,41 +636,6 @@ __device__ __forceinline__ void store(const Dst<St> &dst, uint32_t n,
 }
 
 // ---------------------------------------------------------------- kernels
-// Fused step: propagate (mode M) from src, moments, collide, store to dst.
-// Wavefronts without a wall node take the wall-free propagation.
-template <class St, Mode M, bool WALLS>
-__global__ void __launch_bounds__(BLOCK) step_kernel(CBuf<St> src, Buf<St> dst,
-                                                     DevParams<typename St::R> P) {
-    using R = typename St::R;
-    const Site s = make_site(P);
-    if (!s.valid) return;
-    const Src<St> in = make_src(src, P);
-    R fb[19], gb[19];
-    if constexpr (WALLS) {
-        if (__any(s.wall)) gather<M, true, St>(in, s, P, fb, gb);
-        else gather<M, false, St>(in, s, P, fb, gb);
-    } else {
-        gather<M, false, St>(in, s, P, fb, gb);
-    }
-    const Macro<R> m = moments(P, fb, gb);
-    const NodeCoef<R> q = node_coef(P, m);
-    collide(P, m, q, fb, gb);
-    store<St>(make_dst(dst, P), s.n, P, fb, gb);
-}
-
-// Number of FP64 partial sums per block in the diagnostics reduction.
-constexpr int NSUM = 17;
-// layout: 0 sum_phi 1 mass 2-4 mom 5 ekin 6 umax(max) 7 phi_min(min)
-//         8 phi_max(max) 9-11 com 12-14 phiu 15 l2_num 16 l2_den
-
-struct FieldOut {
-    void *phi, *u, *p;
-    int dtype;                 // 0 double, 1 float
-    double *pdf_f, *pdf_g;     // FP64 post-propagation PDFs (or NULL)
-    const double *phi_ref;     // for the L2 entries (or NULL)
-    double *partials;          // NSUM per block (or NULL)
-};
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -658,6 +651,130 @@ __device__ __forceinline__ double wave_min(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
     return v;
 }
+
+// Deterministic FP64 block sums of two values; thread 0 writes them.
+__device__ __forceinline__ void block_sum2(double a, double b, double *out) {
+    __shared__ double red[BLOCK / 64][2];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+        red[wv][0] = a;
+        red[wv][1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = red[0][0], sb = red[0][1];
+        for (int w = 1; w < BLOCK / 64; ++w) {
+            sa += red[w][0];
+            sb += red[w][1];
+        }
+        out[0] = sa;
+        out[1] = sb;
+    }
+}
+
+// Phase-mass bookkeeping in FP64. Every few steps a step reports per-block
+// sums of phi and of the interface weight w = max(phi (1 - phi), 0);
+// massfix_kernel turns them into c = (M0 - M)/sum(w), and the next step adds
+// c w t_i to the g of each node before its collision, which puts back, on the
+// interface and isotropically, the phase mass that FP32 / 16-bit rounding
+// has added or removed since the start (M0 = sum phi0 in FP64).
+struct MassFix {
+    int mode;               // bit 0: report partial sums; bit 1: apply coef
+    double *partials;       // 2 per block
+    const double *coef;     // c
+};
+
+template <class R>
+__device__ __forceinline__ R mass_weight(R phi) {
+    return fmax(phi * (R(1) - phi), R(0));
+}
+
+// Fused step: propagate (mode M) from src, moments, collide, store to dst.
+// Wavefronts without a wall node take the wall-free propagation.
+template <class St, Mode M, bool WALLS>
+__global__ void __launch_bounds__(BLOCK) step_kernel(CBuf<St> src, Buf<St> dst,
+                                                     DevParams<typename St::R> P, MassFix mf) {
+    using R = typename St::R;
+    const Site s = make_site(P);
+    double rep_phi = 0.0, rep_w = 0.0;
+    if (s.valid) {
+        const Src<St> in = make_src(src, P);
+        R fb[19], gb[19];
+        if constexpr (WALLS) {
+            if (__any(s.wall)) gather<M, true, St>(in, s, P, fb, gb);
+            else gather<M, false, St>(in, s, P, fb, gb);
+        } else {
+            gather<M, false, St>(in, s, P, fb, gb);
+        }
+        if (mf.mode & 2) {
+            R phi = gb[0];
+#pragma unroll
+            for (int i = 1; i < 19; ++i) phi += gb[i];
+            const R cw = R(*mf.coef) * mass_weight(phi);
+            unroll<0, 19>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                gb[i] = fma(wgt<R>(Lat::cls(i)), cw, gb[i]);
+            });
+        }
+        const Macro<R> m = moments(P, fb, gb);
+        if (mf.mode & 1) {
+            rep_phi = m.phi;
+            rep_w = mass_weight(m.phi);
+        }
+        const NodeCoef<R> q = node_coef(P, m);
+        collide(P, m, q, fb, gb);
+        store<St>(make_dst(dst, P), s.n, P, fb, gb);
+    }
+    if (mf.mode & 1) block_sum2(rep_phi, rep_w, mf.partials + 2 * (size_t)blockIdx.x);
+}
+
+// Sums the per-block pairs in a fixed order. init: *M0 = sum phi; otherwise
+// *coef = (M0 - sum phi)/sum w (0 when there is no interface).
+__global__ void __launch_bounds__(256) massfix_kernel(const double *partials, int nblocks,
+                                                      double *M0, double *coef, int init) {
+    __shared__ double red[4][2];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < nblocks; k += blockDim.x) {
+        a += partials[2 * (size_t)k];
+        b += partials[2 * (size_t)k + 1];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+        red[wv][0] = a;
+        red[wv][1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            sa += red[w][0];
+            sb += red[w][1];
+        }
+        if (init) {
+            *M0 = sa;
+            *coef = 0.0;
+        } else {
+            *coef = sb > 0.0 ? (*M0 - sa) / sb : 0.0;
+        }
+    }
+}
+
+// Number of FP64 partial sums per block in the diagnostics reduction.
+constexpr int NSUM = 17;
+// layout: 0 sum_phi 1 mass 2-4 mom 5 ekin 6 umax(max) 7 phi_min(min)
+//         8 phi_max(max) 9-11 com 12-14 phiu 15 l2_num 16 l2_den
+
+struct FieldOut {
+    void *phi, *u, *p;
+    int dtype;                 // 0 double, 1 float
+    double *pdf_f, *pdf_g;     // FP64 post-propagation PDFs (or NULL)
+    const double *phi_ref;     // for the L2 entries (or NULL)
+    double *partials;          // NSUM per block (or NULL)
+};
 
 // Moments of the state at t (propagation mode M from the previous buffer):
 // fields, FP64 PDFs and/or per-block FP64 partial sums of the diagnostics.
@@ -783,13 +900,11 @@ __global__ void __launch_bounds__(256) reduce_partials_kernel(const double *part
 // rounded once to the storage precision. Sets *bad if an input is
 // non-finite or phi0 lies outside [-0.5, 1.5].
 template <class St, bool WALLS>
-__global__ void __launch_bounds__(BLOCK) init_kernel(const double *phi0, const double *u0,
-                                                     const double *p0, DevParams<double> P,
-                                                     DevParams<typename St::R> PR, Buf<St> dst,
-                                                     int *bad) {
+__device__ __forceinline__ void init_node(const double *phi0, const double *u0, const double *p0,
+                                          const DevParams<double> &P,
+                                          const DevParams<typename St::R> &PR, const Buf<St> &dst,
+                                          int *bad, const Site &s) {
     using R = typename St::R;
-    const Site s = make_site(P);
-    if (!s.valid) return;
     const size_t N = (size_t)P.N, n = s.n;
     const double ph0 = phi0[n];
     double g[3] = {0.0, 0.0, 0.0};
@@ -861,6 +976,17 @@ __global__ void __launch_bounds__(BLOCK) init_kernel(const double *phi0, const d
     });
     store<St>(make_dst(dst, PR), s.n, PR, fo, go);
 }
+
+template <class St, bool WALLS>
+__global__ void __launch_bounds__(BLOCK) init_kernel(const double *phi0, const double *u0,
+                                                     const double *p0, DevParams<double> P,
+                                                     DevParams<typename St::R> PR, Buf<St> dst,
+                                                     int *bad, double *partials) {
+    const Site s = make_site(P);
+    if (s.valid) init_node<St, WALLS>(phi0, u0, p0, P, PR, dst, bad, s);
+    block_sum2(s.valid ? phi0[s.n] : 0.0, 0.0, partials + 2 * (size_t)blockIdx.x);
+}
+
 
 // Loads FP64 post-propagation PDFs into the storage format (restart).
 template <class St>

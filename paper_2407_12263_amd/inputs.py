@@ -40,7 +40,7 @@ class Workload:
     sigma: float = 0.0
     delta: float = 4.0
     G: tuple = (0.0, 0.0, 0.0)
-    k1_eps: float = 1e-6         # normal set to 0 where |K1| <= k1_eps
+    k1_eps: float = 1e-5         # normal set to 0 where |K1| <= k1_eps
     steps: int = 100
     phi0: np.ndarray = field(default=None, repr=False)
     u0: np.ndarray = field(default=None, repr=False)

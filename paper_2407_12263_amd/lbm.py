@@ -32,7 +32,7 @@ class LbmParams(C.Structure):
                 ("wall", C.c_int32 * 3),
                 ("store_log2", C.c_int32 * 2),
                 ("check_every", C.c_int32),
-                ("reserved", C.c_int32),
+                ("mass_fix_every", C.c_int32),
                 ("courant", C.c_double),
                 ("rho1", C.c_double), ("rho2", C.c_double),
                 ("tau_rho1", C.c_double), ("tau_rho2", C.c_double),
@@ -104,8 +104,9 @@ def _check(rc: int, where: str):
 
 def make_params(nx, ny, nz, precision="fp32", wall=(0, 0, 0), courant=0.997, rho1=1.0,
                 rho2=1.0, tau_rho1=0.3, tau_rho2=0.3, tau_phi=0.3, sigma=0.0, delta=4.0,
-                G=(0.0, 0.0, 0.0), k1_eps=1e-6, p_ref=0.0, store_log2=(10, 10),
-                check_every=0) -> LbmParams:
+                G=(0.0, 0.0, 0.0), k1_eps=1e-5, p_ref=0.0, store_log2=(10, 10),
+                check_every=0, mass_fix_every=None) -> LbmParams:
+    """mass_fix_every: None picks 100 for FP32 and 16-bit storage, 0 for FP64."""
     p = LbmParams()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -114,6 +115,9 @@ def make_params(nx, ny, nz, precision="fp32", wall=(0, 0, 0), courant=0.997, rho
         p.G[a] = float(G[a])
     p.store_log2[0], p.store_log2[1] = int(store_log2[0]), int(store_log2[1])
     p.check_every = int(check_every)
+    if mass_fix_every is None:
+        mass_fix_every = 0 if p.precision == PRECISIONS["fp64"] else 100
+    p.mass_fix_every = int(mass_fix_every)
     p.courant = float(courant)
     p.rho1, p.rho2 = float(rho1), float(rho2)
     p.tau_rho1, p.tau_rho2 = float(tau_rho1), float(tau_rho2)

@@ -63,19 +63,22 @@ def test_16bit_storage_static_droplet_100_steps(prec):
     _cmp(inputs.static_droplet(), prec, 100, 2e-3)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
-def test_phase_mass_drift_10k_steps(prec):
-    """Relative drift of sum(phi) over 10^4 steps on the static droplet."""
+@pytest.mark.parametrize("prec,fix", [("fp32", 100), ("fp16", 100), ("bf16", 100), ("fp32", 0)])
+def test_phase_mass_drift_10k_steps(prec, fix):
+    """Relative drift of sum(phi) over 10^4 steps on the static droplet, with
+    the FP64 phase-mass bookkeeping every 100 steps (and, for FP32, without
+    it: plain FP32 rounding alone keeps it within the same bound)."""
     w = inputs.static_droplet()
-    say(f"[mass] {w.name} {prec} 10000 steps")
-    sol = gpu_solver(w, prec)
+    say(f"[mass] {w.name} {prec} mass_fix_every={fix} 10000 steps")
+    sol = gpu_solver(w, prec, mass_fix_every=fix)
     m0 = float(w.phi0.sum())
-    d0 = sol.diagnostics()
-    sol.step(10000)
-    d1 = sol.diagnostics()
-    drift = abs(d1["sum_phi"] - m0) / m0
-    say(f"   sum_phi(0)={d0['sum_phi']:.12e} sum_phi(1e4)={d1['sum_phi']:.12e} drift={drift:.2e}")
-    assert drift <= 1e-6
+    worst = 0.0
+    for t in (1000, 2500, 5000, 7500, 10000):
+        sol.step(t - sol.t)
+        d = sol.diagnostics()
+        worst = max(worst, abs(d["sum_phi"] - m0) / m0)
+    say(f"   max relative drift over the run = {worst:.2e}")
+    assert worst <= (1e-7 if fix else 1e-6)
 
 
 # ----------------------------------------------------- other workloads
@@ -179,12 +182,12 @@ def test_checkpoint_restart_bitwise(prec):
     """200 steps straight equal 100 steps, get_pdfs / set_pdfs, 100 steps."""
     w = SMALL["tg"]()
     say(f"[restart] {w.name} {prec}")
-    a = gpu_solver(w, prec)
+    a = gpu_solver(w, prec, mass_fix_every=0)
     a.step(200)
-    b = gpu_solver(w, prec)
+    b = gpu_solver(w, prec, mass_fix_every=0)
     b.step(100)
     f, g = b.get_pdfs()
-    c = gpu_solver(w, prec)
+    c = gpu_solver(w, prec, mass_fix_every=0)
     c.set_pdfs(f, g)
     c.step(100)
     pa = a.fields()[0].cpu().numpy()
