@@ -26,11 +26,12 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Launch shape: one 256-thread block per tile of 2^tx_log2 x (256 >> tx_log2)
-// nodes of one z-plane. The tile spans whole x-rows up to 256 nodes (a
+// nodes of one z-plane. The tile spans whole x-rows up to 128 nodes (a
 // wavefront reads 64 contiguous nodes of a row, and a row's periodic wrap
-// stays inside the tile); tiles are dispatched in XCD runs of a z-banded
-// order (see make_site). LBM_TILE_X_LOG2, LBM_TILE_ORDER and LBM_TILE_BAND
-// override the choice (tuning only; every choice gives the same results).
+// stays inside the tile), in plain block order: on the 128 x 512 x 128
+// Rayleigh-Taylor lattice this measured best among 32/64/128-wide tiles and the
+// XCD-run and z-banded orders of make_site. LBM_TILE_X_LOG2, LBM_TILE_ORDER and
+// LBM_TILE_BAND override the choice (tuning only; results do not depend on it).
 struct TileCfg {
     int tx_log2, order, band;
 };
@@ -43,10 +44,10 @@ int env_int(const char *name, int dflt) {
 TileCfg tile_cfg(const lbm_params *P) {
     TileCfg t;
     int l = 0;
-    while ((1 << l) < P->nx && l < 8) ++l;
+    while ((1 << l) < P->nx && l < 7) ++l;
     t.tx_log2 = env_int("LBM_TILE_X_LOG2", l);
     if (t.tx_log2 < 0 || t.tx_log2 > 8) t.tx_log2 = l;
-    t.order = env_int("LBM_TILE_ORDER", 2);
+    t.order = env_int("LBM_TILE_ORDER", 0);
     if (t.order < 0 || t.order > 2) t.order = 2;
     t.band = env_int("LBM_TILE_BAND", 8);
     if (t.band < 1) t.band = 8;
