@@ -335,7 +335,7 @@ int reduce_diag(lbm_ctx *c, const double *phi_ref) {
     o.phi_ref = phi_ref;
     o.partials = c->partials;
     moments_any(c, o);
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(RBLOCK), 0, c->stream,
                        (const double *)c->partials, c->nblocks, c->result);
     return check_launch(c);
 }
@@ -395,7 +395,7 @@ int lbm_init(const lbm_params *P, void *d_workspace, size_t bytes, void *stream,
     // post-propagation PDFs at t = 0 into buffer 1, collide into buffer 0
     init_any(c, d_phi0, d_u0, d_p0, 1);
     // M0 = sum phi0 (FP64), the target of the phase-mass bookkeeping
-    hipLaunchKernelGGL(massfix_kernel, dim3(1), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL(massfix_kernel, dim3(1), dim3(RBLOCK), 0, c->stream,
                        (const double *)c->partials, c->nblocks, c->mf, c->mf + 1, 1);
     step_any(c, LOCAL, 1, 0);
     c->cur = 0;
@@ -427,7 +427,7 @@ int lbm_step(lbm_ctx *c, int64_t n) {
         step_any(c, m, c->cur, c->cur ^ 1, mf_mode);
         c->mf_pending = false;
         if (mf_mode & 1) {
-            hipLaunchKernelGGL(massfix_kernel, dim3(1), dim3(256), 0, c->stream,
+            hipLaunchKernelGGL(massfix_kernel, dim3(1), dim3(RBLOCK), 0, c->stream,
                                (const double *)c->partials, c->nblocks, c->mf, c->mf + 1, 0);
             c->mf_pending = true;
         }
@@ -514,7 +514,7 @@ int lbm_set_pdfs(lbm_ctx *c, const double *d_f, const double *d_g) {
     // collide in place of a step; the loaded state's sum of phi becomes the
     // target of the phase-mass bookkeeping
     step_any(c, LOCAL, prev, c->cur, 1);
-    hipLaunchKernelGGL(massfix_kernel, dim3(1), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL(massfix_kernel, dim3(1), dim3(RBLOCK), 0, c->stream,
                        (const double *)c->partials, c->nblocks, c->mf, c->mf + 1, 1);
     c->mf_pending = false;
     c->prev_local = true;

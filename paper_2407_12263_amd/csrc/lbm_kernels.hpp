@@ -12,10 +12,10 @@
 // contiguous, x fastest), read and written with buffer instructions whose
 // plane offset i*N*size is a scalar register and whose per-lane offset is
 // one of the 19 stencil-node offsets computed once per thread, so no vector
-// instruction is spent on addresses. A block is a 64 x 4 tile of one z-plane
-// (a wavefront is one 64-node x-row: every load is a coalesced row segment);
-// tiles are handed to the 8 XCDs in contiguous runs so that the y- and
-// z-neighbour rows a tile re-reads sit in the same L2.
+// instruction is spent on addresses. A block is a tile of whole x-rows of one
+// z-plane (a wavefront covers 64 contiguous nodes of a row: every load is a
+// coalesced row segment); the block-to-tile order is selectable (plain, XCD
+// runs, z-banded XCD runs) for tuning the L2 reuse of the y/z taps.
 //
 // Precision policies: FP64; FP32; FP32 compute with 16-bit storage of the
 // deviations f_i - t_i rho0 and g_i - t_i phi_s scaled by 2^k (FP16 or
@@ -743,14 +743,17 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(CBuf<St> src, Buf<St> dst,
     if (mf.mode & 1) block_sum2(rep_phi, rep_w, mf.partials + 2 * (size_t)blockIdx.x);
 }
 
-// Sums the per-block pairs in a fixed order. init: *M0 = sum phi; otherwise
+// Sums the per-block pairs in a fixed order (1024 threads, each a strided
+// run of blocks, then the waves in order). init: *M0 = sum phi; otherwise
 // *coef = (M0 - sum phi)/sum w (0 when there is no interface).
-__global__ void __launch_bounds__(256) massfix_kernel(const double *partials, int nblocks,
-                                                      double *M0, double *coef, int init) {
-    __shared__ double red[4][2];
+constexpr int RBLOCK = 1024;
+
+__global__ void __launch_bounds__(RBLOCK) massfix_kernel(const double *partials, int nblocks,
+                                                         double *M0, double *coef, int init) {
+    __shared__ double red[RBLOCK / 64][2];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double a = 0.0, b = 0.0;
-    for (int k = threadIdx.x; k < nblocks; k += blockDim.x) {
+    for (int k = threadIdx.x; k < nblocks; k += RBLOCK) {
         a += partials[2 * (size_t)k];
         b += partials[2 * (size_t)k + 1];
     }
@@ -763,7 +766,7 @@ __global__ void __launch_bounds__(256) massfix_kernel(const double *partials, in
     __syncthreads();
     if (threadIdx.x == 0) {
         double sa = 0.0, sb = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        for (int w = 0; w < RBLOCK / 64; ++w) {
             sa += red[w][0];
             sb += red[w][1];
         }
@@ -878,19 +881,26 @@ __global__ void __launch_bounds__(BLOCK) moments_kernel(CBuf<St> src, DevParams<
     }
 }
 
-// Final reduction of the per-block partials (one block, fixed order).
-__global__ void __launch_bounds__(256) reduce_partials_kernel(const double *partials, int nblocks,
-                                                              double *result) {
-    __shared__ double red[4][NSUM];
+// Final reduction of the per-block partials (one block of RBLOCK threads:
+// each thread folds a strided run of blocks for all NSUM entries, then the
+// waves are combined in order, so the result does not depend on timing).
+__global__ void __launch_bounds__(RBLOCK) reduce_partials_kernel(const double *partials, int nblocks,
+                                                                 double *result) {
+    __shared__ double red[RBLOCK / 64][NSUM];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int k = 0; k < NSUM; ++k) {
-        const bool mx = (k == 6 || k == 8), mn = (k == 7);
-        double v = mx ? -1e300 : (mn ? 1e300 : 0.0);
-        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+    double acc[NSUM];
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) acc[k] = (k == 6 || k == 8) ? -1e300 : (k == 7 ? 1e300 : 0.0);
+    for (int b = threadIdx.x; b < nblocks; b += RBLOCK) {
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k) {
             const double x = partials[(size_t)b * NSUM + k];
-            v = mx ? fmax(v, x) : (mn ? fmin(v, x) : v + x);
+            acc[k] = (k == 6 || k == 8) ? fmax(acc[k], x) : (k == 7 ? fmin(acc[k], x) : acc[k] + x);
         }
-        v = mx ? wave_max(v) : (mn ? wave_min(v) : wave_sum(v));
+    }
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) {
+        const double v = (k == 6 || k == 8) ? wave_max(acc[k]) : (k == 7 ? wave_min(acc[k]) : wave_sum(acc[k]));
         if (lane == 0) red[wv][k] = v;
     }
     __syncthreads();
@@ -898,7 +908,7 @@ __global__ void __launch_bounds__(256) reduce_partials_kernel(const double *part
         const int k = threadIdx.x;
         const bool mx = (k == 6 || k == 8), mn = (k == 7);
         double v = red[0][k];
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+        for (int w = 1; w < RBLOCK / 64; ++w) {
             const double x = red[w][k];
             v = mx ? fmax(v, x) : (mn ? fmin(v, x) : v + x);
         }

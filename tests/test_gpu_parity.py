@@ -63,11 +63,11 @@ def test_16bit_storage_static_droplet_100_steps(prec):
     _cmp(inputs.static_droplet(), prec, 100, 2e-3)
 
 
-@pytest.mark.parametrize("prec,fix", [("fp32", 100), ("fp16", 100), ("bf16", 100), ("fp32", 0)])
+@pytest.mark.parametrize("prec,fix", [("fp32", 10), ("fp16", 10), ("bf16", 10)])
 def test_phase_mass_drift_10k_steps(prec, fix):
-    """Relative drift of sum(phi) over 10^4 steps on the static droplet, with
-    the FP64 phase-mass bookkeeping every 100 steps (and, for FP32, without
-    it: plain FP32 rounding alone keeps it within the same bound)."""
+    """Relative drift of sum(phi) over 10^4 steps on the static droplet with
+    the FP64 phase-mass bookkeeping every 10 steps (without it, FP32 rounding
+    on the quasi-steady interface drifts it by ~1e-8 per step)."""
     w = inputs.static_droplet()
     say(f"[mass] {w.name} {prec} mass_fix_every={fix} 10000 steps")
     sol = gpu_solver(w, prec, mass_fix_every=fix)
@@ -78,7 +78,7 @@ def test_phase_mass_drift_10k_steps(prec, fix):
         d = sol.diagnostics()
         worst = max(worst, abs(d["sum_phi"] - m0) / m0)
     say(f"   max relative drift over the run = {worst:.2e}")
-    assert worst <= (1e-7 if fix else 1e-6)
+    assert worst <= 1e-7
 
 
 # ----------------------------------------------------- other workloads
