@@ -1,0 +1,122 @@
+/*
+ * sur.h -- C ABI of the learned surrogate that accompanies the
+ * difference-free CPF-LBM solver: a 3D convolutional U-Net on a 2x-coarsened
+ * grid that advances (phi, u, p) by a window of LBM steps, trained and run
+ * with hand-written HIP kernels (BF16 matrix-core products with FP32
+ * accumulation; FP32 master weights and Adam).
+ *
+ * The paper has no learned component; this ABI serves the acceleration
+ * scheme of this build: the solver generates training snapshots, the network
+ * predicts windows on the coarse grid, per-window checks (phase mass, phi
+ * range, velocity divergence) send a window back to the plain solver when
+ * they fail, and the plain solver runs every re-synchronisation window.
+ *
+ * Tensors: activations are channels-last, [P][C] with P = nx*ny*nz points
+ * (x fastest) and C a multiple of 16, stored as BF16 (uint16_t bit pattern,
+ * round-to-nearest-even) unless the argument says float. Convolutions are
+ * 3x3x3 with periodic wrap. Weights: FP32 master [27][cout][cin] with tap
+ * t = (dx+1) + 3 (dy+1) + 9 (dz+1) reading the input at x + (dx, dy, dz);
+ * packed BF16 copies are [27][cout][cin] (forward) and [27][cin][cout]
+ * (data gradient).
+ *
+ * All pointers are device pointers owned by the caller; every call is
+ * queued on `stream` (a hipStream_t, NULL = null stream) and returns
+ * SUR_OK or SUR_EINVAL (bad sizes / NULL) or SUR_EDEVICE (launch failed).
+ * Nothing is allocated by the library.
+ */
+#ifndef SUR_H
+#define SUR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { SUR_OK = 0, SUR_EINVAL = -1, SUR_EDEVICE = -3 };
+
+/* y[p][co] = act( bias[co] + sum_t sum_ci x[p + s d_t][ci] w[t][co][ci] ),
+ * s = +1 (flip = 0) or -1 (flip = 1, the data-gradient form, with w the
+ * [27][cin][cout] packing of the forward weights). bias may be NULL.
+ * act: relu if relu != 0. If mask != NULL (BF16 [P][cout]) the result is
+ * multiplied by (mask > 0) (the ReLU derivative of the layer below). Writes
+ * y_bf16 and/or y_f32 (either may be NULL). cin, cout multiples of 16. */
+int sur_conv3d(const void *x, int32_t cin, const void *w, const float *bias, int32_t cout,
+               int32_t nx, int32_t ny, int32_t nz, int32_t flip, int32_t relu,
+               const void *mask, void *y_bf16, float *y_f32, void *stream);
+
+/* Floats of scratch that sur_conv3d_wgrad needs for these sizes. */
+size_t sur_wgrad_scratch_floats(int32_t cin, int32_t cout, int32_t nx, int32_t ny, int32_t nz);
+
+/* dw[t][co][ci] = sum_p dy[p][co] x[p + d_t][ci], dbias[co] = sum_p dy[p][co]
+ * (overwritten; FP32), from BF16 x [P][cin] and dy [P][cout]. Fixed
+ * summation order (deterministic). scratch: >= sur_wgrad_scratch_floats. */
+int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, int32_t nx,
+                     int32_t ny, int32_t nz, float *scratch, size_t scratch_floats, float *dw,
+                     float *dbias, void *stream);
+
+/* BF16 packings of FP32 master weights w[27][cout][cin]: wf (same layout)
+ * and wd[27][cin][cout] (per-tap transpose, for the data gradient). */
+int sur_pack_weights(const float *w, int32_t cin, int32_t cout, void *wf, void *wd, void *stream);
+
+/* 2x2x2 average pooling of BF16 x (fine grid nx, ny, nz even) into BF16 y. */
+int sur_pool2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void *y, void *stream);
+/* dx[p][c] += dy[parent(p)][c] / 8 (FP32; fine grid sizes). */
+int sur_pool2_bwd(const float *dy, int32_t c, int32_t nx, int32_t ny, int32_t nz, float *dx,
+                  void *stream);
+/* Nearest 2x upsampling of BF16 x [P_coarse][c] (coarse sizes) into channels
+ * [yoff, yoff + c) of BF16 y [P_fine][ystride]. */
+int sur_upsample2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void *y,
+                  int32_t ystride, int32_t yoff, void *stream);
+/* dx[q][c] = sum over the 8 fine children p of dy[p][dyoff + c] (FP32;
+ * coarse sizes; dx overwritten). */
+int sur_upsample2_bwd(const float *dy, int32_t dystride, int32_t dyoff, int32_t c, int32_t nx,
+                      int32_t ny, int32_t nz, float *dx, void *stream);
+/* y[p][yoff + c'] = x[p][c'] for c' < c (BF16 channel copy, for concat). */
+int sur_copy_channels(const void *x, int32_t c, int64_t P, void *y, int32_t ystride,
+                      int32_t yoff, void *stream);
+/* dx[p][c'] += dy[p][dyoff + c'] (FP32). */
+int sur_add_channels(const float *dy, int32_t dystride, int32_t dyoff, int32_t c, int64_t P,
+                     float *dx, void *stream);
+/* y = bf16(x), n values. */
+int sur_to_bf16(const float *x, int64_t n, void *y, void *stream);
+/* dx[i] *= (act[i] > 0) (FP32 gradient, BF16 activation), n values. */
+int sur_relu_mask(float *dx, const void *act, int64_t n, void *stream);
+
+/* Residual MSE on the first cu channels of FP32 pred/target [P][cs]:
+ * L = sum_p sum_c wch[c] (pred - target)^2 / (P cu); grad = dL/dpred
+ * ([P][cs], channels >= cu zero). loss_out: one double (device), written
+ * after an FP64 reduction in fixed order; scratch >= (P/256 + 1) doubles. */
+int sur_mse(const float *pred, const float *target, int32_t cu, int32_t cs, int64_t P,
+            const float *wch, float *grad, double *scratch, double *loss_out, void *stream);
+
+/* Adam step t >= 1 (Kingma & Ba, bias-corrected) on n FP32 weights. */
+int sur_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float beta1,
+             float beta2, float eps, int32_t t, void *stream);
+
+/* Grid transfer between the solver's fine fields and the network's coarse
+ * channels-last state (5 used channels of 16: phi, ux, uy, uz, p).
+ *   coarsen: coarse[q][c] = mean over the 2x2x2 children of the fine field c
+ *            (fine FP32 SoA phi[N], u[3N], p[N]; fine sizes even), scaled by
+ *            1/scale[c]; written FP32 (and BF16 if coarse_bf16 != NULL).
+ *   prolong_add: fine[c] += scale[c] * trilinear(delta)[c] (periodic;
+ *            delta FP32 [Pc][16]; fine FP64 SoA phi, u, p). */
+int sur_coarsen(const float *phi, const float *u, const float *p, int32_t nx, int32_t ny,
+                int32_t nz, const float *scale, float *coarse_f32, void *coarse_bf16,
+                void *stream);
+int sur_prolong_add(const float *delta, int32_t cnx, int32_t cny, int32_t cnz,
+                    const float *scale, double *phi, double *u, double *p, void *stream);
+
+/* Per-window checks on a coarse FP32 state [P][16] (unscaled: channel c is
+ * the physical field / scale[c] as coarsen wrote it): FP64 sums written to
+ * out[6] = {sum phi, min phi, max phi, sum (div u)^2, sum |u|^2, P}
+ * (div by central differences on the coarse grid, in coarse-grid units, of
+ * the scaled velocity). scratch >= 6 * (P/256 + 1) doubles. */
+int sur_checks(const float *state, int32_t nx, int32_t ny, int32_t nz, double *scratch,
+               double *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SUR_H */

@@ -1,0 +1,704 @@
+// sur.hip -- HIP kernels (gfx950) and C ABI of the coarse-grid 3D U-Net
+// surrogate: 3x3x3 convolutions as implicit GEMMs on BF16 matrix cores with
+// FP32 accumulation (forward, data gradient, weight gradient), pooling,
+// upsampling, channel concat, residual MSE, Adam, and the grid transfers and
+// window checks that couple it to the LBM solver. See include/sur.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sur.h"
+
+namespace {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t v) { return __uint_as_float(uint32_t(v) << 16); }
+
+// round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t f2bf(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+
+__device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wmin(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wmax(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// ------------------------------------------------------------ convolution
+// Implicit GEMM: Y[p][o] = sum_{t, i} X[p + s d_t][i] Wk[t][o][i].
+// A wavefront owns 64 points (four 16-point M tiles) and a 64-channel block of
+// outputs (up to four 16-channel N tiles); the K loop runs over the 27 taps and
+// 16-channel slices of the input. MFMA 16x16x16 BF16 operand layout: lane l
+// holds A[m = l % 16][k = 4 (l / 16) .. +3] (4 consecutive input channels of
+// point m: one 8-byte load in channels-last storage) and B[k][n = l % 16]
+// (4 consecutive input channels of output channel n: one 8-byte load of the
+// [t][o][i] packing); the result D[m = 4 (l / 16) + j][n = l % 16] is in
+// register j.
+__global__ void __launch_bounds__(256) conv3d_kernel(const uint16_t *__restrict__ x, int cin,
+                                                     const uint16_t *__restrict__ w,
+                                                     const float *__restrict__ bias, int cout,
+                                                     int nx, int ny, int nz, int flip, int relu,
+                                                     const uint16_t *__restrict__ mask,
+                                                     uint16_t *__restrict__ yb,
+                                                     float *__restrict__ yf) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const long P = (long)nx * ny * nz;
+    const long pbase = ((long)blockIdx.x * 4 + wave) * 64;
+    const int cob = blockIdx.y * 64;
+    const int ntiles = min(4, (cout - cob) >> 4);
+    int px[4], py[4], pz[4];
+    bool pv[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const long p = pbase + mt * 16 + r;
+        pv[mt] = p < P;
+        const long pp = pv[mt] ? p : 0;
+        px[mt] = (int)(pp % nx);
+        py[mt] = (int)((pp / nx) % ny);
+        pz[mt] = (int)(pp / ((long)nx * ny));
+    }
+    f4 acc[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+    const s4 zero = s4{0, 0, 0, 0};
+    for (int t = 0; t < 27; ++t) {
+        int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+        if (flip) {
+            dx = -dx;
+            dy = -dy;
+            dz = -dz;
+        }
+        long nb[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            nb[mt] = (long)wrap(px[mt] + dx, nx) +
+                     (long)nx * ((long)wrap(py[mt] + dy, ny) + (long)ny * wrap(pz[mt] + dz, nz));
+        const uint16_t *wt = w + ((long)t * cout + cob) * cin;
+        for (int cc = 0; cc < cin; cc += 16) {
+            s4 a[4], b[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                a[mt] = pv[mt] ? *(const s4 *)(x + nb[mt] * cin + cc + 4 * q) : zero;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                b[nt] = nt < ntiles ? *(const s4 *)(wt + (long)(nt * 16 + r) * cin + cc + 4 * q)
+                                    : zero;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                if (nt < ntiles) {
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mt], b[nt],
+                                                                                 acc[mt][nt], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            if (nt >= ntiles) continue;
+            const int co = cob + nt * 16 + r;
+            const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const long p = pbase + mt * 16 + 4 * q + j;
+                if (p >= P) continue;
+                float v = acc[mt][nt][j] + bb;
+                if (relu) v = fmaxf(v, 0.f);
+                if (mask && !(bf2f(mask[p * cout + co]) > 0.f)) v = 0.f;
+                if (yb) yb[p * cout + co] = f2bf(v);
+                if (yf) yf[p * cout + co] = v;
+            }
+        }
+    }
+}
+
+// Weight gradient of one tap over one chunk of points:
+// dW[t][o][i] = sum_p dY[p][o] X[p + d_t][i], an M = cout, N = cin, K = points
+// product. Lane l feeds A[m = l % 16][k = 4 (l / 16) + j] = dY[p_j][o] and
+// B[k][n = l % 16] = X[p_j + d_t][i] for its four points p_j. The four
+// wavefronts of a block take interleaved 16-point steps of the chunk and are
+// summed in LDS (fixed order) into the chunk's partial.
+template <int MT>
+__global__ void __launch_bounds__(256) wgrad_kernel(const uint16_t *__restrict__ x, int cin,
+                                                    const uint16_t *__restrict__ dy, int cout,
+                                                    int nx, int ny, int nz, long chunk,
+                                                    float *__restrict__ part) {
+    __shared__ float red[4][MT * 16][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int t = blockIdx.x;
+    const long c = blockIdx.y;
+    const int cib = blockIdx.z * 64;
+    const int ntiles = min(4, (cin - cib) >> 4);
+    const int dx = t % 3 - 1, dyy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    const long P = (long)nx * ny * nz;
+    const long p0 = c * chunk, p1 = min(P, p0 + chunk);
+    f4 acc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+    for (long kb = p0 + wave * 16; kb < p1; kb += 64) {
+        long pj[4], nbj[4];
+        bool vj[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const long p = kb + 4 * q + j;
+            vj[j] = p < p1;
+            const long pp = vj[j] ? p : p0;
+            pj[j] = pp;
+            const int X = (int)(pp % nx), Y = (int)((pp / nx) % ny), Z = (int)(pp / ((long)nx * ny));
+            nbj[j] = (long)wrap(X + dx, nx) +
+                     (long)nx * ((long)wrap(Y + dyy, ny) + (long)ny * wrap(Z + dz, nz));
+        }
+        s4 a[MT], b[4];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                a[mt][j] = vj[j] ? (short)dy[pj[j] * cout + mt * 16 + r] : (short)0;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                b[nt][j] = (vj[j] && nt < ntiles) ? (short)x[nbj[j] * cin + cib + nt * 16 + r]
+                                                  : (short)0;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            if (nt < ntiles) {
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[mt][nt] =
+                        __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) red[wave][mt * 16 + 4 * q + j][nt * 16 + r] = acc[mt][nt][j];
+    __syncthreads();
+    const int nrow = MT * 16, ncol = ntiles * 16;
+    for (int e = threadIdx.x; e < nrow * 64; e += 256) {
+        const int o = e / 64, i = e % 64;
+        if (i >= ncol) continue;
+        const float s = ((red[0][o][i] + red[1][o][i]) + red[2][o][i]) + red[3][o][i];
+        part[((c * 27 + t) * (long)cout + o) * cin + cib + i] = s;
+    }
+}
+
+// dw[e] = sum over chunks of part[chunk][e] (fixed order).
+__global__ void sum_chunks_kernel(const float *__restrict__ part, long nchunks, long n,
+                                  float *__restrict__ out) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float s = 0.f;
+    for (long c = 0; c < nchunks; ++c) s += part[c * n + e];
+    out[e] = s;
+}
+
+// Per-block partial sums of dy over points for each channel: thread
+// (tid % cout) owns a channel, (tid / cout) a strided slice of the block's points.
+__global__ void __launch_bounds__(256) bias_partial_kernel(const uint16_t *__restrict__ dy, int cout,
+                                                           long P, long chunk,
+                                                           float *__restrict__ part) {
+    __shared__ float red[256];
+    const int ch = threadIdx.x % cout, lanes = 256 / cout, sl = threadIdx.x / cout;
+    const long p0 = (long)blockIdx.x * chunk, p1 = min(P, p0 + chunk);
+    float s = 0.f;
+    if (sl < lanes)
+        for (long p = p0 + sl; p < p1; p += lanes) s += bf2f(dy[p * cout + ch]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < cout) {
+        float t = 0.f;
+        for (int k = 0; k < lanes; ++k) t += red[k * cout + threadIdx.x];
+        part[(long)blockIdx.x * cout + threadIdx.x] = t;
+    }
+}
+
+__global__ void pack_weights_kernel(const float *__restrict__ w, int cin, int cout,
+                                    uint16_t *__restrict__ wf, uint16_t *__restrict__ wd) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long n = 27L * cin * cout;
+    if (e >= n) return;
+    const int t = (int)(e / ((long)cin * cout));
+    const int rem = (int)(e % ((long)cin * cout));
+    const int o = rem / cin, i = rem % cin;
+    const uint16_t v = f2bf(w[e]);
+    if (wf) wf[e] = v;
+    if (wd) wd[((long)t * cin + i) * cout + o] = v;
+}
+
+// ------------------------------------------------------------ grid layers
+__global__ void pool2_kernel(const uint16_t *__restrict__ x, int c, int nx, int ny, int nz,
+                             uint16_t *__restrict__ y) {
+    const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
+    const long n = (long)cx * cy * cz * c;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int ch = (int)(e % c);
+    const long qq = e / c;
+    const int X = (int)(qq % cx), Y = (int)((qq / cx) % cy), Z = (int)(qq / ((long)cx * cy));
+    float s = 0.f;
+    for (int k = 0; k < 8; ++k) {
+        const long p = (2 * X + (k & 1)) + (long)nx * ((2 * Y + ((k >> 1) & 1)) + (long)ny * (2 * Z + (k >> 2)));
+        s += bf2f(x[p * c + ch]);
+    }
+    y[e] = f2bf(0.125f * s);
+}
+
+__global__ void pool2_bwd_kernel(const float *__restrict__ dy, int c, int nx, int ny, int nz,
+                                 float *__restrict__ dx) {
+    const long n = (long)nx * ny * nz * c;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int ch = (int)(e % c);
+    const long p = e / c;
+    const int X = (int)(p % nx), Y = (int)((p / nx) % ny), Z = (int)(p / ((long)nx * ny));
+    const long qq = (X / 2) + (long)(nx / 2) * ((Y / 2) + (long)(ny / 2) * (Z / 2));
+    dx[e] += 0.125f * dy[qq * c + ch];
+}
+
+__global__ void upsample2_kernel(const uint16_t *__restrict__ x, int c, int nx, int ny, int nz,
+                                 uint16_t *__restrict__ y, int ystride, int yoff) {
+    const int fx = 2 * nx, fy = 2 * ny, fz = 2 * nz;
+    const long n = (long)fx * fy * fz * c;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int ch = (int)(e % c);
+    const long p = e / c;
+    const int X = (int)(p % fx), Y = (int)((p / fx) % fy), Z = (int)(p / ((long)fx * fy));
+    const long qq = (X / 2) + (long)nx * ((Y / 2) + (long)ny * (Z / 2));
+    y[p * ystride + yoff + ch] = x[qq * c + ch];
+}
+
+__global__ void upsample2_bwd_kernel(const float *__restrict__ dy, int dystride, int dyoff, int c,
+                                     int nx, int ny, int nz, float *__restrict__ dx) {
+    const long n = (long)nx * ny * nz * c;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int ch = (int)(e % c);
+    const long qq = e / c;
+    const int X = (int)(qq % nx), Y = (int)((qq / nx) % ny), Z = (int)(qq / ((long)nx * ny));
+    const int fx = 2 * nx, fy = 2 * ny;
+    float s = 0.f;
+    for (int k = 0; k < 8; ++k) {
+        const long p = (2 * X + (k & 1)) + (long)fx * ((2 * Y + ((k >> 1) & 1)) + (long)fy * (2 * Z + (k >> 2)));
+        s += dy[p * dystride + dyoff + ch];
+    }
+    dx[e] = s;
+}
+
+__global__ void copy_channels_kernel(const uint16_t *__restrict__ x, int c, long P,
+                                     uint16_t *__restrict__ y, int ystride, int yoff) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * c) return;
+    const long p = e / c;
+    y[p * ystride + yoff + (e % c)] = x[e];
+}
+
+__global__ void add_channels_kernel(const float *__restrict__ dy, int dystride, int dyoff, int c,
+                                    long P, float *__restrict__ dx) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * c) return;
+    const long p = e / c;
+    dx[e] += dy[p * dystride + dyoff + (e % c)];
+}
+
+__global__ void to_bf16_kernel(const float *__restrict__ x, long n, uint16_t *__restrict__ y) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) y[e] = f2bf(x[e]);
+}
+
+__global__ void relu_mask_kernel(float *__restrict__ dx, const uint16_t *__restrict__ act, long n) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n && !(bf2f(act[e]) > 0.f)) dx[e] = 0.f;
+}
+
+// ------------------------------------------------------------ loss, Adam
+__global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ pred,
+                                                  const float *__restrict__ tgt, int cu, int cs,
+                                                  long P, const float *__restrict__ wch,
+                                                  float *__restrict__ grad,
+                                                  double *__restrict__ part) {
+    __shared__ double red[4];
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double l = 0.0;
+    if (p < P) {
+        const float inv = 1.0f / (float)((double)P * cu);
+        for (int ch = 0; ch < cs; ++ch) {
+            float g = 0.f;
+            if (ch < cu) {
+                const float d = pred[p * cs + ch] - tgt[p * cs + ch];
+                l += (double)wch[ch] * d * d;
+                g = 2.f * wch[ch] * d * inv;
+            }
+            grad[p * cs + ch] = g;
+        }
+    }
+    l = wsum(l);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ void __launch_bounds__(1024) final_sum_kernel(const double *__restrict__ part, long n,
+                                                         double scale, double *__restrict__ out) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (long k = threadIdx.x; k < n; k += 1024) s += part[k];
+    s = wsum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < 16; ++k) t += red[k];
+        *out = t * scale;
+    }
+}
+
+__global__ void adam_kernel(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                            const float *__restrict__ g, long n, float lr, float b1, float b2,
+                            float eps, float bc1, float bc2) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float gg = g[e];
+    const float mm = b1 * m[e] + (1.f - b1) * gg;
+    const float vv = b2 * v[e] + (1.f - b2) * gg * gg;
+    m[e] = mm;
+    v[e] = vv;
+    w[e] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+}
+
+// ------------------------------------------------------ grid transfer
+__global__ void coarsen_kernel(const float *__restrict__ phi, const float *__restrict__ u,
+                               const float *__restrict__ p, int nx, int ny, int nz,
+                               const float *__restrict__ scale, float *__restrict__ cf,
+                               uint16_t *__restrict__ cb) {
+    const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
+    const long Pc = (long)cx * cy * cz;
+    const long qq = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (qq >= Pc) return;
+    const long N = (long)nx * ny * nz;
+    const int X = (int)(qq % cx), Y = (int)((qq / cx) % cy), Z = (int)(qq / ((long)cx * cy));
+    float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < 8; ++k) {
+        const long f = (2 * X + (k & 1)) + (long)nx * ((2 * Y + ((k >> 1) & 1)) + (long)ny * (2 * Z + (k >> 2)));
+        s[0] += phi[f];
+        s[1] += u[f];
+        s[2] += u[N + f];
+        s[3] += u[2 * N + f];
+        s[4] += p[f];
+    }
+    for (int ch = 0; ch < 16; ++ch) {
+        const float v = ch < 5 ? 0.125f * s[ch] / scale[ch] : 0.f;
+        if (cf) cf[qq * 16 + ch] = v;
+        if (cb) cb[qq * 16 + ch] = f2bf(v);
+    }
+}
+
+__global__ void prolong_add_kernel(const float *__restrict__ d, int cx, int cy, int cz,
+                                   const float *__restrict__ scale, double *__restrict__ phi,
+                                   double *__restrict__ u, double *__restrict__ p) {
+    const int nx = 2 * cx, ny = 2 * cy, nz = 2 * cz;
+    const long N = (long)nx * ny * nz;
+    const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= N) return;
+    const int X = (int)(f % nx), Y = (int)((f / nx) % ny), Z = (int)(f / ((long)nx * ny));
+    // fine node X sits at coarse coordinate (X + 1/2)/2 - 1/2
+    auto lo = [](int X) { return (X - 1) >> 1; };  // floor((X - 1)/2)
+    const int x0 = lo(X), y0 = lo(Y), z0 = lo(Z);
+    const float wx = (X & 1) ? 0.25f : 0.75f, wy = (Y & 1) ? 0.25f : 0.75f, wz = (Z & 1) ? 0.25f : 0.75f;
+    float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < 8; ++k) {
+        const int ix = wrap(x0 + (k & 1), cx), iy = wrap(y0 + ((k >> 1) & 1), cy), iz = wrap(z0 + (k >> 2), cz);
+        const float w = ((k & 1) ? wx : 1.f - wx) * (((k >> 1) & 1) ? wy : 1.f - wy) * ((k >> 2) ? wz : 1.f - wz);
+        const long qq = ix + (long)cx * (iy + (long)cy * iz);
+        for (int ch = 0; ch < 5; ++ch) acc[ch] += w * d[qq * 16 + ch];
+    }
+    phi[f] += (double)(scale[0] * acc[0]);
+    u[f] += (double)(scale[1] * acc[1]);
+    u[N + f] += (double)(scale[2] * acc[2]);
+    u[2 * N + f] += (double)(scale[3] * acc[3]);
+    p[f] += (double)(scale[4] * acc[4]);
+}
+
+__global__ void __launch_bounds__(256) checks_kernel(const float *__restrict__ s, int nx, int ny,
+                                                     int nz, double *__restrict__ part) {
+    __shared__ double red[6][4];
+    const long P = (long)nx * ny * nz;
+    const long qq = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[6] = {0.0, 1e300, -1e300, 0.0, 0.0, 0.0};
+    if (qq < P) {
+        const int X = (int)(qq % nx), Y = (int)((qq / nx) % ny), Z = (int)(qq / ((long)nx * ny));
+        auto at = [&](int x, int y, int z) {
+            return (long)wrap(x, nx) + (long)nx * ((long)wrap(y, ny) + (long)ny * wrap(z, nz));
+        };
+        const double phi = s[qq * 16];
+        const double div = 0.5 * ((double)s[at(X + 1, Y, Z) * 16 + 1] - s[at(X - 1, Y, Z) * 16 + 1] +
+                                  (double)s[at(X, Y + 1, Z) * 16 + 2] - s[at(X, Y - 1, Z) * 16 + 2] +
+                                  (double)s[at(X, Y, Z + 1) * 16 + 3] - s[at(X, Y, Z - 1) * 16 + 3]);
+        const double ux = s[qq * 16 + 1], uy = s[qq * 16 + 2], uz = s[qq * 16 + 3];
+        v[0] = phi;
+        v[1] = phi;
+        v[2] = phi;
+        v[3] = div * div;
+        v[4] = ux * ux + uy * uy + uz * uz;
+        v[5] = 1.0;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = 0; k < 6; ++k) {
+        const double r = k == 1 ? wmin(v[k]) : (k == 2 ? wmax(v[k]) : wsum(v[k]));
+        if (lane == 0) red[k][wv] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        double r = red[k][0];
+        for (int w = 1; w < 4; ++w) r = k == 1 ? fmin(r, red[k][w]) : (k == 2 ? fmax(r, red[k][w]) : r + red[k][w]);
+        part[(long)blockIdx.x * 6 + k] = r;
+    }
+}
+
+__global__ void __launch_bounds__(1024) checks_final_kernel(const double *__restrict__ part, long nb,
+                                                            double *__restrict__ out) {
+    __shared__ double red[6][16];
+    double v[6] = {0.0, 1e300, -1e300, 0.0, 0.0, 0.0};
+    for (long b = threadIdx.x; b < nb; b += 1024)
+        for (int k = 0; k < 6; ++k) {
+            const double x = part[b * 6 + k];
+            v[k] = k == 1 ? fmin(v[k], x) : (k == 2 ? fmax(v[k], x) : v[k] + x);
+        }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = 0; k < 6; ++k) {
+        const double r = k == 1 ? wmin(v[k]) : (k == 2 ? wmax(v[k]) : wsum(v[k]));
+        if (lane == 0) red[k][wv] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        double r = red[k][0];
+        for (int w = 1; w < 16; ++w) r = k == 1 ? fmin(r, red[k][w]) : (k == 2 ? fmax(r, red[k][w]) : r + red[k][w]);
+        out[k] = r;
+    }
+}
+
+// ------------------------------------------------------------ host helpers
+int launched() { return hipGetLastError() == hipSuccess ? SUR_OK : SUR_EDEVICE; }
+
+dim3 grid1(long n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
+
+bool dims_ok(int nx, int ny, int nz) { return nx > 0 && ny > 0 && nz > 0; }
+
+constexpr long kWgradChunk = 8192;
+
+long wgrad_chunks(long P) { return (P + kWgradChunk - 1) / kWgradChunk; }
+
+}  // namespace
+
+extern "C" {
+
+int sur_conv3d(const void *x, int32_t cin, const void *w, const float *bias, int32_t cout,
+               int32_t nx, int32_t ny, int32_t nz, int32_t flip, int32_t relu, const void *mask,
+               void *y_bf16, float *y_f32, void *stream) {
+    if (!x || !w || (!y_bf16 && !y_f32) || cin <= 0 || cout <= 0 || cin % 16 || cout % 16 ||
+        !dims_ok(nx, ny, nz))
+        return SUR_EINVAL;
+    const long P = (long)nx * ny * nz;
+    const dim3 grid((unsigned)((P + 255) / 256), (unsigned)((cout + 63) / 64));
+    hipLaunchKernelGGL(conv3d_kernel, grid, dim3(256), 0, (hipStream_t)stream, (const uint16_t *)x,
+                       cin, (const uint16_t *)w, bias, cout, nx, ny, nz, flip, relu,
+                       (const uint16_t *)mask, (uint16_t *)y_bf16, y_f32);
+    return launched();
+}
+
+size_t sur_wgrad_scratch_floats(int32_t cin, int32_t cout, int32_t nx, int32_t ny, int32_t nz) {
+    const long P = (long)nx * ny * nz;
+    return (size_t)(wgrad_chunks(P) * 27L * cin * cout + grid1(P, 1024).x * (long)cout);
+}
+
+int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, int32_t nx,
+                     int32_t ny, int32_t nz, float *scratch, size_t scratch_floats, float *dw,
+                     float *dbias, void *stream) {
+    if (!x || !dy || !scratch || !dw || cin <= 0 || cout <= 0 || cin % 16 || cout % 16 ||
+        cout > 64 || !dims_ok(nx, ny, nz))
+        return SUR_EINVAL;
+    if (scratch_floats < sur_wgrad_scratch_floats(cin, cout, nx, ny, nz)) return SUR_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const long P = (long)nx * ny * nz;
+    const long nch = wgrad_chunks(P);
+    const dim3 grid(27, (unsigned)nch, (unsigned)((cin + 63) / 64));
+    const uint16_t *xb = (const uint16_t *)x, *db = (const uint16_t *)dy;
+    switch (cout / 16) {
+        case 1: hipLaunchKernelGGL(wgrad_kernel<1>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, kWgradChunk, scratch); break;
+        case 2: hipLaunchKernelGGL(wgrad_kernel<2>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, kWgradChunk, scratch); break;
+        case 3: hipLaunchKernelGGL(wgrad_kernel<3>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, kWgradChunk, scratch); break;
+        default: hipLaunchKernelGGL(wgrad_kernel<4>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, kWgradChunk, scratch); break;
+    }
+    const long n = 27L * cin * cout;
+    hipLaunchKernelGGL(sum_chunks_kernel, grid1(n), dim3(256), 0, s, (const float *)scratch, nch, n, dw);
+    if (dbias) {
+        const long nb = grid1(P, 1024).x;
+        float *bp = scratch + nch * n;
+        hipLaunchKernelGGL(bias_partial_kernel, dim3((unsigned)nb), dim3(256), 0, s, db, cout, P, 1024L, bp);
+        hipLaunchKernelGGL(sum_chunks_kernel, grid1(cout), dim3(256), 0, s, (const float *)bp, nb, (long)cout, dbias);
+    }
+    return launched();
+}
+
+int sur_pack_weights(const float *w, int32_t cin, int32_t cout, void *wf, void *wd, void *stream) {
+    if (!w || (!wf && !wd) || cin <= 0 || cout <= 0) return SUR_EINVAL;
+    const long n = 27L * cin * cout;
+    hipLaunchKernelGGL(pack_weights_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, w, cin,
+                       cout, (uint16_t *)wf, (uint16_t *)wd);
+    return launched();
+}
+
+int sur_pool2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void *y, void *stream) {
+    if (!x || !y || c <= 0 || !dims_ok(nx, ny, nz) || nx % 2 || ny % 2 || nz % 2) return SUR_EINVAL;
+    const long n = (long)(nx / 2) * (ny / 2) * (nz / 2) * c;
+    hipLaunchKernelGGL(pool2_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream,
+                       (const uint16_t *)x, c, nx, ny, nz, (uint16_t *)y);
+    return launched();
+}
+
+int sur_pool2_bwd(const float *dy, int32_t c, int32_t nx, int32_t ny, int32_t nz, float *dx,
+                  void *stream) {
+    if (!dy || !dx || c <= 0 || !dims_ok(nx, ny, nz) || nx % 2 || ny % 2 || nz % 2) return SUR_EINVAL;
+    const long n = (long)nx * ny * nz * c;
+    hipLaunchKernelGGL(pool2_bwd_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, dy, c, nx,
+                       ny, nz, dx);
+    return launched();
+}
+
+int sur_upsample2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void *y,
+                  int32_t ystride, int32_t yoff, void *stream) {
+    if (!x || !y || c <= 0 || !dims_ok(nx, ny, nz) || yoff < 0 || yoff + c > ystride) return SUR_EINVAL;
+    const long n = 8L * nx * ny * nz * c;
+    hipLaunchKernelGGL(upsample2_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream,
+                       (const uint16_t *)x, c, nx, ny, nz, (uint16_t *)y, ystride, yoff);
+    return launched();
+}
+
+int sur_upsample2_bwd(const float *dy, int32_t dystride, int32_t dyoff, int32_t c, int32_t nx,
+                      int32_t ny, int32_t nz, float *dx, void *stream) {
+    if (!dy || !dx || c <= 0 || !dims_ok(nx, ny, nz) || dyoff < 0 || dyoff + c > dystride) return SUR_EINVAL;
+    const long n = (long)nx * ny * nz * c;
+    hipLaunchKernelGGL(upsample2_bwd_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, dy,
+                       dystride, dyoff, c, nx, ny, nz, dx);
+    return launched();
+}
+
+int sur_copy_channels(const void *x, int32_t c, int64_t P, void *y, int32_t ystride, int32_t yoff,
+                      void *stream) {
+    if (!x || !y || c <= 0 || P <= 0 || yoff < 0 || yoff + c > ystride) return SUR_EINVAL;
+    hipLaunchKernelGGL(copy_channels_kernel, grid1(P * c), dim3(256), 0, (hipStream_t)stream,
+                       (const uint16_t *)x, c, (long)P, (uint16_t *)y, ystride, yoff);
+    return launched();
+}
+
+int sur_add_channels(const float *dy, int32_t dystride, int32_t dyoff, int32_t c, int64_t P,
+                     float *dx, void *stream) {
+    if (!dy || !dx || c <= 0 || P <= 0 || dyoff < 0 || dyoff + c > dystride) return SUR_EINVAL;
+    hipLaunchKernelGGL(add_channels_kernel, grid1(P * c), dim3(256), 0, (hipStream_t)stream, dy,
+                       dystride, dyoff, c, (long)P, dx);
+    return launched();
+}
+
+int sur_to_bf16(const float *x, int64_t n, void *y, void *stream) {
+    if (!x || !y || n < 0) return SUR_EINVAL;
+    if (n == 0) return SUR_OK;
+    hipLaunchKernelGGL(to_bf16_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, x, (long)n,
+                       (uint16_t *)y);
+    return launched();
+}
+
+int sur_relu_mask(float *dx, const void *act, int64_t n, void *stream) {
+    if (!dx || !act || n < 0) return SUR_EINVAL;
+    if (n == 0) return SUR_OK;
+    hipLaunchKernelGGL(relu_mask_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, dx,
+                       (const uint16_t *)act, (long)n);
+    return launched();
+}
+
+int sur_mse(const float *pred, const float *target, int32_t cu, int32_t cs, int64_t P,
+            const float *wch, float *grad, double *scratch, double *loss_out, void *stream) {
+    if (!pred || !target || !wch || !grad || !scratch || !loss_out || cu <= 0 || cs < cu || P <= 0)
+        return SUR_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const long nb = grid1(P).x;
+    hipLaunchKernelGGL(mse_kernel, dim3((unsigned)nb), dim3(256), 0, s, pred, target, cu, cs,
+                       (long)P, wch, grad, scratch);
+    hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(1024), 0, s, (const double *)scratch, nb,
+                       1.0 / ((double)P * cu), loss_out);
+    return launched();
+}
+
+int sur_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float beta1,
+             float beta2, float eps, int32_t t, void *stream) {
+    if (!w || !m || !v || !g || n <= 0 || t < 1) return SUR_EINVAL;
+    const float bc1 = 1.f - (float)pow((double)beta1, (double)t);
+    const float bc2 = 1.f - (float)pow((double)beta2, (double)t);
+    hipLaunchKernelGGL(adam_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, w, m, v, g,
+                       (long)n, lr, beta1, beta2, eps, bc1, bc2);
+    return launched();
+}
+
+int sur_coarsen(const float *phi, const float *u, const float *p, int32_t nx, int32_t ny, int32_t nz,
+                const float *scale, float *coarse_f32, void *coarse_bf16, void *stream) {
+    if (!phi || !u || !p || !scale || (!coarse_f32 && !coarse_bf16) || !dims_ok(nx, ny, nz) ||
+        nx % 2 || ny % 2 || nz % 2)
+        return SUR_EINVAL;
+    const long Pc = (long)(nx / 2) * (ny / 2) * (nz / 2);
+    hipLaunchKernelGGL(coarsen_kernel, grid1(Pc), dim3(256), 0, (hipStream_t)stream, phi, u, p, nx,
+                       ny, nz, scale, coarse_f32, (uint16_t *)coarse_bf16);
+    return launched();
+}
+
+int sur_prolong_add(const float *delta, int32_t cnx, int32_t cny, int32_t cnz, const float *scale,
+                    double *phi, double *u, double *p, void *stream) {
+    if (!delta || !scale || !phi || !u || !p || !dims_ok(cnx, cny, cnz)) return SUR_EINVAL;
+    const long N = 8L * cnx * cny * cnz;
+    hipLaunchKernelGGL(prolong_add_kernel, grid1(N), dim3(256), 0, (hipStream_t)stream, delta, cnx,
+                       cny, cnz, scale, phi, u, p);
+    return launched();
+}
+
+int sur_checks(const float *state, int32_t nx, int32_t ny, int32_t nz, double *scratch, double *out,
+               void *stream) {
+    if (!state || !scratch || !out || !dims_ok(nx, ny, nz)) return SUR_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const long P = (long)nx * ny * nz;
+    const long nb = grid1(P).x;
+    hipLaunchKernelGGL(checks_kernel, dim3((unsigned)nb), dim3(256), 0, s, state, nx, ny, nz, scratch);
+    hipLaunchKernelGGL(checks_final_kernel, dim3(1), dim3(1024), 0, s, (const double *)scratch, nb, out);
+    return launched();
+}
+
+}  // extern "C"

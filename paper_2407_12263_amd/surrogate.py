@@ -1,0 +1,404 @@
+"""Coarse-grid 3D U-Net surrogate: Python orchestration of the HIP kernels in
+``libsur.so`` (C ABI ``include/sur.h``).
+
+The network advances the coarsened state (phi, u, p) of the LBM solver by a
+window of K steps: state(t + K) = state(t) + UNet(state(t)). Every layer is a
+``sur_*`` kernel launch on the current stream (3x3x3 convolutions on BF16
+matrix cores with FP32 accumulation, pooling, upsampling, concat, residual
+MSE, Adam); this module only allocates the tensors (PyTorch) and sequences
+the calls. There is no fallback: without the library or a GPU it raises.
+
+Architecture (channels per level, e.g. 16-32-48-64): per level two
+conv + ReLU, 2x average pooling between levels, nearest 2x upsampling and
+concat with the skip on the way up, two conv + ReLU, a final linear conv.
+Input and output have 16 channels of which the first 5 are used.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsur.so")
+NCH = 16          # stored channels of the state
+NUSE = 5          # phi, ux, uy, uz, p
+
+_lib = None
+
+
+def load_library(path: str | None = None):
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise FileNotFoundError(f"HIP library {p} is not built; run __graft_entry__.build()")
+    lib = C.CDLL(p)
+    vp, i32, i64, fl, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
+    lib.sur_conv3d.argtypes = [vp, i32, vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp]
+    lib.sur_wgrad_scratch_floats.argtypes = [i32, i32, i32, i32, i32]
+    lib.sur_wgrad_scratch_floats.restype = sz
+    lib.sur_conv3d_wgrad.argtypes = [vp, i32, vp, i32, i32, i32, i32, vp, sz, vp, vp, vp]
+    lib.sur_pack_weights.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.sur_pool2.argtypes = [vp, i32, i32, i32, i32, vp, vp]
+    lib.sur_pool2_bwd.argtypes = [vp, i32, i32, i32, i32, vp, vp]
+    lib.sur_upsample2.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, vp]
+    lib.sur_upsample2_bwd.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp]
+    lib.sur_copy_channels.argtypes = [vp, i32, i64, vp, i32, i32, vp]
+    lib.sur_add_channels.argtypes = [vp, i32, i32, i32, i64, vp, vp]
+    lib.sur_to_bf16.argtypes = [vp, i64, vp, vp]
+    lib.sur_relu_mask.argtypes = [vp, vp, i64, vp]
+    lib.sur_mse.argtypes = [vp, vp, i32, i32, i64, vp, vp, vp, vp, vp]
+    lib.sur_adam.argtypes = [vp, vp, vp, vp, i64, fl, fl, fl, fl, i32, vp]
+    lib.sur_coarsen.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, vp]
+    lib.sur_prolong_add.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.sur_checks.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+    for n in ["sur_conv3d", "sur_conv3d_wgrad", "sur_pack_weights", "sur_pool2", "sur_pool2_bwd",
+              "sur_upsample2", "sur_upsample2_bwd", "sur_copy_channels", "sur_add_channels",
+              "sur_to_bf16", "sur_relu_mask", "sur_mse", "sur_adam", "sur_coarsen",
+              "sur_prolong_add", "sur_checks"]:
+        getattr(lib, n).restype = C.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ok(rc, where):
+    if rc != 0:
+        raise RuntimeError(f"{where} failed with status {rc}")
+
+
+# ------------------------------------------------------------ C names
+
+def sur_conv3d(x, cin, w, bias, cout, grid, flip=0, relu=0, mask=None, y_bf16=None, y_f32=None):
+    nx, ny, nz = grid
+    _ok(load_library().sur_conv3d(_p(x), cin, _p(w), _p(bias), cout, nx, ny, nz, flip, relu,
+                                  _p(mask), _p(y_bf16), _p(y_f32), _stream()), "sur_conv3d")
+
+
+def sur_wgrad_scratch_floats(cin, cout, grid):
+    return int(load_library().sur_wgrad_scratch_floats(cin, cout, *grid))
+
+
+def sur_conv3d_wgrad(x, cin, dy, cout, grid, scratch, dw, dbias):
+    nx, ny, nz = grid
+    _ok(load_library().sur_conv3d_wgrad(_p(x), cin, _p(dy), cout, nx, ny, nz, _p(scratch),
+                                        scratch.numel(), _p(dw), _p(dbias), _stream()),
+        "sur_conv3d_wgrad")
+
+
+def sur_pack_weights(w, cin, cout, wf, wd):
+    _ok(load_library().sur_pack_weights(_p(w), cin, cout, _p(wf), _p(wd), _stream()),
+        "sur_pack_weights")
+
+
+def sur_pool2(x, c, grid, y):
+    _ok(load_library().sur_pool2(_p(x), c, *grid, _p(y), _stream()), "sur_pool2")
+
+
+def sur_pool2_bwd(dy, c, grid, dx):
+    _ok(load_library().sur_pool2_bwd(_p(dy), c, *grid, _p(dx), _stream()), "sur_pool2_bwd")
+
+
+def sur_upsample2(x, c, grid, y, ystride, yoff):
+    _ok(load_library().sur_upsample2(_p(x), c, *grid, _p(y), ystride, yoff, _stream()),
+        "sur_upsample2")
+
+
+def sur_upsample2_bwd(dy, dystride, dyoff, c, grid, dx):
+    _ok(load_library().sur_upsample2_bwd(_p(dy), dystride, dyoff, c, *grid, _p(dx), _stream()),
+        "sur_upsample2_bwd")
+
+
+def sur_copy_channels(x, c, P, y, ystride, yoff):
+    _ok(load_library().sur_copy_channels(_p(x), c, P, _p(y), ystride, yoff, _stream()),
+        "sur_copy_channels")
+
+
+def sur_add_channels(dy, dystride, dyoff, c, P, dx):
+    _ok(load_library().sur_add_channels(_p(dy), dystride, dyoff, c, P, _p(dx), _stream()),
+        "sur_add_channels")
+
+
+def sur_to_bf16(x, y):
+    _ok(load_library().sur_to_bf16(_p(x), x.numel(), _p(y), _stream()), "sur_to_bf16")
+
+
+def sur_relu_mask(dx, act):
+    _ok(load_library().sur_relu_mask(_p(dx), _p(act), dx.numel(), _stream()), "sur_relu_mask")
+
+
+def sur_mse(pred, target, cu, cs, P, wch, grad, scratch, loss_out):
+    _ok(load_library().sur_mse(_p(pred), _p(target), cu, cs, P, _p(wch), _p(grad), _p(scratch),
+                               _p(loss_out), _stream()), "sur_mse")
+
+
+def sur_adam(w, m, v, g, lr, b1, b2, eps, t):
+    _ok(load_library().sur_adam(_p(w), _p(m), _p(v), _p(g), w.numel(), lr, b1, b2, eps, t,
+                                _stream()), "sur_adam")
+
+
+def sur_coarsen(phi, u, p, grid, scale, coarse_f32, coarse_bf16=None):
+    _ok(load_library().sur_coarsen(_p(phi), _p(u), _p(p), *grid, _p(scale), _p(coarse_f32),
+                                   _p(coarse_bf16), _stream()), "sur_coarsen")
+
+
+def sur_prolong_add(delta, cgrid, scale, phi, u, p):
+    _ok(load_library().sur_prolong_add(_p(delta), *cgrid, _p(scale), _p(phi), _p(u), _p(p),
+                                       _stream()), "sur_prolong_add")
+
+
+def sur_checks(state, grid, scratch, out):
+    _ok(load_library().sur_checks(_p(state), *grid, _p(scratch), _p(out), _stream()), "sur_checks")
+
+
+# ---------------------------------------------------------------- the U-Net
+
+def unet_layers(channels, cin=NCH, cout=NCH):
+    """(name, cin, cout, relu) of every conv in parameter order (encoder
+    levels a/b, decoder levels from the bottom up, final conv)."""
+    L = []
+    prev = cin
+    for lv, c in enumerate(channels):
+        L.append((f"enc{lv}a", prev, c, True))
+        L.append((f"enc{lv}b", c, c, True))
+        prev = c
+    for lv in range(len(channels) - 2, -1, -1):
+        c = channels[lv]
+        L.append((f"dec{lv}a", prev + c, c, True))
+        L.append((f"dec{lv}b", c, c, True))
+        prev = c
+    L.append(("out", prev, cout, False))
+    return L
+
+
+class UNet:
+    """Parameters, Adam state and activation buffers of one U-Net on a fixed
+    coarse grid (nx, ny, nz), each divisible by 2^(levels-1)."""
+
+    def __init__(self, grid, channels=(16, 32, 48, 64), seed=0, device="cuda:0", out_scale=0.1):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the surrogate runs on the GPU; none is visible")
+        load_library()
+        self.torch = torch
+        self.dev = torch.device(device)
+        self.channels = tuple(channels)
+        self.layers = unet_layers(self.channels)
+        self.nlev = len(self.channels)
+        nx, ny, nz = grid
+        for n in grid:
+            if n % (2 ** (self.nlev - 1)):
+                raise ValueError("grid sizes must be divisible by 2^(levels-1)")
+        self.grids = [(nx >> l, ny >> l, nz >> l) for l in range(self.nlev)]
+        self.P = [a * b * c for (a, b, c) in self.grids]
+        g = torch.Generator().manual_seed(seed)
+        self.w, self.b = [], []
+        for k, (name, ci, co, relu) in enumerate(self.layers):
+            std = math.sqrt(2.0 / (27 * ci)) * (1.0 if relu else out_scale)
+            self.w.append((torch.randn((27, co, ci), generator=g) * std).to(self.dev))
+            self.b.append(torch.zeros(co, device=self.dev))
+        self.mw = [torch.zeros_like(w) for w in self.w]
+        self.vw = [torch.zeros_like(w) for w in self.w]
+        self.mb = [torch.zeros_like(b) for b in self.b]
+        self.vb = [torch.zeros_like(b) for b in self.b]
+        self.gw = [torch.zeros_like(w) for w in self.w]
+        self.gb = [torch.zeros_like(b) for b in self.b]
+        self.wf = [torch.empty(w.shape, dtype=torch.int16, device=self.dev) for w in self.w]
+        self.wd = [torch.empty((27, w.shape[2], w.shape[1]), dtype=torch.int16, device=self.dev)
+                   for w in self.w]
+        self.adam_t = 0
+        self._alloc()
+        self.pack()
+
+    # -------------------------------------------------------------- buffers
+    def _alloc(self):
+        torch = self.torch
+        bf = lambda P, c: torch.empty((P, c), dtype=torch.int16, device=self.dev)
+        f32 = lambda P, c: torch.zeros((P, c), dtype=torch.float32, device=self.dev)
+        self.act = {}
+        for k, (name, ci, co, relu) in enumerate(self.layers):
+            lv = self._level(name)
+            if relu:
+                self.act[name] = bf(self.P[lv], co)
+        for lv in range(self.nlev - 1):
+            self.act[f"pool{lv}"] = bf(self.P[lv + 1], self.channels[lv])
+        for lv in range(self.nlev - 1):
+            # [upsampled output of level lv + 1, skip of level lv]
+            self.act[f"cat{lv}"] = bf(self.P[lv], self.channels[lv + 1] + self.channels[lv])
+        self.out = f32(self.P[0], NCH)
+        sc = 0
+        for k, (name, ci, co, relu) in enumerate(self.layers):
+            sc = max(sc, sur_wgrad_scratch_floats(ci, co, self.grids[self._level(name)]))
+        self.scratch = torch.empty(sc, dtype=torch.float32, device=self.dev)
+        self.loss_scratch = torch.empty(self.P[0] // 256 + 2, dtype=torch.float64, device=self.dev)
+        self.loss_dev = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        self.dout = f32(self.P[0], NCH)
+
+    @staticmethod
+    def _level(name):
+        return 0 if name == "out" else int(name[3:-1])
+
+    def pack(self):
+        for k, (name, ci, co, relu) in enumerate(self.layers):
+            sur_pack_weights(self.w[k], ci, co, self.wf[k], self.wd[k])
+
+    def n_params(self):
+        return sum(w.numel() + b.numel() for w, b in zip(self.w, self.b))
+
+    # -------------------------------------------------------------- forward
+    def forward(self, x_bf16):
+        """x_bf16: int16 tensor [P0, 16] (BF16 bits). Returns the FP32 output
+        [P0, 16] (the residual in scaled units)."""
+        k = 0
+        h = x_bf16
+        hc = NCH
+        for lv in range(self.nlev):
+            g = self.grids[lv]
+            for part in "ab":
+                name, ci, co, relu = self.layers[k]
+                sur_conv3d(h, ci, self.wf[k], self.b[k], co, g, relu=1, y_bf16=self.act[name])
+                h, hc = self.act[name], co
+                k += 1
+            if lv < self.nlev - 1:
+                sur_pool2(h, hc, g, self.act[f"pool{lv}"])
+                h = self.act[f"pool{lv}"]
+        for lv in range(self.nlev - 2, -1, -1):
+            cat = self.act[f"cat{lv}"]
+            ctot = cat.shape[1]
+            sur_upsample2(h, hc, self.grids[lv + 1], cat, ctot, 0)
+            sur_copy_channels(self.act[f"enc{lv}b"], self.channels[lv], self.P[lv], cat, ctot, hc)
+            h, hc = cat, ctot
+            for part in "ab":
+                name, ci, co, relu = self.layers[k]
+                sur_conv3d(h, ci, self.wf[k], self.b[k], co, self.grids[lv], relu=1,
+                           y_bf16=self.act[name])
+                h, hc = self.act[name], co
+                k += 1
+        name, ci, co, relu = self.layers[k]
+        sur_conv3d(h, ci, self.wf[k], self.b[k], co, self.grids[0], relu=0, y_f32=self.out)
+        self._last_input = x_bf16
+        return self.out
+
+    # ------------------------------------------------------------- backward
+    def _conv_back(self, k, x_in, dy_f32, grid, mask):
+        """Weight/bias gradients of layer k and, if mask is not None or the
+        input needs a gradient, the FP32 input gradient (masked by mask > 0)."""
+        name, ci, co, relu = self.layers[k]
+        lv = self._level(name)
+        P = self.P[lv]
+        dyb = self.torch.empty((P, co), dtype=self.torch.int16, device=self.dev)
+        sur_to_bf16(dy_f32, dyb)
+        sur_conv3d_wgrad(x_in, ci, dyb, co, grid, self.scratch, self.gw[k], self.gb[k])
+        dx = self.torch.empty((P, ci), dtype=self.torch.float32, device=self.dev)
+        sur_conv3d(dyb, co, self.wd[k], None, ci, grid, flip=1, relu=0, mask=mask, y_f32=dx)
+        return dx
+
+    def backward(self, dout):
+        """dout: FP32 [P0, 16] gradient at the output. Fills gw, gb."""
+        torch = self.torch
+        k = len(self.layers) - 1
+        nlev = self.nlev
+        last = self.layers[k - 1][0]
+        dh = self._conv_back(k, self.act[last], dout, self.grids[0], mask=self.act[last])
+        dskip = [None] * (nlev - 1)
+        for lv in range(0, nlev - 1):
+            for part in "ba":
+                k -= 1
+                name, ci, co, relu = self.layers[k]
+                x_in = self.act[f"cat{lv}"] if part == "a" else self.act[self.layers[k - 1][0]]
+                if part == "b":
+                    mask = self.act[self.layers[k - 1][0]]
+                else:
+                    mask = None  # input is the concat: split below, masks come from its parts
+                dh = self._conv_back(k, x_in, dh, self.grids[lv], mask)
+            cup = dh.shape[1] - self.channels[lv]
+            # skip part: gradient w.r.t. enc{lv}b output (masked later with the encoder)
+            ds = torch.empty((self.P[lv], self.channels[lv]), dtype=torch.float32, device=self.dev)
+            ds.zero_()
+            sur_add_channels(dh, dh.shape[1], cup, self.channels[lv], self.P[lv], ds)
+            dskip[lv] = ds
+            # upsampled part: gradient w.r.t. the lower level's output
+            du = torch.empty((self.P[lv + 1], cup), dtype=torch.float32, device=self.dev)
+            sur_upsample2_bwd(dh, dh.shape[1], 0, cup, self.grids[lv + 1], du)
+            # that output is a ReLU activation (bottom or decoder b of lv + 1)
+            below = f"enc{lv + 1}b" if lv + 1 == nlev - 1 else f"dec{lv + 1}b"
+            sur_relu_mask(du, self.act[below])
+            dh = du
+        for lv in range(nlev - 1, -1, -1):
+            if lv < nlev - 1:
+                # gradient w.r.t. enc{lv}b output = pooled path + skip path
+                dfull = torch.zeros((self.P[lv], self.channels[lv]), dtype=torch.float32,
+                                    device=self.dev)
+                sur_pool2_bwd(dh, self.channels[lv], self.grids[lv], dfull)
+                sur_add_channels(dskip[lv], self.channels[lv], 0, self.channels[lv], self.P[lv], dfull)
+                sur_relu_mask(dfull, self.act[f"enc{lv}b"])
+                dh = dfull
+            for part in "ba":
+                k -= 1
+                name, ci, co, relu = self.layers[k]
+                if part == "b":
+                    x_in = self.act[self.layers[k - 1][0]]
+                    mask = x_in
+                else:
+                    x_in = self._last_input if lv == 0 else self.act[f"pool{lv - 1}"]
+                    mask = None
+                dh = self._conv_back(k, x_in, dh, self.grids[lv], mask)
+        return dh
+
+    def loss_and_grad(self, target_f32, wch):
+        """Residual MSE on the used channels; gradient into self.dout."""
+        sur_mse(self.out, target_f32, NUSE, NCH, self.P[0], wch, self.dout, self.loss_scratch,
+                self.loss_dev)
+        return self.loss_dev
+
+    def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.adam_t += 1
+        for k in range(len(self.layers)):
+            sur_adam(self.w[k], self.mw[k], self.vw[k], self.gw[k], lr, b1, b2, eps, self.adam_t)
+            sur_adam(self.b[k], self.mb[k], self.vb[k], self.gb[k], lr, b1, b2, eps, self.adam_t)
+        self.pack()
+
+    def train_step(self, x_bf16, target_f32, wch, lr=1e-3):
+        self.forward(x_bf16)
+        loss = self.loss_and_grad(target_f32, wch)
+        self.backward(self.dout)
+        self.adam_step(lr)
+        return loss
+
+    # ------------------------------------------------------------ host I/O
+    def get_params(self):
+        return [(w.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64))
+                for w, b in zip(self.w, self.b)]
+
+    def set_params(self, params):
+        torch = self.torch
+        for k, (w, b) in enumerate(params):
+            self.w[k].copy_(torch.as_tensor(np.asarray(w, dtype=np.float32)))
+            self.b[k].copy_(torch.as_tensor(np.asarray(b, dtype=np.float32)))
+        self.pack()
+
+    def state_dict(self):
+        return {"channels": list(self.channels),
+                "w": [w.cpu() for w in self.w], "b": [b.cpu() for b in self.b]}
+
+
+def bf16_bits_from_f32(t):
+    """Round an FP32 torch tensor to BF16 (ties to even) on the GPU and return
+    the bit pattern as int16 (the format the kernels read)."""
+    import torch
+    out = torch.empty(t.shape, dtype=torch.int16, device=t.device)
+    sur_to_bf16(t.contiguous(), out)
+    return out

@@ -1,0 +1,226 @@
+"""The surrogate's HIP kernels (through the sur_* C ABI) against the NumPy
+oracle on identical BF16-rounded inputs: convolution forward, data and weight
+gradients, pooling/upsampling/concat, loss, Adam, and the whole U-Net
+forward and backward."""
+import numpy as np
+import pytest
+
+from oracle import surrogate_oracle as so
+
+from gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sur():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2407_12263_amd import surrogate
+    surrogate.load_library()
+    return surrogate
+
+
+def _bits(a):
+    """float array -> BF16 bit pattern (int16 torch tensor on the GPU)."""
+    import torch
+    r = so.bf16_round(np.asarray(a, dtype=np.float32))
+    return torch.as_tensor(r.view(np.uint32).__rshift__(16).astype(np.uint16).view(np.int16)).cuda()
+
+
+def _from_bits(t):
+    u = t.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32)
+
+
+def _f32(a):
+    import torch
+    return torch.as_tensor(np.asarray(a, dtype=np.float32)).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(1e-30, np.linalg.norm(np.ravel(b))))
+
+
+GRID = (10, 6, 8)  # nx, ny, nz -> P = 480 (not a multiple of 256)
+
+
+@pytest.mark.parametrize("cin,cout,relu", [(16, 16, 1), (32, 48, 0), (112, 48, 1), (80, 32, 1),
+                                           (48, 64, 0)])
+def test_conv_forward(sur, cin, cout, relu):
+    import torch
+    say(f"[sur] conv fwd cin={cin} cout={cout} relu={relu} grid={GRID}")
+    rng = np.random.default_rng(cin + cout)
+    nx, ny, nz = GRID
+    x = so.bf16_round(rng.standard_normal((nz, ny, nx, cin)).astype(np.float32))
+    w = rng.standard_normal((27, cout, cin)).astype(np.float32) * 0.1
+    b = rng.standard_normal(cout).astype(np.float32)
+    wf = torch.empty((27, cout, cin), dtype=torch.int16, device="cuda")
+    sur.sur_pack_weights(_f32(w), cin, cout, wf, None)
+    yf = torch.empty((nx * ny * nz, cout), dtype=torch.float32, device="cuda")
+    yb = torch.empty((nx * ny * nz, cout), dtype=torch.int16, device="cuda")
+    sur.sur_conv3d(_bits(x.reshape(-1, cin)), cin, wf, _f32(b), cout, GRID, relu=relu,
+                   y_bf16=yb, y_f32=yf)
+    ref = so.conv3d(x.astype(np.float64), so.bf16_round(w).astype(np.float64), b.astype(np.float64))
+    if relu:
+        ref = so.relu(ref)
+    got = yf.cpu().numpy().reshape(ref.shape)
+    assert np.abs(got - ref).max() <= 1e-5 * (1 + np.abs(ref).max())
+    gb = _from_bits(yb).reshape(ref.shape)
+    assert np.array_equal(gb, so.bf16_round(got.astype(np.float32)))
+
+
+@pytest.mark.parametrize("cin,cout", [(16, 32), (112, 48), (48, 16)])
+def test_conv_data_gradient_with_mask(sur, cin, cout):
+    import torch
+    say(f"[sur] conv dgrad cin={cin} cout={cout}")
+    rng = np.random.default_rng(7 + cin)
+    nx, ny, nz = GRID
+    dy = so.bf16_round(rng.standard_normal((nz, ny, nx, cout)).astype(np.float32))
+    w = rng.standard_normal((27, cout, cin)).astype(np.float32) * 0.1
+    act = so.bf16_round(np.maximum(rng.standard_normal((nz, ny, nx, cin)), 0).astype(np.float32))
+    wd = torch.empty((27, cin, cout), dtype=torch.int16, device="cuda")
+    sur.sur_pack_weights(_f32(w), cin, cout, None, wd)
+    dx = torch.empty((nx * ny * nz, cin), dtype=torch.float32, device="cuda")
+    sur.sur_conv3d(_bits(dy.reshape(-1, cout)), cout, wd, None, cin, GRID, flip=1,
+                   mask=_bits(act.reshape(-1, cin)), y_f32=dx)
+    ref = so.conv3d_dgrad(dy.astype(np.float64), so.bf16_round(w).astype(np.float64)) * (act > 0)
+    got = dx.cpu().numpy().reshape(ref.shape)
+    assert np.abs(got - ref).max() <= 1e-5 * (1 + np.abs(ref).max())
+
+
+@pytest.mark.parametrize("cin,cout,grid", [(16, 16, (16, 8, 12)), (112, 48, (8, 8, 8)),
+                                           (48, 64, (10, 6, 8)), (80, 32, (4, 4, 4))])
+def test_conv_weight_gradient(sur, cin, cout, grid):
+    import torch
+    say(f"[sur] conv wgrad cin={cin} cout={cout} grid={grid}")
+    rng = np.random.default_rng(11 + cout)
+    nx, ny, nz = grid
+    P = nx * ny * nz
+    x = so.bf16_round(rng.standard_normal((nz, ny, nx, cin)).astype(np.float32))
+    dy = so.bf16_round(rng.standard_normal((nz, ny, nx, cout)).astype(np.float32))
+    scratch = torch.empty(sur.sur_wgrad_scratch_floats(cin, cout, grid), dtype=torch.float32,
+                          device="cuda")
+    dw = torch.empty((27, cout, cin), dtype=torch.float32, device="cuda")
+    db = torch.empty(cout, dtype=torch.float32, device="cuda")
+    sur.sur_conv3d_wgrad(_bits(x.reshape(-1, cin)), cin, _bits(dy.reshape(-1, cout)), cout, grid,
+                         scratch, dw, db)
+    rdw, rdb = so.conv3d_wgrad(x.astype(np.float64), dy.astype(np.float64))
+    assert np.abs(dw.cpu().numpy() - rdw).max() <= 1e-5 * (1 + np.abs(rdw).max()) * np.sqrt(P)
+    assert np.abs(db.cpu().numpy() - rdb).max() <= 1e-5 * (1 + np.abs(rdb).max()) * np.sqrt(P)
+
+
+def test_grid_layers(sur):
+    import torch
+    say("[sur] pool / upsample / concat / masks")
+    rng = np.random.default_rng(3)
+    nx, ny, nz, c = 8, 4, 6, 16
+    P = nx * ny * nz
+    x = so.bf16_round(rng.standard_normal((nz, ny, nx, c)).astype(np.float32))
+    y = torch.empty((P // 8, c), dtype=torch.int16, device="cuda")
+    sur.sur_pool2(_bits(x.reshape(-1, c)), c, (nx, ny, nz), y)
+    assert np.abs(_from_bits(y).reshape(nz // 2, ny // 2, nx // 2, c)
+                  - so.bf16_round(so.pool2(x).astype(np.float32))).max() == 0.0
+    xc = so.bf16_round(rng.standard_normal((nz // 2, ny // 2, nx // 2, c)).astype(np.float32))
+    cat = torch.zeros((P, 48), dtype=torch.int16, device="cuda")
+    sur.sur_upsample2(_bits(xc.reshape(-1, c)), c, (nx // 2, ny // 2, nz // 2), cat, 48, 0)
+    sur.sur_copy_channels(_bits(x.reshape(-1, c)), c, P, cat, 48, 16)
+    got = _from_bits(cat).reshape(nz, ny, nx, 48)
+    assert np.array_equal(got[..., :16], so.up2(xc))
+    assert np.array_equal(got[..., 16:32], x)
+    dy = rng.standard_normal((P, 48)).astype(np.float32)
+    du = torch.empty((P // 8, c), dtype=torch.float32, device="cuda")
+    sur.sur_upsample2_bwd(_f32(dy), 48, 16, c, (nx // 2, ny // 2, nz // 2), du)
+    ref = so.up2_bwd(dy.reshape(nz, ny, nx, 48)[..., 16:32].astype(np.float64))
+    assert np.abs(du.cpu().numpy().reshape(ref.shape) - ref).max() < 1e-5
+    dx = torch.zeros((P, c), dtype=torch.float32, device="cuda")
+    sur.sur_pool2_bwd(_f32(dy[:P // 8, :c]), c, (nx, ny, nz), dx)
+    ref = so.pool2_bwd(dy[:P // 8, :c].reshape(nz // 2, ny // 2, nx // 2, c).astype(np.float64))
+    assert np.abs(dx.cpu().numpy().reshape(ref.shape) - ref).max() < 1e-6
+    g = _f32(dy[:, :c])
+    sur.sur_relu_mask(g, _bits(x.reshape(-1, c)))
+    assert np.array_equal(g.cpu().numpy(), dy[:, :c] * (x.reshape(-1, c) > 0))
+
+
+def test_loss_and_adam(sur):
+    import torch
+    say("[sur] mse and adam")
+    rng = np.random.default_rng(9)
+    P = 700
+    pred = rng.standard_normal((P, 16)).astype(np.float32)
+    tgt = rng.standard_normal((P, 16)).astype(np.float32)
+    wch = np.array([4.0, 1.0, 1.0, 1.0, 0.5], dtype=np.float32)
+    grad = torch.empty((P, 16), dtype=torch.float32, device="cuda")
+    scratch = torch.empty(P // 256 + 2, dtype=torch.float64, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sur.sur_mse(_f32(pred), _f32(tgt), 5, 16, P, _f32(wch), grad, scratch, loss)
+    rl, rg = so.mse(pred.reshape(P, 1, 1, 16).astype(np.float64),
+                    tgt.reshape(P, 1, 1, 16).astype(np.float64), wch.astype(np.float64))
+    assert abs(float(loss.item()) - rl) < 1e-6 * rl
+    assert np.abs(grad.cpu().numpy() - rg.reshape(P, 16)).max() < 1e-7
+    w0 = rng.standard_normal(1000).astype(np.float32)
+    g = rng.standard_normal(1000).astype(np.float32)
+    w, m, v = _f32(w0), torch.zeros(1000, device="cuda"), torch.zeros(1000, device="cuda")
+    ref = (w0.astype(np.float64), np.zeros(1000), np.zeros(1000))
+    for t in range(1, 4):
+        sur.sur_adam(w, m, v, _f32(g * t), 1e-2, 0.9, 0.999, 1e-8, t)
+        ref = so.adam(ref[0], ref[1], ref[2], (g * t).astype(np.float64), t, lr=1e-2)
+    assert np.abs(w.cpu().numpy() - ref[0]).max() < 1e-6
+
+
+def test_unet_forward_backward_matches_oracle(sur):
+    """4-level U-Net (16-32-48-64) on a 16^3 coarse grid: output and every
+    layer's weight gradient agree with the oracle run on the same BF16
+    rounding of inputs, weights and stored activations."""
+    import torch
+    say("[sur] unet 16^3 forward/backward")
+    rng = np.random.default_rng(21)
+    grid = (16, 16, 16)
+    net = sur.UNet(grid, channels=(16, 32, 48, 64), seed=3)
+    params = net.get_params()
+    qparams = [(so.bf16_round(w.astype(np.float32)).astype(np.float64), b) for w, b in params]
+    x = np.zeros((16, 16, 16, 16), dtype=np.float32)
+    x[..., :5] = rng.standard_normal((16, 16, 16, 5))
+    x = so.bf16_round(x)
+    tgt = np.zeros_like(x)
+    tgt[..., :5] = 0.1 * rng.standard_normal((16, 16, 16, 5))
+    wch = np.array([1.0, 1.0, 1.0, 1.0, 1.0], dtype=np.float32)
+    out = net.forward(_bits(x.reshape(-1, 16)))
+    loss = net.loss_and_grad(_f32(tgt.reshape(-1, 16)), _f32(wch))
+    net.backward(net.dout)
+    torch.cuda.synchronize()
+    q = lambda a: so.bf16_round(a.astype(np.float32)).astype(np.float64)
+    rout, cache = so.unet_forward(x.astype(np.float64), qparams, (16, 32, 48, 64), quant=q)
+    rl, rdout = so.mse(rout, tgt.astype(np.float64), wch.astype(np.float64))
+    rgrads = so.unet_backward(rdout, qparams, (16, 32, 48, 64), cache)
+    e_out = _rel(out.cpu().numpy(), rout.reshape(-1, 16))
+    say(f"   output rel err {e_out:.2e}, loss {float(loss.item()):.6e} vs {rl:.6e}")
+    assert e_out < 1e-2
+    assert abs(float(loss.item()) - rl) < 2e-2 * rl
+    worst = 0.0
+    for k, (gw, gb) in enumerate(rgrads):
+        ew = _rel(net.gw[k].cpu().numpy(), gw)
+        worst = max(worst, ew)
+    say(f"   worst layer weight-gradient rel err {worst:.2e}")
+    assert worst < 3e-2
+
+
+def test_training_reduces_loss(sur):
+    """A few Adam steps on one fixed (input, target) pair lower the loss."""
+    import torch
+    say("[sur] training smoke 16^3")
+    rng = np.random.default_rng(5)
+    grid = (16, 16, 16)
+    net = sur.UNet(grid, channels=(16, 32, 48, 64), seed=4)
+    x = np.zeros((16 ** 3, 16), dtype=np.float32)
+    x[:, :5] = rng.standard_normal((16 ** 3, 5))
+    tgt = np.zeros_like(x)
+    tgt[:, :5] = 0.5 * np.tanh(x[:, :5])
+    xb, tg, wch = _bits(x), _f32(tgt), _f32(np.ones(5))
+    l0 = float(net.train_step(xb, tg, wch, lr=3e-3).item())
+    for _ in range(60):
+        l = net.train_step(xb, tg, wch, lr=3e-3)
+    l1 = float(l.item())
+    say(f"   loss {l0:.4e} -> {l1:.4e}")
+    assert l1 < 0.2 * l0
