@@ -148,6 +148,12 @@ int lbm_get_pdfs(lbm_ctx *ctx, double *d_f, double *d_g);
  * (device FP64, 19N each), rounded to the storage precision. */
 int lbm_set_pdfs(lbm_ctx *ctx, const double *d_f, const double *d_g);
 
+/* Rebuilds the state in place from fields (device FP64, as lbm_init) and
+ * sets the time to t; the phase-mass bookkeeping then targets sum(d_phi).
+ * Used to hand a state back to the solver (restart from fields, or after a
+ * window advanced by another model). Synchronises the stream. */
+int lbm_reset(lbm_ctx *ctx, const double *d_phi, const double *d_u, const double *d_p, int64_t t);
+
 /* Current time t (number of steps since lbm_init). */
 int64_t lbm_time(const lbm_ctx *ctx);
 

@@ -108,13 +108,29 @@ int sur_coarsen(const float *phi, const float *u, const float *p, int32_t nx, in
 int sur_prolong_add(const float *delta, int32_t cnx, int32_t cny, int32_t cnz,
                     const float *scale, double *phi, double *u, double *p, void *stream);
 
-/* Per-window checks on a coarse FP32 state [P][16] (unscaled: channel c is
- * the physical field / scale[c] as coarsen wrote it): FP64 sums written to
- * out[6] = {sum phi, min phi, max phi, sum (div u)^2, sum |u|^2, P}
- * (div by central differences on the coarse grid, in coarse-grid units, of
- * the scaled velocity). scratch >= 6 * (P/256 + 1) doubles. */
+/* Per-window checks on a coarse FP32 state [P][16] (channel c is the
+ * physical field / scale[c] as coarsen wrote it): FP64 results written to
+ * out[7] = {sum phi, min phi, max phi, sum (div u)^2, sum |u|^2, P,
+ * sum max(phi (1 - phi), 0)} (div by central differences on the coarse grid,
+ * in coarse-grid units, of the scaled velocity). scratch >= 7 * (P/256 + 1)
+ * doubles. */
 int sur_checks(const float *state, int32_t nx, int32_t ny, int32_t nz, double *scratch,
                double *out, void *stream);
+
+/* state[p][c] += rscale[c] * out[p][c] for c < cu (the network's residual,
+ * in residual units, applied to the scaled state). */
+int sur_apply_residual(float *state, const float *out, const float *rscale, int32_t cu,
+                       int64_t P, void *stream);
+
+/* target[p][c] = (s1[p][c] - s0[p][c]) / rscale[c] for c < cu, 0 beyond. */
+int sur_residual_target(const float *s0, const float *s1, const float *rscale, int32_t cu,
+                        int64_t P, float *target, void *stream);
+
+/* Puts the phase mass back to *target_mass: phi += c phi (1 - phi) with
+ * c = (target - sum phi) / sum phi (1 - phi) from a sur_checks result (all on
+ * the device: no host round trip). */
+int sur_fix_mass(float *state, int64_t P, const double *checks_out, const double *target_mass,
+                 void *stream);
 
 #ifdef __cplusplus
 }

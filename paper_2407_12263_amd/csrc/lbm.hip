@@ -340,6 +340,26 @@ int reduce_diag(lbm_ctx *c, const double *phi_ref) {
     return check_launch(c);
 }
 
+// State at the current time from fields (device FP64): post-propagation
+// PDFs into buffer 1, M0 = sum phi (FP64) for the phase-mass bookkeeping, one
+// collision into buffer 0; checks the inputs (synchronises the stream).
+int build_state(lbm_ctx *c, const double *d_phi, const double *d_u, const double *d_p) {
+    hipLaunchKernelGGL(clear_int_kernel, dim3(1), dim3(1), 0, c->stream, c->flag);
+    init_any(c, d_phi, d_u, d_p, 1);
+    hipLaunchKernelGGL(massfix_kernel, dim3(1), dim3(RBLOCK), 0, c->stream,
+                       (const double *)c->partials, c->nblocks, c->mf, c->mf + 1, 1);
+    step_any(c, LOCAL, 1, 0);
+    c->cur = 0;
+    c->prev_local = true;
+    c->mf_pending = false;
+    int bad = 0;
+    if (check_launch(c) != LBM_OK ||
+        hipMemcpyAsync(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return LBM_EDEVICE;
+    return bad ? LBM_EINVAL : LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -391,29 +411,25 @@ int lbm_init(const lbm_params *P, void *d_workspace, size_t bytes, void *stream,
     c->mf_pending = false;
     c->status = LBM_OK;
 
-    hipLaunchKernelGGL(clear_int_kernel, dim3(1), dim3(1), 0, c->stream, c->flag);
-    // post-propagation PDFs at t = 0 into buffer 1, collide into buffer 0
-    init_any(c, d_phi0, d_u0, d_p0, 1);
-    // M0 = sum phi0 (FP64), the target of the phase-mass bookkeeping
-    hipLaunchKernelGGL(massfix_kernel, dim3(1), dim3(RBLOCK), 0, c->stream,
-                       (const double *)c->partials, c->nblocks, c->mf, c->mf + 1, 1);
-    step_any(c, LOCAL, 1, 0);
-    c->cur = 0;
-    c->prev_local = true;
     c->t = 0;
-    int bad = 0;
-    if (check_launch(c) != LBM_OK ||
-        hipMemcpyAsync(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess) {
+    const int rc2 = build_state(c, d_phi0, d_u0, d_p0);
+    if (rc2 != LBM_OK) {
         delete c;
-        return LBM_EDEVICE;
-    }
-    if (bad) {
-        delete c;
-        return LBM_EINVAL;
+        return rc2;
     }
     *out = c;
     return LBM_OK;
+}
+
+int lbm_reset(lbm_ctx *c, const double *d_phi, const double *d_u, const double *d_p, int64_t t) {
+    if (!c || !d_phi || t < 0) return LBM_EINVAL;
+    if (c->status == LBM_EDEVICE) return LBM_ESTATE;
+    const int rc = build_state(c, d_phi, d_u, d_p);
+    if (rc == LBM_OK) {
+        c->t = t;
+        c->status = LBM_OK;
+    }
+    return rc;
 }
 
 int lbm_step(lbm_ctx *c, int64_t n) {

@@ -449,12 +449,14 @@ __global__ void prolong_add_kernel(const float *__restrict__ d, int cx, int cy, 
     p[f] += (double)(scale[4] * acc[4]);
 }
 
+constexpr int NCHK = 7;
+
 __global__ void __launch_bounds__(256) checks_kernel(const float *__restrict__ s, int nx, int ny,
                                                      int nz, double *__restrict__ part) {
-    __shared__ double red[6][4];
+    __shared__ double red[NCHK][4];
     const long P = (long)nx * ny * nz;
     const long qq = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    double v[6] = {0.0, 1e300, -1e300, 0.0, 0.0, 0.0};
+    double v[NCHK] = {0.0, 1e300, -1e300, 0.0, 0.0, 0.0, 0.0};
     if (qq < P) {
         const int X = (int)(qq % nx), Y = (int)((qq / nx) % ny), Z = (int)(qq / ((long)nx * ny));
         auto at = [&](int x, int y, int z) {
@@ -471,42 +473,74 @@ __global__ void __launch_bounds__(256) checks_kernel(const float *__restrict__ s
         v[3] = div * div;
         v[4] = ux * ux + uy * uy + uz * uz;
         v[5] = 1.0;
+        v[6] = fmax(phi * (1.0 - phi), 0.0);
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < NCHK; ++k) {
         const double r = k == 1 ? wmin(v[k]) : (k == 2 ? wmax(v[k]) : wsum(v[k]));
         if (lane == 0) red[k][wv] = r;
     }
     __syncthreads();
-    if (threadIdx.x < 6) {
+    if (threadIdx.x < NCHK) {
         const int k = threadIdx.x;
         double r = red[k][0];
         for (int w = 1; w < 4; ++w) r = k == 1 ? fmin(r, red[k][w]) : (k == 2 ? fmax(r, red[k][w]) : r + red[k][w]);
-        part[(long)blockIdx.x * 6 + k] = r;
+        part[(long)blockIdx.x * NCHK + k] = r;
     }
 }
 
 __global__ void __launch_bounds__(1024) checks_final_kernel(const double *__restrict__ part, long nb,
                                                             double *__restrict__ out) {
-    __shared__ double red[6][16];
-    double v[6] = {0.0, 1e300, -1e300, 0.0, 0.0, 0.0};
+    __shared__ double red[NCHK][16];
+    double v[NCHK] = {0.0, 1e300, -1e300, 0.0, 0.0, 0.0, 0.0};
     for (long b = threadIdx.x; b < nb; b += 1024)
-        for (int k = 0; k < 6; ++k) {
-            const double x = part[b * 6 + k];
+        for (int k = 0; k < NCHK; ++k) {
+            const double x = part[b * NCHK + k];
             v[k] = k == 1 ? fmin(v[k], x) : (k == 2 ? fmax(v[k], x) : v[k] + x);
         }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < NCHK; ++k) {
         const double r = k == 1 ? wmin(v[k]) : (k == 2 ? wmax(v[k]) : wsum(v[k]));
         if (lane == 0) red[k][wv] = r;
     }
     __syncthreads();
-    if (threadIdx.x < 6) {
+    if (threadIdx.x < NCHK) {
         const int k = threadIdx.x;
         double r = red[k][0];
         for (int w = 1; w < 16; ++w) r = k == 1 ? fmin(r, red[k][w]) : (k == 2 ? fmax(r, red[k][w]) : r + red[k][w]);
         out[k] = r;
     }
+}
+
+// s[p][c] += rscale[c] * out[p][c] for the used channels c < cu.
+__global__ void apply_residual_kernel(float *__restrict__ s, const float *__restrict__ out,
+                                      const float *__restrict__ rscale, int cu, long P) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * cu) return;
+    const long p = e / cu;
+    const int c = (int)(e % cu);
+    s[p * 16 + c] += rscale[c] * out[p * 16 + c];
+}
+
+// t[p][c] = (s1[p][c] - s0[p][c]) / rscale[c] for c < cu, 0 otherwise.
+__global__ void residual_target_kernel(const float *__restrict__ s0, const float *__restrict__ s1,
+                                       const float *__restrict__ rscale, int cu, long P,
+                                       float *__restrict__ t) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * 16) return;
+    const int c = (int)(e % 16);
+    t[e] = c < cu ? (s1[e] - s0[e]) / rscale[c] : 0.f;
+}
+
+// s[p][0] += c w(phi), c = (target - sum phi)/sum w from a checks result.
+__global__ void fix_mass_kernel(float *__restrict__ s, long P, const double *__restrict__ chk,
+                                const double *__restrict__ target) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const double sw = chk[6];
+    const double c = sw > 0.0 ? (*target - chk[0]) / sw : 0.0;
+    const float phi = s[p * 16];
+    s[p * 16] = phi + (float)(c * fmax((double)phi * (1.0 - (double)phi), 0.0));
 }
 
 // ------------------------------------------------------------ host helpers
@@ -687,6 +721,30 @@ int sur_prolong_add(const float *delta, int32_t cnx, int32_t cny, int32_t cnz, c
     const long N = 8L * cnx * cny * cnz;
     hipLaunchKernelGGL(prolong_add_kernel, grid1(N), dim3(256), 0, (hipStream_t)stream, delta, cnx,
                        cny, cnz, scale, phi, u, p);
+    return launched();
+}
+
+int sur_apply_residual(float *state, const float *out, const float *rscale, int32_t cu, int64_t P,
+                       void *stream) {
+    if (!state || !out || !rscale || cu <= 0 || cu > 16 || P <= 0) return SUR_EINVAL;
+    hipLaunchKernelGGL(apply_residual_kernel, grid1(P * cu), dim3(256), 0, (hipStream_t)stream,
+                       state, out, rscale, cu, (long)P);
+    return launched();
+}
+
+int sur_residual_target(const float *s0, const float *s1, const float *rscale, int32_t cu, int64_t P,
+                        float *target, void *stream) {
+    if (!s0 || !s1 || !rscale || !target || cu <= 0 || cu > 16 || P <= 0) return SUR_EINVAL;
+    hipLaunchKernelGGL(residual_target_kernel, grid1(P * 16), dim3(256), 0, (hipStream_t)stream,
+                       s0, s1, rscale, cu, (long)P, target);
+    return launched();
+}
+
+int sur_fix_mass(float *state, int64_t P, const double *checks_out, const double *target_mass,
+                 void *stream) {
+    if (!state || !checks_out || !target_mass || P <= 0) return SUR_EINVAL;
+    hipLaunchKernelGGL(fix_mass_kernel, grid1(P), dim3(256), 0, (hipStream_t)stream, state, (long)P,
+                       checks_out, target_mass);
     return launched();
 }
 

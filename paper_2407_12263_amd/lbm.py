@@ -79,6 +79,7 @@ def load_library(path: str | None = None):
     lib.lbm_diagnostics.argtypes = [vp, vp, C.POINTER(LbmDiag)]
     lib.lbm_get_pdfs.argtypes = [vp, vp, vp]
     lib.lbm_set_pdfs.argtypes = [vp, vp, vp]
+    lib.lbm_reset.argtypes = [vp, vp, vp, vp, C.c_int64]
     lib.lbm_time.argtypes = [vp]
     lib.lbm_time.restype = C.c_int64
     lib.lbm_destroy.argtypes = [vp]
@@ -183,6 +184,11 @@ def lbm_set_pdfs(ctx, f, g):
            "lbm_set_pdfs")
 
 
+def lbm_reset(ctx, phi, u=None, p=None, t: int = 0):
+    ptr = lambda x: None if x is None else C.c_void_p(x.data_ptr())
+    _check(load_library().lbm_reset(ctx, ptr(phi), ptr(u), ptr(p), C.c_int64(int(t))), "lbm_reset")
+
+
 def lbm_time(ctx) -> int:
     return int(load_library().lbm_time(ctx))
 
@@ -267,6 +273,14 @@ class Solver:
         fd, gd = cv(f), cv(g)
         lbm_set_pdfs(self.ctx, fd, gd)
         self.stream.synchronize()
+
+    def reset(self, phi, u=None, p=None, t=None):
+        """Rebuild the state from device FP64 fields (torch tensors)."""
+        torch = self.torch
+        cv = lambda a, shp: None if a is None else torch.as_tensor(a, dtype=torch.float64).to(
+            self.device).reshape(shp).contiguous()
+        lbm_reset(self.ctx, cv(phi, self.shape), cv(u, (3,) + self.shape), cv(p, self.shape),
+                  self.t if t is None else t)
 
     def synchronize(self):
         self.stream.synchronize()

@@ -56,7 +56,10 @@ def load_library(path: str | None = None):
     lib.sur_coarsen.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, vp]
     lib.sur_prolong_add.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.sur_checks.argtypes = [vp, i32, i32, i32, vp, vp, vp]
-    for n in ["sur_conv3d", "sur_conv3d_wgrad", "sur_pack_weights", "sur_pool2", "sur_pool2_bwd",
+    lib.sur_apply_residual.argtypes = [vp, vp, vp, i32, i64, vp]
+    lib.sur_residual_target.argtypes = [vp, vp, vp, i32, i64, vp, vp]
+    lib.sur_fix_mass.argtypes = [vp, i64, vp, vp, vp]
+    for n in ["sur_apply_residual", "sur_residual_target", "sur_fix_mass", "sur_conv3d", "sur_conv3d_wgrad", "sur_pack_weights", "sur_pool2", "sur_pool2_bwd",
               "sur_upsample2", "sur_upsample2_bwd", "sur_copy_channels", "sur_add_channels",
               "sur_to_bf16", "sur_relu_mask", "sur_mse", "sur_adam", "sur_coarsen",
               "sur_prolong_add", "sur_checks"]:
@@ -162,6 +165,21 @@ def sur_prolong_add(delta, cgrid, scale, phi, u, p):
 
 def sur_checks(state, grid, scratch, out):
     _ok(load_library().sur_checks(_p(state), *grid, _p(scratch), _p(out), _stream()), "sur_checks")
+
+
+def sur_apply_residual(state, out, rscale, cu, P):
+    _ok(load_library().sur_apply_residual(_p(state), _p(out), _p(rscale), cu, P, _stream()),
+        "sur_apply_residual")
+
+
+def sur_residual_target(s0, s1, rscale, cu, P, target):
+    _ok(load_library().sur_residual_target(_p(s0), _p(s1), _p(rscale), cu, P, _p(target),
+                                           _stream()), "sur_residual_target")
+
+
+def sur_fix_mass(state, P, checks_out, target_mass):
+    _ok(load_library().sur_fix_mass(_p(state), P, _p(checks_out), _p(target_mass), _stream()),
+        "sur_fix_mass")
 
 
 # ---------------------------------------------------------------- the U-Net
