@@ -1,0 +1,358 @@
+"""Surrogate-accelerated CPF-LBM runs: training data from the solver, GPU
+training of the coarse-grid U-Net, and windowed runs with checks, fallback
+and periodic re-synchronisation by the plain solver.
+
+Every numerical step is a kernel of ``liblbm.so`` or ``libsur.so``; this
+module allocates buffers (PyTorch), sequences the calls and makes the
+per-window decisions on the host.
+
+Coarse state: FP32 [Pc][16] on the 2x-coarsened grid, channels
+(phi, ux, uy, uz, p) divided by ``scale`` (1, U, U, U, rho U^2 with U the
+velocity scale of the workload), the other 11 channels zero. The network
+predicts the K-step change of the state in units of ``rscale`` (the
+per-channel spread of that change in the training data).
+
+A run is split into windows of K solver steps and cycles of ``cycle``
+windows. In a cycle the network advances the coarse state by up to
+``nsur`` windows; each predicted window is checked (phase mass drift, phi
+range, RMS velocity divergence) and, if it passes, its phase mass is put
+back exactly. The accumulated coarse change is prolonged onto the fine
+fields of the cycle start and the solver is rebuilt from them
+(``lbm_reset``); the solver then runs the rest of the cycle. At the first
+of those solver windows the network's prediction of the same window is
+compared with the solver's result: if its error exceeds ``judge_tol`` (in
+units of the window's own change) the next cycle runs on the solver only.
+A window whose checks fail is discarded and the solver runs from the last
+accepted state.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import lbm, surrogate as sur
+
+K_STEPS = 16
+
+
+def state_scale(u_scale: float, rho: float = 1.0) -> np.ndarray:
+    s = np.ones(sur.NCH, dtype=np.float32)
+    s[1:4] = u_scale
+    s[4] = rho * u_scale * u_scale
+    return s
+
+
+class Coupler:
+    """Grid transfer between one Solver (even fine sizes) and the coarse
+    network state."""
+
+    def __init__(self, solver: lbm.Solver, scale):
+        import torch
+        self.torch = torch
+        self.solver = solver
+        nz, ny, nx = solver.shape
+        if nx % 2 or ny % 2 or nz % 2:
+            raise ValueError("fine grid sizes must be even")
+        self.fine = (nx, ny, nz)
+        self.coarse = (nx // 2, ny // 2, nz // 2)
+        self.P = (nx // 2) * (ny // 2) * (nz // 2)
+        dev = solver.device
+        f32 = lambda shp: torch.empty(shp, dtype=torch.float32, device=dev)
+        f64 = lambda shp: torch.empty(shp, dtype=torch.float64, device=dev)
+        self.phi32, self.u32, self.p32 = f32(solver.shape), f32((3,) + solver.shape), f32(solver.shape)
+        self.phi64, self.u64, self.p64 = f64(solver.shape), f64((3,) + solver.shape), f64(solver.shape)
+        self.scale = torch.as_tensor(np.asarray(scale, dtype=np.float32)).to(dev)
+        self.chk_scratch = torch.empty(7 * (self.P // 256 + 1), dtype=torch.float64, device=dev)
+
+    def new_state(self):
+        return self.torch.zeros((self.P, sur.NCH), dtype=self.torch.float32,
+                                device=self.solver.device)
+
+    def snapshot(self, out):
+        """out <- coarsened, scaled (phi, u, p) of the solver's current state."""
+        lbm.lbm_fields(self.solver.ctx, self.phi32, self.u32, self.p32, 1)
+        sur.sur_coarsen(self.phi32, self.u32, self.p32, self.fine, self.scale, out)
+
+    def save_base(self):
+        """Keeps the solver's FP64 fields: the base the coarse change is added to."""
+        lbm.lbm_fields(self.solver.ctx, self.phi64, self.u64, self.p64, 0)
+
+    def push(self, delta, t: int):
+        """fine = base + prolong(delta); the solver is rebuilt from it at time t."""
+        sur.sur_prolong_add(delta, self.coarse, self.scale, self.phi64, self.u64, self.p64)
+        lbm.lbm_reset(self.solver.ctx, self.phi64, self.u64, self.p64, t)
+
+    def checks(self, state, out):
+        sur.sur_checks(state, self.coarse, self.chk_scratch, out)
+
+
+@dataclass
+class CheckLimits:
+    mass_tol: float = 2e-3        # |sum phi - sum phi_0| / sum phi_0 before the fix
+    phi_lo: float = -0.05
+    phi_hi: float = 1.05
+    div_rms: float = math.inf     # RMS divergence of the scaled coarse velocity
+
+    def passed(self, chk, mass0: float) -> bool:
+        P = chk[5]
+        return (abs(chk[0] - mass0) <= self.mass_tol * abs(mass0) and chk[1] >= self.phi_lo
+                and chk[2] <= self.phi_hi and math.sqrt(max(chk[3], 0.0) / P) <= self.div_rms
+                and all(math.isfinite(v) for v in chk))
+
+
+class SnapshotStore:
+    """Ring buffer of coarse states in HBM with their (trajectory, window)
+    labels; a training pair is two consecutive windows of one trajectory."""
+
+    def __init__(self, capacity: int, P: int, device):
+        import torch
+        self.data = torch.zeros((capacity, P, sur.NCH), dtype=torch.float32, device=device)
+        self.label = [None] * capacity
+        self.cap = capacity
+        self.next = 0
+        self.added = 0
+
+    def slot(self, traj: int, win: int):
+        k = self.next
+        self.label[k] = (traj, win)
+        self.next = (k + 1) % self.cap
+        self.added += 1
+        return self.data[k]
+
+    def pairs(self):
+        where = {lab: k for k, lab in enumerate(self.label) if lab is not None}
+        out = []
+        for (tr, w), k in where.items():
+            j = where.get((tr, w - 1))
+            if j is not None:
+                out.append((j, k))
+        return out
+
+
+@dataclass
+class TrainLog:
+    steps: int = 0
+    snapshots: int = 0
+    seconds_lbm: float = 0.0
+    seconds_train: float = 0.0
+    losses: list = field(default_factory=list)
+
+
+class Trainer:
+    """Online training of a U-Net on solver trajectories (all on the GPU)."""
+
+    def __init__(self, net: sur.UNet, coupler: Coupler, store: SnapshotStore, rscale,
+                 wch=None, lr: float = 1e-3, lr_final: float = 1e-4, total_steps: int = 1000,
+                 seed: int = 0):
+        import torch
+        self.torch = torch
+        self.net, self.cp, self.store = net, coupler, store
+        dev = coupler.solver.device
+        self.rscale = torch.as_tensor(np.asarray(rscale, dtype=np.float32)).to(dev)
+        self.wch = torch.as_tensor(np.ones(sur.NUSE, dtype=np.float32) if wch is None
+                                   else np.asarray(wch, dtype=np.float32)).to(dev)
+        self.xb = torch.empty((coupler.P, sur.NCH), dtype=torch.int16, device=dev)
+        self.tgt = coupler.new_state()
+        self.lr0, self.lr1, self.total = lr, lr_final, max(1, total_steps)
+        self.rng = np.random.default_rng(seed)
+        self.log = TrainLog()
+
+    def lr(self):
+        f = min(1.0, self.log.steps / self.total)
+        return self.lr1 + 0.5 * (self.lr0 - self.lr1) * (1.0 + math.cos(math.pi * f))
+
+    def step_on(self, a, b):
+        sur.sur_to_bf16(a, self.xb)
+        sur.sur_residual_target(a, b, self.rscale, sur.NUSE, self.cp.P, self.tgt)
+        loss = self.net.train_step(self.xb, self.tgt, self.wch, lr=self.lr())
+        self.log.steps += 1
+        return loss
+
+    def train(self, n: int, record_every: int = 0):
+        pairs = self.store.pairs()
+        if not pairs:
+            return
+        t0 = time.perf_counter()
+        for i in range(n):
+            a, b = pairs[int(self.rng.integers(len(pairs)))]
+            loss = self.step_on(self.store.data[a], self.store.data[b])
+            if record_every and self.log.steps % record_every == 0:
+                self.log.losses.append((self.log.steps, float(loss.item())))
+        self.torch.cuda.synchronize()
+        self.log.seconds_train += time.perf_counter() - t0
+
+
+def residual_scale(cp: Coupler, store: SnapshotStore, floor: float = 1e-6) -> np.ndarray:
+    """Per-channel RMS of the K-step change over the stored pairs (FP64
+    reductions of the residual-loss kernel with one-hot channel weights)."""
+    torch = cp.torch
+    dev = cp.solver.device
+    grad = cp.new_state()
+    scr = torch.empty(cp.P // 256 + 2, dtype=torch.float64, device=dev)
+    out = torch.empty(sur.NUSE, dtype=torch.float64, device=dev)
+    acc = np.zeros(sur.NUSE)
+    pairs = store.pairs()
+    for a, b in pairs:
+        for c in range(sur.NUSE):
+            wch = torch.zeros(sur.NUSE, dtype=torch.float32, device=dev)
+            wch[c] = float(sur.NUSE)
+            sur.sur_mse(store.data[b], store.data[a], sur.NUSE, sur.NCH, cp.P, wch, grad, scr,
+                        out[c:c + 1])
+        acc += out.cpu().numpy()
+    r = np.ones(sur.NCH, dtype=np.float32)
+    r[:sur.NUSE] = np.maximum(np.sqrt(acc / max(1, len(pairs))), floor)
+    return r
+
+
+def generate(cp: Coupler, store: SnapshotStore, workloads, windows: int, trainer=None,
+             train_per_window: int = 0, on_snapshot=None):
+    """Runs the solver from each workload's initial fields for ``windows``
+    windows, storing the coarse state after every window (and the initial
+    one); optionally trains between windows."""
+    torch = cp.torch
+    solver = cp.solver
+    chk = torch.empty(7, dtype=torch.float64, device=solver.device)
+    log = trainer.log if trainer is not None else TrainLog()
+    for tr, wl in enumerate(workloads):
+        w = wl() if callable(wl) else wl
+        solver.reset(torch.as_tensor(w.phi0), torch.as_tensor(w.u0), torch.as_tensor(w.p0), 0)
+        cp.snapshot(store.slot(tr, 0))
+        for k in range(1, windows + 1):
+            t0 = time.perf_counter()
+            solver.step(K_STEPS)
+            s = store.slot(tr, k)
+            cp.snapshot(s)
+            if on_snapshot is not None:
+                cp.checks(s, chk)
+                on_snapshot(chk.cpu().numpy())
+            torch.cuda.synchronize()
+            log.seconds_lbm += time.perf_counter() - t0
+            log.snapshots += 1
+            if trainer is not None and train_per_window:
+                trainer.train(train_per_window)
+    return log
+
+
+@dataclass
+class RunStats:
+    windows: int = 0
+    sur_windows: int = 0
+    lbm_windows: int = 0
+    fallbacks: int = 0
+    judged: int = 0
+    judge_fail: int = 0
+    judge_err: list = field(default_factory=list)
+    seconds: float = 0.0
+
+
+def accelerated_run(cp: Coupler, net: sur.UNet, rscale, windows: int, nsur: int = 7,
+                    cycle: int = 8, limits: CheckLimits | None = None,
+                    judge_tol: float = 0.5, predictor=None) -> RunStats:
+    """Advances cp.solver by windows * K steps with the surrogate schedule
+    described in the module docstring. ``predictor`` (default: the network)
+    maps a coarse state to its predicted change in rscale units (FP32
+    [Pc][16]); it exists so that the same schedule can be run with a
+    reference predictor."""
+    torch = cp.torch
+    solver = cp.solver
+    limits = limits or CheckLimits()
+    dev = solver.device
+    P = cp.P
+    rs = torch.as_tensor(np.asarray(rscale, dtype=np.float32)).to(dev)
+    ones = torch.ones(sur.NCH, dtype=torch.float32, device=dev)
+    one = torch.ones(1, dtype=torch.float32, device=dev)
+    xb = torch.empty((P, sur.NCH), dtype=torch.int16, device=dev)
+    s0, s, sprev, spred, slbm, delta = (cp.new_state() for _ in range(6))
+    chk0 = torch.empty(7, dtype=torch.float64, device=dev)
+    chk = torch.empty(7, dtype=torch.float64, device=dev)
+    mse_scr = torch.empty(P // 256 + 2, dtype=torch.float64, device=dev)
+    mse_out = torch.empty(2, dtype=torch.float64, device=dev)
+
+    def predict(state):
+        if predictor is not None:
+            return predictor(state)
+        sur.sur_to_bf16(state, xb)
+        return net.forward(xb)
+
+    st = RunStats()
+    probation = False
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    w = 0
+    while w < windows:
+        cyc = min(cycle, windows - w)
+        nsur_c = 0 if probation else min(nsur, cyc - 1)
+        probation = False
+        if nsur_c <= 0:
+            solver.step(K_STEPS * cyc)
+            st.lbm_windows += cyc
+            w += cyc
+            continue
+        cp.snapshot(s0)
+        cp.save_base()
+        cp.checks(s0, chk0)
+        mass0 = float(chk0[0].item())
+        s.copy_(s0)
+        done = 0
+        for _ in range(nsur_c):
+            sprev.copy_(s)
+            out = predict(s)
+            sur.sur_apply_residual(s, out, rs, sur.NUSE, P)
+            cp.checks(s, chk)
+            if not limits.passed(chk.cpu().numpy(), mass0):
+                s.copy_(sprev)
+                st.fallbacks += 1
+                break
+            sur.sur_fix_mass(s, P, chk, chk0[0:1])
+            done += 1
+        t_cycle = solver.t
+        if done:
+            sur.sur_residual_target(s0, s, ones, sur.NUSE, P, delta)
+            try:
+                cp.push(delta, t_cycle + done * K_STEPS)
+            except lbm.LbmError:
+                # the solver rejected the prolonged fields (phi out of its
+                # admissible range): take the change back and rerun the cycle
+                sur.sur_residual_target(s, s0, ones, sur.NUSE, P, delta)
+                cp.push(delta, t_cycle)
+                st.fallbacks += 1
+                done = 0
+                s.copy_(s0)
+        st.sur_windows += done
+        remaining = cyc - done
+        if done == nsur_c and remaining >= 1 and judge_tol is not None:
+            # the solver's first window of the cycle is the judge of the network
+            spred.copy_(s)
+            out = predict(s)
+            sur.sur_apply_residual(spred, out, rs, sur.NUSE, P)
+            solver.step(K_STEPS)
+            cp.snapshot(slbm)
+            sur.sur_mse(spred, slbm, 1, sur.NCH, P, one, delta, mse_scr, mse_out[0:1])
+            sur.sur_mse(s, slbm, 1, sur.NCH, P, one, delta, mse_scr, mse_out[1:2])
+            num, den = mse_out.cpu().numpy()
+            e = math.sqrt(num / den) if den > 0 else (0.0 if num == 0 else math.inf)
+            st.judged += 1
+            st.judge_err.append(e)
+            if not e <= judge_tol:
+                st.judge_fail += 1
+                probation = True
+            remaining -= 1
+            st.lbm_windows += 1
+        if remaining:
+            solver.step(K_STEPS * remaining)
+            st.lbm_windows += remaining
+        w += cyc
+    torch.cuda.synchronize()
+    st.seconds = time.perf_counter() - t_start
+    st.windows = windows
+    return st
+
+
+def phi_error(solver: lbm.Solver, phi_ref) -> float:
+    """Relative L2 error of the solver's phi against phi_ref (FP64 sums on
+    the device)."""
+    d = solver.diagnostics(phi_ref)
+    return math.sqrt(d["l2_num"] / d["l2_den"]) if d["l2_den"] > 0 else math.inf

@@ -223,22 +223,31 @@ def taylor_green_breakup(n: int = 256, R: float | None = None, u0: float = 0.04,
 
 def random_solenoidal(shape, kmax: float = 4.0, rms: float = 0.02, seed: int = 0):
     """Random divergence-free velocity from integer wavevectors 1 <= |k| <= kmax:
-    complex Gaussian amplitudes projected perpendicular to k, Hermitian by
-    construction (real part of the inverse FFT), rescaled to the given rms."""
+    complex Gaussian amplitudes (drawn for those modes only) projected
+    perpendicular to k; the field is the real part of the inverse FFT (the
+    Hermitian part of the spectrum), rescaled to the given rms."""
     nz, ny, nx = shape
     rng = np.random.default_rng(seed)
-    kz = np.fft.fftfreq(nz, 1.0 / nz)[:, None, None]
-    ky = np.fft.fftfreq(ny, 1.0 / ny)[None, :, None]
-    kx = np.fft.fftfreq(nx, 1.0 / nx)[None, None, :]
+    K = int(math.floor(kmax))
+    ks = np.arange(-K, K + 1)
+    kz, ky, kx = [a.ravel() for a in np.meshgrid(ks, ks, ks, indexing="ij")]
     k2 = kx * kx + ky * ky + kz * kz
-    mask = (k2 >= 1.0) & (k2 <= kmax * kmax)
-    amp = (rng.standard_normal((3,) + shape) + 1j * rng.standard_normal((3,) + shape)) * mask
-    kv = [np.broadcast_to(kx, shape), np.broadcast_to(ky, shape), np.broadcast_to(kz, shape)]
-    kdot = sum(kv[a] * amp[a] for a in range(3))
-    k2s = np.where(k2 > 0, k2, 1.0)
+    keep = (k2 >= 1) & (k2 <= kmax * kmax)
+    kv = np.stack([kx[keep], ky[keep], kz[keep]]).astype(float)
+    m = kv.shape[1]
+    amp = rng.standard_normal((3, m)) + 1j * rng.standard_normal((3, m))
+    amp -= kv * (kv * amp).sum(0) / (kv * kv).sum(0)
+    # inverse DFT restricted to the few nonzero wavenumbers per axis, one axis
+    # at a time: u(x) = (1/N) sum_k amp(k) exp(2 pi i k.x / n)
+    E = [np.exp(2j * np.pi * np.outer(ks, np.arange(L)) / L) for L in (nx, ny, nz)]
+    u = np.empty((3,) + shape)
     for a in range(3):
-        amp[a] = amp[a] - kv[a] * kdot / k2s
-    u = np.stack([np.fft.ifftn(amp[a]).real for a in range(3)])
+        B = np.zeros((2 * K + 1,) * 3, dtype=complex)
+        np.add.at(B, (kv[2].astype(int) + K, kv[1].astype(int) + K, kv[0].astype(int) + K), amp[a])
+        T = np.einsum("abk,kx->abx", B, E[0])                 # (kz, ky, x)
+        T = np.einsum("ky,akx->ayx", E[1], T)                 # (kz, y, x)
+        T = T.reshape(2 * K + 1, ny * nx)
+        u[a] = ((E[2].real.T @ T.real) - (E[2].imag.T @ T.imag)).reshape(shape) / (nx * ny * nz)
     cur = math.sqrt(float(np.mean(np.sum(u * u, axis=0))))
     if cur > 0:
         u *= rms / cur
@@ -251,7 +260,10 @@ def emulsion(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rmax: float = 
              max_tries: int = 200000) -> Workload:
     """Emulsion: n_drops non-overlapping droplets (radii uniform in
     [rmin, rmax], minimum-image gap >= r_a + r_b + 2W, rejection sampling)
-    in a periodic cube plus a random solenoidal velocity (rms ``rms``)."""
+    in a periodic cube plus a random solenoidal velocity (rms ``rms``).
+    phi is the maximum of the droplets' tanh profiles; each profile is
+    evaluated in a periodic box reaching 7W beyond its radius, where it has
+    fallen below 1e-12."""
     shape = (n, n, n)
     rng = np.random.default_rng(seed)
     centres, radii = [], []
@@ -260,20 +272,45 @@ def emulsion(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rmax: float = 
         tries += 1
         r = rng.uniform(rmin, rmax)
         c = rng.uniform(0.0, n, size=3)
-        ok = True
-        for c2, r2 in zip(centres, radii):
-            d = c - c2
+        if centres:
+            d = np.asarray(centres) - c
             d -= n * np.round(d / n)
-            if math.sqrt(float(d @ d)) < r + r2 + 2.0 * W:
-                ok = False
-                break
-        if ok:
-            centres.append(c)
-            radii.append(r)
-    phi0 = np.zeros(shape)
-    for c, r in zip(centres, radii):
-        dist = sphere_distance(shape, tuple(c))
-        np.maximum(phi0, tanh_drop(dist, r, W), out=phi0)
+            if (np.sqrt((d * d).sum(1)) < r + np.asarray(radii) + 2.0 * W).any():
+                continue
+        centres.append(c)
+        radii.append(r)
+    # profiles are written into a padded copy with plain slices, then the
+    # padding is folded back periodically (max over the periodic images)
+    H = int(math.ceil(rmax + 7.0 * W)) + 1
+    if 2 * H >= n:
+        phi0 = np.zeros(shape)
+        for c, r in zip(centres, radii):
+            np.maximum(phi0, tanh_drop(sphere_distance(shape, tuple(c)), r, W), out=phi0)
+    else:
+        P = np.zeros((n + 2 * H,) * 3)
+        for c, r in zip(centres, radii):
+            h = int(math.ceil(r + 7.0 * W))
+            lo = [int(math.floor(c[a])) - h for a in range(3)]
+            ax = [np.arange(lo[a], lo[a] + 2 * h + 2) - c[a] for a in range(3)]
+            d = np.sqrt(ax[0][None, None, :] ** 2 + ax[1][None, :, None] ** 2
+                        + ax[2][:, None, None] ** 2)
+            sl = tuple(slice(lo[a] + H, lo[a] + H + 2 * h + 2) for a in (2, 1, 0))
+            np.maximum(P[sl], tanh_drop(d, r, W), out=P[sl])
+        for axis in range(3):
+            core = [slice(None)] * 3
+            left = [slice(None)] * 3
+            right = [slice(None)] * 3
+            core[axis] = slice(H, H + n)
+            left[axis] = slice(0, H)
+            right[axis] = slice(H + n, n + 2 * H)
+            c_lo = list(core)
+            c_lo[axis] = slice(H + n - H, H + n)
+            c_hi = list(core)
+            c_hi[axis] = slice(H, 2 * H)
+            np.maximum(P[tuple(c_lo)], P[tuple(left)], out=P[tuple(c_lo)])
+            np.maximum(P[tuple(c_hi)], P[tuple(right)], out=P[tuple(c_hi)])
+            P = P[tuple(core)]
+        phi0 = np.ascontiguousarray(P)
     u0 = random_solenoidal(shape, rms=rms, seed=seed + 7919)
     return Workload(name=f"emulsion_{n}_seed{seed}", nx=n, ny=n, nz=n, courant=courant,
                     rho1=1.0, rho2=1.0, tau_rho1=tau_rho, tau_rho2=tau_rho,

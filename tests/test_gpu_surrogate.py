@@ -206,21 +206,50 @@ def test_unet_forward_backward_matches_oracle(sur):
     assert worst < 3e-2
 
 
-def test_training_reduces_loss(sur):
-    """A few Adam steps on one fixed (input, target) pair lower the loss."""
-    import torch
-    say("[sur] training smoke 16^3")
+def test_training_trajectory_matches_oracle(sur):
+    """60 Adam steps of the 4-level U-Net on an 8^3 grid (smooth input, target
+    half the one-cell shift of the input): the GPU loss curve follows the
+    oracle's (same initial weights, BF16 rounding of weights and activations
+    emulated in the oracle's forward pass) and falls by more than 20x."""
+    from scipy.ndimage import gaussian_filter
+    say("[sur] training trajectory 8^3 vs oracle")
+    ch = (16, 32, 48, 64)
+    n = 8
     rng = np.random.default_rng(5)
-    grid = (16, 16, 16)
-    net = sur.UNet(grid, channels=(16, 32, 48, 64), seed=4)
-    x = np.zeros((16 ** 3, 16), dtype=np.float32)
-    x[:, :5] = rng.standard_normal((16 ** 3, 5))
+    x = np.zeros((n, n, n, 16))
+    for c in range(5):
+        x[..., c] = 3.0 * gaussian_filter(rng.standard_normal((n, n, n)), 1.0, mode="wrap")
+    x = so.bf16_round(x.astype(np.float32)).astype(np.float64)
     tgt = np.zeros_like(x)
-    tgt[:, :5] = 0.5 * np.tanh(x[:, :5])
-    xb, tg, wch = _bits(x), _f32(tgt), _f32(np.ones(5))
-    l0 = float(net.train_step(xb, tg, wch, lr=3e-3).item())
-    for _ in range(60):
-        l = net.train_step(xb, tg, wch, lr=3e-3)
-    l1 = float(l.item())
-    say(f"   loss {l0:.4e} -> {l1:.4e}")
-    assert l1 < 0.2 * l0
+    tgt[..., :5] = 0.5 * (np.roll(x[..., :5], 1, axis=2) - x[..., :5])
+    net = sur.UNet((n, n, n), channels=ch, seed=4)
+    params = net.get_params()
+    xb, tg, wch = _bits(x.reshape(-1, 16)), _f32(tgt.reshape(-1, 16)), _f32(np.ones(5))
+    lr, steps = 1e-3, 60
+    q = lambda a: so.bf16_round(a.astype(np.float32)).astype(np.float64)
+    st = [(np.zeros_like(w), np.zeros_like(w), np.zeros_like(b), np.zeros_like(b)) for w, b in params]
+    gpu, ref = [], []
+    for t in range(1, steps + 1):
+        gpu.append(float(net.train_step(xb, tg, wch, lr=lr).item()))
+        qp = [(q(w), b) for w, b in params]
+        out, cache = so.unet_forward(x, qp, ch, quant=q)
+        loss, dout = so.mse(out, tgt, np.ones(5))
+        grads = so.unet_backward(dout, qp, ch, cache)
+        ref.append(loss)
+        new_p, new_s = [], []
+        for (w, b), (gw, gb), (mw, vw, mb, vb) in zip(params, grads, st):
+            w, mw, vw = so.adam(w, mw, vw, gw, t, lr=lr)
+            b, mb, vb = so.adam(b, mb, vb, gb, t, lr=lr)
+            new_p.append((w, b))
+            new_s.append((mw, vw, mb, vb))
+        params, st = new_p, new_s
+    gpu, ref = np.array(gpu), np.array(ref)
+    say("   step   gpu loss    oracle loss")
+    for t in (0, 9, 19, 39, 59):
+        say(f"   {t + 1:4d}  {gpu[t]:.5e}  {ref[t]:.5e}")
+    # same weights at step 1: the losses agree to BF16 forward rounding
+    assert abs(gpu[0] - ref[0]) < 1e-4 * ref[0]
+    # later steps: the GPU's BF16 gradients (not emulated in the oracle)
+    # slow the descent a little; the curves stay within a factor 1.6
+    assert np.all(np.abs(np.log(gpu / ref)) < np.log(1.6))
+    assert ref[-1] < 0.05 * ref[0] and gpu[-1] < 0.05 * gpu[0]
