@@ -108,6 +108,30 @@ int sur_coarsen(const float *phi, const float *u, const float *p, int32_t nx, in
 int sur_prolong_add(const float *delta, int32_t cnx, int32_t cny, int32_t cnz,
                     const float *scale, double *phi, double *u, double *p, void *stream);
 
+/* Level-set prolongation of a coarse change s0 -> s1 (FP32 [Pc][16], scaled
+ * as coarsen writes them) onto fine FP64 fields (sizes 2 cnx, 2 cny, 2 cnz):
+ *   u, p    += scale[c] * trilinear(s1 - s0)[c];
+ *   phi     += Phi(Psi(phi) + dpsi) - Phi(Psi(phi)), dpsi = trilinear of
+ *              Psi(s1[0]) - Psi(s0[0]) over the coarse nodes, with
+ *              Psi(f) = (width/4) ln(f/(1-f)) (f clamped to [1e-4, 1-1e-4])
+ *              and Phi(psi) = (1 + tanh(2 psi / width))/2 the equilibrium
+ *              interface profile: the interface moves, its fine profile is
+ *              kept;
+ *   then phi += c max(phi(1-phi), 0) with c restoring the sum of phi before
+ *   the update (FP64, fixed order).
+ * sums (device, 4 doubles) receives {sum phi, sum w} before and after the
+ * update, before the mass fix. scratch >= sur_prolong_update_scratch_doubles. */
+size_t sur_prolong_update_scratch_doubles(int32_t cnx, int32_t cny, int32_t cnz);
+int sur_prolong_update(const float *s0, const float *s1, int32_t cnx, int32_t cny, int32_t cnz,
+                       const float *scale, double width, double *phi, double *u, double *p,
+                       double *scratch, double *sums, void *stream);
+
+/* Network input features from channels 0..4 of a coarse state [P][16]
+ * (periodic central differences in coarse-grid units): channels 5..7 grad
+ * phi, 8 u . grad phi, 9 div u, 10 phi (1 - phi), 11 |grad phi| (in place;
+ * channels 12..15 untouched). */
+int sur_features(float *state, int32_t nx, int32_t ny, int32_t nz, void *stream);
+
 /* Per-window checks on a coarse FP32 state [P][16] (channel c is the
  * physical field / scale[c] as coarsen wrote it): FP64 results written to
  * out[7] = {sum phi, min phi, max phi, sum (div u)^2, sum |u|^2, P,

@@ -64,25 +64,48 @@ class Coupler:
         f64 = lambda shp: torch.empty(shp, dtype=torch.float64, device=dev)
         self.phi32, self.u32, self.p32 = f32(solver.shape), f32((3,) + solver.shape), f32(solver.shape)
         self.phi64, self.u64, self.p64 = f64(solver.shape), f64((3,) + solver.shape), f64(solver.shape)
+        self.backup = (f64(solver.shape), f64((3,) + solver.shape), f64(solver.shape))
         self.scale = torch.as_tensor(np.asarray(scale, dtype=np.float32)).to(dev)
         self.chk_scratch = torch.empty(7 * (self.P // 256 + 1), dtype=torch.float64, device=dev)
+        self.pu_scratch = torch.empty(sur.sur_prolong_update_scratch_doubles(self.coarse),
+                                      dtype=torch.float64, device=dev)
+        self.pu_sums = torch.empty(4, dtype=torch.float64, device=dev)
+        self.ones = torch.ones(sur.NCH, dtype=torch.float32, device=dev)
+        self.width = float(solver.params.delta)
 
     def new_state(self):
         return self.torch.zeros((self.P, sur.NCH), dtype=self.torch.float32,
                                 device=self.solver.device)
 
     def snapshot(self, out):
-        """out <- coarsened, scaled (phi, u, p) of the solver's current state."""
+        """out <- coarsened, scaled (phi, u, p) of the solver's current state,
+        with the network's input features."""
         lbm.lbm_fields(self.solver.ctx, self.phi32, self.u32, self.p32, 1)
         sur.sur_coarsen(self.phi32, self.u32, self.p32, self.fine, self.scale, out)
+        sur.sur_features(out, self.coarse)
 
     def save_base(self):
-        """Keeps the solver's FP64 fields: the base the coarse change is added to."""
+        """Keeps the solver's FP64 fields: the base the coarse change is
+        added to (and a copy to go back to if the solver rejects the result)."""
         lbm.lbm_fields(self.solver.ctx, self.phi64, self.u64, self.p64, 0)
+        for a, b in zip(self.backup, (self.phi64, self.u64, self.p64)):
+            a.copy_(b)
 
-    def push(self, delta, t: int):
-        """fine = base + prolong(delta); the solver is rebuilt from it at time t."""
-        sur.sur_prolong_add(delta, self.coarse, self.scale, self.phi64, self.u64, self.p64)
+    def save_base_restore(self):
+        for a, b in zip(self.backup, (self.phi64, self.u64, self.p64)):
+            b.copy_(a)
+
+    def push(self, s0, s1, t: int, linear: bool = False):
+        """fine = base moved by the coarse change s0 -> s1 (level-set move of
+        phi with its phase mass restored, or the plain trilinear change if
+        ``linear``); the solver is rebuilt from it at time t."""
+        if linear:
+            d = self.new_state()
+            sur.sur_residual_target(s0, s1, self.ones, sur.NUSE, self.P, d)
+            sur.sur_prolong_add(d, self.coarse, self.scale, self.phi64, self.u64, self.p64)
+        else:
+            sur.sur_prolong_update(s0, s1, self.coarse, self.scale, self.width, self.phi64,
+                                   self.u64, self.p64, self.pu_scratch, self.pu_sums)
         lbm.lbm_reset(self.solver.ctx, self.phi64, self.u64, self.p64, t)
 
     def checks(self, state, out):
@@ -141,19 +164,27 @@ class TrainLog:
     losses: list = field(default_factory=list)
 
 
+DEFAULT_WCH = (4.0, 1.0, 1.0, 1.0, 0.25)
+
+
 class Trainer:
-    """Online training of a U-Net on solver trajectories (all on the GPU)."""
+    """Online training of a U-Net on solver trajectories (all on the GPU).
+
+    Loss weights per channel default to DEFAULT_WCH: phi, which the run's
+    error is measured on, counts most; the pressure change over a window is
+    dominated by acoustic waves the network cannot predict and counts
+    least."""
 
     def __init__(self, net: sur.UNet, coupler: Coupler, store: SnapshotStore, rscale,
-                 wch=None, lr: float = 1e-3, lr_final: float = 1e-4, total_steps: int = 1000,
-                 seed: int = 0):
+                 wch=DEFAULT_WCH, lr: float = 1e-3, lr_final: float = 1e-4,
+                 total_steps: int = 1000, seed: int = 0, record_every: int = 50):
         import torch
         self.torch = torch
         self.net, self.cp, self.store = net, coupler, store
         dev = coupler.solver.device
         self.rscale = torch.as_tensor(np.asarray(rscale, dtype=np.float32)).to(dev)
-        self.wch = torch.as_tensor(np.ones(sur.NUSE, dtype=np.float32) if wch is None
-                                   else np.asarray(wch, dtype=np.float32)).to(dev)
+        self.wch = torch.as_tensor(np.asarray(wch, dtype=np.float32)).to(dev)
+        self.record_every = record_every
         self.xb = torch.empty((coupler.P, sur.NCH), dtype=torch.int16, device=dev)
         self.tgt = coupler.new_state()
         self.lr0, self.lr1, self.total = lr, lr_final, max(1, total_steps)
@@ -171,7 +202,8 @@ class Trainer:
         self.log.steps += 1
         return loss
 
-    def train(self, n: int, record_every: int = 0):
+    def train(self, n: int):
+        record_every = self.record_every
         pairs = self.store.pairs()
         if not pairs:
             return
@@ -250,7 +282,7 @@ class RunStats:
 
 def accelerated_run(cp: Coupler, net: sur.UNet, rscale, windows: int, nsur: int = 7,
                     cycle: int = 8, limits: CheckLimits | None = None,
-                    judge_tol: float = 0.5, predictor=None) -> RunStats:
+                    judge_tol: float = 0.5, predictor=None, linear: bool = False) -> RunStats:
     """Advances cp.solver by windows * K steps with the surrogate schedule
     described in the module docstring. ``predictor`` (default: the network)
     maps a coarse state to its predicted change in rscale units (FP32
@@ -262,7 +294,6 @@ def accelerated_run(cp: Coupler, net: sur.UNet, rscale, windows: int, nsur: int 
     dev = solver.device
     P = cp.P
     rs = torch.as_tensor(np.asarray(rscale, dtype=np.float32)).to(dev)
-    ones = torch.ones(sur.NCH, dtype=torch.float32, device=dev)
     one = torch.ones(1, dtype=torch.float32, device=dev)
     xb = torch.empty((P, sur.NCH), dtype=torch.int16, device=dev)
     s0, s, sprev, spred, slbm, delta = (cp.new_state() for _ in range(6))
@@ -307,17 +338,17 @@ def accelerated_run(cp: Coupler, net: sur.UNet, rscale, windows: int, nsur: int 
                 st.fallbacks += 1
                 break
             sur.sur_fix_mass(s, P, chk, chk0[0:1])
+            sur.sur_features(s, cp.coarse)
             done += 1
         t_cycle = solver.t
         if done:
-            sur.sur_residual_target(s0, s, ones, sur.NUSE, P, delta)
             try:
-                cp.push(delta, t_cycle + done * K_STEPS)
+                cp.push(s0, s, t_cycle + done * K_STEPS, linear=linear)
             except lbm.LbmError:
-                # the solver rejected the prolonged fields (phi out of its
-                # admissible range): take the change back and rerun the cycle
-                sur.sur_residual_target(s, s0, ones, sur.NUSE, P, delta)
-                cp.push(delta, t_cycle)
+                # the solver rejected the moved fields (phi out of its
+                # admissible range): rebuild it at the cycle start instead
+                cp.save_base_restore()
+                lbm.lbm_reset(solver.ctx, cp.phi64, cp.u64, cp.p64, t_cycle)
                 st.fallbacks += 1
                 done = 0
                 s.copy_(s0)

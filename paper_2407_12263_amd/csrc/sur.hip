@@ -543,6 +543,136 @@ __global__ void fix_mass_kernel(float *__restrict__ s, long P, const double *__r
     s[p * 16] = phi + (float)(c * fmax((double)phi * (1.0 - (double)phi), 0.0));
 }
 
+// Input features of the network, written into channels 5..11 of the coarse
+// state from channels 0..4 of the node and its six neighbours (periodic):
+// central differences of phi (5, 6, 7), u . grad phi (8), div u (9),
+// phi (1 - phi) (10), |grad phi| (11). Channels 12..15 are left as they are.
+__global__ void features_kernel(float *__restrict__ s, int nx, int ny, int nz) {
+    const long P = (long)nx * ny * nz;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P) return;
+    const int x = (int)(q % nx), y = (int)((q / nx) % ny), z = (int)(q / ((long)nx * ny));
+    auto at = [&](int X, int Y, int Z) {
+        return (wrap(X, nx) + (long)nx * (wrap(Y, ny) + (long)ny * wrap(Z, nz))) * 16;
+    };
+    const long xp = at(x + 1, y, z), xm = at(x - 1, y, z), yp = at(x, y + 1, z), ym = at(x, y - 1, z),
+               zp = at(x, y, z + 1), zm = at(x, y, z - 1);
+    const float gx = 0.5f * (s[xp] - s[xm]), gy = 0.5f * (s[yp] - s[ym]), gz = 0.5f * (s[zp] - s[zm]);
+    const float div = 0.5f * (s[xp + 1] - s[xm + 1] + s[yp + 2] - s[ym + 2] + s[zp + 3] - s[zm + 3]);
+    float *o = s + q * 16;
+    const float phi = o[0];
+    o[5] = gx;
+    o[6] = gy;
+    o[7] = gz;
+    o[8] = o[1] * gx + o[2] * gy + o[3] * gz;
+    o[9] = div;
+    o[10] = phi * (1.f - phi);
+    o[11] = sqrtf(gx * gx + gy * gy + gz * gz);
+}
+
+// Signed distance of the equilibrium profile phi = (1 + tanh(2 psi / W)) / 2,
+// psi = (W / 4) ln(phi / (1 - phi)), with phi clamped to [LS_EPS, 1 - LS_EPS].
+constexpr double LS_EPS = 1e-4;
+__device__ __forceinline__ float ls_psi_f(float f, float W) {
+    f = fminf(fmaxf(f, (float)LS_EPS), 1.f - (float)LS_EPS);
+    return 0.25f * W * logf(f / (1.f - f));
+}
+__device__ __forceinline__ double ls_psi(double f, double W) {
+    f = fmin(fmax(f, LS_EPS), 1.0 - LS_EPS);
+    return 0.25 * W * log(f / (1.0 - f));
+}
+__device__ __forceinline__ double ls_phi(double s, double W) { return 0.5 * (1.0 + tanh(2.0 * s / W)); }
+
+// Fine update from two coarse states s0 -> s1: u and p get the trilinear
+// prolongation of the change; phi moves its level set: the coarse change of
+// psi is prolonged and phi <- phi + Phi(Psi(phi) + dpsi) - Phi(Psi(phi))
+// (no change where dpsi = 0).
+__global__ void prolong_update_kernel(const float *__restrict__ s0, const float *__restrict__ s1,
+                                      int cx, int cy, int cz, const float *__restrict__ scale,
+                                      float width, double *__restrict__ phi,
+                                      double *__restrict__ u, double *__restrict__ p) {
+    const int nx = 2 * cx, ny = 2 * cy, nz = 2 * cz;
+    const long N = (long)nx * ny * nz;
+    const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= N) return;
+    const int X = (int)(f % nx), Y = (int)((f / nx) % ny), Z = (int)(f / ((long)nx * ny));
+    auto lo = [](int X) { return (X - 1) >> 1; };
+    const int x0 = lo(X), y0 = lo(Y), z0 = lo(Z);
+    const float wx = (X & 1) ? 0.25f : 0.75f, wy = (Y & 1) ? 0.25f : 0.75f, wz = (Z & 1) ? 0.25f : 0.75f;
+    float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < 8; ++k) {
+        const int ix = wrap(x0 + (k & 1), cx), iy = wrap(y0 + ((k >> 1) & 1), cy), iz = wrap(z0 + (k >> 2), cz);
+        const float w = ((k & 1) ? wx : 1.f - wx) * (((k >> 1) & 1) ? wy : 1.f - wy) * ((k >> 2) ? wz : 1.f - wz);
+        const long qq = (ix + (long)cx * (iy + (long)cy * iz)) * 16;
+        acc[0] += w * (ls_psi_f(scale[0] * s1[qq], width) - ls_psi_f(scale[0] * s0[qq], width));
+        for (int ch = 1; ch < 5; ++ch) acc[ch] += w * (s1[qq + ch] - s0[qq + ch]);
+    }
+    const double f0 = phi[f];
+    const double so = ls_psi(f0, width);
+    phi[f] = f0 + (ls_phi(so + (double)acc[0], width) - ls_phi(so, width));
+    u[f] += (double)(scale[1] * acc[1]);
+    u[N + f] += (double)(scale[2] * acc[2]);
+    u[2 * N + f] += (double)(scale[3] * acc[3]);
+    p[f] += (double)(scale[4] * acc[4]);
+}
+
+// Per-block FP64 sums {sum phi, sum max(phi (1 - phi), 0)} of a fine field.
+__global__ void __launch_bounds__(256) field_sums_kernel(const double *__restrict__ phi, long N,
+                                                         double *__restrict__ part) {
+    __shared__ double red[2][4];
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double a = 0.0, b = 0.0;
+    if (i < N) {
+        a = phi[i];
+        b = fmax(a * (1.0 - a), 0.0);
+    }
+    a = wsum(a);
+    b = wsum(b);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wv] = a;
+        red[1][wv] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const int k = threadIdx.x;
+        part[(long)blockIdx.x * 2 + k] = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+    }
+}
+
+__global__ void __launch_bounds__(1024) sums2_final_kernel(const double *__restrict__ part, long nb,
+                                                           double *__restrict__ out) {
+    __shared__ double red[2][16];
+    double a = 0.0, b = 0.0;
+    for (long k = threadIdx.x; k < nb; k += 1024) {
+        a += part[2 * k];
+        b += part[2 * k + 1];
+    }
+    a = wsum(a);
+    b = wsum(b);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wv] = a;
+        red[1][wv] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double r = 0.0;
+        for (int w = 0; w < 16; ++w) r += red[threadIdx.x][w];
+        out[threadIdx.x] = r;
+    }
+}
+
+// phi += c max(phi (1 - phi), 0), c = (*target - sums[0]) / sums[1].
+__global__ void fix_mass_field_kernel(double *__restrict__ phi, long N, const double *__restrict__ sums,
+                                      const double *__restrict__ target) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double c = sums[1] > 0.0 ? (*target - sums[0]) / sums[1] : 0.0;
+    const double f = phi[i];
+    phi[i] = f + c * fmax(f * (1.0 - f), 0.0);
+}
+
 // ------------------------------------------------------------ host helpers
 int launched() { return hipGetLastError() == hipSuccess ? SUR_OK : SUR_EDEVICE; }
 
@@ -745,6 +875,38 @@ int sur_fix_mass(float *state, int64_t P, const double *checks_out, const double
     if (!state || !checks_out || !target_mass || P <= 0) return SUR_EINVAL;
     hipLaunchKernelGGL(fix_mass_kernel, grid1(P), dim3(256), 0, (hipStream_t)stream, state, (long)P,
                        checks_out, target_mass);
+    return launched();
+}
+
+int sur_features(float *state, int32_t nx, int32_t ny, int32_t nz, void *stream) {
+    if (!state || !dims_ok(nx, ny, nz)) return SUR_EINVAL;
+    const long P = (long)nx * ny * nz;
+    hipLaunchKernelGGL(features_kernel, grid1(P), dim3(256), 0, (hipStream_t)stream, state, nx, ny, nz);
+    return launched();
+}
+
+size_t sur_prolong_update_scratch_doubles(int32_t cnx, int32_t cny, int32_t cnz) {
+    const long N = 8L * cnx * cny * cnz;
+    return (size_t)(2 * grid1(N).x);
+}
+
+int sur_prolong_update(const float *s0, const float *s1, int32_t cnx, int32_t cny, int32_t cnz,
+                       const float *scale, double width, double *phi, double *u, double *p,
+                       double *scratch, double *sums, void *stream) {
+    if (!s0 || !s1 || !scale || !phi || !u || !p || !scratch || !sums ||
+        !dims_ok(2 * cnx, 2 * cny, 2 * cnz) || !(width > 0.0))
+        return SUR_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const long N = 8L * cnx * cny * cnz;
+    const long nb = grid1(N).x;
+    hipLaunchKernelGGL(field_sums_kernel, dim3((unsigned)nb), dim3(256), 0, st, (const double *)phi, N, scratch);
+    hipLaunchKernelGGL(sums2_final_kernel, dim3(1), dim3(1024), 0, st, (const double *)scratch, nb, sums);
+    hipLaunchKernelGGL(prolong_update_kernel, dim3((unsigned)nb), dim3(256), 0, st, s0, s1, cnx, cny, cnz,
+                       scale, (float)width, phi, u, p);
+    hipLaunchKernelGGL(field_sums_kernel, dim3((unsigned)nb), dim3(256), 0, st, (const double *)phi, N, scratch);
+    hipLaunchKernelGGL(sums2_final_kernel, dim3(1), dim3(1024), 0, st, (const double *)scratch, nb, sums + 2);
+    hipLaunchKernelGGL(fix_mass_field_kernel, dim3((unsigned)nb), dim3(256), 0, st, phi, N,
+                       (const double *)(sums + 2), (const double *)sums);
     return launched();
 }
 

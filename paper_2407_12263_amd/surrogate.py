@@ -59,7 +59,11 @@ def load_library(path: str | None = None):
     lib.sur_apply_residual.argtypes = [vp, vp, vp, i32, i64, vp]
     lib.sur_residual_target.argtypes = [vp, vp, vp, i32, i64, vp, vp]
     lib.sur_fix_mass.argtypes = [vp, i64, vp, vp, vp]
-    for n in ["sur_apply_residual", "sur_residual_target", "sur_fix_mass", "sur_conv3d", "sur_conv3d_wgrad", "sur_pack_weights", "sur_pool2", "sur_pool2_bwd",
+    lib.sur_features.argtypes = [vp, i32, i32, i32, vp]
+    lib.sur_prolong_update_scratch_doubles.argtypes = [i32, i32, i32]
+    lib.sur_prolong_update_scratch_doubles.restype = sz
+    lib.sur_prolong_update.argtypes = [vp, vp, i32, i32, i32, vp, C.c_double, vp, vp, vp, vp, vp, vp]
+    for n in ["sur_features", "sur_prolong_update", "sur_apply_residual", "sur_residual_target", "sur_fix_mass", "sur_conv3d", "sur_conv3d_wgrad", "sur_pack_weights", "sur_pool2", "sur_pool2_bwd",
               "sur_upsample2", "sur_upsample2_bwd", "sur_copy_channels", "sur_add_channels",
               "sur_to_bf16", "sur_relu_mask", "sur_mse", "sur_adam", "sur_coarsen",
               "sur_prolong_add", "sur_checks"]:
@@ -180,6 +184,20 @@ def sur_residual_target(s0, s1, rscale, cu, P, target):
 def sur_fix_mass(state, P, checks_out, target_mass):
     _ok(load_library().sur_fix_mass(_p(state), P, _p(checks_out), _p(target_mass), _stream()),
         "sur_fix_mass")
+
+
+def sur_features(state, grid):
+    _ok(load_library().sur_features(_p(state), *grid, _stream()), "sur_features")
+
+
+def sur_prolong_update_scratch_doubles(cgrid):
+    return int(load_library().sur_prolong_update_scratch_doubles(*cgrid))
+
+
+def sur_prolong_update(s0, s1, cgrid, scale, width, phi, u, p, scratch, sums):
+    _ok(load_library().sur_prolong_update(_p(s0), _p(s1), *cgrid, _p(scale), float(width), _p(phi),
+                                          _p(u), _p(p), _p(scratch), _p(sums), _stream()),
+        "sur_prolong_update")
 
 
 # ---------------------------------------------------------------- the U-Net
