@@ -23,7 +23,9 @@ of those solver windows the network's prediction of the same window is
 compared with the solver's result: if its error exceeds ``judge_tol`` (in
 units of the window's own change) the next cycle runs on the solver only.
 A window whose checks fail is discarded and the solver runs from the last
-accepted state.
+accepted state. The first ``warmup_windows`` windows (the acoustic transient
+of an initial state given without its pressure field) always run on the
+solver.
 """
 from __future__ import annotations
 
@@ -119,11 +121,17 @@ class CheckLimits:
     phi_hi: float = 1.05
     div_rms: float = math.inf     # RMS divergence of the scaled coarse velocity
 
-    def passed(self, chk, mass0: float) -> bool:
-        P = chk[5]
-        return (abs(chk[0] - mass0) <= self.mass_tol * abs(mass0) and chk[1] >= self.phi_lo
-                and chk[2] <= self.phi_hi and math.sqrt(max(chk[3], 0.0) / P) <= self.div_rms
-                and all(math.isfinite(v) for v in chk))
+    def failed(self, chk, mass0: float) -> str:
+        """Name of the first failed check ('' if all pass)."""
+        if not all(math.isfinite(v) for v in chk):
+            return "nonfinite"
+        if abs(chk[0] - mass0) > self.mass_tol * abs(mass0):
+            return "mass"
+        if chk[1] < self.phi_lo or chk[2] > self.phi_hi:
+            return "range"
+        if math.sqrt(max(chk[3], 0.0) / chk[5]) > self.div_rms:
+            return "divergence"
+        return ""
 
 
 class SnapshotStore:
@@ -164,7 +172,7 @@ class TrainLog:
     losses: list = field(default_factory=list)
 
 
-DEFAULT_WCH = (4.0, 1.0, 1.0, 1.0, 0.25)
+DEFAULT_WCH = (4.0, 1.0, 1.0, 1.0, 0.1)
 
 
 class Trainer:
@@ -173,11 +181,16 @@ class Trainer:
     Loss weights per channel default to DEFAULT_WCH: phi, which the run's
     error is measured on, counts most; the pressure change over a window is
     dominated by acoustic waves the network cannot predict and counts
-    least."""
+    least. Pairs that start in the first ``skip_windows`` windows of a
+    trajectory (the acoustic transient of the initial state) are not used.
+    A step whose loss exceeds ``outlier`` times the running mean of the
+    accepted losses is not applied (Adam's second-moment estimate lags a
+    sudden large gradient, and such a step can wreck the weights)."""
 
     def __init__(self, net: sur.UNet, coupler: Coupler, store: SnapshotStore, rscale,
-                 wch=DEFAULT_WCH, lr: float = 1e-3, lr_final: float = 1e-4,
-                 total_steps: int = 1000, seed: int = 0, record_every: int = 50):
+                 wch=DEFAULT_WCH, lr: float = 3e-4, lr_final: float = 3e-5,
+                 total_steps: int = 1000, seed: int = 0, record_every: int = 50,
+                 skip_windows: int = 2, outlier: float = 5.0):
         import torch
         self.torch = torch
         self.net, self.cp, self.store = net, coupler, store
@@ -185,6 +198,10 @@ class Trainer:
         self.rscale = torch.as_tensor(np.asarray(rscale, dtype=np.float32)).to(dev)
         self.wch = torch.as_tensor(np.asarray(wch, dtype=np.float32)).to(dev)
         self.record_every = record_every
+        self.skip_windows = skip_windows
+        self.outlier = outlier
+        self.mean_loss = None
+        self.skipped = 0
         self.xb = torch.empty((coupler.P, sur.NCH), dtype=torch.int16, device=dev)
         self.tgt = coupler.new_state()
         self.lr0, self.lr1, self.total = lr, lr_final, max(1, total_steps)
@@ -195,16 +212,28 @@ class Trainer:
         f = min(1.0, self.log.steps / self.total)
         return self.lr1 + 0.5 * (self.lr0 - self.lr1) * (1.0 + math.cos(math.pi * f))
 
+    def pairs(self):
+        return [(a, b) for a, b in self.store.pairs()
+                if self.store.label[a][1] >= self.skip_windows]
+
     def step_on(self, a, b):
+        net = self.net
         sur.sur_to_bf16(a, self.xb)
         sur.sur_residual_target(a, b, self.rscale, sur.NUSE, self.cp.P, self.tgt)
-        loss = self.net.train_step(self.xb, self.tgt, self.wch, lr=self.lr())
+        net.forward(self.xb)
+        loss = float(net.loss_and_grad(self.tgt, self.wch).item())
+        if self.mean_loss is not None and loss > self.outlier * self.mean_loss:
+            self.skipped += 1
+            return loss
+        self.mean_loss = loss if self.mean_loss is None else 0.95 * self.mean_loss + 0.05 * loss
+        net.backward(net.dout)
+        net.adam_step(self.lr())
         self.log.steps += 1
         return loss
 
     def train(self, n: int):
         record_every = self.record_every
-        pairs = self.store.pairs()
+        pairs = self.pairs()
         if not pairs:
             return
         t0 = time.perf_counter()
@@ -212,7 +241,7 @@ class Trainer:
             a, b = pairs[int(self.rng.integers(len(pairs)))]
             loss = self.step_on(self.store.data[a], self.store.data[b])
             if record_every and self.log.steps % record_every == 0:
-                self.log.losses.append((self.log.steps, float(loss.item())))
+                self.log.losses.append((self.log.steps, loss))
         self.torch.cuda.synchronize()
         self.log.seconds_train += time.perf_counter() - t0
 
@@ -237,6 +266,42 @@ def residual_scale(cp: Coupler, store: SnapshotStore, floor: float = 1e-6) -> np
     r = np.ones(sur.NCH, dtype=np.float32)
     r[:sur.NUSE] = np.maximum(np.sqrt(acc / max(1, len(pairs))), floor)
     return r
+
+
+def prediction_error(net: sur.UNet, cp: Coupler, store: SnapshotStore, rscale,
+                     pairs=None, predictor=None) -> np.ndarray:
+    """Per-channel error of one-window predictions over stored pairs, in
+    units of the window's own change: sqrt(sum |pred - s_b|^2 / sum |s_a -
+    s_b|^2) for phi, ux, uy, uz, p (1 = no better than keeping the state)."""
+    torch = cp.torch
+    dev = cp.solver.device
+    P = cp.P
+    rs = torch.as_tensor(np.asarray(rscale, dtype=np.float32)).to(dev)
+    xb = torch.empty((P, sur.NCH), dtype=torch.int16, device=dev)
+    pred, grad = cp.new_state(), cp.new_state()
+    scr = torch.empty(P // 256 + 2, dtype=torch.float64, device=dev)
+    out = torch.empty(2 * sur.NUSE, dtype=torch.float64, device=dev)
+    onehot = [torch.as_tensor(np.eye(sur.NUSE, dtype=np.float32)[c] * sur.NUSE).to(dev)
+              for c in range(sur.NUSE)]
+    num = np.zeros(sur.NUSE)
+    den = np.zeros(sur.NUSE)
+    for a, b in (store.pairs() if pairs is None else pairs):
+        sa, sb = store.data[a], store.data[b]
+        if predictor is None:
+            sur.sur_to_bf16(sa, xb)
+            o = net.forward(xb)
+        else:
+            o = predictor(sa)
+        pred.copy_(sa)
+        sur.sur_apply_residual(pred, o, rs, sur.NUSE, P)
+        for c in range(sur.NUSE):
+            sur.sur_mse(pred, sb, sur.NUSE, sur.NCH, P, onehot[c], grad, scr, out[c:c + 1])
+            sur.sur_mse(sa, sb, sur.NUSE, sur.NCH, P, onehot[c], grad, scr,
+                        out[sur.NUSE + c:sur.NUSE + c + 1])
+        o_h = out.cpu().numpy()
+        num += o_h[:sur.NUSE]
+        den += o_h[sur.NUSE:]
+    return np.sqrt(num / np.maximum(den, 1e-300))
 
 
 def generate(cp: Coupler, store: SnapshotStore, workloads, windows: int, trainer=None,
@@ -274,6 +339,7 @@ class RunStats:
     sur_windows: int = 0
     lbm_windows: int = 0
     fallbacks: int = 0
+    fail_reasons: dict = field(default_factory=dict)
     judged: int = 0
     judge_fail: int = 0
     judge_err: list = field(default_factory=list)
@@ -282,7 +348,8 @@ class RunStats:
 
 def accelerated_run(cp: Coupler, net: sur.UNet, rscale, windows: int, nsur: int = 7,
                     cycle: int = 8, limits: CheckLimits | None = None,
-                    judge_tol: float = 0.5, predictor=None, linear: bool = False) -> RunStats:
+                    judge_tol: float = 0.5, predictor=None, linear: bool = False,
+                    warmup_windows: int = 2) -> RunStats:
     """Advances cp.solver by windows * K steps with the surrogate schedule
     described in the module docstring. ``predictor`` (default: the network)
     maps a coarse state to its predicted change in rscale units (FP32
@@ -312,7 +379,11 @@ def accelerated_run(cp: Coupler, net: sur.UNet, rscale, windows: int, nsur: int 
     probation = False
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    w = 0
+    # the acoustic transient of the initial state is left to the solver
+    w = min(warmup_windows, windows)
+    if w:
+        solver.step(K_STEPS * w)
+        st.lbm_windows += w
     while w < windows:
         cyc = min(cycle, windows - w)
         nsur_c = 0 if probation else min(nsur, cyc - 1)
@@ -333,9 +404,11 @@ def accelerated_run(cp: Coupler, net: sur.UNet, rscale, windows: int, nsur: int 
             out = predict(s)
             sur.sur_apply_residual(s, out, rs, sur.NUSE, P)
             cp.checks(s, chk)
-            if not limits.passed(chk.cpu().numpy(), mass0):
+            why = limits.failed(chk.cpu().numpy(), mass0)
+            if why:
                 s.copy_(sprev)
                 st.fallbacks += 1
+                st.fail_reasons[why] = st.fail_reasons.get(why, 0) + 1
                 break
             sur.sur_fix_mass(s, P, chk, chk0[0:1])
             sur.sur_features(s, cp.coarse)
@@ -350,6 +423,7 @@ def accelerated_run(cp: Coupler, net: sur.UNet, rscale, windows: int, nsur: int 
                 cp.save_base_restore()
                 lbm.lbm_reset(solver.ctx, cp.phi64, cp.u64, cp.p64, t_cycle)
                 st.fallbacks += 1
+                st.fail_reasons["reset"] = st.fail_reasons.get("reset", 0) + 1
                 done = 0
                 s.copy_(s0)
         st.sur_windows += done
@@ -387,3 +461,146 @@ def phi_error(solver: lbm.Solver, phi_ref) -> float:
     the device)."""
     d = solver.diagnostics(phi_ref)
     return math.sqrt(d["l2_num"] / d["l2_den"]) if d["l2_den"] > 0 else math.inf
+
+
+def _prefetch(fn, keys, depth: int = 2):
+    """Yields fn(k) for k in keys, computing up to ``depth`` ahead in worker
+    threads (input generation on the host overlaps the GPU work)."""
+    from collections import deque
+    from concurrent.futures import ThreadPoolExecutor
+    keys = list(keys)
+    with ThreadPoolExecutor(max_workers=depth) as ex:
+        q = deque(ex.submit(fn, k) for k in keys[:depth])
+        nxt = depth
+        while q:
+            f = q.popleft()
+            if nxt < len(keys):
+                q.append(ex.submit(fn, keys[nxt]))
+                nxt += 1
+            yield f.result()
+
+
+def surrogate_benchmark(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rmax: float = 16.0,
+                        train_seeds=tuple(range(1000, 1032)), windows: int = 64,
+                        test_seed: int = 1, horizon: int = 64, schedules=(7, 3, 1),
+                        precision: str = "fp16", train_per_window: int = 1,
+                        capacity: int = 300, lr: float = 3e-4, cycle: int = 8,
+                        log=print) -> dict:
+    """Emulsion workload: trains the U-Net on solver trajectories from
+    ``train_seeds`` (``windows`` windows each) and runs the held-out
+    ``test_seed`` for ``horizon`` windows with the plain solver and with each
+    surrogate schedule (nsur network windows per cycle), reporting wall time,
+    speedup and the relative L2 error of phi against the plain run. The same
+    schedules with a persistence predictor (no change per window: the method
+    without the network), the per-channel one-window prediction error on the
+    held-out trajectory, and the error floor of the fine-grid reconstruction
+    (an exact coarse change prolonged onto the fine grid) are reported
+    beside them."""
+    import torch
+    from . import inputs
+    mk = lambda seed: inputs.emulsion(n=n, n_drops=n_drops, rmin=rmin, rmax=rmax, seed=seed)
+    gen = _prefetch(mk, [test_seed] + list(train_seeds))
+    wt = next(gen)
+    u_rms = 0.02
+    solver = lbm.Solver(dict(wt.params(), precision=precision), wt.phi0, wt.u0, wt.p0)
+    cp = Coupler(solver, state_scale(u_rms))
+    f0 = tuple(torch.as_tensor(a) for a in (wt.phi0, wt.u0, wt.p0))
+    out = dict(workload=f"emulsion {n}^3, {len(wt.meta['radii'])} droplets r in [{rmin}, {rmax}], "
+                        f"u rms {u_rms}, seed {test_seed}",
+               grid=[n, n, n], coarse=list(cp.coarse), storage=precision, K=K_STEPS,
+               horizon_steps=horizon * K_STEPS, cycle=cycle)
+
+    # plain solver over the horizon: the reference and the time to beat
+    solver.reset(*f0, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(horizon * K_STEPS)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    phi_ref, _, _ = solver.fields()
+    m_ref = solver.diagnostics()["sum_phi"]
+    out["plain_seconds"] = t_plain
+    log(f"[surrogate] plain {horizon * K_STEPS} steps: {t_plain * 1e3:.1f} ms")
+
+    # held-out trajectory for validation
+    hs = SnapshotStore(horizon + 1, cp.P, solver.device)
+    generate(cp, hs, [wt], horizon)
+
+    # training
+    net = sur.UNet(cp.coarse, channels=(16, 32, 48, 64), seed=0)
+    store = SnapshotStore(capacity, cp.P, solver.device)
+    divs = []
+    on_snap = lambda c: divs.append(math.sqrt(max(c[3], 0.0) / c[5]))
+    first = next(gen)
+    generate(cp, store, [first], windows, on_snapshot=on_snap)
+    rscale = residual_scale(cp, store)
+    total = len(train_seeds) * windows * train_per_window
+    tr = Trainer(net, cp, store, rscale, lr=lr, total_steps=total)
+    tr.train(windows * train_per_window)
+    for i, w in enumerate(gen):
+        generate(cp, store, [w], windows, trainer=tr, train_per_window=train_per_window,
+                 on_snapshot=on_snap)
+        log(f"[surrogate] trained on {i + 2}/{len(train_seeds)} trajectories: "
+            f"{tr.log.steps} steps, last loss {tr.log.losses[-1][1] if tr.log.losses else float('nan'):.4f}")
+    val = prediction_error(net, cp, hs, rscale,
+                           pairs=[(a, b) for a, b in hs.pairs() if hs.label[a][1] >= tr.skip_windows])
+    untrained = sur.UNet(cp.coarse, channels=(16, 32, 48, 64), seed=1)
+    val0 = prediction_error(untrained, cp, hs, rscale,
+                            pairs=[(a, b) for a, b in hs.pairs() if hs.label[a][1] >= tr.skip_windows])
+    del untrained
+    out["training"] = dict(trajectories=len(train_seeds), windows=windows,
+                           snapshots=len(train_seeds) * (windows + 1), steps=tr.log.steps,
+                           skipped_outliers=tr.skipped, seconds_solver=tr.log.seconds_lbm,
+                           seconds_train=tr.log.seconds_train, params=net.n_params(),
+                           rscale=[float(x) for x in rscale[:sur.NUSE]])
+    names = ["phi", "ux", "uy", "uz", "p"]
+    out["one_window_error"] = {"trained": dict(zip(names, map(float, val))),
+                               "untrained": dict(zip(names, map(float, val0)))}
+    log(f"[surrogate] held-out one-window error (trained) {np.round(val, 3).tolist()}, "
+        f"untrained {np.round(val0, 3).tolist()}")
+
+    limits = CheckLimits(div_rms=3.0 * max(divs))
+    zero = cp.new_state()
+    runs = {}
+    for ns in schedules:
+        for name, pred, lin in (("net", None, False), ("persistence", lambda s: zero, False)):
+            solver.reset(*f0, 0)
+            st = accelerated_run(cp, net, rscale, horizon, nsur=ns, cycle=cycle,
+                                             limits=limits, predictor=pred, linear=lin,
+                                             judge_tol=0.5 if name == "net" else None)
+            err = phi_error(solver, phi_ref)
+            m = solver.diagnostics()["sum_phi"]
+            runs[f"nsur{ns}_{name}"] = dict(
+                seconds=st.seconds, speedup=t_plain / st.seconds, phi_l2_error=err,
+                mass_drift=(m - m_ref) / m_ref, surrogate_windows=st.sur_windows,
+                solver_windows=st.lbm_windows, fallbacks=st.fallbacks,
+                fallback_reasons=dict(st.fail_reasons), judged=st.judged,
+                judge_fail=st.judge_fail,
+                judge_err_mean=float(np.mean(st.judge_err)) if st.judge_err else None)
+            log(f"[surrogate] nsur={ns} {name}: {st.seconds * 1e3:.1f} ms, speedup "
+                f"{t_plain / st.seconds:.2f}, phi L2 error {err:.3e}, fallbacks {st.fallbacks}")
+    out["runs"] = runs
+
+    # error floor of the fine reconstruction: exact coarse changes
+    floor = {}
+    sa, sb = cp.new_state(), cp.new_state()
+    for k in (1, cycle - 1):
+        for lin in (False, True):
+            solver.reset(*f0, 0)
+            solver.step(2 * K_STEPS)
+            cp.snapshot(sa)
+            cp.save_base()
+            solver.step(k * K_STEPS)
+            cp.snapshot(sb)
+            phik, _, _ = solver.fields()
+            cp.push(sa, sb, solver.t, linear=lin)
+            floor[f"{k}_windows_{'linear' if lin else 'level_set'}"] = phi_error(solver, phik)
+    out["reconstruction_floor"] = floor
+    ok = [(r["speedup"], k) for k, r in runs.items()
+          if k.endswith("_net") and r["phi_l2_error"] <= 1e-2]
+    out["speedup_at_err_1e-2"] = max(ok)[0] if ok else None
+    best = min((r["phi_l2_error"], k) for k, r in runs.items() if k.endswith("_net"))
+    out["lowest_error_schedule"] = dict(schedule=best[1], phi_l2_error=best[0],
+                                        speedup=runs[best[1]]["speedup"])
+    del solver
+    return out
