@@ -147,6 +147,12 @@ DevParams<R> make_params(const lbm_params *P, const TileCfg &tc) {
     d.band = tc.band < d.nty ? tc.band : d.nty;
     d.xq = d.ntiles / 8;
     d.xr = d.ntiles % 8;
+    d.bty0 = 0;
+    d.bnty = d.nty;
+    d.btz0 = 0;
+    d.bnz = P->nz;
+    d.bty_step = 1;
+    d.btz_step = 1;
     const double c = P->courant, cs2 = c * c / 3.0;
     const double eta1 = P->rho1 * cs2 * P->tau_rho1, eta2 = P->rho2 * cs2 * P->tau_rho2;
     d.c = R(c);
@@ -173,6 +179,13 @@ DevParams<R> make_params(const lbm_params *P, const TileCfg &tc) {
     d.iscale_f = R(std::ldexp(1.0, -P->store_log2[0]));
     d.scale_g = R(std::ldexp(1.0, P->store_log2[1]));
     d.iscale_g = R(std::ldexp(1.0, -P->store_log2[1]));
+    const double lwA = 0.5 * c * (1.0 + c), lwD = -0.5 * c * (1.0 - c), lwB = 1.0 - c * c;
+    d.wA_f = R(std::ldexp(lwA, -P->store_log2[0]));
+    d.wB_f = R(std::ldexp(lwB, -P->store_log2[0]));
+    d.wD_f = R(std::ldexp(lwD, -P->store_log2[0]));
+    d.wA_g = R(std::ldexp(lwA, -P->store_log2[1]));
+    d.wB_g = R(std::ldexp(lwB, -P->store_log2[1]));
+    d.wD_g = R(std::ldexp(lwD, -P->store_log2[1]));
     return d;
 }
 
@@ -222,19 +235,68 @@ int check_launch(lbm_ctx *c) {
     return LBM_OK;
 }
 
-template <class St, Mode M, bool W>
-void launch_step(lbm_ctx *c, int src, int dst, const MassFix &mf) {
-    using R = typename St::R;
-    const DevParams<R> P = make_params<R>(&c->P, c->tc);
-    hipLaunchKernelGGL((step_kernel<St, M, W>), dim3(c->nblocks), dim3(BLOCK), 0, c->stream,
-                       cbuf_of<St>(c, src), buf_of<St>(c, dst), P, mf);
+// Launch grid of a tile box: (ntx, rows, planes) in the plain order, a 1-D
+// run of tiles for the XCD-aware orders.
+template <class R>
+dim3 tile_grid(const DevParams<R> &P) {
+    return P.order == 0 ? dim3((unsigned)P.ntx, (unsigned)P.bnty, (unsigned)P.bnz)
+                        : dim3((unsigned)P.ntiles);
 }
 
+// Restricts a launch to tile rows ty0 + k ystep (k < nty) and planes
+// tz0 + k zstep (k < nz).
+template <class R>
+DevParams<R> with_box(DevParams<R> d, int ty0, int nty, int tz0, int nz, int band, int ystep = 1,
+                      int zstep = 1) {
+    d.bty0 = ty0;
+    d.bnty = nty;
+    d.btz0 = tz0;
+    d.bnz = nz;
+    d.bty_step = ystep;
+    d.btz_step = zstep;
+    d.ntiles = d.ntx * nty * nz;
+    d.band = band < nty ? band : nty;
+    d.xq = d.ntiles / 8;
+    d.xr = d.ntiles % 8;
+    return d;
+}
+
+template <class St, Mode M, bool W>
+void launch_step(lbm_ctx *c, int src, int dst, const DevParams<typename St::R> &P, MassFix mf,
+                 int &block_off) {
+    mf.block_off = block_off;
+    hipLaunchKernelGGL((step_kernel<St, M, W>), tile_grid(P), dim3(BLOCK), 0, c->stream,
+                       cbuf_of<St>(c, src), buf_of<St>(c, dst), P, mf);
+    block_off += P.ntiles;
+}
+
+// Periodic lattices: one wall-free launch. Walls in y and/or z: the interior
+// box of tiles runs the wall-free instance, the wall slabs (first and last
+// tile row; first and last plane) one wall-aware launch each. Walls in x
+// touch every tile row: one wall-aware launch.
 template <class St, Mode M>
 void launch_step_w(lbm_ctx *c, int src, int dst, const MassFix &mf) {
-    const bool walls = c->P.wall[0] || c->P.wall[1] || c->P.wall[2];
-    if (walls) launch_step<St, M, true>(c, src, dst, mf);
-    else launch_step<St, M, false>(c, src, dst, mf);
+    using R = typename St::R;
+    const DevParams<R> P = make_params<R>(&c->P, c->tc);
+    const int *w = c->P.wall;
+    int off = 0;
+    if (!w[0] && !w[1] && !w[2]) {
+        launch_step<St, M, false>(c, src, dst, P, mf, off);
+        return;
+    }
+    const int ylo = w[1] ? 1 : 0, yhi = w[1] ? P.nty - 1 : P.nty;
+    const int zlo = w[2] ? 1 : 0, zhi = w[2] ? P.nz - 1 : P.nz;
+    if (w[0] || yhi <= ylo || zhi <= zlo) {
+        launch_step<St, M, true>(c, src, dst, P, mf, off);
+        return;
+    }
+    const int band = c->tc.band;
+    launch_step<St, M, false>(c, src, dst, with_box(P, ylo, yhi - ylo, zlo, zhi - zlo, band), mf, off);
+    if (w[1])  // first and last tile row, all planes
+        launch_step<St, M, true>(c, src, dst, with_box(P, 0, 2, 0, P.nz, band, P.nty - 1), mf, off);
+    if (w[2])  // first and last plane, the interior tile rows
+        launch_step<St, M, true>(c, src, dst,
+                                 with_box(P, ylo, yhi - ylo, 0, 2, band, 1, P.nz - 1), mf, off);
 }
 
 template <class St>
@@ -247,7 +309,7 @@ void step_dispatch(lbm_ctx *c, Mode m, int src, int dst, const MassFix &mf) {
 }
 
 void step_any(lbm_ctx *c, Mode m, int src, int dst, int mf_mode = 0) {
-    const MassFix mf{mf_mode, c->partials, c->mf + 1};
+    const MassFix mf{mf_mode, c->partials, c->mf + 1, 0};
     switch (c->P.precision) {
         case LBM_FP64: step_dispatch<SF64>(c, m, src, dst, mf); break;
         case LBM_FP32: step_dispatch<SF32>(c, m, src, dst, mf); break;
@@ -262,7 +324,7 @@ template <class St, Mode M, bool W>
 void launch_moments(lbm_ctx *c, const FieldOut &o) {
     using R = typename St::R;
     const DevParams<R> P = make_params<R>(&c->P, c->tc);
-    hipLaunchKernelGGL((moments_kernel<St, M, W>), dim3(c->nblocks), dim3(BLOCK), 0, c->stream,
+    hipLaunchKernelGGL((moments_kernel<St, M, W>), tile_grid(P), dim3(BLOCK), 0, c->stream,
                        cbuf_of<St>(c, c->cur ^ 1), P, o);
 }
 
@@ -296,10 +358,10 @@ void launch_init(lbm_ctx *c, const double *phi0, const double *u0, const double 
     const DevParams<R> PR = make_params<R>(&c->P, c->tc);
     const bool walls = c->P.wall[0] || c->P.wall[1] || c->P.wall[2];
     if (walls)
-        hipLaunchKernelGGL((init_kernel<St, true>), dim3(c->nblocks), dim3(BLOCK), 0, c->stream,
+        hipLaunchKernelGGL((init_kernel<St, true>), tile_grid(PR), dim3(BLOCK), 0, c->stream,
                            phi0, u0, p0, PD, PR, buf_of<St>(c, dst), c->flag, c->partials);
     else
-        hipLaunchKernelGGL((init_kernel<St, false>), dim3(c->nblocks), dim3(BLOCK), 0, c->stream,
+        hipLaunchKernelGGL((init_kernel<St, false>), tile_grid(PR), dim3(BLOCK), 0, c->stream,
                            phi0, u0, p0, PD, PR, buf_of<St>(c, dst), c->flag, c->partials);
 }
 
@@ -316,7 +378,7 @@ template <class St>
 void launch_load(lbm_ctx *c, const double *f, const double *g, int dst) {
     using R = typename St::R;
     const DevParams<R> P = make_params<R>(&c->P, c->tc);
-    hipLaunchKernelGGL((load_kernel<St>), dim3(c->nblocks), dim3(BLOCK), 0, c->stream, f, g, P,
+    hipLaunchKernelGGL((load_kernel<St>), tile_grid(P), dim3(BLOCK), 0, c->stream, f, g, P,
                        buf_of<St>(c, dst));
 }
 

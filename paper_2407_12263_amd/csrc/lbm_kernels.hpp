@@ -108,6 +108,9 @@ struct DevParams {
     int order;               // 0: tile = block id; 1: XCD runs; 2: XCD runs of z-banded order
     int band;                // tile-rows per band (order 2)
     int xq, xr;              // ntiles = 8 xq + xr (XCD runs)
+    int bty0, bnty, btz0, bnz;  // tile rows bty0 + k bty_step (k < bnty) x planes
+    int bty_step, btz_step;     // btz0 + k btz_step (k < bnz) covered by one launch
+                                // (ntiles = ntx bnty bnz)
     R c, h;                  // Courant number, c(1-c)/2
     R lwA, lwD;              // Lax-Wendroff weights of x-e and x+e: c(1+c)/2, -c(1-c)/2
     R cs2, inv_cs2, half_inv_cs4;
@@ -120,7 +123,14 @@ struct DevParams {
     R k1_eps;
     R rho0;                  // p_ref/cs2: gauge of the 16-bit f storage
     R scale_f, iscale_f, scale_g, iscale_g;
+    R wA_f, wB_f, wD_f;      // 2^-k (A, 1 - c^2, D): the three-tap weights of the stored
+    R wA_g, wB_g, wD_g;      // 16-bit deviations with their scale folded in (exact)
 };
+
+// Linear index of this block in its launch grid (x fastest).
+__device__ __forceinline__ uint32_t linear_block() {
+    return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
 
 // ---------------------------------------------------------- storage types
 struct SF64 { using R = double; using T = double; static constexpr bool DEV = false; };
@@ -217,15 +227,27 @@ __device__ __forceinline__ Site make_site(const DevParams<R> &P) {
     Site s;
     const uint32_t b = blockIdx.x;
     uint32_t t = b;
-    if (P.order >= 1) {
+    if (P.order == 0) {
+        // the launch grid is (ntx, bnty, bnz): no division
+        t = 0;
+    } else {
         const uint32_t xcd = b & 7u, slot = b >> 3;
         const uint32_t q = (uint32_t)P.xq, r = (uint32_t)P.xr;
         t = (xcd < r ? xcd * (q + 1u) : r * (q + 1u) + (xcd - r) * q) + slot;
     }
-    const uint32_t ntx = (uint32_t)P.ntx, nty = (uint32_t)P.nty, nz = (uint32_t)P.nz;
-    const uint32_t tx = t % ntx, rr = t / ntx;
-    uint32_t ty, tz;
-    if (P.order == 2) {
+    const uint32_t ntx = (uint32_t)P.ntx, nty = (uint32_t)P.bnty, nz = (uint32_t)P.bnz;
+    uint32_t tx, rr, ty, tz;
+    if (P.order == 0) {
+        tx = blockIdx.x;
+        rr = 0;
+        ty = blockIdx.y;
+        tz = blockIdx.z;
+    } else {
+        tx = t % ntx;
+        rr = t / ntx;
+    }
+    if (P.order == 0) {
+    } else if (P.order == 2) {
         const uint32_t bw = (uint32_t)P.band, full = nty / bw, per_band = bw * nz;
         if (rr < full * per_band) {
             const uint32_t k = rr / per_band, w = rr - k * per_band;
@@ -240,6 +262,8 @@ __device__ __forceinline__ Site make_site(const DevParams<R> &P) {
         ty = rr % nty;
         tz = rr / nty;
     }
+    ty = (uint32_t)P.bty0 + ty * (uint32_t)P.bty_step;
+    tz = (uint32_t)P.btz0 + tz * (uint32_t)P.btz_step;
     const uint32_t lx = threadIdx.x & ((1u << P.tx_log2) - 1u), ly = threadIdx.x >> P.tx_log2;
     s.x = (int)((tx << P.tx_log2) + lx);
     s.y = (int)(ty * (uint32_t)(BLOCK >> P.tx_log2) + ly);
@@ -395,9 +419,13 @@ __device__ __forceinline__ void gather(const Src<St> &src, const Site &s,
                 const R g0 = raw<St, i>(src.g, src, s, 0);
                 const R gp = raw<St, i>(src.g, src, s, i);
                 if constexpr (St::DEV) {
-                    // propagate the stored deviations and the phi_s bases apart
-                    fb[i] = fma(P.iscale_f, lw3(P, fm, f0, fp), t * P.rho0);
-                    gb[i] = fma(P.iscale_g, lw3(P, gm, g0, gp), t * lw3(P, ph[o], ph[0], ph[i]));
+                    // propagate the stored deviations and the phi_s bases apart;
+                    // the deviations in the weighted form B h0 + A hm + D hp with
+                    // the storage scale in the weights (FP16 values enter the
+                    // FP32 fmas without a separate conversion)
+                    fb[i] = fma(P.wA_f, fm, fma(P.wD_f, fp, fma(P.wB_f, f0, t * P.rho0)));
+                    gb[i] = fma(P.wA_g, gm, fma(P.wD_g, gp,
+                                fma(P.wB_g, g0, t * lw3(P, ph[o], ph[0], ph[i]))));
                 } else {
                     fb[i] = lw_flux(P, fm, f0, fp);
                     gb[i] = lw_flux(P, gm, g0, gp);
@@ -462,6 +490,10 @@ struct Macro {
 // K1 = sum g e - phi u, n = -K1/|K1| (0 where |K1| <= k1_eps),
 // S = 4 phi (1 - phi)/delta n, grad(phi) = (tau cs2 S - K1)/((tau + 1/2) cs2),
 // grad(rho) = (rho1 - rho2) grad(phi), p = cs2 sum f + cs2/2 u.grad(rho).
+// 1/x: the hardware reciprocal (1 ulp) in FP32, the division in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 template <class R>
 __device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)[19],
                                             const R (&gb)[19]) {
@@ -475,9 +507,9 @@ __device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)
     m.phi = phi;
     m.rho = fma(P.drho, phi, P.rho2);
     const R eta = fma(P.deta, phi, P.eta2);
-    const R irho = R(1) / m.rho;
+    const R irho = recip(m.rho);
     // omega_f = 1/(tau_rho + 1/2), tau_rho = eta/(rho cs2)
-    m.omega_f = R(1) / fma(eta * irho, P.inv_cs2, R(0.5));
+    m.omega_f = recip(fma(eta * irho, P.inv_cs2, R(0.5)));
     const R jx = first_moment<0>(fb), jy = first_moment<1>(fb), jz = first_moment<2>(fb);
     m.u[0] = fma(P.c, jx, R(0.5) * m.rho * P.G[0]) * irho;
     m.u[1] = fma(P.c, jy, R(0.5) * m.rho * P.G[1]) * irho;
@@ -487,7 +519,7 @@ __device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)
                     fma(P.c, first_moment<2>(gb), -phi * m.u[2])};
     const R k = sqrt(fma(K[0], K[0], fma(K[1], K[1], K[2] * K[2])));
     const bool has_n = k > P.k1_eps;
-    const R rk = has_n ? R(1) / k : R(0);
+    const R rk = has_n ? recip(k) : R(0);
     const R s = P.four_over_delta * phi * (R(1) - phi);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -697,6 +729,7 @@ struct MassFix {
     int mode;               // bit 0: report partial sums; bit 1: apply coef
     double *partials;       // 2 per block
     const double *coef;     // c
+    int block_off;          // index of this launch's first block among the step's blocks
 };
 
 template <class R>
@@ -705,7 +738,10 @@ __device__ __forceinline__ R mass_weight(R phi) {
 }
 
 // Fused step: propagate (mode M) from src, moments, collide, store to dst.
-// Wavefronts without a wall node take the wall-free propagation.
+// Wavefronts without a wall node take the wall-free propagation. The host
+// launches the wall-free instance (WALLS = false) over the tiles that touch
+// no wall and the wall-aware one over the wall slabs: the wall path's code
+// and registers then cost nothing in the interior.
 template <class St, Mode M, bool WALLS>
 __global__ void __launch_bounds__(BLOCK) step_kernel(CBuf<St> src, Buf<St> dst,
                                                      DevParams<typename St::R> P, MassFix mf) {
@@ -740,7 +776,8 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(CBuf<St> src, Buf<St> dst,
         collide(P, m, q, fb, gb);
         store<St>(make_dst(dst, P), s.n, P, fb, gb);
     }
-    if (mf.mode & 1) block_sum2(rep_phi, rep_w, mf.partials + 2 * (size_t)blockIdx.x);
+    if (mf.mode & 1)
+        block_sum2(rep_phi, rep_w, mf.partials + 2 * ((size_t)mf.block_off + linear_block()));
 }
 
 // Sums the per-block pairs in a fixed order (1024 threads, each a strided
@@ -876,7 +913,7 @@ __global__ void __launch_bounds__(BLOCK) moments_kernel(CBuf<St> src, DevParams<
                 const double x = red[w][k];
                 v = (k == 6 || k == 8) ? fmax(v, x) : (k == 7 ? fmin(v, x) : v + x);
             }
-            out.partials[(size_t)blockIdx.x * NSUM + k] = v;
+            out.partials[(size_t)linear_block() * NSUM + k] = v;
         }
     }
 }
@@ -1007,7 +1044,7 @@ __global__ void __launch_bounds__(BLOCK) init_kernel(const double *phi0, const d
                                                      int *bad, double *partials) {
     const Site s = make_site(P);
     if (s.valid) init_node<St, WALLS>(phi0, u0, p0, P, PR, dst, bad, s);
-    block_sum2(s.valid ? phi0[s.n] : 0.0, 0.0, partials + 2 * (size_t)blockIdx.x);
+    block_sum2(s.valid ? phi0[s.n] : 0.0, 0.0, partials + 2 * (size_t)linear_block());
 }
 
 
