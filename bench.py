@@ -5,10 +5,16 @@ Workload: Rayleigh-Taylor instability on a 128 x 512 x 128 lattice
 of amplitude 0.05 Lx, Re = 256, W = 4, sigma = 5e-5, periodic in x and z,
 no-slip walls in y, Courant number 0.997; FP32 collision with the
 populations stored in HBM as FP16 deviations (synthetic initial fields).
-A step is one fused launch (propagation, moments, both collisions, store)
-over the whole lattice; the reported value is MLUPS = nodes x steps /
-(seconds x 1e6), timed with HIP events on the solver's stream with the state
-resident in HBM. The same run also reports the FP32-storage rate.
+A step is the fused update (propagation, moments, both collisions, store)
+of the whole lattice: one launch over the tiles that touch no wall and one
+over the two wall slabs (plus the FP64 phase-mass bookkeeping every 10
+steps); the reported value is MLUPS = nodes x steps / (seconds x 1e6), timed
+with HIP events on the solver's stream with the state resident in HBM, and
+the roofline figure divides the algorithmic bytes of a step by that step
+time. The same run reports the BF16- and FP32-storage rates and the rate of
+the finite-difference-normal comparison scheme (Sec. 3.4: grad phi by
+central differences of a stored phi field, a second pass per step) in the
+same storage mode.
 
 The "surrogate" object covers the learned part on the emulsion workload
 (256^3 periodic, 200 droplets, random solenoidal velocity): the coarse-grid
@@ -106,7 +112,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--storage", default="fp16", choices=["fp16", "bf16", "fp32", "fp64"])
-    ap.add_argument("--secondary", default="fp32", help="comma list of extra storage modes")
+    ap.add_argument("--secondary", default="bf16,fp32,fp16+fd",
+                    help="comma list of extra runs: storage mode, '+fd' for the "
+                         "finite-difference-normal comparison scheme")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate-accelerated emulsion runs")
     ap.add_argument("--surrogate-trajectories", type=int, default=32,
@@ -130,9 +138,10 @@ def main():
     results = {}
     modes = [args.storage] + [m for m in args.secondary.split(",") if m and m != args.storage]
     for mode in modes:
-        print(f"[bench] {w.name} storage={mode} warmup={args.warmup} steps={args.steps}",
-              file=sys.stderr, flush=True)
-        sol = lbm.Solver(dict(w.params(), precision=mode), w.phi0, w.u0, w.p0)
+        prec, fd = (mode[:-3], 1) if mode.endswith("+fd") else (mode, 0)
+        print(f"[bench] {w.name} storage={prec} normal_fd={fd} warmup={args.warmup} "
+              f"steps={args.steps}", file=sys.stderr, flush=True)
+        sol = lbm.Solver(dict(w.params(), precision=prec, normal_fd=fd), w.phi0, w.u0, w.p0)
         secs = time_solver(sol, args.steps, args.warmup)
         d = sol.diagnostics()
         ok = all(map(lambda v: v == v, [d["sum_phi"], d["umax"]]))
@@ -169,8 +178,8 @@ def main():
                      "traffic": traffic, "algorithmic_bytes_per_launch": launch_bytes,
                      "kernel": "step_kernel (fused propagate+moments+collide+store)"},
         "secondary": {m: {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 5),
-                          "hbm_frac": round(lbm.BYTES_PER_LU[m] * w.N / (r["seconds"] / args.steps)
-                                            / 1e9 / HBM_PEAK_GBS, 4)}
+                          "hbm_frac": round(lbm.BYTES_PER_LU[m.split("+")[0]] * w.N
+                                            / (r["seconds"] / args.steps) / 1e9 / HBM_PEAK_GBS, 4)}
                       for m, r in results.items() if m != args.storage},
         "checks": {m: {"finite": r["finite"], "sum_phi": r["sum_phi"], "umax": r["umax"]}
                    for m, r in results.items()},

@@ -78,6 +78,14 @@ typedef struct {
                                /* FP64 and the drift from sum(phi0) is put    */
                                /* back on the interface, weighted by          */
                                /* phi(1 - phi), at the next step (0: never)   */
+    int32_t normal_fd;         /* 0: the difference-free method (n and        */
+                               /* |grad phi| from K1, Eqs. 17-19); 1: the     */
+                               /* comparison scheme of Sec. 3.4: grad phi by  */
+                               /* isotropic central differences of phi, which */
+                               /* takes a second pass over the lattice per    */
+                               /* step (phi of the propagated g, stored; a    */
+                               /* neighbour beyond a wall takes the node's    */
+                               /* own value)                                  */
     double courant;            /* c in (0, 1]; the paper uses 0.997; 1 gives  */
                                /* exact streaming                             */
     double rho1, rho2;         /* density of the phi = 1 and phi = 0 phases   */

@@ -80,6 +80,7 @@ struct Layout {
     size_t result_bytes;
     size_t flag_bytes;
     size_t mf_bytes;
+    size_t phifd_bytes;    // phi field of the finite-difference variant (or 0)
     size_t total;
 };
 
@@ -97,7 +98,9 @@ Layout layout_of(const lbm_params *P) {
     L.result_bytes = align_up(NSUM * sizeof(double));
     L.flag_bytes = kAlign;
     L.mf_bytes = kAlign;  // M0, coef
-    L.total = 2 * L.buf_bytes + L.partial_bytes + L.result_bytes + L.flag_bytes + L.mf_bytes;
+    L.phifd_bytes = P->normal_fd ? align_up(N * sizeof(double)) : 0;
+    L.total = 2 * L.buf_bytes + L.partial_bytes + L.result_bytes + L.flag_bytes + L.mf_bytes +
+              L.phifd_bytes;
     return L;
 }
 
@@ -117,6 +120,7 @@ int validate(const lbm_params *P) {
     for (int k = 0; k < 2; ++k)
         if (P->store_log2[k] < -24 || P->store_log2[k] > 24) return LBM_EINVAL;
     if (P->check_every < 0 || P->mass_fix_every < 0) return LBM_EINVAL;
+    if (P->normal_fd != 0 && P->normal_fd != 1) return LBM_EINVAL;
     auto fin = [](double x) { return std::isfinite(x); };
     if (!(fin(P->courant) && P->courant > 0.0 && P->courant <= 1.0)) return LBM_EINVAL;
     if (!(fin(P->rho1) && fin(P->rho2) && P->rho1 > 0.0 && P->rho2 > 0.0)) return LBM_EINVAL;
@@ -186,6 +190,7 @@ DevParams<R> make_params(const lbm_params *P, const TileCfg &tc) {
     d.wA_g = R(std::ldexp(lwA, -P->store_log2[1]));
     d.wB_g = R(std::ldexp(lwB, -P->store_log2[1]));
     d.wD_g = R(std::ldexp(lwD, -P->store_log2[1]));
+    d.phi_fd = nullptr;
     return d;
 }
 
@@ -201,6 +206,7 @@ struct lbm_ctx {
     double *result;
     int *flag;
     double *mf;         // M0, coef of the phase-mass bookkeeping
+    void *phifd;        // phi field of the finite-difference variant (or NULL)
     bool mf_pending;    // the next step applies coef
     TileCfg tc;
     int cur;            // buffer holding the post-collision state
@@ -261,50 +267,91 @@ DevParams<R> with_box(DevParams<R> d, int ty0, int nty, int tz0, int nz, int ban
     return d;
 }
 
-template <class St, Mode M, bool W>
+template <class St, Mode M, bool W, bool FD>
 void launch_step(lbm_ctx *c, int src, int dst, const DevParams<typename St::R> &P, MassFix mf,
                  int &block_off) {
     mf.block_off = block_off;
-    hipLaunchKernelGGL((step_kernel<St, M, W>), tile_grid(P), dim3(BLOCK), 0, c->stream,
-                       cbuf_of<St>(c, src), buf_of<St>(c, dst), P, mf);
+    if constexpr (St::DEV)
+        hipLaunchKernelGGL((step_kernel_o5<St, M, W, FD>), tile_grid(P), dim3(BLOCK), 0,
+                           c->stream, cbuf_of<St>(c, src), buf_of<St>(c, dst), P, mf);
+    else
+        hipLaunchKernelGGL((step_kernel<St, M, W, FD>), tile_grid(P), dim3(BLOCK), 0, c->stream,
+                           cbuf_of<St>(c, src), buf_of<St>(c, dst), P, mf);
     block_off += P.ntiles;
+}
+
+// Parameters of a launch, with the phi field of the finite-difference variant.
+template <class R>
+DevParams<R> launch_params(lbm_ctx *c) {
+    DevParams<R> P = make_params<R>(&c->P, c->tc);
+    P.phi_fd = (R *)c->phifd;
+    return P;
+}
+
+// First pass of the finite-difference variant: phi of the state the next
+// launch reads from buffer src (one launch over all tiles).
+template <class St, Mode M>
+void launch_phi(lbm_ctx *c, int src, const MassFix &mf) {
+    using R = typename St::R;
+    const DevParams<R> P = launch_params<R>(c);
+    const bool walls = c->P.wall[0] || c->P.wall[1] || c->P.wall[2];
+    if (walls)
+        hipLaunchKernelGGL((phi_kernel<St, M, true>), tile_grid(P), dim3(BLOCK), 0, c->stream,
+                           cbuf_of<St>(c, src), P, mf);
+    else
+        hipLaunchKernelGGL((phi_kernel<St, M, false>), tile_grid(P), dim3(BLOCK), 0, c->stream,
+                           cbuf_of<St>(c, src), P, mf);
 }
 
 // Periodic lattices: one wall-free launch. Walls in y and/or z: the interior
 // box of tiles runs the wall-free instance, the wall slabs (first and last
 // tile row; first and last plane) one wall-aware launch each. Walls in x
 // touch every tile row: one wall-aware launch.
-template <class St, Mode M>
+template <class St, Mode M, bool FD>
 void launch_step_w(lbm_ctx *c, int src, int dst, const MassFix &mf) {
     using R = typename St::R;
-    const DevParams<R> P = make_params<R>(&c->P, c->tc);
+    const DevParams<R> P = launch_params<R>(c);
     const int *w = c->P.wall;
     int off = 0;
     if (!w[0] && !w[1] && !w[2]) {
-        launch_step<St, M, false>(c, src, dst, P, mf, off);
+        launch_step<St, M, false, FD>(c, src, dst, P, mf, off);
         return;
     }
     const int ylo = w[1] ? 1 : 0, yhi = w[1] ? P.nty - 1 : P.nty;
     const int zlo = w[2] ? 1 : 0, zhi = w[2] ? P.nz - 1 : P.nz;
     if (w[0] || yhi <= ylo || zhi <= zlo) {
-        launch_step<St, M, true>(c, src, dst, P, mf, off);
+        launch_step<St, M, true, FD>(c, src, dst, P, mf, off);
         return;
     }
     const int band = c->tc.band;
-    launch_step<St, M, false>(c, src, dst, with_box(P, ylo, yhi - ylo, zlo, zhi - zlo, band), mf, off);
+    launch_step<St, M, false, FD>(c, src, dst, with_box(P, ylo, yhi - ylo, zlo, zhi - zlo, band),
+                                  mf, off);
     if (w[1])  // first and last tile row, all planes
-        launch_step<St, M, true>(c, src, dst, with_box(P, 0, 2, 0, P.nz, band, P.nty - 1), mf, off);
+        launch_step<St, M, true, FD>(c, src, dst, with_box(P, 0, 2, 0, P.nz, band, P.nty - 1), mf,
+                                     off);
     if (w[2])  // first and last plane, the interior tile rows
-        launch_step<St, M, true>(c, src, dst,
-                                 with_box(P, ylo, yhi - ylo, 0, 2, band, 1, P.nz - 1), mf, off);
+        launch_step<St, M, true, FD>(c, src, dst,
+                                     with_box(P, ylo, yhi - ylo, 0, 2, band, 1, P.nz - 1), mf, off);
+}
+
+template <class St, Mode M>
+void launch_step_fd(lbm_ctx *c, int src, int dst, const MassFix &mf) {
+    if (c->P.normal_fd) {
+        MassFix apply = mf;
+        apply.mode &= 2;
+        launch_phi<St, M>(c, src, apply);
+        launch_step_w<St, M, true>(c, src, dst, mf);
+    } else {
+        launch_step_w<St, M, false>(c, src, dst, mf);
+    }
 }
 
 template <class St>
 void step_dispatch(lbm_ctx *c, Mode m, int src, int dst, const MassFix &mf) {
     switch (m) {
-        case LOCAL: launch_step_w<St, LOCAL>(c, src, dst, mf); break;
-        case SHIFT: launch_step_w<St, SHIFT>(c, src, dst, mf); break;
-        default: launch_step_w<St, LW>(c, src, dst, mf); break;
+        case LOCAL: launch_step_fd<St, LOCAL>(c, src, dst, mf); break;
+        case SHIFT: launch_step_fd<St, SHIFT>(c, src, dst, mf); break;
+        default: launch_step_fd<St, LW>(c, src, dst, mf); break;
     }
 }
 
@@ -323,9 +370,15 @@ Mode prop_mode(const lbm_ctx *c) { return c->P.courant == 1.0 ? SHIFT : LW; }
 template <class St, Mode M, bool W>
 void launch_moments(lbm_ctx *c, const FieldOut &o) {
     using R = typename St::R;
-    const DevParams<R> P = make_params<R>(&c->P, c->tc);
-    hipLaunchKernelGGL((moments_kernel<St, M, W>), tile_grid(P), dim3(BLOCK), 0, c->stream,
-                       cbuf_of<St>(c, c->cur ^ 1), P, o);
+    const DevParams<R> P = launch_params<R>(c);
+    if (c->P.normal_fd) {
+        launch_phi<St, M>(c, c->cur ^ 1, MassFix{0, nullptr, nullptr, 0});
+        hipLaunchKernelGGL((moments_kernel<St, M, W, true>), tile_grid(P), dim3(BLOCK), 0,
+                           c->stream, cbuf_of<St>(c, c->cur ^ 1), P, o);
+    } else {
+        hipLaunchKernelGGL((moments_kernel<St, M, W, false>), tile_grid(P), dim3(BLOCK), 0,
+                           c->stream, cbuf_of<St>(c, c->cur ^ 1), P, o);
+    }
 }
 
 template <class St, Mode M>
@@ -468,6 +521,9 @@ int lbm_init(const lbm_params *P, void *d_workspace, size_t bytes, void *stream,
     c->result = (double *)(c->ws + 2 * L.buf_bytes + L.partial_bytes);
     c->flag = (int *)(c->ws + 2 * L.buf_bytes + L.partial_bytes + L.result_bytes);
     c->mf = (double *)(c->ws + 2 * L.buf_bytes + L.partial_bytes + L.result_bytes + L.flag_bytes);
+    c->phifd = L.phifd_bytes ? (void *)(c->ws + 2 * L.buf_bytes + L.partial_bytes + L.result_bytes +
+                                        L.flag_bytes + L.mf_bytes)
+                             : nullptr;
     c->tc = tile_cfg(P);
     c->nblocks = (int)num_tiles(P, c->tc);
     c->mf_pending = false;

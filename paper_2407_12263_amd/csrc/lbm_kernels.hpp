@@ -125,6 +125,7 @@ struct DevParams {
     R scale_f, iscale_f, scale_g, iscale_g;
     R wA_f, wB_f, wD_f;      // 2^-k (A, 1 - c^2, D): the three-tap weights of the stored
     R wA_g, wB_g, wD_g;      // 16-bit deviations with their scale folded in (exact)
+    R *phi_fd;               // phi field of the finite-difference variant (or NULL)
 };
 
 // Linear index of this block in its launch grid (x fastest).
@@ -423,9 +424,9 @@ __device__ __forceinline__ void gather(const Src<St> &src, const Site &s,
                     // the deviations in the weighted form B h0 + A hm + D hp with
                     // the storage scale in the weights (FP16 values enter the
                     // FP32 fmas without a separate conversion)
+                    const R tb = fma(t * P.lwA, ph[o] - ph[0], fma(t * P.lwD, ph[i] - ph[0], t * ph[0]));
                     fb[i] = fma(P.wA_f, fm, fma(P.wD_f, fp, fma(P.wB_f, f0, t * P.rho0)));
-                    gb[i] = fma(P.wA_g, gm, fma(P.wD_g, gp,
-                                fma(P.wB_g, g0, t * lw3(P, ph[o], ph[0], ph[i]))));
+                    gb[i] = fma(P.wA_g, gm, fma(P.wD_g, gp, fma(P.wB_g, g0, tb)));
                 } else {
                     fb[i] = lw_flux(P, fm, f0, fp);
                     gb[i] = lw_flux(P, gm, g0, gp);
@@ -494,9 +495,11 @@ struct Macro {
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
-template <class R>
+// FD: grad(phi) is given (the finite-difference variant) instead of recovered
+// from K1: n = grad/|grad| (0 where grad = 0), S = s n, |grad phi| = |grad|.
+template <bool FD = false, class R>
 __device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)[19],
-                                            const R (&gb)[19]) {
+                                            const R (&gb)[19], const R *gfd = nullptr) {
     Macro<R> m;
     R phi = gb[0], sf = fb[0];
 #pragma unroll
@@ -514,13 +517,27 @@ __device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)
     m.u[0] = fma(P.c, jx, R(0.5) * m.rho * P.G[0]) * irho;
     m.u[1] = fma(P.c, jy, R(0.5) * m.rho * P.G[1]) * irho;
     m.u[2] = fma(P.c, jz, R(0.5) * m.rho * P.G[2]) * irho;
+    const R s = P.four_over_delta * phi * (R(1) - phi);
+    if constexpr (FD) {
+        const R gn = sqrt(fma(gfd[0], gfd[0], fma(gfd[1], gfd[1], gfd[2] * gfd[2])));
+        const R rg = gn > R(0) ? recip(gn) : R(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            m.n[a] = gfd[a] * rg;
+            m.S[a] = s * m.n[a];
+            m.gradrho[a] = P.drho * gfd[a];
+        }
+        m.gnorm = gn;
+        const R ug = fma(m.u[0], m.gradrho[0], fma(m.u[1], m.gradrho[1], m.u[2] * m.gradrho[2]));
+        m.p = P.cs2 * fma(R(0.5), ug, sf);
+        return m;
+    }
     const R K[3] = {fma(P.c, first_moment<0>(gb), -phi * m.u[0]),
                     fma(P.c, first_moment<1>(gb), -phi * m.u[1]),
                     fma(P.c, first_moment<2>(gb), -phi * m.u[2])};
     const R k = sqrt(fma(K[0], K[0], fma(K[1], K[1], K[2] * K[2])));
     const bool has_n = k > P.k1_eps;
     const R rk = has_n ? recip(k) : R(0);
-    const R s = P.four_over_delta * phi * (R(1) - phi);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         m.n[a] = -K[a] * rk;
@@ -600,29 +617,39 @@ __device__ __forceinline__ void collide(const DevParams<R> &P, const Macro<R> &m
                                         const NodeCoef<R> &q, R (&fb)[19], R (&gb)[19]) {
     const R of = m.omega_f, cf = R(1) - R(0.5) * of;
     const R og = P.omega_g;
-    unroll<0, 19>([&](auto I) {
+    auto update = [&](auto I, R A, R B, R Gq) {
         constexpr int i = decltype(I)::value;
-        constexpr int cl = Lat::cls(i);
-        constexpr R t = wgt<R>(cl);
-        R poly, A, B, Gq;
-        if constexpr (i == 0) {
-            poly = -q.a3;
-            A = fma(m.rho, poly, q.A0[0]);
-            B = -poly * q.ug - q.uG * P.inv_cs2;
-            Gq = fma(m.phi, poly, m.phi);
-        } else {
-            const R eu = edot<i>(q.cu);
-            const R en = edot<i>(m.n);
-            const R eg = edot<i>(q.cgr);
-            const R eG = edot<i>(q.crG);
-            const R es = edot<i>(q.tS);
-            poly = fma(eu, fma(eu, P.half_inv_cs4, P.inv_cs2), -q.a3);
-            A = fma(m.rho, poly, fma(q.kpsi * en, en, q.A0[cl]));
-            B = fma(poly, eg - q.ug, fma(eG - q.uG, P.inv_cs2, R(2) * P.half_inv_cs4 * eu * eG));
-            Gq = fma(m.phi, poly, m.phi + es);
-        }
+        constexpr R t = wgt<R>(Lat::cls(i));
         fb[i] = fma(of, fma(t, A, -fb[i]), fma(t * cf, B, fb[i]));
         gb[i] = fma(og, fma(t, Gq, -gb[i]), gb[i]);
+    };
+    {
+        const R poly = -q.a3;
+        update(std::integral_constant<int, 0>{}, fma(m.rho, poly, q.A0[0]),
+               -poly * q.ug - q.uG * P.inv_cs2, fma(m.phi, poly, m.phi));
+    }
+    // the directions come in opposite pairs (i, i + 1) for odd i: every e.v
+    // changes sign across a pair, so poly splits into an even part E and an
+    // odd part O and the pair shares one evaluation of each projection
+    const R uGs = q.uG * P.inv_cs2;
+    unroll<0, 9>([&](auto K) {
+        constexpr int i = 2 * decltype(K)::value + 1;
+        constexpr int cl = Lat::cls(i);
+        const R eu = edot<i>(q.cu);
+        const R en = edot<i>(m.n);
+        const R eg = edot<i>(q.cgr);
+        const R eG = edot<i>(q.crG);
+        const R es = edot<i>(q.tS);
+        const R E = fma(eu * eu, P.half_inv_cs4, -q.a3);
+        const R O = eu * P.inv_cs2;
+        const R pp = E + O, pm = E - O;
+        const R kn = fma(q.kpsi * en, en, q.A0[cl]);
+        const R t1 = fma(R(2) * P.half_inv_cs4 * eu, eG, -uGs);
+        const R eGs = eG * P.inv_cs2;
+        update(std::integral_constant<int, i>{}, fma(m.rho, pp, kn), fma(pp, eg - q.ug, t1 + eGs),
+               fma(m.phi, pp, m.phi + es));
+        update(std::integral_constant<int, i + 1>{}, fma(m.rho, pm, kn),
+               fma(pm, -eg - q.ug, t1 - eGs), fma(m.phi, pm, m.phi - es));
     });
 }
 
@@ -742,9 +769,48 @@ __device__ __forceinline__ R mass_weight(R phi) {
 // launches the wall-free instance (WALLS = false) over the tiles that touch
 // no wall and the wall-aware one over the wall slabs: the wall path's code
 // and registers then cost nothing in the interior.
-template <class St, Mode M, bool WALLS>
-__global__ void __launch_bounds__(BLOCK) step_kernel(CBuf<St> src, Buf<St> dst,
-                                                     DevParams<typename St::R> P, MassFix mf) {
+// The pending phase-mass correction: g_i += t_i c w(phi) before the moments.
+template <class R>
+__device__ __forceinline__ void apply_massfix(const MassFix &mf, R (&gb)[19]) {
+    if (mf.mode & 2) {
+        R phi = gb[0];
+#pragma unroll
+        for (int i = 1; i < 19; ++i) phi += gb[i];
+        const R cw = R(*mf.coef) * mass_weight(phi);
+        unroll<0, 19>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            gb[i] = fma(wgt<R>(Lat::cls(i)), cw, gb[i]);
+        });
+    }
+}
+
+// Isotropic central difference of the stored phi field,
+// grad = 3 sum_i t_i e^_i [phi(x + e^_i) - phi(x - e^_i)]/2, summed over
+// opposite pairs; a neighbour beyond a wall takes the node's own value (the
+// finite-difference scheme the paper compares with, Sec. 3.4).
+template <bool WALLS, class R>
+__device__ __forceinline__ void fd_grad(const DevParams<R> &P, const Site &s, R (&g)[3]) {
+    const R *phi = P.phi_fd;
+    const R p0 = phi[s.n];
+    g[0] = g[1] = g[2] = R(0);
+    unroll<0, 9>([&](auto K) {
+        constexpr int i = 2 * decltype(K)::value + 1;
+        constexpr int o = Lat::OPP[i];
+        R pp = phi[s.nb[i]], pm = phi[s.nb[o]];
+        if constexpr (WALLS) {
+            if (beyond_wall<i, -1>(s)) pp = p0;
+            if (beyond_wall<i, 1>(s)) pm = p0;
+        }
+        const R d = R(3) * wgt<R>(Lat::cls(i)) * (pp - pm);
+        if constexpr (Lat::EX[i] != 0) g[0] += R(Lat::EX[i]) * d;
+        if constexpr (Lat::EY[i] != 0) g[1] += R(Lat::EY[i]) * d;
+        if constexpr (Lat::EZ[i] != 0) g[2] += R(Lat::EZ[i]) * d;
+    });
+}
+
+template <class St, Mode M, bool WALLS, bool FD>
+__device__ __forceinline__ void step_body(const CBuf<St> &src, const Buf<St> &dst,
+                                          const DevParams<typename St::R> &P, const MassFix &mf) {
     using R = typename St::R;
     const Site s = make_site(P);
     double rep_phi = 0.0, rep_w = 0.0;
@@ -757,17 +823,10 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(CBuf<St> src, Buf<St> dst,
         } else {
             gather<M, false, St>(in, s, P, fb, gb);
         }
-        if (mf.mode & 2) {
-            R phi = gb[0];
-#pragma unroll
-            for (int i = 1; i < 19; ++i) phi += gb[i];
-            const R cw = R(*mf.coef) * mass_weight(phi);
-            unroll<0, 19>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                gb[i] = fma(wgt<R>(Lat::cls(i)), cw, gb[i]);
-            });
-        }
-        const Macro<R> m = moments(P, fb, gb);
+        apply_massfix(mf, gb);
+        R gfd[3];
+        if constexpr (FD) fd_grad<WALLS>(P, s, gfd);
+        const Macro<R> m = moments<FD>(P, fb, gb, gfd);
         if (mf.mode & 1) {
             rep_phi = m.phi;
             rep_w = mass_weight(m.phi);
@@ -778,6 +837,41 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(CBuf<St> src, Buf<St> dst,
     }
     if (mf.mode & 1)
         block_sum2(rep_phi, rep_w, mf.partials + 2 * ((size_t)mf.block_off + linear_block()));
+}
+
+template <class St, Mode M, bool WALLS, bool FD>
+__global__ void __launch_bounds__(BLOCK) step_kernel(CBuf<St> src, Buf<St> dst,
+                                                     DevParams<typename St::R> P, MassFix mf) {
+    step_body<St, M, WALLS, FD>(src, dst, P, mf);
+}
+
+// The same step held to 96 VGPRs (5 wavefronts per SIMD) for the 16-bit
+// storage modes, whose registers fit without spilling; at the compiler's own
+// choice (97) they would run 4 per SIMD.
+template <class St, Mode M, bool WALLS, bool FD>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8)))
+step_kernel_o5(CBuf<St> src, Buf<St> dst, DevParams<typename St::R> P, MassFix mf) {
+    step_body<St, M, WALLS, FD>(src, dst, P, mf);
+}
+
+// First pass of the finite-difference variant: phi = sum of the propagated g
+// (with the pending phase-mass correction, as the step applies it) into
+// P.phi_fd, which the step then differences.
+template <class St, Mode M, bool WALLS>
+__global__ void __launch_bounds__(BLOCK) phi_kernel(CBuf<St> src, DevParams<typename St::R> P,
+                                                    MassFix mf) {
+    using R = typename St::R;
+    const Site s = make_site(P);
+    if (!s.valid) return;
+    const Src<St> in = make_src(src, P);
+    R fb[19], gb[19];
+    if (WALLS && __any(s.wall)) gather<M, WALLS, St>(in, s, P, fb, gb);
+    else gather<M, false, St>(in, s, P, fb, gb);
+    apply_massfix(mf, gb);
+    R phi = gb[0];
+#pragma unroll
+    for (int i = 1; i < 19; ++i) phi += gb[i];
+    P.phi_fd[s.n] = phi;
 }
 
 // Sums the per-block pairs in a fixed order (1024 threads, each a strided
@@ -831,7 +925,7 @@ struct FieldOut {
 
 // Moments of the state at t (propagation mode M from the previous buffer):
 // fields, FP64 PDFs and/or per-block FP64 partial sums of the diagnostics.
-template <class St, Mode M, bool WALLS>
+template <class St, Mode M, bool WALLS, bool FD>
 __global__ void __launch_bounds__(BLOCK) moments_kernel(CBuf<St> src, DevParams<typename St::R> P,
                                                         FieldOut out) {
     using R = typename St::R;
@@ -846,7 +940,9 @@ __global__ void __launch_bounds__(BLOCK) moments_kernel(CBuf<St> src, DevParams<
         R fb[19], gb[19];
         if (WALLS && __any(s.wall)) gather<M, WALLS, St>(in, s, P, fb, gb);
         else gather<M, false, St>(in, s, P, fb, gb);
-        const Macro<R> m = moments(P, fb, gb);
+        R gfd[3];
+        if constexpr (FD) fd_grad<WALLS>(P, s, gfd);
+        const Macro<R> m = moments<FD>(P, fb, gb, gfd);
         const size_t N = (size_t)P.N, n = s.n;
         if (out.phi) {
             if (out.dtype == 0) ((double *)out.phi)[n] = m.phi;

@@ -33,6 +33,7 @@ class LbmParams(C.Structure):
                 ("store_log2", C.c_int32 * 2),
                 ("check_every", C.c_int32),
                 ("mass_fix_every", C.c_int32),
+                ("normal_fd", C.c_int32),
                 ("courant", C.c_double),
                 ("rho1", C.c_double), ("rho2", C.c_double),
                 ("tau_rho1", C.c_double), ("tau_rho2", C.c_double),
@@ -106,7 +107,7 @@ def _check(rc: int, where: str):
 def make_params(nx, ny, nz, precision="fp32", wall=(0, 0, 0), courant=0.997, rho1=1.0,
                 rho2=1.0, tau_rho1=0.3, tau_rho2=0.3, tau_phi=0.3, sigma=0.0, delta=4.0,
                 G=(0.0, 0.0, 0.0), k1_eps=1e-5, p_ref=0.0, store_log2=(10, 10),
-                check_every=0, mass_fix_every=None) -> LbmParams:
+                check_every=0, mass_fix_every=None, normal_fd=0) -> LbmParams:
     """mass_fix_every: None picks 10 for FP32 and 16-bit storage (FP32 rounding
     alone drifts the phase mass by ~1e-8 of it per step on a quasi-steady
     interface), 0 for FP64."""
@@ -121,6 +122,7 @@ def make_params(nx, ny, nz, precision="fp32", wall=(0, 0, 0), courant=0.997, rho
     if mass_fix_every is None:
         mass_fix_every = 0 if p.precision == PRECISIONS["fp64"] else 10
     p.mass_fix_every = int(mass_fix_every)
+    p.normal_fd = int(normal_fd)
     p.courant = float(courant)
     p.rho1, p.rho2 = float(rho1), float(rho2)
     p.tau_rho1, p.tau_rho2 = float(tau_rho1), float(tau_rho2)

@@ -52,7 +52,8 @@ def test_workspace_bytes_and_validation(lib):
     assert 2 * (2 * 19 * N * 2 + 4 * N) <= n16 < n32
     bad = [dict(courant=1.5), dict(courant=0.0), dict(tau_phi=0.0), dict(rho1=-1.0),
            dict(delta=0.0), dict(wall=(0, 0, 2)), dict(precision=7), dict(sigma=-1.0),
-           dict(k1_eps=-1.0), dict(store_log2=(30, 0)), dict(G=(float("nan"), 0, 0))]
+           dict(k1_eps=-1.0), dict(store_log2=(30, 0)), dict(G=(float("nan"), 0, 0)),
+           dict(normal_fd=2)]
     for kw in bad:
         with pytest.raises(lib.LbmError) as ei:
             lib.lbm_workspace_bytes(lib.make_params(8, 8, 8, **kw))

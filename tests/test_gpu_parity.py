@@ -114,6 +114,34 @@ def test_fp64_walls_all_faces_small_box():
     _cmp(w, "fp64", 50, 1e-12, 1e-13, 1e-13)
 
 
+# ------------------------------- the finite-difference-normal variant (Sec. 3.4)
+
+@pytest.mark.parametrize("name,steps", [("droplet", 100), ("bubble", 50), ("tg", 50),
+                                        ("ragged", 30), ("rt", 10)])
+def test_fd_variant_fp64_trajectory(name, steps):
+    """The comparison scheme: grad(phi) by isotropic central differences of
+    the phi field (a second pass per step), against the oracle's same mode."""
+    w = inputs.static_droplet() if name == "droplet" else SMALL[name]()
+    _cmp(w, "fp64", steps, 1e-12, 1e-13, 1e-13, normal_fd=1)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp16", 2e-3), ("bf16", 2e-3)])
+def test_fd_variant_reduced_precision(prec, tol):
+    _cmp(inputs.static_droplet(), prec, 100, tol, normal_fd=1)
+
+
+def test_fd_variant_differs_from_difference_free():
+    """The two ways of obtaining grad(phi) give different (both valid) runs."""
+    w = inputs.static_droplet()
+    a = gpu_solver(w, "fp64")
+    b = gpu_solver(w, "fp64", normal_fd=1)
+    a.step(50)
+    b.step(50)
+    d = np.abs(gpu_fields(a)[0] - gpu_fields(b)[0]).max()
+    say(f"[fd] difference-free vs FD after 50 steps: max|dphi| = {d:.2e}")
+    assert d > 1e-8
+
+
 @pytest.mark.parametrize("name", ["rt", "bubble", "tg", "ragged"])
 @pytest.mark.parametrize("courant", [0.997, 1.0])
 def test_one_step_parity_from_oracle_state(name, courant):
