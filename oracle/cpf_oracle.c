@@ -149,14 +149,15 @@ static void gradient_from_K1(const orc_params *P, double phi, const double K1[3]
 }
 
 /* Normal, S and |grad phi| from a given gradient (finite-difference variant,
- * n = grad(phi)/|grad(phi)|, and the initial state). */
+ * n = grad(phi)/|grad(phi)|, and the initial state). As for K1, the direction
+ * of a vanishing gradient is undefined: n = 0 where |grad phi| <= k1_eps. */
 static void gradient_given(const orc_params *P, double phi, const double gp[3], macro_t *m)
 {
     const double gn = sqrt(gp[0] * gp[0] + gp[1] * gp[1] + gp[2] * gp[2]);
     const double s = 4.0 * phi * (1.0 - phi) / P->delta;
     for (int a = 0; a < 3; ++a) {
         m->gradphi[a] = gp[a];
-        m->n[a] = (gn > 0.0) ? gp[a] / gn : 0.0;
+        m->n[a] = (gn > P->k1_eps) ? gp[a] / gn : 0.0;
         m->S[a] = s * m->n[a];
     }
     m->gnorm = gn;

@@ -271,7 +271,7 @@ template <class St, Mode M, bool W, bool FD>
 void launch_step(lbm_ctx *c, int src, int dst, const DevParams<typename St::R> &P, MassFix mf,
                  int &block_off) {
     mf.block_off = block_off;
-    if constexpr (St::DEV)
+    if constexpr (St::DEV && !W && !FD)
         hipLaunchKernelGGL((step_kernel_o5<St, M, W, FD>), tile_grid(P), dim3(BLOCK), 0,
                            c->stream, cbuf_of<St>(c, src), buf_of<St>(c, dst), P, mf);
     else

@@ -371,8 +371,8 @@ __device__ __forceinline__ R lw_wall(const DevParams<R> &P, R am, R a0, R ap, R 
     return a0 + (fin - fout);
 }
 
-// Gathers the post-propagation f and g of one node. WALLS selects the
-// wall-aware path (used only by wavefronts that contain a wall node).
+// Gathers the post-propagation f and g of one node. WALLS adds the
+// wall-aware recomputation (used only by wavefronts that contain a wall node).
 template <Mode M, bool WALLS, class St>
 __device__ __forceinline__ void gather(const Src<St> &src, const Site &s,
                                        const DevParams<typename St::R> &P,
@@ -403,7 +403,7 @@ __device__ __forceinline__ void gather(const Src<St> &src, const Site &s,
                 fb[i] = hf;
                 gb[i] = hg;
             }
-        } else if constexpr (!WALLS) {
+        } else {
             const R fm = raw<St, i>(src.f, src, s, o);
             const R gm = raw<St, i>(src.g, src, s, o);
             if constexpr (M == SHIFT) {
@@ -432,46 +432,42 @@ __device__ __forceinline__ void gather(const Src<St> &src, const Site &s,
                     gb[i] = lw_flux(P, gm, g0, gp);
                 }
             }
-        } else {
-            // wall-aware: the wall-free result for nodes whose taps are all
-            // inside, the flux form with bounce-back for populations that
-            // cross a wall face (full values of the taps and of the opposite
-            // population at the node)
-            const bool up = beyond_wall<i, 1>(s), dn = beyond_wall<i, -1>(s);
-            const R hfm = raw<St, i>(src.f, src, s, o), hgm = raw<St, i>(src.g, src, s, o);
-            const R hfo = raw<St, o>(src.f, src, s, 0), hgo = raw<St, o>(src.g, src, s, 0);
-            auto full_f = [&](R h) -> R {
-                if constexpr (St::DEV) return fma(P.iscale_f, h, t * P.rho0);
-                else return h;
-            };
-            auto full_g = [&](R h, R phs) -> R {
-                if constexpr (St::DEV) return fma(P.iscale_g, h, t * phs);
-                else return h;
-            };
-            if constexpr (M == SHIFT) {
-                fb[i] = up ? full_f(hfo) : full_f(hfm);
-                gb[i] = up ? full_g(hgo, ph[0]) : full_g(hgm, ph[o]);
-            } else {
-                const R hf0 = raw<St, i>(src.f, src, s, 0), hfp = raw<St, i>(src.f, src, s, i);
-                const R hg0 = raw<St, i>(src.g, src, s, 0), hgp = raw<St, i>(src.g, src, s, i);
-                R ff, gg;
-                if constexpr (St::DEV) {
-                    ff = fma(P.iscale_f, lw3(P, hfm, hf0, hfp), t * P.rho0);
-                    gg = fma(P.iscale_g, lw3(P, hgm, hg0, hgp), t * lw3(P, ph[o], ph[0], ph[i]));
-                } else {
-                    ff = lw_flux(P, hfm, hf0, hfp);
-                    gg = lw_flux(P, hgm, hg0, hgp);
-                }
-                if (up || dn) {
-                    ff = lw_wall(P, full_f(hfm), full_f(hf0), full_f(hfp), full_f(hfo), up, dn);
-                    gg = lw_wall(P, full_g(hgm, ph[o]), full_g(hg0, ph[0]), full_g(hgp, ph[i]),
-                                 full_g(hgo, ph[0]), up, dn);
-                }
-                fb[i] = ff;
-                gb[i] = gg;
-            }
         }
     });
+    if constexpr (WALLS && M != LOCAL) {
+        // wall-aware: the populations whose taps cross a wall face are
+        // recomputed, on the lanes where they do, in flux form with
+        // bounce-back from the full values of the taps and of the opposite
+        // population at the node (the wall-free values above stand elsewhere)
+        unroll<1, 19>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int o = Lat::OPP[i];
+            constexpr R t = wgt<R>(Lat::cls(i));
+            const bool up = beyond_wall<i, 1>(s), dn = beyond_wall<i, -1>(s);
+            if (up || dn) {
+                auto full_f = [&](R h) -> R {
+                    if constexpr (St::DEV) return fma(P.iscale_f, h, t * P.rho0);
+                    else return h;
+                };
+                auto full_g = [&](R h, R phs) -> R {
+                    if constexpr (St::DEV) return fma(P.iscale_g, h, t * phs);
+                    else return h;
+                };
+                const R hfm = raw<St, i>(src.f, src, s, o), hgm = raw<St, i>(src.g, src, s, o);
+                const R hfo = raw<St, o>(src.f, src, s, 0), hgo = raw<St, o>(src.g, src, s, 0);
+                if constexpr (M == SHIFT) {
+                    fb[i] = up ? full_f(hfo) : full_f(hfm);
+                    gb[i] = up ? full_g(hgo, ph[0]) : full_g(hgm, ph[o]);
+                } else {
+                    const R hf0 = raw<St, i>(src.f, src, s, 0), hfp = raw<St, i>(src.f, src, s, i);
+                    const R hg0 = raw<St, i>(src.g, src, s, 0), hgp = raw<St, i>(src.g, src, s, i);
+                    fb[i] = lw_wall(P, full_f(hfm), full_f(hf0), full_f(hfp), full_f(hfo), up, dn);
+                    gb[i] = lw_wall(P, full_g(hgm, ph[o]), full_g(hg0, ph[0]), full_g(hgp, ph[i]),
+                                    full_g(hgo, ph[0]), up, dn);
+                }
+            }
+        });
+    }
 }
 
 // --------------------------------------------------------------- moments
@@ -496,7 +492,8 @@ __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 // FD: grad(phi) is given (the finite-difference variant) instead of recovered
-// from K1: n = grad/|grad| (0 where grad = 0), S = s n, |grad phi| = |grad|.
+// from K1: n = grad/|grad| (0 where |grad| <= k1_eps, as for K1), S = s n,
+// |grad phi| = |grad|.
 template <bool FD = false, class R>
 __device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)[19],
                                             const R (&gb)[19], const R *gfd = nullptr) {
@@ -520,7 +517,7 @@ __device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)
     const R s = P.four_over_delta * phi * (R(1) - phi);
     if constexpr (FD) {
         const R gn = sqrt(fma(gfd[0], gfd[0], fma(gfd[1], gfd[1], gfd[2] * gfd[2])));
-        const R rg = gn > R(0) ? recip(gn) : R(0);
+        const R rg = gn > P.k1_eps ? recip(gn) : R(0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             m.n[a] = gfd[a] * rg;
@@ -765,7 +762,8 @@ __device__ __forceinline__ R mass_weight(R phi) {
 }
 
 // Fused step: propagate (mode M) from src, moments, collide, store to dst.
-// Wavefronts without a wall node take the wall-free propagation. The host
+// The wall-aware instance recomputes only the populations that cross a wall,
+// on the lanes where they do. The host
 // launches the wall-free instance (WALLS = false) over the tiles that touch
 // no wall and the wall-aware one over the wall slabs: the wall path's code
 // and registers then cost nothing in the interior.
@@ -817,12 +815,7 @@ __device__ __forceinline__ void step_body(const CBuf<St> &src, const Buf<St> &ds
     if (s.valid) {
         const Src<St> in = make_src(src, P);
         R fb[19], gb[19];
-        if constexpr (WALLS) {
-            if (__any(s.wall)) gather<M, true, St>(in, s, P, fb, gb);
-            else gather<M, false, St>(in, s, P, fb, gb);
-        } else {
-            gather<M, false, St>(in, s, P, fb, gb);
-        }
+        gather<M, WALLS, St>(in, s, P, fb, gb);
         apply_massfix(mf, gb);
         R gfd[3];
         if constexpr (FD) fd_grad<WALLS>(P, s, gfd);
@@ -845,9 +838,9 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(CBuf<St> src, Buf<St> dst,
     step_body<St, M, WALLS, FD>(src, dst, P, mf);
 }
 
-// The same step held to 96 VGPRs (5 wavefronts per SIMD) for the 16-bit
-// storage modes, whose registers fit without spilling; at the compiler's own
-// choice (97) they would run 4 per SIMD.
+// The same step held to 96 VGPRs (5 wavefronts per SIMD) for the wall-free
+// 16-bit storage step, whose registers fit without spilling; at the
+// compiler's own choice (97) it would run 4 per SIMD.
 template <class St, Mode M, bool WALLS, bool FD>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8)))
 step_kernel_o5(CBuf<St> src, Buf<St> dst, DevParams<typename St::R> P, MassFix mf) {
@@ -865,8 +858,7 @@ __global__ void __launch_bounds__(BLOCK) phi_kernel(CBuf<St> src, DevParams<type
     if (!s.valid) return;
     const Src<St> in = make_src(src, P);
     R fb[19], gb[19];
-    if (WALLS && __any(s.wall)) gather<M, WALLS, St>(in, s, P, fb, gb);
-    else gather<M, false, St>(in, s, P, fb, gb);
+    gather<M, WALLS, St>(in, s, P, fb, gb);
     apply_massfix(mf, gb);
     R phi = gb[0];
 #pragma unroll
@@ -938,8 +930,7 @@ __global__ void __launch_bounds__(BLOCK) moments_kernel(CBuf<St> src, DevParams<
     if (s.valid) {
         const Src<St> in = make_src(src, P);
         R fb[19], gb[19];
-        if (WALLS && __any(s.wall)) gather<M, WALLS, St>(in, s, P, fb, gb);
-        else gather<M, false, St>(in, s, P, fb, gb);
+        gather<M, WALLS, St>(in, s, P, fb, gb);
         R gfd[3];
         if constexpr (FD) fd_grad<WALLS>(P, s, gfd);
         const Macro<R> m = moments<FD>(P, fb, gb, gfd);
@@ -1093,7 +1084,7 @@ __device__ __forceinline__ void init_node(const double *phi0, const double *u0, 
     const double s4 = P.four_over_delta * ph0 * (1.0 - ph0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        m.n[a] = gn > 0.0 ? g[a] / gn : 0.0;
+        m.n[a] = gn > P.k1_eps ? g[a] / gn : 0.0;
         m.S[a] = s4 * m.n[a];
         m.gradrho[a] = P.drho * g[a];
     }

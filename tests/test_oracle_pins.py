@@ -430,17 +430,20 @@ def test_k1_gradient_matches_fd_to_second_order(orc):
     assert 2.8 < ratio < 5.6, gaps
 
 
-def test_k1_floor_bounds_rounding_sensitivity(orc):
+@pytest.mark.parametrize("normal_fd", [0, 1])
+def test_k1_floor_bounds_rounding_sensitivity(orc, normal_fd):
     """On the static-droplet configuration (32^3, R = 8, W = 4) a perturbation
     of the state at the 1e-15 level stays below 1e-12 after 100 steps with the
-    K1 floor; without it the noise-direction normals where grad(phi) vanishes
-    (droplet centre, box faces) amplify it to about 1e-4. This is the
-    conditioning that makes FP64 parity at 1e-12 meaningful."""
+    floor on the normal (|K1| <= k1_eps, or |grad phi| <= k1_eps in the
+    finite-difference variant); without it the noise-direction normals where
+    grad(phi) vanishes (droplet centre, box faces) amplify it to about 1e-4.
+    This is the conditioning that makes FP64 parity at 1e-12 meaningful."""
     w = inputs.static_droplet()
     res = {}
     for eps in (1e-5, 0.0):
         prm = w.params()
         prm["k1_eps"] = eps
+        prm["normal_fd"] = normal_fd
         P = orc.OracleParams(**prm)
         a = orc.Oracle(P, w.phi0, w.u0, w.p0)
         b = orc.Oracle(P, w.phi0, w.u0, w.p0)
