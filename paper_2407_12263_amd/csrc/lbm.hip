@@ -116,7 +116,9 @@ int validate(const lbm_params *P) {
     if (19.0 * N >= 2147483647.0) return LBM_EINVAL;
     if (P->precision < LBM_FP64 || P->precision > LBM_FP32_BF16STORE) return LBM_EINVAL;
     // every population field is addressed through one 32-bit buffer range
-    if (19.0 * N * (double)elem_bytes(P->precision) >= 4294967295.0) return LBM_EINVAL;
+    // (16-bit storage keeps f and g of a population in one 32-bit plane)
+    const double plane_elem = P->precision >= LBM_FP32_FP16STORE ? 4.0 : (double)elem_bytes(P->precision);
+    if (19.0 * N * plane_elem >= 4294967295.0) return LBM_EINVAL;
     const int nn[3] = {P->nx, P->ny, P->nz};
     for (int a = 0; a < 3; ++a) {
         if (P->wall[a] != 0 && P->wall[a] != 1) return LBM_EINVAL;

@@ -322,21 +322,36 @@ struct Src {
 template <class St>
 __device__ __forceinline__ Src<St> make_src(const CBuf<St> &b, const DevParams<typename St::R> &P) {
     Src<St> s;
-    const uint32_t plane = (uint32_t)P.N * (uint32_t)sizeof(typename St::T);
+    // 16-bit storage keeps f_i and g_i of a node together in one 32-bit word
+    // (f in the low half): one load per tap serves both fields
+    const uint32_t plane = (uint32_t)P.N * (uint32_t)(St::DEV ? 4 : sizeof(typename St::T));
     s.plane = plane;
     s.f = make_rsrc(b.f, 19u * plane);
-    s.g = make_rsrc(b.g, 19u * plane);
+    s.g = St::DEV ? s.f : make_rsrc(b.g, 19u * plane);
     s.phis = make_rsrc(b.phis, St::DEV ? (uint32_t)P.N * 4u : 0u);
     return s;
 }
 
-// raw stored value of population i at stencil node j
+// Stored values of population i of f and g at stencil node j (16-bit
+// storage: the decoded deviations).
 template <class St, int i>
-__device__ __forceinline__ typename St::R raw(rsrc_t r, const Src<St> &src, const Site &s, int j) {
+__device__ __forceinline__ void rawfg(const Src<St> &src, const Site &s, int j, typename St::R &f,
+                                      typename St::R &g) {
     using T = typename St::T;
-    const T v = bload<T>(r, s.nb[j] * (uint32_t)sizeof(T), (uint32_t)i * src.plane);
-    if constexpr (St::DEV) return decode<St>(v);
-    else return typename St::R(v);
+    using R = typename St::R;
+    if constexpr (St::DEV) {
+        const uint32_t w = bload<uint32_t>(src.f, s.nb[j] * 4u, (uint32_t)i * src.plane);
+        if constexpr (std::is_same_v<St, SB16>) {
+            f = __uint_as_float(w << 16);
+            g = __uint_as_float(w & 0xffff0000u);
+        } else {
+            f = R(__builtin_bit_cast(_Float16, uint16_t(w)));
+            g = R(__builtin_bit_cast(_Float16, uint16_t(w >> 16)));
+        }
+    } else {
+        f = R(bload<T>(src.f, s.nb[j] * (uint32_t)sizeof(T), (uint32_t)i * src.plane));
+        g = R(bload<T>(src.g, s.nb[j] * (uint32_t)sizeof(T), (uint32_t)i * src.plane));
+    }
 }
 
 // Lax-Wendroff step of one population from its three taps (Sec. 2.2):
@@ -394,8 +409,8 @@ __device__ __forceinline__ void gather(const Src<St> &src, const Site &s,
         constexpr int o = Lat::OPP[i];
         constexpr R t = wgt<R>(Lat::cls(i));
         if constexpr (M == LOCAL || i == 0) {
-            const R hf = raw<St, i>(src.f, src, s, 0);
-            const R hg = raw<St, i>(src.g, src, s, 0);
+            R hf, hg;
+            rawfg<St, i>(src, s, 0, hf, hg);
             if constexpr (St::DEV) {
                 fb[i] = fma(P.iscale_f, hf, t * P.rho0);
                 gb[i] = fma(P.iscale_g, hg, t * ph[0]);
@@ -404,8 +419,8 @@ __device__ __forceinline__ void gather(const Src<St> &src, const Site &s,
                 gb[i] = hg;
             }
         } else {
-            const R fm = raw<St, i>(src.f, src, s, o);
-            const R gm = raw<St, i>(src.g, src, s, o);
+            R fm, gm;
+            rawfg<St, i>(src, s, o, fm, gm);
             if constexpr (M == SHIFT) {
                 if constexpr (St::DEV) {
                     fb[i] = fma(P.iscale_f, fm, t * P.rho0);
@@ -415,10 +430,9 @@ __device__ __forceinline__ void gather(const Src<St> &src, const Site &s,
                     gb[i] = gm;
                 }
             } else {
-                const R f0 = raw<St, i>(src.f, src, s, 0);
-                const R fp = raw<St, i>(src.f, src, s, i);
-                const R g0 = raw<St, i>(src.g, src, s, 0);
-                const R gp = raw<St, i>(src.g, src, s, i);
+                R f0, fp, g0, gp;
+                rawfg<St, i>(src, s, 0, f0, g0);
+                rawfg<St, i>(src, s, i, fp, gp);
                 if constexpr (St::DEV) {
                     // propagate the stored deviations and the phi_s bases apart;
                     // the deviations in the weighted form B h0 + A hm + D hp with
@@ -453,14 +467,16 @@ __device__ __forceinline__ void gather(const Src<St> &src, const Site &s,
                     if constexpr (St::DEV) return fma(P.iscale_g, h, t * phs);
                     else return h;
                 };
-                const R hfm = raw<St, i>(src.f, src, s, o), hgm = raw<St, i>(src.g, src, s, o);
-                const R hfo = raw<St, o>(src.f, src, s, 0), hgo = raw<St, o>(src.g, src, s, 0);
+                R hfm, hgm, hfo, hgo;
+                rawfg<St, i>(src, s, o, hfm, hgm);
+                rawfg<St, o>(src, s, 0, hfo, hgo);
                 if constexpr (M == SHIFT) {
                     fb[i] = up ? full_f(hfo) : full_f(hfm);
                     gb[i] = up ? full_g(hgo, ph[0]) : full_g(hgm, ph[o]);
                 } else {
-                    const R hf0 = raw<St, i>(src.f, src, s, 0), hfp = raw<St, i>(src.f, src, s, i);
-                    const R hg0 = raw<St, i>(src.g, src, s, 0), hgp = raw<St, i>(src.g, src, s, i);
+                    R hf0, hfp, hg0, hgp;
+                    rawfg<St, i>(src, s, 0, hf0, hg0);
+                    rawfg<St, i>(src, s, i, hfp, hgp);
                     fb[i] = lw_wall(P, full_f(hfm), full_f(hf0), full_f(hfp), full_f(hfo), up, dn);
                     gb[i] = lw_wall(P, full_g(hgm, ph[o]), full_g(hg0, ph[0]), full_g(hgp, ph[i]),
                                     full_g(hgo, ph[0]), up, dn);
@@ -661,10 +677,10 @@ struct Dst {
 template <class St>
 __device__ __forceinline__ Dst<St> make_dst(const Buf<St> &b, const DevParams<typename St::R> &P) {
     Dst<St> d;
-    const uint32_t plane = (uint32_t)P.N * (uint32_t)sizeof(typename St::T);
+    const uint32_t plane = (uint32_t)P.N * (uint32_t)(St::DEV ? 4 : sizeof(typename St::T));
     d.plane = plane;
     d.f = make_rsrc(b.f, 19u * plane);
-    d.g = make_rsrc(b.g, 19u * plane);
+    d.g = St::DEV ? d.f : make_rsrc(b.g, 19u * plane);
     d.phis = make_rsrc(b.phis, St::DEV ? (uint32_t)P.N * 4u : 0u);
     return d;
 }
@@ -676,7 +692,7 @@ __device__ __forceinline__ void store(const Dst<St> &dst, uint32_t n,
                                       const typename St::R (&gs)[19]) {
     using R = typename St::R;
     using T = typename St::T;
-    const uint32_t voff = n * (uint32_t)sizeof(T);
+    const uint32_t voff = n * (uint32_t)(St::DEV ? 4 : sizeof(T));
     if constexpr (!St::DEV) {
         unroll<0, 19>([&](auto I) {
             constexpr int i = decltype(I)::value;
@@ -695,8 +711,9 @@ __device__ __forceinline__ void store(const Dst<St> &dst, uint32_t n,
             const R dg = fma(-t, phi_a, gs[i]);
             const T hg = encode<St>(P.scale_g * dg);
             resid += fma(-P.iscale_g, decode<St>(hg), dg);
-            bstore<T>(hf, dst.f, voff, (uint32_t)i * dst.plane);
-            bstore<T>(hg, dst.g, voff, (uint32_t)i * dst.plane);
+            const uint32_t w = uint32_t(__builtin_bit_cast(uint16_t, hf)) |
+                               (uint32_t(__builtin_bit_cast(uint16_t, hg)) << 16);
+            bstore<uint32_t>(w, dst.f, voff, (uint32_t)i * dst.plane);
         });
         // sum_i (t_i phi_s + 2^-k h_i) = sum_i g*_i: the storage rounding of g
         // is absorbed by phi_s, so the node keeps its phase mass
