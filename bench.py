@@ -55,7 +55,8 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(launch_bytes_alg: float):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    """HBM bytes per step (FETCH_SIZE and WRITE_SIZE of the step's launches,
+    calibrated on a plain copy) from the committed rocprofv3 counter summary,
     or None when the kernel source changed since the counters were taken."""
     path = os.path.join(ROOT, COUNTERS_FILE)
     if not os.path.exists(path):
@@ -69,7 +70,7 @@ def measured_traffic(launch_bytes_alg: float):
     if kv.get("source_hash") != kernel_source_hash():
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv["hbm_bytes_per_step"])
     except (KeyError, ValueError):
         return None
 
@@ -175,8 +176,9 @@ def main():
                    "walls": "y", "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes_per_launch": launch_bytes,
-                     "kernel": "step_kernel (fused propagate+moments+collide+store)"},
+                     "traffic": traffic, "algorithmic_bytes_per_step": launch_bytes,
+                     "kernel": "step_kernel (fused propagate+moments+collide+store; interior "
+                               "and wall-slab launches)"},
         "secondary": {m: {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 5),
                           "hbm_frac": round(lbm.BYTES_PER_LU[m.split("+")[0]] * w.N
                                             / (r["seconds"] / args.steps) / 1e9 / HBM_PEAK_GBS, 4)}

@@ -46,12 +46,10 @@ TileCfg tile_cfg(const lbm_params *P) {
     while ((1 << l) < P->nx && l < 7) ++l;
     t.tx_log2 = env_int("LBM_TILE_X_LOG2", l);
     if (t.tx_log2 < 0 || t.tx_log2 > 8) t.tx_log2 = l;
-    // FP32/FP64 storage is bound by HBM and gains from the z-banded order
-    // (the y/z taps of a band of 32 tile rows stay in L2: 14.6 against 13.9
-    // GLUPS in FP32 on RT); the 16-bit step is bound by issue and latency and
-    // keeps the plain order, whose launch grid needs no division
-    const bool s16 = P->precision == LBM_FP32_FP16STORE || P->precision == LBM_FP32_BF16STORE;
-    const int dflt_order = s16 ? 0 : 2;
+    // default: XCD runs of the z-banded order with bands of 32 tile rows (the
+    // y/z taps of a band stay in L2; on RT: FP32 14.6 against 13.9 GLUPS and
+    // FP16 25.6 against 24.3 in the plain order)
+    const int dflt_order = 2;
     t.order = env_int("LBM_TILE_ORDER", dflt_order);
     if (t.order < 0 || t.order > 2) t.order = dflt_order;
     t.band = env_int("LBM_TILE_BAND", 32);
@@ -142,6 +140,29 @@ int validate(const lbm_params *P) {
     return LBM_OK;
 }
 
+FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f{0u, 0u, d < 1u ? 1u : d};
+    if (f.d == 1u) return f;
+    uint32_t l = 0;
+    while ((1ull << l) < f.d) ++l;  // 2^(l-1) < d <= 2^l
+    const unsigned __int128 num = (unsigned __int128)1 << (31 + l);
+    f.m = (uint32_t)((num + f.d - 1) / f.d);
+    f.s = l - 1;
+    return f;
+}
+
+// Divisors of the tile decomposition of a launch box.
+template <class R>
+void set_divisors(DevParams<R> &d) {
+    d.nfull = d.bnty / d.band;
+    const int rem = d.bnty - d.nfull * d.band;
+    d.d_ntx = make_fastdiv((uint32_t)d.ntx);
+    d.d_nty = make_fastdiv((uint32_t)d.bnty);
+    d.d_band = make_fastdiv((uint32_t)d.band);
+    d.d_perband = make_fastdiv((uint32_t)(d.band * d.bnz));
+    d.d_rem = make_fastdiv((uint32_t)(rem > 0 ? rem : 1));
+}
+
 template <class R>
 DevParams<R> make_params(const lbm_params *P, const TileCfg &tc) {
     DevParams<R> d;
@@ -164,6 +185,7 @@ DevParams<R> make_params(const lbm_params *P, const TileCfg &tc) {
     d.bnz = P->nz;
     d.bty_step = 1;
     d.btz_step = 1;
+    set_divisors(d);
     const double c = P->courant, cs2 = c * c / 3.0;
     const double eta1 = P->rho1 * cs2 * P->tau_rho1, eta2 = P->rho2 * cs2 * P->tau_rho2;
     d.c = R(c);
@@ -271,6 +293,7 @@ DevParams<R> with_box(DevParams<R> d, int ty0, int nty, int tz0, int nz, int ban
     d.band = band < nty ? band : nty;
     d.xq = d.ntiles / 8;
     d.xr = d.ntiles % 8;
+    set_divisors(d);
     return d;
 }
 

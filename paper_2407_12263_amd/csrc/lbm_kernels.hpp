@@ -99,6 +99,17 @@ __device__ __forceinline__ R edot(const R (&v)[3]) {
 // of one z-plane.
 constexpr int BLOCK = 256;
 
+// Division by a launch constant d for dividends below 2^31 (Granlund and
+// Montgomery, 1994): q = floor(n m / 2^(31 + l)) with 2^(l-1) < d <= 2^l and
+// m = ceil(2^(31 + l)/d) < 2^32; d = 1 is passed through.
+struct FastDiv {
+    uint32_t m, s, d;
+};
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f) {
+    return f.d == 1u ? n : (__umulhi(n, f.m) >> f.s);
+}
+
 template <class R>
 struct DevParams {
     int nx, ny, nz, N;
@@ -111,6 +122,8 @@ struct DevParams {
     int bty0, bnty, btz0, bnz;  // tile rows bty0 + k bty_step (k < bnty) x planes
     int bty_step, btz_step;     // btz0 + k btz_step (k < bnz) covered by one launch
                                 // (ntiles = ntx bnty bnz)
+    int nfull;                  // full bands of the z-banded order: bnty / band
+    FastDiv d_ntx, d_nty, d_band, d_perband, d_rem;  // divisors of the tile decomposition
     R c, h;                  // Courant number, c(1-c)/2
     R lwA, lwD;              // Lax-Wendroff weights of x-e and x+e: c(1+c)/2, -c(1-c)/2
     R cs2, inv_cs2, half_inv_cs4;
@@ -229,9 +242,11 @@ __device__ __forceinline__ Site make_site(const DevParams<R> &P) {
     const uint32_t b = blockIdx.x;
     uint32_t t = b;
     if (P.order == 0) {
-        // the launch grid is (ntx, bnty, bnz): no division
+        // the launch grid is (ntx, bnty, bnz)
         t = 0;
     } else {
+        // XCD runs: block b runs on XCD b mod 8; the XCD's blocks take one
+        // contiguous run of tiles
         const uint32_t xcd = b & 7u, slot = b >> 3;
         const uint32_t q = (uint32_t)P.xq, r = (uint32_t)P.xr;
         t = (xcd < r ? xcd * (q + 1u) : r * (q + 1u) + (xcd - r) * q) + slot;
@@ -244,24 +259,24 @@ __device__ __forceinline__ Site make_site(const DevParams<R> &P) {
         ty = blockIdx.y;
         tz = blockIdx.z;
     } else {
-        tx = t % ntx;
-        rr = t / ntx;
+        rr = fdiv(t, P.d_ntx);
+        tx = t - rr * ntx;
     }
     if (P.order == 0) {
     } else if (P.order == 2) {
-        const uint32_t bw = (uint32_t)P.band, full = nty / bw, per_band = bw * nz;
+        const uint32_t bw = (uint32_t)P.band, full = (uint32_t)P.nfull, per_band = bw * nz;
         if (rr < full * per_band) {
-            const uint32_t k = rr / per_band, w = rr - k * per_band;
-            tz = w / bw;
+            const uint32_t k = fdiv(rr, P.d_perband), w = rr - k * per_band;
+            tz = fdiv(w, P.d_band);
             ty = k * bw + (w - tz * bw);
         } else {
             const uint32_t rem = nty - full * bw, w = rr - full * per_band;
-            tz = w / rem;
+            tz = fdiv(w, P.d_rem);
             ty = full * bw + (w - tz * rem);
         }
     } else {
-        ty = rr % nty;
-        tz = rr / nty;
+        tz = fdiv(rr, P.d_nty);
+        ty = rr - tz * nty;
     }
     ty = (uint32_t)P.bty0 + ty * (uint32_t)P.bty_step;
     tz = (uint32_t)P.btz0 + tz * (uint32_t)P.btz_step;
