@@ -319,18 +319,34 @@ DevParams<R> launch_params(lbm_ctx *c) {
 }
 
 // First pass of the finite-difference variant: phi of the state the next
-// launch reads from buffer src (one launch over all tiles).
+// launch reads from buffer src, split into interior and wall slabs as the
+// step is.
+template <class St, Mode M, bool W>
+void launch_phi_box(lbm_ctx *c, int src, const DevParams<typename St::R> &P, const MassFix &mf) {
+    hipLaunchKernelGGL((phi_kernel<St, M, W>), tile_grid(P), dim3(BLOCK), 0, c->stream,
+                       cbuf_of<St>(c, src), P, mf);
+}
+
 template <class St, Mode M>
 void launch_phi(lbm_ctx *c, int src, const MassFix &mf) {
     using R = typename St::R;
     const DevParams<R> P = launch_params<R>(c);
-    const bool walls = c->P.wall[0] || c->P.wall[1] || c->P.wall[2];
-    if (walls)
-        hipLaunchKernelGGL((phi_kernel<St, M, true>), tile_grid(P), dim3(BLOCK), 0, c->stream,
-                           cbuf_of<St>(c, src), P, mf);
-    else
-        hipLaunchKernelGGL((phi_kernel<St, M, false>), tile_grid(P), dim3(BLOCK), 0, c->stream,
-                           cbuf_of<St>(c, src), P, mf);
+    const int *w = c->P.wall;
+    if (!w[0] && !w[1] && !w[2]) {
+        launch_phi_box<St, M, false>(c, src, P, mf);
+        return;
+    }
+    const int ylo = w[1] ? 1 : 0, yhi = w[1] ? P.nty - 1 : P.nty;
+    const int zlo = w[2] ? 1 : 0, zhi = w[2] ? P.nz - 1 : P.nz;
+    if (w[0] || yhi <= ylo || zhi <= zlo) {
+        launch_phi_box<St, M, true>(c, src, P, mf);
+        return;
+    }
+    const int band = c->tc.band;
+    launch_phi_box<St, M, false>(c, src, with_box(P, ylo, yhi - ylo, zlo, zhi - zlo, band), mf);
+    if (w[1]) launch_phi_box<St, M, true>(c, src, with_box(P, 0, 2, 0, P.nz, band, P.nty - 1), mf);
+    if (w[2])
+        launch_phi_box<St, M, true>(c, src, with_box(P, ylo, yhi - ylo, 0, 2, band, 1, P.nz - 1), mf);
 }
 
 // Periodic lattices: one wall-free launch. Walls in y and/or z: the interior
