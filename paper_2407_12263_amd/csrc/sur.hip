@@ -25,6 +25,19 @@ __device__ __forceinline__ uint16_t f2bf(float x) {
 
 __device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
+// e / c and e % c for element indices below 2^31 (32-bit unsigned).
+__device__ __forceinline__ long div32(long e, int c) { return (long)((uint32_t)e / (uint32_t)c); }
+__device__ __forceinline__ int mod32(long e, int c) { return (int)((uint32_t)e % (uint32_t)c); }
+
+// (x, y, z) of point p < 2^31 of an nx x ny x nz grid, x fastest (32-bit
+// unsigned divisions: 64-bit ones cost several times more).
+__device__ __forceinline__ void coords(long p, int nx, int ny, int &x, int &y, int &z) {
+    const uint32_t u = (uint32_t)p, r = u / (uint32_t)nx;
+    x = (int)(u - r * (uint32_t)nx);
+    z = (int)(r / (uint32_t)ny);
+    y = (int)(r - (uint32_t)z * (uint32_t)ny);
+}
+
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -71,9 +84,7 @@ __global__ void __launch_bounds__(256) conv3d_kernel(const uint16_t *__restrict_
         const long p = pbase + mt * 16 + r;
         pv[mt] = p < P;
         const long pp = pv[mt] ? p : 0;
-        px[mt] = (int)(pp % nx);
-        py[mt] = (int)((pp / nx) % ny);
-        pz[mt] = (int)(pp / ((long)nx * ny));
+        coords(pp, nx, ny, px[mt], py[mt], pz[mt]);
     }
     f4 acc[4][4];
 #pragma unroll
@@ -164,15 +175,26 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const uint16_t *__restrict__
     for (long kb = p0 + wave * 16; kb < p1; kb += 64) {
         long pj[4], nbj[4];
         bool vj[4];
+        // the lane's 4 points are consecutive: coordinates of the first, then
+        // one point at a time (a step wraps at most one row)
+        const long pb = kb + 4 * q;
+        int X, Y, Z;
+        coords(pb < p1 ? pb : p0, nx, ny, X, Y, Z);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const long p = kb + 4 * q + j;
+            const long p = pb + j;
             vj[j] = p < p1;
-            const long pp = vj[j] ? p : p0;
-            pj[j] = pp;
-            const int X = (int)(pp % nx), Y = (int)((pp / nx) % ny), Z = (int)(pp / ((long)nx * ny));
-            nbj[j] = (long)wrap(X + dx, nx) +
-                     (long)nx * ((long)wrap(Y + dyy, ny) + (long)ny * wrap(Z + dz, nz));
+            pj[j] = vj[j] ? p : p0;
+            if (j > 0 && ++X >= nx) {
+                X = 0;
+                if (++Y >= ny) {
+                    Y = 0;
+                    ++Z;
+                }
+            }
+            nbj[j] = vj[j] ? (long)wrap(X + dx, nx) +
+                                 (long)nx * ((long)wrap(Y + dyy, ny) + (long)ny * wrap(Z + dz, nz))
+                           : 0;
         }
         s4 a[MT], b[4];
 #pragma unroll
@@ -262,9 +284,10 @@ __global__ void pool2_kernel(const uint16_t *__restrict__ x, int c, int nx, int 
     const long n = (long)cx * cy * cz * c;
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
-    const int ch = (int)(e % c);
-    const long qq = e / c;
-    const int X = (int)(qq % cx), Y = (int)((qq / cx) % cy), Z = (int)(qq / ((long)cx * cy));
+    const int ch = mod32(e, c);
+    const long qq = div32(e, c);
+    int X, Y, Z;
+    coords(qq, cx, cy, X, Y, Z);
     float s = 0.f;
     for (int k = 0; k < 8; ++k) {
         const long p = (2 * X + (k & 1)) + (long)nx * ((2 * Y + ((k >> 1) & 1)) + (long)ny * (2 * Z + (k >> 2)));
@@ -278,9 +301,10 @@ __global__ void pool2_bwd_kernel(const float *__restrict__ dy, int c, int nx, in
     const long n = (long)nx * ny * nz * c;
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
-    const int ch = (int)(e % c);
-    const long p = e / c;
-    const int X = (int)(p % nx), Y = (int)((p / nx) % ny), Z = (int)(p / ((long)nx * ny));
+    const int ch = mod32(e, c);
+    const long p = div32(e, c);
+    int X, Y, Z;
+    coords(p, nx, ny, X, Y, Z);
     const long qq = (X / 2) + (long)(nx / 2) * ((Y / 2) + (long)(ny / 2) * (Z / 2));
     dx[e] += 0.125f * dy[qq * c + ch];
 }
@@ -291,9 +315,10 @@ __global__ void upsample2_kernel(const uint16_t *__restrict__ x, int c, int nx, 
     const long n = (long)fx * fy * fz * c;
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
-    const int ch = (int)(e % c);
-    const long p = e / c;
-    const int X = (int)(p % fx), Y = (int)((p / fx) % fy), Z = (int)(p / ((long)fx * fy));
+    const int ch = mod32(e, c);
+    const long p = div32(e, c);
+    int X, Y, Z;
+    coords(p, fx, fy, X, Y, Z);
     const long qq = (X / 2) + (long)nx * ((Y / 2) + (long)ny * (Z / 2));
     y[p * ystride + yoff + ch] = x[qq * c + ch];
 }
@@ -303,9 +328,10 @@ __global__ void upsample2_bwd_kernel(const float *__restrict__ dy, int dystride,
     const long n = (long)nx * ny * nz * c;
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
-    const int ch = (int)(e % c);
-    const long qq = e / c;
-    const int X = (int)(qq % nx), Y = (int)((qq / nx) % ny), Z = (int)(qq / ((long)nx * ny));
+    const int ch = mod32(e, c);
+    const long qq = div32(e, c);
+    int X, Y, Z;
+    coords(qq, nx, ny, X, Y, Z);
     const int fx = 2 * nx, fy = 2 * ny;
     float s = 0.f;
     for (int k = 0; k < 8; ++k) {
@@ -319,16 +345,16 @@ __global__ void copy_channels_kernel(const uint16_t *__restrict__ x, int c, long
                                      uint16_t *__restrict__ y, int ystride, int yoff) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= P * c) return;
-    const long p = e / c;
-    y[p * ystride + yoff + (e % c)] = x[e];
+    const long p = div32(e, c);
+    y[p * ystride + yoff + mod32(e, c)] = x[e];
 }
 
 __global__ void add_channels_kernel(const float *__restrict__ dy, int dystride, int dyoff, int c,
                                     long P, float *__restrict__ dx) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= P * c) return;
-    const long p = e / c;
-    dx[e] += dy[p * dystride + dyoff + (e % c)];
+    const long p = div32(e, c);
+    dx[e] += dy[p * dystride + dyoff + mod32(e, c)];
 }
 
 __global__ void to_bf16_kernel(const float *__restrict__ x, long n, uint16_t *__restrict__ y) {
@@ -406,7 +432,8 @@ __global__ void coarsen_kernel(const float *__restrict__ phi, const float *__res
     const long qq = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (qq >= Pc) return;
     const long N = (long)nx * ny * nz;
-    const int X = (int)(qq % cx), Y = (int)((qq / cx) % cy), Z = (int)(qq / ((long)cx * cy));
+    int X, Y, Z;
+    coords(qq, cx, cy, X, Y, Z);
     float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     for (int k = 0; k < 8; ++k) {
         const long f = (2 * X + (k & 1)) + (long)nx * ((2 * Y + ((k >> 1) & 1)) + (long)ny * (2 * Z + (k >> 2)));
@@ -430,7 +457,8 @@ __global__ void prolong_add_kernel(const float *__restrict__ d, int cx, int cy, 
     const long N = (long)nx * ny * nz;
     const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= N) return;
-    const int X = (int)(f % nx), Y = (int)((f / nx) % ny), Z = (int)(f / ((long)nx * ny));
+    int X, Y, Z;
+    coords(f, nx, ny, X, Y, Z);
     // fine node X sits at coarse coordinate (X + 1/2)/2 - 1/2
     auto lo = [](int X) { return (X - 1) >> 1; };  // floor((X - 1)/2)
     const int x0 = lo(X), y0 = lo(Y), z0 = lo(Z);
@@ -458,7 +486,8 @@ __global__ void __launch_bounds__(256) checks_kernel(const float *__restrict__ s
     const long qq = (long)blockIdx.x * blockDim.x + threadIdx.x;
     double v[NCHK] = {0.0, 1e300, -1e300, 0.0, 0.0, 0.0, 0.0};
     if (qq < P) {
-        const int X = (int)(qq % nx), Y = (int)((qq / nx) % ny), Z = (int)(qq / ((long)nx * ny));
+        int X, Y, Z;
+    coords(qq, nx, ny, X, Y, Z);
         auto at = [&](int x, int y, int z) {
             return (long)wrap(x, nx) + (long)nx * ((long)wrap(y, ny) + (long)ny * wrap(z, nz));
         };
@@ -517,8 +546,8 @@ __global__ void apply_residual_kernel(float *__restrict__ s, const float *__rest
                                       const float *__restrict__ rscale, int cu, long P) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= P * cu) return;
-    const long p = e / cu;
-    const int c = (int)(e % cu);
+    const long p = div32(e, cu);
+    const int c = mod32(e, cu);
     s[p * 16 + c] += rscale[c] * out[p * 16 + c];
 }
 
@@ -528,7 +557,7 @@ __global__ void residual_target_kernel(const float *__restrict__ s0, const float
                                        float *__restrict__ t) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= P * 16) return;
-    const int c = (int)(e % 16);
+    const int c = (int)(e & 15);
     t[e] = c < cu ? (s1[e] - s0[e]) / rscale[c] : 0.f;
 }
 
@@ -551,7 +580,8 @@ __global__ void features_kernel(float *__restrict__ s, int nx, int ny, int nz) {
     const long P = (long)nx * ny * nz;
     const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= P) return;
-    const int x = (int)(q % nx), y = (int)((q / nx) % ny), z = (int)(q / ((long)nx * ny));
+    int x, y, z;
+    coords(q, nx, ny, x, y, z);
     auto at = [&](int X, int Y, int Z) {
         return (wrap(X, nx) + (long)nx * (wrap(Y, ny) + (long)ny * wrap(Z, nz))) * 16;
     };
@@ -595,7 +625,8 @@ __global__ void prolong_update_kernel(const float *__restrict__ s0, const float 
     const long N = (long)nx * ny * nz;
     const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= N) return;
-    const int X = (int)(f % nx), Y = (int)((f / nx) % ny), Z = (int)(f / ((long)nx * ny));
+    int X, Y, Z;
+    coords(f, nx, ny, X, Y, Z);
     auto lo = [](int X) { return (X - 1) >> 1; };
     const int x0 = lo(X), y0 = lo(Y), z0 = lo(Z);
     const float wx = (X & 1) ? 0.25f : 0.75f, wy = (Y & 1) ? 0.25f : 0.75f, wz = (Z & 1) ? 0.25f : 0.75f;
@@ -678,7 +709,14 @@ int launched() { return hipGetLastError() == hipSuccess ? SUR_OK : SUR_EDEVICE; 
 
 dim3 grid1(long n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
 
-bool dims_ok(int nx, int ny, int nz) { return nx > 0 && ny > 0 && nz > 0; }
+bool dims_ok(int nx, int ny, int nz) {
+    return nx > 0 && ny > 0 && nz > 0 && (long)nx * ny * nz < 2147483647L;
+}
+
+// element counts of channel arrays stay below 2^31 (32-bit index math)
+bool elems_ok(long points, long channels) {
+    return points > 0 && channels > 0 && points * channels < 2147483647L;
+}
 
 constexpr long kWgradChunk = 8192;
 
@@ -745,7 +783,9 @@ int sur_pack_weights(const float *w, int32_t cin, int32_t cout, void *wf, void *
 }
 
 int sur_pool2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void *y, void *stream) {
-    if (!x || !y || c <= 0 || !dims_ok(nx, ny, nz) || nx % 2 || ny % 2 || nz % 2) return SUR_EINVAL;
+    if (!x || !y || c <= 0 || !dims_ok(nx, ny, nz) || nx % 2 || ny % 2 || nz % 2 ||
+        !elems_ok((long)nx * ny * nz, c))
+        return SUR_EINVAL;
     const long n = (long)(nx / 2) * (ny / 2) * (nz / 2) * c;
     hipLaunchKernelGGL(pool2_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream,
                        (const uint16_t *)x, c, nx, ny, nz, (uint16_t *)y);
@@ -754,7 +794,9 @@ int sur_pool2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void
 
 int sur_pool2_bwd(const float *dy, int32_t c, int32_t nx, int32_t ny, int32_t nz, float *dx,
                   void *stream) {
-    if (!dy || !dx || c <= 0 || !dims_ok(nx, ny, nz) || nx % 2 || ny % 2 || nz % 2) return SUR_EINVAL;
+    if (!dy || !dx || c <= 0 || !dims_ok(nx, ny, nz) || nx % 2 || ny % 2 || nz % 2 ||
+        !elems_ok((long)nx * ny * nz, c))
+        return SUR_EINVAL;
     const long n = (long)nx * ny * nz * c;
     hipLaunchKernelGGL(pool2_bwd_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, dy, c, nx,
                        ny, nz, dx);
@@ -763,7 +805,9 @@ int sur_pool2_bwd(const float *dy, int32_t c, int32_t nx, int32_t ny, int32_t nz
 
 int sur_upsample2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void *y,
                   int32_t ystride, int32_t yoff, void *stream) {
-    if (!x || !y || c <= 0 || !dims_ok(nx, ny, nz) || yoff < 0 || yoff + c > ystride) return SUR_EINVAL;
+    if (!x || !y || c <= 0 || !dims_ok(nx, ny, nz) || yoff < 0 || yoff + c > ystride ||
+        !elems_ok(8L * nx * ny * nz, ystride))
+        return SUR_EINVAL;
     const long n = 8L * nx * ny * nz * c;
     hipLaunchKernelGGL(upsample2_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream,
                        (const uint16_t *)x, c, nx, ny, nz, (uint16_t *)y, ystride, yoff);
@@ -772,7 +816,9 @@ int sur_upsample2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, 
 
 int sur_upsample2_bwd(const float *dy, int32_t dystride, int32_t dyoff, int32_t c, int32_t nx,
                       int32_t ny, int32_t nz, float *dx, void *stream) {
-    if (!dy || !dx || c <= 0 || !dims_ok(nx, ny, nz) || dyoff < 0 || dyoff + c > dystride) return SUR_EINVAL;
+    if (!dy || !dx || c <= 0 || !dims_ok(nx, ny, nz) || dyoff < 0 || dyoff + c > dystride ||
+        !elems_ok(8L * nx * ny * nz, dystride))
+        return SUR_EINVAL;
     const long n = (long)nx * ny * nz * c;
     hipLaunchKernelGGL(upsample2_bwd_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, dy,
                        dystride, dyoff, c, nx, ny, nz, dx);
@@ -781,7 +827,8 @@ int sur_upsample2_bwd(const float *dy, int32_t dystride, int32_t dyoff, int32_t 
 
 int sur_copy_channels(const void *x, int32_t c, int64_t P, void *y, int32_t ystride, int32_t yoff,
                       void *stream) {
-    if (!x || !y || c <= 0 || P <= 0 || yoff < 0 || yoff + c > ystride) return SUR_EINVAL;
+    if (!x || !y || c <= 0 || P <= 0 || yoff < 0 || yoff + c > ystride || !elems_ok(P, ystride))
+        return SUR_EINVAL;
     hipLaunchKernelGGL(copy_channels_kernel, grid1(P * c), dim3(256), 0, (hipStream_t)stream,
                        (const uint16_t *)x, c, (long)P, (uint16_t *)y, ystride, yoff);
     return launched();
@@ -789,7 +836,9 @@ int sur_copy_channels(const void *x, int32_t c, int64_t P, void *y, int32_t ystr
 
 int sur_add_channels(const float *dy, int32_t dystride, int32_t dyoff, int32_t c, int64_t P,
                      float *dx, void *stream) {
-    if (!dy || !dx || c <= 0 || P <= 0 || dyoff < 0 || dyoff + c > dystride) return SUR_EINVAL;
+    if (!dy || !dx || c <= 0 || P <= 0 || dyoff < 0 || dyoff + c > dystride ||
+        !elems_ok(P, dystride))
+        return SUR_EINVAL;
     hipLaunchKernelGGL(add_channels_kernel, grid1(P * c), dim3(256), 0, (hipStream_t)stream, dy,
                        dystride, dyoff, c, (long)P, dx);
     return launched();
@@ -856,7 +905,7 @@ int sur_prolong_add(const float *delta, int32_t cnx, int32_t cny, int32_t cnz, c
 
 int sur_apply_residual(float *state, const float *out, const float *rscale, int32_t cu, int64_t P,
                        void *stream) {
-    if (!state || !out || !rscale || cu <= 0 || cu > 16 || P <= 0) return SUR_EINVAL;
+    if (!state || !out || !rscale || cu <= 0 || cu > 16 || !elems_ok(P, 16)) return SUR_EINVAL;
     hipLaunchKernelGGL(apply_residual_kernel, grid1(P * cu), dim3(256), 0, (hipStream_t)stream,
                        state, out, rscale, cu, (long)P);
     return launched();
@@ -864,7 +913,7 @@ int sur_apply_residual(float *state, const float *out, const float *rscale, int3
 
 int sur_residual_target(const float *s0, const float *s1, const float *rscale, int32_t cu, int64_t P,
                         float *target, void *stream) {
-    if (!s0 || !s1 || !rscale || !target || cu <= 0 || cu > 16 || P <= 0) return SUR_EINVAL;
+    if (!s0 || !s1 || !rscale || !target || cu <= 0 || cu > 16 || !elems_ok(P, 16)) return SUR_EINVAL;
     hipLaunchKernelGGL(residual_target_kernel, grid1(P * 16), dim3(256), 0, (hipStream_t)stream,
                        s0, s1, rscale, cu, (long)P, target);
     return launched();
