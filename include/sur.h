@@ -142,13 +142,17 @@ int sur_checks(const float *state, int32_t nx, int32_t ny, int32_t nz, double *s
                double *out, void *stream);
 
 /* state[p][c] += rscale[c] * out[p][c] for c < cu (the network's residual,
- * in residual units, applied to the scaled state). */
+ * in residual units, applied to the scaled state). With width > 0 channel 0
+ * (phi) moves in level-set coordinates instead:
+ * phi += Phi(Psi(phi) + rscale[0] out[p][0]) - Phi(Psi(phi)), with Psi and Phi
+ * of sur_prolong_update (phi stays inside (0, 1) whatever the output). */
 int sur_apply_residual(float *state, const float *out, const float *rscale, int32_t cu,
-                       int64_t P, void *stream);
+                       int64_t P, double width, void *stream);
 
-/* target[p][c] = (s1[p][c] - s0[p][c]) / rscale[c] for c < cu, 0 beyond. */
+/* target[p][c] = (s1[p][c] - s0[p][c]) / rscale[c] for c < cu, 0 beyond;
+ * with width > 0 channel 0 is (Psi(s1) - Psi(s0)) / rscale[0]. */
 int sur_residual_target(const float *s0, const float *s1, const float *rscale, int32_t cu,
-                        int64_t P, float *target, void *stream);
+                        int64_t P, double width, float *target, void *stream);
 
 /* Puts the phase mass back to *target_mass: phi += c phi (1 - phi) with
  * c = (target - sum phi) / sum phi (1 - phi) from a sur_checks result (all on

@@ -16,7 +16,8 @@ are (z, y, x) for fine fields and (z, y, x, 16) for coarse states:
   features       periodic central differences and products used as network
                  inputs.
   checks         the per-window check sums.
-  apply_residual / residual_target / fix_mass  the state updates of a window.
+  apply_residual / residual_target / fix_mass  the state updates of a window
+                 (phi's change optionally in level-set coordinates).
 
 The paper has no learned component, so nothing here follows a passage of it
 except the equilibrium profile (the tanh interface of width delta used for the
@@ -127,15 +128,28 @@ def checks(s):
                      np.maximum(phi * (1.0 - phi), 0.0).sum()])
 
 
-def apply_residual(s, out, rscale, cu=NUSE):
+def apply_residual(s, out, rscale, cu=NUSE, width=0.0):
+    """s + rscale * out on the first cu channels; with width > 0 channel 0
+    (phi) moves in level-set coordinates: phi + Phi(Psi(phi) + d) - Phi(Psi(phi))."""
     s = s.copy()
-    s[..., :cu] += rscale[:cu] * out[..., :cu]
+    d = rscale[:cu] * out[..., :cu]
+    if width > 0:
+        phi = s[..., 0]
+        so = psi(phi, width)
+        s[..., 0] = phi + (profile(so + d[..., 0], width) - profile(so, width))
+        s[..., 1:cu] += d[..., 1:cu]
+    else:
+        s[..., :cu] += d
     return s
 
 
-def residual_target(s0, s1, rscale, cu=NUSE):
+def residual_target(s0, s1, rscale, cu=NUSE, width=0.0):
+    """(s1 - s0)/rscale on the first cu channels (channel 0 as the change of
+    Psi(phi) when width > 0), 0 beyond."""
     t = np.zeros_like(s0)
     t[..., :cu] = (s1[..., :cu] - s0[..., :cu]) / rscale[:cu]
+    if width > 0:
+        t[..., 0] = (psi(s1[..., 0], width) - psi(s0[..., 0], width)) / rscale[0]
     return t
 
 

@@ -54,6 +54,20 @@ __device__ __forceinline__ double wmax(double v) {
     return v;
 }
 
+// Signed distance of the equilibrium profile phi = (1 + tanh(2 psi / W)) / 2,
+// psi = (W / 4) ln(phi / (1 - phi)), with phi clamped to [LS_EPS, 1 - LS_EPS].
+constexpr double LS_EPS = 1e-4;
+__device__ __forceinline__ float ls_psi_f(float f, float W) {
+    f = fminf(fmaxf(f, (float)LS_EPS), 1.f - (float)LS_EPS);
+    return 0.25f * W * logf(f / (1.f - f));
+}
+__device__ __forceinline__ double ls_psi(double f, double W) {
+    f = fmin(fmax(f, LS_EPS), 1.0 - LS_EPS);
+    return 0.25 * W * log(f / (1.0 - f));
+}
+__device__ __forceinline__ double ls_phi(double s, double W) { return 0.5 * (1.0 + tanh(2.0 * s / W)); }
+__device__ __forceinline__ float ls_phi_f(float s, float W) { return 0.5f * (1.f + tanhf(2.f * s / W)); }
+
 // ------------------------------------------------------------ convolution
 // Implicit GEMM: Y[p][o] = sum_{t, i} X[p + s d_t][i] Wk[t][o][i].
 // A wavefront owns 64 points (four 16-point M tiles) and a 64-channel block of
@@ -542,23 +556,38 @@ __global__ void __launch_bounds__(1024) checks_final_kernel(const double *__rest
 }
 
 // s[p][c] += rscale[c] * out[p][c] for the used channels c < cu.
+// s[p][c] += rscale[c] out[p][c] for c < cu; with width > 0 channel 0 (phi)
+// moves in level-set coordinates: phi <- phi + Phi(Psi(phi) + r o) - Phi(Psi(phi)).
 __global__ void apply_residual_kernel(float *__restrict__ s, const float *__restrict__ out,
-                                      const float *__restrict__ rscale, int cu, long P) {
+                                      const float *__restrict__ rscale, int cu, long P,
+                                      float width) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= P * cu) return;
     const long p = div32(e, cu);
     const int c = mod32(e, cu);
-    s[p * 16 + c] += rscale[c] * out[p * 16 + c];
+    const float d = rscale[c] * out[p * 16 + c];
+    if (c == 0 && width > 0.f) {
+        const float f = s[p * 16];
+        const float so = ls_psi_f(f, width);
+        s[p * 16] = f + (ls_phi_f(so + d, width) - ls_phi_f(so, width));
+    } else {
+        s[p * 16 + c] += d;
+    }
 }
 
 // t[p][c] = (s1[p][c] - s0[p][c]) / rscale[c] for c < cu, 0 otherwise.
+// t = (s1 - s0)/rscale on the first cu channels (channel 0 as the change of
+// Psi(phi) when width > 0), 0 beyond.
 __global__ void residual_target_kernel(const float *__restrict__ s0, const float *__restrict__ s1,
                                        const float *__restrict__ rscale, int cu, long P,
-                                       float *__restrict__ t) {
+                                       float width, float *__restrict__ t) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= P * 16) return;
     const int c = (int)(e & 15);
-    t[e] = c < cu ? (s1[e] - s0[e]) / rscale[c] : 0.f;
+    float d = 0.f;
+    if (c < cu)
+        d = (c == 0 && width > 0.f) ? ls_psi_f(s1[e], width) - ls_psi_f(s0[e], width) : s1[e] - s0[e];
+    t[e] = c < cu ? d / rscale[c] : 0.f;
 }
 
 // s[p][0] += c w(phi), c = (target - sum phi)/sum w from a checks result.
@@ -599,19 +628,6 @@ __global__ void features_kernel(float *__restrict__ s, int nx, int ny, int nz) {
     o[10] = phi * (1.f - phi);
     o[11] = sqrtf(gx * gx + gy * gy + gz * gz);
 }
-
-// Signed distance of the equilibrium profile phi = (1 + tanh(2 psi / W)) / 2,
-// psi = (W / 4) ln(phi / (1 - phi)), with phi clamped to [LS_EPS, 1 - LS_EPS].
-constexpr double LS_EPS = 1e-4;
-__device__ __forceinline__ float ls_psi_f(float f, float W) {
-    f = fminf(fmaxf(f, (float)LS_EPS), 1.f - (float)LS_EPS);
-    return 0.25f * W * logf(f / (1.f - f));
-}
-__device__ __forceinline__ double ls_psi(double f, double W) {
-    f = fmin(fmax(f, LS_EPS), 1.0 - LS_EPS);
-    return 0.25 * W * log(f / (1.0 - f));
-}
-__device__ __forceinline__ double ls_phi(double s, double W) { return 0.5 * (1.0 + tanh(2.0 * s / W)); }
 
 // Fine update from two coarse states s0 -> s1: u and p get the trilinear
 // prolongation of the change; phi moves its level set: the coarse change of
@@ -904,18 +920,20 @@ int sur_prolong_add(const float *delta, int32_t cnx, int32_t cny, int32_t cnz, c
 }
 
 int sur_apply_residual(float *state, const float *out, const float *rscale, int32_t cu, int64_t P,
-                       void *stream) {
+                       double width, void *stream) {
     if (!state || !out || !rscale || cu <= 0 || cu > 16 || !elems_ok(P, 16)) return SUR_EINVAL;
+    if (!(width >= 0.0)) return SUR_EINVAL;
     hipLaunchKernelGGL(apply_residual_kernel, grid1(P * cu), dim3(256), 0, (hipStream_t)stream,
-                       state, out, rscale, cu, (long)P);
+                       state, out, rscale, cu, (long)P, (float)width);
     return launched();
 }
 
 int sur_residual_target(const float *s0, const float *s1, const float *rscale, int32_t cu, int64_t P,
-                        float *target, void *stream) {
+                        double width, float *target, void *stream) {
     if (!s0 || !s1 || !rscale || !target || cu <= 0 || cu > 16 || !elems_ok(P, 16)) return SUR_EINVAL;
+    if (!(width >= 0.0)) return SUR_EINVAL;
     hipLaunchKernelGGL(residual_target_kernel, grid1(P * 16), dim3(256), 0, (hipStream_t)stream,
-                       s0, s1, rscale, cu, (long)P, target);
+                       s0, s1, rscale, cu, (long)P, (float)width, target);
     return launched();
 }
 

@@ -56,8 +56,8 @@ def load_library(path: str | None = None):
     lib.sur_coarsen.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, vp]
     lib.sur_prolong_add.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.sur_checks.argtypes = [vp, i32, i32, i32, vp, vp, vp]
-    lib.sur_apply_residual.argtypes = [vp, vp, vp, i32, i64, vp]
-    lib.sur_residual_target.argtypes = [vp, vp, vp, i32, i64, vp, vp]
+    lib.sur_apply_residual.argtypes = [vp, vp, vp, i32, i64, C.c_double, vp]
+    lib.sur_residual_target.argtypes = [vp, vp, vp, i32, i64, C.c_double, vp, vp]
     lib.sur_fix_mass.argtypes = [vp, i64, vp, vp, vp]
     lib.sur_features.argtypes = [vp, i32, i32, i32, vp]
     lib.sur_prolong_update_scratch_doubles.argtypes = [i32, i32, i32]
@@ -171,14 +171,14 @@ def sur_checks(state, grid, scratch, out):
     _ok(load_library().sur_checks(_p(state), *grid, _p(scratch), _p(out), _stream()), "sur_checks")
 
 
-def sur_apply_residual(state, out, rscale, cu, P):
-    _ok(load_library().sur_apply_residual(_p(state), _p(out), _p(rscale), cu, P, _stream()),
-        "sur_apply_residual")
+def sur_apply_residual(state, out, rscale, cu, P, width=0.0):
+    _ok(load_library().sur_apply_residual(_p(state), _p(out), _p(rscale), cu, P, float(width),
+                                          _stream()), "sur_apply_residual")
 
 
-def sur_residual_target(s0, s1, rscale, cu, P, target):
-    _ok(load_library().sur_residual_target(_p(s0), _p(s1), _p(rscale), cu, P, _p(target),
-                                           _stream()), "sur_residual_target")
+def sur_residual_target(s0, s1, rscale, cu, P, target, width=0.0):
+    _ok(load_library().sur_residual_target(_p(s0), _p(s1), _p(rscale), cu, P, float(width),
+                                           _p(target), _stream()), "sur_residual_target")
 
 
 def sur_fix_mass(state, P, checks_out, target_mass):

@@ -158,3 +158,31 @@ def test_mass_fix_and_residual_roundtrip():
     target = s0[..., 0].sum()
     fixed = co.fix_mass(s1, co.checks(s1), target)
     assert abs(fixed[..., 0].sum() - target) < 1e-12 * target
+
+
+def test_level_set_residual_roundtrip_and_bounds():
+    """In level-set mode the target of a change and its application invert
+    each other for phi inside the clamp range, a zero residual leaves phi
+    unchanged, and any residual keeps phi inside (0, 1)."""
+    rng = np.random.default_rng(4)
+    W = 4.0
+    s0 = np.zeros((4, 4, 4, 16))
+    s0[..., :5] = rng.random((4, 4, 4, 5)) * 0.98 + 0.01
+    s1 = s0.copy()
+    s1[..., :5] += 0.005 * rng.standard_normal((4, 4, 4, 5))
+    r = np.array([0.1, 0.2, 0.3, 0.4, 0.5] + [1.0] * 11)
+    t = co.residual_target(s0, s1, r, width=W)
+    back = co.apply_residual(s0, t, r, width=W)
+    assert np.abs(back[..., :5] - s1[..., :5]).max() < 1e-12
+    assert np.array_equal(co.apply_residual(s0, np.zeros_like(s0), r, width=W), s0)
+    wild = co.apply_residual(s0, 1e3 * rng.standard_normal(s0.shape), r, width=W)
+    assert wild[..., 0].min() > -1e-12 and wild[..., 0].max() < 1 + 1e-12
+    # a translated planar profile has a uniform level-set change
+    x = np.arange(32.0)
+    a = np.zeros((1, 1, 32, 16))
+    b = np.zeros((1, 1, 32, 16))
+    a[0, 0, :, 0] = co.profile(x - 15.3, W)
+    b[0, 0, :, 0] = co.profile(x - 15.8, W)
+    tt = co.residual_target(a, b, np.ones(16), width=W)[0, 0, :, 0]
+    inside = (a[0, 0, :, 0] > 1e-3) & (a[0, 0, :, 0] < 1 - 1e-3)
+    assert np.abs(tt[inside] + 0.5).max() < 1e-9

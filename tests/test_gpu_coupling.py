@@ -159,3 +159,31 @@ def test_residual_updates_and_coarse_mass_fix(sur):
     assert np.abs(got - ref).max() <= 1e-6
     # FP32 storage of the fixed phi: the mass is back to FP32 rounding
     assert abs(got[:, 0].astype(np.float64).sum() - target.item()) <= 1e-6 * target.item()
+
+
+def test_level_set_residual_kernels(sur):
+    import torch
+    say("[coupling] apply_residual / residual_target in level-set mode")
+    rng = np.random.default_rng(5)
+    P = int(np.prod(CGRID))
+    W = 4.0
+    s0 = np.zeros((P, 16), dtype=np.float32)
+    s0[:, :5] = rng.random((P, 5)).astype(np.float32)
+    s0[:7, 0] = [0.0, 1.0, 1e-6, 1 - 1e-6, 0.5, -0.01, 1.02]   # clamp edges
+    out = (0.5 * rng.standard_normal((P, 16))).astype(np.float32)
+    r = np.array([0.2, 0.2, 0.2, 0.2, 0.5] + [1.0] * 11, dtype=np.float32)
+    ds = _dev(s0, torch.float32)
+    sur.sur_apply_residual(ds, _dev(out, torch.float32), _dev(r, torch.float32), 5, P, W)
+    ref = co.apply_residual(s0.astype(np.float64), out.astype(np.float64), r.astype(np.float64),
+                            width=W)
+    got = ds.cpu().numpy()
+    say(f"   max|d| {np.abs(got - ref).max():.2e}")
+    assert np.abs(got - ref).max() <= 2e-6
+    t = torch.empty((P, 16), dtype=torch.float32, device="cuda")
+    sur.sur_residual_target(_dev(s0, torch.float32), ds, _dev(r, torch.float32), 5, P, t, W)
+    rt = co.residual_target(s0.astype(np.float64), got.astype(np.float64), r.astype(np.float64),
+                            width=W)
+    # Psi is steep near the clamp: compare where phi is away from it
+    mid = (s0[:, 0] > 1e-3) & (s0[:, 0] < 1 - 1e-3) & (got[:, 0] > 1e-3) & (got[:, 0] < 1 - 1e-3)
+    assert np.abs(t.cpu().numpy()[mid] - rt[mid]).max() <= 2e-4
+    assert np.abs(t.cpu().numpy()[:, 1:5] - rt[:, 1:5]).max() <= 1e-4
