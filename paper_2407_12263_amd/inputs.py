@@ -135,6 +135,29 @@ def static_droplet(n: int = 32, R: float = 8.0, W: float = 4.0, sigma: float = 1
                     meta=dict(R=R, W=W, center=center))
 
 
+def droplet_2d(L0: int = 100, Cn: float = 0.06, La: float = 1.0, tau_rho: float = 0.02,
+               M: float = 0.02, courant: float = COURANT) -> Workload:
+    """Static droplet in 2D (Sec. 3.1: the convergence study): diameter
+    D = L0/2 in a periodic L0 x L0 box, interface width delta = Cn D,
+    rho1 = rho2 = 1, equal viscosities from tau_rho, sigma from
+    La = sigma rho D / eta, t0 = eta D / (2 sigma). The lattice is D3Q19 on a
+    single z-plane (nz = 1, periodic): the z-moving populations stay in the
+    plane and the projected weights are those of D2Q9 (4/9, 1/9, 1/36)."""
+    cs2 = cs2_of(courant)
+    D = L0 / 2.0
+    W = Cn * D
+    eta = tau_rho * cs2
+    sigma = La * eta / D
+    shape = (1, L0, L0)
+    r = sphere_distance(shape, (L0 / 2.0, L0 / 2.0, 0.0))
+    phi0 = tanh_drop(r, D / 2.0, W)
+    return Workload(name=f"droplet_2d_{L0}", nx=L0, ny=L0, nz=1, courant=courant,
+                    rho1=1.0, rho2=1.0, tau_rho1=tau_rho, tau_rho2=tau_rho,
+                    tau_phi=tau_from_mobility(M, courant), sigma=sigma, delta=W,
+                    steps=0, phi0=phi0, u0=np.zeros((3,) + shape), p0=np.zeros(shape),
+                    meta=dict(D=D, W=W, t0=eta * D / (2.0 * sigma), sigma=sigma, eta=eta))
+
+
 def rayleigh_taylor(nx: int = 128, ny: int = 512, nz: int = 128, W: float = 4.0,
                     Re: float = 256.0, U: float = 0.04, sigma: float = 5e-5,
                     M: float = 0.02, amp_frac: float = 0.05, courant: float = COURANT,

@@ -456,3 +456,18 @@ def test_k1_floor_bounds_rounding_sensitivity(orc, normal_fd):
         res[eps] = np.abs(a.fields()[0] - b.fields()[0]).max()
     assert res[1e-5] < 1e-12
     assert res[0.0] > 1e-8
+
+
+def test_single_plane_lattice_projects_to_d2q9(orc):
+    """On one periodic z-plane the D3Q19 populations with e_z != 0 stay in the
+    plane: grouped by their in-plane velocity, the weights are D2Q9's
+    (4/9 rest, 1/9 axis, 1/36 diagonal), which makes nz = 1 runs 2D runs."""
+    e, t = orc.lattice()
+    proj = {}
+    for i in range(19):
+        k = (int(e[i][0]), int(e[i][1]))
+        proj[k] = proj.get(k, 0.0) + t[i]
+    assert len(proj) == 9
+    for (ex, ey), w in proj.items():
+        want = 4 / 9 if ex == ey == 0 else (1 / 9 if ex * ey == 0 else 1 / 36)
+        assert abs(w - want) < 1e-15, ((ex, ey), w)
