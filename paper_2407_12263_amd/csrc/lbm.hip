@@ -75,8 +75,24 @@ bool is16(int precision) {
     return precision == LBM_FP32_FP16STORE || precision == LBM_FP32_BF16STORE;
 }
 
+// Bytes from one population plane to the next: N elements (16-bit storage:
+// the 32-bit f/g words) rounded up to 256 B, plus a pad of 64 KiB + 256 B.
+// With power-of-two strides (the usual lattice sizes) the 19 planes of a
+// node fall on the same L2 sets and channels and evict each other's tap
+// lines: unpadded, 256^3 FP16 steps fetch 1.6x the algorithmic bytes. The
+// pad was measured best over 256 B .. 128 KiB on the Rayleigh-Taylor,
+// rising-bubble and 256^3 lattices. LBM_PLANE_PAD (bytes) overrides it
+// (tuning only; results do not depend on it).
+size_t plane_pitch(const lbm_params *P) {
+    const size_t N = (size_t)P->nx * P->ny * P->nz;
+    const size_t pe = is16(P->precision) ? 4 : (size_t)elem_bytes(P->precision);
+    const int pad = env_int("LBM_PLANE_PAD", 65536 + 256);
+    return align_up(N * pe) + align_up((size_t)(pad > 0 ? pad : 0));
+}
+
 struct Layout {
-    size_t pdf_bytes;      // one field (19 N values)
+    size_t pdf_bytes;      // f (16-bit storage: f and g words), 19 planes
+    size_t g_bytes;        // g, 19 planes (0 for 16-bit storage)
     size_t phis_bytes;     // N floats (16-bit storage) or 0
     size_t buf_bytes;      // f + g + phis of one ping-pong buffer
     size_t partial_bytes;  // NSUM doubles per reduction block
@@ -94,9 +110,10 @@ Layout layout_of(const lbm_params *P) {
     // shape can give (tile width 1)
     TileCfg narrow{0, 0, 1};
     const size_t nblocks = num_tiles(P, narrow);
-    L.pdf_bytes = align_up(19 * N * elem_bytes(P->precision));
+    L.pdf_bytes = align_up(19 * plane_pitch(P));
+    L.g_bytes = is16(P->precision) ? 0 : L.pdf_bytes;
     L.phis_bytes = is16(P->precision) ? align_up(N * sizeof(float)) : 0;
-    L.buf_bytes = 2 * L.pdf_bytes + L.phis_bytes;
+    L.buf_bytes = L.pdf_bytes + L.g_bytes + L.phis_bytes;
     L.partial_bytes = align_up(nblocks * NSUM * sizeof(double));
     L.result_bytes = align_up(NSUM * sizeof(double));
     L.flag_bytes = kAlign;
@@ -115,8 +132,7 @@ int validate(const lbm_params *P) {
     if (P->precision < LBM_FP64 || P->precision > LBM_FP32_BF16STORE) return LBM_EINVAL;
     // every population field is addressed through one 32-bit buffer range
     // (16-bit storage keeps f and g of a population in one 32-bit plane)
-    const double plane_elem = P->precision >= LBM_FP32_FP16STORE ? 4.0 : (double)elem_bytes(P->precision);
-    if (19.0 * N * plane_elem >= 4294967295.0) return LBM_EINVAL;
+    if (19.0 * (double)plane_pitch(P) >= 4294967295.0) return LBM_EINVAL;
     const int nn[3] = {P->nx, P->ny, P->nz};
     for (int a = 0; a < 3; ++a) {
         if (P->wall[a] != 0 && P->wall[a] != 1) return LBM_EINVAL;
@@ -170,6 +186,7 @@ DevParams<R> make_params(const lbm_params *P, const TileCfg &tc) {
     d.ny = P->ny;
     d.nz = P->nz;
     d.N = P->nx * P->ny * P->nz;
+    d.plane_bytes = (uint32_t)plane_pitch(P);
     for (int a = 0; a < 3; ++a) d.wall[a] = P->wall[a];
     d.tx_log2 = tc.tx_log2;
     d.ntx = (P->nx + (1 << tc.tx_log2) - 1) >> tc.tx_log2;
@@ -252,7 +269,7 @@ Buf<St> buf_of(lbm_ctx *c, int k) {
     Buf<St> b;
     b.f = (typename St::T *)c->buf[k];
     b.g = (typename St::T *)(c->buf[k] + c->L.pdf_bytes);
-    b.phis = c->L.phis_bytes ? (float *)(c->buf[k] + 2 * c->L.pdf_bytes) : nullptr;
+    b.phis = c->L.phis_bytes ? (float *)(c->buf[k] + c->L.pdf_bytes + c->L.g_bytes) : nullptr;
     return b;
 }
 

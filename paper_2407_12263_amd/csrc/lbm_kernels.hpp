@@ -139,6 +139,7 @@ struct DevParams {
     R wA_f, wB_f, wD_f;      // 2^-k (A, 1 - c^2, D): the three-tap weights of the stored
     R wA_g, wB_g, wD_g;      // 16-bit deviations with their scale folded in (exact)
     R *phi_fd;               // phi field of the finite-difference variant (or NULL)
+    uint32_t plane_bytes;    // bytes from one population plane to the next
 };
 
 // Linear index of this block in its launch grid (x fastest).
@@ -331,7 +332,7 @@ enum Mode { LOCAL = 0, SHIFT = 1, LW = 2 };
 template <class St>
 struct Src {
     rsrc_t f, g, phis;
-    uint32_t plane;      // bytes of one population plane (N * sizeof(T))
+    uint32_t plane;      // bytes from one population plane to the next (padded)
 };
 
 template <class St>
@@ -339,7 +340,7 @@ __device__ __forceinline__ Src<St> make_src(const CBuf<St> &b, const DevParams<t
     Src<St> s;
     // 16-bit storage keeps f_i and g_i of a node together in one 32-bit word
     // (f in the low half): one load per tap serves both fields
-    const uint32_t plane = (uint32_t)P.N * (uint32_t)(St::DEV ? 4 : sizeof(typename St::T));
+    const uint32_t plane = P.plane_bytes;
     s.plane = plane;
     s.f = make_rsrc(b.f, 19u * plane);
     s.g = St::DEV ? s.f : make_rsrc(b.g, 19u * plane);
@@ -692,7 +693,7 @@ struct Dst {
 template <class St>
 __device__ __forceinline__ Dst<St> make_dst(const Buf<St> &b, const DevParams<typename St::R> &P) {
     Dst<St> d;
-    const uint32_t plane = (uint32_t)P.N * (uint32_t)(St::DEV ? 4 : sizeof(typename St::T));
+    const uint32_t plane = P.plane_bytes;
     d.plane = plane;
     d.f = make_rsrc(b.f, 19u * plane);
     d.g = St::DEV ? d.f : make_rsrc(b.g, 19u * plane);

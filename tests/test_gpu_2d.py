@@ -84,7 +84,8 @@ def test_2d_droplet_second_order_convergence():
 
 
 def test_2d_spurious_currents_against_la():
-    """|u|max^2 after 20 capillary times t0 for La = 16, 1 and 0.25 (D = 50,
+    """|u|max^2 after 200 capillary times t0 (the paper's steady state) for
+    La = 16, 1 and 0.25 (D = 50,
     Cn = 0.06, tau_rho = 0.02; La is varied through sigma). Table 1's values
     rest on sigma and eta from earlier work that the paper does not give, so
     its trend is checked (the currents are weaker at lower La) and their size
@@ -93,7 +94,7 @@ def test_2d_spurious_currents_against_la():
     res, ca = {}, {}
     for La in (16.0, 1.0, 0.25):
         w = inputs.droplet_2d(100, La=La)
-        T = int(round(20 * w.meta["t0"]))
+        T = int(round(200 * w.meta["t0"]))
         sol = gpu_solver(w, "fp64")
         sol.step(T)
         _, u, _ = gpu_fields(sol)
@@ -102,6 +103,6 @@ def test_2d_spurious_currents_against_la():
         say(f"[2d] La = {La}: {T} steps, |u|max^2 = {res[La]:.3e}, "
             f"|u|max eta/sigma = {ca[La]:.2e}")
     assert res[16.0] > res[1.0] > res[0.25]
-    # measured 4.5e-7, 2.4e-9, 1.6e-10 -> 2.1e-3, 2.4e-3, 2.5e-3
+    # measured 5.9e-7, 2.3e-9, 1.6e-10 -> 2.4e-3, 2.4e-3, 2.5e-3
     assert max(ca.values()) < 5e-3
     assert max(ca.values()) < 2.0 * min(ca.values())
