@@ -5,6 +5,7 @@
 // window checks that couple it to the LBM solver. See include/sur.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "sur.h"
@@ -160,6 +161,118 @@ __global__ void __launch_bounds__(256) conv3d_kernel(const uint16_t *__restrict_
     }
 }
 
+// The same convolution for grids whose sizes are multiples of the 16 x 4 x 4
+// point tile. A block stages the tile's 18 x 6 x 6 halo of 16 input channels
+// at a time (32 B per point, 20.7 KB) in LDS, so each input value is read
+// from memory about twice instead of 27 times. Wavefront w owns plane z0 + w
+// of the tile: four rows of 16 points, the four M tiles; a block computes
+// 32 output channels (two N tiles). The K steps use the
+// 16x16x32 BF16 MFMA; one step covers two taps (lanes l / 16 = 0, 1: tap t,
+// 2, 3: tap t + 1) x 16 channels (8 per lane). A and B place the same (tap,
+// channel) in the same lane group and element, so the product does not
+// depend on how the hardware orders K within a step. The 14th step's second
+// tap does not exist and enters as zeros.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+constexpr int kTX = 16, kTY = 4, kTZ = 4;
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2, kHP = kHX * kHY * kHZ;
+constexpr int kNT = 2;  // 16-channel output tiles per block (LDS <= 48.4 KB)
+
+__global__ void __launch_bounds__(256) conv3d_tiled_kernel(
+    const uint16_t *__restrict__ x, int cin, const uint16_t *__restrict__ w,
+    const float *__restrict__ bias, int cout, int nx, int ny, int nz, int flip, int relu,
+    const uint16_t *__restrict__ mask, uint16_t *__restrict__ yb, float *__restrict__ yf) {
+    // LDS: the input halo (kHP points x 16 channels) and the chunk's weights
+    // (27 taps x the block's output channels x 16 channels), 32 B per row
+    extern __shared__ uint4 lds[];
+    uint4 *tile = lds, *wl = lds + kHP * 2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int ntx = nx / kTX, nty = ny / kTY;
+    const int bx = (int)blockIdx.x % ntx, rest = (int)blockIdx.x / ntx;
+    const int by = rest % nty, bz = rest / nty;
+    const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
+    const int cob = blockIdx.y * (16 * kNT);
+    const int ntiles = min(kNT, (cout - cob) >> 4);
+    const int nco = ntiles * 16;
+    const int half = q & 1;
+    f4 acc[4][kNT];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+    const uint4 z4 = uint4{0u, 0u, 0u, 0u};
+    for (int cc = 0; cc < cin; cc += 16) {
+        __syncthreads();  // the previous chunk's reads are done
+        for (int c = threadIdx.x; c < kHP * 2; c += 256) {
+            const int h = c >> 1;
+            const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
+            const int gp = wrap(x0 - 1 + hx, nx) + nx * (wrap(y0 - 1 + hy, ny) + ny * wrap(z0 - 1 + hz, nz));
+            tile[c] = *(const uint4 *)(x + gp * cin + cc + 8 * (c & 1));
+        }
+        // weight row (t, o) of this chunk: w[t][cob + o][cc .. cc + 15]
+        for (int c = threadIdx.x; c < 27 * nco * 2; c += 256) {
+            const int row = c >> 1, t = row / nco, o = row - t * nco;
+            wl[c] = *(const uint4 *)(w + (t * cout + cob + o) * cin + cc + 8 * (c & 1));
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int t = 0; t < 27; t += 2) {
+            const int tap = t + (q >> 1);
+            const bool tv = tap < 27;
+            const int tc = tv ? tap : 26;
+            int dx = tc % 3 - 1, dy = (tc / 3) % 3 - 1, dz = tc / 9 - 1;
+            if (flip) {
+                dx = -dx;
+                dy = -dy;
+                dz = -dz;
+            }
+            bf8 a[4], b[kNT];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int h = (r + 1 + dx) + kHX * ((mt + 1 + dy) + kHY * (wave + 1 + dz));
+                a[mt] = __builtin_bit_cast(bf8, tv ? tile[2 * h + half] : z4);
+            }
+#pragma unroll
+            for (int nt = 0; nt < kNT; ++nt) {
+                uint4 v = z4;
+                if (nt < ntiles && tv) v = wl[2 * (tc * nco + nt * 16 + r) + half];
+                b[nt] = __builtin_bit_cast(bf8, v);
+            }
+#pragma unroll
+            for (int nt = 0; nt < kNT; ++nt) {
+                if (nt < ntiles) {
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt],
+                                                                               acc[mt][nt], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const int prow = nx * ((y0 + mt) + ny * (z0 + wave));
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) {
+            if (nt >= ntiles) continue;
+            const int co = cob + nt * 16 + r;
+            const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int p = prow + x0 + 4 * q + j;
+                float v = acc[mt][nt][j] + bb;
+                if (relu) v = fmaxf(v, 0.f);
+                if (mask && !(bf2f(mask[p * cout + co]) > 0.f)) v = 0.f;
+                if (yb) yb[p * cout + co] = f2bf(v);
+                if (yf) yf[p * cout + co] = v;
+            }
+        }
+    }
+}
+
+// LDS bytes of conv3d_tiled_kernel for a block of nco output channels.
+size_t conv_tiled_lds(int nco) { return (size_t)(kHP * 2 + 27 * nco * 2) * sizeof(uint4); }
+
 // Weight gradient of one tap over one chunk of points:
 // dW[t][o][i] = sum_p dY[p][o] X[p + d_t][i], an M = cout, N = cin, K = points
 // product. Lane l feeds A[m = l % 16][k = 4 (l / 16) + j] = dY[p_j][o] and
@@ -248,14 +361,138 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const uint16_t *__restrict__
     }
 }
 
+// Weight gradient on the 16 x 4 x 4 point tiles of the forward kernel:
+// dW[t][o][i] = sum_p dY[p][o] X[p + d_t][i] as M = o, N = i, K = points
+// products on the 16x16x32 BF16 MFMA. A persistent block takes tiles
+// blockIdx.x, + gridDim.x, ... for the 16 input channels blockIdx.y; per tile
+// it stages in LDS the output gradient transposed, dYt[o][point], and the
+// input halo transposed, XhT[i][hz][hy][hx] (rows of 24, 16-byte aligned).
+// K steps take 32 points (two 16-point rows); a lane's 8 consecutive k are
+// 8 consecutive x, so its A fragment (dY of one output channel) is one
+// aligned 16-byte read, shared by all the wavefront's taps, and its B
+// fragment (X of one input channel, shifted by the tap) starts dx + 1
+// elements into an aligned pair of 16-byte words (a byte shift that is the
+// same for the whole wavefront). Wavefront w owns taps w, w + 4, ... and
+// keeps their sums over all its tiles in registers; the block's partial
+// dW goes to part[block][t][o][i] and the partials are summed in fixed order.
+template <int MT>
+__global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__restrict__ x, int cin,
+                                                          const uint16_t *__restrict__ dy, int cout,
+                                                          int nx, int ny, int nz,
+                                                          float *__restrict__ part) {
+    constexpr int kRow = 24;                    // hx row length in XhT
+    constexpr int kXh = 16 * kHZ * kHY * kRow;  // XhT elements
+    constexpr int kNTap = 7;                    // taps per wavefront (27 = 4 x 7 - 1)
+    __shared__ __attribute__((aligned(16))) uint16_t xht[kXh];
+    __shared__ __attribute__((aligned(16))) uint16_t dyt[MT * 16 * 256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int cc = blockIdx.y * 16;
+    const int ntx = nx / kTX, nty = ny / kTY;
+    const int ntile = ntx * nty * (nz / kTZ);
+    f4 acc[kNTap][MT];
+#pragma unroll
+    for (int u = 0; u < kNTap; ++u)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[u][mt] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int bx = tile % ntx, rest = tile / ntx;
+        const int by = rest % nty, bz = rest / nty;
+        const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
+        __syncthreads();  // the previous tile's reads are done
+        // input halo, channels cc .. cc + 15, transposed
+        for (int c = threadIdx.x; c < kHP * 2; c += 256) {
+            const int h = c >> 1, e0 = 8 * (c & 1);
+            const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
+            const int gp = wrap(x0 - 1 + hx, nx) + nx * (wrap(y0 - 1 + hy, ny) + ny * wrap(z0 - 1 + hz, nz));
+            const uint4 v = *(const uint4 *)(x + gp * cin + cc + e0);
+            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                xht[(((e0 + e) * kHZ + hz) * kHY + hy) * kRow + hx] = uint16_t(wd[e >> 1] >> (16 * (e & 1)));
+        }
+        // output gradient of the tile's points, transposed
+        for (int c = threadIdx.x; c < 256 * MT * 2; c += 256) {
+            const int pl = c / (MT * 2), oc = c - pl * (MT * 2);
+            const int gp = (x0 + (pl & 15)) + nx * ((y0 + ((pl >> 4) & 3)) + ny * (z0 + (pl >> 6)));
+            const uint4 v = *(const uint4 *)(dy + gp * cout + 8 * oc);
+            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dyt[(8 * oc + e) * 256 + pl] = uint16_t(wd[e >> 1] >> (16 * (e & 1)));
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int st = 0; st < 8; ++st) {
+            const int pl0 = 32 * st + 8 * q;  // the lane's first point of the step
+            const int lx0 = pl0 & 15, ly = (pl0 >> 4) & 3, lz = pl0 >> 6;
+            bf8 a[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                a[mt] = __builtin_bit_cast(bf8, *(const uint4 *)(dyt + (mt * 16 + r) * 256 + pl0));
+#pragma unroll
+            for (int u = 0; u < kNTap; ++u) {
+                const int t = wave + 4 * u;
+                if (t < 27) {
+                    const int dx = t % 3 - 1, dyo = (t / 3) % 3 - 1, dz = t / 9 - 1;
+                    const int start = lx0 + dx + 1;  // 0 .. 10; start % 8 = dx + 1
+                    const uint16_t *row = xht + ((r * kHZ + lz + dz + 1) * kHY + ly + dyo + 1) * kRow;
+                    const uint4 w0 = *(const uint4 *)(row + (start & ~7));
+                    uint4 bw;
+                    if (dx < 0) {
+                        bw = w0;
+                    } else {
+                        const uint4 w1 = *(const uint4 *)(row + (start & ~7) + 8);
+                        if (dx == 0) {  // shift by one element (2 bytes)
+                            bw = uint4{__builtin_amdgcn_alignbyte(w0.y, w0.x, 2),
+                                       __builtin_amdgcn_alignbyte(w0.z, w0.y, 2),
+                                       __builtin_amdgcn_alignbyte(w0.w, w0.z, 2),
+                                       __builtin_amdgcn_alignbyte(w1.x, w0.w, 2)};
+                        } else {  // shift by two elements (one dword)
+                            bw = uint4{w0.y, w0.z, w0.w, w1.x};
+                        }
+                    }
+                    const bf8 b = __builtin_bit_cast(bf8, bw);
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        acc[u][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[u][mt], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // D[m = 4 q + j][n = r] of tap t, M tile mt: dW[t][mt 16 + 4 q + j][cc + r]
+#pragma unroll
+    for (int u = 0; u < kNTap; ++u) {
+        const int t = wave + 4 * u;
+        if (t >= 27) continue;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                part[(((long)blockIdx.x * 27 + t) * cout + mt * 16 + 4 * q + j) * cin + cc + r] = acc[u][mt][j];
+    }
+}
+
 // dw[e] = sum over chunks of part[chunk][e] (fixed order).
-__global__ void sum_chunks_kernel(const float *__restrict__ part, long nchunks, long n,
-                                  float *__restrict__ out) {
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
+// A block sums 32 consecutive elements; its 8 thread groups take the chunks
+// g, g + 8, g + 16, ... in order and are combined in group order (fixed
+// order, so the result does not depend on scheduling).
+__global__ void __launch_bounds__(256) sum_chunks_kernel(const float *__restrict__ part,
+                                                         long nchunks, long n,
+                                                         float *__restrict__ out) {
+    __shared__ float red[8][32];
+    const int el = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const long e = (long)blockIdx.x * 32 + el;
     float s = 0.f;
-    for (long c = 0; c < nchunks; ++c) s += part[c * n + e];
-    out[e] = s;
+    if (e < n)
+        for (long c = g; c < nchunks; c += 8) s += part[c * n + e];
+    red[g][el] = s;
+    __syncthreads();
+    if (g == 0 && e < n) {
+        float t = red[0][el];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) t += red[k][el];
+        out[e] = t;
+    }
 }
 
 // Per-block partial sums of dy over points for each channel: thread
@@ -386,20 +623,42 @@ __global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ pred
                                                   const float *__restrict__ tgt, int cu, int cs,
                                                   long P, const float *__restrict__ wch,
                                                   float *__restrict__ grad,
-                                                  double *__restrict__ part) {
+                                                  double *__restrict__ part, int vec4) {
     __shared__ double red[4];
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     double l = 0.0;
     if (p < P) {
         const float inv = 1.0f / (float)((double)P * cu);
-        for (int ch = 0; ch < cs; ++ch) {
-            float g = 0.f;
-            if (ch < cu) {
-                const float d = pred[p * cs + ch] - tgt[p * cs + ch];
-                l += (double)wch[ch] * d * d;
-                g = 2.f * wch[ch] * d * inv;
+        if (vec4) {
+            // 16-byte accesses, four channels at a time (same arithmetic)
+            const float4 *p4 = (const float4 *)(pred + p * cs), *t4 = (const float4 *)(tgt + p * cs);
+            float4 *g4 = (float4 *)(grad + p * cs);
+            for (int c4 = 0; c4 < cs / 4; ++c4) {
+                const float4 a = p4[c4], b = t4[c4];
+                const float pa[4] = {a.x, a.y, a.z, a.w}, tb[4] = {b.x, b.y, b.z, b.w};
+                float gg[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int ch = 4 * c4 + k;
+                    gg[k] = 0.f;
+                    if (ch < cu) {
+                        const float d = pa[k] - tb[k];
+                        l += (double)wch[ch] * d * d;
+                        gg[k] = 2.f * wch[ch] * d * inv;
+                    }
+                }
+                g4[c4] = float4{gg[0], gg[1], gg[2], gg[3]};
             }
-            grad[p * cs + ch] = g;
+        } else {
+            for (int ch = 0; ch < cs; ++ch) {
+                float g = 0.f;
+                if (ch < cu) {
+                    const float d = pred[p * cs + ch] - tgt[p * cs + ch];
+                    l += (double)wch[ch] * d * d;
+                    g = 2.f * wch[ch] * d * inv;
+                }
+                grad[p * cs + ch] = g;
+            }
         }
     }
     l = wsum(l);
@@ -738,6 +997,22 @@ constexpr long kWgradChunk = 8192;
 
 long wgrad_chunks(long P) { return (P + kWgradChunk - 1) / kWgradChunk; }
 
+// The tiled weight gradient: lattice sizes multiples of the 16 x 4 x 4 tile,
+// 32-bit element indices, aligned operands, at most 64 output channels.
+bool wgrad_tiled_ok(const void *x, int cin, const void *dy, int cout, int nx, int ny, int nz) {
+    const long P = (long)nx * ny * nz;
+    return nx % kTX == 0 && ny % kTY == 0 && nz % kTZ == 0 && cout <= 64 && elems_ok(P, cin) &&
+           elems_ok(P, cout) && ((uintptr_t)x & 15) == 0 && ((uintptr_t)dy & 15) == 0;
+}
+
+// Persistent blocks of the tiled weight gradient per 16-channel input chunk:
+// about 1024 blocks in all, at most one per tile.
+long wgrad_tiled_blocks(int cin, long P) {
+    const long tiles = P / (kTX * kTY * kTZ);
+    return std::max(1L, std::min(tiles, 1024L / (cin / 16)));
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -749,6 +1024,18 @@ int sur_conv3d(const void *x, int32_t cin, const void *w, const float *bias, int
         !dims_ok(nx, ny, nz))
         return SUR_EINVAL;
     const long P = (long)nx * ny * nz;
+    // the tiled kernel: sizes multiples of its tile, 32-bit element indices,
+    // 16-byte aligned x and w (its 16-byte loads)
+    if (nx % kTX == 0 && ny % kTY == 0 && nz % kTZ == 0 && elems_ok(P, cin) && elems_ok(P, cout) &&
+        ((uintptr_t)x & 15) == 0 && ((uintptr_t)w & 15) == 0) {
+        const int nb = 16 * kNT;
+        const dim3 grid((unsigned)(P / (kTX * kTY * kTZ)), (unsigned)((cout + nb - 1) / nb));
+        hipLaunchKernelGGL(conv3d_tiled_kernel, grid, dim3(256), conv_tiled_lds(min(cout, nb)),
+                           (hipStream_t)stream,
+                           (const uint16_t *)x, cin, (const uint16_t *)w, bias, cout, nx, ny, nz,
+                           flip, relu, (const uint16_t *)mask, (uint16_t *)y_bf16, y_f32);
+        return launched();
+    }
     const dim3 grid((unsigned)((P + 255) / 256), (unsigned)((cout + 63) / 64));
     hipLaunchKernelGGL(conv3d_kernel, grid, dim3(256), 0, (hipStream_t)stream, (const uint16_t *)x,
                        cin, (const uint16_t *)w, bias, cout, nx, ny, nz, flip, relu,
@@ -758,7 +1045,8 @@ int sur_conv3d(const void *x, int32_t cin, const void *w, const float *bias, int
 
 size_t sur_wgrad_scratch_floats(int32_t cin, int32_t cout, int32_t nx, int32_t ny, int32_t nz) {
     const long P = (long)nx * ny * nz;
-    return (size_t)(wgrad_chunks(P) * 27L * cin * cout + grid1(P, 1024).x * (long)cout);
+    const long parts = std::max(wgrad_chunks(P), wgrad_tiled_blocks(cin, P));
+    return (size_t)(parts * 27L * cin * cout + grid1(P, 1024).x * (long)cout);
 }
 
 int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, int32_t nx,
@@ -770,22 +1058,34 @@ int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, i
     if (scratch_floats < sur_wgrad_scratch_floats(cin, cout, nx, ny, nz)) return SUR_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const long P = (long)nx * ny * nz;
-    const long nch = wgrad_chunks(P);
-    const dim3 grid(27, (unsigned)nch, (unsigned)((cin + 63) / 64));
     const uint16_t *xb = (const uint16_t *)x, *db = (const uint16_t *)dy;
-    switch (cout / 16) {
-        case 1: hipLaunchKernelGGL(wgrad_kernel<1>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, kWgradChunk, scratch); break;
-        case 2: hipLaunchKernelGGL(wgrad_kernel<2>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, kWgradChunk, scratch); break;
-        case 3: hipLaunchKernelGGL(wgrad_kernel<3>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, kWgradChunk, scratch); break;
-        default: hipLaunchKernelGGL(wgrad_kernel<4>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, kWgradChunk, scratch); break;
+    long nch;  // partial sums in scratch
+    if (wgrad_tiled_ok(x, cin, dy, cout, nx, ny, nz)) {
+        nch = wgrad_tiled_blocks(cin, P);
+        const dim3 grid((unsigned)nch, (unsigned)(cin / 16));
+        switch (cout / 16) {
+            case 1: hipLaunchKernelGGL(wgrad_tiled_kernel<1>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, scratch); break;
+            case 2: hipLaunchKernelGGL(wgrad_tiled_kernel<2>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, scratch); break;
+            case 3: hipLaunchKernelGGL(wgrad_tiled_kernel<3>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, scratch); break;
+            default: hipLaunchKernelGGL(wgrad_tiled_kernel<4>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, scratch); break;
+        }
+    } else {
+        nch = wgrad_chunks(P);
+        const dim3 grid(27, (unsigned)nch, (unsigned)((cin + 63) / 64));
+        switch (cout / 16) {
+            case 1: hipLaunchKernelGGL(wgrad_kernel<1>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, kWgradChunk, scratch); break;
+            case 2: hipLaunchKernelGGL(wgrad_kernel<2>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, kWgradChunk, scratch); break;
+            case 3: hipLaunchKernelGGL(wgrad_kernel<3>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, kWgradChunk, scratch); break;
+            default: hipLaunchKernelGGL(wgrad_kernel<4>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, kWgradChunk, scratch); break;
+        }
     }
     const long n = 27L * cin * cout;
-    hipLaunchKernelGGL(sum_chunks_kernel, grid1(n), dim3(256), 0, s, (const float *)scratch, nch, n, dw);
+    hipLaunchKernelGGL(sum_chunks_kernel, grid1(n, 32), dim3(256), 0, s, (const float *)scratch, nch, n, dw);
     if (dbias) {
         const long nb = grid1(P, 1024).x;
         float *bp = scratch + nch * n;
         hipLaunchKernelGGL(bias_partial_kernel, dim3((unsigned)nb), dim3(256), 0, s, db, cout, P, 1024L, bp);
-        hipLaunchKernelGGL(sum_chunks_kernel, grid1(cout), dim3(256), 0, s, (const float *)bp, nb, (long)cout, dbias);
+        hipLaunchKernelGGL(sum_chunks_kernel, grid1(cout, 32), dim3(256), 0, s, (const float *)bp, nb, (long)cout, dbias);
     }
     return launched();
 }
@@ -882,8 +1182,10 @@ int sur_mse(const float *pred, const float *target, int32_t cu, int32_t cs, int6
         return SUR_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const long nb = grid1(P).x;
+    const int vec4 = cs % 4 == 0 && ((uintptr_t)pred & 15) == 0 && ((uintptr_t)target & 15) == 0 &&
+                     ((uintptr_t)grad & 15) == 0;
     hipLaunchKernelGGL(mse_kernel, dim3((unsigned)nb), dim3(256), 0, s, pred, target, cu, cs,
-                       (long)P, wch, grad, scratch);
+                       (long)P, wch, grad, scratch, vec4);
     hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(1024), 0, s, (const double *)scratch, nb,
                        1.0 / ((double)P * cu), loss_out);
     return launched();

@@ -44,15 +44,20 @@ def _rel(a, b):
 
 
 GRID = (10, 6, 8)  # nx, ny, nz -> P = 480 (not a multiple of 256)
+# grids of the convolution's two kernels: sizes not multiples of its 16 x 4 x 4
+# tile (the general kernel), 2 x 2 x 2 tiles, and one tile whose halo wraps
+# onto itself (the LDS-tiled kernel)
+CONV_GRIDS = [GRID, (32, 8, 8), (16, 4, 4)]
 
 
+@pytest.mark.parametrize("grid", CONV_GRIDS)
 @pytest.mark.parametrize("cin,cout,relu", [(16, 16, 1), (32, 48, 0), (112, 48, 1), (80, 32, 1),
-                                           (48, 64, 0)])
-def test_conv_forward(sur, cin, cout, relu):
+                                           (48, 64, 0), (48, 112, 1)])
+def test_conv_forward(sur, cin, cout, relu, grid):
     import torch
-    say(f"[sur] conv fwd cin={cin} cout={cout} relu={relu} grid={GRID}")
+    say(f"[sur] conv fwd cin={cin} cout={cout} relu={relu} grid={grid}")
     rng = np.random.default_rng(cin + cout)
-    nx, ny, nz = GRID
+    nx, ny, nz = grid
     x = so.bf16_round(rng.standard_normal((nz, ny, nx, cin)).astype(np.float32))
     w = rng.standard_normal((27, cout, cin)).astype(np.float32) * 0.1
     b = rng.standard_normal(cout).astype(np.float32)
@@ -60,7 +65,7 @@ def test_conv_forward(sur, cin, cout, relu):
     sur.sur_pack_weights(_f32(w), cin, cout, wf, None)
     yf = torch.empty((nx * ny * nz, cout), dtype=torch.float32, device="cuda")
     yb = torch.empty((nx * ny * nz, cout), dtype=torch.int16, device="cuda")
-    sur.sur_conv3d(_bits(x.reshape(-1, cin)), cin, wf, _f32(b), cout, GRID, relu=relu,
+    sur.sur_conv3d(_bits(x.reshape(-1, cin)), cin, wf, _f32(b), cout, grid, relu=relu,
                    y_bf16=yb, y_f32=yf)
     ref = so.conv3d(x.astype(np.float64), so.bf16_round(w).astype(np.float64), b.astype(np.float64))
     if relu:
@@ -71,27 +76,33 @@ def test_conv_forward(sur, cin, cout, relu):
     assert np.array_equal(gb, so.bf16_round(got.astype(np.float32)))
 
 
+@pytest.mark.parametrize("grid", CONV_GRIDS)
 @pytest.mark.parametrize("cin,cout", [(16, 32), (112, 48), (48, 16)])
-def test_conv_data_gradient_with_mask(sur, cin, cout):
+def test_conv_data_gradient_with_mask(sur, cin, cout, grid):
     import torch
-    say(f"[sur] conv dgrad cin={cin} cout={cout}")
+    say(f"[sur] conv dgrad cin={cin} cout={cout} grid={grid}")
     rng = np.random.default_rng(7 + cin)
-    nx, ny, nz = GRID
+    nx, ny, nz = grid
     dy = so.bf16_round(rng.standard_normal((nz, ny, nx, cout)).astype(np.float32))
     w = rng.standard_normal((27, cout, cin)).astype(np.float32) * 0.1
     act = so.bf16_round(np.maximum(rng.standard_normal((nz, ny, nx, cin)), 0).astype(np.float32))
     wd = torch.empty((27, cin, cout), dtype=torch.int16, device="cuda")
     sur.sur_pack_weights(_f32(w), cin, cout, None, wd)
     dx = torch.empty((nx * ny * nz, cin), dtype=torch.float32, device="cuda")
-    sur.sur_conv3d(_bits(dy.reshape(-1, cout)), cout, wd, None, cin, GRID, flip=1,
+    sur.sur_conv3d(_bits(dy.reshape(-1, cout)), cout, wd, None, cin, grid, flip=1,
                    mask=_bits(act.reshape(-1, cin)), y_f32=dx)
     ref = so.conv3d_dgrad(dy.astype(np.float64), so.bf16_round(w).astype(np.float64)) * (act > 0)
     got = dx.cpu().numpy().reshape(ref.shape)
     assert np.abs(got - ref).max() <= 1e-5 * (1 + np.abs(ref).max())
 
 
-@pytest.mark.parametrize("cin,cout,grid", [(16, 16, (16, 8, 12)), (112, 48, (8, 8, 8)),
-                                           (48, 64, (10, 6, 8)), (80, 32, (4, 4, 4))])
+# the first five grids are multiples of the 16 x 4 x 4 tile (the LDS-tiled
+# kernel, one to 24 tiles, every output-channel count), the rest are not
+@pytest.mark.parametrize("cin,cout,grid", [(16, 16, (16, 8, 12)), (112, 48, (32, 8, 8)),
+                                           (48, 64, (16, 4, 4)), (80, 32, (16, 8, 4)),
+                                           (32, 16, (48, 4, 8)),
+                                           (112, 48, (8, 8, 8)), (48, 64, (10, 6, 8)),
+                                           (80, 32, (4, 4, 4))])
 def test_conv_weight_gradient(sur, cin, cout, grid):
     import torch
     say(f"[sur] conv wgrad cin={cin} cout={cout} grid={grid}")
