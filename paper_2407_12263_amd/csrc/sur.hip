@@ -7,6 +7,8 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
+#include <type_traits>
 
 #include "sur.h"
 
@@ -162,11 +164,14 @@ __global__ void __launch_bounds__(256) conv3d_kernel(const uint16_t *__restrict_
 }
 
 // The same convolution for grids whose sizes are multiples of the 16 x 4 x 4
-// point tile. A block stages the tile's 18 x 6 x 6 halo of 16 input channels
-// at a time (32 B per point, 20.7 KB) in LDS, so each input value is read
-// from memory about twice instead of 27 times. Wavefront w owns plane z0 + w
-// of the tile: four rows of 16 points, the four M tiles; a block computes
-// 32 output channels (two N tiles). The K steps use the
+// point tile. Blocks are persistent: block b takes the tiles b, b + gridDim.x,
+// ..., each over its 16-channel input chunks, and stages an item's 18 x 6 x 6
+// halo (32 B per point, 20.7 KB) and the chunk's weights in LDS, so each
+// input value is read from memory about 2.5 times instead of 27 times. While
+// an item is computed from LDS, each thread's six 16-byte pieces of the next
+// item's halo are already loading into registers. Wavefront w owns plane
+// z0 + w of the tile: four rows of 16 points, the four M tiles; a block
+// computes 32 output channels (two N tiles). The K steps use the
 // 16x16x32 BF16 MFMA; one step covers two taps (lanes l / 16 = 0, 1: tap t,
 // 2, 3: tap t + 1) x 16 channels (8 per lane). A and B place the same (tap,
 // channel) in the same lane group and element, so the product does not
@@ -176,6 +181,36 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 constexpr int kTX = 16, kTY = 4, kTZ = 4;
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2, kHP = kHX * kHY * kHZ;
 constexpr int kNT = 2;  // 16-channel output tiles per block (LDS <= 48.4 KB)
+
+static_assert(kHP * 2 > 1280 && kHP * 2 <= 1536, "six 16-byte halo pieces per thread");
+
+// The halo of work item it of this (persistent) block (tile blockIdx.x + k
+// gridDim.x, k = it / nchunk, input chunk it % nchunk) into registers:
+// thread t holds the 16-byte pieces t, t + 256, ... of the kHP x 32 B halo.
+// Piece k (16 bytes) of the halo of work item it for this thread, or zeros
+// beyond the halo.
+__device__ __forceinline__ uint4 conv_halo_piece(const uint16_t *__restrict__ x, int cin, int nx,
+                                                 int ny, int nz, int ntx, int nty, int nchunk,
+                                                 int it, int k) {
+    const int c = threadIdx.x + 256 * k;
+    if (c >= kHP * 2) return uint4{0u, 0u, 0u, 0u};
+    const int tl = (int)blockIdx.x + (it / nchunk) * (int)gridDim.x, cc = (it % nchunk) * 16;
+    const int bx = tl % ntx, rest = tl / ntx, by = rest % nty, bz = rest / nty;
+    const int h = c >> 1;
+    const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
+    const int gp = wrap(bx * kTX - 1 + hx, nx) +
+                   nx * (wrap(by * kTY - 1 + hy, ny) + ny * wrap(bz * kTZ - 1 + hz, nz));
+    return *(const uint4 *)(x + gp * cin + cc + 8 * (c & 1));
+}
+
+// Weight rows (t, o) of an input chunk into LDS: w[t][cob + o][cc .. cc + 15].
+__device__ __forceinline__ void conv_stage_weights(uint4 *wl, const uint16_t *__restrict__ w,
+                                                   int cin, int cout, int cob, int nco, int cc) {
+    for (int c = threadIdx.x; c < 27 * nco * 2; c += 256) {
+        const int row = c >> 1, t = row / nco, o = row - t * nco;
+        wl[c] = *(const uint4 *)(w + (t * cout + cob + o) * cin + cc + 8 * (c & 1));
+    }
+}
 
 __global__ void __launch_bounds__(256) conv3d_tiled_kernel(
     const uint16_t *__restrict__ x, int cin, const uint16_t *__restrict__ w,
@@ -188,50 +223,68 @@ __global__ void __launch_bounds__(256) conv3d_tiled_kernel(
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, q = lane >> 4;
     const int ntx = nx / kTX, nty = ny / kTY;
-    const int bx = (int)blockIdx.x % ntx, rest = (int)blockIdx.x / ntx;
-    const int by = rest % nty, bz = rest / nty;
-    const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
+    const int ntile = ntx * nty * (nz / kTZ);
+    const int nchunk = cin / 16;
     const int cob = blockIdx.y * (16 * kNT);
     const int ntiles = min(kNT, (cout - cob) >> 4);
     const int nco = ntiles * 16;
     const int half = q & 1;
-    f4 acc[4][kNT];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < kNT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+    const int sgn = flip ? -1 : 1;
+    // halo index of the lane's point in M tile 0 (tile x = r, y = 0, z = wave)
+    const int hb = (r + 1) + kHX * (1 + kHY * (wave + 1));
     const uint4 z4 = uint4{0u, 0u, 0u, 0u};
-    for (int cc = 0; cc < cin; cc += 16) {
-        __syncthreads();  // the previous chunk's reads are done
-        for (int c = threadIdx.x; c < kHP * 2; c += 256) {
-            const int h = c >> 1;
-            const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
-            const int gp = wrap(x0 - 1 + hx, nx) + nx * (wrap(y0 - 1 + hy, ny) + ny * wrap(z0 - 1 + hz, nz));
-            tile[c] = *(const uint4 *)(x + gp * cin + cc + 8 * (c & 1));
-        }
-        // weight row (t, o) of this chunk: w[t][cob + o][cc .. cc + 15]
-        for (int c = threadIdx.x; c < 27 * nco * 2; c += 256) {
-            const int row = c >> 1, t = row / nco, o = row - t * nco;
-            wl[c] = *(const uint4 *)(w + (t * cout + cob + o) * cin + cc + 8 * (c & 1));
-        }
+    // work items of this (persistent) block: (tile blockIdx.x + k gridDim.x,
+    // input chunk); the halo of the next item is loaded into registers while
+    // the current one is computed from LDS
+    const int nmine = ntile > (int)blockIdx.x ? (ntile - 1 - (int)blockIdx.x) / (int)gridDim.x + 1 : 0;
+    const int nwork = nmine * nchunk;
+    // the thread's six halo pieces of the next item, held in registers
+    uint4 pf0, pf1, pf2, pf3, pf4, pf5;
+#define CONV_LOAD_HALO(it)                                                   \
+    do {                                                                     \
+        pf0 = conv_halo_piece(x, cin, nx, ny, nz, ntx, nty, nchunk, it, 0);  \
+        pf1 = conv_halo_piece(x, cin, nx, ny, nz, ntx, nty, nchunk, it, 1);  \
+        pf2 = conv_halo_piece(x, cin, nx, ny, nz, ntx, nty, nchunk, it, 2);  \
+        pf3 = conv_halo_piece(x, cin, nx, ny, nz, ntx, nty, nchunk, it, 3);  \
+        pf4 = conv_halo_piece(x, cin, nx, ny, nz, ntx, nty, nchunk, it, 4);  \
+        pf5 = conv_halo_piece(x, cin, nx, ny, nz, ntx, nty, nchunk, it, 5);  \
+    } while (0)
+    if (nwork > 0) CONV_LOAD_HALO(0);
+    if (nchunk == 1) conv_stage_weights(wl, w, cin, cout, cob, nco, 0);  // the same for every item
+    f4 acc[4][kNT];
+    for (int it = 0; it < nwork; ++it) {
+        const int chunk = it % nchunk;
+        __syncthreads();  // the previous item's reads are done
+        tile[threadIdx.x] = pf0;
+        tile[threadIdx.x + 256] = pf1;
+        tile[threadIdx.x + 512] = pf2;
+        tile[threadIdx.x + 768] = pf3;
+        tile[threadIdx.x + 1024] = pf4;
+        if (threadIdx.x + 1280 < kHP * 2) tile[threadIdx.x + 1280] = pf5;
+        if (nchunk > 1) conv_stage_weights(wl, w, cin, cout, cob, nco, chunk * 16);
         __syncthreads();
-#pragma unroll 2
+        if (it + 1 < nwork) CONV_LOAD_HALO(it + 1);
+        if (chunk == 0) {
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < kNT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
         for (int t = 0; t < 27; t += 2) {
-            const int tap = t + (q >> 1);
-            const bool tv = tap < 27;
-            const int tc = tv ? tap : 26;
-            int dx = tc % 3 - 1, dy = (tc / 3) % 3 - 1, dz = tc / 9 - 1;
-            if (flip) {
-                dx = -dx;
-                dy = -dy;
-                dz = -dz;
-            }
+            // halo offsets of taps t and t + 1 (constants once unrolled),
+            // negated for the flipped convolution
+            const int offa = (t % 3 - 1) + kHX * (((t / 3) % 3 - 1) + kHY * (t / 9 - 1));
+            const int t1 = t + 1 < 27 ? t + 1 : t;
+            const int offb = (t1 % 3 - 1) + kHX * (((t1 / 3) % 3 - 1) + kHY * (t1 / 9 - 1));
+            const bool second = (q >> 1) != 0;
+            const bool tv = !second || t + 1 < 27;
+            const int tc = second ? t1 : t;
+            const int off = sgn * (second ? offb : offa);
             bf8 a[4], b[kNT];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const int h = (r + 1 + dx) + kHX * ((mt + 1 + dy) + kHY * (wave + 1 + dz));
-                a[mt] = __builtin_bit_cast(bf8, tv ? tile[2 * h + half] : z4);
-            }
+            for (int mt = 0; mt < 4; ++mt)
+                a[mt] = __builtin_bit_cast(bf8, tv ? tile[2 * (hb + kHX * mt + off) + half] : z4);
 #pragma unroll
             for (int nt = 0; nt < kNT; ++nt) {
                 uint4 v = z4;
@@ -248,27 +301,34 @@ __global__ void __launch_bounds__(256) conv3d_tiled_kernel(
                 }
             }
         }
-    }
+        if (chunk == nchunk - 1) {
+            const int tl = (int)blockIdx.x + (it / nchunk) * (int)gridDim.x;
+            const int bx = tl % ntx, rest = tl / ntx, by = rest % nty, bz = rest / nty;
+            const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        const int prow = nx * ((y0 + mt) + ny * (z0 + wave));
+            for (int mt = 0; mt < 4; ++mt) {
+                const int prow = nx * ((y0 + mt) + ny * (z0 + wave));
 #pragma unroll
-        for (int nt = 0; nt < kNT; ++nt) {
-            if (nt >= ntiles) continue;
-            const int co = cob + nt * 16 + r;
-            const float bb = bias ? bias[co] : 0.f;
+                for (int nt = 0; nt < kNT; ++nt) {
+                    if (nt >= ntiles) continue;
+                    const int co = cob + nt * 16 + r;
+                    const float bb = bias ? bias[co] : 0.f;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int p = prow + x0 + 4 * q + j;
-                float v = acc[mt][nt][j] + bb;
-                if (relu) v = fmaxf(v, 0.f);
-                if (mask && !(bf2f(mask[p * cout + co]) > 0.f)) v = 0.f;
-                if (yb) yb[p * cout + co] = f2bf(v);
-                if (yf) yf[p * cout + co] = v;
+                    for (int j = 0; j < 4; ++j) {
+                        const int p = prow + x0 + 4 * q + j;
+                        float v = acc[mt][nt][j] + bb;
+                        if (relu) v = fmaxf(v, 0.f);
+                        if (mask && !(bf2f(mask[p * cout + co]) > 0.f)) v = 0.f;
+                        if (yb) yb[p * cout + co] = f2bf(v);
+                        if (yf) yf[p * cout + co] = v;
+                    }
+                }
             }
         }
     }
 }
+
+#undef CONV_LOAD_HALO
 
 // LDS bytes of conv3d_tiled_kernel for a block of nco output channels.
 size_t conv_tiled_lds(int nco) { return (size_t)(kHP * 2 + 27 * nco * 2) * sizeof(uint4); }
@@ -598,6 +658,67 @@ __global__ void copy_channels_kernel(const uint16_t *__restrict__ x, int c, long
     if (e >= P * c) return;
     const long p = div32(e, c);
     y[p * ystride + yoff + mod32(e, c)] = x[e];
+}
+
+// 16-byte variants (8 BF16 channels per thread) of pooling, upsampling and
+// the channel copy, for channel counts, strides and offsets that are
+// multiples of 8 and 16-byte aligned arrays; element e = point * (c / 8) + g.
+__device__ __forceinline__ void unpack8(const uint4 v, float (&f)[8]) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        f[2 * k] = __uint_as_float(w[k] << 16);
+        f[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+    }
+}
+
+__global__ void pool2_v8_kernel(const uint16_t *__restrict__ x, int c, int nx, int ny, int nz,
+                                uint16_t *__restrict__ y) {
+    const int cx = nx / 2, cy = ny / 2, cz = nz / 2, c8 = c / 8;
+    const long n = (long)cx * cy * cz * c8;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int g = mod32(e, c8);
+    const long qq = div32(e, c8);
+    int X, Y, Z;
+    coords(qq, cx, cy, X, Y, Z);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < 8; ++k) {
+        const long p = (2 * X + (k & 1)) + (long)nx * ((2 * Y + ((k >> 1) & 1)) + (long)ny * (2 * Z + (k >> 2)));
+        float f[8];
+        unpack8(*(const uint4 *)(x + p * c + 8 * g), f);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s[j] += f[j];
+    }
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        w[k] = uint32_t(f2bf(0.125f * s[2 * k])) | (uint32_t(f2bf(0.125f * s[2 * k + 1])) << 16);
+    *(uint4 *)(y + qq * c + 8 * g) = uint4{w[0], w[1], w[2], w[3]};
+}
+
+__global__ void upsample2_v8_kernel(const uint16_t *__restrict__ x, int c, int nx, int ny, int nz,
+                                    uint16_t *__restrict__ y, int ystride, int yoff) {
+    const int fx = 2 * nx, fy = 2 * ny, fz = 2 * nz, c8 = c / 8;
+    const long n = (long)fx * fy * fz * c8;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int g = mod32(e, c8);
+    const long p = div32(e, c8);
+    int X, Y, Z;
+    coords(p, fx, fy, X, Y, Z);
+    const long qq = (X / 2) + (long)nx * ((Y / 2) + (long)ny * (Z / 2));
+    *(uint4 *)(y + p * ystride + yoff + 8 * g) = *(const uint4 *)(x + qq * c + 8 * g);
+}
+
+__global__ void copy_channels_v8_kernel(const uint16_t *__restrict__ x, int c, long P,
+                                        uint16_t *__restrict__ y, int ystride, int yoff) {
+    const int c8 = c / 8;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * c8) return;
+    const long p = div32(e, c8);
+    const int g = mod32(e, c8);
+    *(uint4 *)(y + p * ystride + yoff + 8 * g) = *(const uint4 *)(x + p * c + 8 * g);
 }
 
 __global__ void add_channels_kernel(const float *__restrict__ dy, int dystride, int dyoff, int c,
@@ -997,6 +1118,17 @@ constexpr long kWgradChunk = 8192;
 
 long wgrad_chunks(long P) { return (P + kWgradChunk - 1) / kWgradChunk; }
 
+bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+// Persistent blocks of the tiled convolution in all (at most one per tile):
+// 2048 measured best of 512 .. 4096 on the U-Net's 128^3 layers (within 5%
+// everywhere). SUR_CONV_BLOCKS overrides it (tuning only; results do not
+// depend on it).
+int env_blocks() {
+    const char *v = std::getenv("SUR_CONV_BLOCKS");
+    return v && *v ? std::max(1, std::atoi(v)) : 2048;
+}
+
 // The tiled weight gradient: lattice sizes multiples of the 16 x 4 x 4 tile,
 // 32-bit element indices, aligned operands, at most 64 output channels.
 bool wgrad_tiled_ok(const void *x, int cin, const void *dy, int cout, int nx, int ny, int nz) {
@@ -1029,7 +1161,10 @@ int sur_conv3d(const void *x, int32_t cin, const void *w, const float *bias, int
     if (nx % kTX == 0 && ny % kTY == 0 && nz % kTZ == 0 && elems_ok(P, cin) && elems_ok(P, cout) &&
         ((uintptr_t)x & 15) == 0 && ((uintptr_t)w & 15) == 0) {
         const int nb = 16 * kNT;
-        const dim3 grid((unsigned)(P / (kTX * kTY * kTZ)), (unsigned)((cout + nb - 1) / nb));
+        const long tiles = P / (kTX * kTY * kTZ);
+        const long ncb = (cout + nb - 1) / nb;
+        const long nblk = std::max(1L, std::min(tiles, (long)env_blocks() / ncb));
+        const dim3 grid((unsigned)nblk, (unsigned)ncb);
         hipLaunchKernelGGL(conv3d_tiled_kernel, grid, dim3(256), conv_tiled_lds(min(cout, nb)),
                            (hipStream_t)stream,
                            (const uint16_t *)x, cin, (const uint16_t *)w, bias, cout, nx, ny, nz,
@@ -1103,6 +1238,11 @@ int sur_pool2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void
         !elems_ok((long)nx * ny * nz, c))
         return SUR_EINVAL;
     const long n = (long)(nx / 2) * (ny / 2) * (nz / 2) * c;
+    if (c % 8 == 0 && aligned16(x) && aligned16(y)) {
+        hipLaunchKernelGGL(pool2_v8_kernel, grid1(n / 8), dim3(256), 0, (hipStream_t)stream,
+                           (const uint16_t *)x, c, nx, ny, nz, (uint16_t *)y);
+        return launched();
+    }
     hipLaunchKernelGGL(pool2_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream,
                        (const uint16_t *)x, c, nx, ny, nz, (uint16_t *)y);
     return launched();
@@ -1125,6 +1265,11 @@ int sur_upsample2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, 
         !elems_ok(8L * nx * ny * nz, ystride))
         return SUR_EINVAL;
     const long n = 8L * nx * ny * nz * c;
+    if (c % 8 == 0 && ystride % 8 == 0 && yoff % 8 == 0 && aligned16(x) && aligned16(y)) {
+        hipLaunchKernelGGL(upsample2_v8_kernel, grid1(n / 8), dim3(256), 0, (hipStream_t)stream,
+                           (const uint16_t *)x, c, nx, ny, nz, (uint16_t *)y, ystride, yoff);
+        return launched();
+    }
     hipLaunchKernelGGL(upsample2_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream,
                        (const uint16_t *)x, c, nx, ny, nz, (uint16_t *)y, ystride, yoff);
     return launched();
@@ -1145,6 +1290,12 @@ int sur_copy_channels(const void *x, int32_t c, int64_t P, void *y, int32_t ystr
                       void *stream) {
     if (!x || !y || c <= 0 || P <= 0 || yoff < 0 || yoff + c > ystride || !elems_ok(P, ystride))
         return SUR_EINVAL;
+    if (c % 8 == 0 && ystride % 8 == 0 && yoff % 8 == 0 && aligned16(x) && aligned16(y)) {
+        hipLaunchKernelGGL(copy_channels_v8_kernel, grid1(P * c / 8), dim3(256), 0,
+                           (hipStream_t)stream, (const uint16_t *)x, c, (long)P, (uint16_t *)y,
+                           ystride, yoff);
+        return launched();
+    }
     hipLaunchKernelGGL(copy_channels_kernel, grid1(P * c), dim3(256), 0, (hipStream_t)stream,
                        (const uint16_t *)x, c, (long)P, (uint16_t *)y, ystride, yoff);
     return launched();

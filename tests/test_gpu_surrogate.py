@@ -122,28 +122,31 @@ def test_conv_weight_gradient(sur, cin, cout, grid):
     assert np.abs(db.cpu().numpy() - rdb).max() <= 1e-5 * (1 + np.abs(rdb).max()) * np.sqrt(P)
 
 
-def test_grid_layers(sur):
+@pytest.mark.parametrize("c", [16, 12])  # 16-byte kernels (c, strides, offsets % 8 == 0) / per element
+def test_grid_layers(sur, c):
     import torch
-    say("[sur] pool / upsample / concat / masks")
+    say(f"[sur] pool / upsample / concat / masks, {c} channels")
     rng = np.random.default_rng(3)
-    nx, ny, nz, c = 8, 4, 6, 16
+    nx, ny, nz = 8, 4, 6
     P = nx * ny * nz
+    cs = 3 * c  # concat stride; pieces at offsets 0 and c
     x = so.bf16_round(rng.standard_normal((nz, ny, nx, c)).astype(np.float32))
     y = torch.empty((P // 8, c), dtype=torch.int16, device="cuda")
     sur.sur_pool2(_bits(x.reshape(-1, c)), c, (nx, ny, nz), y)
     assert np.abs(_from_bits(y).reshape(nz // 2, ny // 2, nx // 2, c)
                   - so.bf16_round(so.pool2(x).astype(np.float32))).max() == 0.0
     xc = so.bf16_round(rng.standard_normal((nz // 2, ny // 2, nx // 2, c)).astype(np.float32))
-    cat = torch.zeros((P, 48), dtype=torch.int16, device="cuda")
-    sur.sur_upsample2(_bits(xc.reshape(-1, c)), c, (nx // 2, ny // 2, nz // 2), cat, 48, 0)
-    sur.sur_copy_channels(_bits(x.reshape(-1, c)), c, P, cat, 48, 16)
-    got = _from_bits(cat).reshape(nz, ny, nx, 48)
-    assert np.array_equal(got[..., :16], so.up2(xc))
-    assert np.array_equal(got[..., 16:32], x)
-    dy = rng.standard_normal((P, 48)).astype(np.float32)
+    cat = torch.zeros((P, cs), dtype=torch.int16, device="cuda")
+    sur.sur_upsample2(_bits(xc.reshape(-1, c)), c, (nx // 2, ny // 2, nz // 2), cat, cs, 0)
+    sur.sur_copy_channels(_bits(x.reshape(-1, c)), c, P, cat, cs, c)
+    got = _from_bits(cat).reshape(nz, ny, nx, cs)
+    assert np.array_equal(got[..., :c], so.up2(xc))
+    assert np.array_equal(got[..., c:2 * c], x)
+    assert not got[..., 2 * c:].any()
+    dy = rng.standard_normal((P, cs)).astype(np.float32)
     du = torch.empty((P // 8, c), dtype=torch.float32, device="cuda")
-    sur.sur_upsample2_bwd(_f32(dy), 48, 16, c, (nx // 2, ny // 2, nz // 2), du)
-    ref = so.up2_bwd(dy.reshape(nz, ny, nx, 48)[..., 16:32].astype(np.float64))
+    sur.sur_upsample2_bwd(_f32(dy), cs, c, c, (nx // 2, ny // 2, nz // 2), du)
+    ref = so.up2_bwd(dy.reshape(nz, ny, nx, cs)[..., c:2 * c].astype(np.float64))
     assert np.abs(du.cpu().numpy().reshape(ref.shape) - ref).max() < 1e-5
     dx = torch.zeros((P, c), dtype=torch.float32, device="cuda")
     sur.sur_pool2_bwd(_f32(dy[:P // 8, :c]), c, (nx, ny, nz), dx)
