@@ -489,6 +489,46 @@ def _prefetch(fn, keys, depth: int = 2):
             yield f.result()
 
 
+def unet_flops(net) -> float:
+    """Multiply-add FLOPs of one forward pass: 2 x 27 x cin x cout per point
+    of each convolution's grid."""
+    return float(sum(2 * 27 * ci * co * net.P[net._level(name)]
+                     for name, ci, co, _ in net.layers))
+
+
+def unet_roofline(net, cp, reps: int = 20) -> dict:
+    """Forward time of the network on the coarse grid (HIP events on the
+    stream the kernels run on, over `reps` calls) against the dense BF16
+    MFMA peak, and the time of one training step (forward, both gradients,
+    Adam; it changes the weights, so it is taken last)."""
+    import torch
+    x = torch.zeros((cp.P, sur.NCH), dtype=torch.int16, device=cp.scale.device)
+    x.random_(0, 1 << 14)  # BF16 bit patterns of values in [0, 2)
+    for _ in range(3):
+        net.forward(x)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        net.forward(x)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flop = unet_flops(net)
+    tgt = torch.zeros((cp.P, sur.NCH), dtype=torch.float32, device=cp.scale.device)
+    wch = torch.ones(sur.NUSE, dtype=torch.float32, device=cp.scale.device)
+    net.train_step(x, tgt, wch, lr=0.0)
+    e0.record(st)
+    for _ in range(5):
+        net.train_step(x, tgt, wch, lr=0.0)
+    e1.record(st)
+    e1.synchronize()
+    achieved = flop / (ms * 1e-3) / 1e12
+    return dict(bound="mfma", grid=list(cp.coarse), forward_ms=ms, flop_per_forward=flop,
+                achieved=achieved, peak=2500.0, unit="TFLOP/s", frac=achieved / 2500.0,
+                train_step_ms=e0.elapsed_time(e1) / 5)
+
+
 def surrogate_benchmark(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rmax: float = 16.0,
                         train_seeds=tuple(range(1000, 1032)), windows: int = 64,
                         test_seed: int = 1, horizon: int = 64, schedules=(7, 3, 1),
@@ -605,6 +645,7 @@ def surrogate_benchmark(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rma
             cp.push(sa, sb, solver.t, linear=lin)
             floor[f"{k}_windows_{'linear' if lin else 'level_set'}"] = phi_error(solver, phik)
     out["reconstruction_floor"] = floor
+    out["unet_roofline"] = unet_roofline(net, cp)
     ok = [(r["speedup"], k) for k, r in runs.items()
           if k.endswith("_net") and r["phi_l2_error"] <= 1e-2]
     out["speedup_at_err_1e-2"] = max(ok)[0] if ok else None

@@ -438,3 +438,41 @@ def bf16_bits_from_f32(t):
     out = torch.empty(t.shape, dtype=torch.int16, device=t.device)
     sur_to_bf16(t.contiguous(), out)
     return out
+
+
+def _main(argv=None):
+    """Times the U-Net on an n^3 coarse grid: `reps` forward passes, then
+    `reps` training steps (forward, both gradients, Adam with lr 0), with
+    HIP events on the stream the kernels run on."""
+    import argparse
+    import torch
+    ap = argparse.ArgumentParser(description=_main.__doc__)
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--reps", type=int, default=20)
+    a = ap.parse_args(argv)
+    g = (a.grid,) * 3
+    net = UNet(g, channels=(16, 32, 48, 64), seed=0)
+    P = a.grid ** 3
+    x = torch.zeros((P, NCH), dtype=torch.int16, device=net.dev)
+    x.random_(0, 1 << 14)  # BF16 bit patterns of values in [0, 2)
+    tgt = torch.zeros((P, NCH), dtype=torch.float32, device=net.dev)
+    wch = torch.ones(NUSE, dtype=torch.float32, device=net.dev)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    flop = sum(2 * 27 * ci * co * net.P[net._level(n)] for n, ci, co, _ in net.layers)
+    for what, fn in (("forward", lambda: net.forward(x)),
+                     ("train step", lambda: net.train_step(x, tgt, wch, lr=0.0))):
+        for _ in range(3):
+            fn()
+        e0.record(st)
+        for _ in range(a.reps):
+            fn()
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / a.reps
+        extra = f", {flop / (ms * 1e-3) / 1e12:.1f} TFLOP/s" if what == "forward" else ""
+        print(f"unet {a.grid}^3 {what}: {ms:.3f} ms{extra}", flush=True)
+
+
+if __name__ == "__main__":
+    _main()
