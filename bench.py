@@ -23,7 +23,10 @@ U-Net is trained on the GPU from solver trajectories of held-out seeds
 1024 steps by the plain solver and by each surrogate schedule; it reports
 wall time, speedup, phi relative L2 error against the plain run, fallbacks,
 the same schedules with a persistence predictor, and the error floor of the
-fine-grid reconstruction.
+fine-grid reconstruction. Its "unet_roofline" object gives the network's
+forward time on the 128^3 coarse grid (HIP events) against the dense BF16
+MFMA peak, the training-step time, and beside them the oracle's forward
+(FP64 NumPy) on a 64^3 sample, FLOP-scaled to one 128^3 forward.
 
 Prints ONE JSON line (see the keys below).
 """
@@ -103,6 +106,31 @@ def cpu_baseline(w, steps: int = 2):
     threads = oracle.num_threads()
     del o
     return w.N * steps / dt / 1e6, threads, dt
+
+
+def unet_cpu_baseline(n: int = 64):
+    """The oracle's U-Net forward (FP64 NumPy, untuned) once on an n^3 grid
+    with random weights (bounded sample); returns (GFLOP/s, threads, seconds,
+    FLOP of the sample)."""
+    import numpy as np
+    from oracle import surrogate_oracle as so
+    ch = (16, 32, 48, 64)
+    rng = np.random.default_rng(0)
+    layers = so.unet_layers(ch)
+    params = [(rng.standard_normal((27, co, ci)) * 0.05, np.zeros(co)) for _, ci, co, _ in layers]
+    x = rng.standard_normal((n, n, n, 16))
+    lev = lambda name: 0 if name == "out" else int(name[3:-1])
+    flop = sum(2 * 27 * ci * co * (n >> lev(name)) ** 3 for name, ci, co, _ in layers)
+    t0 = time.perf_counter()
+    so.unet_forward(x, params, ch)
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()
+                       if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = 1
+    return flop / dt / 1e9, threads, dt, flop
 
 
 def main():
@@ -204,6 +232,15 @@ def main():
                 log=lambda *a: print(*a, file=sys.stderr, flush=True))
         except Exception as e:  # the main metric is still reported
             line["surrogate"] = {"error": f"{type(e).__name__}: {e}"}
+        ur = line["surrogate"].get("unet_roofline")
+        if ur and not args.no_cpu_baseline:
+            print("[bench] cpu baseline: oracle U-Net forward on 64^3", file=sys.stderr, flush=True)
+            gflops, threads, dt, flop = unet_cpu_baseline(64)
+            ur["cpu_baseline"] = {"value": round(ur["flop_per_forward"] / (gflops * 1e9) * 1e3, 1),
+                                  "unit": "ms per forward (FLOP-scaled)", "gflops": round(gflops, 2),
+                                  "cores": threads, "kind": "oracle",
+                                  "sample": f"one forward pass on a 64^3 grid in FP64 "
+                                            f"({flop / 1e9:.1f} GFLOP, {dt:.1f} s)"}
     print(json.dumps(line), flush=True)
 
 
