@@ -1,0 +1,115 @@
+"""The surrogate's convolution kernels at the network's full sizes (the
+128^3 and 64^3 levels of the coarse grid, LDS-tiled persistent kernels in
+the launch configuration the network uses): the forward and the flipped,
+masked data gradient on 4096 sampled output points, each computed by the
+definition Y[p][o] = sum_t sum_i X[p + d_t][i] W[t][o][i] (+ b) in FP64
+from the same BF16 inputs; the weight gradient in full against the oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import surrogate_oracle as so
+
+from gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sur():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2407_12263_amd import surrogate
+    surrogate.load_library()
+    return surrogate
+
+
+def _bits(a):
+    import torch
+    r = so.bf16_round(np.asarray(a, dtype=np.float32))
+    return torch.as_tensor(r.view(np.uint32).__rshift__(16).astype(np.uint16).view(np.int16)).cuda()
+
+
+def _f32(a):
+    import torch
+    return torch.as_tensor(np.asarray(a, dtype=np.float32)).cuda()
+
+
+def _sampled_conv(x, w, b, pts, flip):
+    """Y at sampled points (z, y, x) by the definition (periodic), FP64."""
+    nz, ny, nx, _ = x.shape
+    s = -1 if flip else 1
+    out = np.zeros((len(pts), w.shape[1]))
+    for t, (dx, dy, dz) in enumerate(so.TAPS):
+        zz = (pts[:, 0] + s * dz) % nz
+        yy = (pts[:, 1] + s * dy) % ny
+        xx = (pts[:, 2] + s * dx) % nx
+        out += x[zz, yy, xx].astype(np.float64) @ w[t].T
+    if b is not None:
+        out += b
+    return out
+
+
+@pytest.mark.parametrize("n,cin,cout,flip", [(128, 16, 16, 0), (128, 48, 16, 0), (128, 16, 48, 1),
+                                             (64, 80, 32, 0), (64, 32, 32, 1)])
+def test_conv_full_size_sampled(sur, n, cin, cout, flip):
+    import torch
+    say(f"[sur-full] conv {n}^3 {cin}->{cout} flip={flip}: 4096 sampled points")
+    rng = np.random.default_rng(n + cin + cout + flip)
+    x = so.bf16_round(rng.standard_normal((n, n, n, cin)).astype(np.float32))
+    w = so.bf16_round((rng.standard_normal((27, cout, cin)) * 0.1).astype(np.float32))
+    b = rng.standard_normal(cout).astype(np.float32)
+    wf = torch.empty((27, cout, cin), dtype=torch.int16, device="cuda")
+    wd = torch.empty((27, cin, cout), dtype=torch.int16, device="cuda")
+    P = n ** 3
+    y = torch.empty((P, cout), dtype=torch.float32, device="cuda")
+    if not flip:
+        sur.sur_pack_weights(_f32(w), cin, cout, wf, None)
+        sur.sur_conv3d(_bits(x.reshape(-1, cin)), cin, wf, _f32(b), cout, (n, n, n), relu=1,
+                       y_f32=y)
+    else:
+        # the data gradient of a layer with cout -> cin: weights packed
+        # transposed per tap, mask = the layer input's ReLU pattern
+        wl = so.bf16_round((rng.standard_normal((27, cin, cout)) * 0.1).astype(np.float32))
+        sur.sur_pack_weights(_f32(wl), cout, cin, None, wd)
+        mask = so.bf16_round(np.maximum(rng.standard_normal((n, n, n, cout)), 0).astype(np.float32))
+        sur.sur_conv3d(_bits(x.reshape(-1, cin)), cin, wd, None, cout, (n, n, n), flip=1,
+                       mask=_bits(mask.reshape(-1, cout)), y_f32=y)
+        w = np.transpose(wl, (0, 2, 1))  # Wd[t][o][i] = Wl[t][i][o]
+        b = None
+    pts = rng.integers(0, n, size=(4096, 3))
+    ref = _sampled_conv(x, w.astype(np.float64), None if b is None else b.astype(np.float64),
+                        pts, flip)
+    if flip:
+        ref = ref * (mask[pts[:, 0], pts[:, 1], pts[:, 2]] > 0)
+    else:
+        ref = np.maximum(ref, 0.0)
+    got = y.cpu().numpy().reshape(n, n, n, cout)[pts[:, 0], pts[:, 1], pts[:, 2]]
+    e = np.abs(got - ref).max()
+    say(f"   max|dy| {e:.2e} (scale {np.abs(ref).max():.2f})")
+    assert e <= 1e-5 * (1 + np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n,cin,cout", [(128, 16, 16), (128, 48, 16), (64, 80, 32)])
+def test_conv_weight_gradient_full_size(sur, n, cin, cout):
+    import torch
+    say(f"[sur-full] weight gradient {n}^3 {cin}->{cout}")
+    rng = np.random.default_rng(3 * n + cin + cout)
+    x = so.bf16_round(rng.standard_normal((n, n, n, cin)).astype(np.float32))
+    dy = so.bf16_round(rng.standard_normal((n, n, n, cout)).astype(np.float32))
+    grid = (n, n, n)
+    scratch = torch.empty(sur.sur_wgrad_scratch_floats(cin, cout, grid), dtype=torch.float32,
+                          device="cuda")
+    dw = torch.empty((27, cout, cin), dtype=torch.float32, device="cuda")
+    db = torch.empty(cout, dtype=torch.float32, device="cuda")
+    sur.sur_conv3d_wgrad(_bits(x.reshape(-1, cin)), cin, _bits(dy.reshape(-1, cout)), cout, grid,
+                         scratch, dw, db)
+    rdw, rdb = so.conv3d_wgrad(x.astype(np.float64), dy.astype(np.float64))
+    e = np.abs(dw.cpu().numpy() - rdw).max()
+    eb = np.abs(db.cpu().numpy() - rdb).max()
+    say(f"   max|ddw| {e:.2e} (scale {np.abs(rdw).max():.1f}), max|ddb| {eb:.2e}")
+    # FP32 sums of n^3 BF16 products: rounding grows like sqrt(n^3)
+    P = n ** 3
+    assert e <= 1e-5 * (1 + np.abs(rdw).max()) * np.sqrt(P) / 64
+    assert eb <= 1e-5 * (1 + np.abs(rdb).max()) * np.sqrt(P) / 64
