@@ -209,15 +209,22 @@ __device__ __forceinline__ T bload(rsrc_t r, uint32_t voff, uint32_t soff) {
     }
 }
 
+// Stores of the post-collision state are nontemporal (cache policy nt): no
+// kernel re-reads them before the next step, which reads them from HBM, and
+// streaming them past L2 leaves it to the neighbour taps of the current band
+// (RT 128x512x128: FP16 27.9 -> 28.8 GLUPS, FP32 16.2 -> 16.8; 256^3 FP16
+// 26.2 -> 27.5).
+constexpr int kStoreNT = 2;
+
 template <class T>
 __device__ __forceinline__ void bstore(T v, rsrc_t r, uint32_t voff, uint32_t soff) {
     if constexpr (sizeof(T) == 8) {
         using V2 = unsigned int __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, soff, kStoreNT);
     } else if constexpr (sizeof(T) == 4) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, kStoreNT);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff, kStoreNT);
     }
 }
 
