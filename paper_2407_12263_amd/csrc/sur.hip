@@ -171,7 +171,8 @@ __global__ void __launch_bounds__(256) conv3d_kernel(const uint16_t *__restrict_
 // an item is computed from LDS, each thread's six 16-byte pieces of the next
 // item's halo are already loading into registers. Wavefront w owns plane
 // z0 + w of the tile: four rows of 16 points, the four M tiles; a block
-// computes 32 output channels (two N tiles). The K steps use the
+// computes NT 16-channel N tiles (one for 16 output channels, run at four
+// wavefronts per SIMD; two otherwise). The K steps use the
 // 16x16x32 BF16 MFMA; one step covers two taps (lanes l / 16 = 0, 1: tap t,
 // 2, 3: tap t + 1) x 16 channels (8 per lane). A and B place the same (tap,
 // channel) in the same lane group and element, so the product does not
@@ -180,7 +181,7 @@ __global__ void __launch_bounds__(256) conv3d_kernel(const uint16_t *__restrict_
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 constexpr int kTX = 16, kTY = 4, kTZ = 4;
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2, kHP = kHX * kHY * kHZ;
-constexpr int kNT = 2;  // 16-channel output tiles per block (LDS <= 48.4 KB)
+constexpr int kNT = 2;  // 16-channel output tiles per block at most (LDS <= 48.4 KB)
 
 static_assert(kHP * 2 > 1280 && kHP * 2 <= 1536, "six 16-byte halo pieces per thread");
 
@@ -212,7 +213,9 @@ __device__ __forceinline__ void conv_stage_weights(uint4 *wl, const uint16_t *__
     }
 }
 
-__global__ void __launch_bounds__(256) conv3d_tiled_kernel(
+template <int NT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 4 : 1, 8)))
+conv3d_tiled_kernel(
     const uint16_t *__restrict__ x, int cin, const uint16_t *__restrict__ w,
     const float *__restrict__ bias, int cout, int nx, int ny, int nz, int flip, int relu,
     const uint16_t *__restrict__ mask, uint16_t *__restrict__ yb, float *__restrict__ yf) {
@@ -225,8 +228,8 @@ __global__ void __launch_bounds__(256) conv3d_tiled_kernel(
     const int ntx = nx / kTX, nty = ny / kTY;
     const int ntile = ntx * nty * (nz / kTZ);
     const int nchunk = cin / 16;
-    const int cob = blockIdx.y * (16 * kNT);
-    const int ntiles = min(kNT, (cout - cob) >> 4);
+    const int cob = blockIdx.y * (16 * NT);
+    const int ntiles = min(NT, (cout - cob) >> 4);
     const int nco = ntiles * 16;
     const int half = q & 1;
     const int sgn = flip ? -1 : 1;
@@ -251,7 +254,7 @@ __global__ void __launch_bounds__(256) conv3d_tiled_kernel(
     } while (0)
     if (nwork > 0) CONV_LOAD_HALO(0);
     if (nchunk == 1) conv_stage_weights(wl, w, cin, cout, cob, nco, 0);  // the same for every item
-    f4 acc[4][kNT];
+    f4 acc[4][NT];
     for (int it = 0; it < nwork; ++it) {
         const int chunk = it % nchunk;
         __syncthreads();  // the previous item's reads are done
@@ -268,7 +271,7 @@ __global__ void __launch_bounds__(256) conv3d_tiled_kernel(
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                for (int nt = 0; nt < kNT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+                for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
         for (int t = 0; t < 27; t += 2) {
@@ -281,18 +284,18 @@ __global__ void __launch_bounds__(256) conv3d_tiled_kernel(
             const bool tv = !second || t + 1 < 27;
             const int tc = second ? t1 : t;
             const int off = sgn * (second ? offb : offa);
-            bf8 a[4], b[kNT];
+            bf8 a[4], b[NT];
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
                 a[mt] = __builtin_bit_cast(bf8, tv ? tile[2 * (hb + kHX * mt + off) + half] : z4);
 #pragma unroll
-            for (int nt = 0; nt < kNT; ++nt) {
+            for (int nt = 0; nt < NT; ++nt) {
                 uint4 v = z4;
                 if (nt < ntiles && tv) v = wl[2 * (tc * nco + nt * 16 + r) + half];
                 b[nt] = __builtin_bit_cast(bf8, v);
             }
 #pragma unroll
-            for (int nt = 0; nt < kNT; ++nt) {
+            for (int nt = 0; nt < NT; ++nt) {
                 if (nt < ntiles) {
 #pragma unroll
                     for (int mt = 0; mt < 4; ++mt)
@@ -309,7 +312,7 @@ __global__ void __launch_bounds__(256) conv3d_tiled_kernel(
             for (int mt = 0; mt < 4; ++mt) {
                 const int prow = nx * ((y0 + mt) + ny * (z0 + wave));
 #pragma unroll
-                for (int nt = 0; nt < kNT; ++nt) {
+                for (int nt = 0; nt < NT; ++nt) {
                     if (nt >= ntiles) continue;
                     const int co = cob + nt * 16 + r;
                     const float bb = bias ? bias[co] : 0.f;
@@ -1160,15 +1163,21 @@ int sur_conv3d(const void *x, int32_t cin, const void *w, const float *bias, int
     // 16-byte aligned x and w (its 16-byte loads)
     if (nx % kTX == 0 && ny % kTY == 0 && nz % kTZ == 0 && elems_ok(P, cin) && elems_ok(P, cout) &&
         ((uintptr_t)x & 15) == 0 && ((uintptr_t)w & 15) == 0) {
-        const int nb = 16 * kNT;
+        // one N tile per block for 16 output channels (fewer registers), two otherwise
+        const int nt = cout <= 16 ? 1 : kNT, nb = 16 * nt;
         const long tiles = P / (kTX * kTY * kTZ);
         const long ncb = (cout + nb - 1) / nb;
         const long nblk = std::max(1L, std::min(tiles, (long)env_blocks() / ncb));
         const dim3 grid((unsigned)nblk, (unsigned)ncb);
-        hipLaunchKernelGGL(conv3d_tiled_kernel, grid, dim3(256), conv_tiled_lds(min(cout, nb)),
-                           (hipStream_t)stream,
-                           (const uint16_t *)x, cin, (const uint16_t *)w, bias, cout, nx, ny, nz,
-                           flip, relu, (const uint16_t *)mask, (uint16_t *)y_bf16, y_f32);
+        const size_t lds = conv_tiled_lds(std::min(cout, nb));
+        if (nt == 1)
+            hipLaunchKernelGGL(conv3d_tiled_kernel<1>, grid, dim3(256), lds, (hipStream_t)stream,
+                               (const uint16_t *)x, cin, (const uint16_t *)w, bias, cout, nx, ny, nz,
+                               flip, relu, (const uint16_t *)mask, (uint16_t *)y_bf16, y_f32);
+        else
+            hipLaunchKernelGGL(conv3d_tiled_kernel<kNT>, grid, dim3(256), lds, (hipStream_t)stream,
+                               (const uint16_t *)x, cin, (const uint16_t *)w, bias, cout, nx, ny, nz,
+                               flip, relu, (const uint16_t *)mask, (uint16_t *)y_bf16, y_f32);
         return launched();
     }
     const dim3 grid((unsigned)((P + 255) / 256), (unsigned)((cout + 63) / 64));
