@@ -150,7 +150,7 @@ def main():
                     help="training trajectories of 64 windows (32 -> 2080 snapshots)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the step would shard by z-slabs with one halo exchange per step)",
               file=sys.stderr)
         sys.exit(2)

@@ -5,8 +5,8 @@
  * with hand-written HIP kernels (BF16 matrix-core products with FP32
  * accumulation; FP32 master weights and Adam).
  *
- * The paper has no learned component; this ABI serves the acceleration
- * scheme of this build: the solver generates training snapshots, the network
+ * The paper has no learned component; this ABI serves a surrogate
+ * acceleration scheme around the solver: it generates training snapshots, the network
  * predicts windows on the coarse grid, per-window checks (phase mass, phi
  * range, velocity divergence) send a window back to the plain solver when
  * they fail, and the plain solver runs every re-synchronisation window.
