@@ -26,7 +26,11 @@ the same schedules with a persistence predictor, and the error floor of the
 fine-grid reconstruction. Its "unet_roofline" object gives the network's
 forward time on the 128^3 coarse grid (HIP events) against the dense BF16
 MFMA peak, the training-step time, and beside them the oracle's forward
-(FP64 NumPy) on a 64^3 sample, FLOP-scaled to one 128^3 forward.
+(FP64 NumPy) on a 64^3 sample, FLOP-scaled to one 128^3 forward, and its
+training step on 32^3 scaled to 128^3. Its "coupling" object gives the wall
+time of the transfer operations of a surrogate cycle (snapshot, base copy,
+checks, level-set push with the solver rebuild) beside the coupling
+oracle's round at the same 256^3 / 128^3 size.
 
 Prints ONE JSON line (see the keys below).
 """
@@ -131,6 +135,42 @@ def unet_cpu_baseline(n: int = 64):
     except Exception:
         threads = 1
     return flop / dt / 1e9, threads, dt, flop
+
+
+def train_cpu_baseline(n: int = 32):
+    """The oracle's training step (U-Net forward, MSE, backward, Adam; FP64
+    NumPy, untuned) once on an n^3 grid; returns seconds."""
+    import numpy as np
+    from oracle import surrogate_oracle as so
+    ch = (16, 32, 48, 64)
+    rng = np.random.default_rng(0)
+    params = [(rng.standard_normal((27, co, ci)) * 0.05, np.zeros(co))
+              for _, ci, co, _ in so.unet_layers(ch)]
+    x = rng.standard_normal((n, n, n, 16))
+    t0 = time.perf_counter()
+    out, cache = so.unet_forward(x, params, ch)
+    _, dout = so.mse(out, np.zeros_like(out), np.ones(5))
+    grads = so.unet_backward(dout, params, ch, cache)
+    for (w, _), (gw, _) in zip(params, grads):
+        so.adam(w, np.zeros_like(w), np.zeros_like(w), gw, 1)
+    return time.perf_counter() - t0
+
+
+def coupling_cpu_baseline(n: int = 256):
+    """The coupling oracle's round at the full size (fine n^3, coarse
+    (n/2)^3): coarsen, level-set prolongation with mass restoration,
+    features and checks (FP64 NumPy); returns seconds."""
+    import numpy as np
+    from oracle import coupling_oracle as co
+    rng = np.random.default_rng(0)
+    shp = (n, n, n)
+    phi, u, p = rng.random(shp), 0.02 * rng.standard_normal((3,) + shp), 4e-4 * rng.standard_normal(shp)
+    scale = np.array([1.0, 0.02, 0.02, 0.02, 4e-4] + [1.0] * 11)
+    t0 = time.perf_counter()
+    s0 = co.coarsen(phi, u, p, scale)
+    co.checks(co.features(s0))
+    co.prolong_update(s0, s0, scale, 4.0, phi, u, p)
+    return time.perf_counter() - t0
 
 
 def main():
@@ -241,6 +281,20 @@ def main():
                                   "cores": threads, "kind": "oracle",
                                   "sample": f"one forward pass on a 64^3 grid in FP64 "
                                             f"({flop / 1e9:.1f} GFLOP, {dt:.1f} s)"}
+            dt = train_cpu_baseline(32)
+            ur["train_cpu_baseline"] = {"value": round(dt * 64 * 1e3, 1),
+                                        "unit": "ms per training step (scaled by points)",
+                                        "cores": threads, "kind": "oracle",
+                                        "sample": f"one training step on a 32^3 grid in FP64 "
+                                                  f"({dt:.1f} s), x 64 for 128^3"}
+        cpl = line["surrogate"].get("coupling")
+        if cpl and not args.no_cpu_baseline:
+            print("[bench] cpu baseline: coupling oracle at 256^3", file=sys.stderr, flush=True)
+            dt = coupling_cpu_baseline(256)
+            cpl["cpu_baseline"] = {"value": round(dt * 1e3, 1), "unit": "ms per round",
+                                   "kind": "oracle",
+                                   "sample": "coarsen, features, checks and level-set "
+                                             "prolongation at 256^3 / 128^3 in FP64, once"}
     print(json.dumps(line), flush=True)
 
 

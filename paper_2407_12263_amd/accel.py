@@ -489,6 +489,33 @@ def _prefetch(fn, keys, depth: int = 2):
             yield f.result()
 
 
+def coupling_timing(cp: Coupler, reps: int = 5) -> dict:
+    """Wall time per call (host clock around `reps` calls, synchronised) of
+    the coupling operations of one surrogate cycle at the coupler's sizes:
+    snapshot (FP32 fields, coarsening, features), save_base (FP64 fields and
+    their copy), checks, push (level-set prolongation with mass restoration
+    and the solver rebuild). push changes the solver state: call last."""
+    import torch
+    sync = torch.cuda.synchronize
+    s0, s1 = cp.new_state(), cp.new_state()
+    chk = torch.empty(7, dtype=torch.float64, device=cp.scale.device)
+    cp.snapshot(s0)
+    s1.copy_(s0)
+    out = {}
+    for name, fn in (("snapshot", lambda: cp.snapshot(s0)), ("save_base", cp.save_base),
+                     ("checks", lambda: cp.checks(s0, chk)),
+                     ("push", lambda: cp.push(s0, s1, cp.solver.t))):
+        fn()
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        sync()
+        out[f"{name}_ms"] = (time.perf_counter() - t0) / reps * 1e3
+    out["grid"] = list(cp.fine)
+    return out
+
+
 def unet_flops(net) -> float:
     """Multiply-add FLOPs of one forward pass: 2 x 27 x cin x cout per point
     of each convolution's grid."""
@@ -646,6 +673,7 @@ def surrogate_benchmark(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rma
             floor[f"{k}_windows_{'linear' if lin else 'level_set'}"] = phi_error(solver, phik)
     out["reconstruction_floor"] = floor
     out["unet_roofline"] = unet_roofline(net, cp)
+    out["coupling"] = coupling_timing(cp)
     ok = [(r["speedup"], k) for k, r in runs.items()
           if k.endswith("_net") and r["phi_l2_error"] <= 1e-2]
     out["speedup_at_err_1e-2"] = max(ok)[0] if ok else None
