@@ -442,7 +442,8 @@ template <int MT>
 __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__restrict__ x, int cin,
                                                           const uint16_t *__restrict__ dy, int cout,
                                                           int nx, int ny, int nz,
-                                                          float *__restrict__ part) {
+                                                          float *__restrict__ part,
+                                                          float *__restrict__ bpart) {
     constexpr int kRow = 24;                    // hx row length in XhT
     constexpr int kXh = 16 * kHZ * kHY * kRow;  // XhT elements
     constexpr int kNTap = 7;                    // taps per wavefront (27 = 4 x 7 - 1)
@@ -458,6 +459,10 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
     for (int u = 0; u < kNTap; ++u)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) acc[u][mt] = f4{0.f, 0.f, 0.f, 0.f};
+    // bias gradient (blocks of the first input chunk): thread t sums output
+    // channel t / 4 over the quarter t % 4 of each tile's points
+    const bool do_bias = bpart != nullptr && blockIdx.y == 0 && threadIdx.x < MT * 64;
+    float bsum = 0.f;
     for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
         const int bx = tile % ntx, rest = tile / ntx;
         const int by = rest % nty, bz = rest / nty;
@@ -484,6 +489,17 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
             for (int e = 0; e < 8; ++e) dyt[(8 * oc + e) * 256 + pl] = uint16_t(wd[e >> 1] >> (16 * (e & 1)));
         }
         __syncthreads();
+        if (do_bias) {
+            const uint16_t *row = dyt + (threadIdx.x >> 2) * 256 + 64 * (threadIdx.x & 3);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint4 v = *(const uint4 *)(row + 8 * k);
+                const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    bsum += __uint_as_float(wd[e] << 16) + __uint_as_float(wd[e] & 0xffff0000u);
+            }
+        }
 #pragma unroll 1
         for (int st = 0; st < 8; ++st) {
             const int pl0 = 32 * st + 8 * q;  // the lane's first point of the step
@@ -532,6 +548,17 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 part[(((long)blockIdx.x * 27 + t) * cout + mt * 16 + 4 * q + j) * cin + cc + r] = acc[u][mt][j];
+    }
+    if (bpart != nullptr && blockIdx.y == 0) {
+        // the four quarter sums of each channel, combined in order
+        __shared__ float bred[256];
+        __syncthreads();
+        bred[threadIdx.x] = do_bias ? bsum : 0.f;
+        __syncthreads();
+        if (threadIdx.x < MT * 16) {
+            const float* b4 = bred + 4 * threadIdx.x;
+            bpart[(long)blockIdx.x * cout + threadIdx.x] = ((b4[0] + b4[1]) + b4[2]) + b4[3];
+        }
     }
 }
 
@@ -1190,7 +1217,9 @@ int sur_conv3d(const void *x, int32_t cin, const void *w, const float *bias, int
 size_t sur_wgrad_scratch_floats(int32_t cin, int32_t cout, int32_t nx, int32_t ny, int32_t nz) {
     const long P = (long)nx * ny * nz;
     const long parts = std::max(wgrad_chunks(P), wgrad_tiled_blocks(cin, P));
-    return (size_t)(parts * 27L * cin * cout + grid1(P, 1024).x * (long)cout);
+    // bias partials: one per 1024 points, or one per tiled block
+    const long bparts = std::max((long)grid1(P, 1024).x, wgrad_tiled_blocks(cin, P));
+    return (size_t)(parts * 27L * cin * cout + bparts * (long)cout);
 }
 
 int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, int32_t nx,
@@ -1204,15 +1233,22 @@ int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, i
     const long P = (long)nx * ny * nz;
     const uint16_t *xb = (const uint16_t *)x, *db = (const uint16_t *)dy;
     long nch;  // partial sums in scratch
+    const long n = 27L * cin * cout;
+    bool bias_done = false;
     if (wgrad_tiled_ok(x, cin, dy, cout, nx, ny, nz)) {
         nch = wgrad_tiled_blocks(cin, P);
         const dim3 grid((unsigned)nch, (unsigned)(cin / 16));
+        // the bias partials follow the weight partials: one per block
+        float *bp = dbias ? scratch + nch * n : nullptr;
         switch (cout / 16) {
-            case 1: hipLaunchKernelGGL(wgrad_tiled_kernel<1>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, scratch); break;
-            case 2: hipLaunchKernelGGL(wgrad_tiled_kernel<2>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, scratch); break;
-            case 3: hipLaunchKernelGGL(wgrad_tiled_kernel<3>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, scratch); break;
-            default: hipLaunchKernelGGL(wgrad_tiled_kernel<4>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, scratch); break;
+            case 1: hipLaunchKernelGGL(wgrad_tiled_kernel<1>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, scratch, bp); break;
+            case 2: hipLaunchKernelGGL(wgrad_tiled_kernel<2>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, scratch, bp); break;
+            case 3: hipLaunchKernelGGL(wgrad_tiled_kernel<3>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, scratch, bp); break;
+            default: hipLaunchKernelGGL(wgrad_tiled_kernel<4>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, scratch, bp); break;
         }
+        if (dbias)
+            hipLaunchKernelGGL(sum_chunks_kernel, grid1(cout, 32), dim3(256), 0, s, (const float *)bp, nch, (long)cout, dbias);
+        bias_done = true;
     } else {
         nch = wgrad_chunks(P);
         const dim3 grid(27, (unsigned)nch, (unsigned)((cin + 63) / 64));
@@ -1223,9 +1259,8 @@ int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, i
             default: hipLaunchKernelGGL(wgrad_kernel<4>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, kWgradChunk, scratch); break;
         }
     }
-    const long n = 27L * cin * cout;
     hipLaunchKernelGGL(sum_chunks_kernel, grid1(n, 32), dim3(256), 0, s, (const float *)scratch, nch, n, dw);
-    if (dbias) {
+    if (dbias && !bias_done) {
         const long nb = grid1(P, 1024).x;
         float *bp = scratch + nch * n;
         hipLaunchKernelGGL(bias_partial_kernel, dim3((unsigned)nb), dim3(256), 0, s, db, cout, P, 1024L, bp);
