@@ -329,17 +329,26 @@ class UNet:
         return self.out
 
     # ------------------------------------------------------------- backward
-    def _conv_back(self, k, x_in, dy_f32, grid, mask):
-        """Weight/bias gradients of layer k and, if mask is not None or the
-        input needs a gradient, the FP32 input gradient (masked by mask > 0)."""
+    def _conv_back(self, k, x_in, dy, grid, mask, out_bf16=False):
+        """Weight/bias gradients of layer k and the input gradient (masked by
+        mask > 0 if given): FP32, or BF16 bits (int16) with ``out_bf16`` when
+        it only feeds the next layer's backward. dy is FP32 or BF16 bits."""
+        torch = self.torch
         name, ci, co, relu = self.layers[k]
         lv = self._level(name)
         P = self.P[lv]
-        dyb = self.torch.empty((P, co), dtype=self.torch.int16, device=self.dev)
-        sur_to_bf16(dy_f32, dyb)
+        if dy.dtype == torch.int16:
+            dyb = dy
+        else:
+            dyb = torch.empty((P, co), dtype=torch.int16, device=self.dev)
+            sur_to_bf16(dy, dyb)
         sur_conv3d_wgrad(x_in, ci, dyb, co, grid, self.scratch, self.gw[k], self.gb[k])
-        dx = self.torch.empty((P, ci), dtype=self.torch.float32, device=self.dev)
-        sur_conv3d(dyb, co, self.wd[k], None, ci, grid, flip=1, relu=0, mask=mask, y_f32=dx)
+        if out_bf16:
+            dx = torch.empty((P, ci), dtype=torch.int16, device=self.dev)
+            sur_conv3d(dyb, co, self.wd[k], None, ci, grid, flip=1, relu=0, mask=mask, y_bf16=dx)
+        else:
+            dx = torch.empty((P, ci), dtype=torch.float32, device=self.dev)
+            sur_conv3d(dyb, co, self.wd[k], None, ci, grid, flip=1, relu=0, mask=mask, y_f32=dx)
         return dx
 
     def backward(self, dout):
@@ -348,7 +357,11 @@ class UNet:
         k = len(self.layers) - 1
         nlev = self.nlev
         last = self.layers[k - 1][0]
-        dh = self._conv_back(k, self.act[last], dout, self.grids[0], mask=self.act[last])
+        # gradients that only feed the next layer's backward stay BF16 (the
+        # rounding it would apply anyway); those that are split, upsampled
+        # or pooled first are FP32
+        dh = self._conv_back(k, self.act[last], dout, self.grids[0], mask=self.act[last],
+                             out_bf16=True)
         dskip = [None] * (nlev - 1)
         for lv in range(0, nlev - 1):
             for part in "ba":
@@ -359,7 +372,7 @@ class UNet:
                     mask = self.act[self.layers[k - 1][0]]
                 else:
                     mask = None  # input is the concat: split below, masks come from its parts
-                dh = self._conv_back(k, x_in, dh, self.grids[lv], mask)
+                dh = self._conv_back(k, x_in, dh, self.grids[lv], mask, out_bf16=part == "b")
             cup = dh.shape[1] - self.channels[lv]
             # skip part: gradient w.r.t. enc{lv}b output (masked later with the encoder)
             ds = torch.empty((self.P[lv], self.channels[lv]), dtype=torch.float32, device=self.dev)
@@ -391,7 +404,7 @@ class UNet:
                 else:
                     x_in = self._last_input if lv == 0 else self.act[f"pool{lv - 1}"]
                     mask = None
-                dh = self._conv_back(k, x_in, dh, self.grids[lv], mask)
+                dh = self._conv_back(k, x_in, dh, self.grids[lv], mask, out_bf16=part == "b")
         return dh
 
     def loss_and_grad(self, target_f32, wch):
