@@ -559,7 +559,7 @@ def unet_roofline(net, cp, reps: int = 20) -> dict:
 def surrogate_benchmark(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rmax: float = 16.0,
                         train_seeds=tuple(range(1000, 1032)), windows: int = 64,
                         test_seed: int = 1, horizon: int = 64, schedules=(7, 3, 1),
-                        precision: str = "fp16", train_per_window: int = 6,
+                        precision: str = "fp16", train_per_window: int = 9,
                         capacity: int = 300, lr: float = 3e-4, cycle: int = 8,
                         log=print) -> dict:
     """Emulsion workload: trains the U-Net on solver trajectories from
