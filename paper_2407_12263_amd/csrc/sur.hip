@@ -435,9 +435,11 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const uint16_t *__restrict__
 // aligned 16-byte read, shared by all the wavefront's taps, and its B
 // fragment (X of one input channel, shifted by the tap) starts dx + 1
 // elements into an aligned pair of 16-byte words (a byte shift that is the
-// same for the whole wavefront). Wavefront w owns taps w, w + 4, ... and
-// keeps their sums over all its tiles in registers; the block's partial
-// dW goes to part[block][t][o][i] and the partials are summed in fixed order.
+// same for the whole wavefront). Wavefront w owns the tap rows (dy, dz)
+// w, w + 4, w + 8 (9 or 6 taps: the three dx of a row share those two
+// words) and keeps their sums over all its tiles in registers; the block's
+// partial dW goes to part[block][t][o][i] and the partials are summed in
+// fixed order.
 template <int MT>
 __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__restrict__ x, int cin,
                                                           const uint16_t *__restrict__ dy, int cout,
@@ -446,7 +448,7 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
                                                           float *__restrict__ bpart) {
     constexpr int kRow = 24;                    // hx row length in XhT
     constexpr int kXh = 16 * kHZ * kHY * kRow;  // XhT elements
-    constexpr int kNTap = 7;                    // taps per wavefront (27 = 4 x 7 - 1)
+    constexpr int kNTap = 9;                    // taps per wavefront: 3 rows x 3 dx at most
     __shared__ __attribute__((aligned(16))) uint16_t xht[kXh];
     __shared__ __attribute__((aligned(16))) uint16_t dyt[MT * 16 * 256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -508,41 +510,45 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
                 a[mt] = __builtin_bit_cast(bf8, *(const uint4 *)(dyt + (mt * 16 + r) * 256 + pl0));
+            // wavefront w takes the tap rows (dy, dz) w, w + 4, w + 8: the
+            // three dx taps of a row start dx + 1 elements into the same two
+            // aligned 16-byte words (lx0 is 0 or 8), read once per row
 #pragma unroll
-            for (int u = 0; u < kNTap; ++u) {
-                const int t = wave + 4 * u;
-                if (t < 27) {
-                    const int dx = t % 3 - 1, dyo = (t / 3) % 3 - 1, dz = t / 9 - 1;
-                    const int start = lx0 + dx + 1;  // 0 .. 10; start % 8 = dx + 1
-                    const uint16_t *row = xht + ((r * kHZ + lz + dz + 1) * kHY + ly + dyo + 1) * kRow;
-                    const uint4 w0 = *(const uint4 *)(row + (start & ~7));
-                    uint4 bw;
-                    if (dx < 0) {
-                        bw = w0;
-                    } else {
-                        const uint4 w1 = *(const uint4 *)(row + (start & ~7) + 8);
-                        if (dx == 0) {  // shift by one element (2 bytes)
-                            bw = uint4{__builtin_amdgcn_alignbyte(w0.y, w0.x, 2),
-                                       __builtin_amdgcn_alignbyte(w0.z, w0.y, 2),
-                                       __builtin_amdgcn_alignbyte(w0.w, w0.z, 2),
-                                       __builtin_amdgcn_alignbyte(w1.x, w0.w, 2)};
-                        } else {  // shift by two elements (one dword)
-                            bw = uint4{w0.y, w0.z, w0.w, w1.x};
-                        }
+            for (int rr = 0; rr < 3; ++rr) {
+                const int rid = wave + 4 * rr;
+                if (rid < 9) {
+                    const int dyo = rid % 3 - 1, dz = rid / 3 - 1;
+                    const uint16_t *row =
+                        xht + ((r * kHZ + lz + dz + 1) * kHY + ly + dyo + 1) * kRow + lx0;
+                    const uint4 w0 = *(const uint4 *)row;
+                    const uint4 w1 = *(const uint4 *)(row + 8);
+                    const uint4 bw[3] = {
+                        w0,  // dx = -1
+                        uint4{__builtin_amdgcn_alignbyte(w0.y, w0.x, 2),  // dx = 0: one element
+                              __builtin_amdgcn_alignbyte(w0.z, w0.y, 2),
+                              __builtin_amdgcn_alignbyte(w0.w, w0.z, 2),
+                              __builtin_amdgcn_alignbyte(w1.x, w0.w, 2)},
+                        uint4{w0.y, w0.z, w0.w, w1.x}};  // dx = +1: two elements
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const bf8 b = __builtin_bit_cast(bf8, bw[d]);
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+                            acc[3 * rr + d][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                a[mt], b, acc[3 * rr + d][mt], 0, 0, 0);
                     }
-                    const bf8 b = __builtin_bit_cast(bf8, bw);
-#pragma unroll
-                    for (int mt = 0; mt < MT; ++mt)
-                        acc[u][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[u][mt], 0, 0, 0);
                 }
             }
         }
     }
-    // D[m = 4 q + j][n = r] of tap t, M tile mt: dW[t][mt 16 + 4 q + j][cc + r]
+    // D[m = 4 q + j][n = r] of tap t, M tile mt: dW[t][mt 16 + 4 q + j][cc + r];
+    // accumulator u = 3 rr + d holds tap t = d + 3 (dy + 1) + 9 (dz + 1) of row
+    // rid = wave + 4 rr = (dy + 1) + 3 (dz + 1)
 #pragma unroll
     for (int u = 0; u < kNTap; ++u) {
-        const int t = wave + 4 * u;
-        if (t >= 27) continue;
+        const int rid = wave + 4 * (u / 3);
+        if (rid >= 9) continue;
+        const int t = u % 3 + 3 * rid;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
