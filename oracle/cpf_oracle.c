@@ -18,7 +18,9 @@
  *
  * Readings of the paper taken where it is silent or inconsistent (each is
  * listed with its justification in the design notes of the repository):
- *   - 3D lattice: D3Q19 for both f and g (the paper prints only D2Q9).
+ *   - 3D lattice: D3Q19 for both f and g (the paper prints only D2Q9); the
+ *     same steps on D3Q27 when built with -DORC_Q=27 (a variant the method
+ *     admits: only the lattice table changes).
  *   - velocities e_i = c*e^_i with the Courant number c, c_s^2 = c^2/3.
  *   - surface-stress term of f_eq enters with a minus sign (App. A requires
  *     Pi_eq = rho u u + p I - Pi_s; the printed "+" gives the opposite).
@@ -58,20 +60,24 @@ static double TW[Q];     /* weights t_i            */
 static int    OPP[Q];    /* index of -e^_i         */
 static int    lattice_done = 0;
 
-/* D3Q19 built from its definition: every vector of {-1,0,1}^3 with squared
- * length at most 2, ordered by speed class; weights 1/3, 1/18, 1/36. */
+/* The lattice built from its definition, ordered by speed class |e^|^2:
+ * D3Q19 = every vector of {-1,0,1}^3 with |e^|^2 <= 2, weights 1/3, 1/18,
+ * 1/36; D3Q27 = all of {-1,0,1}^3, weights 8/27, 2/27, 1/54, 1/216 (the
+ * tensor product of the one-dimensional weights 2/3, 1/6, 1/6). */
 static void lattice_build(void)
 {
     if (lattice_done) return;
-    const double wclass[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
+    const double w19[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
+    const double w27[4] = {8.0 / 27.0, 2.0 / 27.0, 1.0 / 54.0, 1.0 / 216.0};
+    const int smax = Q == 27 ? 3 : 2;
     int i = 0;
-    for (int s = 0; s <= 2; ++s)
+    for (int s = 0; s <= smax; ++s)
         for (int z = -1; z <= 1; ++z)
             for (int y = -1; y <= 1; ++y)
                 for (int x = -1; x <= 1; ++x) {
                     if (x * x + y * y + z * z != s) continue;
                     EH[i][0] = x; EH[i][1] = y; EH[i][2] = z;
-                    TW[i] = wclass[s];
+                    TW[i] = Q == 27 ? w27[s] : w19[s];
                     ++i;
                 }
     for (int a = 0; a < Q; ++a)

@@ -8,8 +8,12 @@
  * the GPU path; the two agree only through the paper.
  *
  * Units: grid units, dx = dt = 1. The discrete velocities are e_i = c*e^_i
- * with e^_i the integer D3Q19 vectors and c the Courant number of the
- * Lax-Wendroff propagation (Sec. 2.2), so c_s^2 = c^2/3.
+ * with e^_i the integer vectors of the lattice and c the Courant number of
+ * the Lax-Wendroff propagation (Sec. 2.2), so c_s^2 = c^2/3.
+ *
+ * The lattice is fixed at compile time by ORC_Q: 19 (D3Q19, the default) or
+ * 27 (D3Q27, built as a second library with -DORC_Q=27). Both carry the same
+ * sound speed and the fourth-order isotropy the equilibria need.
  *
  * Arrays are host arrays, structure-of-arrays, index  n = x + nx*(y + ny*z),
  * a population i at  i*N + n,  a vector component a at  a*N + n.
@@ -21,7 +25,12 @@
 extern "C" {
 #endif
 
+#ifndef ORC_Q
 #define ORC_Q 19
+#endif
+#if ORC_Q != 19 && ORC_Q != 27
+#error "ORC_Q must be 19 or 27"
+#endif
 
 typedef struct {
     int nx, ny, nz;
@@ -62,7 +71,7 @@ long orc_time(const orc_state *S);
 void orc_fields(const orc_state *S, double *phi, double *u, double *p);
 /* phi_ref may be NULL (then the L2 entries are 0) */
 void orc_diag(const orc_state *S, const double *phi_ref, double out[ORC_NDIAG]);
-/* copy out / in the post-propagation PDFs f-bar and g (19N each) */
+/* copy out / in the post-propagation PDFs f-bar and g (ORC_Q*N each) */
 void orc_get_pdfs(const orc_state *S, double *f, double *g);
 void orc_set_pdfs(orc_state *S, const double *f, const double *g);
 
@@ -70,7 +79,7 @@ void orc_set_pdfs(orc_state *S, const double *f, const double *g);
 
 /* Equilibria and forcings at one node for given macroscopic values and a given
  * order-parameter gradient (normal and |grad phi| follow from it):
- * feq, geq, S_i (compensation), R_i (body force), all of length 19. */
+ * feq, geq, S_i (compensation), R_i (body force), all of length ORC_Q. */
 void orc_node_equilibria(const orc_params *P, double phi, const double u[3],
                          double p, const double gradphi[3],
                          double feq[ORC_Q], double geq[ORC_Q],
@@ -81,7 +90,7 @@ void orc_node_equilibria(const orc_params *P, double phi, const double u[3],
 void orc_node_macro(const orc_params *P, const double fb[ORC_Q],
                     const double g[ORC_Q], double out[10]);
 
-/* Lax-Wendroff propagation of one 19-population field (with the walls of P). */
+/* Lax-Wendroff propagation of one ORC_Q-population field (with the walls of P). */
 void orc_propagate(const orc_params *P, const double *in, double *out);
 
 /* Isotropic central-difference gradient of a scalar field (3N out). */

@@ -2,7 +2,8 @@
 
 Arrays are numpy float64, structure-of-arrays with x fastest:
 scalar fields have shape (nz, ny, nx), vector fields (3, nz, ny, nx) and
-PDF fields (19, nz, ny, nx).
+PDF fields (Q, nz, ny, nx) with Q = 19 (D3Q19) or 27 (D3Q27), chosen by
+``OracleParams.lattice``; the two lattices are two builds of the same C source.
 """
 from __future__ import annotations
 
@@ -14,9 +15,16 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libcpf_oracle.so")
 _SRC = os.path.join(_HERE, "cpf_oracle.c")
-Q = 19
+LATTICES = (19, 27)
+Q = 19   # the default lattice
+
+
+def _lib_path(q: int) -> str:
+    return os.path.join(_HERE, "libcpf_oracle.so" if q == 19 else f"libcpf_oracle_q{q}.so")
+
+
+_LIB_PATH = _lib_path(19)
 
 DIAG_NAMES = ("sum_phi", "mass", "momx", "momy", "momz", "ekin", "umax", "phi_min",
               "phi_max", "comx", "comy", "comz", "phiux", "phiuy", "phiuz", "l2_num",
@@ -24,13 +32,16 @@ DIAG_NAMES = ("sum_phi", "mass", "momx", "momy", "momz", "ekin", "umax", "phi_mi
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP, strict IEEE: no fast-math)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-               "-Wall", "-o", tmp, _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB_PATH)
+    """Compile the oracle with gcc (-O2, OpenMP, strict IEEE: no fast-math),
+    once per lattice; returns the D3Q19 library's path."""
+    for q in LATTICES:
+        path = _lib_path(q)
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+                   "-Wall", f"-DORC_Q={q}", "-o", tmp, _SRC, "-lm"]
+            subprocess.run(cmd, check=True)
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
@@ -63,6 +74,7 @@ class OracleParams:
     G: tuple = (0.0, 0.0, 0.0)
     normal_fd: int = 0
     k1_eps: float = 1e-5
+    lattice: int = 19        # 19 (D3Q19) or 27 (D3Q27): which build runs
 
     def to_c(self) -> _Params:
         p = _Params()
@@ -86,17 +98,28 @@ class OracleParams:
     def N(self):
         return self.nx * self.ny * self.nz
 
+    @property
+    def Q(self):
+        return _check_q(self.lattice)
 
-_lib = None
+
+_libs = {}
 _dp = C.POINTER(C.c_double)
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build()
-        lib = C.CDLL(_LIB_PATH)
+def _check_q(q) -> int:
+    q = int(q)
+    if q not in LATTICES:
+        raise ValueError(f"lattice must be one of {LATTICES}, got {q}")
+    return q
+
+
+def _load(q: int = 19):
+    q = _check_q(q)
+    if q not in _libs:
+        if not os.path.exists(_lib_path(q)):
+            build(force=False)
+        lib = C.CDLL(_lib_path(q))
         lib.orc_create.argtypes = [C.POINTER(_Params), _dp, _dp, _dp, C.POINTER(C.c_void_p)]
         lib.orc_create.restype = C.c_int
         lib.orc_destroy.argtypes = [C.c_void_p]
@@ -114,8 +137,8 @@ def _load():
         lib.orc_propagate.argtypes = [C.POINTER(_Params), _dp, _dp]
         lib.orc_fd_gradient.argtypes = [C.POINTER(_Params), _dp, _dp]
         lib.orc_num_threads.restype = C.c_int
-        _lib = lib
-    return _lib
+        _libs[q] = lib
+    return _libs[q]
 
 
 def _ptr(a):
@@ -138,46 +161,46 @@ def num_threads() -> int:
     return int(_load().orc_num_threads())
 
 
-def lattice():
-    """(e^ (19,3) int, t (19,)) of the oracle's own D3Q19 table."""
-    lib = _load()
-    e = (C.c_int * (Q * 3))()
-    t = np.zeros(Q)
+def lattice(q: int = 19):
+    """(e^ (q,3) int, t (q,)) of the oracle's own D3Q19 or D3Q27 table."""
+    lib = _load(q)
+    e = (C.c_int * (q * 3))()
+    t = np.zeros(q)
     lib.orc_lattice(e, _ptr(t))
-    return np.array(list(e), dtype=np.int64).reshape(Q, 3), t
+    return np.array(list(e), dtype=np.int64).reshape(q, 3), t
 
 
 def node_equilibria(P: OracleParams, phi, u, p, gradphi):
-    lib = _load()
+    lib = _load(P.Q)
     cp = P.to_c()
     u = _f64(u, (3,))
     gp = _f64(gradphi, (3,))
-    out = [np.zeros(Q) for _ in range(4)]
+    out = [np.zeros(P.Q) for _ in range(4)]
     lib.orc_node_equilibria(C.byref(cp), float(phi), _ptr(u), float(p), _ptr(gp),
                             *[_ptr(o) for o in out])
     return tuple(out)  # feq, geq, S_i, R_i
 
 
 def node_macro(P: OracleParams, fb, g):
-    lib = _load()
+    lib = _load(P.Q)
     cp = P.to_c()
     out = np.zeros(10)
-    lib.orc_node_macro(C.byref(cp), _ptr(_f64(fb, (Q,))), _ptr(_f64(g, (Q,))), _ptr(out))
+    lib.orc_node_macro(C.byref(cp), _ptr(_f64(fb, (P.Q,))), _ptr(_f64(g, (P.Q,))), _ptr(out))
     return dict(phi=out[0], rho=out[1], tau_rho=out[2], u=out[3:6].copy(), p=out[6],
                 gradphi=out[7:10].copy())
 
 
 def propagate(P: OracleParams, fin):
-    lib = _load()
+    lib = _load(P.Q)
     cp = P.to_c()
-    fin = _f64(fin, (Q,) + P.shape)
+    fin = _f64(fin, (P.Q,) + P.shape)
     out = np.empty_like(fin)
     lib.orc_propagate(C.byref(cp), _ptr(fin), _ptr(out))
     return out
 
 
 def fd_gradient(P: OracleParams, phi):
-    lib = _load()
+    lib = _load(P.Q)
     cp = P.to_c()
     phi = _f64(phi, P.shape)
     out = np.empty((3,) + P.shape)
@@ -190,7 +213,7 @@ class Oracle:
 
     def __init__(self, P: OracleParams, phi0, u0=None, p0=None):
         self.P = P
-        self._lib = _load()
+        self._lib = _load(P.Q)
         self._cp = P.to_c()
         phi0 = _f64(phi0, P.shape)
         u0 = _f64(u0, (3,) + P.shape) if u0 is not None else None
@@ -230,12 +253,12 @@ class Oracle:
 
     def pdfs(self):
         P = self.P
-        f = np.empty((Q,) + P.shape)
-        g = np.empty((Q,) + P.shape)
+        f = np.empty((P.Q,) + P.shape)
+        g = np.empty((P.Q,) + P.shape)
         self._lib.orc_get_pdfs(self._h, _ptr(f), _ptr(g))
         return f, g
 
     def set_pdfs(self, f, g):
         P = self.P
-        self._lib.orc_set_pdfs(self._h, _ptr(_f64(f, (Q,) + P.shape)),
-                               _ptr(_f64(g, (Q,) + P.shape)))
+        self._lib.orc_set_pdfs(self._h, _ptr(_f64(f, (P.Q,) + P.shape)),
+                               _ptr(_f64(g, (P.Q,) + P.shape)))

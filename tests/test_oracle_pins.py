@@ -19,23 +19,27 @@ from paper_2407_12263_amd import inputs
 C = 0.997
 CS2 = C * C / 3.0
 
+# every pin runs on both lattices the oracle is built for (D3Q19, D3Q27)
+LAT = pytest.mark.parametrize("q", [19, 27])
 
-def _params(orc, **kw):
+
+def _params(orc, q=19, **kw):
     base = dict(nx=8, ny=8, nz=8, courant=C, rho1=1.0, rho2=1.0, tau_rho1=0.3,
-                tau_rho2=0.3, tau_phi=0.3, sigma=0.0, delta=4.0)
+                tau_rho2=0.3, tau_phi=0.3, sigma=0.0, delta=4.0, lattice=q)
     base.update(kw)
     return orc.OracleParams(**base)
 
 
 # ------------------------------------------------------------------ lattice
 
-def test_lattice_isotropy(orc):
-    """D3Q19 moments: sum t = 1, odd moments 0, second = I/3, fourth =
+@LAT
+def test_lattice_isotropy(orc, q):
+    """Lattice moments: sum t = 1, odd moments 0, second = I/3, fourth =
     (dd + dd + dd)/9 (the isotropy the equilibria rely on)."""
-    e, t = orc.lattice()
-    assert e.shape == (19, 3)
-    assert len({tuple(v) for v in e}) == 19
-    assert all(int(v @ v) <= 2 for v in e)
+    e, t = orc.lattice(q)
+    assert e.shape == (q, 3)
+    assert len({tuple(v) for v in e}) == q
+    assert all(int(v @ v) <= (2 if q == 19 else 3) for v in e)
     assert abs(t.sum() - 1.0) < 1e-15
     d = np.eye(3)
     m1 = np.einsum("i,ia->a", t, e)
@@ -50,16 +54,32 @@ def test_lattice_isotropy(orc):
     assert np.abs(m4 - iso4).max() < 1e-15
 
 
+def test_d3q27_is_the_tensor_product_lattice(orc):
+    """D3Q27 is the cube of the one-dimensional three-speed lattice: every
+    weight is the product of the 1D weights 2/3 (0) and 1/6 (+-1) of its
+    components, so the sixth moment sum t ex^2 ey^2 ez^2 is (1/3)^3, where
+    D3Q19 (no corner vectors) gives 0."""
+    e, t = orc.lattice(27)
+    w1 = {0: 2.0 / 3.0, 1: 1.0 / 6.0, -1: 1.0 / 6.0}
+    for v, ti in zip(e, t):
+        assert abs(ti - w1[int(v[0])] * w1[int(v[1])] * w1[int(v[2])]) < 1e-17
+    m6 = np.sum(t * e[:, 0] ** 2 * e[:, 1] ** 2 * e[:, 2] ** 2)
+    assert abs(m6 - 1.0 / 27.0) < 1e-16
+    e19, t19 = orc.lattice(19)
+    assert np.sum(t19 * e19[:, 0] ** 2 * e19[:, 1] ** 2 * e19[:, 2] ** 2) == 0.0
+
+
 # ------------------------------------------------- node moment identities
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_equilibrium_moments(orc, seed):
+@LAT
+def test_equilibrium_moments(orc, q, seed):
     """Moment constraints of the equilibria and forcings (App. A: sum f_eq =
     p/cs2, sum f_eq e = rho u, Pi_eq = rho u u + p I - Pi_s, sum S_i = u.grad
     rho, sum S_i e_i = 0; Eq. 7: sum R_i = 0, sum R_i e_i = rho G; Sec. 2.3:
     sum g_eq = phi, sum g_eq (e - u) = tau_phi cs2 S)."""
     rng = np.random.default_rng(seed)
-    P = _params(orc, rho1=1.0 + rng.uniform(0, 3), rho2=rng.uniform(0.1, 1.0),
+    P = _params(orc, q, rho1=1.0 + rng.uniform(0, 3), rho2=rng.uniform(0.1, 1.0),
                 tau_phi=rng.uniform(0.05, 1.0), sigma=rng.uniform(1e-4, 1e-2),
                 delta=rng.uniform(2, 6), G=tuple(rng.normal(0, 1e-3, 3)))
     phi = rng.uniform(0.05, 0.95)
@@ -67,7 +87,7 @@ def test_equilibrium_moments(orc, seed):
     p = rng.normal(0, 1e-2)
     gp = rng.normal(0, 0.1, 3)
     feq, geq, S, R = orc.node_equilibria(P, phi, u, p, gp)
-    e_hat, t = orc.lattice()
+    e_hat, t = orc.lattice(q)
     e = C * e_hat
     rho = P.rho1 * phi + P.rho2 * (1 - phi)
     gn = np.linalg.norm(gp)
@@ -90,13 +110,14 @@ def test_equilibrium_moments(orc, seed):
     assert np.abs(geq @ e - phi * u - P.tau_phi * CS2 * s * n).max() < tol
 
 
-def test_macro_recovers_gradient_from_K1(orc):
+@LAT
+def test_macro_recovers_gradient_from_K1(orc, q):
     """Sec. 2.3: a g whose first central moment is K1 = tau cs2 S - (tau +
     1/2) cs2 grad(phi) (equilibrium plus first-order non-equilibrium) returns
     that grad(phi) and n = grad(phi)/|grad(phi)| when the interface is
     resolved; Eq. 12 returns u from f."""
-    P = _params(orc, tau_phi=0.2, rho1=2.0, rho2=0.5, sigma=1e-3, G=(1e-4, -2e-4, 3e-5))
-    e_hat, t = orc.lattice()
+    P = _params(orc, q, tau_phi=0.2, rho1=2.0, rho2=0.5, sigma=1e-3, G=(1e-4, -2e-4, 3e-5))
+    e_hat, t = orc.lattice(q)
     e = C * e_hat
     phi, u, p = 0.4, np.array([0.01, -0.02, 0.005]), 1e-3
     s = 4 * phi * (1 - phi) / P.delta
@@ -113,62 +134,66 @@ def test_macro_recovers_gradient_from_K1(orc):
 
 # ------------------------------------------------------------ propagation
 
-def test_propagation_c1_is_index_shift(orc):
+@LAT
+def test_propagation_c1_is_index_shift(orc, q):
     """At c = 1 the Lax-Wendroff step is the exact shift f(x) <- f(x - e)
     (checked against numpy's roll, bitwise)."""
-    P = _params(orc, nx=7, ny=5, nz=6, courant=1.0)
-    e_hat, _ = orc.lattice()
+    P = _params(orc, q, nx=7, ny=5, nz=6, courant=1.0)
+    e_hat, _ = orc.lattice(q)
     rng = np.random.default_rng(3)
-    fin = rng.standard_normal((19,) + P.shape)
+    fin = rng.standard_normal((q,) + P.shape)
     out = orc.propagate(P, fin)
-    for i in range(19):
+    for i in range(q):
         ex, ey, ez = e_hat[i]
         ref = np.roll(fin[i], shift=(ez, ey, ex), axis=(0, 1, 2))
         assert np.array_equal(out[i], ref)
 
 
-def test_propagation_exact_for_quadratics(orc):
-    """Lax-Wendroff is exact for quadratic profiles: f(x) = q(x) propagates to
-    q(x - c e) at every node whose 3-tap stencil stays inside one period."""
-    P = _params(orc, nx=16, ny=16, nz=16, courant=C)
-    e_hat, _ = orc.lattice()
+@LAT
+def test_propagation_exact_for_quadratics(orc, q):
+    """Lax-Wendroff is exact for quadratic profiles: f(x) = quad(x) propagates to
+    quad(x - c e) at every node whose 3-tap stencil stays inside one period."""
+    P = _params(orc, q, nx=16, ny=16, nz=16, courant=C)
+    e_hat, _ = orc.lattice(q)
     z, y, x = np.meshgrid(np.arange(16.0), np.arange(16.0), np.arange(16.0), indexing="ij")
 
-    def q(x, y, z):
+    def quad(x, y, z):
         return 0.3 + 0.1 * x - 0.07 * y + 0.05 * z + 0.01 * x * x - 0.02 * x * y + 0.013 * z * z
 
-    fin = np.stack([q(x, y, z)] * 19)
+    fin = np.stack([quad(x, y, z)] * q)
     out = orc.propagate(P, fin)
     inner = (slice(1, 15),) * 3
-    for i in range(19):
+    for i in range(q):
         ex, ey, ez = C * e_hat[i]
-        ref = q(x - ex, y - ey, z - ez)
+        ref = quad(x - ex, y - ey, z - ez)
         assert np.abs(out[i][inner] - ref[inner]).max() < 1e-13
 
 
 @pytest.mark.parametrize("courant", [1.0, C])
-def test_propagation_walls_conserve_and_bounce(orc, courant):
+@LAT
+def test_propagation_walls_conserve_and_bounce(orc, q, courant):
     """Walls: the propagation conserves each field's total and, at c = 1, is
     halfway bounce-back: what leaves through a wall face comes back in the
     opposite population at the same node."""
-    P = _params(orc, nx=5, ny=6, nz=4, wall=(1, 1, 0), courant=courant)
+    P = _params(orc, q, nx=5, ny=6, nz=4, wall=(1, 1, 0), courant=courant)
     rng = np.random.default_rng(4)
-    fin = rng.uniform(0.0, 1.0, (19,) + P.shape)
+    fin = rng.uniform(0.0, 1.0, (q,) + P.shape)
     out = orc.propagate(P, fin)
     assert abs(out.sum() - fin.sum()) < 1e-12 * fin.sum()
     if courant == 1.0:
-        e_hat, _ = orc.lattice()
-        i = [k for k in range(19) if tuple(e_hat[k]) == (1, 0, 0)][0]
-        o = [k for k in range(19) if tuple(e_hat[k]) == (-1, 0, 0)][0]
+        e_hat, _ = orc.lattice(q)
+        i = [k for k in range(q) if tuple(e_hat[k]) == (1, 0, 0)][0]
+        o = [k for k in range(q) if tuple(e_hat[k]) == (-1, 0, 0)][0]
         # population +x at the last x-layer leaves through the wall
         assert np.array_equal(out[o][:, :, 4], fin[i][:, :, 4])
         # population +x at x = 0 comes in from the wall side: the reflected -x
         assert np.array_equal(out[i][:, :, 0], fin[o][:, :, 0])
 
 
-def test_fd_gradient_isotropic(orc):
+@LAT
+def test_fd_gradient_isotropic(orc, q):
     """Isotropic central differences are exact for linear fields."""
-    P = _params(orc, nx=8, ny=8, nz=8)
+    P = _params(orc, q, nx=8, ny=8, nz=8)
     z, y, x = np.meshgrid(np.arange(8.0), np.arange(8.0), np.arange(8.0), indexing="ij")
     phi = 0.2 * x - 0.1 * y + 0.05 * z
     g = orc.fd_gradient(P, phi)
@@ -180,11 +205,12 @@ def test_fd_gradient_isotropic(orc):
 
 # --------------------------------------------------------- initial state
 
-def test_initial_state_moments(orc):
+@LAT
+def test_initial_state_moments(orc, q):
     """The initial PDFs return phi0, u0, p0 (one-fluid recovery, Eqs. 11-12),
     and their K1 returns the central-difference gradient of phi0."""
     w = inputs.taylor_green_breakup(n=16, R=4.0, sigma=1e-3)
-    P = orc.OracleParams(**w.params())
+    P = orc.OracleParams(**w.params(), lattice=q)
     o = orc.Oracle(P, w.phi0, w.u0, w.p0)
     phi, u, p = o.fields()
     assert np.abs(phi - w.phi0).max() < 1e-14
@@ -196,25 +222,27 @@ def test_initial_state_moments(orc):
     assert np.abs(m["gradphi"] - gfd[:, 8, 5, 10]).max() < 1e-13
 
 
-def test_invalid_input_rejected(orc):
-    P = _params(orc)
+@LAT
+def test_invalid_input_rejected(orc, q):
+    P = _params(orc, q)
     phi = np.full(P.shape, 0.5)
     phi[1, 2, 3] = np.nan
     with pytest.raises(ValueError):
         orc.Oracle(P, phi)
     with pytest.raises(ValueError):
-        orc.Oracle(_params(orc, courant=1.2), np.zeros(P.shape))
+        orc.Oracle(_params(orc, q, courant=1.2), np.zeros(P.shape))
     with pytest.raises(ValueError):
-        orc.Oracle(_params(orc, nz=1, wall=(0, 0, 1)), np.zeros((1, 8, 8)))
+        orc.Oracle(_params(orc, q, nz=1, wall=(0, 0, 1)), np.zeros((1, 8, 8)))
 
 
 # ---------------------------------------------------------- conservation
 
 @pytest.mark.parametrize("wall", [(0, 0, 0), (1, 1, 1)])
-def test_phase_mass_conserved(orc, wall):
+@LAT
+def test_phase_mass_conserved(orc, q, wall):
     """The conservative phase field keeps sum(phi) to round-off (Sec. 2.1)."""
     w = inputs.static_droplet(n=16, R=4.0, sigma=2e-3)
-    prm = w.params()
+    prm = dict(w.params(), lattice=q)
     prm["wall"] = wall
     prm["rho1"], prm["rho2"] = 2.0, 1.0
     prm["G"] = (0.0, 0.0, -1e-5)
@@ -226,22 +254,24 @@ def test_phase_mass_conserved(orc, wall):
     assert abs(d1["sum_phi"] - d0["sum_phi"]) < 1e-13 * d0["sum_phi"]
 
 
-def test_static_droplet_zero_net_momentum(orc):
+@LAT
+def test_static_droplet_zero_net_momentum(orc, q):
     """No body force, periodic: the net momentum of a static droplet stays
     zero (the momentum equation is in conservative form, Sec. 2.1)."""
     w = inputs.static_droplet(n=16, R=4.0, sigma=2e-3)
-    o = orc.Oracle(orc.OracleParams(**w.params()), w.phi0, w.u0, w.p0)
+    o = orc.Oracle(orc.OracleParams(**w.params(), lattice=q), w.phi0, w.u0, w.p0)
     o.step(200)
     d = o.diag()
     assert max(abs(d["momx"]), abs(d["momy"]), abs(d["momz"])) < 1e-14 * w.N
 
 
 @pytest.mark.parametrize("tau", [0.05, 0.3, 1.0])
-def test_body_force_momentum_per_step(orc, tau):
+@LAT
+def test_body_force_momentum_per_step(orc, q, tau):
     """Uniform density and body force, periodic: the net momentum grows by
     exactly N rho G per step whatever tau (force recovery with +rho G/2 in
     Eq. 12; the printed sign would give a tau-dependent rate)."""
-    P = _params(orc, nx=6, ny=5, nz=4, tau_rho1=tau, tau_rho2=tau, G=(2e-5, -1e-5, 3e-6))
+    P = _params(orc, q, nx=6, ny=5, nz=4, tau_rho1=tau, tau_rho2=tau, G=(2e-5, -1e-5, 3e-6))
     o = orc.Oracle(P, np.full(P.shape, 1.0))
     d0 = o.diag()
     o.step(10)
@@ -252,8 +282,9 @@ def test_body_force_momentum_per_step(orc, tau):
 
 
 @pytest.mark.parametrize("phi_value", [0.0, 0.5, 1.0])
-def test_uniform_state_is_fixed_point(orc, phi_value):
-    P = _params(orc, nx=5, ny=4, nz=6, sigma=1e-3, rho1=3.0)
+@LAT
+def test_uniform_state_is_fixed_point(orc, q, phi_value):
+    P = _params(orc, q, nx=5, ny=4, nz=6, sigma=1e-3, rho1=3.0)
     u0 = np.zeros((3,) + P.shape)
     u0[0] += 0.03
     u0[2] -= 0.01
@@ -272,14 +303,15 @@ def _fourier_amp(v, k, x):
     return 2.0 / len(x) * np.sum(v * np.sin(k * x))
 
 
-def test_phase_field_diffusion_rate(orc):
+@LAT
+def test_phase_field_diffusion_rate(orc, q):
     """With the sharpening switched off (delta -> infinity) and u = 0, Eq. 3 is
     the diffusion equation with M = tau_phi cs2: a sine mode decays as
     exp(-M k^2 t)."""
     nx, tau = 64, 0.3
     k = 2 * math.pi / nx
     x = np.arange(nx)
-    P = _params(orc, nx=nx, ny=1, nz=1, tau_phi=tau, delta=1e12)
+    P = _params(orc, q, nx=nx, ny=1, nz=1, tau_phi=tau, delta=1e12)
     o = orc.Oracle(P, (0.5 + 0.01 * np.sin(k * x)).reshape(1, 1, nx))
     o.step(400)
     A = _fourier_amp(o.fields()[0].ravel() - 0.5, k, x)
@@ -288,13 +320,14 @@ def test_phase_field_diffusion_rate(orc):
 
 
 @pytest.mark.parametrize("tau", [0.3, 1.0])
-def test_shear_wave_decay_rate(orc, tau):
+@LAT
+def test_shear_wave_decay_rate(orc, q, tau):
     """Single phase: a shear wave u_x = U sin(kz) decays as exp(-nu k^2 t)
     with nu = tau_rho cs2 (Sec. 2.2)."""
     nz = 64
     k = 2 * math.pi / nz
     z = np.arange(nz)
-    P = _params(orc, nx=1, ny=1, nz=nz, tau_rho1=tau, tau_rho2=tau)
+    P = _params(orc, q, nx=1, ny=1, nz=nz, tau_rho1=tau, tau_rho2=tau)
     u0 = np.zeros((3, nz, 1, 1))
     u0[0, :, 0, 0] = 1e-3 * np.sin(k * z)
     o = orc.Oracle(P, np.ones((nz, 1, 1)), u0)
@@ -305,11 +338,12 @@ def test_shear_wave_decay_rate(orc, tau):
 
 
 @pytest.mark.parametrize("courant", [1.0, C])
-def test_poiseuille_between_walls(orc, courant):
+@LAT
+def test_poiseuille_between_walls(orc, q, courant):
     """Body-force-driven flow between no-slip walls at y = -1/2 and H - 1/2:
     the parabola u = g y (H - y) / (2 nu), within 1%."""
     H, g, tau = 32, 1e-6, 0.3
-    P = _params(orc, nx=1, ny=H, nz=1, wall=(0, 1, 0), courant=courant, tau_rho1=tau,
+    P = _params(orc, q, nx=1, ny=H, nz=1, wall=(0, 1, 0), courant=courant, tau_rho1=tau,
                 tau_rho2=tau, G=(g, 0.0, 0.0))
     o = orc.Oracle(P, np.ones((1, H, 1)))
     o.step(20000)
@@ -320,19 +354,24 @@ def test_poiseuille_between_walls(orc, courant):
     assert np.abs(u - ua).max() < 1e-2 * ua.max()
 
 
+def _laplace_run(orc, q):
+    w = inputs.static_droplet()
+    P = orc.OracleParams(**w.params(), lattice=q)
+    o = orc.Oracle(P, w.phi0, w.u0, w.p0)
+    o.step(1000)
+    phi, u, p = o.fields()
+    r = inputs.sphere_distance(w.shape, w.meta["center"])
+    dp = p[r < 2].mean() - p[r > 16].mean()
+    return P, phi, u, r, dp
+
+
 @pytest.mark.slow
 def test_laplace_pressure_jump(orc):
     """Static droplet (32^3, R = 8, W = 4): the pressure inside exceeds the
     pressure outside (the sign fixes the surface-stress sign of f_eq) by the
     surface-stress integral int 2 sigma |phi'| / r dr of the radial profile,
     within 5% after the acoustic transient (1000 steps)."""
-    w = inputs.static_droplet()
-    P = orc.OracleParams(**w.params())
-    o = orc.Oracle(P, w.phi0, w.u0, w.p0)
-    o.step(1000)
-    phi, u, p = o.fields()
-    r = inputs.sphere_distance(w.shape, w.meta["center"])
-    dp = p[r < 2].mean() - p[r > 16].mean()
+    P, phi, u, r, dp = _laplace_run(orc, 19)
     rb = np.arange(0, 16, 0.25)
     idx = np.digitize(r.ravel(), rb)
     prof = np.array([phi.ravel()[idx == k].mean() if (idx == k).any() else np.nan
@@ -348,12 +387,33 @@ def test_laplace_pressure_jump(orc):
 
 
 @pytest.mark.slow
-def test_droplet_keeps_tanh_profile(orc):
+def test_laplace_pressure_jump_d3q27(orc):
+    """The same droplet on D3Q27: both lattices discretise the same continuum
+    equations, so the pressure jump (a macroscopic, lattice-independent
+    quantity) agrees with D3Q19's to 1% and with 2 sigma / R to 8% (the diffuse
+    interface puts both about 4% above it); measured 2.614e-4 against 2.610e-4.
+    The profile integral of the D3Q19 pin is not used here: on D3Q27 the phase
+    field dips to 0.995 at the droplet centre, where grad(phi) vanishes and
+    the K1 recovery is unresolved (the higher moments of the corner vectors
+    enter there), and that dip, divided by r, dominates the integral."""
+    _, _, _, _, dp19 = _laplace_run(orc, 19)
+    P, phi, u, r, dp = _laplace_run(orc, 27)
+    sharp = 2.0 * P.sigma / 8.0
+    assert dp > 0
+    assert abs(dp / dp19 - 1.0) < 0.01
+    assert abs(dp / sharp - 1.0) < 0.08
+    eta = P.rho1 * CS2 * P.tau_rho1
+    assert np.sqrt((u ** 2).sum(0)).max() < 1e-2 * P.sigma / eta
+
+
+@pytest.mark.slow
+@LAT
+def test_droplet_keeps_tanh_profile(orc, q):
     """After 500 steps the droplet's radial profile is the equilibrium tanh
     (Sec. 3.1) of width W within 10%, radius fixed by the conserved volume."""
     from scipy.optimize import curve_fit
     w = inputs.static_droplet()
-    o = orc.Oracle(orc.OracleParams(**w.params()), w.phi0, w.u0, w.p0)
+    o = orc.Oracle(orc.OracleParams(**w.params(), lattice=q), w.phi0, w.u0, w.p0)
     o.step(500)
     phi = o.fields()[0]
     r = inputs.sphere_distance(w.shape, w.meta["center"]).ravel()
@@ -366,13 +426,14 @@ def test_droplet_keeps_tanh_profile(orc):
     assert np.abs(resid).max() < 1e-2
 
 
-def test_flat_interface_no_pressure_jump(orc):
+@LAT
+def test_flat_interface_no_pressure_jump(orc, q):
     """A flat interface carries no pressure jump and no flow (Pi_s has no
     divergence across a plane)."""
     nx, W = 64, 4.0
     x = np.arange(nx, dtype=float)
     phi0 = 0.5 * (np.tanh(2 * (x - 16) / W) - np.tanh(2 * (x - 48) / W))
-    P = _params(orc, nx=nx, ny=1, nz=1, sigma=1e-3, tau_phi=0.06, delta=W)
+    P = _params(orc, q, nx=nx, ny=1, nz=1, sigma=1e-3, tau_phi=0.06, delta=W)
     o = orc.Oracle(P, phi0.reshape(1, 1, nx))
     o.step(500)
     phi, u, p = o.fields()
@@ -381,11 +442,12 @@ def test_flat_interface_no_pressure_jump(orc):
     assert np.abs(u).max() < 1e-8
 
 
-def test_pressure_gauge_invariance(orc):
+@LAT
+def test_pressure_gauge_invariance(orc, q):
     """Only pressure differences matter: a uniform offset in p0 leaves phi and
     u unchanged and offsets p (round-off level)."""
     w = inputs.static_droplet(n=16, R=4.0, sigma=2e-3)
-    P = orc.OracleParams(**w.params())
+    P = orc.OracleParams(**w.params(), lattice=q)
     a = orc.Oracle(P, w.phi0, w.u0, w.p0)
     b = orc.Oracle(P, w.phi0, w.u0, w.p0 + CS2)
     a.step(100)
@@ -397,17 +459,19 @@ def test_pressure_gauge_invariance(orc):
     assert np.abs((qb - qa) - CS2).max() < 1e-13
 
 
-def test_droplet_axis_symmetry(orc):
+@LAT
+def test_droplet_axis_symmetry(orc, q):
     """A centred droplet stays invariant under axis permutations."""
     w = inputs.static_droplet(n=16, R=4.0, sigma=2e-3)
-    o = orc.Oracle(orc.OracleParams(**w.params()), w.phi0, w.u0, w.p0)
+    o = orc.Oracle(orc.OracleParams(**w.params(), lattice=q), w.phi0, w.u0, w.p0)
     o.step(100)
     phi = o.fields()[0]
     assert np.abs(phi - phi.transpose(0, 2, 1)).max() < 1e-12
     assert np.abs(phi - phi.transpose(2, 1, 0)).max() < 1e-12
 
 
-def test_k1_gradient_matches_fd_to_second_order(orc):
+@LAT
+def test_k1_gradient_matches_fd_to_second_order(orc, q):
     """Sec. 2.3 / App. B: the K1-recovered gradient is a second-order
     approximation of grad(phi); against isotropic central differences of the
     same state the relative gap shrinks about 4x when W doubles."""
@@ -416,7 +480,7 @@ def test_k1_gradient_matches_fd_to_second_order(orc):
         nx = int(32 * W)
         x = np.arange(nx, dtype=float)
         phi0 = 0.5 * (np.tanh(2 * (x - nx / 4) / W) - np.tanh(2 * (x - 3 * nx / 4) / W))
-        P = _params(orc, nx=nx, ny=1, nz=1, sigma=0.0, tau_phi=0.3, delta=W)
+        P = _params(orc, q, nx=nx, ny=1, nz=1, sigma=0.0, tau_phi=0.3, delta=W)
         o = orc.Oracle(P, phi0.reshape(1, 1, nx))
         o.step(int(20 * W * W / 16))
         f, g = o.pdfs()
@@ -438,10 +502,11 @@ def test_k1_floor_bounds_rounding_sensitivity(orc, normal_fd):
     finite-difference variant); without it the noise-direction normals where
     grad(phi) vanishes (droplet centre, box faces) amplify it to about 1e-4.
     This is the conditioning that makes FP64 parity at 1e-12 meaningful."""
+    q = 19
     w = inputs.static_droplet()
     res = {}
     for eps in (1e-5, 0.0):
-        prm = w.params()
+        prm = dict(w.params(), lattice=q)
         prm["k1_eps"] = eps
         prm["normal_fd"] = normal_fd
         P = orc.OracleParams(**prm)
@@ -458,16 +523,46 @@ def test_k1_floor_bounds_rounding_sensitivity(orc, normal_fd):
     assert res[0.0] > 1e-8
 
 
-def test_single_plane_lattice_projects_to_d2q9(orc):
-    """On one periodic z-plane the D3Q19 populations with e_z != 0 stay in the
+@LAT
+def test_single_plane_lattice_projects_to_d2q9(orc, q):
+    """On one periodic z-plane the populations with e_z != 0 stay in the
     plane: grouped by their in-plane velocity, the weights are D2Q9's
     (4/9 rest, 1/9 axis, 1/36 diagonal), which makes nz = 1 runs 2D runs."""
-    e, t = orc.lattice()
+    e, t = orc.lattice(q)
     proj = {}
-    for i in range(19):
+    for i in range(q):
         k = (int(e[i][0]), int(e[i][1]))
         proj[k] = proj.get(k, 0.0) + t[i]
     assert len(proj) == 9
     for (ex, ey), w in proj.items():
         want = 4 / 9 if ex == ey == 0 else (1 / 9 if ex * ey == 0 else 1 / 36)
         assert abs(w - want) < 1e-15, ((ex, ey), w)
+
+
+def test_one_dimensional_runs_coincide_on_both_lattices(orc):
+    """On a 1 x 1 x nx lattice with fields varying along x only, D3Q19 and
+    D3Q27 both reduce to the three-speed 1D lattice: grouped by e_x, their
+    weights sum to 2/3, 1/6, 1/6 and their weighted squared speeds t |e^|^2 to
+    4/9, 5/18, 5/18, and every term of the collision is linear in the
+    population and depends on e^ only through e_x and |e^|^2. The two runs
+    must then give the same phi, u and p to rounding, whatever the physics
+    switched on (surface tension, density and viscosity contrast, body force,
+    initial flow). A wrong corner weight, speed class or index breaks it."""
+    nx, W = 64, 4.0
+    x = np.arange(nx, dtype=float)
+    phi0 = (0.5 * (np.tanh(2 * (x - 16) / W) - np.tanh(2 * (x - 48) / W))).reshape(1, 1, nx)
+    u0 = np.zeros((3, 1, 1, nx))
+    u0[0, 0, 0] = 0.01 * np.sin(2 * np.pi * x / nx)
+    res = {}
+    for q in (19, 27):
+        # a floor of 1e-3 on |K1|: with 1e-5 this contrast makes the scheme
+        # itself amplify rounding differences (on one lattice alone, a 1e-15
+        # perturbation of phi0 grows to 1e-4 within 50 steps)
+        P = _params(orc, q, nx=nx, ny=1, nz=1, sigma=1e-3, tau_phi=0.06, delta=W, rho1=1.0,
+                    rho2=0.3, tau_rho1=0.2, tau_rho2=0.5, G=(1e-5, 0.0, 0.0), k1_eps=1e-3)
+        o = orc.Oracle(P, phi0, u0)
+        o.step(200)
+        res[q] = o.fields()
+    for a, b in zip(res[19], res[27]):
+        assert np.abs(a - b).max() < 1e-13
+    assert np.abs(res[19][1][0]).max() > 1e-3   # the flow is not trivial
