@@ -181,9 +181,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--storage", default="fp16", choices=["fp16", "bf16", "fp32", "fp64"])
-    ap.add_argument("--secondary", default="bf16,fp32,fp16+fd",
+    ap.add_argument("--secondary", default="bf16,fp32,fp16+fd,fp16+q27",
                     help="comma list of extra runs: storage mode, '+fd' for the "
-                         "finite-difference-normal comparison scheme")
+                         "finite-difference-normal comparison scheme, '+q27' for D3Q27")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate-accelerated emulsion runs")
     ap.add_argument("--surrogate-trajectories", type=int, default=32,
@@ -206,11 +206,16 @@ def main():
     w = inputs.rayleigh_taylor()  # 128 x 512 x 128, Re = 256, At = 0.5
     results = {}
     modes = [args.storage] + [m for m in args.secondary.split(",") if m and m != args.storage]
+    def parse_mode(mode):
+        parts = mode.split("+")
+        return parts[0], int("fd" in parts[1:]), 27 if "q27" in parts[1:] else 19
+
     for mode in modes:
-        prec, fd = (mode[:-3], 1) if mode.endswith("+fd") else (mode, 0)
-        print(f"[bench] {w.name} storage={prec} normal_fd={fd} warmup={args.warmup} "
-              f"steps={args.steps}", file=sys.stderr, flush=True)
-        sol = lbm.Solver(dict(w.params(), precision=prec, normal_fd=fd), w.phi0, w.u0, w.p0)
+        prec, fd, q = parse_mode(mode)
+        print(f"[bench] {w.name} storage={prec} normal_fd={fd} lattice=D3Q{q} "
+              f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+        sol = lbm.Solver(dict(w.params(), precision=prec, normal_fd=fd, lattice=q), w.phi0, w.u0,
+                         w.p0)
         secs = time_solver(sol, args.steps, args.warmup)
         d = sol.diagnostics()
         ok = all(map(lambda v: v == v, [d["sum_phi"], d["umax"]]))
@@ -248,7 +253,8 @@ def main():
                      "kernel": "step_kernel (fused propagate+moments+collide+store; interior "
                                "and wall-slab launches)"},
         "secondary": {m: {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 5),
-                          "hbm_frac": round(lbm.BYTES_PER_LU[m.split("+")[0]] * w.N
+                          "hbm_frac": round((lbm.BYTES_PER_LU_Q27 if parse_mode(m)[2] == 27
+                                             else lbm.BYTES_PER_LU)[parse_mode(m)[0]] * w.N
                                             / (r["seconds"] / args.steps) / 1e9 / HBM_PEAK_GBS, 4)}
                       for m, r in results.items() if m != args.storage},
         "checks": {m: {"finite": r["finite"], "sum_phi": r["sum_phi"], "umax": r["umax"]}

@@ -2,7 +2,8 @@
  * lbm.h -- C ABI of the MI355X difference-free conservative phase-field
  * lattice Boltzmann solver (Zhao, Patel & Lee, arXiv 2407.12263).
  *
- * One time step advances two D3Q19 populations per lattice node:
+ * One time step advances two populations per lattice node (D3Q19, or D3Q27
+ * with lbm_params.lattice = 27):
  *   f  -- the one-fluid hydrodynamic PDF: sum f = p/c_s^2, surface tension as
  *         a continuous surface stress inside its equilibrium (Sec. 2.2,
  *         Eqs. 6-12; the surface-stress term enters f_eq with a minus sign so
@@ -15,10 +16,11 @@
  * Crank-Nicolson collision of both populations (Eqs. 10, 16).
  *
  * Units: grid units, dx = dt = 1, discrete velocities c*e^_i (e^_i integer
- * D3Q19 vectors), c_s^2 = c^2/3, nu = tau_rho c_s^2, M = tau_phi c_s^2.
+ * lattice vectors), c_s^2 = c^2/3, nu = tau_rho c_s^2, M = tau_phi c_s^2.
  * Scalar fields are structure-of-arrays with index n = x + nx*(y + ny*z);
  * a vector field stores component a at a*N + n; a PDF field stores
- * population i at i*N + n, in the library's own D3Q19 order (see lbm_lattice).
+ * population i at i*N + n, in the library's own lattice order (see
+ * lbm_lattice_q); Q = 19 or 27 populations per field.
  *
  * Ownership: the caller owns every device buffer (workspace, inputs,
  * outputs) and the stream; the library only borrows them. The library owns
@@ -63,8 +65,8 @@ typedef enum {
 } lbm_precision;
 
 typedef struct {
-    int32_t nx, ny, nz;        /* lattice size; N = nx*ny*nz, 19*N < 2^31 and */
-                               /* 19*N*bytes per value < 2^32                 */
+    int32_t nx, ny, nz;        /* lattice size; N = nx*ny*nz, Q*N < 2^31 and  */
+                               /* Q*N*bytes per value < 2^32                  */
     int32_t precision;         /* lbm_precision                               */
     int32_t wall[3];           /* per axis: 0 periodic, 1 no-slip walls on    */
                                /* both faces (halfway between nodes; neutral  */
@@ -98,6 +100,9 @@ typedef struct {
     double k1_eps;             /* normal n = -K1/|K1| where |K1| > k1_eps,    */
                                /* n = 0 otherwise (>= 0; 1e-5 recommended)    */
     double p_ref;              /* pressure gauge of the 16-bit f storage      */
+    int32_t lattice;           /* 19 or 0: D3Q19; 27: D3Q27 (the same method  */
+                               /* on the 27-vector lattice, weights 8/27,     */
+                               /* 2/27, 1/54, 1/216; no normal_fd = 1 on it)  */
 } lbm_params;
 
 /* Diagnostics of the state at the current time t (moments of the
@@ -119,6 +124,12 @@ typedef struct {
 
 /* The library's D3Q19 order: e (19x3 integers, row-major) and weights t. */
 void lbm_lattice(int32_t e[57], double t[19]);
+
+/* The library's order of lattice q (19 or 27): e (q x 3 integers, row-major)
+ * and weights t (q); the PDFs of lbm_get_pdfs / lbm_set_pdfs follow it. The
+ * D3Q27 order is the D3Q19 order followed by the 8 corner vectors, opposite
+ * directions adjacent. Returns LBM_EINVAL for another q or a NULL pointer. */
+int lbm_lattice_q(int32_t q, int32_t *e, double *t);
 
 /* Bytes of device workspace a context with these parameters needs. */
 int lbm_workspace_bytes(const lbm_params *P, size_t *bytes);
@@ -148,12 +159,12 @@ int lbm_fields(lbm_ctx *ctx, void *d_phi, void *d_u, void *d_p, int32_t dtype);
  * Blocks until the result is on the host. */
 int lbm_diagnostics(lbm_ctx *ctx, const double *d_phi_ref, lbm_diag *out);
 
-/* Writes the post-propagation PDFs at t as FP64 (19N each, device).
+/* Writes the post-propagation PDFs at t as FP64 (Q*N each, device).
  * Together with lbm_set_pdfs this is checkpoint and restart. */
 int lbm_get_pdfs(lbm_ctx *ctx, double *d_f, double *d_g);
 
 /* Replaces the state at the current t by the given post-propagation PDFs
- * (device FP64, 19N each), rounded to the storage precision. */
+ * (device FP64, Q*N each), rounded to the storage precision. */
 int lbm_set_pdfs(lbm_ctx *ctx, const double *d_f, const double *d_g);
 
 /* Rebuilds the state in place from fields (device FP64, as lbm_init) and

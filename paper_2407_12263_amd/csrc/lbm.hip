@@ -75,6 +75,9 @@ bool is16(int precision) {
     return precision == LBM_FP32_FP16STORE || precision == LBM_FP32_BF16STORE;
 }
 
+// Populations per field: 19 (D3Q19; lattice = 0 means the same) or 27.
+int num_pop(const lbm_params *P) { return P->lattice == 27 ? 27 : 19; }
+
 // Bytes from one population plane to the next: N elements (16-bit storage:
 // the 32-bit f/g words) rounded up to 256 B, plus a pad of 64 KiB + 256 B.
 // With power-of-two strides (the usual lattice sizes) the 19 planes of a
@@ -91,8 +94,8 @@ size_t plane_pitch(const lbm_params *P) {
 }
 
 struct Layout {
-    size_t pdf_bytes;      // f (16-bit storage: f and g words), 19 planes
-    size_t g_bytes;        // g, 19 planes (0 for 16-bit storage)
+    size_t pdf_bytes;      // f (16-bit storage: f and g words), Q planes
+    size_t g_bytes;        // g, Q planes (0 for 16-bit storage)
     size_t phis_bytes;     // N floats (16-bit storage) or 0
     size_t buf_bytes;      // f + g + phis of one ping-pong buffer
     size_t partial_bytes;  // NSUM doubles per reduction block
@@ -110,7 +113,7 @@ Layout layout_of(const lbm_params *P) {
     // shape can give (tile width 1)
     TileCfg narrow{0, 0, 1};
     const size_t nblocks = num_tiles(P, narrow);
-    L.pdf_bytes = align_up(19 * plane_pitch(P));
+    L.pdf_bytes = align_up((size_t)num_pop(P) * plane_pitch(P));
     L.g_bytes = is16(P->precision) ? 0 : L.pdf_bytes;
     L.phis_bytes = is16(P->precision) ? align_up(N * sizeof(float)) : 0;
     L.buf_bytes = L.pdf_bytes + L.g_bytes + L.phis_bytes;
@@ -127,12 +130,16 @@ Layout layout_of(const lbm_params *P) {
 int validate(const lbm_params *P) {
     if (!P) return LBM_EINVAL;
     if (P->nx < 1 || P->ny < 1 || P->nz < 1) return LBM_EINVAL;
+    if (P->lattice != 0 && P->lattice != 19 && P->lattice != 27) return LBM_EINVAL;
+    // the finite-difference comparison scheme is built for D3Q19 only
+    if (P->lattice == 27 && P->normal_fd) return LBM_EINVAL;
     const double N = (double)P->nx * P->ny * P->nz;
-    if (19.0 * N >= 2147483647.0) return LBM_EINVAL;
+    const double Q = num_pop(P);
+    if (Q * N >= 2147483647.0) return LBM_EINVAL;
     if (P->precision < LBM_FP64 || P->precision > LBM_FP32_BF16STORE) return LBM_EINVAL;
     // every population field is addressed through one 32-bit buffer range
     // (16-bit storage keeps f and g of a population in one 32-bit plane)
-    if (19.0 * (double)plane_pitch(P) >= 4294967295.0) return LBM_EINVAL;
+    if (Q * (double)plane_pitch(P) >= 4294967295.0) return LBM_EINVAL;
     const int nn[3] = {P->nx, P->ny, P->nz};
     for (int a = 0; a < 3; ++a) {
         if (P->wall[a] != 0 && P->wall[a] != 1) return LBM_EINVAL;
@@ -318,7 +325,7 @@ template <class St, Mode M, bool W, bool FD>
 void launch_step(lbm_ctx *c, int src, int dst, const DevParams<typename St::R> &P, MassFix mf,
                  int &block_off) {
     mf.block_off = block_off;
-    if constexpr (St::DEV && !W && !FD)
+    if constexpr (St::DEV && !W && !FD && St::Q == 19)
         hipLaunchKernelGGL((step_kernel_o5<St, M, W, FD>), tile_grid(P), dim3(BLOCK), 0,
                            c->stream, cbuf_of<St>(c, src), buf_of<St>(c, dst), P, mf);
     else
@@ -399,14 +406,16 @@ void launch_step_w(lbm_ctx *c, int src, int dst, const MassFix &mf) {
 
 template <class St, Mode M>
 void launch_step_fd(lbm_ctx *c, int src, int dst, const MassFix &mf) {
-    if (c->P.normal_fd) {
-        MassFix apply = mf;
-        apply.mode &= 2;
-        launch_phi<St, M>(c, src, apply);
-        launch_step_w<St, M, true>(c, src, dst, mf);
-    } else {
-        launch_step_w<St, M, false>(c, src, dst, mf);
+    if constexpr (St::Q == 19) {
+        if (c->P.normal_fd) {
+            MassFix apply = mf;
+            apply.mode &= 2;
+            launch_phi<St, M>(c, src, apply);
+            launch_step_w<St, M, true>(c, src, dst, mf);
+            return;
+        }
     }
+    launch_step_w<St, M, false>(c, src, dst, mf);
 }
 
 template <class St>
@@ -418,14 +427,37 @@ void step_dispatch(lbm_ctx *c, Mode m, int src, int dst, const MassFix &mf) {
     }
 }
 
+// Calls F::template run<St>(args...) with the storage type of the context's
+// precision and lattice.
+template <class F, class... A>
+void with_storage(const lbm_ctx *c, A &&...args) {
+    const bool q27 = num_pop(&c->P) == 27;
+    switch (c->P.precision) {
+        case LBM_FP64:
+            q27 ? F::template run<Q27<SF64>>(args...) : F::template run<SF64>(args...);
+            break;
+        case LBM_FP32:
+            q27 ? F::template run<Q27<SF32>>(args...) : F::template run<SF32>(args...);
+            break;
+        case LBM_FP32_FP16STORE:
+            q27 ? F::template run<Q27<SH16>>(args...) : F::template run<SH16>(args...);
+            break;
+        default:
+            q27 ? F::template run<Q27<SB16>>(args...) : F::template run<SB16>(args...);
+            break;
+    }
+}
+
+struct StepOp {
+    template <class St>
+    static void run(lbm_ctx *c, Mode m, int src, int dst, const MassFix &mf) {
+        step_dispatch<St>(c, m, src, dst, mf);
+    }
+};
+
 void step_any(lbm_ctx *c, Mode m, int src, int dst, int mf_mode = 0) {
     const MassFix mf{mf_mode, c->partials, c->mf + 1, 0};
-    switch (c->P.precision) {
-        case LBM_FP64: step_dispatch<SF64>(c, m, src, dst, mf); break;
-        case LBM_FP32: step_dispatch<SF32>(c, m, src, dst, mf); break;
-        case LBM_FP32_FP16STORE: step_dispatch<SH16>(c, m, src, dst, mf); break;
-        default: step_dispatch<SB16>(c, m, src, dst, mf); break;
-    }
+    with_storage<StepOp>(c, c, m, src, dst, mf);
 }
 
 Mode prop_mode(const lbm_ctx *c) { return c->P.courant == 1.0 ? SHIFT : LW; }
@@ -434,14 +466,16 @@ template <class St, Mode M, bool W>
 void launch_moments(lbm_ctx *c, const FieldOut &o) {
     using R = typename St::R;
     const DevParams<R> P = launch_params<R>(c);
-    if (c->P.normal_fd) {
-        launch_phi<St, M>(c, c->cur ^ 1, MassFix{0, nullptr, nullptr, 0});
-        hipLaunchKernelGGL((moments_kernel<St, M, W, true>), tile_grid(P), dim3(BLOCK), 0,
-                           c->stream, cbuf_of<St>(c, c->cur ^ 1), P, o);
-    } else {
-        hipLaunchKernelGGL((moments_kernel<St, M, W, false>), tile_grid(P), dim3(BLOCK), 0,
-                           c->stream, cbuf_of<St>(c, c->cur ^ 1), P, o);
+    if constexpr (St::Q == 19) {
+        if (c->P.normal_fd) {
+            launch_phi<St, M>(c, c->cur ^ 1, MassFix{0, nullptr, nullptr, 0});
+            hipLaunchKernelGGL((moments_kernel<St, M, W, true>), tile_grid(P), dim3(BLOCK), 0,
+                               c->stream, cbuf_of<St>(c, c->cur ^ 1), P, o);
+            return;
+        }
     }
+    hipLaunchKernelGGL((moments_kernel<St, M, W, false>), tile_grid(P), dim3(BLOCK), 0,
+                       c->stream, cbuf_of<St>(c, c->cur ^ 1), P, o);
 }
 
 template <class St, Mode M>
@@ -458,14 +492,14 @@ void moments_dispatch(lbm_ctx *c, const FieldOut &o) {
     else moments_w<St, LW>(c, o);
 }
 
-void moments_any(lbm_ctx *c, const FieldOut &o) {
-    switch (c->P.precision) {
-        case LBM_FP64: moments_dispatch<SF64>(c, o); break;
-        case LBM_FP32: moments_dispatch<SF32>(c, o); break;
-        case LBM_FP32_FP16STORE: moments_dispatch<SH16>(c, o); break;
-        default: moments_dispatch<SB16>(c, o); break;
+struct MomentsOp {
+    template <class St>
+    static void run(lbm_ctx *c, const FieldOut &o) {
+        moments_dispatch<St>(c, o);
     }
-}
+};
+
+void moments_any(lbm_ctx *c, const FieldOut &o) { with_storage<MomentsOp>(c, c, o); }
 
 template <class St>
 void launch_init(lbm_ctx *c, const double *phi0, const double *u0, const double *p0, int dst) {
@@ -481,13 +515,15 @@ void launch_init(lbm_ctx *c, const double *phi0, const double *u0, const double 
                            phi0, u0, p0, PD, PR, buf_of<St>(c, dst), c->flag, c->partials);
 }
 
-void init_any(lbm_ctx *c, const double *phi0, const double *u0, const double *p0, int dst) {
-    switch (c->P.precision) {
-        case LBM_FP64: launch_init<SF64>(c, phi0, u0, p0, dst); break;
-        case LBM_FP32: launch_init<SF32>(c, phi0, u0, p0, dst); break;
-        case LBM_FP32_FP16STORE: launch_init<SH16>(c, phi0, u0, p0, dst); break;
-        default: launch_init<SB16>(c, phi0, u0, p0, dst); break;
+struct InitOp {
+    template <class St>
+    static void run(lbm_ctx *c, const double *phi0, const double *u0, const double *p0, int dst) {
+        launch_init<St>(c, phi0, u0, p0, dst);
     }
+};
+
+void init_any(lbm_ctx *c, const double *phi0, const double *u0, const double *p0, int dst) {
+    with_storage<InitOp>(c, c, phi0, u0, p0, dst);
 }
 
 template <class St>
@@ -498,13 +534,15 @@ void launch_load(lbm_ctx *c, const double *f, const double *g, int dst) {
                        buf_of<St>(c, dst));
 }
 
-void load_any(lbm_ctx *c, const double *f, const double *g, int dst) {
-    switch (c->P.precision) {
-        case LBM_FP64: launch_load<SF64>(c, f, g, dst); break;
-        case LBM_FP32: launch_load<SF32>(c, f, g, dst); break;
-        case LBM_FP32_FP16STORE: launch_load<SH16>(c, f, g, dst); break;
-        default: launch_load<SB16>(c, f, g, dst); break;
+struct LoadOp {
+    template <class St>
+    static void run(lbm_ctx *c, const double *f, const double *g, int dst) {
+        launch_load<St>(c, f, g, dst);
     }
+};
+
+void load_any(lbm_ctx *c, const double *f, const double *g, int dst) {
+    with_storage<LoadOp>(c, c, f, g, dst);
 }
 
 // Runs the diagnostics reduction of the state at t into c->result (device).
@@ -542,14 +580,24 @@ int build_state(lbm_ctx *c, const double *d_phi, const double *d_u, const double
 
 extern "C" {
 
-void lbm_lattice(int32_t e[57], double t[19]) {
-    for (int i = 0; i < 19; ++i) {
-        e[3 * i + 0] = Lat::EX[i];
-        e[3 * i + 1] = Lat::EY[i];
-        e[3 * i + 2] = Lat::EZ[i];
-        const int cl = Lat::cls(i);
-        t[i] = cl == 0 ? 1.0 / 3.0 : (cl == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+void lbm_lattice(int32_t e[57], double t[19]) { lbm_lattice_q(19, e, t); }
+
+int lbm_lattice_q(int32_t q, int32_t *e, double *t) {
+    if ((q != 19 && q != 27) || !e || !t) return LBM_EINVAL;
+    for (int i = 0; i < q; ++i) {
+        const int ex = q == 27 ? LatQ<27>::EX[i] : LatQ<19>::EX[i];
+        const int ey = q == 27 ? LatQ<27>::EY[i] : LatQ<19>::EY[i];
+        const int ez = q == 27 ? LatQ<27>::EZ[i] : LatQ<19>::EZ[i];
+        e[3 * i + 0] = ex;
+        e[3 * i + 1] = ey;
+        e[3 * i + 2] = ez;
+        const int cl = ex * ex + ey * ey + ez * ez;
+        if (q == 27)
+            t[i] = cl == 0 ? 8.0 / 27.0 : (cl == 1 ? 2.0 / 27.0 : (cl == 2 ? 1.0 / 54.0 : 1.0 / 216.0));
+        else
+            t[i] = cl == 0 ? 1.0 / 3.0 : (cl == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
     }
+    return LBM_OK;
 }
 
 int lbm_workspace_bytes(const lbm_params *P, size_t *bytes) {

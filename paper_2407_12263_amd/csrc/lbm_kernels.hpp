@@ -2,16 +2,16 @@
 // conservative phase-field LBM step (Zhao, Patel & Lee, arXiv 2407.12263).
 //
 // One thread per lattice node, one pass per step: each thread pulls the
-// Lax-Wendroff taps of its 2 x 19 populations from the post-collision
-// buffer, recovers phi, u, K1, n, grad(phi), p in registers, collides both
-// populations and writes 2 x 19 post-collision values. The only non-local
+// Lax-Wendroff taps of its 2 x Q populations (D3Q19, or D3Q27) from the
+// post-collision buffer, recovers phi, u, K1, n, grad(phi), p in registers,
+// collides both populations and writes 2 x Q post-collision values. The only non-local
 // operation is the propagation; the interface normal and grad(phi) come from
 // the node's own K1 (Sec. 2.3), so no neighbour field is ever differenced.
 //
 // Memory access: structure-of-arrays planes (population i of all nodes is
 // contiguous, x fastest), read and written with buffer instructions whose
 // plane offset i*N*size is a scalar register and whose per-lane offset is
-// one of the 19 stencil-node offsets computed once per thread, so no vector
+// one of the Q stencil-node offsets computed once per thread, so no vector
 // instruction is spent on addresses. A block is a tile of whole x-rows of one
 // z-plane (a wavefront covers 64 contiguous nodes of a row: every load is a
 // coalesced row segment); the block-to-tile order is selectable (plain, XCD
@@ -32,7 +32,15 @@ namespace cpf {
 
 // ---------------------------------------------------------------- lattice
 // D3Q19: rest, 6 axis vectors, 12 edge vectors; weights 1/3, 1/18, 1/36.
-struct Lat {
+// D3Q27: the same 19 followed by the 8 corner vectors; weights 8/27, 2/27,
+// 1/54, 1/216 (products of the 1D weights 2/3, 1/6, 1/6). In both, the
+// directions after the rest come in opposite pairs (i, i + 1) for odd i.
+template <int NQ>
+struct LatQ;
+
+template <>
+struct LatQ<19> {
+    static constexpr int Q = 19;
     static constexpr int EX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
     static constexpr int EY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
     static constexpr int EZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
@@ -40,18 +48,43 @@ struct Lat {
     static constexpr int cls(int i) { return EX[i] * EX[i] + EY[i] * EY[i] + EZ[i] * EZ[i]; }
 };
 
+template <>
+struct LatQ<27> {
+    static constexpr int Q = 27;
+    static constexpr int EX[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                                   1, -1, 1, -1, 1, -1, -1, 1};
+    static constexpr int EY[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                                   1, -1, 1, -1, -1, 1, 1, -1};
+    static constexpr int EZ[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                                   1, -1, -1, 1, 1, -1, 1, -1};
+    static constexpr int OPP[27] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17,
+                                    20, 19, 22, 21, 24, 23, 26, 25};
+    static constexpr int cls(int i) { return EX[i] * EX[i] + EY[i] * EY[i] + EZ[i] * EZ[i]; }
+};
+
 // Weights by speed class. In FP32 the rounded 1/3, 1/18, 1/36 sum to
 // 1 + 1.5e-8, which would make every collision create that fraction of phi
-// (a 1e-4 relative drift of the phase mass over 1e4 steps); the FP32 set below
-// is exactly representable, sums to exactly 1 (t0 + 6 t1 + 12 t2) and is
-// within 2 ulp of the true weights.
-template <class R>
+// (a 1e-4 relative drift of the phase mass over 1e4 steps); the FP32 sets
+// below are exactly representable, sum to exactly 1 (t0 + 6 t1 + 12 t2
+// [+ 8 t3]) and are within 2.1 ulp of the true weights.
+template <class R, int NQ = 19>
 __device__ __forceinline__ constexpr R wgt(int cls) {
-    if constexpr (std::is_same_v<R, float>) {
-        return cls == 0 ? 89478496.0f / 268435456.0f
-                        : (cls == 1 ? 14913080.0f / 268435456.0f : 7456540.0f / 268435456.0f);
+    constexpr float s = 1.0f / 268435456.0f;  // 2^-28
+    if constexpr (NQ == 27) {
+        if constexpr (std::is_same_v<R, float>) {
+            return cls == 0 ? 79536440.0f * s
+                            : (cls == 1 ? 19884104.0f * s
+                                        : (cls == 2 ? 4971028.0f * s : 1242757.0f * s));
+        } else {
+            return cls == 0 ? R(8) / R(27)
+                            : (cls == 1 ? R(2) / R(27) : (cls == 2 ? R(1) / R(54) : R(1) / R(216)));
+        }
     } else {
-        return cls == 0 ? R(1) / R(3) : (cls == 1 ? R(1) / R(18) : R(1) / R(36));
+        if constexpr (std::is_same_v<R, float>) {
+            return cls == 0 ? 89478496.0f * s : (cls == 1 ? 14913080.0f * s : 7456540.0f * s);
+        } else {
+            return cls == 0 ? R(1) / R(3) : (cls == 1 ? R(1) / R(18) : R(1) / R(36));
+        }
     }
 }
 
@@ -64,12 +97,13 @@ __device__ __forceinline__ void unroll(F &&f) {
 }
 
 // sum_i v_i * e^_ia with compile-time integer components
-template <int A, class R>
-__device__ __forceinline__ R first_moment(const R (&v)[19]) {
+template <int A, class R, int NQ>
+__device__ __forceinline__ R first_moment(const R (&v)[NQ]) {
+    using L = LatQ<NQ>;
     R s = R(0);
-    unroll<1, 19>([&](auto I) {
+    unroll<1, NQ>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        constexpr int e = A == 0 ? Lat::EX[i] : (A == 1 ? Lat::EY[i] : Lat::EZ[i]);
+        constexpr int e = A == 0 ? L::EX[i] : (A == 1 ? L::EY[i] : L::EZ[i]);
         if constexpr (e > 0) s += v[i];
         if constexpr (e < 0) s -= v[i];
     });
@@ -77,9 +111,10 @@ __device__ __forceinline__ R first_moment(const R (&v)[19]) {
 }
 
 // e^_i . v for a compile-time direction
-template <int i, class R>
+template <int i, int NQ, class R>
 __device__ __forceinline__ R edot(const R (&v)[3]) {
-    constexpr int ex = Lat::EX[i], ey = Lat::EY[i], ez = Lat::EZ[i];
+    using L = LatQ<NQ>;
+    constexpr int ex = L::EX[i], ey = L::EY[i], ez = L::EZ[i];
     R s = R(0);
     bool first = true;
     auto add = [&](int e, R x) {
@@ -148,14 +183,18 @@ __device__ __forceinline__ uint32_t linear_block() {
 }
 
 // ---------------------------------------------------------- storage types
-struct SF64 { using R = double; using T = double; static constexpr bool DEV = false; };
-struct SF32 { using R = float;  using T = float;  static constexpr bool DEV = false; };
-struct SH16 { using R = float;  using T = _Float16; static constexpr bool DEV = true; };
-struct SB16 { using R = float;  using T = uint16_t; static constexpr bool DEV = true; };
+// Q: populations per field (the lattice); BF: BF16 storage.
+struct SF64 { using R = double; using T = double; static constexpr bool DEV = false, BF = false; static constexpr int Q = 19; };
+struct SF32 { using R = float;  using T = float;  static constexpr bool DEV = false, BF = false; static constexpr int Q = 19; };
+struct SH16 { using R = float;  using T = _Float16; static constexpr bool DEV = true, BF = false; static constexpr int Q = 19; };
+struct SB16 { using R = float;  using T = uint16_t; static constexpr bool DEV = true, BF = true; static constexpr int Q = 19; };
+// The same storage on D3Q27.
+template <class S>
+struct Q27 : S { static constexpr int Q = 27; };
 
 template <class St>
 __device__ __forceinline__ typename St::R decode(typename St::T v) {
-    if constexpr (std::is_same_v<St, SB16>) {
+    if constexpr (St::BF) {
         return __uint_as_float(uint32_t(v) << 16);
     } else {
         return typename St::R(v);
@@ -164,7 +203,7 @@ __device__ __forceinline__ typename St::R decode(typename St::T v) {
 
 template <class St>
 __device__ __forceinline__ typename St::T encode(typename St::R x) {
-    if constexpr (std::is_same_v<St, SB16>) {
+    if constexpr (St::BF) {
         // round to nearest even (finite inputs)
         uint32_t u = __float_as_uint(x);
         u += 0x7fffu + ((u >> 16) & 1u);
@@ -176,8 +215,8 @@ __device__ __forceinline__ typename St::T encode(typename St::R x) {
 
 template <class St>
 struct Buf {
-    typename St::T *f;   // 19 planes of N
-    typename St::T *g;   // 19 planes of N
+    typename St::T *f;   // Q planes of N
+    typename St::T *g;   // Q planes of N
     float *phis;         // N (16-bit storage only)
 };
 
@@ -229,11 +268,12 @@ __device__ __forceinline__ void bstore(T v, rsrc_t r, uint32_t voff, uint32_t so
 }
 
 // ------------------------------------------------------- node geometry
+template <int NQ>
 struct Site {
     int x, y, z;
     bool valid;
     uint32_t n;          // node index
-    uint32_t nb[19];     // index of node x + e^_j (wrapped), nb[0] = n
+    uint32_t nb[NQ];     // index of node x + e^_j (wrapped), nb[0] = n
     bool lo[3], hi[3];   // node on the first / last layer of a wall axis
     bool wall;           // lo or hi on some axis
 };
@@ -244,9 +284,10 @@ struct Site {
 // tiles run x fastest, then (order 1) y, then z, or (order 2) y within a band
 // of `band` tile-rows, then z, then the band: the z-neighbour planes a tile
 // re-reads are then only a band's width of tiles away.
-template <class R>
-__device__ __forceinline__ Site make_site(const DevParams<R> &P) {
-    Site s;
+template <int NQ, class R>
+__device__ __forceinline__ Site<NQ> make_site(const DevParams<R> &P) {
+    using L = LatQ<NQ>;
+    Site<NQ> s;
     const uint32_t b = blockIdx.x;
     uint32_t t = b;
     if (P.order == 0) {
@@ -301,9 +342,9 @@ __device__ __forceinline__ Site make_site(const DevParams<R> &P) {
                            uint32_t(y == P.ny - 1 ? 0 : y + 1) * nx};
     const uint32_t Z[3] = {uint32_t(z == 0 ? P.nz - 1 : z - 1) * nxy, uint32_t(z) * nxy,
                            uint32_t(z == P.nz - 1 ? 0 : z + 1) * nxy};
-    unroll<0, 19>([&](auto J) {
+    unroll<0, NQ>([&](auto J) {
         constexpr int j = decltype(J)::value;
-        s.nb[j] = X[Lat::EX[j] + 1] + Y[Lat::EY[j] + 1] + Z[Lat::EZ[j] + 1];
+        s.nb[j] = X[L::EX[j] + 1] + Y[L::EY[j] + 1] + Z[L::EZ[j] + 1];
     });
     s.n = s.nb[0];
     const int c[3] = {x, y, z};
@@ -320,9 +361,10 @@ __device__ __forceinline__ Site make_site(const DevParams<R> &P) {
 }
 
 // x - s*e^_i lies beyond a wall (s = +1: upstream, s = -1: downstream)
-template <int i, int sgn>
-__device__ __forceinline__ bool beyond_wall(const Site &s) {
-    constexpr int e[3] = {sgn * Lat::EX[i], sgn * Lat::EY[i], sgn * Lat::EZ[i]};
+template <int i, int sgn, int NQ>
+__device__ __forceinline__ bool beyond_wall(const Site<NQ> &s) {
+    using L = LatQ<NQ>;
+    constexpr int e[3] = {sgn * L::EX[i], sgn * L::EY[i], sgn * L::EZ[i]};
     bool b = false;
     if constexpr (e[0] > 0) b = b || s.lo[0];
     if constexpr (e[0] < 0) b = b || s.hi[0];
@@ -349,8 +391,8 @@ __device__ __forceinline__ Src<St> make_src(const CBuf<St> &b, const DevParams<t
     // (f in the low half): one load per tap serves both fields
     const uint32_t plane = P.plane_bytes;
     s.plane = plane;
-    s.f = make_rsrc(b.f, 19u * plane);
-    s.g = St::DEV ? s.f : make_rsrc(b.g, 19u * plane);
+    s.f = make_rsrc(b.f, (uint32_t)St::Q * plane);
+    s.g = St::DEV ? s.f : make_rsrc(b.g, (uint32_t)St::Q * plane);
     s.phis = make_rsrc(b.phis, St::DEV ? (uint32_t)P.N * 4u : 0u);
     return s;
 }
@@ -358,13 +400,13 @@ __device__ __forceinline__ Src<St> make_src(const CBuf<St> &b, const DevParams<t
 // Stored values of population i of f and g at stencil node j (16-bit
 // storage: the decoded deviations).
 template <class St, int i>
-__device__ __forceinline__ void rawfg(const Src<St> &src, const Site &s, int j, typename St::R &f,
-                                      typename St::R &g) {
+__device__ __forceinline__ void rawfg(const Src<St> &src, const Site<St::Q> &s, int j,
+                                      typename St::R &f, typename St::R &g) {
     using T = typename St::T;
     using R = typename St::R;
     if constexpr (St::DEV) {
         const uint32_t w = bload<uint32_t>(src.f, s.nb[j] * 4u, (uint32_t)i * src.plane);
-        if constexpr (std::is_same_v<St, SB16>) {
+        if constexpr (St::BF) {
             f = __uint_as_float(w << 16);
             g = __uint_as_float(w & 0xffff0000u);
         } else {
@@ -412,13 +454,15 @@ __device__ __forceinline__ R lw_wall(const DevParams<R> &P, R am, R a0, R ap, R 
 // Gathers the post-propagation f and g of one node. WALLS adds the
 // wall-aware recomputation (used only by wavefronts that contain a wall node).
 template <Mode M, bool WALLS, class St>
-__device__ __forceinline__ void gather(const Src<St> &src, const Site &s,
+__device__ __forceinline__ void gather(const Src<St> &src, const Site<St::Q> &s,
                                        const DevParams<typename St::R> &P,
-                                       typename St::R (&fb)[19], typename St::R (&gb)[19]) {
+                                       typename St::R (&fb)[St::Q], typename St::R (&gb)[St::Q]) {
     using R = typename St::R;
-    R ph[19];  // phi_s at the stencil nodes x + e^_j (16-bit storage only)
+    using L = LatQ<St::Q>;
+    constexpr int NQ = St::Q;
+    R ph[NQ];  // phi_s at the stencil nodes x + e^_j (16-bit storage only)
     if constexpr (St::DEV) {
-        unroll<0, 19>([&](auto J) {
+        unroll<0, NQ>([&](auto J) {
             constexpr int j = decltype(J)::value;
             if constexpr (M == LOCAL && j > 0) {
                 ph[j] = R(0);
@@ -427,10 +471,10 @@ __device__ __forceinline__ void gather(const Src<St> &src, const Site &s,
             }
         });
     }
-    unroll<0, 19>([&](auto I) {
+    unroll<0, NQ>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        constexpr int o = Lat::OPP[i];
-        constexpr R t = wgt<R>(Lat::cls(i));
+        constexpr int o = L::OPP[i];
+        constexpr R t = wgt<R, NQ>(L::cls(i));
         if constexpr (M == LOCAL || i == 0) {
             R hf, hg;
             rawfg<St, i>(src, s, 0, hf, hg);
@@ -476,10 +520,10 @@ __device__ __forceinline__ void gather(const Src<St> &src, const Site &s,
         // recomputed, on the lanes where they do, in flux form with
         // bounce-back from the full values of the taps and of the opposite
         // population at the node (the wall-free values above stand elsewhere)
-        unroll<1, 19>([&](auto I) {
+        unroll<1, NQ>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            constexpr int o = Lat::OPP[i];
-            constexpr R t = wgt<R>(Lat::cls(i));
+            constexpr int o = L::OPP[i];
+            constexpr R t = wgt<R, NQ>(L::cls(i));
             const bool up = beyond_wall<i, 1>(s), dn = beyond_wall<i, -1>(s);
             if (up || dn) {
                 auto full_f = [&](R h) -> R {
@@ -533,13 +577,13 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 // FD: grad(phi) is given (the finite-difference variant) instead of recovered
 // from K1: n = grad/|grad| (0 where |grad| <= k1_eps, as for K1), S = s n,
 // |grad phi| = |grad|.
-template <bool FD = false, class R>
-__device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)[19],
-                                            const R (&gb)[19], const R *gfd = nullptr) {
+template <bool FD = false, class R, int NQ>
+__device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)[NQ],
+                                            const R (&gb)[NQ], const R *gfd = nullptr) {
     Macro<R> m;
     R phi = gb[0], sf = fb[0];
 #pragma unroll
-    for (int i = 1; i < 19; ++i) {
+    for (int i = 1; i < NQ; ++i) {
         phi += gb[i];
         sf += fb[i];
     }
@@ -604,7 +648,7 @@ struct NodeCoef {
     R tS[3];          // tau_phi c S
     R a3;             // u^2/(2 cs2)
     R ug, uG;         // u.grad(rho), u.(rho G)
-    R A0[3];          // p/cs2 - Pi_s:(e e - cs2 I)/(2cs4) minus the (e.n)^2 part, per speed class
+    R A0[4];          // p/cs2 - Pi_s:(e e - cs2 I)/(2cs4) minus the (e.n)^2 part, per speed class
     R kpsi;           // sigma |grad phi| c^2/(2 cs4): coefficient of (e^.n)^2
 };
 
@@ -633,14 +677,9 @@ __device__ __forceinline__ NodeCoef<R> node_coef(const DevParams<R> &P, const Ma
     q.A0[0] = base;
     q.A0[1] = base - q.kpsi;
     q.A0[2] = base - R(2) * q.kpsi;
+    q.A0[3] = base - R(3) * q.kpsi;   // corner vectors (D3Q27)
     return q;
 }
-
-template <class R>
-struct Collided {
-    R f[19];
-    R g[19];
-};
 
 // f* = f - omega_f (f - feq + F/2) + F ;  g* = g - omega_g (g - geq)   (Eqs. 10, 16)
 // evaluated as the population plus its increment, f + [omega_f (feq - f) +
@@ -648,14 +687,15 @@ struct Collided {
 // floating point: the over-relaxed form (1 - omega) f + omega feq rounds the
 // same way at every node of a uniform region and makes the phase mass drift
 // coherently (about 3e-4 over 1e4 FP32 steps).
-template <class R>
+template <class R, int NQ>
 __device__ __forceinline__ void collide(const DevParams<R> &P, const Macro<R> &m,
-                                        const NodeCoef<R> &q, R (&fb)[19], R (&gb)[19]) {
+                                        const NodeCoef<R> &q, R (&fb)[NQ], R (&gb)[NQ]) {
+    using L = LatQ<NQ>;
     const R of = m.omega_f, cf = R(1) - R(0.5) * of;
     const R og = P.omega_g;
     auto update = [&](auto I, R A, R B, R Gq) {
         constexpr int i = decltype(I)::value;
-        constexpr R t = wgt<R>(Lat::cls(i));
+        constexpr R t = wgt<R, NQ>(L::cls(i));
         fb[i] = fma(of, fma(t, A, -fb[i]), fma(t * cf, B, fb[i]));
         gb[i] = fma(og, fma(t, Gq, -gb[i]), gb[i]);
     };
@@ -668,14 +708,14 @@ __device__ __forceinline__ void collide(const DevParams<R> &P, const Macro<R> &m
     // changes sign across a pair, so poly splits into an even part E and an
     // odd part O and the pair shares one evaluation of each projection
     const R uGs = q.uG * P.inv_cs2;
-    unroll<0, 9>([&](auto K) {
+    unroll<0, (NQ - 1) / 2>([&](auto K) {
         constexpr int i = 2 * decltype(K)::value + 1;
-        constexpr int cl = Lat::cls(i);
-        const R eu = edot<i>(q.cu);
-        const R en = edot<i>(m.n);
-        const R eg = edot<i>(q.cgr);
-        const R eG = edot<i>(q.crG);
-        const R es = edot<i>(q.tS);
+        constexpr int cl = L::cls(i);
+        const R eu = edot<i, NQ>(q.cu);
+        const R en = edot<i, NQ>(m.n);
+        const R eg = edot<i, NQ>(q.cgr);
+        const R eG = edot<i, NQ>(q.crG);
+        const R es = edot<i, NQ>(q.tS);
         const R E = fma(eu * eu, P.half_inv_cs4, -q.a3);
         const R O = eu * P.inv_cs2;
         const R pp = E + O, pm = E - O;
@@ -702,8 +742,8 @@ __device__ __forceinline__ Dst<St> make_dst(const Buf<St> &b, const DevParams<ty
     Dst<St> d;
     const uint32_t plane = P.plane_bytes;
     d.plane = plane;
-    d.f = make_rsrc(b.f, 19u * plane);
-    d.g = St::DEV ? d.f : make_rsrc(b.g, 19u * plane);
+    d.f = make_rsrc(b.f, (uint32_t)St::Q * plane);
+    d.g = St::DEV ? d.f : make_rsrc(b.g, (uint32_t)St::Q * plane);
     d.phis = make_rsrc(b.phis, St::DEV ? (uint32_t)P.N * 4u : 0u);
     return d;
 }
@@ -711,13 +751,15 @@ __device__ __forceinline__ Dst<St> make_dst(const Buf<St> &b, const DevParams<ty
 template <class St>
 __device__ __forceinline__ void store(const Dst<St> &dst, uint32_t n,
                                       const DevParams<typename St::R> &P,
-                                      const typename St::R (&fs)[19],
-                                      const typename St::R (&gs)[19]) {
+                                      const typename St::R (&fs)[St::Q],
+                                      const typename St::R (&gs)[St::Q]) {
     using R = typename St::R;
     using T = typename St::T;
+    using L = LatQ<St::Q>;
+    constexpr int NQ = St::Q;
     const uint32_t voff = n * (uint32_t)(St::DEV ? 4 : sizeof(T));
     if constexpr (!St::DEV) {
-        unroll<0, 19>([&](auto I) {
+        unroll<0, NQ>([&](auto I) {
             constexpr int i = decltype(I)::value;
             bstore<T>(T(fs[i]), dst.f, voff, (uint32_t)i * dst.plane);
             bstore<T>(T(gs[i]), dst.g, voff, (uint32_t)i * dst.plane);
@@ -725,11 +767,11 @@ __device__ __forceinline__ void store(const Dst<St> &dst, uint32_t n,
     } else {
         R phi_a = gs[0];
 #pragma unroll
-        for (int i = 1; i < 19; ++i) phi_a += gs[i];
+        for (int i = 1; i < NQ; ++i) phi_a += gs[i];
         R resid = R(0);
-        unroll<0, 19>([&](auto I) {
+        unroll<0, NQ>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            constexpr R t = wgt<R>(Lat::cls(i));
+            constexpr R t = wgt<R, NQ>(L::cls(i));
             const T hf = encode<St>(P.scale_f * (fs[i] - t * P.rho0));
             const R dg = fma(-t, phi_a, gs[i]);
             const T hg = encode<St>(P.scale_g * dg);
@@ -808,16 +850,16 @@ __device__ __forceinline__ R mass_weight(R phi) {
 // no wall and the wall-aware one over the wall slabs: the wall path's code
 // and registers then cost nothing in the interior.
 // The pending phase-mass correction: g_i += t_i c w(phi) before the moments.
-template <class R>
-__device__ __forceinline__ void apply_massfix(const MassFix &mf, R (&gb)[19]) {
+template <class R, int NQ>
+__device__ __forceinline__ void apply_massfix(const MassFix &mf, R (&gb)[NQ]) {
     if (mf.mode & 2) {
         R phi = gb[0];
 #pragma unroll
-        for (int i = 1; i < 19; ++i) phi += gb[i];
+        for (int i = 1; i < NQ; ++i) phi += gb[i];
         const R cw = R(*mf.coef) * mass_weight(phi);
-        unroll<0, 19>([&](auto I) {
+        unroll<0, NQ>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            gb[i] = fma(wgt<R>(Lat::cls(i)), cw, gb[i]);
+            gb[i] = fma(wgt<R, NQ>(LatQ<NQ>::cls(i)), cw, gb[i]);
         });
     }
 }
@@ -826,23 +868,24 @@ __device__ __forceinline__ void apply_massfix(const MassFix &mf, R (&gb)[19]) {
 // grad = 3 sum_i t_i e^_i [phi(x + e^_i) - phi(x - e^_i)]/2, summed over
 // opposite pairs; a neighbour beyond a wall takes the node's own value (the
 // finite-difference scheme the paper compares with, Sec. 3.4).
-template <bool WALLS, class R>
-__device__ __forceinline__ void fd_grad(const DevParams<R> &P, const Site &s, R (&g)[3]) {
+template <bool WALLS, class R, int NQ>
+__device__ __forceinline__ void fd_grad(const DevParams<R> &P, const Site<NQ> &s, R (&g)[3]) {
+    using L = LatQ<NQ>;
     const R *phi = P.phi_fd;
     const R p0 = phi[s.n];
     g[0] = g[1] = g[2] = R(0);
-    unroll<0, 9>([&](auto K) {
+    unroll<0, (NQ - 1) / 2>([&](auto K) {
         constexpr int i = 2 * decltype(K)::value + 1;
-        constexpr int o = Lat::OPP[i];
+        constexpr int o = L::OPP[i];
         R pp = phi[s.nb[i]], pm = phi[s.nb[o]];
         if constexpr (WALLS) {
             if (beyond_wall<i, -1>(s)) pp = p0;
             if (beyond_wall<i, 1>(s)) pm = p0;
         }
-        const R d = R(3) * wgt<R>(Lat::cls(i)) * (pp - pm);
-        if constexpr (Lat::EX[i] != 0) g[0] += R(Lat::EX[i]) * d;
-        if constexpr (Lat::EY[i] != 0) g[1] += R(Lat::EY[i]) * d;
-        if constexpr (Lat::EZ[i] != 0) g[2] += R(Lat::EZ[i]) * d;
+        const R d = R(3) * wgt<R, NQ>(L::cls(i)) * (pp - pm);
+        if constexpr (L::EX[i] != 0) g[0] += R(L::EX[i]) * d;
+        if constexpr (L::EY[i] != 0) g[1] += R(L::EY[i]) * d;
+        if constexpr (L::EZ[i] != 0) g[2] += R(L::EZ[i]) * d;
     });
 }
 
@@ -850,11 +893,11 @@ template <class St, Mode M, bool WALLS, bool FD>
 __device__ __forceinline__ void step_body(const CBuf<St> &src, const Buf<St> &dst,
                                           const DevParams<typename St::R> &P, const MassFix &mf) {
     using R = typename St::R;
-    const Site s = make_site(P);
+    const Site<St::Q> s = make_site<St::Q>(P);
     double rep_phi = 0.0, rep_w = 0.0;
     if (s.valid) {
         const Src<St> in = make_src(src, P);
-        R fb[19], gb[19];
+        R fb[St::Q], gb[St::Q];
         gather<M, WALLS, St>(in, s, P, fb, gb);
         apply_massfix(mf, gb);
         R gfd[3];
@@ -894,15 +937,15 @@ template <class St, Mode M, bool WALLS>
 __global__ void __launch_bounds__(BLOCK) phi_kernel(CBuf<St> src, DevParams<typename St::R> P,
                                                     MassFix mf) {
     using R = typename St::R;
-    const Site s = make_site(P);
+    const Site<St::Q> s = make_site<St::Q>(P);
     if (!s.valid) return;
     const Src<St> in = make_src(src, P);
-    R fb[19], gb[19];
+    R fb[St::Q], gb[St::Q];
     gather<M, WALLS, St>(in, s, P, fb, gb);
     apply_massfix(mf, gb);
     R phi = gb[0];
 #pragma unroll
-    for (int i = 1; i < 19; ++i) phi += gb[i];
+    for (int i = 1; i < St::Q; ++i) phi += gb[i];
     P.phi_fd[s.n] = phi;
 }
 
@@ -961,7 +1004,7 @@ template <class St, Mode M, bool WALLS, bool FD>
 __global__ void __launch_bounds__(BLOCK) moments_kernel(CBuf<St> src, DevParams<typename St::R> P,
                                                         FieldOut out) {
     using R = typename St::R;
-    const Site s = make_site(P);
+    const Site<St::Q> s = make_site<St::Q>(P);
     double acc[NSUM];
 #pragma unroll
     for (int k = 0; k < NSUM; ++k) acc[k] = 0.0;
@@ -969,7 +1012,7 @@ __global__ void __launch_bounds__(BLOCK) moments_kernel(CBuf<St> src, DevParams<
     acc[8] = -1e300;
     if (s.valid) {
         const Src<St> in = make_src(src, P);
-        R fb[19], gb[19];
+        R fb[St::Q], gb[St::Q];
         gather<M, WALLS, St>(in, s, P, fb, gb);
         R gfd[3];
         if constexpr (FD) fd_grad<WALLS>(P, s, gfd);
@@ -991,7 +1034,7 @@ __global__ void __launch_bounds__(BLOCK) moments_kernel(CBuf<St> src, DevParams<
         }
         if (out.pdf_f) {
 #pragma unroll
-            for (int i = 0; i < 19; ++i) {
+            for (int i = 0; i < St::Q; ++i) {
                 out.pdf_f[i * N + n] = fb[i];
                 out.pdf_g[i * N + n] = gb[i];
             }
@@ -1090,17 +1133,19 @@ template <class St, bool WALLS>
 __device__ __forceinline__ void init_node(const double *phi0, const double *u0, const double *p0,
                                           const DevParams<double> &P,
                                           const DevParams<typename St::R> &PR, const Buf<St> &dst,
-                                          int *bad, const Site &s) {
+                                          int *bad, const Site<St::Q> &s) {
     using R = typename St::R;
+    using L = LatQ<St::Q>;
+    constexpr int NQ = St::Q;
     const size_t N = (size_t)P.N, n = s.n;
     const double ph0 = phi0[n];
     double g[3] = {0.0, 0.0, 0.0};
-    unroll<1, 19>([&](auto I) {
+    unroll<1, NQ>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        constexpr int ex = Lat::EX[i], ey = Lat::EY[i], ez = Lat::EZ[i];
-        constexpr double t = wgt<double>(Lat::cls(i));
+        constexpr int ex = L::EX[i], ey = L::EY[i], ez = L::EZ[i];
+        constexpr double t = wgt<double, NQ>(L::cls(i));
         double vp = phi0[s.nb[i]];
-        double vm = phi0[s.nb[Lat::OPP[i]]];
+        double vm = phi0[s.nb[L::OPP[i]]];
         if constexpr (WALLS) {
             if (beyond_wall<i, -1>(s)) vp = ph0;
             if (beyond_wall<i, 1>(s)) vm = ph0;
@@ -1134,11 +1179,11 @@ __device__ __forceinline__ void init_node(const double *phi0, const double *u0, 
         atomicOr(bad, 1);
 
     const NodeCoef<double> q = node_coef(P, m);
-    R fo[19], go[19];
-    unroll<0, 19>([&](auto I) {
+    R fo[NQ], go[NQ];
+    unroll<0, NQ>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        constexpr int cl = Lat::cls(i);
-        constexpr double t = wgt<double>(cl);
+        constexpr int cl = L::cls(i);
+        constexpr double t = wgt<double, NQ>(cl);
         double poly, A, B, Gq, eg0;
         if constexpr (i == 0) {
             poly = -q.a3;
@@ -1147,16 +1192,16 @@ __device__ __forceinline__ void init_node(const double *phi0, const double *u0, 
             Gq = fma(m.phi, poly, m.phi);
             eg0 = 0.0;
         } else {
-            const double eu = edot<i>(q.cu);
-            const double en = edot<i>(m.n);
-            const double eg = edot<i>(q.cgr);
-            const double eG = edot<i>(q.crG);
-            const double es = edot<i>(q.tS);
+            const double eu = edot<i, NQ>(q.cu);
+            const double en = edot<i, NQ>(m.n);
+            const double eg = edot<i, NQ>(q.cgr);
+            const double eG = edot<i, NQ>(q.crG);
+            const double es = edot<i, NQ>(q.tS);
             poly = fma(eu, fma(eu, P.half_inv_cs4, P.inv_cs2), -q.a3);
             A = fma(m.rho, poly, fma(q.kpsi * en, en, q.A0[cl]));
             B = fma(poly, eg - q.ug, fma(eG - q.uG, P.inv_cs2, 2.0 * P.half_inv_cs4 * eu * eG));
             Gq = fma(m.phi, poly, m.phi + es);
-            eg0 = P.c * edot<i>(g);
+            eg0 = P.c * edot<i, NQ>(g);
         }
         fo[i] = R(t * (A - 0.5 * B));
         go[i] = R(t * (Gq - (1.0 / P.omega_g) * eg0));
@@ -1169,7 +1214,7 @@ __global__ void __launch_bounds__(BLOCK) init_kernel(const double *phi0, const d
                                                      const double *p0, DevParams<double> P,
                                                      DevParams<typename St::R> PR, Buf<St> dst,
                                                      int *bad, double *partials) {
-    const Site s = make_site(P);
+    const Site<St::Q> s = make_site<St::Q>(P);
     if (s.valid) init_node<St, WALLS>(phi0, u0, p0, P, PR, dst, bad, s);
     block_sum2(s.valid ? phi0[s.n] : 0.0, 0.0, partials + 2 * (size_t)linear_block());
 }
@@ -1180,12 +1225,12 @@ template <class St>
 __global__ void __launch_bounds__(BLOCK) load_kernel(const double *f, const double *g,
                                                      DevParams<typename St::R> P, Buf<St> dst) {
     using R = typename St::R;
-    const Site s = make_site(P);
+    const Site<St::Q> s = make_site<St::Q>(P);
     if (!s.valid) return;
     const size_t N = (size_t)P.N, n = s.n;
-    R fo[19], go[19];
+    R fo[St::Q], go[St::Q];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
+    for (int i = 0; i < St::Q; ++i) {
         fo[i] = R(f[i * N + n]);
         go[i] = R(g[i * N + n]);
     }

@@ -24,6 +24,8 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 # algorithmic HBM bytes per lattice update of the fused step (2 x 19 values
 # read once and written once, plus phi_s for 16-bit storage)
 BYTES_PER_LU = {"fp64": 608, "fp32": 304, "fp16": 160, "bf16": 160}
+# the same on D3Q27 (2 x 27 values)
+BYTES_PER_LU_Q27 = {"fp64": 864, "fp32": 432, "fp16": 224, "bf16": 224}
 
 
 class LbmParams(C.Structure):
@@ -40,7 +42,8 @@ class LbmParams(C.Structure):
                 ("tau_phi", C.c_double), ("sigma", C.c_double), ("delta", C.c_double),
                 ("G", C.c_double * 3),
                 ("k1_eps", C.c_double),
-                ("p_ref", C.c_double)]
+                ("p_ref", C.c_double),
+                ("lattice", C.c_int32)]
 
 
 class LbmDiag(C.Structure):
@@ -72,6 +75,8 @@ def load_library(path: str | None = None):
     vp, dp = C.c_void_p, C.POINTER(C.c_double)
     lib.lbm_lattice.argtypes = [C.POINTER(C.c_int32), dp]
     lib.lbm_lattice.restype = None
+    lib.lbm_lattice_q.argtypes = [C.c_int32, C.POINTER(C.c_int32), dp]
+    lib.lbm_lattice_q.restype = C.c_int
     lib.lbm_workspace_bytes.argtypes = [C.POINTER(LbmParams), C.POINTER(C.c_size_t)]
     lib.lbm_init.argtypes = [C.POINTER(LbmParams), vp, C.c_size_t, vp, vp, vp, vp,
                              C.POINTER(vp)]
@@ -107,10 +112,10 @@ def _check(rc: int, where: str):
 def make_params(nx, ny, nz, precision="fp32", wall=(0, 0, 0), courant=0.997, rho1=1.0,
                 rho2=1.0, tau_rho1=0.3, tau_rho2=0.3, tau_phi=0.3, sigma=0.0, delta=4.0,
                 G=(0.0, 0.0, 0.0), k1_eps=1e-5, p_ref=0.0, store_log2=(10, 10),
-                check_every=0, mass_fix_every=None, normal_fd=0) -> LbmParams:
+                check_every=0, mass_fix_every=None, normal_fd=0, lattice=19) -> LbmParams:
     """mass_fix_every: None picks 10 for FP32 and 16-bit storage (FP32 rounding
     alone drifts the phase mass by ~1e-8 of it per step on a quasi-steady
-    interface), 0 for FP64."""
+    interface), 0 for FP64. lattice: 19 (D3Q19) or 27 (D3Q27)."""
     p = LbmParams()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -128,6 +133,7 @@ def make_params(nx, ny, nz, precision="fp32", wall=(0, 0, 0), courant=0.997, rho
     p.tau_rho1, p.tau_rho2 = float(tau_rho1), float(tau_rho2)
     p.tau_phi, p.sigma, p.delta = float(tau_phi), float(sigma), float(delta)
     p.k1_eps, p.p_ref = float(k1_eps), float(p_ref)
+    p.lattice = int(lattice)
     return p
 
 
@@ -139,6 +145,14 @@ def lbm_lattice():
     t = (C.c_double * 19)()
     lib.lbm_lattice(e, t)
     return np.array(list(e), dtype=np.int64).reshape(19, 3), np.array(list(t))
+
+
+def lbm_lattice_q(q: int = 19):
+    lib = load_library()
+    e = (C.c_int32 * (3 * max(int(q), 1)))()
+    t = (C.c_double * max(int(q), 1))()
+    _check(lib.lbm_lattice_q(int(q), e, t), "lbm_lattice_q")
+    return np.array(list(e), dtype=np.int64).reshape(q, 3), np.array(list(t))
 
 
 def lbm_workspace_bytes(params: LbmParams) -> int:
@@ -214,6 +228,7 @@ class Solver:
         self.device = torch.device(device)
         self.params = make_params(**params)
         self.shape = (self.params.nz, self.params.ny, self.params.nx)
+        self.Q = 27 if self.params.lattice == 27 else 19
         self.N = self.params.nx * self.params.ny * self.params.nz
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -263,15 +278,15 @@ class Solver:
 
     def get_pdfs(self):
         torch = self.torch
-        f = torch.empty((19,) + self.shape, dtype=torch.float64, device=self.device)
-        g = torch.empty((19,) + self.shape, dtype=torch.float64, device=self.device)
+        f = torch.empty((self.Q,) + self.shape, dtype=torch.float64, device=self.device)
+        g = torch.empty((self.Q,) + self.shape, dtype=torch.float64, device=self.device)
         lbm_get_pdfs(self.ctx, f, g)
         return f, g
 
     def set_pdfs(self, f, g):
         torch = self.torch
         cv = lambda a: torch.as_tensor(np.asarray(a) if not isinstance(a, torch.Tensor) else a,
-                                       dtype=torch.float64).to(self.device).reshape((19,) + self.shape).contiguous()
+                                       dtype=torch.float64).to(self.device).reshape((self.Q,) + self.shape).contiguous()
         fd, gd = cv(f), cv(g)
         lbm_set_pdfs(self.ctx, fd, gd)
         self.stream.synchronize()

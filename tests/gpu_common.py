@@ -13,12 +13,12 @@ def say(msg: str):
     sys.stdout.flush()
 
 
-def order_maps():
-    """perm such that gpu[i] = oracle[perm[i]]."""
-    eg, _ = lbm.lbm_lattice()
-    eo, _ = oracle.lattice()
-    perm = [next(k for k in range(19) if tuple(eo[k]) == tuple(eg[i])) for i in range(19)]
-    inv = [perm.index(k) for k in range(19)]
+def order_maps(q=19):
+    """perm such that gpu[i] = oracle[perm[i]] (lattice q = 19 or 27)."""
+    eg, _ = lbm.lbm_lattice_q(q)
+    eo, _ = oracle.lattice(q)
+    perm = [next(k for k in range(q) if tuple(eo[k]) == tuple(eg[i])) for i in range(q)]
+    inv = [perm.index(k) for k in range(q)]
     return np.array(perm), np.array(inv)
 
 

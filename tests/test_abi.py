@@ -42,6 +42,25 @@ def test_lattice_is_d3q19(lib, orc):
     assert e[0].tolist() == [0, 0, 0]
 
 
+def test_lattice_q27_matches_oracle(lib, orc):
+    """lbm_lattice_q(27): the oracle's D3Q27 vectors and weights, the D3Q19
+    order as its first 19 entries, opposite directions adjacent (i, i + 1
+    for odd i, which the collision's pair evaluation relies on)."""
+    e, t = lib.lbm_lattice_q(27)
+    eo, to = orc.lattice(27)
+    assert sorted(map(tuple, e)) == sorted(map(tuple, eo))
+    for i in range(27):
+        j = [k for k in range(27) if tuple(eo[k]) == tuple(e[i])][0]
+        assert t[i] == to[j]
+    e19, _ = lib.lbm_lattice()
+    assert np.array_equal(e[:19], e19)
+    for i in range(1, 27, 2):
+        assert np.array_equal(e[i], -e[i + 1])
+    assert np.array_equal(lib.lbm_lattice_q(19)[0], e19)
+    with pytest.raises(lib.LbmError):
+        lib.lbm_lattice_q(15)
+
+
 def test_workspace_bytes_and_validation(lib):
     p = lib.make_params(32, 32, 32, precision="fp32")
     n32 = lib.lbm_workspace_bytes(p)
@@ -62,6 +81,17 @@ def test_workspace_bytes_and_validation(lib):
         lib.lbm_workspace_bytes(lib.make_params(8, 1, 8, wall=(0, 1, 0)))
     with pytest.raises(lib.LbmError):
         lib.lbm_workspace_bytes(lib.make_params(1024, 1024, 128))  # 19 N >= 2^31
+    # D3Q27: 27 planes per field; the comparison FD scheme is D3Q19 only
+    n27 = lib.lbm_workspace_bytes(lib.make_params(32, 32, 32, precision="fp32", lattice=27))
+    assert n27 >= 2 * 2 * 27 * N * 4 and n27 > n32
+    for kw in (dict(lattice=23), dict(lattice=27, normal_fd=1)):
+        with pytest.raises(lib.LbmError) as ei:
+            lib.lbm_workspace_bytes(lib.make_params(8, 8, 8, **kw))
+        assert ei.value.status == lib.LBM_EINVAL
+    # 19 planes of 512 x 512 x 160 FP32 fit one 32-bit buffer range, 27 do not
+    lib.lbm_workspace_bytes(lib.make_params(512, 512, 160))
+    with pytest.raises(lib.LbmError):
+        lib.lbm_workspace_bytes(lib.make_params(512, 512, 160, lattice=27))
 
 
 def test_strerror(lib):
