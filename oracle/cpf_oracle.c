@@ -41,6 +41,14 @@
  *   - planar no-slip walls halfway between nodes: flux-form Lax-Wendroff
  *     with the solid-side neighbour replaced by the node itself and the
  *     outgoing flux returned into the opposite population.
+ *   - wetting walls (the paper has neutral walls only): on the first node
+ *     layer next to a wall, the normal recovered from K1 is turned, keeping
+ *     its direction along the wall, until n . n_w = -cos(theta) (n_w the
+ *     inward wall normal); S and grad(phi) of Eq. 19 then use that normal.
+ *     Since the wall passes no phase flux, the wall-normal part of
+ *     M (grad phi - s n) vanishes there at grad(phi) . n_w = -s cos(theta),
+ *     the contact-angle condition of the equilibrium profile. Nodes whose
+ *     normal has no component along the wall (|n_t| <= 1e-6) keep it.
  */
 #include "cpf_oracle.h"
 
@@ -137,15 +145,53 @@ static double tau_rho_of(const orc_params *P, double phi, double rho)
     return eta / (rho * cs2);
 }
 
+/* Inward unit normal of the walls node n touches (the first layer next to a
+ * wall face; at an edge or corner the normalised sum of its faces'), or NULL
+ * when wetting is off or the node touches no wall. */
+static const double *wall_normal(const orc_params *P, long n, double nw[3])
+{
+    if (!P->wetting) return NULL;
+    const int nn[3] = {P->nx, P->ny, P->nz};
+    const long c[3] = {n % P->nx, (n / P->nx) % P->ny, n / ((long)P->nx * P->ny)};
+    double len2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        nw[a] = 0.0;
+        if (P->wall[a] && c[a] == 0) nw[a] += 1.0;
+        if (P->wall[a] && c[a] == nn[a] - 1) nw[a] -= 1.0;
+        len2 += nw[a] * nw[a];
+    }
+    if (len2 == 0.0) return NULL;
+    for (int a = 0; a < 3; ++a) nw[a] /= sqrt(len2);
+    return nw;
+}
+
+/* Turns a unit normal n so that n . n_w = -cos(theta), keeping its part along
+ * the wall (the wetting reading in the header); n = 0 stays 0. */
+static void wet_normal(const orc_params *P, const double nw[3], double n[3])
+{
+    const double dn = n[0] * nw[0] + n[1] * nw[1] + n[2] * nw[2];
+    double t[3], tt = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        t[a] = n[a] - dn * nw[a];
+        tt += t[a] * t[a];
+    }
+    tt = sqrt(tt);
+    if (tt <= 1e-6) return;
+    const double ct = P->cos_theta, st = sqrt(1.0 - ct * ct);
+    for (int a = 0; a < 3; ++a) n[a] = -ct * nw[a] + st * t[a] / tt;
+}
+
 /* Normal, S and grad(phi) from the central moment K1 (Sec. 2.3, Eqs. 15,
- * 18, 19). */
-static void gradient_from_K1(const orc_params *P, double phi, const double K1[3], macro_t *m)
+ * 18, 19); nw: inward wall normal of a wetting wall node, or NULL. */
+static void gradient_from_K1(const orc_params *P, double phi, const double K1[3],
+                             const double *nw, macro_t *m)
 {
     const double cs2 = cs2_of(P);
     const double k = sqrt(K1[0] * K1[0] + K1[1] * K1[1] + K1[2] * K1[2]);
     /* Eq. 18; the direction of a vanishing K1 is undefined, so n = 0 where
      * |K1| <= k1_eps (reading of the degenerate case, see header) */
     for (int a = 0; a < 3; ++a) m->n[a] = (k > P->k1_eps) ? -K1[a] / k : 0.0;
+    if (nw && k > P->k1_eps) wet_normal(P, nw, m->n);
     const double s = 4.0 * phi * (1.0 - phi) / P->delta;
     for (int a = 0; a < 3; ++a) m->S[a] = s * m->n[a];                       /* Eq. 15 */
     for (int a = 0; a < 3; ++a)                                              /* Eq. 19 */
@@ -170,9 +216,10 @@ static void gradient_given(const orc_params *P, double phi, const double gp[3], 
 }
 
 /* Macroscopic recovery at one node from its post-propagation PDFs. With
- * gradphi_fd != NULL the gradient is that one (comparison scheme). */
+ * gradphi_fd != NULL the gradient is that one (comparison scheme); nw: the
+ * inward normal of a wetting wall the node touches, or NULL. */
 static void node_macro(const orc_params *P, const double fb[Q], const double g[Q],
-                       const double *gradphi_fd, macro_t *m)
+                       const double *gradphi_fd, const double *nw, macro_t *m)
 {
     const double c = P->courant, cs2 = cs2_of(P);
     double phi = 0.0;
@@ -193,7 +240,7 @@ static void node_macro(const orc_params *P, const double fb[Q], const double g[Q
         double K1[3] = {0.0, 0.0, 0.0};                              /* Eq. 17 */
         for (int i = 0; i < Q; ++i)
             for (int a = 0; a < 3; ++a) K1[a] += g[i] * (c * EH[i][a] - m->u[a]);
-        gradient_from_K1(P, phi, K1, m);
+        gradient_from_K1(P, phi, K1, nw, m);
     }
     for (int a = 0; a < 3; ++a) m->gradrho[a] = (P->rho1 - P->rho2) * m->gradphi[a];
 
@@ -248,10 +295,10 @@ static void node_equilibria(const orc_params *P, const macro_t *m, double feq[Q]
 /* Crank-Nicolson collision of one node (Sec. 2.2 Eq. 10 with
  * f-bar_eq = f_eq - F/2; Sec. 2.3 Eq. 16). */
 static void node_collide(const orc_params *P, const double fb[Q], const double g[Q],
-                         const double *gradphi_fd, double fs[Q], double gs[Q])
+                         const double *gradphi_fd, const double *nw, double fs[Q], double gs[Q])
 {
     macro_t m;
-    node_macro(P, fb, g, gradphi_fd, &m);
+    node_macro(P, fb, g, gradphi_fd, nw, &m);
     double feq[Q], geq[Q], Sf[Q], Rf[Q];
     node_equilibria(P, &m, feq, geq, Sf, Rf);
     for (int i = 0; i < Q; ++i) {
@@ -373,10 +420,10 @@ void orc_step(orc_state *S, long nsteps)
         if (P->normal_fd) phase_field(S);
 #pragma omp parallel for schedule(static)
         for (long n = 0; n < N; ++n) {
-            double fb[Q], g[Q], fs[Q], gs[Q], gbuf[3];
+            double fb[Q], g[Q], fs[Q], gs[Q], gbuf[3], wbuf[3];
             gather(S->fb, N, n, fb);
             gather(S->g, N, n, g);
-            node_collide(P, fb, g, fd_at(S, n, gbuf), fs, gs);
+            node_collide(P, fb, g, fd_at(S, n, gbuf), wall_normal(P, n, wbuf), fs, gs);
             for (int i = 0; i < Q; ++i) {
                 S->fs[(long)i * N + n] = fs[i];
                 S->gs[(long)i * N + n] = gs[i];
@@ -403,6 +450,8 @@ int orc_create(const orc_params *Pin, const double *phi0, const double *u0,
     const int nn[3] = {P->nx, P->ny, P->nz};
     for (int a = 0; a < 3; ++a)
         if (P->wall[a] && nn[a] < 2) return -1;
+    if (P->wetting != 0 && P->wetting != 1) return -1;
+    if (P->wetting && !(P->cos_theta >= -1.0 && P->cos_theta <= 1.0)) return -1;
     const long N = (long)P->nx * P->ny * P->nz;
     for (long n = 0; n < N; ++n) {
         if (!isfinite(phi0[n])) return -1;
@@ -487,11 +536,11 @@ void orc_fields(const orc_state *Sc, double *phi, double *u, double *p)
     const long N = S->N;
     if (S->P.normal_fd) phase_field(S);
     for (long n = 0; n < N; ++n) {
-        double fb[Q], g[Q], gbuf[3];
+        double fb[Q], g[Q], gbuf[3], wbuf[3];
         gather(S->fb, N, n, fb);
         gather(S->g, N, n, g);
         macro_t m;
-        node_macro(&S->P, fb, g, fd_at(S, n, gbuf), &m);
+        node_macro(&S->P, fb, g, fd_at(S, n, gbuf), wall_normal(&S->P, n, wbuf), &m);
         if (phi) phi[n] = m.phi;
         if (u) for (int a = 0; a < 3; ++a) u[(long)a * N + n] = m.u[a];
         if (p) p[n] = m.p;
@@ -515,11 +564,11 @@ void orc_diag(const orc_state *Sc, const double *phi_ref, double out[ORC_NDIAG])
         for (int y = 0; y < P->ny; ++y)
             for (int x = 0; x < P->nx; ++x) {
                 const long n = node_index(P, x, y, z);
-                double fb[Q], g[Q], gbuf[3];
+                double fb[Q], g[Q], gbuf[3], wbuf[3];
                 gather(S->fb, N, n, fb);
                 gather(S->g, N, n, g);
                 macro_t m;
-                node_macro(P, fb, g, fd_at(S, n, gbuf), &m);
+                node_macro(P, fb, g, fd_at(S, n, gbuf), wall_normal(P, n, wbuf), &m);
                 const double uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
                 out[ORC_D_SUM_PHI] += m.phi;
                 out[ORC_D_MASS] += m.rho * m.phi;
@@ -568,7 +617,7 @@ void orc_node_macro(const orc_params *P, const double fb[ORC_Q], const double g[
 {
     lattice_build();
     macro_t m;
-    node_macro(P, fb, g, NULL, &m);
+    node_macro(P, fb, g, NULL, NULL, &m);
     out[0] = m.phi; out[1] = m.rho; out[2] = m.tau_rho;
     out[3] = m.u[0]; out[4] = m.u[1]; out[5] = m.u[2];
     out[6] = m.p;

@@ -45,6 +45,8 @@ typedef struct {
     int normal_fd;      /* 0: normal and grad(phi) from K1 (the paper's scheme)  */
                         /* 1: isotropic central differences of phi (comparison)  */
     double k1_eps;      /* n = 0 where |K1| <= k1_eps (0: only where K1 = 0)     */
+    int wetting;        /* 0: neutral walls; 1: contact angle theta at the walls  */
+    double cos_theta;   /* cos(theta), theta measured through the phi = 1 phase   */
 } orc_params;
 
 /* diagnostics of the state at the current time, see orc_diag */

@@ -54,7 +54,9 @@ class _Params(C.Structure):
                 ("tau_phi", C.c_double), ("sigma", C.c_double), ("delta", C.c_double),
                 ("G", C.c_double * 3),
                 ("normal_fd", C.c_int),
-                ("k1_eps", C.c_double)]
+                ("k1_eps", C.c_double),
+                ("wetting", C.c_int),
+                ("cos_theta", C.c_double)]
 
 
 @dataclass
@@ -75,6 +77,8 @@ class OracleParams:
     normal_fd: int = 0
     k1_eps: float = 1e-5
     lattice: int = 19        # 19 (D3Q19) or 27 (D3Q27): which build runs
+    wetting: int = 0         # 1: contact angle at the walls (see cpf_oracle.c)
+    cos_theta: float = 0.0
 
     def to_c(self) -> _Params:
         p = _Params()
@@ -88,6 +92,8 @@ class OracleParams:
         p.tau_phi, p.sigma, p.delta = float(self.tau_phi), float(self.sigma), float(self.delta)
         p.normal_fd = int(self.normal_fd)
         p.k1_eps = float(self.k1_eps)
+        p.wetting = int(self.wetting)
+        p.cos_theta = float(self.cos_theta)
         return p
 
     @property

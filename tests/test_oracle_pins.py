@@ -566,3 +566,101 @@ def test_one_dimensional_runs_coincide_on_both_lattices(orc):
     for a, b in zip(res[19], res[27]):
         assert np.abs(a - b).max() < 1e-13
     assert np.abs(res[19][1][0]).max() > 1e-3   # the flow is not trivial
+
+
+# ------------------------------------------------------------ wetting walls
+
+def _contact_angle(phi, yw=-0.5, ycut=3.0):
+    """Contact angle (degrees, through the phi = 1 phase) of a 2D sessile
+    droplet on the wall y = yw: circle fit to the phi = 1/2 contour above
+    y = ycut, cos(theta) = -(y_centre - yw) / radius."""
+    ny, nx = phi.shape
+    pts = []
+    for j in range(nx):
+        for i in range(ny - 1):
+            a, b = phi[i, j] - 0.5, phi[i + 1, j] - 0.5
+            if a * b < 0:
+                pts.append((j, i + a / (a - b)))
+    for i in range(ny):
+        for j in range(nx - 1):
+            a, b = phi[i, j] - 0.5, phi[i, j + 1] - 0.5
+            if a * b < 0:
+                pts.append((j + a / (a - b), i))
+    pts = np.array(pts)
+    pts = pts[pts[:, 1] > ycut]
+    A = np.c_[2 * pts[:, 0], 2 * pts[:, 1], np.ones(len(pts))]
+    cx, cy, c = np.linalg.lstsq(A, (pts ** 2).sum(1), rcond=None)[0]
+    r = math.sqrt(c + cx * cx + cy * cy)
+    return math.degrees(math.acos(max(-1.0, min(1.0, -(cy - yw) / r))))
+
+
+def _sessile(orc, theta0, theta, R=20.0, q=19, wetting=1):
+    """2D droplet (one z-plane) on the wall y = -1/2, its initial circle
+    cutting the wall at theta0; walls at contact angle theta."""
+    W = 4.0
+    nx, ny = int(5.4 * R) // 2 * 2, int(2.7 * R)
+    x = np.arange(nx)[None, :]
+    y = np.arange(ny)[:, None]
+    yc = -0.5 - R * math.cos(math.radians(theta0))
+    d = np.sqrt((x - (nx - 1) / 2) ** 2 + (y - yc) ** 2)
+    phi0 = (0.5 * (1 - np.tanh(2 * (d - R) / W))).reshape(1, ny, nx)
+    P = _params(orc, q, nx=nx, ny=ny, nz=1, wall=(0, 1, 0), tau_phi=1.0, sigma=5e-3, delta=W,
+                wetting=wetting, cos_theta=math.cos(math.radians(theta)))
+    return orc.Oracle(P, phi0)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("theta", [60.0, 90.0, 120.0])
+def test_wetting_keeps_the_contact_angle(orc, theta):
+    """A sessile droplet (R = 16, W = 4) started as the circular cap of the
+    imposed angle keeps it: after 3000 steps the fitted cap's angle is within
+    4 degrees of theta (measured +3.5, +0.8, +1.1 degrees). The bias is
+    about first order in W/R: after 8000 steps it is +6, +1.9, +2.9 degrees at
+    R = 12 and +3.2, +1.0, +1.6 at R = 20."""
+    o = _sessile(orc, theta, theta, R=16.0)
+    o.step(3000)
+    a = _contact_angle(o.fields()[0][0])
+    assert abs(a - theta) < 4.0, a
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("theta", [60.0, 120.0])
+def test_wetting_drives_the_contact_line(orc, theta):
+    """Started as a half circle (90 degrees; R = 16), the droplet spreads
+    (theta = 60) or retracts (theta = 120) towards the imposed angle: after
+    3000 steps it has covered more than 40% of the way (measured 74.6 and
+    108.3 degrees), while with neutral walls it stays within 2 degrees of 90
+    (measured 89.2)."""
+    o = _sessile(orc, 90.0, theta, R=16.0)
+    o.step(3000)
+    a = _contact_angle(o.fields()[0][0])
+    assert abs(a - theta) < 0.6 * abs(90.0 - theta), a
+    n = _sessile(orc, 90.0, theta, R=16.0, wetting=0)
+    n.step(3000)
+    assert abs(_contact_angle(n.fields()[0][0]) - 90.0) < 2.0
+
+
+@LAT
+def test_wetting_conserves_phase_mass(orc, q):
+    o = _sessile(orc, 60.0, 120.0, R=8.0, q=q)
+    m0 = o.diag()["sum_phi"]
+    o.step(300)
+    assert abs(o.diag()["sum_phi"] - m0) < 1e-13 * m0
+
+
+def test_wetting_leaves_a_film_parallel_to_the_wall(orc):
+    """A flat film on the wall (phi varying across the wall only) has its
+    normal along the wall normal: there is no contact line, and the run is
+    bitwise the neutral-wall run."""
+    ny, W = 48, 4.0
+    y = np.arange(ny, dtype=float)
+    phi0 = np.broadcast_to((0.5 * (1 - np.tanh(2 * (y - 12) / W)))[None, :, None], (1, ny, 4))
+    runs = []
+    for wet in (0, 1):
+        P = _params(orc, nx=4, ny=ny, nz=1, wall=(0, 1, 0), sigma=1e-3, wetting=wet,
+                    cos_theta=0.5)
+        o = orc.Oracle(P, np.ascontiguousarray(phi0))
+        o.step(200)
+        runs.append(o.fields())
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
