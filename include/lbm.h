@@ -103,6 +103,14 @@ typedef struct {
     int32_t lattice;           /* 19 or 0: D3Q19; 27: D3Q27 (the same method  */
                                /* on the 27-vector lattice, weights 8/27,     */
                                /* 2/27, 1/54, 1/216; no normal_fd = 1 on it)  */
+    int32_t wetting;           /* 0: neutral walls; 1: contact angle theta at */
+                               /* every wall (the paper has neutral walls):   */
+                               /* on the first node layer next to a wall the  */
+                               /* K1 normal is turned along the wall until    */
+                               /* n . n_wall = -cos(theta); not with          */
+                               /* normal_fd = 1                               */
+    double cos_theta;          /* cos(theta) in [-1, 1], theta measured       */
+                               /* through the phi = 1 phase                   */
 } lbm_params;
 
 /* Diagnostics of the state at the current time t (moments of the

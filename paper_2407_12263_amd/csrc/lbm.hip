@@ -133,6 +133,11 @@ int validate(const lbm_params *P) {
     if (P->lattice != 0 && P->lattice != 19 && P->lattice != 27) return LBM_EINVAL;
     // the finite-difference comparison scheme is built for D3Q19 only
     if (P->lattice == 27 && P->normal_fd) return LBM_EINVAL;
+    // wetting walls act on the K1 normal; not combined with the FD scheme
+    if (P->wetting != 0 && P->wetting != 1) return LBM_EINVAL;
+    if (P->wetting && P->normal_fd) return LBM_EINVAL;
+    if (P->wetting && !(std::isfinite(P->cos_theta) && P->cos_theta >= -1.0 && P->cos_theta <= 1.0))
+        return LBM_EINVAL;
     const double N = (double)P->nx * P->ny * P->nz;
     const double Q = num_pop(P);
     if (Q * N >= 2147483647.0) return LBM_EINVAL;
@@ -247,6 +252,15 @@ DevParams<R> make_params(const lbm_params *P, const TileCfg &tc) {
     return d;
 }
 
+template <class R>
+Wet<R> make_wet(const lbm_params *P) {
+    Wet<R> w;
+    w.on = P->wetting;
+    w.cos_theta = R(P->wetting ? P->cos_theta : 0.0);
+    w.sin_theta = R(P->wetting ? std::sqrt(1.0 - P->cos_theta * P->cos_theta) : 1.0);
+    return w;
+}
+
 }  // namespace
 
 struct lbm_ctx {
@@ -330,7 +344,8 @@ void launch_step(lbm_ctx *c, int src, int dst, const DevParams<typename St::R> &
                            c->stream, cbuf_of<St>(c, src), buf_of<St>(c, dst), P, mf);
     else
         hipLaunchKernelGGL((step_kernel<St, M, W, FD>), tile_grid(P), dim3(BLOCK), 0, c->stream,
-                           cbuf_of<St>(c, src), buf_of<St>(c, dst), P, mf);
+                           cbuf_of<St>(c, src), buf_of<St>(c, dst), P, mf,
+                           make_wet<typename St::R>(&c->P));
     block_off += P.ntiles;
 }
 
@@ -470,12 +485,12 @@ void launch_moments(lbm_ctx *c, const FieldOut &o) {
         if (c->P.normal_fd) {
             launch_phi<St, M>(c, c->cur ^ 1, MassFix{0, nullptr, nullptr, 0});
             hipLaunchKernelGGL((moments_kernel<St, M, W, true>), tile_grid(P), dim3(BLOCK), 0,
-                               c->stream, cbuf_of<St>(c, c->cur ^ 1), P, o);
+                               c->stream, cbuf_of<St>(c, c->cur ^ 1), P, o, make_wet<R>(&c->P));
             return;
         }
     }
     hipLaunchKernelGGL((moments_kernel<St, M, W, false>), tile_grid(P), dim3(BLOCK), 0,
-                       c->stream, cbuf_of<St>(c, c->cur ^ 1), P, o);
+                       c->stream, cbuf_of<St>(c, c->cur ^ 1), P, o, make_wet<R>(&c->P));
 }
 
 template <class St, Mode M>

@@ -177,6 +177,14 @@ struct DevParams {
     uint32_t plane_bytes;    // bytes from one population plane to the next
 };
 
+// Wetting walls: contact angle theta at every wall (on = 0: neutral walls).
+// A kernel argument of the wall-aware launches only.
+template <class R>
+struct Wet {
+    int on;
+    R cos_theta, sin_theta;
+};
+
 // Linear index of this block in its launch grid (x fastest).
 __device__ __forceinline__ uint32_t linear_block() {
     return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
@@ -373,6 +381,23 @@ __device__ __forceinline__ bool beyond_wall(const Site<NQ> &s) {
     if constexpr (e[2] > 0) b = b || s.lo[2];
     if constexpr (e[2] < 0) b = b || s.hi[2];
     return b;
+}
+
+// Inward unit normal of the walls a wall node touches (the normalised sum of
+// its faces' at an edge or corner); returns false on other nodes.
+template <class R, int NQ>
+__device__ __forceinline__ bool wall_normal(const Site<NQ> &s, R (&nw)[3]) {
+    R l2 = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        nw[a] = (s.lo[a] ? R(1) : R(0)) - (s.hi[a] ? R(1) : R(0));
+        l2 += nw[a] * nw[a];
+    }
+    if (!(l2 > R(0))) return false;
+    const R r = R(1) / sqrt(l2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) nw[a] *= r;
+    return true;
 }
 
 // ------------------------------------------------------------ propagation
@@ -577,9 +602,17 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 // FD: grad(phi) is given (the finite-difference variant) instead of recovered
 // from K1: n = grad/|grad| (0 where |grad| <= k1_eps, as for K1), S = s n,
 // |grad phi| = |grad|.
-template <bool FD = false, class R, int NQ>
+// nw (wetting walls): the inward unit normal of the walls the node touches.
+// The normal from K1 is turned, keeping its direction along the wall, until
+// n . nw = -cos(theta); S and grad(phi) then follow from that normal. With
+// the wall passing no phase flux, the wall-normal part of M (grad phi - s n)
+// then vanishes at grad(phi) . nw = -s cos(theta), the contact-angle
+// condition of the equilibrium profile. A normal with no part along the wall
+// (|n_t| <= 1e-6) is kept.
+template <bool FD = false, bool WET = false, class R, int NQ>
 __device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)[NQ],
-                                            const R (&gb)[NQ], const R *gfd = nullptr) {
+                                            const R (&gb)[NQ], const R *gfd = nullptr,
+                                            const R *nw = nullptr, const Wet<R> *wp = nullptr) {
     Macro<R> m;
     R phi = gb[0], sf = fb[0];
 #pragma unroll
@@ -625,6 +658,26 @@ __device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)
     }
     // |grad phi|: with n = -K1/|K1|, grad phi = n (tau cs2 s + |K1|)/((tau+1/2)cs2)
     m.gnorm = has_n ? fabs(fma(P.tau_phi_cs2, s, k)) * P.inv_tp : k * P.inv_tp;
+    if constexpr (WET) {
+        if (nw && has_n) {
+            const R dn = fma(m.n[0], nw[0], fma(m.n[1], nw[1], m.n[2] * nw[2]));
+            R t[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) t[a] = fma(-dn, nw[a], m.n[a]);
+            const R tt = sqrt(fma(t[0], t[0], fma(t[1], t[1], t[2] * t[2])));
+            if (tt > R(1e-6)) {
+                const R st = wp->sin_theta / tt;
+                R gp[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    m.n[a] = fma(st, t[a], -wp->cos_theta * nw[a]);
+                    m.S[a] = s * m.n[a];
+                    gp[a] = fma(P.tau_phi_cs2, m.S[a], -K[a]) * P.inv_tp;
+                }
+                m.gnorm = sqrt(fma(gp[0], gp[0], fma(gp[1], gp[1], gp[2] * gp[2])));
+            }
+        }
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         m.gradrho[a] = P.drho * fma(P.tau_phi_cs2, m.S[a], -K[a]) * P.inv_tp;
@@ -889,9 +942,24 @@ __device__ __forceinline__ void fd_grad(const DevParams<R> &P, const Site<NQ> &s
     });
 }
 
+// Moments of one node; the wall-aware instances apply the wetting walls.
+template <bool WALLS, bool FD, class R, int NQ>
+__device__ __forceinline__ Macro<R> site_moments(const DevParams<R> &P, const Site<NQ> &s,
+                                                 const R (&fb)[NQ], const R (&gb)[NQ],
+                                                 const R (&gfd)[3], const Wet<R> &wp) {
+    if constexpr (WALLS && !FD) {
+        R nw[3];
+        const bool wet = wp.on && s.wall && wall_normal(s, nw);
+        return moments<FD, true>(P, fb, gb, gfd, wet ? nw : nullptr, &wp);
+    } else {
+        return moments<FD>(P, fb, gb, gfd);
+    }
+}
+
 template <class St, Mode M, bool WALLS, bool FD>
 __device__ __forceinline__ void step_body(const CBuf<St> &src, const Buf<St> &dst,
-                                          const DevParams<typename St::R> &P, const MassFix &mf) {
+                                          const DevParams<typename St::R> &P, const MassFix &mf,
+                                          const Wet<typename St::R> &wp) {
     using R = typename St::R;
     const Site<St::Q> s = make_site<St::Q>(P);
     double rep_phi = 0.0, rep_w = 0.0;
@@ -902,7 +970,7 @@ __device__ __forceinline__ void step_body(const CBuf<St> &src, const Buf<St> &ds
         apply_massfix(mf, gb);
         R gfd[3];
         if constexpr (FD) fd_grad<WALLS>(P, s, gfd);
-        const Macro<R> m = moments<FD>(P, fb, gb, gfd);
+        const Macro<R> m = site_moments<WALLS, FD>(P, s, fb, gb, gfd, wp);
         if (mf.mode & 1) {
             rep_phi = m.phi;
             rep_w = mass_weight(m.phi);
@@ -917,8 +985,9 @@ __device__ __forceinline__ void step_body(const CBuf<St> &src, const Buf<St> &ds
 
 template <class St, Mode M, bool WALLS, bool FD>
 __global__ void __launch_bounds__(BLOCK) step_kernel(CBuf<St> src, Buf<St> dst,
-                                                     DevParams<typename St::R> P, MassFix mf) {
-    step_body<St, M, WALLS, FD>(src, dst, P, mf);
+                                                     DevParams<typename St::R> P, MassFix mf,
+                                                     Wet<typename St::R> wp) {
+    step_body<St, M, WALLS, FD>(src, dst, P, mf, wp);
 }
 
 // The same step held to 96 VGPRs (5 wavefronts per SIMD) for the wall-free
@@ -927,7 +996,7 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(CBuf<St> src, Buf<St> dst,
 template <class St, Mode M, bool WALLS, bool FD>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8)))
 step_kernel_o5(CBuf<St> src, Buf<St> dst, DevParams<typename St::R> P, MassFix mf) {
-    step_body<St, M, WALLS, FD>(src, dst, P, mf);
+    step_body<St, M, WALLS, FD>(src, dst, P, mf, Wet<typename St::R>{0, 0, 1});
 }
 
 // First pass of the finite-difference variant: phi = sum of the propagated g
@@ -1002,7 +1071,7 @@ struct FieldOut {
 // fields, FP64 PDFs and/or per-block FP64 partial sums of the diagnostics.
 template <class St, Mode M, bool WALLS, bool FD>
 __global__ void __launch_bounds__(BLOCK) moments_kernel(CBuf<St> src, DevParams<typename St::R> P,
-                                                        FieldOut out) {
+                                                        FieldOut out, Wet<typename St::R> wp) {
     using R = typename St::R;
     const Site<St::Q> s = make_site<St::Q>(P);
     double acc[NSUM];
@@ -1016,7 +1085,7 @@ __global__ void __launch_bounds__(BLOCK) moments_kernel(CBuf<St> src, DevParams<
         gather<M, WALLS, St>(in, s, P, fb, gb);
         R gfd[3];
         if constexpr (FD) fd_grad<WALLS>(P, s, gfd);
-        const Macro<R> m = moments<FD>(P, fb, gb, gfd);
+        const Macro<R> m = site_moments<WALLS, FD>(P, s, fb, gb, gfd, wp);
         const size_t N = (size_t)P.N, n = s.n;
         if (out.phi) {
             if (out.dtype == 0) ((double *)out.phi)[n] = m.phi;

@@ -43,7 +43,9 @@ class LbmParams(C.Structure):
                 ("G", C.c_double * 3),
                 ("k1_eps", C.c_double),
                 ("p_ref", C.c_double),
-                ("lattice", C.c_int32)]
+                ("lattice", C.c_int32),
+                ("wetting", C.c_int32),
+                ("cos_theta", C.c_double)]
 
 
 class LbmDiag(C.Structure):
@@ -112,10 +114,12 @@ def _check(rc: int, where: str):
 def make_params(nx, ny, nz, precision="fp32", wall=(0, 0, 0), courant=0.997, rho1=1.0,
                 rho2=1.0, tau_rho1=0.3, tau_rho2=0.3, tau_phi=0.3, sigma=0.0, delta=4.0,
                 G=(0.0, 0.0, 0.0), k1_eps=1e-5, p_ref=0.0, store_log2=(10, 10),
-                check_every=0, mass_fix_every=None, normal_fd=0, lattice=19) -> LbmParams:
+                check_every=0, mass_fix_every=None, normal_fd=0, lattice=19, wetting=0,
+                cos_theta=0.0) -> LbmParams:
     """mass_fix_every: None picks 10 for FP32 and 16-bit storage (FP32 rounding
     alone drifts the phase mass by ~1e-8 of it per step on a quasi-steady
-    interface), 0 for FP64. lattice: 19 (D3Q19) or 27 (D3Q27)."""
+    interface), 0 for FP64. lattice: 19 (D3Q19) or 27 (D3Q27). wetting = 1 with
+    cos_theta: contact angle theta at the walls."""
     p = LbmParams()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -134,6 +138,8 @@ def make_params(nx, ny, nz, precision="fp32", wall=(0, 0, 0), courant=0.997, rho
     p.tau_phi, p.sigma, p.delta = float(tau_phi), float(sigma), float(delta)
     p.k1_eps, p.p_ref = float(k1_eps), float(p_ref)
     p.lattice = int(lattice)
+    p.wetting = int(wetting)
+    p.cos_theta = float(cos_theta)
     return p
 
 

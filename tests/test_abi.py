@@ -84,7 +84,9 @@ def test_workspace_bytes_and_validation(lib):
     # D3Q27: 27 planes per field; the comparison FD scheme is D3Q19 only
     n27 = lib.lbm_workspace_bytes(lib.make_params(32, 32, 32, precision="fp32", lattice=27))
     assert n27 >= 2 * 2 * 27 * N * 4 and n27 > n32
-    for kw in (dict(lattice=23), dict(lattice=27, normal_fd=1)):
+    for kw in (dict(lattice=23), dict(lattice=27, normal_fd=1), dict(wetting=2),
+               dict(wetting=1, cos_theta=1.5), dict(wetting=1, cos_theta=float("nan")),
+               dict(wetting=1, normal_fd=1)):
         with pytest.raises(lib.LbmError) as ei:
             lib.lbm_workspace_bytes(lib.make_params(8, 8, 8, **kw))
         assert ei.value.status == lib.LBM_EINVAL
