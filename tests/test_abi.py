@@ -72,10 +72,11 @@ def test_workspace_bytes_and_validation(lib):
     bad = [dict(courant=1.5), dict(courant=0.0), dict(tau_phi=0.0), dict(rho1=-1.0),
            dict(delta=0.0), dict(wall=(0, 0, 2)), dict(precision=7), dict(sigma=-1.0),
            dict(k1_eps=-1.0), dict(store_log2=(30, 0)), dict(G=(float("nan"), 0, 0)),
-           dict(normal_fd=2)]
+           dict(normal_fd=2), dict(nx=0), dict(ny=0), dict(nz=-1)]
     for kw in bad:
+        kw = dict(dict(nx=8, ny=8, nz=8), **kw)
         with pytest.raises(lib.LbmError) as ei:
-            lib.lbm_workspace_bytes(lib.make_params(8, 8, 8, **kw))
+            lib.lbm_workspace_bytes(lib.make_params(**kw))
         assert ei.value.status == lib.LBM_EINVAL
     with pytest.raises(lib.LbmError):
         lib.lbm_workspace_bytes(lib.make_params(8, 1, 8, wall=(0, 1, 0)))

@@ -79,3 +79,29 @@ def test_full_size_one_step_parity(name, prec):
     assert e[0] <= tp and e[1] <= tu and e[2] <= tq
     assert max(ef, eg) <= tp
     assert max(e[0], ef, eg) <= ONE_STEP[prec]
+
+
+def test_largest_lattice_fp16():
+    """The largest lattice whose 19 population planes of 16-bit storage fit
+    one 32-bit buffer range: 512 x 512 x 215 (56.4 M nodes; the last plane
+    starts 3.99 GB into the range). 216 planes are rejected. The initial
+    moments return phi0 at every node, and 20 steps keep the phase mass to
+    1e-6 and every value finite."""
+    import torch
+    from paper_2407_12263_amd import lbm
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_workspace_bytes(lbm.make_params(512, 512, 216, precision="fp16"))
+    w = inputs.static_droplet(n=512, R=40.0, nz=215, sigma=1e-3)
+    say(f"[full] largest lattice {w.nx}x{w.ny}x{w.nz} fp16: init, 20 steps")
+    sol = gpu_solver(w, "fp16")
+    phi0 = torch.as_tensor(w.phi0, device="cuda")
+    e0 = float((sol.fields()[0] - phi0).abs().max())
+    m0 = float(phi0.sum())
+    del phi0
+    sol.step(20)
+    d = sol.diagnostics()
+    drift = abs(d["sum_phi"] - m0) / m0
+    say(f"   init max|dphi| {e0:.2e}, mass drift after 20 steps {drift:.2e}, umax {d['umax']:.2e}")
+    assert e0 < 2e-3
+    assert np.isfinite(d["sum_phi"]) and np.isfinite(d["umax"]) and d["umax"] < 1e-2
+    assert drift < 1e-6
