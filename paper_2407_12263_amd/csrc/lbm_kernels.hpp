@@ -384,20 +384,19 @@ __device__ __forceinline__ bool beyond_wall(const Site<NQ> &s) {
 }
 
 // Inward unit normal of the walls a wall node touches (the normalised sum of
-// its faces' at an edge or corner); returns false on other nodes.
+// its faces' at an edge or corner); 0 on other nodes (then l2 = 0).
 template <class R, int NQ>
-__device__ __forceinline__ bool wall_normal(const Site<NQ> &s, R (&nw)[3]) {
+__device__ __forceinline__ R wall_normal(const Site<NQ> &s, R (&nw)[3]) {
     R l2 = R(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         nw[a] = (s.lo[a] ? R(1) : R(0)) - (s.hi[a] ? R(1) : R(0));
         l2 += nw[a] * nw[a];
     }
-    if (!(l2 > R(0))) return false;
-    const R r = R(1) / sqrt(l2);
+    const R r = l2 > R(0) ? R(1) / sqrt(l2) : R(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) nw[a] *= r;
-    return true;
+    return l2;
 }
 
 // ------------------------------------------------------------ propagation
@@ -609,10 +608,19 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 // then vanishes at grad(phi) . nw = -s cos(theta), the contact-angle
 // condition of the equilibrium profile. A normal with no part along the wall
 // (|n_t| <= 1e-6) is kept.
+// A wall node's inward normal for the wetting walls (on: the node touches a
+// wetting wall).
+template <class R>
+struct WallNormal {
+    R v[3];
+    bool on;
+};
+
 template <bool FD = false, bool WET = false, class R, int NQ>
 __device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)[NQ],
                                             const R (&gb)[NQ], const R *gfd = nullptr,
-                                            const R *nw = nullptr, const Wet<R> *wp = nullptr) {
+                                            const WallNormal<R> &nw = WallNormal<R>{},
+                                            const Wet<R> &wp = Wet<R>{}) {
     Macro<R> m;
     R phi = gb[0], sf = fb[0];
 #pragma unroll
@@ -659,18 +667,18 @@ __device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)
     // |grad phi|: with n = -K1/|K1|, grad phi = n (tau cs2 s + |K1|)/((tau+1/2)cs2)
     m.gnorm = has_n ? fabs(fma(P.tau_phi_cs2, s, k)) * P.inv_tp : k * P.inv_tp;
     if constexpr (WET) {
-        if (nw && has_n) {
-            const R dn = fma(m.n[0], nw[0], fma(m.n[1], nw[1], m.n[2] * nw[2]));
+        if (nw.on && has_n) {
+            const R dn = fma(m.n[0], nw.v[0], fma(m.n[1], nw.v[1], m.n[2] * nw.v[2]));
             R t[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) t[a] = fma(-dn, nw[a], m.n[a]);
+            for (int a = 0; a < 3; ++a) t[a] = fma(-dn, nw.v[a], m.n[a]);
             const R tt = sqrt(fma(t[0], t[0], fma(t[1], t[1], t[2] * t[2])));
             if (tt > R(1e-6)) {
-                const R st = wp->sin_theta / tt;
+                const R st = wp.sin_theta / tt;
                 R gp[3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    m.n[a] = fma(st, t[a], -wp->cos_theta * nw[a]);
+                    m.n[a] = fma(st, t[a], -wp.cos_theta * nw.v[a]);
                     m.S[a] = s * m.n[a];
                     gp[a] = fma(P.tau_phi_cs2, m.S[a], -K[a]) * P.inv_tp;
                 }
@@ -948,9 +956,10 @@ __device__ __forceinline__ Macro<R> site_moments(const DevParams<R> &P, const Si
                                                  const R (&fb)[NQ], const R (&gb)[NQ],
                                                  const R (&gfd)[3], const Wet<R> &wp) {
     if constexpr (WALLS && !FD) {
-        R nw[3];
-        const bool wet = wp.on && s.wall && wall_normal(s, nw);
-        return moments<FD, true>(P, fb, gb, gfd, wet ? nw : nullptr, &wp);
+        WallNormal<R> nw;
+        const R l2 = wall_normal(s, nw.v);
+        nw.on = wp.on && s.wall && l2 > R(0);
+        return moments<FD, true>(P, fb, gb, gfd, nw, wp);
     } else {
         return moments<FD>(P, fb, gb, gfd);
     }
