@@ -130,13 +130,13 @@ def test_one_step_parity_from_oracle_state(courant):
 
 
 def test_contact_angle_matches_oracle():
-    import test_oracle_pins as pins
+    from shapes import contact_angle
     w = sessile(90.0, 60.0)
     sol = gpu_solver(w, "fp32")
     o = oracle_run(w, 2000)
     sol.step(2000)
-    a = pins._contact_angle(gpu_fields(sol)[0][0])
-    ao = pins._contact_angle(o.fields()[0][0])
+    a = contact_angle(gpu_fields(sol)[0][0])
+    ao = contact_angle(o.fields()[0][0])
     say(f"[wet] contact angle after 2000 steps: GPU fp32 {a:.3f}, oracle {ao:.3f}")
     assert abs(a - ao) < 0.05
     assert a < 85.0

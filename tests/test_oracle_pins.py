@@ -16,6 +16,8 @@ import pytest
 
 from paper_2407_12263_amd import inputs
 
+from shapes import contact_angle
+
 C = 0.997
 CS2 = C * C / 3.0
 
@@ -570,30 +572,6 @@ def test_one_dimensional_runs_coincide_on_both_lattices(orc):
 
 # ------------------------------------------------------------ wetting walls
 
-def _contact_angle(phi, yw=-0.5, ycut=3.0):
-    """Contact angle (degrees, through the phi = 1 phase) of a 2D sessile
-    droplet on the wall y = yw: circle fit to the phi = 1/2 contour above
-    y = ycut, cos(theta) = -(y_centre - yw) / radius."""
-    ny, nx = phi.shape
-    pts = []
-    for j in range(nx):
-        for i in range(ny - 1):
-            a, b = phi[i, j] - 0.5, phi[i + 1, j] - 0.5
-            if a * b < 0:
-                pts.append((j, i + a / (a - b)))
-    for i in range(ny):
-        for j in range(nx - 1):
-            a, b = phi[i, j] - 0.5, phi[i, j + 1] - 0.5
-            if a * b < 0:
-                pts.append((j + a / (a - b), i))
-    pts = np.array(pts)
-    pts = pts[pts[:, 1] > ycut]
-    A = np.c_[2 * pts[:, 0], 2 * pts[:, 1], np.ones(len(pts))]
-    cx, cy, c = np.linalg.lstsq(A, (pts ** 2).sum(1), rcond=None)[0]
-    r = math.sqrt(c + cx * cx + cy * cy)
-    return math.degrees(math.acos(max(-1.0, min(1.0, -(cy - yw) / r))))
-
-
 def _sessile(orc, theta0, theta, R=20.0, q=19, wetting=1):
     """2D droplet (one z-plane) on the wall y = -1/2, its initial circle
     cutting the wall at theta0; walls at contact angle theta."""
@@ -619,7 +597,7 @@ def test_wetting_keeps_the_contact_angle(orc, theta):
     R = 12 and +3.2, +1.0, +1.6 at R = 20."""
     o = _sessile(orc, theta, theta, R=16.0)
     o.step(3000)
-    a = _contact_angle(o.fields()[0][0])
+    a = contact_angle(o.fields()[0][0])
     assert abs(a - theta) < 4.0, a
 
 
@@ -633,11 +611,11 @@ def test_wetting_drives_the_contact_line(orc, theta):
     (measured 89.2)."""
     o = _sessile(orc, 90.0, theta, R=16.0)
     o.step(3000)
-    a = _contact_angle(o.fields()[0][0])
+    a = contact_angle(o.fields()[0][0])
     assert abs(a - theta) < 0.6 * abs(90.0 - theta), a
     n = _sessile(orc, 90.0, theta, R=16.0, wetting=0)
     n.step(3000)
-    assert abs(_contact_angle(n.fields()[0][0]) - 90.0) < 2.0
+    assert abs(contact_angle(n.fields()[0][0]) - 90.0) < 2.0
 
 
 @LAT
