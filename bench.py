@@ -100,7 +100,8 @@ def time_solver(sol, steps: int, warmup: int):
 
 def cpu_baseline(w, steps: int = 2):
     """The FP64 CPU oracle, untuned, on the full lattice of the same workload
-    for a few steps (bounded sample); returns (MLUPS, threads, seconds)."""
+    for a few steps (bounded sample), on all host threads and then one step
+    on one thread; returns (MLUPS, threads, seconds, single-thread MLUPS)."""
     import oracle
     oracle.build(force=False)
     P = oracle.OracleParams(**w.params())
@@ -109,8 +110,13 @@ def cpu_baseline(w, steps: int = 2):
     o.step(steps)
     dt = time.perf_counter() - t0
     threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    o.step(1)
+    dt1 = time.perf_counter() - t1
+    oracle.set_num_threads(threads)
     del o
-    return w.N * steps / dt / 1e6, threads, dt
+    return w.N * steps / dt / 1e6, threads, dt, w.N / dt1 / 1e6
 
 
 def unet_cpu_baseline(n: int = 64):
@@ -264,11 +270,12 @@ def main():
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: oracle FP64, {args.cpu_steps} steps on the full lattice",
               file=sys.stderr, flush=True)
-        mlups, threads, dt = cpu_baseline(w, args.cpu_steps)
+        mlups, threads, dt, mlups1 = cpu_baseline(w, args.cpu_steps)
         line["cpu_baseline"] = {"value": round(mlups, 3), "unit": "MLUPS", "cores": threads,
                                 "kind": "oracle",
                                 "sample": f"{args.cpu_steps} steps of the full {w.nx}x{w.ny}x{w.nz} "
-                                          f"lattice in FP64 ({dt:.1f} s)"}
+                                          f"lattice in FP64 ({dt:.1f} s)",
+                                "single_thread_value": round(mlups1, 3)}
     if not args.no_surrogate:
         from paper_2407_12263_amd import accel
         print(f"[bench] surrogate: emulsion 256^3, {args.surrogate_trajectories} training "

@@ -98,8 +98,9 @@ void orc_propagate(const orc_params *P, const double *in, double *out);
 /* Isotropic central-difference gradient of a scalar field (3N out). */
 void orc_fd_gradient(const orc_params *P, const double *phi, double *grad);
 
-/* OpenMP threads the grid passes use. */
+/* OpenMP threads the grid passes use; set them (n > 0). */
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

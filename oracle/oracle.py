@@ -143,6 +143,7 @@ def _load(q: int = 19):
         lib.orc_propagate.argtypes = [C.POINTER(_Params), _dp, _dp]
         lib.orc_fd_gradient.argtypes = [C.POINTER(_Params), _dp, _dp]
         lib.orc_num_threads.restype = C.c_int
+        lib.orc_set_num_threads.argtypes = [C.c_int]
         _libs[q] = lib
     return _libs[q]
 
@@ -163,8 +164,12 @@ def _f64(a, shape=None):
     return a
 
 
-def num_threads() -> int:
-    return int(_load().orc_num_threads())
+def num_threads(q: int = 19) -> int:
+    return int(_load(q).orc_num_threads())
+
+
+def set_num_threads(n: int, q: int = 19):
+    _load(q).orc_set_num_threads(int(n))
 
 
 def lattice(q: int = 19):
