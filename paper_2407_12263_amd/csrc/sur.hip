@@ -593,6 +593,46 @@ __global__ void __launch_bounds__(256) sum_chunks_kernel(const float *__restrict
 
 // Per-block partial sums of dy over points for each channel: thread
 // (tid % cout) owns a channel, (tid / cout) a strided slice of the block's points.
+// First pass of the same fixed-order sum for wide rows (n a multiple of 4):
+// block (x, k) sums rows [k L, min((k + 1) L, nrows)) of elements
+// [128 x, 128 x + 128), four per thread with 16-byte loads, in 8 interleaved
+// groups combined in order, into row k of mid; sum_chunks_kernel then adds
+// the rows of mid in order. More blocks and wider loads keep more bytes in
+// flight than one pass over all rows.
+constexpr int kSumSeg = 8;
+__global__ void __launch_bounds__(256) sum_rows4_kernel(const float4 *__restrict__ part,
+                                                        long nrows, long n4, int L,
+                                                        float4 *__restrict__ mid) {
+    __shared__ float4 red[8][32];
+    const int l = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const long e = (long)blockIdx.x * 32 + l;
+    const long r0 = (long)blockIdx.y * L, r1 = r0 + L < nrows ? r0 + L : nrows;
+    float4 acc = float4{0.f, 0.f, 0.f, 0.f};
+    if (e < n4) {
+#pragma unroll 4
+        for (long r = r0 + g; r < r1; r += 8) {
+            const float4 v = part[r * n4 + e];
+            acc.x += v.x;
+            acc.y += v.y;
+            acc.z += v.z;
+            acc.w += v.w;
+        }
+    }
+    red[g][l] = acc;
+    __syncthreads();
+    if (g == 0 && e < n4) {
+        float4 t = red[0][l];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) {
+            t.x += red[k][l].x;
+            t.y += red[k][l].y;
+            t.z += red[k][l].z;
+            t.w += red[k][l].w;
+        }
+        mid[(long)blockIdx.y * n4 + e] = t;
+    }
+}
+
 __global__ void __launch_bounds__(256) bias_partial_kernel(const uint16_t *__restrict__ dy, int cout,
                                                            long P, long chunk,
                                                            float *__restrict__ part) {
@@ -791,6 +831,10 @@ __global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ pred
             const float4 *p4 = (const float4 *)(pred + p * cs), *t4 = (const float4 *)(tgt + p * cs);
             float4 *g4 = (float4 *)(grad + p * cs);
             for (int c4 = 0; c4 < cs / 4; ++c4) {
+                if (4 * c4 >= cu) {  // padding channels: no loss, zero gradient
+                    g4[c4] = float4{0.f, 0.f, 0.f, 0.f};
+                    continue;
+                }
                 const float4 a = p4[c4], b = t4[c4];
                 const float pa[4] = {a.x, a.y, a.z, a.w}, tb[4] = {b.x, b.y, b.z, b.w};
                 float gg[4];
@@ -1225,7 +1269,8 @@ size_t sur_wgrad_scratch_floats(int32_t cin, int32_t cout, int32_t nx, int32_t n
     const long parts = std::max(wgrad_chunks(P), wgrad_tiled_blocks(cin, P));
     // bias partials: one per 1024 points, or one per tiled block
     const long bparts = std::max((long)grid1(P, 1024).x, wgrad_tiled_blocks(cin, P));
-    return (size_t)(parts * 27L * cin * cout + bparts * (long)cout);
+    // the rows of the first reduction pass
+    return (size_t)(parts * 27L * cin * cout + bparts * (long)cout + kSumSeg * 27L * cin * cout);
 }
 
 int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, int32_t nx,
@@ -1265,7 +1310,25 @@ int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, i
             default: hipLaunchKernelGGL(wgrad_kernel<4>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, kWgradChunk, scratch); break;
         }
     }
-    hipLaunchKernelGGL(sum_chunks_kernel, grid1(n, 32), dim3(256), 0, s, (const float *)scratch, nch, n, dw);
+    {
+        // two passes: kSumSeg row segments into mid, then mid's rows in order
+        // (n = 27 cin cout is a multiple of 4; the partial rows are 16-byte
+        // aligned when the scratch is)
+        const long bparts = std::max((long)grid1(P, 1024).x, wgrad_tiled_blocks(cin, P));
+        float *mid = scratch + nch * n + bparts * (long)cout;
+        if (aligned16(scratch) && aligned16(mid) && n % 4 == 0 && nch >= 2 * kSumSeg) {
+            const long n4 = n / 4;
+            const int L = (int)((nch + kSumSeg - 1) / kSumSeg);
+            const dim3 g1((unsigned)((n4 + 31) / 32), (unsigned)kSumSeg);
+            hipLaunchKernelGGL(sum_rows4_kernel, g1, dim3(256), 0, s, (const float4 *)scratch, nch,
+                               n4, L, (float4 *)mid);
+            hipLaunchKernelGGL(sum_chunks_kernel, grid1(n, 32), dim3(256), 0, s,
+                               (const float *)mid, (long)kSumSeg, n, dw);
+        } else {
+            hipLaunchKernelGGL(sum_chunks_kernel, grid1(n, 32), dim3(256), 0, s,
+                               (const float *)scratch, nch, n, dw);
+        }
+    }
     if (dbias && !bias_done) {
         const long nb = grid1(P, 1024).x;
         float *bp = scratch + nch * n;
