@@ -65,6 +65,14 @@ int sur_pool2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void
 /* dx[p][c] += dy[parent(p)][c] / 8 (FP32; fine grid sizes). */
 int sur_pool2_bwd(const float *dy, int32_t c, int32_t nx, int32_t ny, int32_t nz, float *dx,
                   void *stream);
+/* The gradient at an encoder output that feeds both the 2x2x2 pooling and
+ * the skip connection, through its ReLU, in one pass (fine grid sizes; dx
+ * [P][c] overwritten): dx[p][c'] = act[p][c'] > 0 ? dy[parent(p)][c'] / 8 +
+ * skip[p][skip_off + c'] : 0, dy FP32 on the coarse grid, skip FP32
+ * [P][skip_stride], act BF16 [P][c]. */
+int sur_pool2_bwd_skip(const float *dy, int32_t c, int32_t nx, int32_t ny, int32_t nz,
+                       const float *skip, int32_t skip_stride, int32_t skip_off, const void *act,
+                       float *dx, void *stream);
 /* Nearest 2x upsampling of BF16 x [P_coarse][c] (coarse sizes) into channels
  * [yoff, yoff + c) of BF16 y [P_fine][ystride]. */
 int sur_upsample2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void *y,

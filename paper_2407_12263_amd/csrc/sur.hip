@@ -797,6 +797,28 @@ __global__ void copy_channels_v8_kernel(const uint16_t *__restrict__ x, int c, l
     *(uint4 *)(y + p * ystride + yoff + 8 * g) = *(const uint4 *)(x + p * c + 8 * g);
 }
 
+// Gradient at an encoder output that feeds both the pooling and the skip
+// connection, masked by its ReLU: dx[p][ch] = act > 0 ? dy[parent(p)][ch] / 8
+// + skip[p][soff + ch] : 0, in one pass (the same two additions as zero,
+// pool2_bwd, add_channels and relu_mask in turn).
+__global__ void pool2_bwd_skip_kernel(const float *__restrict__ dy, int c, int nx, int ny, int nz,
+                                      const float *__restrict__ skip, int sstride, int soff,
+                                      const uint16_t *__restrict__ act, float *__restrict__ dx) {
+    const long n = (long)nx * ny * nz * c;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int ch = mod32(e, c);
+    const long p = div32(e, c);
+    float v = 0.f;
+    if (bf2f(act[e]) > 0.f) {
+        int X, Y, Z;
+        coords(p, nx, ny, X, Y, Z);
+        const long qq = (X / 2) + (long)(nx / 2) * ((Y / 2) + (long)(ny / 2) * (Z / 2));
+        v = 0.125f * dy[qq * c + ch] + skip[p * sstride + soff + ch];
+    }
+    dx[e] = v;
+}
+
 __global__ void add_channels_kernel(const float *__restrict__ dy, int dystride, int dyoff, int c,
                                     long P, float *__restrict__ dx) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1369,6 +1391,19 @@ int sur_pool2_bwd(const float *dy, int32_t c, int32_t nx, int32_t ny, int32_t nz
     const long n = (long)nx * ny * nz * c;
     hipLaunchKernelGGL(pool2_bwd_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, dy, c, nx,
                        ny, nz, dx);
+    return launched();
+}
+
+int sur_pool2_bwd_skip(const float *dy, int32_t c, int32_t nx, int32_t ny, int32_t nz,
+                       const float *skip, int32_t skip_stride, int32_t skip_off, const void *act,
+                       float *dx, void *stream) {
+    if (!dy || !skip || !act || !dx || c <= 0 || !dims_ok(nx, ny, nz) || nx % 2 || ny % 2 ||
+        nz % 2 || skip_off < 0 || skip_off + c > skip_stride ||
+        !elems_ok((long)nx * ny * nz, skip_stride))
+        return SUR_EINVAL;
+    const long n = (long)nx * ny * nz * c;
+    hipLaunchKernelGGL(pool2_bwd_skip_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, dy, c,
+                       nx, ny, nz, skip, skip_stride, skip_off, (const uint16_t *)act, dx);
     return launched();
 }
 

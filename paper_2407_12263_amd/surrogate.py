@@ -45,6 +45,7 @@ def load_library(path: str | None = None):
     lib.sur_pack_weights.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.sur_pool2.argtypes = [vp, i32, i32, i32, i32, vp, vp]
     lib.sur_pool2_bwd.argtypes = [vp, i32, i32, i32, i32, vp, vp]
+    lib.sur_pool2_bwd_skip.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, vp, vp, vp]
     lib.sur_upsample2.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, vp]
     lib.sur_upsample2_bwd.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp]
     lib.sur_copy_channels.argtypes = [vp, i32, i64, vp, i32, i32, vp]
@@ -117,6 +118,11 @@ def sur_pool2(x, c, grid, y):
 
 def sur_pool2_bwd(dy, c, grid, dx):
     _ok(load_library().sur_pool2_bwd(_p(dy), c, *grid, _p(dx), _stream()), "sur_pool2_bwd")
+
+
+def sur_pool2_bwd_skip(dy, c, grid, skip, skip_stride, skip_off, act, dx):
+    _ok(load_library().sur_pool2_bwd_skip(_p(dy), c, *grid, _p(skip), skip_stride, skip_off,
+                                          _p(act), _p(dx), _stream()), "sur_pool2_bwd_skip")
 
 
 def sur_upsample2(x, c, grid, y, ystride, yoff):
@@ -374,11 +380,9 @@ class UNet:
                     mask = None  # input is the concat: split below, masks come from its parts
                 dh = self._conv_back(k, x_in, dh, self.grids[lv], mask, out_bf16=part == "b")
             cup = dh.shape[1] - self.channels[lv]
-            # skip part: gradient w.r.t. enc{lv}b output (masked later with the encoder)
-            ds = torch.empty((self.P[lv], self.channels[lv]), dtype=torch.float32, device=self.dev)
-            ds.zero_()
-            sur_add_channels(dh, dh.shape[1], cup, self.channels[lv], self.P[lv], ds)
-            dskip[lv] = ds
+            # skip part: gradient w.r.t. enc{lv}b output, channels cup .. of dh
+            # (added and masked later with the encoder's pooled path)
+            dskip[lv] = (dh, dh.shape[1], cup)
             # upsampled part: gradient w.r.t. the lower level's output
             du = torch.empty((self.P[lv + 1], cup), dtype=torch.float32, device=self.dev)
             sur_upsample2_bwd(dh, dh.shape[1], 0, cup, self.grids[lv + 1], du)
@@ -388,12 +392,13 @@ class UNet:
             dh = du
         for lv in range(nlev - 1, -1, -1):
             if lv < nlev - 1:
-                # gradient w.r.t. enc{lv}b output = pooled path + skip path
-                dfull = torch.zeros((self.P[lv], self.channels[lv]), dtype=torch.float32,
+                # gradient w.r.t. enc{lv}b output = pooled path + skip path,
+                # through its ReLU (one pass)
+                dfull = torch.empty((self.P[lv], self.channels[lv]), dtype=torch.float32,
                                     device=self.dev)
-                sur_pool2_bwd(dh, self.channels[lv], self.grids[lv], dfull)
-                sur_add_channels(dskip[lv], self.channels[lv], 0, self.channels[lv], self.P[lv], dfull)
-                sur_relu_mask(dfull, self.act[f"enc{lv}b"])
+                skip, sstride, soff = dskip[lv]
+                sur_pool2_bwd_skip(dh, self.channels[lv], self.grids[lv], skip, sstride, soff,
+                                   self.act[f"enc{lv}b"], dfull)
                 dh = dfull
             for part in "ba":
                 k -= 1

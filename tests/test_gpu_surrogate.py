@@ -155,6 +155,19 @@ def test_grid_layers(sur, c):
     g = _f32(dy[:, :c])
     sur.sur_relu_mask(g, _bits(x.reshape(-1, c)))
     assert np.array_equal(g.cpu().numpy(), dy[:, :c] * (x.reshape(-1, c) > 0))
+    # the fused encoder gradient: pooled path + skip columns c .. 2c of dy,
+    # through the ReLU of x; bitwise the same as the four separate passes
+    fused = torch.empty((P, c), dtype=torch.float32, device="cuda")
+    sur.sur_pool2_bwd_skip(_f32(dy[:P // 8, :c]), c, (nx, ny, nz), _f32(dy), cs, c,
+                           _bits(x.reshape(-1, c)), fused)
+    sep = torch.zeros((P, c), dtype=torch.float32, device="cuda")
+    sur.sur_pool2_bwd(_f32(dy[:P // 8, :c]), c, (nx, ny, nz), sep)
+    sur.sur_add_channels(_f32(dy), cs, c, c, P, sep)
+    sur.sur_relu_mask(sep, _bits(x.reshape(-1, c)))
+    assert np.array_equal(fused.cpu().numpy(), sep.cpu().numpy())
+    ref = (so.pool2_bwd(dy[:P // 8, :c].reshape(nz // 2, ny // 2, nx // 2, c).astype(np.float64))
+           .reshape(P, c) + dy[:, c:2 * c]) * (x.reshape(-1, c) > 0)
+    assert np.abs(fused.cpu().numpy() - ref).max() < 1e-6
 
 
 def test_loss_and_adam(sur):
