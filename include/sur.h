@@ -66,13 +66,20 @@ int sur_pool2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void
 int sur_pool2_bwd(const float *dy, int32_t c, int32_t nx, int32_t ny, int32_t nz, float *dx,
                   void *stream);
 /* The gradient at an encoder output that feeds both the 2x2x2 pooling and
- * the skip connection, through its ReLU, in one pass (fine grid sizes; dx
- * [P][c] overwritten): dx[p][c'] = act[p][c'] > 0 ? dy[parent(p)][c'] / 8 +
- * skip[p][skip_off + c'] : 0, dy FP32 on the coarse grid, skip FP32
- * [P][skip_stride], act BF16 [P][c]. */
+ * the skip connection, through its ReLU, in one pass (fine grid sizes):
+ * dx[p][c'] = act[p][c'] > 0 ? dy[parent(p)][c'] / 8 + skip[p][skip_off + c']
+ * : 0, dy FP32 on the coarse grid, skip FP32 [P][skip_stride], act BF16
+ * [P][c]; written to FP32 dx and/or BF16 dx_bf16 [P][c] (either may be NULL,
+ * not both). */
 int sur_pool2_bwd_skip(const float *dy, int32_t c, int32_t nx, int32_t ny, int32_t nz,
                        const float *skip, int32_t skip_stride, int32_t skip_off, const void *act,
-                       float *dx, void *stream);
+                       float *dx, void *dx_bf16, void *stream);
+/* sur_upsample2_bwd through the ReLU of the coarse activation act (BF16
+ * [P_coarse][c]), rounded to BF16: dx_bf16[q][c'] = bf16(act[q][c'] > 0 ?
+ * sum over the 8 fine children p of dy[p][dyoff + c'] : 0) (coarse sizes). */
+int sur_upsample2_bwd_mask(const float *dy, int32_t dystride, int32_t dyoff, int32_t c,
+                           int32_t nx, int32_t ny, int32_t nz, const void *act, void *dx_bf16,
+                           void *stream);
 /* Nearest 2x upsampling of BF16 x [P_coarse][c] (coarse sizes) into channels
  * [yoff, yoff + c) of BF16 y [P_fine][ystride]. */
 int sur_upsample2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void *y,

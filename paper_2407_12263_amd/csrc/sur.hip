@@ -800,10 +800,12 @@ __global__ void copy_channels_v8_kernel(const uint16_t *__restrict__ x, int c, l
 // Gradient at an encoder output that feeds both the pooling and the skip
 // connection, masked by its ReLU: dx[p][ch] = act > 0 ? dy[parent(p)][ch] / 8
 // + skip[p][soff + ch] : 0, in one pass (the same two additions as zero,
-// pool2_bwd, add_channels and relu_mask in turn).
+// pool2_bwd, add_channels and relu_mask in turn), into FP32 dx and/or BF16
+// dxb (the rounding to_bf16 would apply).
 __global__ void pool2_bwd_skip_kernel(const float *__restrict__ dy, int c, int nx, int ny, int nz,
                                       const float *__restrict__ skip, int sstride, int soff,
-                                      const uint16_t *__restrict__ act, float *__restrict__ dx) {
+                                      const uint16_t *__restrict__ act, float *__restrict__ dx,
+                                      uint16_t *__restrict__ dxb) {
     const long n = (long)nx * ny * nz * c;
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
@@ -816,7 +818,34 @@ __global__ void pool2_bwd_skip_kernel(const float *__restrict__ dy, int c, int n
         const long qq = (X / 2) + (long)(nx / 2) * ((Y / 2) + (long)(ny / 2) * (Z / 2));
         v = 0.125f * dy[qq * c + ch] + skip[p * sstride + soff + ch];
     }
-    dx[e] = v;
+    if (dx) dx[e] = v;
+    if (dxb) dxb[e] = f2bf(v);
+}
+
+// Upsampling backward through the ReLU of the coarse activation, into BF16:
+// dxb[q][ch] = bf16(act[q][ch] > 0 ? sum of the 8 children : 0) (the same sum
+// as upsample2_bwd, then relu_mask and to_bf16).
+__global__ void upsample2_bwd_mask_kernel(const float *__restrict__ dy, int dystride, int dyoff,
+                                          int c, int nx, int ny, int nz,
+                                          const uint16_t *__restrict__ act,
+                                          uint16_t *__restrict__ dxb) {
+    const long n = (long)nx * ny * nz * c;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float s = 0.f;
+    if (bf2f(act[e]) > 0.f) {
+        const int ch = mod32(e, c);
+        const long qq = div32(e, c);
+        int X, Y, Z;
+        coords(qq, nx, ny, X, Y, Z);
+        const int fx = 2 * nx, fy = 2 * ny;
+        for (int k = 0; k < 8; ++k) {
+            const long p = (2 * X + (k & 1)) +
+                           (long)fx * ((2 * Y + ((k >> 1) & 1)) + (long)fy * (2 * Z + (k >> 2)));
+            s += dy[p * dystride + dyoff + ch];
+        }
+    }
+    dxb[e] = f2bf(s);
 }
 
 __global__ void add_channels_kernel(const float *__restrict__ dy, int dystride, int dyoff, int c,
@@ -1396,14 +1425,27 @@ int sur_pool2_bwd(const float *dy, int32_t c, int32_t nx, int32_t ny, int32_t nz
 
 int sur_pool2_bwd_skip(const float *dy, int32_t c, int32_t nx, int32_t ny, int32_t nz,
                        const float *skip, int32_t skip_stride, int32_t skip_off, const void *act,
-                       float *dx, void *stream) {
-    if (!dy || !skip || !act || !dx || c <= 0 || !dims_ok(nx, ny, nz) || nx % 2 || ny % 2 ||
+                       float *dx, void *dx_bf16, void *stream) {
+    if (!dy || !skip || !act || (!dx && !dx_bf16) || c <= 0 || !dims_ok(nx, ny, nz) || nx % 2 || ny % 2 ||
         nz % 2 || skip_off < 0 || skip_off + c > skip_stride ||
         !elems_ok((long)nx * ny * nz, skip_stride))
         return SUR_EINVAL;
     const long n = (long)nx * ny * nz * c;
     hipLaunchKernelGGL(pool2_bwd_skip_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, dy, c,
-                       nx, ny, nz, skip, skip_stride, skip_off, (const uint16_t *)act, dx);
+                       nx, ny, nz, skip, skip_stride, skip_off, (const uint16_t *)act, dx,
+                       (uint16_t *)dx_bf16);
+    return launched();
+}
+
+int sur_upsample2_bwd_mask(const float *dy, int32_t dystride, int32_t dyoff, int32_t c,
+                           int32_t nx, int32_t ny, int32_t nz, const void *act, void *dx_bf16,
+                           void *stream) {
+    if (!dy || !act || !dx_bf16 || c <= 0 || !dims_ok(nx, ny, nz) || dyoff < 0 ||
+        dyoff + c > dystride || !elems_ok(8L * nx * ny * nz, dystride))
+        return SUR_EINVAL;
+    const long n = (long)nx * ny * nz * c;
+    hipLaunchKernelGGL(upsample2_bwd_mask_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, dy,
+                       dystride, dyoff, c, nx, ny, nz, (const uint16_t *)act, (uint16_t *)dx_bf16);
     return launched();
 }
 

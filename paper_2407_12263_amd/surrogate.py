@@ -45,7 +45,8 @@ def load_library(path: str | None = None):
     lib.sur_pack_weights.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.sur_pool2.argtypes = [vp, i32, i32, i32, i32, vp, vp]
     lib.sur_pool2_bwd.argtypes = [vp, i32, i32, i32, i32, vp, vp]
-    lib.sur_pool2_bwd_skip.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, vp, vp, vp]
+    lib.sur_pool2_bwd_skip.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, vp, vp, vp, vp]
+    lib.sur_upsample2_bwd_mask.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp, vp]
     lib.sur_upsample2.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, vp]
     lib.sur_upsample2_bwd.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp]
     lib.sur_copy_channels.argtypes = [vp, i32, i64, vp, i32, i32, vp]
@@ -67,7 +68,7 @@ def load_library(path: str | None = None):
     for n in ["sur_features", "sur_prolong_update", "sur_apply_residual", "sur_residual_target", "sur_fix_mass", "sur_conv3d", "sur_conv3d_wgrad", "sur_pack_weights", "sur_pool2", "sur_pool2_bwd",
               "sur_upsample2", "sur_upsample2_bwd", "sur_copy_channels", "sur_add_channels",
               "sur_to_bf16", "sur_relu_mask", "sur_mse", "sur_adam", "sur_coarsen",
-              "sur_prolong_add", "sur_checks"]:
+              "sur_prolong_add", "sur_checks", "sur_pool2_bwd_skip", "sur_upsample2_bwd_mask"]:
         getattr(lib, n).restype = C.c_int
     if path is None:
         _lib = lib
@@ -120,9 +121,15 @@ def sur_pool2_bwd(dy, c, grid, dx):
     _ok(load_library().sur_pool2_bwd(_p(dy), c, *grid, _p(dx), _stream()), "sur_pool2_bwd")
 
 
-def sur_pool2_bwd_skip(dy, c, grid, skip, skip_stride, skip_off, act, dx):
+def sur_pool2_bwd_skip(dy, c, grid, skip, skip_stride, skip_off, act, dx=None, dx_bf16=None):
     _ok(load_library().sur_pool2_bwd_skip(_p(dy), c, *grid, _p(skip), skip_stride, skip_off,
-                                          _p(act), _p(dx), _stream()), "sur_pool2_bwd_skip")
+                                          _p(act), _p(dx), _p(dx_bf16), _stream()),
+        "sur_pool2_bwd_skip")
+
+
+def sur_upsample2_bwd_mask(dy, dystride, dyoff, c, grid, act, dx_bf16):
+    _ok(load_library().sur_upsample2_bwd_mask(_p(dy), dystride, dyoff, c, *grid, _p(act),
+                                              _p(dx_bf16), _stream()), "sur_upsample2_bwd_mask")
 
 
 def sur_upsample2(x, c, grid, y, ystride, yoff):
@@ -383,22 +390,22 @@ class UNet:
             # skip part: gradient w.r.t. enc{lv}b output, channels cup .. of dh
             # (added and masked later with the encoder's pooled path)
             dskip[lv] = (dh, dh.shape[1], cup)
-            # upsampled part: gradient w.r.t. the lower level's output
-            du = torch.empty((self.P[lv + 1], cup), dtype=torch.float32, device=self.dev)
-            sur_upsample2_bwd(dh, dh.shape[1], 0, cup, self.grids[lv + 1], du)
-            # that output is a ReLU activation (bottom or decoder b of lv + 1)
+            # upsampled part: gradient w.r.t. the lower level's output, a ReLU
+            # activation (bottom or decoder b of lv + 1); BF16, it only feeds
+            # that layer's backward
             below = f"enc{lv + 1}b" if lv + 1 == nlev - 1 else f"dec{lv + 1}b"
-            sur_relu_mask(du, self.act[below])
+            du = torch.empty((self.P[lv + 1], cup), dtype=torch.int16, device=self.dev)
+            sur_upsample2_bwd_mask(dh, dh.shape[1], 0, cup, self.grids[lv + 1], self.act[below], du)
             dh = du
         for lv in range(nlev - 1, -1, -1):
             if lv < nlev - 1:
                 # gradient w.r.t. enc{lv}b output = pooled path + skip path,
                 # through its ReLU (one pass)
-                dfull = torch.empty((self.P[lv], self.channels[lv]), dtype=torch.float32,
+                dfull = torch.empty((self.P[lv], self.channels[lv]), dtype=torch.int16,
                                     device=self.dev)
                 skip, sstride, soff = dskip[lv]
                 sur_pool2_bwd_skip(dh, self.channels[lv], self.grids[lv], skip, sstride, soff,
-                                   self.act[f"enc{lv}b"], dfull)
+                                   self.act[f"enc{lv}b"], dx_bf16=dfull)
                 dh = dfull
             for part in "ba":
                 k -= 1

@@ -158,8 +158,9 @@ def test_grid_layers(sur, c):
     # the fused encoder gradient: pooled path + skip columns c .. 2c of dy,
     # through the ReLU of x; bitwise the same as the four separate passes
     fused = torch.empty((P, c), dtype=torch.float32, device="cuda")
+    fused_b = torch.empty((P, c), dtype=torch.int16, device="cuda")
     sur.sur_pool2_bwd_skip(_f32(dy[:P // 8, :c]), c, (nx, ny, nz), _f32(dy), cs, c,
-                           _bits(x.reshape(-1, c)), fused)
+                           _bits(x.reshape(-1, c)), dx=fused, dx_bf16=fused_b)
     sep = torch.zeros((P, c), dtype=torch.float32, device="cuda")
     sur.sur_pool2_bwd(_f32(dy[:P // 8, :c]), c, (nx, ny, nz), sep)
     sur.sur_add_channels(_f32(dy), cs, c, c, P, sep)
@@ -168,6 +169,20 @@ def test_grid_layers(sur, c):
     ref = (so.pool2_bwd(dy[:P // 8, :c].reshape(nz // 2, ny // 2, nx // 2, c).astype(np.float64))
            .reshape(P, c) + dy[:, c:2 * c]) * (x.reshape(-1, c) > 0)
     assert np.abs(fused.cpu().numpy() - ref).max() < 1e-6
+    sb = torch.empty((P, c), dtype=torch.int16, device="cuda")
+    sur.sur_to_bf16(sep, sb)
+    assert torch.equal(fused_b, sb)
+    # upsampling backward through the coarse ReLU, into BF16: the same as
+    # upsample2_bwd, relu_mask and to_bf16 in turn
+    actc = xc.reshape(-1, c)
+    um = torch.empty((P // 8, c), dtype=torch.int16, device="cuda")
+    sur.sur_upsample2_bwd_mask(_f32(dy), cs, c, c, (nx // 2, ny // 2, nz // 2), _bits(actc), um)
+    us = torch.empty((P // 8, c), dtype=torch.float32, device="cuda")
+    sur.sur_upsample2_bwd(_f32(dy), cs, c, c, (nx // 2, ny // 2, nz // 2), us)
+    sur.sur_relu_mask(us, _bits(actc))
+    ub = torch.empty((P // 8, c), dtype=torch.int16, device="cuda")
+    sur.sur_to_bf16(us, ub)
+    assert torch.equal(um, ub)
 
 
 def test_loss_and_adam(sur):
