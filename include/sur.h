@@ -101,10 +101,12 @@ int sur_relu_mask(float *dx, const void *act, int64_t n, void *stream);
 
 /* Residual MSE on the first cu channels of FP32 pred/target [P][cs]:
  * L = sum_p sum_c wch[c] (pred - target)^2 / (P cu); grad = dL/dpred
- * ([P][cs], channels >= cu zero). loss_out: one double (device), written
- * after an FP64 reduction in fixed order; scratch >= (P/256 + 1) doubles. */
+ * ([P][cs], channels >= cu zero) in FP32 grad and/or BF16 grad_bf16 (either
+ * may be NULL, not both). loss_out: one double (device), written after an
+ * FP64 reduction in fixed order; scratch >= (P/256 + 1) doubles. */
 int sur_mse(const float *pred, const float *target, int32_t cu, int32_t cs, int64_t P,
-            const float *wch, float *grad, double *scratch, double *loss_out, void *stream);
+            const float *wch, float *grad, void *grad_bf16, double *scratch, double *loss_out,
+            void *stream);
 
 /* Adam step t >= 1 (Kingma & Ba, bias-corrected) on n FP32 weights. */
 int sur_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float beta1,

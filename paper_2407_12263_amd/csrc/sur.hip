@@ -871,6 +871,7 @@ __global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ pred
                                                   const float *__restrict__ tgt, int cu, int cs,
                                                   long P, const float *__restrict__ wch,
                                                   float *__restrict__ grad,
+                                                  uint16_t *__restrict__ gradb,
                                                   double *__restrict__ part, int vec4) {
     __shared__ double red[4];
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -880,10 +881,12 @@ __global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ pred
         if (vec4) {
             // 16-byte accesses, four channels at a time (same arithmetic)
             const float4 *p4 = (const float4 *)(pred + p * cs), *t4 = (const float4 *)(tgt + p * cs);
-            float4 *g4 = (float4 *)(grad + p * cs);
+            float4 *g4 = grad ? (float4 *)(grad + p * cs) : nullptr;
+            uint2 *b4 = gradb ? (uint2 *)(gradb + p * cs) : nullptr;
             for (int c4 = 0; c4 < cs / 4; ++c4) {
                 if (4 * c4 >= cu) {  // padding channels: no loss, zero gradient
-                    g4[c4] = float4{0.f, 0.f, 0.f, 0.f};
+                    if (g4) g4[c4] = float4{0.f, 0.f, 0.f, 0.f};
+                    if (b4) b4[c4] = uint2{0u, 0u};
                     continue;
                 }
                 const float4 a = p4[c4], b = t4[c4];
@@ -899,7 +902,10 @@ __global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ pred
                         gg[k] = 2.f * wch[ch] * d * inv;
                     }
                 }
-                g4[c4] = float4{gg[0], gg[1], gg[2], gg[3]};
+                if (g4) g4[c4] = float4{gg[0], gg[1], gg[2], gg[3]};
+                if (b4)
+                    b4[c4] = uint2{uint32_t(f2bf(gg[0])) | (uint32_t(f2bf(gg[1])) << 16),
+                                   uint32_t(f2bf(gg[2])) | (uint32_t(f2bf(gg[3])) << 16)};
             }
         } else {
             for (int ch = 0; ch < cs; ++ch) {
@@ -909,7 +915,8 @@ __global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ pred
                     l += (double)wch[ch] * d * d;
                     g = 2.f * wch[ch] * d * inv;
                 }
-                grad[p * cs + ch] = g;
+                if (grad) grad[p * cs + ch] = g;
+                if (gradb) gradb[p * cs + ch] = f2bf(g);
             }
         }
     }
@@ -1518,15 +1525,17 @@ int sur_relu_mask(float *dx, const void *act, int64_t n, void *stream) {
 }
 
 int sur_mse(const float *pred, const float *target, int32_t cu, int32_t cs, int64_t P,
-            const float *wch, float *grad, double *scratch, double *loss_out, void *stream) {
-    if (!pred || !target || !wch || !grad || !scratch || !loss_out || cu <= 0 || cs < cu || P <= 0)
+            const float *wch, float *grad, void *grad_bf16, double *scratch, double *loss_out,
+            void *stream) {
+    if (!pred || !target || !wch || (!grad && !grad_bf16) || !scratch || !loss_out || cu <= 0 ||
+        cs < cu || P <= 0)
         return SUR_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const long nb = grid1(P).x;
     const int vec4 = cs % 4 == 0 && ((uintptr_t)pred & 15) == 0 && ((uintptr_t)target & 15) == 0 &&
-                     ((uintptr_t)grad & 15) == 0;
+                     ((uintptr_t)grad & 15) == 0 && ((uintptr_t)grad_bf16 & 7) == 0;
     hipLaunchKernelGGL(mse_kernel, dim3((unsigned)nb), dim3(256), 0, s, pred, target, cu, cs,
-                       (long)P, wch, grad, scratch, vec4);
+                       (long)P, wch, grad, (uint16_t *)grad_bf16, scratch, vec4);
     hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(1024), 0, s, (const double *)scratch, nb,
                        1.0 / ((double)P * cu), loss_out);
     return launched();

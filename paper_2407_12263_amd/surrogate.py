@@ -53,7 +53,7 @@ def load_library(path: str | None = None):
     lib.sur_add_channels.argtypes = [vp, i32, i32, i32, i64, vp, vp]
     lib.sur_to_bf16.argtypes = [vp, i64, vp, vp]
     lib.sur_relu_mask.argtypes = [vp, vp, i64, vp]
-    lib.sur_mse.argtypes = [vp, vp, i32, i32, i64, vp, vp, vp, vp, vp]
+    lib.sur_mse.argtypes = [vp, vp, i32, i32, i64, vp, vp, vp, vp, vp, vp]
     lib.sur_adam.argtypes = [vp, vp, vp, vp, i64, fl, fl, fl, fl, i32, vp]
     lib.sur_coarsen.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, vp]
     lib.sur_prolong_add.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
@@ -160,9 +160,9 @@ def sur_relu_mask(dx, act):
     _ok(load_library().sur_relu_mask(_p(dx), _p(act), dx.numel(), _stream()), "sur_relu_mask")
 
 
-def sur_mse(pred, target, cu, cs, P, wch, grad, scratch, loss_out):
-    _ok(load_library().sur_mse(_p(pred), _p(target), cu, cs, P, _p(wch), _p(grad), _p(scratch),
-                               _p(loss_out), _stream()), "sur_mse")
+def sur_mse(pred, target, cu, cs, P, wch, grad, scratch, loss_out, grad_bf16=None):
+    _ok(load_library().sur_mse(_p(pred), _p(target), cu, cs, P, _p(wch), _p(grad), _p(grad_bf16),
+                               _p(scratch), _p(loss_out), _stream()), "sur_mse")
 
 
 def sur_adam(w, m, v, g, lr, b1, b2, eps, t):
@@ -294,7 +294,8 @@ class UNet:
         self.scratch = torch.empty(sc, dtype=torch.float32, device=self.dev)
         self.loss_scratch = torch.empty(self.P[0] // 256 + 2, dtype=torch.float64, device=self.dev)
         self.loss_dev = torch.zeros(1, dtype=torch.float64, device=self.dev)
-        self.dout = f32(self.P[0], NCH)
+        # the loss gradient only feeds the output layer's backward: BF16
+        self.dout = torch.empty((self.P[0], NCH), dtype=torch.int16, device=self.dev)
 
     @staticmethod
     def _level(name):
@@ -421,8 +422,8 @@ class UNet:
 
     def loss_and_grad(self, target_f32, wch):
         """Residual MSE on the used channels; gradient into self.dout."""
-        sur_mse(self.out, target_f32, NUSE, NCH, self.P[0], wch, self.dout, self.loss_scratch,
-                self.loss_dev)
+        sur_mse(self.out, target_f32, NUSE, NCH, self.P[0], wch, None, self.loss_scratch,
+                self.loss_dev, grad_bf16=self.dout)
         return self.loss_dev
 
     def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

@@ -201,6 +201,12 @@ def test_loss_and_adam(sur):
                     tgt.reshape(P, 1, 1, 16).astype(np.float64), wch.astype(np.float64))
     assert abs(float(loss.item()) - rl) < 1e-6 * rl
     assert np.abs(grad.cpu().numpy() - rg.reshape(P, 16)).max() < 1e-7
+    # the BF16 gradient is the rounding of the FP32 one (both outputs at once)
+    gb = torch.empty((P, 16), dtype=torch.int16, device="cuda")
+    sur.sur_mse(_f32(pred), _f32(tgt), 5, 16, P, _f32(wch), grad, scratch, loss, grad_bf16=gb)
+    gr = torch.empty((P, 16), dtype=torch.int16, device="cuda")
+    sur.sur_to_bf16(grad, gr)
+    assert torch.equal(gb, gr)
     w0 = rng.standard_normal(1000).astype(np.float32)
     g = rng.standard_normal(1000).astype(np.float32)
     w, m, v = _f32(w0), torch.zeros(1000, device="cuda"), torch.zeros(1000, device="cuda")
