@@ -822,6 +822,36 @@ __global__ void pool2_bwd_skip_kernel(const float *__restrict__ dy, int c, int n
     if (dxb) dxb[e] = f2bf(v);
 }
 
+// The same four channels per thread (c, sstride, soff multiples of 4, 16-byte
+// aligned FP32 rows): 16-byte loads of dy and skip, 8-byte act loads and
+// BF16 stores; the same arithmetic per element.
+__global__ void pool2_bwd_skip4_kernel(const float4 *__restrict__ dy, int c, int nx, int ny, int nz,
+                                       const float4 *__restrict__ skip, int sstride, int soff,
+                                       const uint2 *__restrict__ act, float4 *__restrict__ dx,
+                                       uint2 *__restrict__ dxb) {
+    const int c4 = c / 4;
+    const long n4 = (long)nx * ny * nz * c4;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n4) return;
+    const int ch4 = mod32(e, c4);
+    const long p = div32(e, c4);
+    int X, Y, Z;
+    coords(p, nx, ny, X, Y, Z);
+    const long qq = (X / 2) + (long)(nx / 2) * ((Y / 2) + (long)(ny / 2) * (Z / 2));
+    const float4 d = dy[qq * c4 + ch4];
+    const float4 k = skip[(p * sstride + soff) / 4 + ch4];
+    const uint2 a = act[e];
+    const float dd[4] = {d.x, d.y, d.z, d.w}, kk[4] = {k.x, k.y, k.z, k.w};
+    const uint16_t aa[4] = {uint16_t(a.x), uint16_t(a.x >> 16), uint16_t(a.y), uint16_t(a.y >> 16)};
+    float v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = bf2f(aa[j]) > 0.f ? 0.125f * dd[j] + kk[j] : 0.f;
+    if (dx) dx[e] = float4{v[0], v[1], v[2], v[3]};
+    if (dxb)
+        dxb[e] = uint2{uint32_t(f2bf(v[0])) | (uint32_t(f2bf(v[1])) << 16),
+                       uint32_t(f2bf(v[2])) | (uint32_t(f2bf(v[3])) << 16)};
+}
+
 // Upsampling backward through the ReLU of the coarse activation, into BF16:
 // dxb[q][ch] = bf16(act[q][ch] > 0 ? sum of the 8 children : 0) (the same sum
 // as upsample2_bwd, then relu_mask and to_bf16).
@@ -846,6 +876,42 @@ __global__ void upsample2_bwd_mask_kernel(const float *__restrict__ dy, int dyst
         }
     }
     dxb[e] = f2bf(s);
+}
+
+// The same four channels per thread (c, dystride, dyoff multiples of 4,
+// 16-byte aligned FP32 rows); the children are added in the same order.
+__global__ void upsample2_bwd_mask4_kernel(const float4 *__restrict__ dy, int dystride, int dyoff,
+                                           int c, int nx, int ny, int nz,
+                                           const uint2 *__restrict__ act,
+                                           uint2 *__restrict__ dxb) {
+    const int c4 = c / 4;
+    const long n4 = (long)nx * ny * nz * c4;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n4) return;
+    const uint2 a = act[e];
+    const uint16_t aa[4] = {uint16_t(a.x), uint16_t(a.x >> 16), uint16_t(a.y), uint16_t(a.y >> 16)};
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+    if (bf2f(aa[0]) > 0.f || bf2f(aa[1]) > 0.f || bf2f(aa[2]) > 0.f || bf2f(aa[3]) > 0.f) {
+        const int ch4 = mod32(e, c4);
+        const long qq = div32(e, c4);
+        int X, Y, Z;
+        coords(qq, nx, ny, X, Y, Z);
+        const int fx = 2 * nx, fy = 2 * ny;
+        for (int k = 0; k < 8; ++k) {
+            const long p = (2 * X + (k & 1)) +
+                           (long)fx * ((2 * Y + ((k >> 1) & 1)) + (long)fy * (2 * Z + (k >> 2)));
+            const float4 v = dy[(p * dystride + dyoff) / 4 + ch4];
+            s[0] += v.x;
+            s[1] += v.y;
+            s[2] += v.z;
+            s[3] += v.w;
+        }
+    }
+    float o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = bf2f(aa[j]) > 0.f ? s[j] : 0.f;
+    dxb[e] = uint2{uint32_t(f2bf(o[0])) | (uint32_t(f2bf(o[1])) << 16),
+                   uint32_t(f2bf(o[2])) | (uint32_t(f2bf(o[3])) << 16)};
 }
 
 __global__ void add_channels_kernel(const float *__restrict__ dy, int dystride, int dyoff, int c,
@@ -1438,9 +1504,17 @@ int sur_pool2_bwd_skip(const float *dy, int32_t c, int32_t nx, int32_t ny, int32
         !elems_ok((long)nx * ny * nz, skip_stride))
         return SUR_EINVAL;
     const long n = (long)nx * ny * nz * c;
-    hipLaunchKernelGGL(pool2_bwd_skip_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, dy, c,
-                       nx, ny, nz, skip, skip_stride, skip_off, (const uint16_t *)act, dx,
-                       (uint16_t *)dx_bf16);
+    const bool v4 = c % 4 == 0 && skip_stride % 4 == 0 && skip_off % 4 == 0 && aligned16(dy) &&
+                    aligned16(skip) && ((uintptr_t)act & 7) == 0 && (!dx || aligned16(dx)) &&
+                    ((uintptr_t)dx_bf16 & 7) == 0;
+    if (v4)
+        hipLaunchKernelGGL(pool2_bwd_skip4_kernel, grid1(n / 4), dim3(256), 0, (hipStream_t)stream,
+                           (const float4 *)dy, c, nx, ny, nz, (const float4 *)skip, skip_stride,
+                           skip_off, (const uint2 *)act, (float4 *)dx, (uint2 *)dx_bf16);
+    else
+        hipLaunchKernelGGL(pool2_bwd_skip_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, dy,
+                           c, nx, ny, nz, skip, skip_stride, skip_off, (const uint16_t *)act, dx,
+                           (uint16_t *)dx_bf16);
     return launched();
 }
 
@@ -1451,8 +1525,16 @@ int sur_upsample2_bwd_mask(const float *dy, int32_t dystride, int32_t dyoff, int
         dyoff + c > dystride || !elems_ok(8L * nx * ny * nz, dystride))
         return SUR_EINVAL;
     const long n = (long)nx * ny * nz * c;
-    hipLaunchKernelGGL(upsample2_bwd_mask_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, dy,
-                       dystride, dyoff, c, nx, ny, nz, (const uint16_t *)act, (uint16_t *)dx_bf16);
+    const bool v4 = c % 4 == 0 && dystride % 4 == 0 && dyoff % 4 == 0 && aligned16(dy) &&
+                    ((uintptr_t)act & 7) == 0 && ((uintptr_t)dx_bf16 & 7) == 0;
+    if (v4)
+        hipLaunchKernelGGL(upsample2_bwd_mask4_kernel, grid1(n / 4), dim3(256), 0,
+                           (hipStream_t)stream, (const float4 *)dy, dystride, dyoff, c, nx, ny, nz,
+                           (const uint2 *)act, (uint2 *)dx_bf16);
+    else
+        hipLaunchKernelGGL(upsample2_bwd_mask_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream,
+                           dy, dystride, dyoff, c, nx, ny, nz, (const uint16_t *)act,
+                           (uint16_t *)dx_bf16);
     return launched();
 }
 

@@ -122,7 +122,7 @@ def test_conv_weight_gradient(sur, cin, cout, grid):
     assert np.abs(db.cpu().numpy() - rdb).max() <= 1e-5 * (1 + np.abs(rdb).max()) * np.sqrt(P)
 
 
-@pytest.mark.parametrize("c", [16, 12])  # 16-byte kernels (c, strides, offsets % 8 == 0) / per element
+@pytest.mark.parametrize("c", [16, 12, 6])  # 16-byte (c % 8 == 0), 4-channel (c % 4 == 0), per element
 def test_grid_layers(sur, c):
     import torch
     say(f"[sur] pool / upsample / concat / masks, {c} channels")
