@@ -572,12 +572,11 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
 // A block sums 32 consecutive elements; its 8 thread groups take the chunks
 // g, g + 8, g + 16, ... in order and are combined in group order (fixed
 // order, so the result does not depend on scheduling).
-__global__ void __launch_bounds__(256) sum_chunks_kernel(const float *__restrict__ part,
-                                                         long nchunks, long n,
-                                                         float *__restrict__ out) {
+__device__ __forceinline__ void sum_chunks_block(const float *__restrict__ part, long nchunks,
+                                                 long n, float *__restrict__ out, long blk) {
     __shared__ float red[8][32];
     const int el = threadIdx.x & 31, g = threadIdx.x >> 5;
-    const long e = (long)blockIdx.x * 32 + el;
+    const long e = blk * 32 + el;
     float s = 0.f;
     if (e < n)
         for (long c = g; c < nchunks; c += 8) s += part[c * n + e];
@@ -589,6 +588,25 @@ __global__ void __launch_bounds__(256) sum_chunks_kernel(const float *__restrict
         for (int k = 1; k < 8; ++k) t += red[k][el];
         out[e] = t;
     }
+}
+
+__global__ void __launch_bounds__(256) sum_chunks_kernel(const float *__restrict__ part,
+                                                         long nchunks, long n,
+                                                         float *__restrict__ out) {
+    sum_chunks_block(part, nchunks, n, out, blockIdx.x);
+}
+
+// Two independent sums of the same kind in one launch: blocks [0, nblk_a)
+// reduce (part_a, rows_a, n_a) into out_a, the rest (part_b, ...) into out_b.
+__global__ void __launch_bounds__(256) sum_chunks2_kernel(const float *__restrict__ part_a,
+                                                          long rows_a, long n_a,
+                                                          float *__restrict__ out_a, long nblk_a,
+                                                          const float *__restrict__ part_b,
+                                                          long rows_b, long n_b,
+                                                          float *__restrict__ out_b) {
+    const long b = blockIdx.x;
+    if (b < nblk_a) sum_chunks_block(part_a, rows_a, n_a, out_a, b);
+    else sum_chunks_block(part_b, rows_b, n_b, out_b, b - nblk_a);
 }
 
 // Per-block partial sums of dy over points for each channel: thread
@@ -1410,6 +1428,7 @@ int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, i
     long nch;  // partial sums in scratch
     const long n = 27L * cin * cout;
     bool bias_done = false;
+    float *tiled_bp = nullptr;  // bias partials of the tiled kernel, summed with dw's last pass
     if (wgrad_tiled_ok(x, cin, dy, cout, nx, ny, nz)) {
         nch = wgrad_tiled_blocks(cin, P);
         const dim3 grid((unsigned)nch, (unsigned)(cin / 16));
@@ -1421,8 +1440,7 @@ int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, i
             case 3: hipLaunchKernelGGL(wgrad_tiled_kernel<3>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, scratch, bp); break;
             default: hipLaunchKernelGGL(wgrad_tiled_kernel<4>, grid, dim3(256), 0, s, xb, cin, db, cout, nx, ny, nz, scratch, bp); break;
         }
-        if (dbias)
-            hipLaunchKernelGGL(sum_chunks_kernel, grid1(cout, 32), dim3(256), 0, s, (const float *)bp, nch, (long)cout, dbias);
+        tiled_bp = bp;
         bias_done = true;
     } else {
         nch = wgrad_chunks(P);
@@ -1446,13 +1464,24 @@ int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, i
             const dim3 g1((unsigned)((n4 + 31) / 32), (unsigned)kSumSeg);
             hipLaunchKernelGGL(sum_rows4_kernel, g1, dim3(256), 0, s, (const float4 *)scratch, nch,
                                n4, L, (float4 *)mid);
-            hipLaunchKernelGGL(sum_chunks_kernel, grid1(n, 32), dim3(256), 0, s,
-                               (const float *)mid, (long)kSumSeg, n, dw);
+            if (tiled_bp) {  // dw's last pass and the bias partials in one launch
+                const long na = grid1(n, 32).x;
+                hipLaunchKernelGGL(sum_chunks2_kernel, dim3((unsigned)(na + grid1(cout, 32).x)),
+                                   dim3(256), 0, s, (const float *)mid, (long)kSumSeg, n, dw, na,
+                                   (const float *)tiled_bp, nch, (long)cout, dbias);
+                tiled_bp = nullptr;
+            } else {
+                hipLaunchKernelGGL(sum_chunks_kernel, grid1(n, 32), dim3(256), 0, s,
+                                   (const float *)mid, (long)kSumSeg, n, dw);
+            }
         } else {
             hipLaunchKernelGGL(sum_chunks_kernel, grid1(n, 32), dim3(256), 0, s,
                                (const float *)scratch, nch, n, dw);
         }
     }
+    if (tiled_bp)
+        hipLaunchKernelGGL(sum_chunks_kernel, grid1(cout, 32), dim3(256), 0, s,
+                           (const float *)tiled_bp, nch, (long)cout, dbias);
     if (dbias && !bias_done) {
         const long nb = grid1(P, 1024).x;
         float *bp = scratch + nch * n;
