@@ -88,6 +88,11 @@ int sur_upsample2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, 
  * coarse sizes; dx overwritten). */
 int sur_upsample2_bwd(const float *dy, int32_t dystride, int32_t dyoff, int32_t c, int32_t nx,
                       int32_t ny, int32_t nz, float *dx, void *stream);
+/* The decoder's concat (fine grid sizes): y[p] = [xc[parent(p)][0 .. hc),
+ * xf[p][0 .. fc)], BF16, y [P][hc + fc]: sur_upsample2 and sur_copy_channels
+ * in one pass. */
+int sur_concat_up2(const void *xc, int32_t hc, const void *xf, int32_t fc, int32_t nx, int32_t ny,
+                   int32_t nz, void *y, void *stream);
 /* y[p][yoff + c'] = x[p][c'] for c' < c (BF16 channel copy, for concat). */
 int sur_copy_channels(const void *x, int32_t c, int64_t P, void *y, int32_t ystride,
                       int32_t yoff, void *stream);

@@ -805,6 +805,30 @@ __global__ void upsample2_v8_kernel(const uint16_t *__restrict__ x, int c, int n
     *(uint4 *)(y + p * ystride + yoff + 8 * g) = *(const uint4 *)(x + qq * c + 8 * g);
 }
 
+// The decoder's concat in one pass, 16 bytes per thread: row p of y is the
+// upsampled coarse row (channels 0 .. hc) followed by row p of the skip
+// tensor (channels hc .. hc + fc); every row is written whole, once.
+__global__ void concat_up2_v8_kernel(const uint16_t *__restrict__ xc, int hc,
+                                     const uint16_t *__restrict__ xf, int fc, int nx, int ny,
+                                     int nz, uint16_t *__restrict__ y) {
+    const int g8 = (hc + fc) / 8, h8 = hc / 8;
+    const long n = (long)nx * ny * nz * g8;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int g = mod32(e, g8);
+    const long p = div32(e, g8);
+    uint4 v;
+    if (g < h8) {
+        int X, Y, Z;
+        coords(p, nx, ny, X, Y, Z);
+        const long qq = (X / 2) + (long)(nx / 2) * ((Y / 2) + (long)(ny / 2) * (Z / 2));
+        v = *(const uint4 *)(xc + qq * hc + 8 * g);
+    } else {
+        v = *(const uint4 *)(xf + p * fc + 8 * (g - h8));
+    }
+    *(uint4 *)(y + 8 * e) = v;
+}
+
 __global__ void copy_channels_v8_kernel(const uint16_t *__restrict__ x, int c, long P,
                                         uint16_t *__restrict__ y, int ystride, int yoff) {
     const int c8 = c / 8;
@@ -1592,6 +1616,24 @@ int sur_upsample2_bwd(const float *dy, int32_t dystride, int32_t dyoff, int32_t 
     hipLaunchKernelGGL(upsample2_bwd_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, dy,
                        dystride, dyoff, c, nx, ny, nz, dx);
     return launched();
+}
+
+int sur_concat_up2(const void *xc, int32_t hc, const void *xf, int32_t fc, int32_t nx, int32_t ny,
+                   int32_t nz, void *y, void *stream) {
+    if (!xc || !xf || !y || hc <= 0 || fc <= 0 || !dims_ok(nx, ny, nz) || nx % 2 || ny % 2 ||
+        nz % 2 || !elems_ok((long)nx * ny * nz, hc + fc))
+        return SUR_EINVAL;
+    if (hc % 8 == 0 && fc % 8 == 0 && aligned16(xc) && aligned16(xf) && aligned16(y)) {
+        const long n = (long)nx * ny * nz * ((hc + fc) / 8);
+        hipLaunchKernelGGL(concat_up2_v8_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream,
+                           (const uint16_t *)xc, hc, (const uint16_t *)xf, fc, nx, ny, nz,
+                           (uint16_t *)y);
+        return launched();
+    }
+    // otherwise the two separate passes
+    const int rc = sur_upsample2(xc, hc, nx / 2, ny / 2, nz / 2, y, hc + fc, 0, stream);
+    if (rc != SUR_OK) return rc;
+    return sur_copy_channels(xf, fc, (long)nx * ny * nz, y, hc + fc, hc, stream);
 }
 
 int sur_copy_channels(const void *x, int32_t c, int64_t P, void *y, int32_t ystride, int32_t yoff,

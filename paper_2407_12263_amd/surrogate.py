@@ -47,6 +47,7 @@ def load_library(path: str | None = None):
     lib.sur_pool2_bwd.argtypes = [vp, i32, i32, i32, i32, vp, vp]
     lib.sur_pool2_bwd_skip.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, vp, vp, vp, vp]
     lib.sur_upsample2_bwd_mask.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp, vp]
+    lib.sur_concat_up2.argtypes = [vp, i32, vp, i32, i32, i32, i32, vp, vp]
     lib.sur_upsample2.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, vp]
     lib.sur_upsample2_bwd.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp]
     lib.sur_copy_channels.argtypes = [vp, i32, i64, vp, i32, i32, vp]
@@ -68,7 +69,8 @@ def load_library(path: str | None = None):
     for n in ["sur_features", "sur_prolong_update", "sur_apply_residual", "sur_residual_target", "sur_fix_mass", "sur_conv3d", "sur_conv3d_wgrad", "sur_pack_weights", "sur_pool2", "sur_pool2_bwd",
               "sur_upsample2", "sur_upsample2_bwd", "sur_copy_channels", "sur_add_channels",
               "sur_to_bf16", "sur_relu_mask", "sur_mse", "sur_adam", "sur_coarsen",
-              "sur_prolong_add", "sur_checks", "sur_pool2_bwd_skip", "sur_upsample2_bwd_mask"]:
+              "sur_prolong_add", "sur_checks", "sur_pool2_bwd_skip", "sur_upsample2_bwd_mask",
+              "sur_concat_up2"]:
         getattr(lib, n).restype = C.c_int
     if path is None:
         _lib = lib
@@ -130,6 +132,11 @@ def sur_pool2_bwd_skip(dy, c, grid, skip, skip_stride, skip_off, act, dx=None, d
 def sur_upsample2_bwd_mask(dy, dystride, dyoff, c, grid, act, dx_bf16):
     _ok(load_library().sur_upsample2_bwd_mask(_p(dy), dystride, dyoff, c, *grid, _p(act),
                                               _p(dx_bf16), _stream()), "sur_upsample2_bwd_mask")
+
+
+def sur_concat_up2(xc, hc, xf, fc, grid, y):
+    _ok(load_library().sur_concat_up2(_p(xc), hc, _p(xf), fc, *grid, _p(y), _stream()),
+        "sur_concat_up2")
 
 
 def sur_upsample2(x, c, grid, y, ystride, yoff):
@@ -328,8 +335,7 @@ class UNet:
         for lv in range(self.nlev - 2, -1, -1):
             cat = self.act[f"cat{lv}"]
             ctot = cat.shape[1]
-            sur_upsample2(h, hc, self.grids[lv + 1], cat, ctot, 0)
-            sur_copy_channels(self.act[f"enc{lv}b"], self.channels[lv], self.P[lv], cat, ctot, hc)
+            sur_concat_up2(h, hc, self.act[f"enc{lv}b"], self.channels[lv], self.grids[lv], cat)
             h, hc = cat, ctot
             for part in "ab":
                 name, ci, co, relu = self.layers[k]

@@ -143,6 +143,12 @@ def test_grid_layers(sur, c):
     assert np.array_equal(got[..., :c], so.up2(xc))
     assert np.array_equal(got[..., c:2 * c], x)
     assert not got[..., 2 * c:].any()
+    # the decoder's concat in one pass equals the two passes
+    cat2 = torch.empty((P, 2 * c), dtype=torch.int16, device="cuda")
+    sur.sur_concat_up2(_bits(xc.reshape(-1, c)), c, _bits(x.reshape(-1, c)), c, (nx, ny, nz), cat2)
+    got2 = _from_bits(cat2).reshape(nz, ny, nx, 2 * c)
+    assert np.array_equal(got2[..., :c], so.up2(xc))
+    assert np.array_equal(got2[..., c:], x)
     dy = rng.standard_normal((P, cs)).astype(np.float32)
     du = torch.empty((P // 8, c), dtype=torch.float32, device="cuda")
     sur.sur_upsample2_bwd(_f32(dy), cs, c, c, (nx // 2, ny // 2, nz // 2), du)
