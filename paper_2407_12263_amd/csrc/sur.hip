@@ -618,12 +618,23 @@ __global__ void __launch_bounds__(256) sum_chunks2_kernel(const float *__restric
 // the rows of mid in order. More blocks and wider loads keep more bytes in
 // flight than one pass over all rows.
 constexpr int kSumSeg = 8;
+// Blocks with blockIdx.x >= nblk_a take a second array (part_b, n4_b, mid_b)
+// with the same rows and segments (the bias partials beside the weights').
 __global__ void __launch_bounds__(256) sum_rows4_kernel(const float4 *__restrict__ part,
                                                         long nrows, long n4, int L,
-                                                        float4 *__restrict__ mid) {
+                                                        float4 *__restrict__ mid, long nblk_a,
+                                                        const float4 *__restrict__ part_b,
+                                                        long n4_b, float4 *__restrict__ mid_b) {
     __shared__ float4 red[8][32];
     const int l = threadIdx.x & 31, g = threadIdx.x >> 5;
-    const long e = (long)blockIdx.x * 32 + l;
+    long bx = blockIdx.x;
+    if (bx >= nblk_a) {
+        bx -= nblk_a;
+        part = part_b;
+        n4 = n4_b;
+        mid = mid_b;
+    }
+    const long e = bx * 32 + l;
     const long r0 = (long)blockIdx.y * L, r1 = r0 + L < nrows ? r0 + L : nrows;
     float4 acc = float4{0.f, 0.f, 0.f, 0.f};
     if (e < n4) {
@@ -1435,8 +1446,9 @@ size_t sur_wgrad_scratch_floats(int32_t cin, int32_t cout, int32_t nx, int32_t n
     const long parts = std::max(wgrad_chunks(P), wgrad_tiled_blocks(cin, P));
     // bias partials: one per 1024 points, or one per tiled block
     const long bparts = std::max((long)grid1(P, 1024).x, wgrad_tiled_blocks(cin, P));
-    // the rows of the first reduction pass
-    return (size_t)(parts * 27L * cin * cout + bparts * (long)cout + kSumSeg * 27L * cin * cout);
+    // the rows of the first reduction pass (weights, then bias)
+    return (size_t)(parts * 27L * cin * cout + bparts * (long)cout + kSumSeg * 27L * cin * cout +
+                    kSumSeg * (long)cout);
 }
 
 int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, int32_t nx,
@@ -1485,14 +1497,21 @@ int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, i
         if (aligned16(scratch) && aligned16(mid) && n % 4 == 0 && nch >= 2 * kSumSeg) {
             const long n4 = n / 4;
             const int L = (int)((nch + kSumSeg - 1) / kSumSeg);
-            const dim3 g1((unsigned)((n4 + 31) / 32), (unsigned)kSumSeg);
+            const long na4 = (n4 + 31) / 32;
+            // the bias partials (rows of cout, 16-byte aligned: cout % 16 == 0)
+            // take the same two passes, in the same launches
+            float *mid_b = mid + kSumSeg * n;
+            const bool with_b = tiled_bp && aligned16(tiled_bp);
+            const long nb4 = with_b ? ((long)cout / 4 + 31) / 32 : 0;
+            const dim3 g1((unsigned)(na4 + nb4), (unsigned)kSumSeg);
             hipLaunchKernelGGL(sum_rows4_kernel, g1, dim3(256), 0, s, (const float4 *)scratch, nch,
-                               n4, L, (float4 *)mid);
-            if (tiled_bp) {  // dw's last pass and the bias partials in one launch
+                               n4, L, (float4 *)mid, na4, (const float4 *)tiled_bp,
+                               (long)cout / 4, (float4 *)mid_b);
+            if (with_b) {  // dw's and dbias's last passes in one launch
                 const long na = grid1(n, 32).x;
                 hipLaunchKernelGGL(sum_chunks2_kernel, dim3((unsigned)(na + grid1(cout, 32).x)),
                                    dim3(256), 0, s, (const float *)mid, (long)kSumSeg, n, dw, na,
-                                   (const float *)tiled_bp, nch, (long)cout, dbias);
+                                   (const float *)mid_b, (long)kSumSeg, (long)cout, dbias);
                 tiled_bp = nullptr;
             } else {
                 hipLaunchKernelGGL(sum_chunks_kernel, grid1(n, 32), dim3(256), 0, s,
