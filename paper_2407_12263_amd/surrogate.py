@@ -261,17 +261,32 @@ class UNet:
         self.grids = [(nx >> l, ny >> l, nz >> l) for l in range(self.nlev)]
         self.P = [a * b * c for (a, b, c) in self.grids]
         g = torch.Generator().manual_seed(seed)
-        self.w, self.b = [], []
+        # every layer's weights and bias are views of one flat FP32 buffer (and
+        # so are their Adam moments and gradients), so that one Adam launch
+        # updates all parameters
+        sizes = []
+        for name, ci, co, relu in self.layers:
+            sizes += [27 * co * ci, co]
+        ntot = sum(sizes)
+        self.flat = {k: torch.zeros(ntot, dtype=torch.float32, device=self.dev)
+                     for k in ("w", "m", "v", "g")}
+
+        def views(buf):
+            out, off = [], 0
+            for k, (name, ci, co, relu) in enumerate(self.layers):
+                out.append(buf[off:off + 27 * co * ci].view(27, co, ci))
+                off += 27 * co * ci
+                out.append(buf[off:off + co])
+                off += co
+            return out[0::2], out[1::2]
+
+        self.w, self.b = views(self.flat["w"])
+        self.mw, self.mb = views(self.flat["m"])
+        self.vw, self.vb = views(self.flat["v"])
+        self.gw, self.gb = views(self.flat["g"])
         for k, (name, ci, co, relu) in enumerate(self.layers):
             std = math.sqrt(2.0 / (27 * ci)) * (1.0 if relu else out_scale)
-            self.w.append((torch.randn((27, co, ci), generator=g) * std).to(self.dev))
-            self.b.append(torch.zeros(co, device=self.dev))
-        self.mw = [torch.zeros_like(w) for w in self.w]
-        self.vw = [torch.zeros_like(w) for w in self.w]
-        self.mb = [torch.zeros_like(b) for b in self.b]
-        self.vb = [torch.zeros_like(b) for b in self.b]
-        self.gw = [torch.zeros_like(w) for w in self.w]
-        self.gb = [torch.zeros_like(b) for b in self.b]
+            self.w[k].copy_((torch.randn((27, co, ci), generator=g) * std).to(self.dev))
         self.wf = [torch.empty(w.shape, dtype=torch.int16, device=self.dev) for w in self.w]
         self.wd = [torch.empty((27, w.shape[2], w.shape[1]), dtype=torch.int16, device=self.dev)
                    for w in self.w]
@@ -434,9 +449,8 @@ class UNet:
 
     def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         self.adam_t += 1
-        for k in range(len(self.layers)):
-            sur_adam(self.w[k], self.mw[k], self.vw[k], self.gw[k], lr, b1, b2, eps, self.adam_t)
-            sur_adam(self.b[k], self.mb[k], self.vb[k], self.gb[k], lr, b1, b2, eps, self.adam_t)
+        f = self.flat
+        sur_adam(f["w"], f["m"], f["v"], f["g"], lr, b1, b2, eps, self.adam_t)
         self.pack()
 
     def train_step(self, x_bf16, target_f32, wch, lr=1e-3):
