@@ -59,6 +59,12 @@ int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, i
 /* BF16 packings of FP32 master weights w[27][cout][cin]: wf (same layout)
  * and wd[27][cin][cout] (per-tap transpose, for the data gradient). */
 int sur_pack_weights(const float *w, int32_t cin, int32_t cout, void *wf, void *wd, void *stream);
+/* The same for nlayers (<= 32) layers in one launch: layer l's FP32 weights
+ * [27][cout[l]][cin[l]] start at float offset w_off[l] of w (host array); its
+ * packings are written back to back into wf and wd, layer l at offset
+ * sum_{k<l} 27 cin[k] cout[k] (BF16 elements). cin, cout: host arrays. */
+int sur_pack_weights_all(const float *w, int32_t nlayers, const int64_t *w_off, const int32_t *cin,
+                         const int32_t *cout, void *wf, void *wd, void *stream);
 
 /* 2x2x2 average pooling of BF16 x (fine grid nx, ny, nz even) into BF16 y. */
 int sur_pool2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void *y, void *stream);

@@ -694,6 +694,33 @@ __global__ void pack_weights_kernel(const float *__restrict__ w, int cin, int co
 }
 
 // ------------------------------------------------------------ grid layers
+// Every layer's packing in one launch. Layer l's FP32 weights start at
+// woff[l] of w; its packings at poff[l] of wf and wd (poff[l + 1] - poff[l] =
+// 27 cin cout).
+constexpr int kMaxPackLayers = 32;
+struct PackTable {
+    int n;
+    long woff[kMaxPackLayers];
+    long poff[kMaxPackLayers + 1];
+    int cin[kMaxPackLayers], cout[kMaxPackLayers];
+};
+
+__global__ void pack_all_kernel(const float *__restrict__ w, PackTable tb,
+                                uint16_t *__restrict__ wf, uint16_t *__restrict__ wd) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= tb.poff[tb.n]) return;
+    int l = 0;
+    while (l + 1 < tb.n && e >= tb.poff[l + 1]) ++l;
+    const long el = e - tb.poff[l];
+    const int cin = tb.cin[l], cout = tb.cout[l];
+    const int t = (int)(el / ((long)cin * cout));
+    const int rem = (int)(el % ((long)cin * cout));
+    const int o = rem / cin, i = rem % cin;
+    const uint16_t v = f2bf(w[tb.woff[l] + el]);
+    wf[e] = v;
+    wd[tb.poff[l] + ((long)t * cin + i) * cout + o] = v;
+}
+
 __global__ void pool2_kernel(const uint16_t *__restrict__ x, int c, int nx, int ny, int nz,
                              uint16_t *__restrict__ y) {
     const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
@@ -1531,6 +1558,25 @@ int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, i
         hipLaunchKernelGGL(bias_partial_kernel, dim3((unsigned)nb), dim3(256), 0, s, db, cout, P, 1024L, bp);
         hipLaunchKernelGGL(sum_chunks_kernel, grid1(cout, 32), dim3(256), 0, s, (const float *)bp, nb, (long)cout, dbias);
     }
+    return launched();
+}
+
+int sur_pack_weights_all(const float *w, int32_t nlayers, const int64_t *w_off, const int32_t *cin,
+                         const int32_t *cout, void *wf, void *wd, void *stream) {
+    if (!w || !w_off || !cin || !cout || !wf || !wd || nlayers <= 0 || nlayers > kMaxPackLayers)
+        return SUR_EINVAL;
+    PackTable tb;
+    tb.n = nlayers;
+    tb.poff[0] = 0;
+    for (int l = 0; l < nlayers; ++l) {
+        if (cin[l] <= 0 || cout[l] <= 0 || w_off[l] < 0) return SUR_EINVAL;
+        tb.woff[l] = (long)w_off[l];
+        tb.cin[l] = cin[l];
+        tb.cout[l] = cout[l];
+        tb.poff[l + 1] = tb.poff[l] + 27L * cin[l] * cout[l];
+    }
+    hipLaunchKernelGGL(pack_all_kernel, grid1(tb.poff[nlayers]), dim3(256), 0, (hipStream_t)stream,
+                       w, tb, (uint16_t *)wf, (uint16_t *)wd);
     return launched();
 }
 

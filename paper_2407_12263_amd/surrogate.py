@@ -48,6 +48,7 @@ def load_library(path: str | None = None):
     lib.sur_pool2_bwd_skip.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, vp, vp, vp, vp]
     lib.sur_upsample2_bwd_mask.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp, vp]
     lib.sur_concat_up2.argtypes = [vp, i32, vp, i32, i32, i32, i32, vp, vp]
+    lib.sur_pack_weights_all.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     lib.sur_upsample2.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, vp]
     lib.sur_upsample2_bwd.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp]
     lib.sur_copy_channels.argtypes = [vp, i32, i64, vp, i32, i32, vp]
@@ -70,7 +71,7 @@ def load_library(path: str | None = None):
               "sur_upsample2", "sur_upsample2_bwd", "sur_copy_channels", "sur_add_channels",
               "sur_to_bf16", "sur_relu_mask", "sur_mse", "sur_adam", "sur_coarsen",
               "sur_prolong_add", "sur_checks", "sur_pool2_bwd_skip", "sur_upsample2_bwd_mask",
-              "sur_concat_up2"]:
+              "sur_concat_up2", "sur_pack_weights_all"]:
         getattr(lib, n).restype = C.c_int
     if path is None:
         _lib = lib
@@ -132,6 +133,15 @@ def sur_pool2_bwd_skip(dy, c, grid, skip, skip_stride, skip_off, act, dx=None, d
 def sur_upsample2_bwd_mask(dy, dystride, dyoff, c, grid, act, dx_bf16):
     _ok(load_library().sur_upsample2_bwd_mask(_p(dy), dystride, dyoff, c, *grid, _p(act),
                                               _p(dx_bf16), _stream()), "sur_upsample2_bwd_mask")
+
+
+def sur_pack_weights_all(w_flat, w_off, cin, cout, wf_flat, wd_flat):
+    n = len(w_off)
+    offs = (C.c_int64 * n)(*[int(o) for o in w_off])
+    ci = (C.c_int32 * n)(*[int(c) for c in cin])
+    co = (C.c_int32 * n)(*[int(c) for c in cout])
+    _ok(load_library().sur_pack_weights_all(_p(w_flat), n, offs, ci, co, _p(wf_flat), _p(wd_flat),
+                                            _stream()), "sur_pack_weights_all")
 
 
 def sur_concat_up2(xc, hc, xf, fc, grid, y):
@@ -287,9 +297,16 @@ class UNet:
         for k, (name, ci, co, relu) in enumerate(self.layers):
             std = math.sqrt(2.0 / (27 * ci)) * (1.0 if relu else out_scale)
             self.w[k].copy_((torch.randn((27, co, ci), generator=g) * std).to(self.dev))
-        self.wf = [torch.empty(w.shape, dtype=torch.int16, device=self.dev) for w in self.w]
-        self.wd = [torch.empty((27, w.shape[2], w.shape[1]), dtype=torch.int16, device=self.dev)
-                   for w in self.w]
+        # BF16 packings, back to back in two flat buffers (one packing launch)
+        npk = [27 * co * ci for name, ci, co, relu in self.layers]
+        self.pk_flat = {k: torch.empty(sum(npk), dtype=torch.int16, device=self.dev)
+                        for k in ("f", "d")}
+        self.wf, self.wd, off = [], [], 0
+        for (name, ci, co, relu), n in zip(self.layers, npk):
+            self.wf.append(self.pk_flat["f"][off:off + n].view(27, co, ci))
+            self.wd.append(self.pk_flat["d"][off:off + n].view(27, ci, co))
+            off += n
+        self._w_off = [w.storage_offset() - self.flat["w"].storage_offset() for w in self.w]
         self.adam_t = 0
         self._alloc()
         self.pack()
@@ -324,8 +341,9 @@ class UNet:
         return 0 if name == "out" else int(name[3:-1])
 
     def pack(self):
-        for k, (name, ci, co, relu) in enumerate(self.layers):
-            sur_pack_weights(self.w[k], ci, co, self.wf[k], self.wd[k])
+        sur_pack_weights_all(self.flat["w"], self._w_off, [ci for _, ci, _, _ in self.layers],
+                             [co for _, _, co, _ in self.layers], self.pk_flat["f"],
+                             self.pk_flat["d"])
 
     def n_params(self):
         return sum(w.numel() + b.numel() for w, b in zip(self.w, self.b))

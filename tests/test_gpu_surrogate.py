@@ -307,3 +307,30 @@ def test_training_trajectory_matches_oracle(sur):
     # slow the descent a little; the curves stay within a factor 1.6
     assert np.all(np.abs(np.log(gpu / ref)) < np.log(1.6))
     assert ref[-1] < 0.05 * ref[0] and gpu[-1] < 0.05 * gpu[0]
+
+
+def test_pack_weights_all_equals_per_layer(sur):
+    """One packing launch over several layers (weights at offsets of a flat
+    buffer) writes the same BF16 packings as one launch per layer."""
+    import torch
+    say("[sur] packing of three layers in one launch")
+    rng = np.random.default_rng(5)
+    shapes = [(16, 16), (48, 16), (32, 64)]  # (cin, cout)
+    w_off, off = [], 0
+    for ci, co in shapes:
+        w_off.append(off)
+        off += 27 * ci * co + co  # a bias after each layer's weights
+    flat = _f32(rng.standard_normal(off).astype(np.float32))
+    n = sum(27 * ci * co for ci, co in shapes)
+    wf = torch.empty(n, dtype=torch.int16, device="cuda")
+    wd = torch.empty(n, dtype=torch.int16, device="cuda")
+    sur.sur_pack_weights_all(flat, w_off, [ci for ci, _ in shapes], [co for _, co in shapes], wf, wd)
+    p = 0
+    for (ci, co), o in zip(shapes, w_off):
+        m = 27 * ci * co
+        f1 = torch.empty((27, co, ci), dtype=torch.int16, device="cuda")
+        d1 = torch.empty((27, ci, co), dtype=torch.int16, device="cuda")
+        sur.sur_pack_weights(flat[o:o + m].view(27, co, ci), ci, co, f1, d1)
+        assert torch.equal(wf[p:p + m], f1.view(-1))
+        assert torch.equal(wd[p:p + m], d1.view(-1))
+        p += m
