@@ -10,7 +10,9 @@ HIP library against the oracle's same reading.
 * the step map from the oracle's state (walls on all faces, c = 0.997 and
   1): every PDF to 1e-14;
 * the contact angle the GPU run reaches equals the oracle's to 0.05 degrees
-  in FP32.
+  in FP32;
+* the Rayleigh-Taylor lattice at full size with wetting walls: one step from
+  the GPU's own state, every node, FP16 and FP32.
 
 The sessile droplets use a floor of 1e-4 on |K1|: with 1e-5 the wall nodes
 far from the droplet, where |K1| hovers at the floor, make the scheme itself
@@ -140,3 +142,36 @@ def test_contact_angle_matches_oracle():
     say(f"[wet] contact angle after 2000 steps: GPU fp32 {a:.3f}, oracle {ao:.3f}")
     assert abs(a - ao) < 0.05
     assert a < 85.0
+
+
+@pytest.mark.parametrize("prec,tol", [("fp16", 1e-4), ("fp32", 2e-6)])
+def test_full_size_one_step_with_wetting_walls(prec, tol):
+    """Rayleigh-Taylor 128 x 512 x 128 with its y walls at a 60 degree
+    contact angle, in the launch configuration of the benchmark (interior and
+    wall-slab launches): the GPU evolves 40 steps, its state is loaded into
+    the oracle and both take one step; every node's phi and PDFs agree to the
+    one-step bounds of the arithmetic (as for neutral walls)."""
+    import oracle
+    wet = dict(wetting=1, cos_theta=0.5)
+    w = inputs.rayleigh_taylor()
+    say(f"[wet full] {w.name} {prec}: 40 GPU steps, then one step on both")
+    perm, inv = order_maps()
+    sol = gpu_solver(w, prec, **wet)
+    sol.step(40)
+    f, g = sol.get_pdfs()
+    f, g = f.cpu().numpy(), g.cpu().numpy()
+    o = oracle.Oracle(oracle.OracleParams(**w.params(), **wet), w.phi0, w.u0, w.p0)
+    o.set_pdfs(f[inv], g[inv])
+    del f, g
+    o.step(1)
+    sol.step(1)
+    phi = sol.fields()[0].cpu().numpy()
+    e = np.abs(phi - o.fields()[0]).max()
+    fo, go = o.pdfs()
+    del o
+    fg, gg = sol.get_pdfs()
+    ef = np.abs(fg.cpu().numpy() - fo[perm]).max()
+    del fo
+    eg = np.abs(gg.cpu().numpy() - go[perm]).max()
+    say(f"   max|dphi| {e:.2e}  max|df| {ef:.2e}  max|dg| {eg:.2e}")
+    assert max(e, ef, eg) <= tol
