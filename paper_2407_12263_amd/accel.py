@@ -125,7 +125,9 @@ class CheckLimits:
     mass_tol: float = 2e-3        # |sum phi - sum phi_0| / sum phi_0 before the fix
     phi_lo: float = -0.05
     phi_hi: float = 1.05
-    div_rms: float = math.inf     # RMS divergence of the scaled coarse velocity
+    div_rms: float = 1.0          # RMS divergence of the scaled coarse velocity
+                                  # (units of the velocity scale per coarse cell;
+                                  # runs set it from their training data)
 
     def failed(self, chk, mass0: float) -> str:
         """Name of the first failed check ('' if all pass)."""
@@ -142,27 +144,44 @@ class CheckLimits:
 
 class SnapshotStore:
     """Ring buffer of coarse states in HBM with their (trajectory, window)
-    labels; a training pair is two consecutive windows of one trajectory."""
+    labels; a training pair is two consecutive windows of one trajectory.
 
-    def __init__(self, capacity: int, P: int, device):
-        import torch
-        self.data = torch.zeros((capacity, P, sur.NCH), dtype=torch.float32, device=device)
+    Trajectory ids come from the store (``new_trajectory``), so two
+    trajectories never share a label however the caller batches them; a
+    slot that the ring overwrites loses its old label, and a label written
+    twice resolves to its most recent slot."""
+
+    def __init__(self, capacity: int, P: int, device=None, data=None):
+        if data is None:
+            import torch
+            data = torch.zeros((capacity, P, sur.NCH), dtype=torch.float32, device=device)
+        self.data = data
         self.label = [None] * capacity
+        self.seq = [-1] * capacity
         self.cap = capacity
         self.next = 0
         self.added = 0
+        self.trajectories = 0
+
+    def new_trajectory(self) -> int:
+        self.trajectories += 1
+        return self.trajectories - 1
 
     def slot(self, traj: int, win: int):
         k = self.next
         self.label[k] = (traj, win)
+        self.seq[k] = self.added
         self.next = (k + 1) % self.cap
         self.added += 1
         return self.data[k]
 
     def pairs(self):
-        where = {lab: k for k, lab in enumerate(self.label) if lab is not None}
+        where = {}
+        for k, lab in enumerate(self.label):
+            if lab is not None and (lab not in where or self.seq[k] > self.seq[where[lab]]):
+                where[lab] = k
         out = []
-        for (tr, w), k in where.items():
+        for (tr, w), k in sorted(where.items(), key=lambda it: self.seq[it[1]]):
             j = where.get((tr, w - 1))
             if j is not None:
                 out.append((j, k))
@@ -189,14 +208,19 @@ class Trainer:
     dominated by acoustic waves the network cannot predict and counts
     least. Pairs that start in the first ``skip_windows`` windows of a
     trajectory (the acoustic transient of the initial state) are not used.
-    A step whose loss exceeds ``outlier`` times the running mean of the
-    accepted losses is not applied (Adam's second-moment estimate lags a
-    sudden large gradient, and such a step can wreck the weights)."""
+
+    Every step is applied by default. With ``outlier`` set, a step whose loss
+    exceeds ``outlier`` times the running mean of the applied losses is not
+    applied; each such step is recorded in ``skipped_log`` with its pair's
+    labels, and a warning is issued once they exceed 1% of the steps. The
+    largest ratio of a step's loss to the running mean is kept in
+    ``max_loss_ratio`` either way (a data or pairing defect shows there
+    first)."""
 
     def __init__(self, net: sur.UNet, coupler: Coupler, store: SnapshotStore, rscale,
                  wch=DEFAULT_WCH, lr: float = 3e-4, lr_final: float = 3e-5,
                  total_steps: int = 1000, seed: int = 0, record_every: int = 50,
-                 skip_windows: int = 2, outlier: float = 5.0):
+                 skip_windows: int = 2, outlier: float | None = None):
         import torch
         self.torch = torch
         self.net, self.cp, self.store = net, coupler, store
@@ -208,6 +232,9 @@ class Trainer:
         self.outlier = outlier
         self.mean_loss = None
         self.skipped = 0
+        self.skipped_log = []
+        self.max_loss_ratio = 0.0
+        self._warned = False
         self.xb = torch.empty((coupler.P, sur.NCH), dtype=torch.int16, device=dev)
         self.tgt = coupler.new_state()
         self.lr0, self.lr1, self.total = lr, lr_final, max(1, total_steps)
@@ -222,16 +249,26 @@ class Trainer:
         return [(a, b) for a, b in self.store.pairs()
                 if self.store.label[a][1] >= self.skip_windows]
 
-    def step_on(self, a, b):
+    def step_on(self, a, b, labels=None):
         net = self.net
         sur.sur_to_bf16(a, self.xb)
         sur.sur_residual_target(a, b, self.rscale, sur.NUSE, self.cp.P, self.tgt,
                                 self.cp.res_width)
         net.forward(self.xb)
         loss = float(net.loss_and_grad(self.tgt, self.wch).item())
-        if self.mean_loss is not None and loss > self.outlier * self.mean_loss:
-            self.skipped += 1
-            return loss
+        if self.mean_loss is not None and self.mean_loss > 0:
+            ratio = loss / self.mean_loss
+            self.max_loss_ratio = max(self.max_loss_ratio, ratio)
+            if self.outlier is not None and ratio > self.outlier:
+                self.skipped += 1
+                self.skipped_log.append(dict(step=self.log.steps, loss=loss, ratio=ratio,
+                                             labels=labels))
+                if not self._warned and self.skipped > 0.01 * max(1, self.log.steps):
+                    import warnings
+                    warnings.warn(f"{self.skipped} training steps skipped as outliers "
+                                  f"(last pair {labels}, loss {loss:.3g})")
+                    self._warned = True
+                return loss
         self.mean_loss = loss if self.mean_loss is None else 0.95 * self.mean_loss + 0.05 * loss
         net.backward(net.dout)
         net.adam_step(self.lr())
@@ -246,7 +283,8 @@ class Trainer:
         t0 = time.perf_counter()
         for i in range(n):
             a, b = pairs[int(self.rng.integers(len(pairs)))]
-            loss = self.step_on(self.store.data[a], self.store.data[b])
+            loss = self.step_on(self.store.data[a], self.store.data[b],
+                                (self.store.label[a], self.store.label[b]))
             if record_every and self.log.steps % record_every == 0:
                 self.log.losses.append((self.log.steps, loss))
         self.torch.cuda.synchronize()
@@ -322,7 +360,8 @@ def generate(cp: Coupler, store: SnapshotStore, workloads, windows: int, trainer
     solver = cp.solver
     chk = torch.empty(7, dtype=torch.float64, device=solver.device)
     log = trainer.log if trainer is not None else TrainLog()
-    for tr, wl in enumerate(workloads):
+    for wl in workloads:
+        tr = store.new_trajectory()
         w = wl() if callable(wl) else wl
         solver.reset(torch.as_tensor(w.phi0), torch.as_tensor(w.u0), torch.as_tensor(w.p0), 0)
         cp.snapshot(store.slot(tr, 0))
@@ -626,7 +665,8 @@ def surrogate_benchmark(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rma
     del untrained
     out["training"] = dict(trajectories=len(train_seeds), windows=windows,
                            snapshots=len(train_seeds) * (windows + 1), steps=tr.log.steps,
-                           skipped_outliers=tr.skipped, seconds_solver=tr.log.seconds_lbm,
+                           skipped_outliers=tr.skipped, max_loss_ratio=tr.max_loss_ratio,
+                           seconds_solver=tr.log.seconds_lbm,
                            seconds_train=tr.log.seconds_train, params=net.n_params(),
                            rscale=[float(x) for x in rscale[:sur.NUSE]])
     names = ["phi", "ux", "uy", "uz", "p"]
