@@ -30,8 +30,9 @@
  * concurrently.
  *
  * Errors: every call returns an lbm_status. A failed lbm_init leaves *out
- * NULL. After LBM_EDEVICE or LBM_EUNSTABLE the context refuses lbm_step
- * with LBM_ESTATE.
+ * NULL. After LBM_EDEVICE or LBM_EUNSTABLE, and after an lbm_reset that
+ * rejected its fields, the context refuses lbm_step with LBM_ESTATE until an
+ * lbm_reset succeeds (after LBM_EDEVICE it refuses every call).
  */
 #ifndef LBM_H
 #define LBM_H
@@ -98,7 +99,7 @@ typedef struct {
     double delta;              /* interface thickness (> 0)                   */
     double G[3];               /* body acceleration                           */
     double k1_eps;             /* normal n = -K1/|K1| where |K1| > k1_eps,    */
-                               /* n = 0 otherwise (>= 0; 1e-5 recommended)    */
+                               /* n = 0 otherwise (>= 0; 1e-4 recommended)    */
     double p_ref;              /* pressure gauge of the 16-bit f storage      */
     int32_t lattice;           /* 19 or 0: D3Q19; 27: D3Q27 (the same method  */
                                /* on the 27-vector lattice, weights 8/27,     */
@@ -178,7 +179,10 @@ int lbm_set_pdfs(lbm_ctx *ctx, const double *d_f, const double *d_g);
 /* Rebuilds the state in place from fields (device FP64, as lbm_init) and
  * sets the time to t; the phase-mass bookkeeping then targets sum(d_phi).
  * Used to hand a state back to the solver (restart from fields, or after a
- * window advanced by another model). Synchronises the stream. */
+ * window advanced by another model). Synchronises the stream. Fields outside
+ * the range lbm_init accepts give LBM_EINVAL after the device check; the
+ * state buffers are overwritten by then, so the context refuses lbm_step
+ * (LBM_ESTATE) until a later lbm_reset succeeds. */
 int lbm_reset(lbm_ctx *ctx, const double *d_phi, const double *d_u, const double *d_p, int64_t t);
 
 /* Current time t (number of steps since lbm_init). */

@@ -75,7 +75,7 @@ class OracleParams:
     delta: float = 4.0
     G: tuple = (0.0, 0.0, 0.0)
     normal_fd: int = 0
-    k1_eps: float = 1e-5
+    k1_eps: float = 1e-4
     lattice: int = 19        # 19 (D3Q19) or 27 (D3Q27): which build runs
     wetting: int = 0         # 1: contact angle at the walls (see cpf_oracle.c)
     cos_theta: float = 0.0

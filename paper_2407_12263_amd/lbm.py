@@ -113,7 +113,7 @@ def _check(rc: int, where: str):
 
 def make_params(nx, ny, nz, precision="fp32", wall=(0, 0, 0), courant=0.997, rho1=1.0,
                 rho2=1.0, tau_rho1=0.3, tau_rho2=0.3, tau_phi=0.3, sigma=0.0, delta=4.0,
-                G=(0.0, 0.0, 0.0), k1_eps=1e-5, p_ref=0.0, store_log2=(10, 10),
+                G=(0.0, 0.0, 0.0), k1_eps=1e-4, p_ref=0.0, store_log2=(10, 10),
                 check_every=0, mass_fix_every=None, normal_fd=0, lattice=19, wetting=0,
                 cos_theta=0.0) -> LbmParams:
     """mass_fix_every: None picks 10 for FP32 and 16-bit storage (FP32 rounding

@@ -19,7 +19,7 @@ from paper_2407_12263_amd import inputs  # noqa: E402
 def main():
     out = {"description": "oracle ||phi - phi0||_2 / ||phi0||_2 after T = round(2 t0) steps",
            "Cn": 0.06, "La": 1.0, "tau_rho": 0.02, "M": 0.02, "runs": {}}
-    for L0 in (50, 100, 200):
+    for L0 in [int(a) for a in sys.argv[1:]] or (50, 100, 200):
         w = inputs.droplet_2d(L0)
         T = int(round(2 * w.meta["t0"]))
         o = oracle.Oracle(oracle.OracleParams(**w.params()), w.phi0, w.u0, w.p0)

@@ -267,6 +267,36 @@ def test_static_droplet_zero_net_momentum(orc, q):
     assert max(abs(d["momx"]), abs(d["momy"]), abs(d["momz"])) < 1e-14 * w.N
 
 
+@LAT
+def test_diagnostics_are_their_definitions(orc, q):
+    """Each diagnostic is the sum of its definition over the node fields:
+    sum phi, mass sum rho phi (Sec. 3.3), net momentum sum rho u, kinetic
+    energy sum rho |u|^2 / 2 (Sec. 3.4), max |u| (Sec. 3.1), the phi range,
+    the centroid and phase-velocity numerators sum phi x, sum phi u
+    (Sec. 3.3) and the two sums of ||delta phi||_2 (Sec. 3.1), here taken
+    with numpy from the oracle's fields, rho = rho2 + (rho1 - rho2) phi,
+    on a ragged Rayleigh-Taylor box (density ratio 3, flow under way)."""
+    w = inputs.rayleigh_taylor(nx=12, ny=40, nz=6)
+    o = orc.Oracle(orc.OracleParams(**w.params(), lattice=q), w.phi0, w.u0, w.p0)
+    o.step(60)
+    ref = np.roll(w.phi0, 3, axis=2)
+    d = o.diag(ref)
+    phi, u, _ = o.fields()
+    rho = w.rho2 + (w.rho1 - w.rho2) * phi
+    uu = (u * u).sum(0)
+    z, y, x = np.meshgrid(np.arange(w.nz), np.arange(w.ny), np.arange(w.nx), indexing="ij")
+    want = dict(sum_phi=phi.sum(), mass=(rho * phi).sum(), momx=(rho * u[0]).sum(),
+                momy=(rho * u[1]).sum(), momz=(rho * u[2]).sum(), ekin=0.5 * (rho * uu).sum(),
+                umax=np.sqrt(uu).max(), phi_min=phi.min(), phi_max=phi.max(),
+                comx=(phi * x).sum(), comy=(phi * y).sum(), comz=(phi * z).sum(),
+                phiux=(phi * u[0]).sum(), phiuy=(phi * u[1]).sum(), phiuz=(phi * u[2]).sum(),
+                l2_num=((phi - ref) ** 2).sum(), l2_den=(ref ** 2).sum())
+    assert np.sqrt(uu).max() > 1e-5          # the flow is under way
+    for k, v in want.items():
+        scale = max(abs(v), np.abs(phi).max(), 1e-300)
+        assert abs(d[k] - v) <= 1e-12 * scale * w.N, (k, d[k], v)
+
+
 @pytest.mark.parametrize("tau", [0.05, 0.3, 1.0])
 @LAT
 def test_body_force_momentum_per_step(orc, q, tau):
@@ -337,6 +367,37 @@ def test_shear_wave_decay_rate(orc, q, tau):
     A = _fourier_amp(o.fields()[1][0].ravel(), k, z)
     rate = -math.log(A / 1e-3) / 400
     assert abs(rate / (tau * CS2 * k * k) - 1.0) < 5e-3
+
+
+@pytest.mark.parametrize("phi", [0.0, 0.25, 0.5, 1.0])
+@LAT
+def test_two_phase_viscosity_shear_wave(orc, q, phi):
+    """Variable viscosity between the phases (reading: dynamic viscosity
+    linear in phi, Sec. 2.2 with the densities of Sec. 2.3): in a box of
+    uniform phi a shear wave decays at nu(phi) k^2 with
+    nu(phi) = [eta2 + (eta1 - eta2) phi] / [rho2 + (rho1 - rho2) phi] and
+    eta_k = rho_k cs2 tau_rho_k. Densities 1 and 1/4 with relaxation times
+    0.1 and 1.0 make the alternatives distinguishable: at phi = 0.25 the
+    kinematic interpolation gives 0.78 cs2, swapped phases 0.31 cs2 and
+    the reading 0.49 cs2. The sharpening is switched off (delta -> infinity)
+    so the uniform phase field stays uniform. The wave is 128 nodes long:
+    the gap to the continuum rate is a discretisation correction that falls
+    as k^2 (0.68% at 64 nodes and tau 0.1, 0.17% at 128)."""
+    nz, U = 128, 1e-3
+    rho1, rho2, t1, t2 = 1.0, 0.25, 0.1, 1.0
+    k = 2 * math.pi / nz
+    z = np.arange(nz)
+    P = _params(orc, q, nx=1, ny=1, nz=nz, rho1=rho1, rho2=rho2, tau_rho1=t1, tau_rho2=t2,
+                delta=1e12)
+    u0 = np.zeros((3, nz, 1, 1))
+    u0[0, :, 0, 0] = U * np.sin(k * z)
+    o = orc.Oracle(P, np.full((nz, 1, 1), phi), u0)
+    o.step(1600)
+    A = _fourier_amp(o.fields()[1][0].ravel(), k, z)
+    rate = -math.log(A / U) / 1600
+    eta = rho2 * CS2 * t2 + (rho1 * CS2 * t1 - rho2 * CS2 * t2) * phi
+    rho = rho2 + (rho1 - rho2) * phi
+    assert abs(rate / (eta / rho * k * k) - 1.0) < 3e-3, (rate, eta / rho * k * k)
 
 
 @pytest.mark.parametrize("courant", [1.0, C])
@@ -496,6 +557,39 @@ def test_k1_gradient_matches_fd_to_second_order(orc, q):
     assert 2.8 < ratio < 5.6, gaps
 
 
+def _perturbed_gap(orc, w, steps, rel, **over):
+    """max|dphi| after `steps` between the oracle's run of w and the same run
+    from a state perturbed by `rel` relative noise."""
+    prm = dict(w.params(), **over)
+    P = orc.OracleParams(**prm)
+    a = orc.Oracle(P, w.phi0, w.u0, w.p0)
+    b = orc.Oracle(P, w.phi0, w.u0, w.p0)
+    f, g = b.pdfs()
+    rng = np.random.default_rng(0)
+    b.set_pdfs(f * (1 + rel * rng.standard_normal(f.shape)),
+               g * (1 + rel * rng.standard_normal(g.shape)))
+    a.step(steps)
+    b.step(steps)
+    return float(np.abs(a.fields()[0] - b.fields()[0]).max())
+
+
+def test_k1_floor_conditions_rayleigh_taylor(orc):
+    """The Rayleigh-Taylor workload (32 x 128 x 16, walls in y, gravity,
+    density ratio 3) with the default floor on the normal: a 1e-15
+    perturbation of the state stays below 1e-12 after 100 steps (measured
+    3.6e-15), and a perturbation at FP32 rounding (1e-7) below 1e-6
+    (measured 2.1e-8). With the floor at 1e-5 the same perturbations grow to
+    1.2e-9 and 5.3e-4: the normal of nodes in the heavy phase next to the
+    accelerated walls, where K1 is of order 1e-5 but carries no gradient,
+    follows the noise. That is what makes the FP64 and FP32 trajectory
+    gates meaningful on this workload."""
+    w = inputs.rayleigh_taylor(nx=32, ny=128, nz=16)
+    assert w.k1_eps == 1e-4
+    assert _perturbed_gap(orc, w, 100, 1e-15) < 1e-12
+    assert _perturbed_gap(orc, w, 100, 1e-7) < 1e-6
+    assert _perturbed_gap(orc, w, 100, 1e-15, k1_eps=1e-5) > 1e-11
+
+
 @pytest.mark.parametrize("normal_fd", [0, 1])
 def test_k1_floor_bounds_rounding_sensitivity(orc, normal_fd):
     """On the static-droplet configuration (32^3, R = 8, W = 4) a perturbation
@@ -507,7 +601,7 @@ def test_k1_floor_bounds_rounding_sensitivity(orc, normal_fd):
     q = 19
     w = inputs.static_droplet()
     res = {}
-    for eps in (1e-5, 0.0):
+    for eps in (1e-4, 0.0):
         prm = dict(w.params(), lattice=q)
         prm["k1_eps"] = eps
         prm["normal_fd"] = normal_fd
@@ -521,7 +615,7 @@ def test_k1_floor_bounds_rounding_sensitivity(orc, normal_fd):
         a.step(100)
         b.step(100)
         res[eps] = np.abs(a.fields()[0] - b.fields()[0]).max()
-    assert res[1e-5] < 1e-12
+    assert res[1e-4] < 1e-12
     assert res[0.0] > 1e-8
 
 

@@ -73,16 +73,19 @@ def test_pool_and_upsample_adjoints():
     assert np.abs(so.pool2(so.up2(yc)) - yc).max() < 1e-15
 
 
-def test_unet_gradient_by_finite_differences():
-    """Two-level U-Net (channels 4, 6) on 4x4x4 in FP64: every weight gradient
+@pytest.mark.parametrize("ch,n", [((4, 6), 4), ((2, 3, 4, 5), 8)])
+def test_unet_gradient_by_finite_differences(ch, n):
+    """U-Net in FP64, two levels (channels 4, 6) on 4^3 and four levels (the
+    product's depth; channels 2, 3, 4, 5) on 8^3, whose coarsest level is a
+    single point: every sampled weight and bias gradient of every layer
     agrees with a central finite difference of the loss."""
     rng = _rng(5)
-    ch = (4, 6)
     layers = so.unet_layers(ch, cin=3, cout=3)
+    assert len(layers) == 4 * len(ch) - 1
     params = [(0.3 * rng.standard_normal((27, o, i)), 0.1 * rng.standard_normal(o))
               for _, i, o, _ in layers]
-    x = rng.standard_normal((4, 4, 4, 3))
-    tgt = rng.standard_normal((4, 4, 4, 3))
+    x = rng.standard_normal((n, n, n, 3))
+    tgt = rng.standard_normal((n, n, n, 3))
     wch = [1.0, 0.5, 2.0]
 
     def loss_of(params):
@@ -118,6 +121,28 @@ def test_adam_first_step_is_signed_learning_rate():
     w0 = rng.standard_normal(100)
     w1, m, v = so.adam(w0, np.zeros(100), np.zeros(100), g, t=1, lr=1e-2, eps=1e-12)
     assert np.abs((w1 - w0) + 1e-2 * np.sign(g)).max() < 1e-10
+
+
+def test_adam_bias_correction_over_three_steps():
+    """Kingma & Ba's bias correction in closed form: with a constant gradient
+    g the corrected moments are g and g^2 at every t, so each of the first
+    three steps moves w by -lr sign(g) (without the correction, or with it
+    at a fixed t, steps 2 and 3 differ); with g then -g the second step is
+    +lr (1 - b1)/(1 + b1) sign(g), since m_2/(1 - b1^2) = -(1 - b1)/(1 + b1) g
+    and v_2/(1 - b2^2) = g^2."""
+    rng = _rng(7)
+    g = rng.standard_normal(50)
+    w0 = rng.standard_normal(50)
+    lr, b1, b2 = 1e-2, 0.9, 0.999
+    w, m, v = w0, np.zeros(50), np.zeros(50)
+    for t in (1, 2, 3):
+        w1, m, v = so.adam(w, m, v, g, t=t, lr=lr, b1=b1, b2=b2, eps=1e-14)
+        assert np.abs((w1 - w) + lr * np.sign(g)).max() < 1e-11, t
+        w = w1
+    assert np.abs(w - (w0 - 3 * lr * np.sign(g))).max() < 1e-11
+    w1, m, v = so.adam(w0, np.zeros(50), np.zeros(50), g, t=1, lr=lr, b1=b1, b2=b2, eps=1e-14)
+    w2, m, v = so.adam(w1, m, v, -g, t=2, lr=lr, b1=b1, b2=b2, eps=1e-14)
+    assert np.abs((w2 - w1) - lr * (1 - b1) / (1 + b1) * np.sign(g)).max() < 1e-11
 
 
 def test_bf16_rounding_ties_to_even():
