@@ -16,6 +16,11 @@ the finite-difference-normal comparison scheme (Sec. 3.4: grad phi by
 central differences of a stored phi field, a second pass per step) in the
 same storage mode, and the rate of the same step on the D3Q27 lattice
 (224 instead of 160 algorithmic bytes per update in FP16 storage).
+"roofline" also carries the bandwidth of a plain 1 GiB streaming copy on
+the same GPU (probe_copy, include/probe.h: half read, half write, as the
+step) and the step's fraction of it. "workloads" gives the rates of the
+static droplet (32^3, FP64 and FP16), the rising bubble (128 x 128 x 256,
+walls on all faces) and the Taylor-Green breakup (256^3) in FP16 and FP32.
 
 The "surrogate" object covers the learned part on the emulsion workload
 (256^3 periodic, 200 droplets, random solenoidal velocity): the coarse-grid
@@ -96,6 +101,50 @@ def time_solver(sol, steps: int, warmup: int):
         end.record(stream)
     torch.cuda.synchronize()
     return start.elapsed_time(end) / 1e3  # seconds
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+WORKLOADS = {
+    # the paper's other test problems at the sizes of their configurations
+    "static_droplet_32": (lambda inputs: inputs.static_droplet(), ("fp64", "fp16")),
+    "rising_bubble_128x128x256": (lambda inputs: inputs.rising_bubble(), ("fp16", "fp32")),
+    "taylor_green_256": (lambda inputs: inputs.taylor_green_breakup(), ("fp16", "fp32")),
+}
+
+
+def workload_rates(steps: int, warmup: int) -> dict:
+    """MLUPS and the algorithmic-byte fraction of the HBM peak for the static
+    droplet (32^3 periodic), the rising bubble (128 x 128 x 256, walls on all
+    faces) and the Taylor-Green breakup (256^3 periodic), timed as the main
+    workload."""
+    import torch
+    from paper_2407_12263_amd import inputs, lbm
+    out = {}
+    for name, (mk, precs) in WORKLOADS.items():
+        w = mk(inputs)
+        for prec in precs:
+            print(f"[bench] {w.name} storage={prec} steps={steps}", file=sys.stderr, flush=True)
+            sol = lbm.Solver(dict(w.params(), precision=prec), w.phi0, w.u0, w.p0)
+            secs = time_solver(sol, steps, warmup)
+            gbs = lbm.BYTES_PER_LU[prec] * w.N * steps / secs / 1e9
+            out[f"{name}_{prec}"] = dict(mlups=round(w.N * steps / secs / 1e6, 1),
+                                         ms_per_step=round(secs * 1e3 / steps, 5),
+                                         grid=[w.nx, w.ny, w.nz], walls=list(w.wall),
+                                         achieved_gbs=round(gbs, 1),
+                                         hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+            del sol
+            torch.cuda.synchronize()
+    return out
 
 
 def cpu_baseline(w, steps: int = 2):
@@ -195,6 +244,8 @@ def main():
                     help="skip the surrogate-accelerated emulsion runs")
     ap.add_argument("--surrogate-trajectories", type=int, default=32,
                     help="training trajectories of 64 windows (32 -> 2080 snapshots)")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the droplet, rising-bubble and Taylor-Green rates")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -238,6 +289,9 @@ def main():
     launch_s = main_r["seconds"] / args.steps
     achieved = launch_bytes / launch_s / 1e9
     traffic = measured_traffic(launch_bytes)
+    from paper_2407_12263_amd import probe
+    print("[bench] streaming copy probe, 1 GiB", file=sys.stderr, flush=True)
+    copy = probe.copy_bandwidth()
     line = {
         "metric": METRIC,
         "value": round(main_r["mlups"], 1),
@@ -258,7 +312,10 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes_per_step": launch_bytes,
                      "kernel": "step_kernel (fused propagate+moments+collide+store; interior "
-                               "and wall-slab launches)"},
+                               "and wall-slab launches)",
+                     "copy_gbs": copy["copy_gbs"],
+                     "frac_of_copy": round(achieved / copy["copy_gbs"], 4),
+                     "copy_probe": copy},
         "secondary": {m: {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 5),
                           "hbm_frac": round((lbm.BYTES_PER_LU_Q27 if parse_mode(m)[2] == 27
                                              else lbm.BYTES_PER_LU)[parse_mode(m)[0]] * w.N
@@ -267,12 +324,14 @@ def main():
         "checks": {m: {"finite": r["finite"], "sum_phi": r["sum_phi"], "umax": r["umax"]}
                    for m, r in results.items()},
     }
+    if not args.no_workloads:
+        line["workloads"] = workload_rates(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: oracle FP64, {args.cpu_steps} steps on the full lattice",
               file=sys.stderr, flush=True)
         mlups, threads, dt, mlups1 = cpu_baseline(w, args.cpu_steps)
         line["cpu_baseline"] = {"value": round(mlups, 3), "unit": "MLUPS", "cores": threads,
-                                "kind": "oracle",
+                                "kind": "oracle", "cpu_model": cpu_model(),
                                 "sample": f"{args.cpu_steps} steps of the full {w.nx}x{w.ny}x{w.nz} "
                                           f"lattice in FP64 ({dt:.1f} s)",
                                 "single_thread_value": round(mlups1, 3)}

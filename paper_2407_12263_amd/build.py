@@ -16,6 +16,7 @@ HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 LIBRARIES = {
     "liblbm.so": ["lbm.hip"],
     "libsur.so": ["sur.hip"],
+    "libprobe.so": ["probe.hip"],
 }
 
 

@@ -34,6 +34,16 @@ def test_surrogate_library_exports_every_declared_symbol():
         assert hasattr(so, n), n
 
 
+def test_probe_library_exports_every_declared_symbol():
+    from paper_2407_12263_amd import probe
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "probe.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(probe_[a-z0-9_]+)\s*\(", src)))
+    assert names == ["probe_copy"]
+    so = probe.load_library()
+    for n in names:
+        assert hasattr(so, n), n
+
+
 def test_library_exports_every_declared_symbol(lib):
     names = _declared()
     assert "lbm_init" in names and "lbm_step" in names and "lbm_diagnostics" in names
