@@ -672,6 +672,10 @@ int lbm_reset(lbm_ctx *c, const double *d_phi, const double *d_u, const double *
     if (rc == LBM_OK) {
         c->t = t;
         c->status = LBM_OK;
+    } else {
+        // the buffers now hold the rejected fields' state: refuse lbm_step
+        // until a reset succeeds
+        c->status = rc == LBM_EDEVICE ? LBM_EDEVICE : LBM_ESTATE;
     }
     return rc;
 }
