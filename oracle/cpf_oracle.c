@@ -30,12 +30,18 @@
  *     so that K1_eq = tau_phi c_s^2 S as used by Eq. 19 and App. B (Eq. B.13).
  *   - Gamma_i(u) = t_i[1 + e.u/cs2 + (e.u)^2/(2cs4) - u^2/(2cs2)], w_i = t_i.
  *   - dynamic viscosity linear in phi; tau_rho = eta/(rho cs2).
- *   - n = 0 where |K1| <= k1_eps. Where grad(phi) vanishes inside the
- *     interface (droplet centres, where two tails meet) K1 is pure rounding
- *     noise, and the sharpening term S = s*n then injects a flux of size s in
- *     a direction set by that noise, which the scheme amplifies; a floor well
- *     above rounding noise and far below interface values of |K1| (about
- *     c_s^2/(2W)) removes this without touching resolved interfaces.
+ *   - a floor on the normal: n = -w K1/|K1| with w = 0 where |K1| <= k1_eps,
+ *     w = 1 where |K1| >= 2 k1_eps and linear between. Where grad(phi)
+ *     vanishes inside the interface (droplet centres, where two tails meet)
+ *     K1 is rounding noise, and next to accelerated walls it carries a part
+ *     of order 1e-5 that is no gradient; the sharpening term S = s*n then
+ *     injects a flux of size s in a direction set by that noise, which the
+ *     scheme amplifies. A floor above those values and far below interface
+ *     values of |K1| (about c_s^2/(2W)) removes this without touching
+ *     resolved interfaces; the linear rise keeps the normal continuous in
+ *     K1, so a small change of K1 near the floor (a rounding) cannot switch
+ *     a whole unit normal on or off. The same floor applies to a given
+ *     gradient (the finite-difference variant and the initial state).
  *   - initial state: equilibrium plus the first-order non-equilibrium part of
  *     g that makes the K1 recovery return the initial gradient.
  *   - planar no-slip walls halfway between nodes: flux-form Lax-Wendroff
@@ -181,6 +187,16 @@ static void wet_normal(const orc_params *P, const double nw[3], double n[3])
     for (int a = 0; a < 3; ++a) n[a] = -ct * nw[a] + st * t[a] / tt;
 }
 
+/* Weight of the normal at a central moment or gradient of size k: 0 up to
+ * k1_eps, 1 from 2 k1_eps, linear between (k1_eps = 0: 1 for any k > 0). */
+static double floor_weight(const orc_params *P, double k)
+{
+    if (P->k1_eps <= 0.0) return k > 0.0 ? 1.0 : 0.0;
+    if (k <= P->k1_eps) return 0.0;
+    if (k >= 2.0 * P->k1_eps) return 1.0;
+    return (k - P->k1_eps) / P->k1_eps;
+}
+
 /* Normal, S and grad(phi) from the central moment K1 (Sec. 2.3, Eqs. 15,
  * 18, 19); nw: inward wall normal of a wetting wall node, or NULL. */
 static void gradient_from_K1(const orc_params *P, double phi, const double K1[3],
@@ -188,10 +204,14 @@ static void gradient_from_K1(const orc_params *P, double phi, const double K1[3]
 {
     const double cs2 = cs2_of(P);
     const double k = sqrt(K1[0] * K1[0] + K1[1] * K1[1] + K1[2] * K1[2]);
-    /* Eq. 18; the direction of a vanishing K1 is undefined, so n = 0 where
-     * |K1| <= k1_eps (reading of the degenerate case, see header) */
-    for (int a = 0; a < 3; ++a) m->n[a] = (k > P->k1_eps) ? -K1[a] / k : 0.0;
-    if (nw && k > P->k1_eps) wet_normal(P, nw, m->n);
+    /* Eq. 18; the direction of a vanishing K1 is undefined: n = 0 where
+     * |K1| <= k1_eps, the unit normal where |K1| >= 2 k1_eps, and between
+     * the two the unit normal scaled linearly from 0 to 1 (reading of the
+     * degenerate case, see header) */
+    const double w = floor_weight(P, k);
+    for (int a = 0; a < 3; ++a) m->n[a] = w > 0.0 ? -K1[a] / k : 0.0;
+    if (nw && w > 0.0) wet_normal(P, nw, m->n);
+    for (int a = 0; a < 3; ++a) m->n[a] *= w;
     const double s = 4.0 * phi * (1.0 - phi) / P->delta;
     for (int a = 0; a < 3; ++a) m->S[a] = s * m->n[a];                       /* Eq. 15 */
     for (int a = 0; a < 3; ++a)                                              /* Eq. 19 */
@@ -207,9 +227,10 @@ static void gradient_given(const orc_params *P, double phi, const double gp[3], 
 {
     const double gn = sqrt(gp[0] * gp[0] + gp[1] * gp[1] + gp[2] * gp[2]);
     const double s = 4.0 * phi * (1.0 - phi) / P->delta;
+    const double w = floor_weight(P, gn);
     for (int a = 0; a < 3; ++a) {
         m->gradphi[a] = gp[a];
-        m->n[a] = (gn > P->k1_eps) ? gp[a] / gn : 0.0;
+        m->n[a] = w > 0.0 ? w * gp[a] / gn : 0.0;
         m->S[a] = s * m->n[a];
     }
     m->gnorm = gn;

@@ -44,7 +44,8 @@ typedef struct {
     double G[3];        /* body acceleration                                     */
     int normal_fd;      /* 0: normal and grad(phi) from K1 (the paper's scheme)  */
                         /* 1: isotropic central differences of phi (comparison)  */
-    double k1_eps;      /* n = 0 where |K1| <= k1_eps (0: only where K1 = 0)     */
+    double k1_eps;      /* floor of the normal: weight 0 up to k1_eps, 1 from    */
+                        /* 2 k1_eps, linear between (0: no floor)               */
     int wetting;        /* 0: neutral walls; 1: contact angle theta at the walls  */
     double cos_theta;   /* cos(theta), theta measured through the phi = 1 phase   */
 } orc_params;
