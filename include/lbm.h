@@ -98,8 +98,11 @@ typedef struct {
     double sigma;              /* surface tension (>= 0)                      */
     double delta;              /* interface thickness (> 0)                   */
     double G[3];               /* body acceleration                           */
-    double k1_eps;             /* normal n = -K1/|K1| where |K1| > k1_eps,    */
-                               /* n = 0 otherwise (>= 0; 1e-4 recommended)    */
+    double k1_eps;             /* floor of the normal (>= 0; 1e-4 recommended):*/
+                               /* n = -w K1/|K1| with w = 0 for |K1| <=       */
+                               /* k1_eps, 1 for |K1| >= 2 k1_eps, linear      */
+                               /* between (0: w = 1 wherever K1 != 0); the    */
+                               /* same for |grad phi| with normal_fd = 1      */
     double p_ref;              /* pressure gauge of the 16-bit f storage      */
     int32_t lattice;           /* 19 or 0: D3Q19; 27: D3Q27 (the same method  */
                                /* on the 27-vector lattice, weights 8/27,     */

@@ -591,15 +591,25 @@ struct Macro {
 
 // Moments of the post-propagation PDFs (Sec. 2.2 Eqs. 11-12, Sec. 2.3
 // Eqs. 15, 17-19): phi = sum g, rho(phi), u = (sum f e + rho G/2)/rho,
-// K1 = sum g e - phi u, n = -K1/|K1| (0 where |K1| <= k1_eps),
+// K1 = sum g e - phi u, n = -K1/|K1| times floor_weight(|K1|),
 // S = 4 phi (1 - phi)/delta n, grad(phi) = (tau cs2 S - K1)/((tau + 1/2) cs2),
 // grad(rho) = (rho1 - rho2) grad(phi), p = cs2 sum f + cs2/2 u.grad(rho).
 // 1/x: the hardware reciprocal (1 ulp) in FP32, the division in FP64.
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
+// Weight of the normal at a central moment (or a given gradient) of size k:
+// 0 up to k1_eps, 1 from 2 k1_eps, linear between; with k1_eps = 0 it is 1
+// for any k > 0 ((k - 0)/0 = inf). The normal is continuous in K1, so a
+// perturbation of K1 near the floor moves it a little, never by a whole
+// unit vector.
+template <class R>
+__device__ __forceinline__ R floor_weight(const DevParams<R> &P, R k) {
+    return k > P.k1_eps ? fmin((k - P.k1_eps) / P.k1_eps, R(1)) : R(0);
+}
+
 // FD: grad(phi) is given (the finite-difference variant) instead of recovered
-// from K1: n = grad/|grad| (0 where |grad| <= k1_eps, as for K1), S = s n,
+// from K1: n = grad/|grad| times floor_weight(|grad|), as for K1, S = s n,
 // |grad phi| = |grad|.
 // nw (wetting walls): the inward unit normal of the walls the node touches.
 // The normal from K1 is turned, keeping its direction along the wall, until
@@ -641,7 +651,8 @@ __device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)
     const R s = P.four_over_delta * phi * (R(1) - phi);
     if constexpr (FD) {
         const R gn = sqrt(fma(gfd[0], gfd[0], fma(gfd[1], gfd[1], gfd[2] * gfd[2])));
-        const R rg = gn > P.k1_eps ? recip(gn) : R(0);
+        const R wg = floor_weight(P, gn);
+        const R rg = wg > R(0) ? wg * recip(gn) : R(0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             m.n[a] = gfd[a] * rg;
@@ -657,15 +668,12 @@ __device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)
                     fma(P.c, first_moment<1>(gb), -phi * m.u[1]),
                     fma(P.c, first_moment<2>(gb), -phi * m.u[2])};
     const R k = sqrt(fma(K[0], K[0], fma(K[1], K[1], K[2] * K[2])));
-    const bool has_n = k > P.k1_eps;
+    const R wn = floor_weight(P, k);
+    const bool has_n = wn > R(0);
     const R rk = has_n ? recip(k) : R(0);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        m.n[a] = -K[a] * rk;
-        m.S[a] = s * m.n[a];
-    }
-    // |grad phi|: with n = -K1/|K1|, grad phi = n (tau cs2 s + |K1|)/((tau+1/2)cs2)
-    m.gnorm = has_n ? fabs(fma(P.tau_phi_cs2, s, k)) * P.inv_tp : k * P.inv_tp;
+    for (int a = 0; a < 3; ++a) m.n[a] = -K[a] * rk;  // the unit normal (or 0)
+    bool turned = false;
     if constexpr (WET) {
         if (nw.on && has_n) {
             const R dn = fma(m.n[0], nw.v[0], fma(m.n[1], nw.v[1], m.n[2] * nw.v[2]));
@@ -675,16 +683,24 @@ __device__ __forceinline__ Macro<R> moments(const DevParams<R> &P, const R (&fb)
             const R tt = sqrt(fma(t[0], t[0], fma(t[1], t[1], t[2] * t[2])));
             if (tt > R(1e-6)) {
                 const R st = wp.sin_theta / tt;
-                R gp[3];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    m.n[a] = fma(st, t[a], -wp.cos_theta * nw.v[a]);
-                    m.S[a] = s * m.n[a];
-                    gp[a] = fma(P.tau_phi_cs2, m.S[a], -K[a]) * P.inv_tp;
-                }
-                m.gnorm = sqrt(fma(gp[0], gp[0], fma(gp[1], gp[1], gp[2] * gp[2])));
+                for (int a = 0; a < 3; ++a) m.n[a] = fma(st, t[a], -wp.cos_theta * nw.v[a]);
+                turned = true;
             }
         }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        m.n[a] *= wn;
+        m.S[a] = s * m.n[a];
+    }
+    // |grad phi|: with n = -wn K1/|K1|, grad phi = n^ (tau cs2 s wn + |K1|)/((tau+1/2)cs2)
+    m.gnorm = fabs(fma(P.tau_phi_cs2, s * wn, k)) * P.inv_tp;
+    if (turned) {
+        R gp[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gp[a] = fma(P.tau_phi_cs2, m.S[a], -K[a]) * P.inv_tp;
+        m.gnorm = sqrt(fma(gp[0], gp[0], fma(gp[1], gp[1], gp[2] * gp[2])));
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -1245,9 +1261,10 @@ __device__ __forceinline__ void init_node(const double *phi0, const double *u0, 
     m.p = p0 ? p0[n] : 0.0;
     const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     const double s4 = P.four_over_delta * ph0 * (1.0 - ph0);
+    const double wg = floor_weight(P, gn);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        m.n[a] = gn > P.k1_eps ? g[a] / gn : 0.0;
+        m.n[a] = wg > 0.0 ? wg * g[a] / gn : 0.0;
         m.S[a] = s4 * m.n[a];
         m.gradrho[a] = P.drho * g[a];
     }
