@@ -21,6 +21,12 @@ using namespace cpf;
 
 namespace {
 
+// Discards an error that an earlier HIP call of another library left pending
+// in this thread, so that the check after an entry point's launches
+// (hipGetLastError) reports only that entry point's own failures.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
+
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -625,6 +631,7 @@ int lbm_workspace_bytes(const lbm_params *P, size_t *bytes) {
 
 int lbm_init(const lbm_params *P, void *d_workspace, size_t bytes, void *stream,
              const double *d_phi0, const double *d_u0, const double *d_p0, lbm_ctx **out) {
+    clear_stale_error();
     if (!out) return LBM_EINVAL;
     *out = nullptr;
     int rc = validate(P);
@@ -666,6 +673,7 @@ int lbm_init(const lbm_params *P, void *d_workspace, size_t bytes, void *stream,
 }
 
 int lbm_reset(lbm_ctx *c, const double *d_phi, const double *d_u, const double *d_p, int64_t t) {
+    clear_stale_error();
     if (!c || !d_phi || t < 0) return LBM_EINVAL;
     if (c->status == LBM_EDEVICE) return LBM_ESTATE;
     const int rc = build_state(c, d_phi, d_u, d_p);
@@ -681,6 +689,7 @@ int lbm_reset(lbm_ctx *c, const double *d_phi, const double *d_u, const double *
 }
 
 int lbm_step(lbm_ctx *c, int64_t n) {
+    clear_stale_error();
     if (!c || n < 0) return LBM_EINVAL;
     if (c->status != LBM_OK) return LBM_ESTATE;
     const Mode m = prop_mode(c);
@@ -720,6 +729,7 @@ int lbm_step(lbm_ctx *c, int64_t n) {
 }
 
 int lbm_fields(lbm_ctx *c, void *d_phi, void *d_u, void *d_p, int32_t dtype) {
+    clear_stale_error();
     if (!c || (dtype != 0 && dtype != 1)) return LBM_EINVAL;
     if (c->status == LBM_EDEVICE) return LBM_ESTATE;
     FieldOut o{};
@@ -732,6 +742,7 @@ int lbm_fields(lbm_ctx *c, void *d_phi, void *d_u, void *d_p, int32_t dtype) {
 }
 
 int lbm_diagnostics(lbm_ctx *c, const double *d_phi_ref, lbm_diag *out) {
+    clear_stale_error();
     if (!c || !out) return LBM_EINVAL;
     if (c->status == LBM_EDEVICE) return LBM_ESTATE;
     if (reduce_diag(c, d_phi_ref) != LBM_OK) return LBM_EDEVICE;
@@ -761,6 +772,7 @@ int lbm_diagnostics(lbm_ctx *c, const double *d_phi_ref, lbm_diag *out) {
 }
 
 int lbm_get_pdfs(lbm_ctx *c, double *d_f, double *d_g) {
+    clear_stale_error();
     if (!c || !d_f || !d_g) return LBM_EINVAL;
     if (c->status == LBM_EDEVICE) return LBM_ESTATE;
     FieldOut o{};
@@ -771,6 +783,7 @@ int lbm_get_pdfs(lbm_ctx *c, double *d_f, double *d_g) {
 }
 
 int lbm_set_pdfs(lbm_ctx *c, const double *d_f, const double *d_g) {
+    clear_stale_error();
     if (!c || !d_f || !d_g) return LBM_EINVAL;
     if (c->status == LBM_EDEVICE) return LBM_ESTATE;
     const int prev = c->cur ^ 1;

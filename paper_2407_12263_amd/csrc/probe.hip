@@ -8,6 +8,12 @@
 
 namespace {
 
+// Discards an error that an earlier HIP call of another library left pending
+// in this thread, so that the check after an entry point's launches
+// (hipGetLastError) reports only that entry point's own failures.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
+
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Four 16-byte values per thread and trip: the four loads are issued before
@@ -36,6 +42,7 @@ __global__ void __launch_bounds__(256) copy_kernel(const u32x4 *__restrict__ src
 
 extern "C" int probe_copy(const void *src, void *dst, size_t bytes, int32_t nontemporal,
                           int32_t blocks, void *stream) {
+    clear_stale_error();
     if (!src || !dst || bytes == 0 || bytes % 64 != 0 || blocks < 1 || blocks > (1 << 20))
         return PROBE_EINVAL;
     if (((uintptr_t)src | (uintptr_t)dst) % 16 != 0) return PROBE_EINVAL;

@@ -65,6 +65,16 @@ class LbmError(RuntimeError):
 _lib = None
 
 
+def hip_runtime_first():
+    """Loads PyTorch's HIP runtime before any of this package's libraries.
+    PyTorch ships its own libamdhip64 with the same soname as the system's;
+    a library of ours opened first would bring in the system copy and
+    PyTorch then a second one, and streams and device memory of one runtime
+    are invalid in the other (lbm_init then fails with LBM_EDEVICE). Opened
+    after PyTorch, our libraries bind to the runtime it already holds."""
+    import torch  # noqa: F401
+
+
 def load_library(path: str | None = None):
     """Loads liblbm.so (built by __graft_entry__.build()); raises if absent."""
     global _lib
@@ -73,6 +83,7 @@ def load_library(path: str | None = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise FileNotFoundError(f"HIP library {p} is not built; run __graft_entry__.build()")
+    hip_runtime_first()
     lib = C.CDLL(p)
     vp, dp = C.c_void_p, C.POINTER(C.c_double)
     lib.lbm_lattice.argtypes = [C.POINTER(C.c_int32), dp]

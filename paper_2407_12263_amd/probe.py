@@ -17,6 +17,8 @@ def load_library():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise FileNotFoundError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        from .lbm import hip_runtime_first
+        hip_runtime_first()  # one HIP runtime per process (see there)
         lib = C.CDLL(LIB_PATH)
         lib.probe_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_int32,
                                    C.c_void_p]
