@@ -14,6 +14,12 @@
 
 namespace {
 
+// Discards an error that an earlier HIP call of another library left pending
+// in this thread, so that the check after an entry point's launches
+// (hipGetLastError) reports only that entry point's own failures.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
+
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -27,6 +33,15 @@ __device__ __forceinline__ uint16_t f2bf(float x) {
 }
 
 __device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// f(integral_constant<int, i>) for i = B .. E - 1, unrolled at compile time.
+template <int B, int E, class F>
+__device__ __forceinline__ void unroll(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        unroll<B + 1, E>(f);
+    }
+}
 
 // e / c and e % c for element indices below 2^31 (32-bit unsigned).
 __device__ __forceinline__ long div32(long e, int c) { return (long)((uint32_t)e / (uint32_t)c); }
@@ -179,162 +194,303 @@ __global__ void __launch_bounds__(256) conv3d_kernel(const uint16_t *__restrict_
 // depend on how the hardware orders K within a step. The 14th step's second
 // tap does not exist and enters as zeros.
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
 constexpr int kTX = 16, kTY = 4, kTZ = 4;
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2, kHP = kHX * kHY * kHZ;
 constexpr int kNT = 2;  // 16-channel output tiles per block at most (LDS <= 48.4 KB)
+constexpr int kStage = 20;  // floats per point of the epilogue's staging rows (16 + 4 pad)
 
 static_assert(kHP * 2 > 1280 && kHP * 2 <= 1536, "six 16-byte halo pieces per thread");
+static_assert(4 * 64 * kStage * 4 <= kHP * 32, "the epilogue's staging fits in the halo area");
 
-// The halo of work item it of this (persistent) block (tile blockIdx.x + k
-// gridDim.x, k = it / nchunk, input chunk it % nchunk) into registers:
-// thread t holds the 16-byte pieces t, t + 256, ... of the kHP x 32 B halo.
-// Piece k (16 bytes) of the halo of work item it for this thread, or zeros
-// beyond the halo.
-__device__ __forceinline__ uint4 conv_halo_piece(const uint16_t *__restrict__ x, int cin, int nx,
-                                                 int ny, int nz, int ntx, int nty, int nchunk,
-                                                 int it, int k) {
-    const int c = threadIdx.x + 256 * k;
-    if (c >= kHP * 2) return uint4{0u, 0u, 0u, 0u};
-    const int tl = (int)blockIdx.x + (it / nchunk) * (int)gridDim.x, cc = (it % nchunk) * 16;
-    const int bx = tl % ntx, rest = tl / ntx, by = rest % nty, bz = rest / nty;
-    const int h = c >> 1;
-    const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
-    const int gp = wrap(bx * kTX - 1 + hx, nx) +
-                   nx * (wrap(by * kTY - 1 + hy, ny) + ny * wrap(bz * kTZ - 1 + hz, nz));
-    return *(const uint4 *)(x + gp * cin + cc + 8 * (c & 1));
+// Halo offset of tap t (x fastest) and the offset step from tap t to t + 1
+// (0 for the last tap, which has no partner in its K step).
+__host__ __device__ constexpr int tap_off(int t) {
+    return (t % 3 - 1) + kHX * ((t / 3) % 3 - 1) + kHX * kHY * (t / 9 - 1);
+}
+__host__ __device__ constexpr int pair_step(int t) { return t + 1 < 27 ? tap_off(t + 1) - tap_off(t) : 0; }
+// Over the K steps t = 0, 2, .., 26 whose pair step is d: the largest
+// -(s tap_off(t)), s = -1 for the flipped convolution. A lane base lowered
+// by it keeps every LDS offset of those steps a non-negative immediate.
+__host__ __device__ constexpr int step_bias(int d, int s) {
+    int k = -(1 << 20);
+    for (int t = 0; t < 27; t += 2)
+        if (pair_step(t) == d && -s * tap_off(t) > k) k = -s * tap_off(t);
+    return k;
 }
 
-// Weight rows (t, o) of an input chunk into LDS: w[t][cob + o][cc .. cc + 15].
-__device__ __forceinline__ void conv_stage_weights(uint4 *wl, const uint16_t *__restrict__ w,
-                                                   int cin, int cout, int cob, int nco, int cc) {
-    for (int c = threadIdx.x; c < 27 * nco * 2; c += 256) {
-        const int row = c >> 1, t = row / nco, o = row - t * nco;
-        wl[c] = *(const uint4 *)(w + (t * cout + cob + o) * cin + cc + 8 * (c & 1));
+// Grid of the tiled convolution (host-computed): sizes, tile counts, and for
+// power-of-two sizes the shifts that replace divisions and the periodic wrap.
+struct ConvGeom {
+    int nx, ny, nz;
+    int ntx, nty, ntz;
+    int lx, lxy;    // log2 nx, log2 (nx ny)
+    int ltx, ltxy;  // log2 ntx, log2 (ntx nty)
+};
+
+// Origin of tile tl (x fastest over tiles).
+template <bool POW2>
+__device__ __forceinline__ void tile_origin(const ConvGeom &G, int tl, int &x0, int &y0, int &z0) {
+    int bx, by, bz;
+    if constexpr (POW2) {
+        bx = tl & (G.ntx - 1);
+        by = (tl >> G.ltx) & (G.nty - 1);
+        bz = tl >> G.ltxy;
+    } else {
+        bx = tl % G.ntx;
+        const int rest = tl / G.ntx;
+        by = rest % G.nty;
+        bz = rest / G.nty;
+    }
+    x0 = bx * kTX;
+    y0 = by * kTY;
+    z0 = bz * kTZ;
+}
+
+// Point index of (x, y, z), each at most one period outside the grid.
+template <bool POW2>
+__device__ __forceinline__ int grid_point(const ConvGeom &G, int x, int y, int z) {
+    if constexpr (POW2)
+        return (x & (G.nx - 1)) | ((y & (G.ny - 1)) << G.lx) | ((z & (G.nz - 1)) << G.lxy);
+    else
+        return wrap(x, G.nx) + G.nx * (wrap(y, G.ny) + G.ny * wrap(z, G.nz));
+}
+
+// One 16-byte piece of a work item's halo: halo point hp (packed hx | hy << 8
+// | hz << 16, or -1 for no piece) of the tile at (x0, y0, z0), channels
+// cc + 8 part .. + 7.
+template <bool POW2>
+__device__ __forceinline__ uint4 halo_piece(const uint16_t *__restrict__ x, int cin,
+                                            const ConvGeom &G, int x0, int y0, int z0, int cc,
+                                            int hp, int part) {
+    if (hp < 0) return uint4{0u, 0u, 0u, 0u};
+    const int gp = grid_point<POW2>(G, x0 - 1 + (hp & 255), y0 - 1 + ((hp >> 8) & 255),
+                                    z0 - 1 + (hp >> 16));
+    return *(const uint4 *)(x + (uint32_t)gp * (uint32_t)cin + cc + 8 * part);
+}
+
+// The 14 K steps of one work item from LDS into the accumulators of the
+// first NTA of the block's NT output tiles (NTA is the number the block
+// actually has, so the loop carries no per-step test of it). baseA0..3: the
+// lane's A bases of the four step classes (pair step 0, 1, kHX - 2,
+// kHX kHY - 2 kHX - 2), baseB its weight base; every read adds an immediate.
+// With PIPE (blocks of one output tile) the loop is software-pipelined: the
+// fragments of step s + 1 are read before the MFMAs of step s are issued (the
+// scheduling barriers keep that order), so each wavefront has a whole step's
+// reads in flight while its MFMAs run. Two output tiles would need the
+// registers of a third wavefront per SIMD for it.
+template <int NTA, int NT, bool FLIP, bool PIPE>
+__device__ __forceinline__ void conv_kloop(const uint4 *tile, const uint4 *wl, int baseA0, int baseA1,
+                                           int baseA2, int baseA3, int baseB, int second,
+                                           f4 (&acc)[4][NT]) {
+    constexpr int S = FLIP ? -1 : 1;
+    constexpr int NCO = 16 * NT;
+    constexpr int D1 = pair_step(0), D2 = pair_step(2), D3 = pair_step(8);
+    const uint4 z4 = uint4{0u, 0u, 0u, 0u};
+    bf8 a[2][4], b[2][NTA];
+    auto load = [&](auto T, int buf) {
+        constexpr int t = decltype(T)::value;
+        constexpr int d = pair_step(t);
+        const int base = d == D1 ? baseA1 : (d == D2 ? baseA2 : (d == D3 ? baseA3 : baseA0));
+        constexpr int imm = 2 * (S * tap_off(t) + step_bias(d, S));
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            uint4 v = tile[base + imm + 2 * kHX * mt];
+            if (t + 1 >= 27 && second) v = z4;
+            a[buf][mt] = __builtin_bit_cast(bf8, v);
+        }
+#pragma unroll
+        for (int nt = 0; nt < NTA; ++nt) {
+            uint4 v = wl[baseB + 2 * (t * NCO + nt * 16)];
+            if (t + 1 >= 27 && second) v = z4;
+            b[buf][nt] = __builtin_bit_cast(bf8, v);
+        }
+    };
+    auto mfmas = [&](int buf) {
+#pragma unroll
+        for (int nt = 0; nt < NTA; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[buf][mt], b[buf][nt],
+                                                                       acc[mt][nt], 0, 0, 0);
+    };
+    if constexpr (PIPE) {
+        load(std::integral_constant<int, 0>{}, 0);
+        unroll<0, 14>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            if constexpr (k + 1 < 14) load(std::integral_constant<int, 2 * (k + 1)>{}, (k + 1) & 1);
+            __builtin_amdgcn_sched_barrier(0);
+            mfmas(k & 1);
+            __builtin_amdgcn_sched_barrier(0);
+        });
+    } else {
+        unroll<0, 14>([&](auto K) {
+            load(std::integral_constant<int, 2 * decltype(K)::value>{}, 0);
+            mfmas(0);
+        });
     }
 }
 
-template <int NT>
+// The same convolution for grids whose sizes are multiples of the 16 x 4 x 4
+// point tile. Blocks are persistent: block b takes the tiles b, b + gridDim.x,
+// ..., each over its 16-channel input chunks, and stages an item's 18 x 6 x 6
+// halo (32 B per point, 20.7 KB) and the chunk's weights in LDS, so each
+// input value is read from memory about 2.5 times instead of 27 times. While
+// an item is computed from LDS, each thread's six 16-byte pieces of the next
+// item's halo are already loading into registers. Wavefront w owns plane
+// z0 + w of the tile: four rows of 16 points, the four M tiles; a block
+// computes NT 16-channel N tiles (one for 16 output channels, run at four
+// wavefronts per SIMD; two otherwise). The K steps use the 16x16x32 BF16
+// MFMA; one step covers two taps (lanes l / 16 = 0, 1: tap t, 2, 3: tap
+// t + 1) x 16 channels (8 per lane). A and B place the same (tap, channel)
+// in the same lane group and element, so the product does not depend on how
+// the hardware orders K within a step. The 14th step's second tap does not
+// exist and enters as zeros.
+// Addressing costs no vector instruction in the K loop: the flip is a
+// template parameter, every LDS read is a per-lane base (one per step class
+// of tap pairs, see step_bias) plus an immediate. The epilogue stages each
+// wavefront's 64 x 16 results in LDS (FP32 rows of kStage floats) so that
+// every point's 16 channels leave as 16-byte stores, converted to BF16 by
+// the hardware (round to nearest even).
+template <int NT, bool FLIP, bool POW2>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 4 : 1, 8)))
 conv3d_tiled_kernel(
     const uint16_t *__restrict__ x, int cin, const uint16_t *__restrict__ w,
-    const float *__restrict__ bias, int cout, int nx, int ny, int nz, int flip, int relu,
+    const float *__restrict__ bias, int cout, ConvGeom G, int relu,
     const uint16_t *__restrict__ mask, uint16_t *__restrict__ yb, float *__restrict__ yf) {
     // LDS: the input halo (kHP points x 16 channels) and the chunk's weights
-    // (27 taps x the block's output channels x 16 channels), 32 B per row
+    // (27 taps x 16 NT output channels x 16 channels), 32 B per row
     extern __shared__ uint4 lds[];
     uint4 *tile = lds, *wl = lds + kHP * 2;
+    constexpr int S = FLIP ? -1 : 1;
+    constexpr int NCO = 16 * NT;  // weight rows per tap in LDS
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, q = lane >> 4;
-    const int ntx = nx / kTX, nty = ny / kTY;
-    const int ntile = ntx * nty * (nz / kTZ);
-    const int nchunk = cin / 16;
-    const int cob = blockIdx.y * (16 * NT);
-    const int ntiles = min(NT, (cout - cob) >> 4);
+    const int half = q & 1, second = q >> 1;
+    const int ntile = G.ntx * G.nty * G.ntz;
+    const int nchunk = cin >> 4;
+    const int cob = blockIdx.y * NCO;
+    const int ntiles = NT == 1 ? 1 : min(NT, (cout - cob) >> 4);
     const int nco = ntiles * 16;
-    const int half = q & 1;
-    const int sgn = flip ? -1 : 1;
-    // halo index of the lane's point in M tile 0 (tile x = r, y = 0, z = wave)
-    const int hb = (r + 1) + kHX * (1 + kHY * (wave + 1));
-    const uint4 z4 = uint4{0u, 0u, 0u, 0u};
-    // work items of this (persistent) block: (tile blockIdx.x + k gridDim.x,
-    // input chunk); the halo of the next item is loaded into registers while
-    // the current one is computed from LDS
+    // halo index (uint4 units) of the lane's point in M tile 0 and its part
+    const int hb2 = 2 * ((r + 1) + kHX * (1 + kHY * (wave + 1))) + half;
+    // per step class of tap pairs: lane base of the A reads (see step_bias)
+    constexpr int D1 = pair_step(0), D2 = pair_step(2), D3 = pair_step(8);
+    static_assert(D1 == 1 && D2 == kHX - 2 && D3 == kHX * kHY - 2 * kHX - 2, "tap pair steps");
+    const int baseA1 = hb2 + 2 * S * second * D1 - 2 * step_bias(D1, S);
+    const int baseA2 = hb2 + 2 * S * second * D2 - 2 * step_bias(D2, S);
+    const int baseA3 = hb2 + 2 * S * second * D3 - 2 * step_bias(D3, S);
+    const int baseA0 = hb2 - 2 * step_bias(0, S);
+    const int baseB = 2 * (second * NCO + r) + half;
+    // this thread's halo pieces c = threadIdx.x + 256 k: point (packed) or -1
+    int hp[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int c = threadIdx.x + 256 * k, h = c >> 1;
+        hp[k] = c < kHP * 2 ? (h % kHX) | (((h / kHX) % kHY) << 8) | ((h / (kHX * kHY)) << 16) : -1;
+    }
+    const int part = threadIdx.x & 1;
     const int nmine = ntile > (int)blockIdx.x ? (ntile - 1 - (int)blockIdx.x) / (int)gridDim.x + 1 : 0;
-    const int nwork = nmine * nchunk;
-    // the thread's six halo pieces of the next item, held in registers
-    uint4 pf0, pf1, pf2, pf3, pf4, pf5;
-#define CONV_LOAD_HALO(it)                                                   \
-    do {                                                                     \
-        pf0 = conv_halo_piece(x, cin, nx, ny, nz, ntx, nty, nchunk, it, 0);  \
-        pf1 = conv_halo_piece(x, cin, nx, ny, nz, ntx, nty, nchunk, it, 1);  \
-        pf2 = conv_halo_piece(x, cin, nx, ny, nz, ntx, nty, nchunk, it, 2);  \
-        pf3 = conv_halo_piece(x, cin, nx, ny, nz, ntx, nty, nchunk, it, 3);  \
-        pf4 = conv_halo_piece(x, cin, nx, ny, nz, ntx, nty, nchunk, it, 4);  \
-        pf5 = conv_halo_piece(x, cin, nx, ny, nz, ntx, nty, nchunk, it, 5);  \
-    } while (0)
-    if (nwork > 0) CONV_LOAD_HALO(0);
-    if (nchunk == 1) conv_stage_weights(wl, w, cin, cout, cob, nco, 0);  // the same for every item
+    uint4 pf[6];
+    auto load_halo = [&](int k, int chunk) {
+        int ox, oy, oz;
+        tile_origin<POW2>(G, (int)blockIdx.x + k * (int)gridDim.x, ox, oy, oz);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) pf[j] = halo_piece<POW2>(x, cin, G, ox, oy, oz, chunk * 16, hp[j], part);
+    };
+    // weight rows (t, o) of input chunk cc: w[t][cob + o][cc .. cc + 15]
+    auto stage_weights = [&](int cc) {
+        const int ls = ntiles == 2 ? 5 : 4;
+        for (int c = threadIdx.x; c < 27 * nco * 2; c += 256) {
+            const int row = c >> 1, t = row >> ls, o = row & (nco - 1);
+            wl[2 * (t * NCO + o) + (c & 1)] = *(const uint4 *)(w + (t * cout + cob + o) * cin + cc + 8 * (c & 1));
+        }
+    };
+    if (nmine > 0) load_halo(0, 0);
+    if (nchunk == 1) stage_weights(0);  // the same for every item
     f4 acc[4][NT];
-    for (int it = 0; it < nwork; ++it) {
-        const int chunk = it % nchunk;
-        __syncthreads();  // the previous item's reads are done
-        tile[threadIdx.x] = pf0;
-        tile[threadIdx.x + 256] = pf1;
-        tile[threadIdx.x + 512] = pf2;
-        tile[threadIdx.x + 768] = pf3;
-        tile[threadIdx.x + 1024] = pf4;
-        if (threadIdx.x + 1280 < kHP * 2) tile[threadIdx.x + 1280] = pf5;
-        if (nchunk > 1) conv_stage_weights(wl, w, cin, cout, cob, nco, chunk * 16);
-        __syncthreads();
-        if (it + 1 < nwork) CONV_LOAD_HALO(it + 1);
-        if (chunk == 0) {
+    for (int k = 0; k < nmine; ++k) {
+        for (int chunk = 0; chunk < nchunk; ++chunk) {
+            __syncthreads();  // the previous item's reads are done
+#pragma unroll
+            for (int j = 0; j < 5; ++j) tile[threadIdx.x + 256 * j] = pf[j];
+            if (threadIdx.x + 1280 < kHP * 2) tile[threadIdx.x + 1280] = pf[5];
+            if (nchunk > 1) stage_weights(chunk * 16);
+            __syncthreads();
+            if (chunk + 1 < nchunk) load_halo(k, chunk + 1);
+            else if (k + 1 < nmine) load_halo(k + 1, 0);
+            if (chunk == 0) {
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+            }
+            if (NT == 1 || ntiles == NT)
+                conv_kloop<NT, NT, FLIP, NT == 1>(tile, wl, baseA0, baseA1, baseA2, baseA3, baseB,
+                                                 second, acc);
+            else
+                conv_kloop<1, NT, FLIP, false>(tile, wl, baseA0, baseA1, baseA2, baseA3, baseB,
+                                              second, acc);
+        }
+        // epilogue: through LDS, one point's 16 channels per lane
+        int x0, y0, z0;
+        tile_origin<POW2>(G, (int)blockIdx.x + k * (int)gridDim.x, x0, y0, z0);
+        float *st = (float *)tile + wave * (64 * kStage);
+        const int pmt = lane >> 4, px = lane & 15;
+        const int p = grid_point<POW2>(G, x0 + px, y0 + pmt, z0 + wave);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            if (nt >= ntiles) break;
+            __syncthreads();  // the halo (or the previous pass's staging) is no longer read
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
-        }
+                for (int j = 0; j < 4; ++j) st[(mt * 16 + 4 * q + j) * kStage + r] = acc[mt][nt][j];
+            __syncthreads();
+            const int co0 = cob + nt * 16;
+            float v[16];
 #pragma unroll
-        for (int t = 0; t < 27; t += 2) {
-            // halo offsets of taps t and t + 1 (constants once unrolled),
-            // negated for the flipped convolution
-            const int offa = (t % 3 - 1) + kHX * (((t / 3) % 3 - 1) + kHY * (t / 9 - 1));
-            const int t1 = t + 1 < 27 ? t + 1 : t;
-            const int offb = (t1 % 3 - 1) + kHX * (((t1 / 3) % 3 - 1) + kHY * (t1 / 9 - 1));
-            const bool second = (q >> 1) != 0;
-            const bool tv = !second || t + 1 < 27;
-            const int tc = second ? t1 : t;
-            const int off = sgn * (second ? offb : offa);
-            bf8 a[4], b[NT];
+            for (int c4 = 0; c4 < 4; ++c4) {
+                const f4 s = *(const f4 *)(st + lane * kStage + 4 * c4);
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
-                a[mt] = __builtin_bit_cast(bf8, tv ? tile[2 * (hb + kHX * mt + off) + half] : z4);
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                uint4 v = z4;
-                if (nt < ntiles && tv) v = wl[2 * (tc * nco + nt * 16 + r) + half];
-                b[nt] = __builtin_bit_cast(bf8, v);
+                for (int e = 0; e < 4; ++e) v[4 * c4 + e] = s[e];
             }
+            if (bias) {
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                if (nt < ntiles) {
-#pragma unroll
-                    for (int mt = 0; mt < 4; ++mt)
-                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt],
-                                                                               acc[mt][nt], 0, 0, 0);
-                }
+                for (int c = 0; c < 16; ++c) v[c] += bias[co0 + c];
             }
-        }
-        if (chunk == nchunk - 1) {
-            const int tl = (int)blockIdx.x + (it / nchunk) * (int)gridDim.x;
-            const int bx = tl % ntx, rest = tl / ntx, by = rest % nty, bz = rest / nty;
-            const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
+            if (relu) {
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const int prow = nx * ((y0 + mt) + ny * (z0 + wave));
+                for (int c = 0; c < 16; ++c) v[c] = fmaxf(v[c], 0.f);
+            }
+            const uint32_t o = (uint32_t)p * (uint32_t)cout + co0;
+            if (mask) {
+                const uint4 m0 = *(const uint4 *)(mask + o), m1 = *(const uint4 *)(mask + o + 8);
+                const uint32_t mw[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    if (nt >= ntiles) continue;
-                    const int co = cob + nt * 16 + r;
-                    const float bb = bias ? bias[co] : 0.f;
+                for (int c = 0; c < 16; ++c)
+                    if (!(bf2f((uint16_t)(mw[c >> 1] >> (16 * (c & 1)))) > 0.f)) v[c] = 0.f;
+            }
+            if (yb) {
+                uint32_t pk[8];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int p = prow + x0 + 4 * q + j;
-                        float v = acc[mt][nt][j] + bb;
-                        if (relu) v = fmaxf(v, 0.f);
-                        if (mask && !(bf2f(mask[p * cout + co]) > 0.f)) v = 0.f;
-                        if (yb) yb[p * cout + co] = f2bf(v);
-                        if (yf) yf[p * cout + co] = v;
-                    }
-                }
+                for (int c = 0; c < 8; ++c)
+                    pk[c] = __builtin_bit_cast(uint32_t, __builtin_convertvector(fl2{v[2 * c], v[2 * c + 1]}, bf2));
+                *(uint4 *)(yb + o) = uint4{pk[0], pk[1], pk[2], pk[3]};
+                *(uint4 *)(yb + o + 8) = uint4{pk[4], pk[5], pk[6], pk[7]};
+            }
+            if (yf) {
+#pragma unroll
+                for (int c4 = 0; c4 < 4; ++c4)
+                    *(f4 *)(yf + o + 4 * c4) = f4{v[4 * c4], v[4 * c4 + 1], v[4 * c4 + 2], v[4 * c4 + 3]};
             }
         }
     }
 }
 
-#undef CONV_LOAD_HALO
-
-// LDS bytes of conv3d_tiled_kernel for a block of nco output channels.
-size_t conv_tiled_lds(int nco) { return (size_t)(kHP * 2 + 27 * nco * 2) * sizeof(uint4); }
+// LDS bytes of conv3d_tiled_kernel with NT output tiles per block.
+size_t conv_tiled_lds(int nt) { return (size_t)(kHP * 2 + 27 * 16 * nt * 2) * sizeof(uint4); }
 
 // Weight gradient of one tap over one chunk of points:
 // dW[t][o][i] = sum_p dY[p][o] X[p + d_t][i], an M = cout, N = cin, K = points
@@ -429,7 +585,10 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const uint16_t *__restrict__
 // products on the 16x16x32 BF16 MFMA. A persistent block takes tiles
 // blockIdx.x, + gridDim.x, ... for the 16 input channels blockIdx.y; per tile
 // it stages in LDS the output gradient transposed, dYt[o][point], and the
-// input halo transposed, XhT[i][hz][hy][hx] (rows of 24, 16-byte aligned).
+// input halo transposed, XhT[i][hz][hy][hx] (rows of 24, 16-byte aligned;
+// the planes of consecutive channels, and the rows dYt[o] of consecutive
+// output channels, start an odd multiple of 16 bytes apart modulo 256, so the
+// 16-byte fragment reads of eight consecutive lanes fall in distinct banks).
 // K steps take 32 points (two 16-point rows); a lane's 8 consecutive k are
 // 8 consecutive x, so its A fragment (dY of one output channel) is one
 // aligned 16-byte read, shared by all the wavefront's taps, and its B
@@ -447,10 +606,12 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
                                                           float *__restrict__ part,
                                                           float *__restrict__ bpart) {
     constexpr int kRow = 24;                    // hx row length in XhT
-    constexpr int kXh = 16 * kHZ * kHY * kRow;  // XhT elements
+    constexpr int kCh = kHZ * kHY * kRow + 8;   // XhT channel stride (1744 B)
+    constexpr int kXh = 16 * kCh;               // XhT elements
+    constexpr int kDy = 256 + 8;                // dYt row stride (528 B)
     constexpr int kNTap = 9;                    // taps per wavefront: 3 rows x 3 dx at most
     __shared__ __attribute__((aligned(16))) uint16_t xht[kXh];
-    __shared__ __attribute__((aligned(16))) uint16_t dyt[MT * 16 * 256];
+    __shared__ __attribute__((aligned(16))) uint16_t dyt[MT * 16 * kDy];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, q = lane >> 4;
     const int cc = blockIdx.y * 16;
@@ -479,7 +640,7 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
             const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                xht[(((e0 + e) * kHZ + hz) * kHY + hy) * kRow + hx] = uint16_t(wd[e >> 1] >> (16 * (e & 1)));
+                xht[(e0 + e) * kCh + (hz * kHY + hy) * kRow + hx] = uint16_t(wd[e >> 1] >> (16 * (e & 1)));
         }
         // output gradient of the tile's points, transposed
         for (int c = threadIdx.x; c < 256 * MT * 2; c += 256) {
@@ -488,11 +649,11 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
             const uint4 v = *(const uint4 *)(dy + gp * cout + 8 * oc);
             const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-            for (int e = 0; e < 8; ++e) dyt[(8 * oc + e) * 256 + pl] = uint16_t(wd[e >> 1] >> (16 * (e & 1)));
+            for (int e = 0; e < 8; ++e) dyt[(8 * oc + e) * kDy + pl] = uint16_t(wd[e >> 1] >> (16 * (e & 1)));
         }
         __syncthreads();
         if (do_bias) {
-            const uint16_t *row = dyt + (threadIdx.x >> 2) * 256 + 64 * (threadIdx.x & 3);
+            const uint16_t *row = dyt + (threadIdx.x >> 2) * kDy + 64 * (threadIdx.x & 3);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const uint4 v = *(const uint4 *)(row + 8 * k);
@@ -509,7 +670,7 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
             bf8 a[MT];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
-                a[mt] = __builtin_bit_cast(bf8, *(const uint4 *)(dyt + (mt * 16 + r) * 256 + pl0));
+                a[mt] = __builtin_bit_cast(bf8, *(const uint4 *)(dyt + (mt * 16 + r) * kDy + pl0));
             // wavefront w takes the tap rows (dy, dz) w, w + 4, w + 8: the
             // three dx taps of a row start dx + 1 elements into the same two
             // aligned 16-byte words (lx0 is 0 or 8), read once per row
@@ -519,7 +680,7 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
                 if (rid < 9) {
                     const int dyo = rid % 3 - 1, dz = rid / 3 - 1;
                     const uint16_t *row =
-                        xht + ((r * kHZ + lz + dz + 1) * kHY + ly + dyo + 1) * kRow + lx0;
+                        xht + r * kCh + ((lz + dz + 1) * kHY + ly + dyo + 1) * kRow + lx0;
                     const uint4 w0 = *(const uint4 *)row;
                     const uint4 w1 = *(const uint4 *)(row + 8);
                     const uint4 bw[3] = {
@@ -1408,6 +1569,13 @@ bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 // 2048 measured best of 512 .. 4096 on the U-Net's 128^3 layers (within 5%
 // everywhere). SUR_CONV_BLOCKS overrides it (tuning only; results do not
 // depend on it).
+bool pow2_ok(int n) { return n > 0 && (n & (n - 1)) == 0; }
+int ilog2(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
 int env_blocks() {
     const char *v = std::getenv("SUR_CONV_BLOCKS");
     return v && *v ? std::max(1, std::atoi(v)) : 2048;
@@ -1436,6 +1604,7 @@ extern "C" {
 int sur_conv3d(const void *x, int32_t cin, const void *w, const float *bias, int32_t cout,
                int32_t nx, int32_t ny, int32_t nz, int32_t flip, int32_t relu, const void *mask,
                void *y_bf16, float *y_f32, void *stream) {
+    clear_stale_error();
     if (!x || !w || (!y_bf16 && !y_f32) || cin <= 0 || cout <= 0 || cin % 16 || cout % 16 ||
         !dims_ok(nx, ny, nz))
         return SUR_EINVAL;
@@ -1450,15 +1619,29 @@ int sur_conv3d(const void *x, int32_t cin, const void *w, const float *bias, int
         const long ncb = (cout + nb - 1) / nb;
         const long nblk = std::max(1L, std::min(tiles, (long)env_blocks() / ncb));
         const dim3 grid((unsigned)nblk, (unsigned)ncb);
-        const size_t lds = conv_tiled_lds(std::min(cout, nb));
-        if (nt == 1)
-            hipLaunchKernelGGL(conv3d_tiled_kernel<1>, grid, dim3(256), lds, (hipStream_t)stream,
-                               (const uint16_t *)x, cin, (const uint16_t *)w, bias, cout, nx, ny, nz,
-                               flip, relu, (const uint16_t *)mask, (uint16_t *)y_bf16, y_f32);
-        else
-            hipLaunchKernelGGL(conv3d_tiled_kernel<kNT>, grid, dim3(256), lds, (hipStream_t)stream,
-                               (const uint16_t *)x, cin, (const uint16_t *)w, bias, cout, nx, ny, nz,
-                               flip, relu, (const uint16_t *)mask, (uint16_t *)y_bf16, y_f32);
+        const size_t lds = conv_tiled_lds(nt);
+        ConvGeom G{nx, ny, nz, nx / kTX, ny / kTY, nz / kTZ, 0, 0, 0, 0};
+        const bool pow2 = pow2_ok(nx) && pow2_ok(ny) && pow2_ok(nz);
+        if (pow2) {
+            G.lx = ilog2(nx);
+            G.lxy = ilog2(nx) + ilog2(ny);
+            G.ltx = ilog2(G.ntx);
+            G.ltxy = ilog2(G.ntx) + ilog2(G.nty);
+        }
+        hipStream_t st = (hipStream_t)stream;
+        const uint16_t *xb = (const uint16_t *)x, *wb = (const uint16_t *)w, *mb = (const uint16_t *)mask;
+        uint16_t *yb = (uint16_t *)y_bf16;
+#define SUR_CONV_LAUNCH(NTV, FL, P2)                                                              \
+    hipLaunchKernelGGL((conv3d_tiled_kernel<NTV, FL, P2>), grid, dim3(256), lds, st, xb, cin, wb, \
+                       bias, cout, G, relu, mb, yb, y_f32)
+        if (nt == 1) {
+            if (flip) { if (pow2) SUR_CONV_LAUNCH(1, true, true); else SUR_CONV_LAUNCH(1, true, false); }
+            else { if (pow2) SUR_CONV_LAUNCH(1, false, true); else SUR_CONV_LAUNCH(1, false, false); }
+        } else {
+            if (flip) { if (pow2) SUR_CONV_LAUNCH(kNT, true, true); else SUR_CONV_LAUNCH(kNT, true, false); }
+            else { if (pow2) SUR_CONV_LAUNCH(kNT, false, true); else SUR_CONV_LAUNCH(kNT, false, false); }
+        }
+#undef SUR_CONV_LAUNCH
         return launched();
     }
     const dim3 grid((unsigned)((P + 255) / 256), (unsigned)((cout + 63) / 64));
@@ -1481,6 +1664,7 @@ size_t sur_wgrad_scratch_floats(int32_t cin, int32_t cout, int32_t nx, int32_t n
 int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, int32_t nx,
                      int32_t ny, int32_t nz, float *scratch, size_t scratch_floats, float *dw,
                      float *dbias, void *stream) {
+    clear_stale_error();
     if (!x || !dy || !scratch || !dw || cin <= 0 || cout <= 0 || cin % 16 || cout % 16 ||
         cout > 64 || !dims_ok(nx, ny, nz))
         return SUR_EINVAL;
@@ -1563,6 +1747,7 @@ int sur_conv3d_wgrad(const void *x, int32_t cin, const void *dy, int32_t cout, i
 
 int sur_pack_weights_all(const float *w, int32_t nlayers, const int64_t *w_off, const int32_t *cin,
                          const int32_t *cout, void *wf, void *wd, void *stream) {
+    clear_stale_error();
     if (!w || !w_off || !cin || !cout || !wf || !wd || nlayers <= 0 || nlayers > kMaxPackLayers)
         return SUR_EINVAL;
     PackTable tb;
@@ -1581,6 +1766,7 @@ int sur_pack_weights_all(const float *w, int32_t nlayers, const int64_t *w_off, 
 }
 
 int sur_pack_weights(const float *w, int32_t cin, int32_t cout, void *wf, void *wd, void *stream) {
+    clear_stale_error();
     if (!w || (!wf && !wd) || cin <= 0 || cout <= 0) return SUR_EINVAL;
     const long n = 27L * cin * cout;
     hipLaunchKernelGGL(pack_weights_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, w, cin,
@@ -1589,6 +1775,7 @@ int sur_pack_weights(const float *w, int32_t cin, int32_t cout, void *wf, void *
 }
 
 int sur_pool2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void *y, void *stream) {
+    clear_stale_error();
     if (!x || !y || c <= 0 || !dims_ok(nx, ny, nz) || nx % 2 || ny % 2 || nz % 2 ||
         !elems_ok((long)nx * ny * nz, c))
         return SUR_EINVAL;
@@ -1605,6 +1792,7 @@ int sur_pool2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void
 
 int sur_pool2_bwd(const float *dy, int32_t c, int32_t nx, int32_t ny, int32_t nz, float *dx,
                   void *stream) {
+    clear_stale_error();
     if (!dy || !dx || c <= 0 || !dims_ok(nx, ny, nz) || nx % 2 || ny % 2 || nz % 2 ||
         !elems_ok((long)nx * ny * nz, c))
         return SUR_EINVAL;
@@ -1617,6 +1805,7 @@ int sur_pool2_bwd(const float *dy, int32_t c, int32_t nx, int32_t ny, int32_t nz
 int sur_pool2_bwd_skip(const float *dy, int32_t c, int32_t nx, int32_t ny, int32_t nz,
                        const float *skip, int32_t skip_stride, int32_t skip_off, const void *act,
                        float *dx, void *dx_bf16, void *stream) {
+    clear_stale_error();
     if (!dy || !skip || !act || (!dx && !dx_bf16) || c <= 0 || !dims_ok(nx, ny, nz) || nx % 2 || ny % 2 ||
         nz % 2 || skip_off < 0 || skip_off + c > skip_stride ||
         !elems_ok((long)nx * ny * nz, skip_stride))
@@ -1639,6 +1828,7 @@ int sur_pool2_bwd_skip(const float *dy, int32_t c, int32_t nx, int32_t ny, int32
 int sur_upsample2_bwd_mask(const float *dy, int32_t dystride, int32_t dyoff, int32_t c,
                            int32_t nx, int32_t ny, int32_t nz, const void *act, void *dx_bf16,
                            void *stream) {
+    clear_stale_error();
     if (!dy || !act || !dx_bf16 || c <= 0 || !dims_ok(nx, ny, nz) || dyoff < 0 ||
         dyoff + c > dystride || !elems_ok(8L * nx * ny * nz, dystride))
         return SUR_EINVAL;
@@ -1658,6 +1848,7 @@ int sur_upsample2_bwd_mask(const float *dy, int32_t dystride, int32_t dyoff, int
 
 int sur_upsample2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, void *y,
                   int32_t ystride, int32_t yoff, void *stream) {
+    clear_stale_error();
     if (!x || !y || c <= 0 || !dims_ok(nx, ny, nz) || yoff < 0 || yoff + c > ystride ||
         !elems_ok(8L * nx * ny * nz, ystride))
         return SUR_EINVAL;
@@ -1674,6 +1865,7 @@ int sur_upsample2(const void *x, int32_t c, int32_t nx, int32_t ny, int32_t nz, 
 
 int sur_upsample2_bwd(const float *dy, int32_t dystride, int32_t dyoff, int32_t c, int32_t nx,
                       int32_t ny, int32_t nz, float *dx, void *stream) {
+    clear_stale_error();
     if (!dy || !dx || c <= 0 || !dims_ok(nx, ny, nz) || dyoff < 0 || dyoff + c > dystride ||
         !elems_ok(8L * nx * ny * nz, dystride))
         return SUR_EINVAL;
@@ -1685,6 +1877,7 @@ int sur_upsample2_bwd(const float *dy, int32_t dystride, int32_t dyoff, int32_t 
 
 int sur_concat_up2(const void *xc, int32_t hc, const void *xf, int32_t fc, int32_t nx, int32_t ny,
                    int32_t nz, void *y, void *stream) {
+    clear_stale_error();
     if (!xc || !xf || !y || hc <= 0 || fc <= 0 || !dims_ok(nx, ny, nz) || nx % 2 || ny % 2 ||
         nz % 2 || !elems_ok((long)nx * ny * nz, hc + fc))
         return SUR_EINVAL;
@@ -1703,6 +1896,7 @@ int sur_concat_up2(const void *xc, int32_t hc, const void *xf, int32_t fc, int32
 
 int sur_copy_channels(const void *x, int32_t c, int64_t P, void *y, int32_t ystride, int32_t yoff,
                       void *stream) {
+    clear_stale_error();
     if (!x || !y || c <= 0 || P <= 0 || yoff < 0 || yoff + c > ystride || !elems_ok(P, ystride))
         return SUR_EINVAL;
     if (c % 8 == 0 && ystride % 8 == 0 && yoff % 8 == 0 && aligned16(x) && aligned16(y)) {
@@ -1718,6 +1912,7 @@ int sur_copy_channels(const void *x, int32_t c, int64_t P, void *y, int32_t ystr
 
 int sur_add_channels(const float *dy, int32_t dystride, int32_t dyoff, int32_t c, int64_t P,
                      float *dx, void *stream) {
+    clear_stale_error();
     if (!dy || !dx || c <= 0 || P <= 0 || dyoff < 0 || dyoff + c > dystride ||
         !elems_ok(P, dystride))
         return SUR_EINVAL;
@@ -1727,6 +1922,7 @@ int sur_add_channels(const float *dy, int32_t dystride, int32_t dyoff, int32_t c
 }
 
 int sur_to_bf16(const float *x, int64_t n, void *y, void *stream) {
+    clear_stale_error();
     if (!x || !y || n < 0) return SUR_EINVAL;
     if (n == 0) return SUR_OK;
     hipLaunchKernelGGL(to_bf16_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, x, (long)n,
@@ -1735,6 +1931,7 @@ int sur_to_bf16(const float *x, int64_t n, void *y, void *stream) {
 }
 
 int sur_relu_mask(float *dx, const void *act, int64_t n, void *stream) {
+    clear_stale_error();
     if (!dx || !act || n < 0) return SUR_EINVAL;
     if (n == 0) return SUR_OK;
     hipLaunchKernelGGL(relu_mask_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, dx,
@@ -1745,6 +1942,7 @@ int sur_relu_mask(float *dx, const void *act, int64_t n, void *stream) {
 int sur_mse(const float *pred, const float *target, int32_t cu, int32_t cs, int64_t P,
             const float *wch, float *grad, void *grad_bf16, double *scratch, double *loss_out,
             void *stream) {
+    clear_stale_error();
     if (!pred || !target || !wch || (!grad && !grad_bf16) || !scratch || !loss_out || cu <= 0 ||
         cs < cu || P <= 0)
         return SUR_EINVAL;
@@ -1761,6 +1959,7 @@ int sur_mse(const float *pred, const float *target, int32_t cu, int32_t cs, int6
 
 int sur_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float beta1,
              float beta2, float eps, int32_t t, void *stream) {
+    clear_stale_error();
     if (!w || !m || !v || !g || n <= 0 || t < 1) return SUR_EINVAL;
     const float bc1 = 1.f - (float)pow((double)beta1, (double)t);
     const float bc2 = 1.f - (float)pow((double)beta2, (double)t);
@@ -1771,6 +1970,7 @@ int sur_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, 
 
 int sur_coarsen(const float *phi, const float *u, const float *p, int32_t nx, int32_t ny, int32_t nz,
                 const float *scale, float *coarse_f32, void *coarse_bf16, void *stream) {
+    clear_stale_error();
     if (!phi || !u || !p || !scale || (!coarse_f32 && !coarse_bf16) || !dims_ok(nx, ny, nz) ||
         nx % 2 || ny % 2 || nz % 2)
         return SUR_EINVAL;
@@ -1782,6 +1982,7 @@ int sur_coarsen(const float *phi, const float *u, const float *p, int32_t nx, in
 
 int sur_prolong_add(const float *delta, int32_t cnx, int32_t cny, int32_t cnz, const float *scale,
                     double *phi, double *u, double *p, void *stream) {
+    clear_stale_error();
     if (!delta || !scale || !phi || !u || !p || !dims_ok(cnx, cny, cnz)) return SUR_EINVAL;
     const long N = 8L * cnx * cny * cnz;
     hipLaunchKernelGGL(prolong_add_kernel, grid1(N), dim3(256), 0, (hipStream_t)stream, delta, cnx,
@@ -1791,6 +1992,7 @@ int sur_prolong_add(const float *delta, int32_t cnx, int32_t cny, int32_t cnz, c
 
 int sur_apply_residual(float *state, const float *out, const float *rscale, int32_t cu, int64_t P,
                        double width, void *stream) {
+    clear_stale_error();
     if (!state || !out || !rscale || cu <= 0 || cu > 16 || !elems_ok(P, 16)) return SUR_EINVAL;
     if (!(width >= 0.0)) return SUR_EINVAL;
     hipLaunchKernelGGL(apply_residual_kernel, grid1(P * cu), dim3(256), 0, (hipStream_t)stream,
@@ -1800,6 +2002,7 @@ int sur_apply_residual(float *state, const float *out, const float *rscale, int3
 
 int sur_residual_target(const float *s0, const float *s1, const float *rscale, int32_t cu, int64_t P,
                         double width, float *target, void *stream) {
+    clear_stale_error();
     if (!s0 || !s1 || !rscale || !target || cu <= 0 || cu > 16 || !elems_ok(P, 16)) return SUR_EINVAL;
     if (!(width >= 0.0)) return SUR_EINVAL;
     hipLaunchKernelGGL(residual_target_kernel, grid1(P * 16), dim3(256), 0, (hipStream_t)stream,
@@ -1809,6 +2012,7 @@ int sur_residual_target(const float *s0, const float *s1, const float *rscale, i
 
 int sur_fix_mass(float *state, int64_t P, const double *checks_out, const double *target_mass,
                  void *stream) {
+    clear_stale_error();
     if (!state || !checks_out || !target_mass || P <= 0) return SUR_EINVAL;
     hipLaunchKernelGGL(fix_mass_kernel, grid1(P), dim3(256), 0, (hipStream_t)stream, state, (long)P,
                        checks_out, target_mass);
@@ -1816,6 +2020,7 @@ int sur_fix_mass(float *state, int64_t P, const double *checks_out, const double
 }
 
 int sur_features(float *state, int32_t nx, int32_t ny, int32_t nz, void *stream) {
+    clear_stale_error();
     if (!state || !dims_ok(nx, ny, nz)) return SUR_EINVAL;
     const long P = (long)nx * ny * nz;
     hipLaunchKernelGGL(features_kernel, grid1(P), dim3(256), 0, (hipStream_t)stream, state, nx, ny, nz);
@@ -1830,6 +2035,7 @@ size_t sur_prolong_update_scratch_doubles(int32_t cnx, int32_t cny, int32_t cnz)
 int sur_prolong_update(const float *s0, const float *s1, int32_t cnx, int32_t cny, int32_t cnz,
                        const float *scale, double width, double *phi, double *u, double *p,
                        double *scratch, double *sums, void *stream) {
+    clear_stale_error();
     if (!s0 || !s1 || !scale || !phi || !u || !p || !scratch || !sums ||
         !dims_ok(2 * cnx, 2 * cny, 2 * cnz) || !(width > 0.0))
         return SUR_EINVAL;
@@ -1849,6 +2055,7 @@ int sur_prolong_update(const float *s0, const float *s1, int32_t cnx, int32_t cn
 
 int sur_checks(const float *state, int32_t nx, int32_t ny, int32_t nz, double *scratch, double *out,
                void *stream) {
+    clear_stale_error();
     if (!state || !scratch || !out || !dims_ok(nx, ny, nz)) return SUR_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const long P = (long)nx * ny * nz;

@@ -36,6 +36,8 @@ def load_library(path: str | None = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise FileNotFoundError(f"HIP library {p} is not built; run __graft_entry__.build()")
+    from .lbm import hip_runtime_first
+    hip_runtime_first()  # one HIP runtime per process (see there)
     lib = C.CDLL(p)
     vp, i32, i64, fl, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
     lib.sur_conv3d.argtypes = [vp, i32, vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp]
