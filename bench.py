@@ -21,6 +21,11 @@ the same GPU (probe_copy, include/probe.h: half read, half write, as the
 step) and the step's fraction of it. "workloads" gives the rates of the
 static droplet (32^3, FP64 and FP16), the rising bubble (128 x 128 x 256,
 walls on all faces) and the Taylor-Green breakup (256^3) in FP16 and FP32.
+"horizons" runs those three problems over their configured horizons (20k,
+30k and 40k steps; FP16 and FP32 storage) with the observables of the
+paper's Sec. 3: Rayleigh-Taylor spike and bubble fronts, the bubble's
+centroid and rise velocity, the Taylor-Green fragment count and kinetic
+energy, and the phase-mass drift of each (paper_2407_12263_amd/runs.py).
 
 The "surrogate" object covers the learned part on the emulsion workload
 (256^3 periodic, 200 droplets, random solenoidal velocity): the coarse-grid
@@ -246,6 +251,8 @@ def main():
                     help="training trajectories of 64 windows (32 -> 2080 snapshots)")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the droplet, rising-bubble and Taylor-Green rates")
+    ap.add_argument("--no-horizons", action="store_true",
+                    help="skip the runs of the 3D test problems over their horizons")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -326,6 +333,11 @@ def main():
     }
     if not args.no_workloads:
         line["workloads"] = workload_rates(args.steps, args.warmup)
+    if not args.no_horizons:
+        from paper_2407_12263_amd import runs
+        print("[bench] horizons: Rayleigh-Taylor 20k, rising bubble 30k, Taylor-Green 40k steps",
+              file=sys.stderr, flush=True)
+        line["horizons"] = runs.horizons(log=lambda *a: print(*a, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: oracle FP64, {args.cpu_steps} steps on the full lattice",
               file=sys.stderr, flush=True)
