@@ -22,7 +22,8 @@
  * All pointers are device pointers owned by the caller; every call is
  * queued on `stream` (a hipStream_t, NULL = null stream) and returns
  * SUR_OK or SUR_EINVAL (bad sizes / NULL) or SUR_EDEVICE (launch failed).
- * Nothing is allocated by the library.
+ * Nothing is allocated by the library; sur_checks_noalloc alone keeps one
+ * static device buffer per GPU (see there).
  */
 #ifndef SUR_H
 #define SUR_H
@@ -168,6 +169,24 @@ int sur_features(float *state, int32_t nx, int32_t ny, int32_t nz, void *stream)
  * doubles. */
 int sur_checks(const float *state, int32_t nx, int32_t ny, int32_t nz, double *scratch,
                double *out, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * sur_checks with its per-block partial sums in a buffer the library keeps
+ * in device memory instead of a caller's scratch. Same kernels and
+ * summation order, so the same out[7] bit for bit. P = nx*ny*nz must not
+ * exceed SUR_CHECKS_NOALLOC_MAX_POINTS (2^22, e.g. 256 x 128 x 128;
+ * SUR_EINVAL otherwise). Each GPU holds one such buffer (917,504 bytes) from
+ * the first call on it until the process ends; every call on that GPU
+ * shares it, so calls that may overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller. Nothing needs to start
+ * at zero: each call writes every partial it reads. The buffer's address is
+ * looked up on the first call on each device, with the caller's current
+ * device (the stream's device); SUR_EDEVICE if that lookup fails. Allocates
+ * nothing. */
+#define SUR_CHECKS_NOALLOC_MAX_POINTS (1L << 22)
+int sur_checks_noalloc(const float *state, int32_t nx, int32_t ny, int32_t nz, double *out,
+                       void *stream);
 
 /* state[p][c] += rscale[c] * out[p][c] for c < cu (the network's residual,
  * in residual units, applied to the scaled state). With width > 0 channel 0

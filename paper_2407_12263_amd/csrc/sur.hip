@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstdlib>
+#include <mutex>
 #include <type_traits>
 
 #include "sur.h"
@@ -1599,6 +1600,36 @@ long wgrad_tiled_blocks(int cin, long P) {
 
 }  // namespace
 
+// Partial sums of sur_checks_noalloc: one per 256-point block and check, for
+// up to SUR_CHECKS_NOALLOC_MAX_POINTS points (917,504 bytes). Every GPU the
+// library runs on holds its own copy until the process ends. In host code the
+// array's name is no device address: the kernels are given the address that
+// hipGetSymbolAddress returns on each device (checks_scratch_here).
+constexpr long kChecksScratchDoubles = NCHK * (SUR_CHECKS_NOALLOC_MAX_POINTS / 256);
+static __device__ __align__(256) double checks_scratch[kChecksScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex checks_scratch_mu;
+double *checks_scratch_dev[kMaxDevices];
+
+// Device address of checks_scratch on the current device, looked up once per
+// device (with that device current) and kept; NULL if the lookup fails.
+double *checks_scratch_here() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(checks_scratch_mu);
+    if (!checks_scratch_dev[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(checks_scratch)) != hipSuccess || !p) return nullptr;
+        checks_scratch_dev[dev] = (double *)p;
+    }
+    return checks_scratch_dev[dev];
+}
+
+}  // namespace
+
 extern "C" {
 
 int sur_conv3d(const void *x, int32_t cin, const void *w, const float *bias, int32_t cout,
@@ -2062,6 +2093,21 @@ int sur_checks(const float *state, int32_t nx, int32_t ny, int32_t nz, double *s
     const long nb = grid1(P).x;
     hipLaunchKernelGGL(checks_kernel, dim3((unsigned)nb), dim3(256), 0, s, state, nx, ny, nz, scratch);
     hipLaunchKernelGGL(checks_final_kernel, dim3(1), dim3(1024), 0, s, (const double *)scratch, nb, out);
+    return launched();
+}
+
+int sur_checks_noalloc(const float *state, int32_t nx, int32_t ny, int32_t nz, double *out,
+                       void *stream) {
+    clear_stale_error();
+    if (!state || !out || !dims_ok(nx, ny, nz)) return SUR_EINVAL;
+    const long P = (long)nx * ny * nz;
+    if (P > SUR_CHECKS_NOALLOC_MAX_POINTS) return SUR_EINVAL;
+    double *part = checks_scratch_here();
+    if (!part) return SUR_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    const long nb = grid1(P).x;
+    hipLaunchKernelGGL(checks_kernel, dim3((unsigned)nb), dim3(256), 0, s, state, nx, ny, nz, part);
+    hipLaunchKernelGGL(checks_final_kernel, dim3(1), dim3(1024), 0, s, (const double *)part, nb, out);
     return launched();
 }
 

@@ -62,6 +62,7 @@ def load_library(path: str | None = None):
     lib.sur_coarsen.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, vp]
     lib.sur_prolong_add.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.sur_checks.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+    lib.sur_checks_noalloc.argtypes = [vp, i32, i32, i32, vp, vp]
     lib.sur_apply_residual.argtypes = [vp, vp, vp, i32, i64, C.c_double, vp]
     lib.sur_residual_target.argtypes = [vp, vp, vp, i32, i64, C.c_double, vp, vp]
     lib.sur_fix_mass.argtypes = [vp, i64, vp, vp, vp]
@@ -72,7 +73,7 @@ def load_library(path: str | None = None):
     for n in ["sur_features", "sur_prolong_update", "sur_apply_residual", "sur_residual_target", "sur_fix_mass", "sur_conv3d", "sur_conv3d_wgrad", "sur_pack_weights", "sur_pool2", "sur_pool2_bwd",
               "sur_upsample2", "sur_upsample2_bwd", "sur_copy_channels", "sur_add_channels",
               "sur_to_bf16", "sur_relu_mask", "sur_mse", "sur_adam", "sur_coarsen",
-              "sur_prolong_add", "sur_checks", "sur_pool2_bwd_skip", "sur_upsample2_bwd_mask",
+              "sur_prolong_add", "sur_checks", "sur_checks_noalloc", "sur_pool2_bwd_skip", "sur_upsample2_bwd_mask",
               "sur_concat_up2", "sur_pack_weights_all"]:
         getattr(lib, n).restype = C.c_int
     if path is None:
@@ -201,6 +202,15 @@ def sur_prolong_add(delta, cgrid, scale, phi, u, p):
 
 def sur_checks(state, grid, scratch, out):
     _ok(load_library().sur_checks(_p(state), *grid, _p(scratch), _p(out), _stream()), "sur_checks")
+
+
+def sur_checks_noalloc(state, grid, out):
+    """sur_checks with the library's own partials buffer (no scratch)."""
+    _ok(load_library().sur_checks_noalloc(_p(state), *grid, _p(out), _stream()),
+        "sur_checks_noalloc")
+
+
+CHECKS_NOALLOC_MAX_POINTS = 1 << 22
 
 
 def sur_apply_residual(state, out, rscale, cu, P, width=0.0):
