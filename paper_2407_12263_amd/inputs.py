@@ -143,11 +143,13 @@ def droplet_2d(L0: int = 100, Cn: float = 0.06, La: float = 1.0, tau_rho: float 
     La = sigma rho D / eta, t0 = eta D / (2 sigma). The lattice is D3Q19 on a
     single z-plane (nz = 1, periodic): the z-moving populations stay in the
     plane and the projected weights are those of D2Q9 (4/9, 1/9, 1/36).
-    The floor on the normal is 1e-5 here: the droplet has no walls or body
-    force, so K1 carries no non-gradient part for the floor to remove, and
-    below the floor the profile's tail diffuses without sharpening, an
-    error that grows with the run's length (2 t0 is 40,000 steps at L0 = 400)
-    and would put a floor under the convergence study."""
+    The floor on the normal is 1e-5 (3/W)^2: the droplet has no walls or
+    body force, so K1 carries no non-gradient part for the floor to remove
+    beyond rounding noise, and below the floor the profile's tail diffuses
+    without sharpening. |K1| of a profile falls as 1/W, so a fixed floor
+    would cut a band of the profile that widens with the resolution, an
+    error that does not shrink and puts a floor under a convergence study;
+    falling as W^-2, the band narrows faster than the O(W^2) error does."""
     cs2 = cs2_of(courant)
     D = L0 / 2.0
     W = Cn * D
@@ -159,7 +161,7 @@ def droplet_2d(L0: int = 100, Cn: float = 0.06, La: float = 1.0, tau_rho: float 
     return Workload(name=f"droplet_2d_{L0}", nx=L0, ny=L0, nz=1, courant=courant,
                     rho1=1.0, rho2=1.0, tau_rho1=tau_rho, tau_rho2=tau_rho,
                     tau_phi=tau_from_mobility(M, courant), sigma=sigma, delta=W,
-                    k1_eps=1e-5, steps=0, phi0=phi0, u0=np.zeros((3,) + shape), p0=np.zeros(shape),
+                    k1_eps=1e-5 * (3.0 / W) ** 2, steps=0, phi0=phi0, u0=np.zeros((3,) + shape), p0=np.zeros(shape),
                     meta=dict(D=D, W=W, t0=eta * D / (2.0 * sigma), sigma=sigma, eta=eta))
 
 
