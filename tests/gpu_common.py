@@ -22,9 +22,14 @@ def order_maps(q=19):
     return np.array(perm), np.array(inv)
 
 
+# parameters of the GPU solver only (the oracle has no phase-mass bookkeeping
+# and no storage modes)
+SOLVER_ONLY = ("mass_fix_every", "check_every", "store_log2", "p_ref")
+
+
 def oracle_run(w, steps, **over):
     prm = w.params()
-    prm.update(over)
+    prm.update({k: v for k, v in over.items() if k not in SOLVER_ONLY})
     o = oracle.Oracle(oracle.OracleParams(**prm), w.phi0, w.u0, w.p0)
     o.step(steps)
     return o

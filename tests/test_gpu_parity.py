@@ -94,8 +94,8 @@ SMALL = {
 }
 
 
-@pytest.mark.parametrize("name,steps", [("bubble", 100), ("tg", 100), ("rt", 10),
-                                        ("ragged", 50), ("slab", 100)])
+@pytest.mark.parametrize("name,steps", [("bubble", 100), ("tg", 100), ("ragged", 50),
+                                        ("slab", 100)])
 def test_fp64_trajectory(name, steps):
     _cmp(SMALL[name](), "fp64", steps, 1e-12, 1e-13, 1e-13)
 
@@ -103,6 +103,44 @@ def test_fp64_trajectory(name, steps):
 @pytest.mark.parametrize("name", ["bubble", "tg"])
 def test_fp32_trajectory(name):
     _cmp(SMALL[name](), "fp32", 100, 1e-5)
+
+
+# ------------------------------ the headline workload (Sec. 3.2), 100 steps
+
+@pytest.mark.parametrize("prec,tol,fix", [("fp64", 1e-12, 0), ("fp32", 1e-5, 0), ("fp32", 5e-5, 10),
+                                          ("fp16", 2e-3, 10), ("bf16", 2e-3, 10)])
+def test_rayleigh_taylor_100_steps(prec, tol, fix):
+    """Rayleigh-Taylor (32 x 128 x 16: walls in y, gravity, density ratio 3,
+    the interface accelerating) at each storage mode's tolerance after 100
+    steps against the FP64 oracle. FP32 is compared like for like, without
+    the phase-mass bookkeeping, which the oracle does not have (measured
+    3.2e-6). With it (every 10 steps, the default) the FP32 run differs by
+    what it puts back: FP32 rounding drifts sum(phi) by about 1.3e-8 of it
+    per step, the bookkeeping returns that on the interface in proportion to
+    phi (1 - phi), a few 1e-6 per node each time (measured 1.9e-5 after 100
+    steps; bound 5e-5). The 16-bit modes run with it, at their 2e-3."""
+    _cmp(SMALL["rt"](), prec, 100, tol, mass_fix_every=fix)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16", "fp32"])
+def test_rayleigh_taylor_full_size_mass_drift_10k_steps(prec):
+    """Relative drift of sum(phi) over 10^4 steps on the full Rayleigh-Taylor
+    lattice (128 x 512 x 128, walls in y, gravity, density ratio 3: the
+    benchmark's workload and launch configuration) with the default FP64
+    phase-mass bookkeeping. Bound: 1e-6 per 10^4 steps. The run is also
+    checked to stay finite with a bounded velocity (|u| < 0.1)."""
+    w = inputs.rayleigh_taylor()
+    say(f"[mass] {w.name} {prec} 10000 steps")
+    sol = gpu_solver(w, prec)
+    m0 = float(w.phi0.sum())
+    worst = 0.0
+    for t in (1000, 2500, 5000, 7500, 10000):
+        sol.step(t - sol.t)
+        d = sol.diagnostics()
+        worst = max(worst, abs(d["sum_phi"] - m0) / m0)
+        assert np.isfinite(d["umax"]) and d["umax"] < 0.1, d["umax"]
+    say(f"   max relative drift over the run = {worst:.2e}, umax at the end {d['umax']:.3e}")
+    assert worst <= 1e-6
 
 
 def test_fp64_exact_streaming_c1():

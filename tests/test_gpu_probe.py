@@ -13,7 +13,7 @@ def test_probe_copy_is_exact():
         pytest.skip("no GPU")
     from paper_2407_12263_amd import probe
     st = torch.cuda.current_stream().cuda_stream
-    n = (1 << 22) + 48                                 # bytes: not a multiple of the grid
+    n = (1 << 22) + 192                                # bytes: not a multiple of the grid
     src = torch.randint(0, 1 << 30, (n // 4,), dtype=torch.int32, device="cuda")
     for nt in (False, True):
         for blocks in (1, 7, 4096):
