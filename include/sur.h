@@ -47,6 +47,18 @@ int sur_conv3d(const void *x, int32_t cin, const void *w, const float *bias, int
                int32_t nx, int32_t ny, int32_t nz, int32_t flip, int32_t relu,
                const void *mask, void *y_bf16, float *y_f32, void *stream);
 
+/* The decoder's first convolution of a level, reading its input concat in
+ * place: sur_conv3d (flip = 0, no mask) of x = [xc[parent(p)][0 .. cc),
+ * xf[p][0 .. fc)] with cin = cc + fc, bitwise the result of sur_concat_up2
+ * followed by sur_conv3d, without writing the concat. xc is BF16 at half the
+ * fine sizes (nx/2, ny/2, nz/2), parent(p) = (x/2, y/2, z/2); xf, y and the
+ * sizes are fine-grid. w: the [27][cout][cc + fc] packing. Needs the tiled
+ * kernel: nx a multiple of 16, ny and nz of 4, 16-byte aligned xc, xf and w;
+ * otherwise SUR_EINVAL (concat first, then sur_conv3d). */
+int sur_conv3d_cat(const void *xc, int32_t cc, const void *xf, int32_t fc, const void *w,
+                   const float *bias, int32_t cout, int32_t nx, int32_t ny, int32_t nz,
+                   int32_t relu, void *y_bf16, float *y_f32, void *stream);
+
 /* Floats of scratch that sur_conv3d_wgrad needs for these sizes. */
 size_t sur_wgrad_scratch_floats(int32_t cin, int32_t cout, int32_t nx, int32_t ny, int32_t nz);
 

@@ -254,7 +254,7 @@ class Trainer:
         sur.sur_to_bf16(a, self.xb)
         sur.sur_residual_target(a, b, self.rscale, sur.NUSE, self.cp.P, self.tgt,
                                 self.cp.res_width)
-        net.forward(self.xb)
+        net.forward(self.xb, keep_cat=True)
         loss = float(net.loss_and_grad(self.tgt, self.wch).item())
         if self.mean_loss is not None and self.mean_loss > 0:
             ratio = loss / self.mean_loss

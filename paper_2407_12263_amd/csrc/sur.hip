@@ -200,10 +200,8 @@ typedef float fl2 __attribute__((ext_vector_type(2)));
 constexpr int kTX = 16, kTY = 4, kTZ = 4;
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2, kHP = kHX * kHY * kHZ;
 constexpr int kNT = 2;  // 16-channel output tiles per block at most (LDS <= 48.4 KB)
-constexpr int kStage = 20;  // floats per point of the epilogue's staging rows (16 + 4 pad)
 
 static_assert(kHP * 2 > 1280 && kHP * 2 <= 1536, "six 16-byte halo pieces per thread");
-static_assert(4 * 64 * kStage * 4 <= kHP * 32, "the epilogue's staging fits in the halo area");
 
 // Halo offset of tap t (x fastest) and the offset step from tap t to t + 1
 // (0 for the last tap, which has no partner in its K step).
@@ -271,6 +269,24 @@ __device__ __forceinline__ uint4 halo_piece(const uint16_t *__restrict__ x, int 
     return *(const uint4 *)(x + (uint32_t)gp * (uint32_t)cin + cc + 8 * part);
 }
 
+// The same piece of the nearest 2x upsampling of the coarse tensor xc (cc
+// channels, half the grid's sizes): fine point (x, y, z) reads coarse point
+// (x / 2, y / 2, z / 2) after the periodic wrap on the fine grid.
+template <bool POW2>
+__device__ __forceinline__ uint4 halo_piece_up(const uint16_t *__restrict__ xc, int cc,
+                                               const ConvGeom &G, int x0, int y0, int z0, int c0,
+                                               int hp, int part) {
+    if (hp < 0) return uint4{0u, 0u, 0u, 0u};
+    const int fx = x0 - 1 + (hp & 255), fy = y0 - 1 + ((hp >> 8) & 255), fz = z0 - 1 + (hp >> 16);
+    int gp;
+    if constexpr (POW2)
+        gp = ((fx & (G.nx - 1)) >> 1) | (((fy & (G.ny - 1)) >> 1) << (G.lx - 1)) |
+             (((fz & (G.nz - 1)) >> 1) << (G.lxy - 2));
+    else
+        gp = (wrap(fx, G.nx) >> 1) + (G.nx >> 1) * ((wrap(fy, G.ny) >> 1) + (G.ny >> 1) * (wrap(fz, G.nz) >> 1));
+    return *(const uint4 *)(xc + (uint32_t)gp * (uint32_t)cc + c0 + 8 * part);
+}
+
 // The 14 K steps of one work item from LDS into the accumulators of the
 // first NTA of the block's NT output tiles (NTA is the number the block
 // actually has, so the loop carries no per-step test of it). baseA0..3: the
@@ -313,7 +329,7 @@ __device__ __forceinline__ void conv_kloop(const uint4 *tile, const uint4 *wl, i
         for (int nt = 0; nt < NTA; ++nt)
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[buf][mt], b[buf][nt],
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[buf][nt], a[buf][mt],
                                                                        acc[mt][nt], 0, 0, 0);
     };
     if constexpr (PIPE) {
@@ -350,14 +366,22 @@ __device__ __forceinline__ void conv_kloop(const uint4 *tile, const uint4 *wl, i
 // exist and enters as zeros.
 // Addressing costs no vector instruction in the K loop: the flip is a
 // template parameter, every LDS read is a per-lane base (one per step class
-// of tap pairs, see step_bias) plus an immediate. The epilogue stages each
-// wavefront's 64 x 16 results in LDS (FP32 rows of kStage floats) so that
-// every point's 16 channels leave as 16-byte stores, converted to BF16 by
-// the hardware (round to nearest even).
-template <int NT, bool FLIP, bool POW2>
+// of tap pairs, see step_bias) plus an immediate. The weights are the MFMA's
+// first operand and the points its second, so the result tile is output
+// channel x point: lane (px, q) holds channels 4q .. 4q + 3 of point px, and
+// the lanes of one store instruction write 16 points x 16 channels of one
+// row (512 contiguous bytes when cout = 16) straight from the accumulators,
+// converted to BF16 by the hardware (round to nearest even).
+// With CAT the input is the decoder's concat [up2(xc), x] read in place: the
+// first cc / 16 chunks come from the coarse tensor xc (cc channels) at the
+// parent point, the others from x (cin - cc channels), so the concatenated
+// tensor is never written; the products and their order are those of the
+// convolution of the concatenated tensor.
+template <int NT, bool FLIP, bool POW2, bool CAT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 4 : 1, 8)))
 conv3d_tiled_kernel(
-    const uint16_t *__restrict__ x, int cin, const uint16_t *__restrict__ w,
+    const uint16_t *__restrict__ x, int cin, const uint16_t *__restrict__ xc, int cc,
+    const uint16_t *__restrict__ w,
     const float *__restrict__ bias, int cout, ConvGeom G, int relu,
     const uint16_t *__restrict__ mask, uint16_t *__restrict__ yb, float *__restrict__ yf) {
     // LDS: the input halo (kHP points x 16 channels) and the chunk's weights
@@ -397,8 +421,20 @@ conv3d_tiled_kernel(
     auto load_halo = [&](int k, int chunk) {
         int ox, oy, oz;
         tile_origin<POW2>(G, (int)blockIdx.x + k * (int)gridDim.x, ox, oy, oz);
+        if constexpr (CAT) {
+            if (chunk * 16 < cc) {
 #pragma unroll
-        for (int j = 0; j < 6; ++j) pf[j] = halo_piece<POW2>(x, cin, G, ox, oy, oz, chunk * 16, hp[j], part);
+                for (int j = 0; j < 6; ++j)
+                    pf[j] = halo_piece_up<POW2>(xc, cc, G, ox, oy, oz, chunk * 16, hp[j], part);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 6; ++j)
+                    pf[j] = halo_piece<POW2>(x, cin - cc, G, ox, oy, oz, chunk * 16 - cc, hp[j], part);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 6; ++j) pf[j] = halo_piece<POW2>(x, cin, G, ox, oy, oz, chunk * 16, hp[j], part);
+        }
     };
     // weight rows (t, o) of input chunk cc: w[t][cob + o][cc .. cc + 15]
     auto stage_weights = [&](int cc) {
@@ -434,57 +470,43 @@ conv3d_tiled_kernel(
                 conv_kloop<1, NT, FLIP, false>(tile, wl, baseA0, baseA1, baseA2, baseA3, baseB,
                                               second, acc);
         }
-        // epilogue: through LDS, one point's 16 channels per lane
+        // epilogue: lane (px, q) holds output channels 4q .. 4q + 3 of point
+        // x0 + px of row mt of its plane, in register j of acc[mt][nt]
         int x0, y0, z0;
         tile_origin<POW2>(G, (int)blockIdx.x + k * (int)gridDim.x, x0, y0, z0);
-        float *st = (float *)tile + wave * (64 * kStage);
-        const int pmt = lane >> 4, px = lane & 15;
-        const int p = grid_point<POW2>(G, x0 + px, y0 + pmt, z0 + wave);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             if (nt >= ntiles) break;
-            __syncthreads();  // the halo (or the previous pass's staging) is no longer read
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) st[(mt * 16 + 4 * q + j) * kStage + r] = acc[mt][nt][j];
-            __syncthreads();
-            const int co0 = cob + nt * 16;
-            float v[16];
-#pragma unroll
-            for (int c4 = 0; c4 < 4; ++c4) {
-                const f4 s = *(const f4 *)(st + lane * kStage + 4 * c4);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) v[4 * c4 + e] = s[e];
-            }
+            const int co = cob + nt * 16 + 4 * q;
+            float bv[4] = {0.f, 0.f, 0.f, 0.f};
             if (bias) {
 #pragma unroll
-                for (int c = 0; c < 16; ++c) v[c] += bias[co0 + c];
+                for (int j = 0; j < 4; ++j) bv[j] = bias[co + j];
             }
-            if (relu) {
 #pragma unroll
-                for (int c = 0; c < 16; ++c) v[c] = fmaxf(v[c], 0.f);
-            }
-            const uint32_t o = (uint32_t)p * (uint32_t)cout + co0;
-            if (mask) {
-                const uint4 m0 = *(const uint4 *)(mask + o), m1 = *(const uint4 *)(mask + o + 8);
-                const uint32_t mw[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
+            for (int mt = 0; mt < 4; ++mt) {
+                const int p = grid_point<POW2>(G, x0 + r, y0 + mt, z0 + wave);
+                const uint32_t o = (uint32_t)p * (uint32_t)cout + co;
+                float v[4];
 #pragma unroll
-                for (int c = 0; c < 16; ++c)
-                    if (!(bf2f((uint16_t)(mw[c >> 1] >> (16 * (c & 1)))) > 0.f)) v[c] = 0.f;
-            }
-            if (yb) {
-                uint32_t pk[8];
+                for (int j = 0; j < 4; ++j) {
+                    v[j] = acc[mt][nt][j];
+                    if (bias) v[j] += bv[j];
+                    if (relu) v[j] = fmaxf(v[j], 0.f);
+                }
+                if (mask) {
+                    const uint2 m = *(const uint2 *)(mask + o);
+                    const uint32_t mw[2] = {m.x, m.y};
 #pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    pk[c] = __builtin_bit_cast(uint32_t, __builtin_convertvector(fl2{v[2 * c], v[2 * c + 1]}, bf2));
-                *(uint4 *)(yb + o) = uint4{pk[0], pk[1], pk[2], pk[3]};
-                *(uint4 *)(yb + o + 8) = uint4{pk[4], pk[5], pk[6], pk[7]};
-            }
-            if (yf) {
-#pragma unroll
-                for (int c4 = 0; c4 < 4; ++c4)
-                    *(f4 *)(yf + o + 4 * c4) = f4{v[4 * c4], v[4 * c4 + 1], v[4 * c4 + 2], v[4 * c4 + 3]};
+                    for (int j = 0; j < 4; ++j)
+                        if (!(bf2f((uint16_t)(mw[j >> 1] >> (16 * (j & 1)))) > 0.f)) v[j] = 0.f;
+                }
+                if (yb) {
+                    const uint32_t lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(fl2{v[0], v[1]}, bf2));
+                    const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(fl2{v[2], v[3]}, bf2));
+                    *(uint2 *)(yb + o) = uint2{lo, hi};
+                }
+                if (yf) *(f4 *)(yf + o) = f4{v[0], v[1], v[2], v[3]};
             }
         }
     }
@@ -1628,6 +1650,57 @@ double *checks_scratch_here() {
     return checks_scratch_dev[dev];
 }
 
+// The tiled convolution applies: sizes multiples of its tile, 32-bit element
+// indices, 16-byte aligned x and w (its 16-byte loads).
+bool conv_tiled_ok(const void *x, int cin, const void *w, int cout, int nx, int ny, int nz) {
+    const long P = (long)nx * ny * nz;
+    return nx % kTX == 0 && ny % kTY == 0 && nz % kTZ == 0 && elems_ok(P, cin) && elems_ok(P, cout) &&
+           ((uintptr_t)x & 15) == 0 && ((uintptr_t)w & 15) == 0;
+}
+
+// Launches conv3d_tiled_kernel; xc != NULL selects the concat form (cc
+// channels of the upsampled coarse tensor first, then cin - cc of x).
+void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const void *w,
+                       const float *bias, int cout, int nx, int ny, int nz, bool flip, int relu,
+                       const void *mask, void *y_bf16, float *y_f32, hipStream_t st) {
+    const long P = (long)nx * ny * nz;
+    // one N tile per block for 16 output channels (fewer registers), two otherwise
+    const int nt = cout <= 16 ? 1 : kNT, nb = 16 * nt;
+    const long tiles = P / (kTX * kTY * kTZ);
+    const long ncb = (cout + nb - 1) / nb;
+    const long nblk = std::max(1L, std::min(tiles, (long)env_blocks() / ncb));
+    const dim3 grid((unsigned)nblk, (unsigned)ncb);
+    const size_t lds = conv_tiled_lds(nt);
+    ConvGeom G{nx, ny, nz, nx / kTX, ny / kTY, nz / kTZ, 0, 0, 0, 0};
+    const bool pow2 = pow2_ok(nx) && pow2_ok(ny) && pow2_ok(nz);
+    if (pow2) {
+        G.lx = ilog2(nx);
+        G.lxy = ilog2(nx) + ilog2(ny);
+        G.ltx = ilog2(G.ntx);
+        G.ltxy = ilog2(G.ntx) + ilog2(G.nty);
+    }
+    const uint16_t *xb = (const uint16_t *)x, *xcb = (const uint16_t *)xc;
+    const uint16_t *wb = (const uint16_t *)w, *mb = (const uint16_t *)mask;
+    uint16_t *yb = (uint16_t *)y_bf16;
+#define SUR_CONV_LAUNCH(NTV, FL, P2, CT)                                                     \
+    hipLaunchKernelGGL((conv3d_tiled_kernel<NTV, FL, P2, CT>), grid, dim3(256), lds, st, xb, \
+                       cin, xcb, cc, wb, bias, cout, G, relu, mb, yb, y_f32)
+#define SUR_CONV_POW2(NTV, FL, CT) \
+    do { if (pow2) SUR_CONV_LAUNCH(NTV, FL, true, CT); else SUR_CONV_LAUNCH(NTV, FL, false, CT); } while (0)
+    if (xc) {
+        if (nt == 1) SUR_CONV_POW2(1, false, true);
+        else SUR_CONV_POW2(kNT, false, true);
+    } else if (nt == 1) {
+        if (flip) SUR_CONV_POW2(1, true, false);
+        else SUR_CONV_POW2(1, false, false);
+    } else {
+        if (flip) SUR_CONV_POW2(kNT, true, false);
+        else SUR_CONV_POW2(kNT, false, false);
+    }
+#undef SUR_CONV_POW2
+#undef SUR_CONV_LAUNCH
+}
+
 }  // namespace
 
 extern "C" {
@@ -1640,45 +1713,28 @@ int sur_conv3d(const void *x, int32_t cin, const void *w, const float *bias, int
         !dims_ok(nx, ny, nz))
         return SUR_EINVAL;
     const long P = (long)nx * ny * nz;
-    // the tiled kernel: sizes multiples of its tile, 32-bit element indices,
-    // 16-byte aligned x and w (its 16-byte loads)
-    if (nx % kTX == 0 && ny % kTY == 0 && nz % kTZ == 0 && elems_ok(P, cin) && elems_ok(P, cout) &&
-        ((uintptr_t)x & 15) == 0 && ((uintptr_t)w & 15) == 0) {
-        // one N tile per block for 16 output channels (fewer registers), two otherwise
-        const int nt = cout <= 16 ? 1 : kNT, nb = 16 * nt;
-        const long tiles = P / (kTX * kTY * kTZ);
-        const long ncb = (cout + nb - 1) / nb;
-        const long nblk = std::max(1L, std::min(tiles, (long)env_blocks() / ncb));
-        const dim3 grid((unsigned)nblk, (unsigned)ncb);
-        const size_t lds = conv_tiled_lds(nt);
-        ConvGeom G{nx, ny, nz, nx / kTX, ny / kTY, nz / kTZ, 0, 0, 0, 0};
-        const bool pow2 = pow2_ok(nx) && pow2_ok(ny) && pow2_ok(nz);
-        if (pow2) {
-            G.lx = ilog2(nx);
-            G.lxy = ilog2(nx) + ilog2(ny);
-            G.ltx = ilog2(G.ntx);
-            G.ltxy = ilog2(G.ntx) + ilog2(G.nty);
-        }
-        hipStream_t st = (hipStream_t)stream;
-        const uint16_t *xb = (const uint16_t *)x, *wb = (const uint16_t *)w, *mb = (const uint16_t *)mask;
-        uint16_t *yb = (uint16_t *)y_bf16;
-#define SUR_CONV_LAUNCH(NTV, FL, P2)                                                              \
-    hipLaunchKernelGGL((conv3d_tiled_kernel<NTV, FL, P2>), grid, dim3(256), lds, st, xb, cin, wb, \
-                       bias, cout, G, relu, mb, yb, y_f32)
-        if (nt == 1) {
-            if (flip) { if (pow2) SUR_CONV_LAUNCH(1, true, true); else SUR_CONV_LAUNCH(1, true, false); }
-            else { if (pow2) SUR_CONV_LAUNCH(1, false, true); else SUR_CONV_LAUNCH(1, false, false); }
-        } else {
-            if (flip) { if (pow2) SUR_CONV_LAUNCH(kNT, true, true); else SUR_CONV_LAUNCH(kNT, true, false); }
-            else { if (pow2) SUR_CONV_LAUNCH(kNT, false, true); else SUR_CONV_LAUNCH(kNT, false, false); }
-        }
-#undef SUR_CONV_LAUNCH
+    if (conv_tiled_ok(x, cin, w, cout, nx, ny, nz)) {
+        conv_tiled_launch(x, cin, nullptr, 0, w, bias, cout, nx, ny, nz, flip != 0, relu, mask,
+                          y_bf16, y_f32, (hipStream_t)stream);
         return launched();
     }
     const dim3 grid((unsigned)((P + 255) / 256), (unsigned)((cout + 63) / 64));
     hipLaunchKernelGGL(conv3d_kernel, grid, dim3(256), 0, (hipStream_t)stream, (const uint16_t *)x,
                        cin, (const uint16_t *)w, bias, cout, nx, ny, nz, flip, relu,
                        (const uint16_t *)mask, (uint16_t *)y_bf16, y_f32);
+    return launched();
+}
+
+int sur_conv3d_cat(const void *xc, int32_t cc, const void *xf, int32_t fc, const void *w,
+                   const float *bias, int32_t cout, int32_t nx, int32_t ny, int32_t nz,
+                   int32_t relu, void *y_bf16, float *y_f32, void *stream) {
+    clear_stale_error();
+    if (!xc || !xf || !w || (!y_bf16 && !y_f32) || cc <= 0 || fc <= 0 || cout <= 0 || cc % 16 ||
+        fc % 16 || cout % 16 || !dims_ok(nx, ny, nz) || !conv_tiled_ok(xf, cc + fc, w, cout, nx, ny, nz) ||
+        ((uintptr_t)xc & 15) != 0 || !elems_ok((long)nx * ny * nz, cc))
+        return SUR_EINVAL;
+    conv_tiled_launch(xf, cc + fc, xc, cc, w, bias, cout, nx, ny, nz, false, relu, nullptr, y_bf16,
+                      y_f32, (hipStream_t)stream);
     return launched();
 }
 

@@ -41,6 +41,7 @@ def load_library(path: str | None = None):
     lib = C.CDLL(p)
     vp, i32, i64, fl, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
     lib.sur_conv3d.argtypes = [vp, i32, vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp]
+    lib.sur_conv3d_cat.argtypes = [vp, i32, vp, i32, vp, vp, i32, i32, i32, i32, i32, vp, vp, vp]
     lib.sur_wgrad_scratch_floats.argtypes = [i32, i32, i32, i32, i32]
     lib.sur_wgrad_scratch_floats.restype = sz
     lib.sur_conv3d_wgrad.argtypes = [vp, i32, vp, i32, i32, i32, i32, vp, sz, vp, vp, vp]
@@ -70,7 +71,7 @@ def load_library(path: str | None = None):
     lib.sur_prolong_update_scratch_doubles.argtypes = [i32, i32, i32]
     lib.sur_prolong_update_scratch_doubles.restype = sz
     lib.sur_prolong_update.argtypes = [vp, vp, i32, i32, i32, vp, C.c_double, vp, vp, vp, vp, vp, vp]
-    for n in ["sur_features", "sur_prolong_update", "sur_apply_residual", "sur_residual_target", "sur_fix_mass", "sur_conv3d", "sur_conv3d_wgrad", "sur_pack_weights", "sur_pool2", "sur_pool2_bwd",
+    for n in ["sur_features", "sur_prolong_update", "sur_apply_residual", "sur_residual_target", "sur_fix_mass", "sur_conv3d", "sur_conv3d_cat", "sur_conv3d_wgrad", "sur_pack_weights", "sur_pool2", "sur_pool2_bwd",
               "sur_upsample2", "sur_upsample2_bwd", "sur_copy_channels", "sur_add_channels",
               "sur_to_bf16", "sur_relu_mask", "sur_mse", "sur_adam", "sur_coarsen",
               "sur_prolong_add", "sur_checks", "sur_checks_noalloc", "sur_pool2_bwd_skip", "sur_upsample2_bwd_mask",
@@ -101,6 +102,19 @@ def sur_conv3d(x, cin, w, bias, cout, grid, flip=0, relu=0, mask=None, y_bf16=No
     nx, ny, nz = grid
     _ok(load_library().sur_conv3d(_p(x), cin, _p(w), _p(bias), cout, nx, ny, nz, flip, relu,
                                   _p(mask), _p(y_bf16), _p(y_f32), _stream()), "sur_conv3d")
+
+
+def sur_conv3d_cat(xc, cc, xf, fc, w, bias, cout, grid, relu=0, y_bf16=None, y_f32=None):
+    nx, ny, nz = grid
+    _ok(load_library().sur_conv3d_cat(_p(xc), cc, _p(xf), fc, _p(w), _p(bias), cout, nx, ny, nz,
+                                      relu, _p(y_bf16), _p(y_f32), _stream()), "sur_conv3d_cat")
+
+
+def conv_cat_fits(grid):
+    """Whether sur_conv3d_cat takes these fine-grid sizes (its tiled kernel's
+    16 x 4 x 4 point tile)."""
+    nx, ny, nz = grid
+    return nx % 16 == 0 and ny % 4 == 0 and nz % 4 == 0
 
 
 def sur_wgrad_scratch_floats(cin, cout, grid):
@@ -361,9 +375,12 @@ class UNet:
         return sum(w.numel() + b.numel() for w, b in zip(self.w, self.b))
 
     # -------------------------------------------------------------- forward
-    def forward(self, x_bf16):
+    def forward(self, x_bf16, keep_cat=False):
         """x_bf16: int16 tensor [P0, 16] (BF16 bits). Returns the FP32 output
-        [P0, 16] (the residual in scaled units)."""
+        [P0, 16] (the residual in scaled units). The decoder convolutions read
+        their concat in place (sur_conv3d_cat) unless keep_cat is set (the
+        training step: the weight gradient reads the concat) or the grid does
+        not fit that kernel; both ways give the same bits."""
         k = 0
         h = x_bf16
         hc = NCH
@@ -377,12 +394,23 @@ class UNet:
             if lv < self.nlev - 1:
                 sur_pool2(h, hc, g, self.act[f"pool{lv}"])
                 h = self.act[f"pool{lv}"]
+        self._cat_kept = True
         for lv in range(self.nlev - 2, -1, -1):
-            cat = self.act[f"cat{lv}"]
-            ctot = cat.shape[1]
-            sur_concat_up2(h, hc, self.act[f"enc{lv}b"], self.channels[lv], self.grids[lv], cat)
-            h, hc = cat, ctot
-            for part in "ab":
+            skip = self.act[f"enc{lv}b"]
+            if not keep_cat and conv_cat_fits(self.grids[lv]):
+                self._cat_kept = False
+                name, ci, co, relu = self.layers[k]
+                sur_conv3d_cat(h, hc, skip, self.channels[lv], self.wf[k], self.b[k], co,
+                               self.grids[lv], relu=1, y_bf16=self.act[name])
+                h, hc = self.act[name], co
+                k += 1
+                parts = "b"
+            else:
+                cat = self.act[f"cat{lv}"]
+                sur_concat_up2(h, hc, skip, self.channels[lv], self.grids[lv], cat)
+                h, hc = cat, cat.shape[1]
+                parts = "ab"
+            for part in parts:
                 name, ci, co, relu = self.layers[k]
                 sur_conv3d(h, ci, self.wf[k], self.b[k], co, self.grids[lv], relu=1,
                            y_bf16=self.act[name])
@@ -417,7 +445,10 @@ class UNet:
         return dx
 
     def backward(self, dout):
-        """dout: FP32 [P0, 16] gradient at the output. Fills gw, gb."""
+        """dout: FP32 [P0, 16] gradient at the output. Fills gw, gb. Needs the
+        concat buffers of the last forward (forward with keep_cat=True)."""
+        if not getattr(self, "_cat_kept", False):
+            raise RuntimeError("UNet.backward needs the forward pass run with keep_cat=True")
         torch = self.torch
         k = len(self.layers) - 1
         nlev = self.nlev
@@ -484,7 +515,7 @@ class UNet:
         self.pack()
 
     def train_step(self, x_bf16, target_f32, wch, lr=1e-3):
-        self.forward(x_bf16)
+        self.forward(x_bf16, keep_cat=True)
         loss = self.loss_and_grad(target_f32, wch)
         self.backward(self.dout)
         self.adam_step(lr)

@@ -96,6 +96,78 @@ def test_conv_data_gradient_with_mask(sur, cin, cout, grid):
     assert np.abs(got - ref).max() <= 1e-5 * (1 + np.abs(ref).max())
 
 
+# fine grids of the in-place concat: power-of-two sizes, others (the general
+# index path), one tile whose halo wraps onto itself
+CAT_GRIDS = [(32, 8, 8), (48, 12, 8), (16, 4, 4)]
+
+
+@pytest.mark.parametrize("grid", CAT_GRIDS)
+@pytest.mark.parametrize("cc,fc,cout,relu", [(32, 16, 16, 1), (64, 48, 48, 1), (48, 32, 32, 0),
+                                             (16, 16, 64, 1)])
+def test_conv_reading_the_concat_in_place(sur, cc, fc, cout, relu, grid):
+    """sur_conv3d_cat = the convolution of [up2(xc), xf]: within 1e-5 of the
+    oracle's, and bitwise the concat pass followed by sur_conv3d."""
+    import torch
+    say(f"[sur] conv of the concat in place cc={cc} fc={fc} cout={cout} grid={grid}")
+    rng = np.random.default_rng(cc + 3 * fc + cout)
+    nx, ny, nz = grid
+    P = nx * ny * nz
+    cin = cc + fc
+    xc = so.bf16_round(rng.standard_normal((nz // 2, ny // 2, nx // 2, cc)).astype(np.float32))
+    xf = so.bf16_round(rng.standard_normal((nz, ny, nx, fc)).astype(np.float32))
+    w = rng.standard_normal((27, cout, cin)).astype(np.float32) * 0.1
+    b = rng.standard_normal(cout).astype(np.float32)
+    wf = torch.empty((27, cout, cin), dtype=torch.int16, device="cuda")
+    sur.sur_pack_weights(_f32(w), cin, cout, wf, None)
+    xcb, xfb, bb = _bits(xc.reshape(-1, cc)), _bits(xf.reshape(-1, fc)), _f32(b)
+    yf = torch.empty((P, cout), dtype=torch.float32, device="cuda")
+    yb = torch.empty((P, cout), dtype=torch.int16, device="cuda")
+    sur.sur_conv3d_cat(xcb, cc, xfb, fc, wf, bb, cout, grid, relu=relu, y_bf16=yb, y_f32=yf)
+    cat = np.concatenate([so.up2(xc.astype(np.float64)), xf.astype(np.float64)], axis=-1)
+    ref = so.conv3d(cat, so.bf16_round(w).astype(np.float64), b.astype(np.float64))
+    if relu:
+        ref = so.relu(ref)
+    got = yf.cpu().numpy().reshape(ref.shape)
+    assert np.abs(got - ref).max() <= 1e-5 * (1 + np.abs(ref).max())
+    # the two-pass form on the GPU gives the same bits
+    catb = torch.empty((P, cin), dtype=torch.int16, device="cuda")
+    sur.sur_concat_up2(xcb, cc, xfb, fc, grid, catb)
+    yf2 = torch.empty_like(yf)
+    yb2 = torch.empty_like(yb)
+    sur.sur_conv3d(catb, cin, wf, bb, cout, grid, relu=relu, y_bf16=yb2, y_f32=yf2)
+    assert torch.equal(yf, yf2) and torch.equal(yb, yb2)
+
+
+def test_conv_cat_rejects_grids_off_its_tile(sur):
+    """Sizes that are not multiples of the 16 x 4 x 4 tile are refused on the
+    host (the caller concatenates and calls sur_conv3d)."""
+    import torch
+    grid = (8, 8, 8)
+    xc = torch.zeros((64, 32), dtype=torch.int16, device="cuda")
+    xf = torch.zeros((512, 16), dtype=torch.int16, device="cuda")
+    wf = torch.zeros((27, 16, 48), dtype=torch.int16, device="cuda")
+    yb = torch.empty((512, 16), dtype=torch.int16, device="cuda")
+    assert not sur.conv_cat_fits(grid)
+    with pytest.raises(RuntimeError):
+        sur.sur_conv3d_cat(xc, 32, xf, 16, wf, None, 16, grid, y_bf16=yb)
+
+
+def test_unet_inference_forward_equals_training_forward(sur):
+    """The forward that reads the decoder concats in place gives the bits of
+    the one that writes them (the training step's); a backward after the
+    former is refused."""
+    import torch
+    say("[sur] unet 32^3 forward, concat in place vs written")
+    net = sur.UNet((32, 32, 32), channels=(16, 32, 48, 64), seed=9)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    x = torch.randint(0, 1 << 14, (32 ** 3, 16), dtype=torch.int16, device="cuda", generator=g)
+    a = net.forward(x).clone()
+    with pytest.raises(RuntimeError):
+        net.backward(net.dout)
+    b = net.forward(x, keep_cat=True).clone()
+    assert torch.equal(a, b)
+
+
 # the first five grids are multiples of the 16 x 4 x 4 tile (the LDS-tiled
 # kernel, one to 24 tiles, every output-channel count), the rest are not
 @pytest.mark.parametrize("cin,cout,grid", [(16, 16, (16, 8, 12)), (112, 48, (32, 8, 8)),
@@ -240,7 +312,7 @@ def test_unet_forward_backward_matches_oracle(sur):
     tgt = np.zeros_like(x)
     tgt[..., :5] = 0.1 * rng.standard_normal((16, 16, 16, 5))
     wch = np.array([1.0, 1.0, 1.0, 1.0, 1.0], dtype=np.float32)
-    out = net.forward(_bits(x.reshape(-1, 16)))
+    out = net.forward(_bits(x.reshape(-1, 16)), keep_cat=True)
     loss = net.loss_and_grad(_f32(tgt.reshape(-1, 16)), _f32(wch))
     net.backward(net.dout)
     torch.cuda.synchronize()
@@ -257,7 +329,7 @@ def test_unet_forward_backward_matches_oracle(sur):
         ew = _rel(net.gw[k].cpu().numpy(), gw)
         worst = max(worst, ew)
     say(f"   worst layer weight-gradient rel err {worst:.2e}")
-    assert worst < 3e-2
+    assert worst < 2e-2
 
 
 def test_training_trajectory_matches_oracle(sur):
