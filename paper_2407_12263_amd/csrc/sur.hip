@@ -197,6 +197,7 @@ __global__ void __launch_bounds__(256) conv3d_kernel(const uint16_t *__restrict_
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 typedef float fl2 __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
 constexpr int kTX = 16, kTY = 4, kTZ = 4;
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2, kHP = kHX * kHY * kHZ;
 constexpr int kNT = 2;  // 16-channel output tiles per block at most (LDS <= 48.4 KB)
@@ -377,8 +378,15 @@ __device__ __forceinline__ void conv_kloop(const uint4 *tile, const uint4 *wl, i
 // parent point, the others from x (cin - cc channels), so the concatenated
 // tensor is never written; the products and their order are those of the
 // convolution of the concatenated tensor.
-template <int NT, bool FLIP, bool POW2, bool CAT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 4 : 1, 8)))
+// With WPF (two output tiles, grids of fewer blocks than two per CU) the
+// next chunk's weights load into registers with its halo; those blocks run
+// at two wavefronts per SIMD, which costs nothing where there is at most one
+// block per CU. Otherwise each chunk stages its weights when it starts.
+template <int NT, bool WPF>
+constexpr int conv_min_waves() { return NT == 1 ? 4 : (WPF ? 2 : 1); }
+
+template <int NT, bool FLIP, bool POW2, bool CAT, bool WPF>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv_min_waves<NT, WPF>(), 8)))
 conv3d_tiled_kernel(
     const uint16_t *__restrict__ x, int cin, const uint16_t *__restrict__ xc, int cc,
     const uint16_t *__restrict__ w,
@@ -403,11 +411,11 @@ conv3d_tiled_kernel(
     // per step class of tap pairs: lane base of the A reads (see step_bias)
     constexpr int D1 = pair_step(0), D2 = pair_step(2), D3 = pair_step(8);
     static_assert(D1 == 1 && D2 == kHX - 2 && D3 == kHX * kHY - 2 * kHX - 2, "tap pair steps");
-    const int baseA1 = hb2 + 2 * S * second * D1 - 2 * step_bias(D1, S);
-    const int baseA2 = hb2 + 2 * S * second * D2 - 2 * step_bias(D2, S);
-    const int baseA3 = hb2 + 2 * S * second * D3 - 2 * step_bias(D3, S);
-    const int baseA0 = hb2 - 2 * step_bias(0, S);
-    const int baseB = 2 * (second * NCO + r) + half;
+    int baseA1 = hb2 + 2 * S * second * D1 - 2 * step_bias(D1, S);
+    int baseA2 = hb2 + 2 * S * second * D2 - 2 * step_bias(D2, S);
+    int baseA3 = hb2 + 2 * S * second * D3 - 2 * step_bias(D3, S);
+    int baseA0 = hb2 - 2 * step_bias(0, S);
+    int baseB = 2 * (second * NCO + r) + half;
     // this thread's halo pieces c = threadIdx.x + 256 k: point (packed) or -1
     int hp[6];
 #pragma unroll
@@ -437,14 +445,39 @@ conv3d_tiled_kernel(
         }
     };
     // weight rows (t, o) of input chunk cc: w[t][cob + o][cc .. cc + 15]
+    const int ls = ntiles == 2 ? 5 : 4;
     auto stage_weights = [&](int cc) {
-        const int ls = ntiles == 2 ? 5 : 4;
         for (int c = threadIdx.x; c < 27 * nco * 2; c += 256) {
             const int row = c >> 1, t = row >> ls, o = row & (nco - 1);
             wl[2 * (t * NCO + o) + (c & 1)] = *(const uint4 *)(w + (t * cout + cob + o) * cin + cc + 8 * (c & 1));
         }
     };
-    if (nmine > 0) load_halo(0, 0);
+    constexpr int NPW = WPF ? (27 * NCO * 2 + 255) / 256 : 1;
+    u4v pw[NPW];
+    auto load_weights = [&](int cc) __attribute__((always_inline)) {
+        unroll<0, NPW>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            // a thread past the last piece loads the last piece again (an
+            // unconditional load keeps pw in registers); it is not stored
+            const int c = min((int)threadIdx.x + 256 * j, 27 * nco * 2 - 1);
+            const int row = c >> 1, t = row >> ls, o = row & (nco - 1);
+            pw[j] = *(const u4v *)(w + (t * cout + cob + o) * cin + cc + 8 * (c & 1));
+        });
+    };
+    auto store_weights = [&]() __attribute__((always_inline)) {
+        unroll<0, NPW>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            const int c = threadIdx.x + 256 * j;
+            if (c < 27 * nco * 2) {
+                const int row = c >> 1, t = row >> ls, o = row & (nco - 1);
+                *(u4v *)&wl[2 * (t * NCO + o) + (c & 1)] = pw[j];
+            }
+        });
+    };
+    if (nmine > 0) {
+        load_halo(0, 0);
+        if (WPF && nchunk > 1) load_weights(0);
+    }
     if (nchunk == 1) stage_weights(0);  // the same for every item
     f4 acc[4][NT];
     for (int k = 0; k < nmine; ++k) {
@@ -453,16 +486,30 @@ conv3d_tiled_kernel(
 #pragma unroll
             for (int j = 0; j < 5; ++j) tile[threadIdx.x + 256 * j] = pf[j];
             if (threadIdx.x + 1280 < kHP * 2) tile[threadIdx.x + 1280] = pf[5];
-            if (nchunk > 1) stage_weights(chunk * 16);
+            if (nchunk > 1) {
+                if constexpr (WPF) store_weights();
+                else stage_weights(chunk * 16);
+            }
             __syncthreads();
-            if (chunk + 1 < nchunk) load_halo(k, chunk + 1);
-            else if (k + 1 < nmine) load_halo(k + 1, 0);
+            if (chunk + 1 < nchunk) {
+                load_halo(k, chunk + 1);
+                if (WPF) load_weights((chunk + 1) * 16);
+            } else if (k + 1 < nmine) {
+                load_halo(k + 1, 0);
+                if (WPF && nchunk > 1) load_weights(0);
+            }
             if (chunk == 0) {
 #pragma unroll
                 for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
             }
+            // with the weights' registers in use, the lane bases are made
+            // opaque here, so the compiler addresses the K loop's LDS reads
+            // as base + immediate instead of keeping one register per (base,
+            // offset) pair across the item loop
+            if constexpr (WPF)
+                asm volatile("" : "+v"(baseA0), "+v"(baseA1), "+v"(baseA2), "+v"(baseA3), "+v"(baseB));
             if (NT == 1 || ntiles == NT)
                 conv_kloop<NT, NT, FLIP, NT == 1>(tile, wl, baseA0, baseA1, baseA2, baseA3, baseB,
                                                  second, acc);
@@ -1658,6 +1705,17 @@ bool conv_tiled_ok(const void *x, int cin, const void *w, int cout, int nx, int 
            ((uintptr_t)x & 15) == 0 && ((uintptr_t)w & 15) == 0;
 }
 
+// Compute units of the current device (0 if the runtime cannot say).
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return cus;
+}
+
 // Launches conv3d_tiled_kernel; xc != NULL selects the concat form (cc
 // channels of the upsampled coarse tensor first, then cin - cc of x).
 void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const void *w,
@@ -1682,21 +1740,36 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
     const uint16_t *xb = (const uint16_t *)x, *xcb = (const uint16_t *)xc;
     const uint16_t *wb = (const uint16_t *)w, *mb = (const uint16_t *)mask;
     uint16_t *yb = (uint16_t *)y_bf16;
-#define SUR_CONV_LAUNCH(NTV, FL, P2, CT)                                                     \
-    hipLaunchKernelGGL((conv3d_tiled_kernel<NTV, FL, P2, CT>), grid, dim3(256), lds, st, xb, \
+    // weights prefetched with the halo: two output tiles, several input
+    // chunks, fewer blocks than two per CU (SUR_CONV_WPF=0 turns it off; for
+    // comparisons only, both give the same bits)
+    const char *wv = std::getenv("SUR_CONV_WPF");
+    const int cus = device_cus();
+    const bool wpf = nt == kNT && cin > 16 && cus > 0 && nblk * ncb < 2L * cus && !(wv && *wv == '0');
+#define SUR_CONV_LAUNCH(NTV, FL, P2, CT, WP)                                                     \
+    hipLaunchKernelGGL((conv3d_tiled_kernel<NTV, FL, P2, CT, WP>), grid, dim3(256), lds, st, xb, \
                        cin, xcb, cc, wb, bias, cout, G, relu, mb, yb, y_f32)
-#define SUR_CONV_POW2(NTV, FL, CT) \
-    do { if (pow2) SUR_CONV_LAUNCH(NTV, FL, true, CT); else SUR_CONV_LAUNCH(NTV, FL, false, CT); } while (0)
+#define SUR_CONV_POW2(NTV, FL, CT, WP)                                   \
+    do {                                                                 \
+        if (pow2) SUR_CONV_LAUNCH(NTV, FL, true, CT, WP);                \
+        else SUR_CONV_LAUNCH(NTV, FL, false, CT, WP);                    \
+    } while (0)
+#define SUR_CONV_NT2(FL, CT)                                             \
+    do {                                                                 \
+        if (wpf) SUR_CONV_POW2(kNT, FL, CT, true);                       \
+        else SUR_CONV_POW2(kNT, FL, CT, false);                          \
+    } while (0)
     if (xc) {
-        if (nt == 1) SUR_CONV_POW2(1, false, true);
-        else SUR_CONV_POW2(kNT, false, true);
+        if (nt == 1) SUR_CONV_POW2(1, false, true, false);
+        else SUR_CONV_NT2(false, true);
     } else if (nt == 1) {
-        if (flip) SUR_CONV_POW2(1, true, false);
-        else SUR_CONV_POW2(1, false, false);
+        if (flip) SUR_CONV_POW2(1, true, false, false);
+        else SUR_CONV_POW2(1, false, false, false);
     } else {
-        if (flip) SUR_CONV_POW2(kNT, true, false);
-        else SUR_CONV_POW2(kNT, false, false);
+        if (flip) SUR_CONV_NT2(true, false);
+        else SUR_CONV_NT2(false, false);
     }
+#undef SUR_CONV_NT2
 #undef SUR_CONV_POW2
 #undef SUR_CONV_LAUNCH
 }
