@@ -59,6 +59,17 @@ int sur_conv3d_cat(const void *xc, int32_t cc, const void *xf, int32_t fc, const
                    const float *bias, int32_t cout, int32_t nx, int32_t ny, int32_t nz,
                    int32_t relu, void *y_bf16, float *y_f32, void *stream);
 
+/* The encoder's second convolution of a level with its pooling: sur_conv3d
+ * (flip = 0, no mask) into BF16 y_bf16 [P][cout], and y_pool
+ * [P/8][cout] = sur_pool2 of y_bf16 (the mean of each 2 x 2 x 2 cell of
+ * the stored BF16 values, summed in FP32 in x, y, z order, rounded to BF16),
+ * bitwise, in one pass (two for cout = 16). Needs the tiled kernel (nx a multiple of 16, ny and
+ * nz of 4, 16-byte aligned x and w) and 8-byte aligned outputs; otherwise
+ * SUR_EINVAL (call sur_conv3d, then sur_pool2). */
+int sur_conv3d_pool(const void *x, int32_t cin, const void *w, const float *bias, int32_t cout,
+                    int32_t nx, int32_t ny, int32_t nz, int32_t relu, void *y_bf16, void *y_pool,
+                    void *stream);
+
 /* Floats of scratch that sur_conv3d_wgrad needs for these sizes. */
 size_t sur_wgrad_scratch_floats(int32_t cin, int32_t cout, int32_t nx, int32_t ny, int32_t nz);
 

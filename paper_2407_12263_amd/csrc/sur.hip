@@ -385,13 +385,20 @@ __device__ __forceinline__ void conv_kloop(const uint4 *tile, const uint4 *wl, i
 template <int NT, bool WPF>
 constexpr int conv_min_waves() { return NT == 1 ? 4 : (WPF ? 2 : 1); }
 
-template <int NT, bool FLIP, bool POW2, bool CAT, bool WPF>
+// With POOL the block also writes yp, the 2 x 2 x 2 average pooling of the
+// BF16 outputs it stores (a tile holds whole cells): the eight rounded
+// values of a cell are summed in FP32 in the order x, then y, then z, scaled
+// by 1/8 and rounded, as the pooling pass over the stored tensor does. The
+// x pair is in the neighbouring lane, the y pair in the lane's next row and
+// the z pair in the next wavefront, which hands its values over in LDS.
+template <int NT, bool FLIP, bool POW2, bool CAT, bool WPF, bool POOL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv_min_waves<NT, WPF>(), 8)))
 conv3d_tiled_kernel(
     const uint16_t *__restrict__ x, int cin, const uint16_t *__restrict__ xc, int cc,
     const uint16_t *__restrict__ w,
     const float *__restrict__ bias, int cout, ConvGeom G, int relu,
-    const uint16_t *__restrict__ mask, uint16_t *__restrict__ yb, float *__restrict__ yf) {
+    const uint16_t *__restrict__ mask, uint16_t *__restrict__ yb, float *__restrict__ yf,
+    uint16_t *__restrict__ yp) {
     // LDS: the input halo (kHP points x 16 channels) and the chunk's weights
     // (27 taps x 16 NT output channels x 16 channels), 32 B per row
     extern __shared__ uint4 lds[];
@@ -521,6 +528,7 @@ conv3d_tiled_kernel(
         // x0 + px of row mt of its plane, in register j of acc[mt][nt]
         int x0, y0, z0;
         tile_origin<POW2>(G, (int)blockIdx.x + k * (int)gridDim.x, x0, y0, z0);
+        float rv[POOL ? NT : 1][4][4];  // the stored BF16 values, for the pooling
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             if (nt >= ntiles) break;
@@ -552,8 +560,86 @@ conv3d_tiled_kernel(
                     const uint32_t lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(fl2{v[0], v[1]}, bf2));
                     const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(fl2{v[2], v[3]}, bf2));
                     *(uint2 *)(yb + o) = uint2{lo, hi};
+                    if constexpr (POOL) {
+                        rv[nt][mt][0] = __uint_as_float(lo << 16);
+                        rv[nt][mt][1] = __uint_as_float(lo & 0xffff0000u);
+                        rv[nt][mt][2] = __uint_as_float(hi << 16);
+                        rv[nt][mt][3] = __uint_as_float(hi & 0xffff0000u);
+                    }
                 }
                 if (yf) *(f4 *)(yf + o) = f4{v[0], v[1], v[2], v[3]};
+            }
+        }
+        if constexpr (POOL) {
+            // cell (x0 + r, y0 + 2 pr, z0 + w) .. + 1 of the even lanes r and
+            // wavefronts w; value i = dx + 2 dy of plane dz = w & 1, channel j
+            float *ex = (float *)tile;  // free once every wavefront is here
+            const int pair = wave >> 1;
+            __syncthreads();
+            // slot of an even lane's cell: 2 pairs x NT x 2 row pairs x 32
+            // lanes x 4 values x 4 channels (at most 16 KB, inside the halo)
+            auto slot = [&](int nt, int pr) {
+                return (f4 *)(ex + ((((pair * NT + nt) * 2 + pr) * 32) + (q * 8 + (r >> 1))) * 16);
+            };
+            const int cx = G.nx >> 1, cy = G.ny >> 1;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                if (nt >= ntiles) break;
+#pragma unroll
+                for (int pr = 0; pr < 2; ++pr) {
+                    // the x neighbours (lane r + 1), shuffled with every lane active
+                    float n0[4], n1[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        n0[j] = __shfl_xor(rv[nt][2 * pr][j], 1, 64);
+                        n1[j] = __shfl_xor(rv[nt][2 * pr + 1][j], 1, 64);
+                    }
+                    if ((wave & 1) && !(r & 1)) {
+                        f4 *e = slot(nt, pr);
+                        e[0] = f4{rv[nt][2 * pr][0], rv[nt][2 * pr][1], rv[nt][2 * pr][2], rv[nt][2 * pr][3]};
+                        e[1] = f4{n0[0], n0[1], n0[2], n0[3]};
+                        e[2] = f4{rv[nt][2 * pr + 1][0], rv[nt][2 * pr + 1][1], rv[nt][2 * pr + 1][2],
+                                  rv[nt][2 * pr + 1][3]};
+                        e[3] = f4{n1[0], n1[1], n1[2], n1[3]};
+                    }
+                    // the lower plane keeps its running sums over the barrier
+                    if (!(wave & 1)) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            float sum = 0.f;
+                            sum += rv[nt][2 * pr][j];
+                            sum += n0[j];
+                            sum += rv[nt][2 * pr + 1][j];
+                            sum += n1[j];
+                            rv[nt][2 * pr][j] = sum;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (!(wave & 1) && !(r & 1)) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    if (nt >= ntiles) break;
+                    const int co = cob + nt * 16 + 4 * q;
+#pragma unroll
+                    for (int pr = 0; pr < 2; ++pr) {
+                        const f4 *e = slot(nt, pr);
+                        float sum[4] = {rv[nt][2 * pr][0], rv[nt][2 * pr][1], rv[nt][2 * pr][2], rv[nt][2 * pr][3]};
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const f4 bv4 = e[i];
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) sum[j] += bv4[j];
+                        }
+                        uint32_t h[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) h[j] = f2bf(0.125f * sum[j]);
+                        const int X = (x0 + r) >> 1, Y = (y0 >> 1) + pr, Z = (z0 + wave) >> 1;
+                        const uint32_t qo = (uint32_t)(X + cx * (Y + cy * Z)) * (uint32_t)cout + co;
+                        *(uint2 *)(yp + qo) = uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+                    }
+                }
             }
         }
     }
@@ -1717,10 +1803,11 @@ int device_cus() {
 }
 
 // Launches conv3d_tiled_kernel; xc != NULL selects the concat form (cc
-// channels of the upsampled coarse tensor first, then cin - cc of x).
+// channels of the upsampled coarse tensor first, then cin - cc of x);
+// y_pool != NULL the pooled output as well (forward form, BF16 output).
 void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const void *w,
                        const float *bias, int cout, int nx, int ny, int nz, bool flip, int relu,
-                       const void *mask, void *y_bf16, float *y_f32, hipStream_t st) {
+                       const void *mask, void *y_bf16, float *y_f32, void *y_pool, hipStream_t st) {
     const long P = (long)nx * ny * nz;
     // one N tile per block for 16 output channels (fewer registers), two otherwise
     const int nt = cout <= 16 ? 1 : kNT, nb = 16 * nt;
@@ -1739,35 +1826,37 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
     }
     const uint16_t *xb = (const uint16_t *)x, *xcb = (const uint16_t *)xc;
     const uint16_t *wb = (const uint16_t *)w, *mb = (const uint16_t *)mask;
-    uint16_t *yb = (uint16_t *)y_bf16;
+    uint16_t *yb = (uint16_t *)y_bf16, *yp = (uint16_t *)y_pool;
     // weights prefetched with the halo: two output tiles, several input
     // chunks, fewer blocks than two per CU (SUR_CONV_WPF=0 turns it off; for
     // comparisons only, both give the same bits)
     const char *wv = std::getenv("SUR_CONV_WPF");
     const int cus = device_cus();
     const bool wpf = nt == kNT && cin > 16 && cus > 0 && nblk * ncb < 2L * cus && !(wv && *wv == '0');
-#define SUR_CONV_LAUNCH(NTV, FL, P2, CT, WP)                                                     \
-    hipLaunchKernelGGL((conv3d_tiled_kernel<NTV, FL, P2, CT, WP>), grid, dim3(256), lds, st, xb, \
-                       cin, xcb, cc, wb, bias, cout, G, relu, mb, yb, y_f32)
-#define SUR_CONV_POW2(NTV, FL, CT, WP)                                   \
+#define SUR_CONV_LAUNCH(NTV, FL, P2, CT, WP, PL)                                                     \
+    hipLaunchKernelGGL((conv3d_tiled_kernel<NTV, FL, P2, CT, WP, PL>), grid, dim3(256), lds, st, xb, \
+                       cin, xcb, cc, wb, bias, cout, G, relu, mb, yb, y_f32, yp)
+#define SUR_CONV_POW2(NTV, FL, CT, WP, PL)                               \
     do {                                                                 \
-        if (pow2) SUR_CONV_LAUNCH(NTV, FL, true, CT, WP);                \
-        else SUR_CONV_LAUNCH(NTV, FL, false, CT, WP);                    \
+        if (pow2) SUR_CONV_LAUNCH(NTV, FL, true, CT, WP, PL);            \
+        else SUR_CONV_LAUNCH(NTV, FL, false, CT, WP, PL);                \
     } while (0)
-#define SUR_CONV_NT2(FL, CT)                                             \
+#define SUR_CONV_NT2(FL, CT, PL)                                         \
     do {                                                                 \
-        if (wpf) SUR_CONV_POW2(kNT, FL, CT, true);                       \
-        else SUR_CONV_POW2(kNT, FL, CT, false);                          \
+        if (wpf) SUR_CONV_POW2(kNT, FL, CT, true, PL);                   \
+        else SUR_CONV_POW2(kNT, FL, CT, false, PL);                      \
     } while (0)
     if (xc) {
-        if (nt == 1) SUR_CONV_POW2(1, false, true, false);
-        else SUR_CONV_NT2(false, true);
+        if (nt == 1) SUR_CONV_POW2(1, false, true, false, false);
+        else SUR_CONV_NT2(false, true, false);
+    } else if (y_pool && nt == kNT) {
+        SUR_CONV_NT2(false, false, true);
     } else if (nt == 1) {
-        if (flip) SUR_CONV_POW2(1, true, false, false);
-        else SUR_CONV_POW2(1, false, false, false);
+        if (flip) SUR_CONV_POW2(1, true, false, false, false);
+        else SUR_CONV_POW2(1, false, false, false, false);
     } else {
-        if (flip) SUR_CONV_NT2(true, false);
-        else SUR_CONV_NT2(false, false);
+        if (flip) SUR_CONV_NT2(true, false, false);
+        else SUR_CONV_NT2(false, false, false);
     }
 #undef SUR_CONV_NT2
 #undef SUR_CONV_POW2
@@ -1788,7 +1877,7 @@ int sur_conv3d(const void *x, int32_t cin, const void *w, const float *bias, int
     const long P = (long)nx * ny * nz;
     if (conv_tiled_ok(x, cin, w, cout, nx, ny, nz)) {
         conv_tiled_launch(x, cin, nullptr, 0, w, bias, cout, nx, ny, nz, flip != 0, relu, mask,
-                          y_bf16, y_f32, (hipStream_t)stream);
+                          y_bf16, y_f32, nullptr, (hipStream_t)stream);
         return launched();
     }
     const dim3 grid((unsigned)((P + 255) / 256), (unsigned)((cout + 63) / 64));
@@ -1807,7 +1896,28 @@ int sur_conv3d_cat(const void *xc, int32_t cc, const void *xf, int32_t fc, const
         ((uintptr_t)xc & 15) != 0 || !elems_ok((long)nx * ny * nz, cc))
         return SUR_EINVAL;
     conv_tiled_launch(xf, cc + fc, xc, cc, w, bias, cout, nx, ny, nz, false, relu, nullptr, y_bf16,
-                      y_f32, (hipStream_t)stream);
+                      y_f32, nullptr, (hipStream_t)stream);
+    return launched();
+}
+
+int sur_conv3d_pool(const void *x, int32_t cin, const void *w, const float *bias, int32_t cout,
+                    int32_t nx, int32_t ny, int32_t nz, int32_t relu, void *y_bf16, void *y_pool,
+                    void *stream) {
+    clear_stale_error();
+    if (!x || !w || !y_bf16 || !y_pool || cin <= 0 || cout <= 0 || cin % 16 || cout % 16 ||
+        !dims_ok(nx, ny, nz) || !conv_tiled_ok(x, cin, w, cout, nx, ny, nz) ||
+        ((uintptr_t)y_bf16 & 7) != 0 || ((uintptr_t)y_pool & 7) != 0)
+        return SUR_EINVAL;
+    if (cout <= 16) {
+        // one output tile: its epilogue has no registers to spare for the
+        // pooling (it would run slower than the two passes), so pool after
+        conv_tiled_launch(x, cin, nullptr, 0, w, bias, cout, nx, ny, nz, false, relu, nullptr,
+                          y_bf16, nullptr, nullptr, (hipStream_t)stream);
+        if (launched() != SUR_OK) return SUR_EDEVICE;
+        return sur_pool2(y_bf16, cout, nx, ny, nz, y_pool, stream);
+    }
+    conv_tiled_launch(x, cin, nullptr, 0, w, bias, cout, nx, ny, nz, false, relu, nullptr, y_bf16,
+                      nullptr, y_pool, (hipStream_t)stream);
     return launched();
 }
 

@@ -42,6 +42,7 @@ def load_library(path: str | None = None):
     vp, i32, i64, fl, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
     lib.sur_conv3d.argtypes = [vp, i32, vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp]
     lib.sur_conv3d_cat.argtypes = [vp, i32, vp, i32, vp, vp, i32, i32, i32, i32, i32, vp, vp, vp]
+    lib.sur_conv3d_pool.argtypes = [vp, i32, vp, vp, i32, i32, i32, i32, i32, vp, vp, vp]
     lib.sur_wgrad_scratch_floats.argtypes = [i32, i32, i32, i32, i32]
     lib.sur_wgrad_scratch_floats.restype = sz
     lib.sur_conv3d_wgrad.argtypes = [vp, i32, vp, i32, i32, i32, i32, vp, sz, vp, vp, vp]
@@ -71,7 +72,7 @@ def load_library(path: str | None = None):
     lib.sur_prolong_update_scratch_doubles.argtypes = [i32, i32, i32]
     lib.sur_prolong_update_scratch_doubles.restype = sz
     lib.sur_prolong_update.argtypes = [vp, vp, i32, i32, i32, vp, C.c_double, vp, vp, vp, vp, vp, vp]
-    for n in ["sur_features", "sur_prolong_update", "sur_apply_residual", "sur_residual_target", "sur_fix_mass", "sur_conv3d", "sur_conv3d_cat", "sur_conv3d_wgrad", "sur_pack_weights", "sur_pool2", "sur_pool2_bwd",
+    for n in ["sur_features", "sur_prolong_update", "sur_apply_residual", "sur_residual_target", "sur_fix_mass", "sur_conv3d", "sur_conv3d_cat", "sur_conv3d_pool", "sur_conv3d_wgrad", "sur_pack_weights", "sur_pool2", "sur_pool2_bwd",
               "sur_upsample2", "sur_upsample2_bwd", "sur_copy_channels", "sur_add_channels",
               "sur_to_bf16", "sur_relu_mask", "sur_mse", "sur_adam", "sur_coarsen",
               "sur_prolong_add", "sur_checks", "sur_checks_noalloc", "sur_pool2_bwd_skip", "sur_upsample2_bwd_mask",
@@ -110,9 +111,15 @@ def sur_conv3d_cat(xc, cc, xf, fc, w, bias, cout, grid, relu=0, y_bf16=None, y_f
                                       relu, _p(y_bf16), _p(y_f32), _stream()), "sur_conv3d_cat")
 
 
+def sur_conv3d_pool(x, cin, w, bias, cout, grid, relu=0, y_bf16=None, y_pool=None):
+    nx, ny, nz = grid
+    _ok(load_library().sur_conv3d_pool(_p(x), cin, _p(w), _p(bias), cout, nx, ny, nz, relu,
+                                       _p(y_bf16), _p(y_pool), _stream()), "sur_conv3d_pool")
+
+
 def conv_cat_fits(grid):
-    """Whether sur_conv3d_cat takes these fine-grid sizes (its tiled kernel's
-    16 x 4 x 4 point tile)."""
+    """Whether sur_conv3d_cat and sur_conv3d_pool take these (fine-grid)
+    sizes: their tiled kernel's 16 x 4 x 4 point tile."""
     nx, ny, nz = grid
     return nx % 16 == 0 and ny % 4 == 0 and nz % 4 == 0
 
@@ -388,11 +395,19 @@ class UNet:
             g = self.grids[lv]
             for part in "ab":
                 name, ci, co, relu = self.layers[k]
-                sur_conv3d(h, ci, self.wf[k], self.b[k], co, g, relu=1, y_bf16=self.act[name])
+                if part == "b" and lv < self.nlev - 1 and conv_cat_fits(g):
+                    # the pooled output in the same pass
+                    sur_conv3d_pool(h, ci, self.wf[k], self.b[k], co, g, relu=1,
+                                    y_bf16=self.act[name], y_pool=self.act[f"pool{lv}"])
+                    pooled = True
+                else:
+                    sur_conv3d(h, ci, self.wf[k], self.b[k], co, g, relu=1, y_bf16=self.act[name])
+                    pooled = False
                 h, hc = self.act[name], co
                 k += 1
             if lv < self.nlev - 1:
-                sur_pool2(h, hc, g, self.act[f"pool{lv}"])
+                if not pooled:
+                    sur_pool2(h, hc, g, self.act[f"pool{lv}"])
                 h = self.act[f"pool{lv}"]
         self._cat_kept = True
         for lv in range(self.nlev - 2, -1, -1):

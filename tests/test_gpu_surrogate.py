@@ -138,9 +138,41 @@ def test_conv_reading_the_concat_in_place(sur, cc, fc, cout, relu, grid):
     assert torch.equal(yf, yf2) and torch.equal(yb, yb2)
 
 
+@pytest.mark.parametrize("wpf", ["", "0"])
+@pytest.mark.parametrize("grid", CAT_GRIDS + [(64, 16, 12)])
+@pytest.mark.parametrize("cin,cout", [(16, 16), (32, 32), (48, 48), (16, 64), (64, 16)])
+def test_conv_with_pooling_in_the_same_pass(sur, cin, cout, grid, wpf, monkeypatch):
+    """sur_conv3d_pool = sur_conv3d then sur_pool2, bitwise, and the pooled
+    output within BF16 rounding of the oracle's pool2 of the BF16 output;
+    with and without the weight prefetch of small grids (SUR_CONV_WPF)."""
+    import torch
+    monkeypatch.setenv("SUR_CONV_WPF", wpf)
+    say(f"[sur] conv + pooling in one pass cin={cin} cout={cout} grid={grid} wpf={wpf!r}")
+    rng = np.random.default_rng(cin * 7 + cout)
+    nx, ny, nz = grid
+    P = nx * ny * nz
+    x = so.bf16_round(rng.standard_normal((nz, ny, nx, cin)).astype(np.float32))
+    w = rng.standard_normal((27, cout, cin)).astype(np.float32) * 0.1
+    b = rng.standard_normal(cout).astype(np.float32)
+    wf = torch.empty((27, cout, cin), dtype=torch.int16, device="cuda")
+    sur.sur_pack_weights(_f32(w), cin, cout, wf, None)
+    xb, bb = _bits(x.reshape(-1, cin)), _f32(b)
+    yb = torch.empty((P, cout), dtype=torch.int16, device="cuda")
+    yp = torch.empty((P // 8, cout), dtype=torch.int16, device="cuda")
+    sur.sur_conv3d_pool(xb, cin, wf, bb, cout, grid, relu=1, y_bf16=yb, y_pool=yp)
+    yb2 = torch.empty_like(yb)
+    yp2 = torch.empty_like(yp)
+    sur.sur_conv3d(xb, cin, wf, bb, cout, grid, relu=1, y_bf16=yb2)
+    sur.sur_pool2(yb2, cout, grid, yp2)
+    assert torch.equal(yb, yb2) and torch.equal(yp, yp2)
+    ref = so.pool2(_from_bits(yb).reshape(nz, ny, nx, cout).astype(np.float64))
+    got = _from_bits(yp).reshape(ref.shape)
+    assert np.abs(got - ref).max() <= 2 ** -8 * (np.abs(ref).max() + 1e-30)
+
+
 def test_conv_cat_rejects_grids_off_its_tile(sur):
     """Sizes that are not multiples of the 16 x 4 x 4 tile are refused on the
-    host (the caller concatenates and calls sur_conv3d)."""
+    host by the concat and pooling forms (the caller takes two passes)."""
     import torch
     grid = (8, 8, 8)
     xc = torch.zeros((64, 32), dtype=torch.int16, device="cuda")
@@ -150,6 +182,10 @@ def test_conv_cat_rejects_grids_off_its_tile(sur):
     assert not sur.conv_cat_fits(grid)
     with pytest.raises(RuntimeError):
         sur.sur_conv3d_cat(xc, 32, xf, 16, wf, None, 16, grid, y_bf16=yb)
+    yp = torch.empty((64, 16), dtype=torch.int16, device="cuda")
+    w16 = torch.zeros((27, 16, 16), dtype=torch.int16, device="cuda")
+    with pytest.raises(RuntimeError):
+        sur.sur_conv3d_pool(xf, 16, w16, None, 16, grid, y_bf16=yb, y_pool=yp)
 
 
 def test_unet_inference_forward_equals_training_forward(sur):
