@@ -1721,10 +1721,6 @@ long wgrad_chunks(long P) { return (P + kWgradChunk - 1) / kWgradChunk; }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
-// Persistent blocks of the tiled convolution in all (at most one per tile):
-// 2048 measured best of 512 .. 4096 on the U-Net's 128^3 layers (within 5%
-// everywhere). SUR_CONV_BLOCKS overrides it (tuning only; results do not
-// depend on it).
 bool pow2_ok(int n) { return n > 0 && (n & (n - 1)) == 0; }
 int ilog2(int n) {
     int l = 0;
@@ -1732,9 +1728,17 @@ int ilog2(int n) {
     return l;
 }
 
-int env_blocks() {
+// Persistent blocks of the tiled convolution (over all output-channel
+// blocks): eight per CU for one output tile and one input chunk (two rounds
+// of four resident blocks, so a block's next item overlaps another's
+// epilogue), otherwise as many as are resident at once (three per CU, LDS
+// bound), which keeps the last round of a grid from running a third full.
+// SUR_CONV_BLOCKS overrides it (tuning only; results do not depend on it).
+int conv_blocks(int nt, int nchunk, int cus) {
     const char *v = std::getenv("SUR_CONV_BLOCKS");
-    return v && *v ? std::max(1, std::atoi(v)) : 2048;
+    if (v && *v) return std::max(1, std::atoi(v));
+    if (cus <= 0) return 2048;
+    return (nt == 1 && nchunk == 1 ? 8 : 3) * cus;
 }
 
 // The tiled weight gradient: lattice sizes multiples of the 16 x 4 x 4 tile,
@@ -1813,7 +1817,8 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
     const int nt = cout <= 16 ? 1 : kNT, nb = 16 * nt;
     const long tiles = P / (kTX * kTY * kTZ);
     const long ncb = (cout + nb - 1) / nb;
-    const long nblk = std::max(1L, std::min(tiles, (long)env_blocks() / ncb));
+    const int cus = device_cus();
+    const long nblk = std::max(1L, std::min(tiles, (long)conv_blocks(nt, cin / 16, cus) / ncb));
     const dim3 grid((unsigned)nblk, (unsigned)ncb);
     const size_t lds = conv_tiled_lds(nt);
     ConvGeom G{nx, ny, nz, nx / kTX, ny / kTY, nz / kTZ, 0, 0, 0, 0};
@@ -1831,7 +1836,6 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
     // chunks, fewer blocks than two per CU (SUR_CONV_WPF=0 turns it off; for
     // comparisons only, both give the same bits)
     const char *wv = std::getenv("SUR_CONV_WPF");
-    const int cus = device_cus();
     const bool wpf = nt == kNT && cin > 16 && cus > 0 && nblk * ncb < 2L * cus && !(wv && *wv == '0');
 #define SUR_CONV_LAUNCH(NTV, FL, P2, CT, WP, PL)                                                     \
     hipLaunchKernelGGL((conv3d_tiled_kernel<NTV, FL, P2, CT, WP, PL>), grid, dim3(256), lds, st, xb, \
