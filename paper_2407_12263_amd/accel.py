@@ -394,6 +394,30 @@ class RunStats:
     seconds: float = 0.0
 
 
+class ExactChange:
+    """Reference predictor: the coarse change of the plain run itself, window
+    w -> w + 1, from a store holding that trajectory's snapshots (labels
+    (traj, 0 .. windows)). With it a schedule's error is that of the grid
+    transfers and resets alone: the lowest error the schedule can reach with
+    any network."""
+    windowed = True
+
+    def __init__(self, cp: Coupler, store: SnapshotStore, rscale, traj: int = 0):
+        torch = cp.torch
+        self.cp = cp
+        self.store = store
+        self.slots = {lab[1]: k for k, lab in enumerate(store.label)
+                      if lab is not None and lab[0] == traj}
+        self.rs = torch.as_tensor(np.asarray(rscale, dtype=np.float32)).to(store.data.device)
+        self.out = torch.empty((cp.P, sur.NCH), dtype=torch.float32, device=store.data.device)
+
+    def __call__(self, state, window: int):
+        a, b = self.slots[window], self.slots[window + 1]
+        sur.sur_residual_target(self.store.data[a], self.store.data[b], self.rs, sur.NUSE,
+                                self.cp.P, self.out, self.cp.res_width)
+        return self.out
+
+
 def accelerated_run(cp: Coupler, net: sur.UNet, rscale, windows: int, nsur: int = 7,
                     cycle: int = 8, limits: CheckLimits | None = None,
                     judge_tol: float = 0.5, predictor=None, linear: bool = False,
@@ -402,7 +426,8 @@ def accelerated_run(cp: Coupler, net: sur.UNet, rscale, windows: int, nsur: int 
     described in the module docstring. ``predictor`` (default: the network)
     maps a coarse state to its predicted change in rscale units (FP32
     [Pc][16]); it exists so that the same schedule can be run with a
-    reference predictor."""
+    reference predictor. One with ``windowed = True`` is also given the
+    index of the window it predicts (windows since the run's start)."""
     torch = cp.torch
     solver = cp.solver
     limits = limits or CheckLimits()
@@ -417,8 +442,10 @@ def accelerated_run(cp: Coupler, net: sur.UNet, rscale, windows: int, nsur: int 
     mse_scr = torch.empty(P // 256 + 2, dtype=torch.float64, device=dev)
     mse_out = torch.empty(2, dtype=torch.float64, device=dev)
 
-    def predict(state):
+    def predict(state, window):
         if predictor is not None:
+            if getattr(predictor, "windowed", False):
+                return predictor(state, window)
             return predictor(state)
         sur.sur_to_bf16(state, xb)
         return net.forward(xb)
@@ -447,9 +474,9 @@ def accelerated_run(cp: Coupler, net: sur.UNet, rscale, windows: int, nsur: int 
         mass0 = float(chk0[0].item())
         s.copy_(s0)
         done = 0
-        for _ in range(nsur_c):
+        for i in range(nsur_c):
             sprev.copy_(s)
-            out = predict(s)
+            out = predict(s, w + i)
             sur.sur_apply_residual(s, out, rs, sur.NUSE, P, cp.res_width)
             cp.checks(s, chk)
             why = limits.failed(chk.cpu().numpy(), mass0)
@@ -479,7 +506,7 @@ def accelerated_run(cp: Coupler, net: sur.UNet, rscale, windows: int, nsur: int 
         if done == nsur_c and remaining >= 1 and judge_tol is not None:
             # the solver's first window of the cycle is the judge of the network
             spred.copy_(s)
-            out = predict(s)
+            out = predict(s, w + done)
             sur.sur_apply_residual(spred, out, rs, sur.NUSE, P, cp.res_width)
             solver.step(K_STEPS)
             cp.snapshot(slbm)
@@ -677,13 +704,15 @@ def surrogate_benchmark(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rma
 
     limits = CheckLimits(div_rms=3.0 * max(divs))
     zero = cp.new_state()
+    exact = ExactChange(cp, hs, rscale, traj=hs.label[0][0])
     runs = {}
     for ns in schedules:
-        for name, pred, lin in (("net", None, False), ("persistence", lambda s: zero, False)):
+        for name, pred, lin in (("net", None, False), ("persistence", lambda s: zero, False),
+                                ("exact", exact, False)):
             solver.reset(*f0, 0)
             st = accelerated_run(cp, net, rscale, horizon, nsur=ns, cycle=cycle,
                                              limits=limits, predictor=pred, linear=lin,
-                                             judge_tol=0.5 if name == "net" else None)
+                                             judge_tol=0.5 if name != "persistence" else None)
             err = phi_error(solver, phi_ref)
             m = solver.diagnostics()["sum_phi"]
             runs[f"nsur{ns}_{name}"] = dict(

@@ -62,3 +62,19 @@ def test_level_set_reconstruction_floor_is_below_linear(result):
     say(f"   reconstruction floor {f}")
     assert f["1_windows_level_set"] < f["1_windows_linear"]
     assert f["7_windows_level_set"] < f["7_windows_linear"]
+
+
+def test_exact_coarse_changes_bound_the_schedule_error(result):
+    """The same schedules fed the plain run's own coarse changes: what is
+    left is the error of the grid transfers and resets, below the network's
+    and far below persistence; it bounds what any network can reach."""
+    for ns in (1, 3):
+        ex = result["runs"][f"nsur{ns}_exact"]
+        net = result["runs"][f"nsur{ns}_net"]
+        per = result["runs"][f"nsur{ns}_persistence"]
+        say(f"   nsur={ns}: exact-change err {ex['phi_l2_error']:.3e}, net {net['phi_l2_error']:.3e}, "
+            f"persistence {per['phi_l2_error']:.3e}")
+        assert ex["surrogate_windows"] == per["surrogate_windows"]
+        assert ex["fallbacks"] == 0
+        assert ex["phi_l2_error"] < net["phi_l2_error"]
+        assert ex["phi_l2_error"] < 0.2 * per["phi_l2_error"]
