@@ -20,11 +20,13 @@ extern "C" {
 
 enum { PROBE_OK = 0, PROBE_EINVAL = -1, PROBE_EDEVICE = -3 };
 
-/* dst[0 .. bytes) = src[0 .. bytes) with 16-byte accesses, four per thread
- * and loop trip, grid-stride over `blocks` blocks of 256 threads (blocks in
- * [1, 2^20]). nontemporal != 0: loads and stores carry the nontemporal cache
- * policy (the policy of the solver's stores). bytes a multiple of 64, both
- * pointers 16-byte aligned, ranges not overlapping; PROBE_EINVAL otherwise. */
+/* dst[0 .. bytes) = src[0 .. bytes) with 16-byte accesses: blocks in
+ * [1, 2^20] gives four per thread and loop trip, grid-stride over that many
+ * blocks of 256 threads; blocks = 0 one per thread and no loop, as many
+ * blocks as the range needs. nontemporal != 0: loads and stores carry the
+ * nontemporal cache policy (the policy of the solver's stores). bytes a
+ * multiple of 64, both pointers 16-byte aligned, ranges not overlapping;
+ * PROBE_EINVAL otherwise. */
 int probe_copy(const void *src, void *dst, size_t bytes, int32_t nontemporal, int32_t blocks,
                void *stream);
 

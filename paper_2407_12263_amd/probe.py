@@ -35,7 +35,7 @@ def probe_copy(src, dst, nbytes: int, nontemporal: bool, blocks: int, stream):
         raise RuntimeError(f"probe_copy failed with status {rc}")
 
 
-def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10, blocks=(2048, 8192, 32768),
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10, blocks=(0, 2048, 8192, 32768),
                    device="cuda:0") -> dict:
     """GB/s of a copy of nbytes (bytes read + bytes written per second), for
     each variant (nontemporal or not, block count) the median of `reps`
@@ -58,7 +58,7 @@ def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10, blocks=(2048, 8192, 32
                 e1.synchronize()
                 ts.append(e0.elapsed_time(e1) * 1e-3)
             ts.sort()
-            out[f"{'nt' if nt else 'plain'}_{b}"] = 2 * nbytes / ts[len(ts) // 2] / 1e9
+            out[f"{'nt' if nt else 'plain'}_{b or 'per_thread'}"] = 2 * nbytes / ts[len(ts) // 2] / 1e9
     if not torch.equal(src[:: 1 << 16], dst[:: 1 << 16]):
         raise RuntimeError("probe_copy: the copy is wrong")
     best = max(out, key=out.get)

@@ -1,5 +1,6 @@
 """The streaming copy probe (include/probe.h) copies exactly, in both cache
-policies and at odd block counts, and rejects bad arguments on the host."""
+policies, one element per thread and at odd block counts, and rejects bad
+arguments on the host."""
 import pytest
 
 from gpu_common import say
@@ -16,7 +17,7 @@ def test_probe_copy_is_exact():
     n = (1 << 22) + 192                                # bytes: not a multiple of the grid
     src = torch.randint(0, 1 << 30, (n // 4,), dtype=torch.int32, device="cuda")
     for nt in (False, True):
-        for blocks in (1, 7, 4096):
+        for blocks in (0, 1, 7, 4096):
             say(f"[probe] copy {n} B nontemporal={nt} blocks={blocks}")
             dst = torch.zeros_like(src)
             probe.probe_copy(src, dst, n, nt, blocks, st)
@@ -26,3 +27,5 @@ def test_probe_copy_is_exact():
         probe.probe_copy(src, src, n, False, 8, st)   # overlapping ranges
     with pytest.raises(RuntimeError):
         probe.probe_copy(src, dst, n - 16, False, 8, st)  # not a multiple of 64
+    with pytest.raises(RuntimeError):
+        probe.probe_copy(src, dst, n, False, -1, st)  # negative block count
