@@ -765,6 +765,8 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
     constexpr int kCh = kHZ * kHY * kRow + 8;   // XhT channel stride (1744 B)
     constexpr int kXh = 16 * kCh;               // XhT elements
     constexpr int kDy = 256 + 8;                // dYt row stride (528 B)
+    static_assert(kHX % 2 == 0 && kHP % 2 == 0 && kRow % 2 == 0 && kCh % 2 == 0 && kDy % 2 == 0,
+                  "halo rows and strides hold whole pairs of points");
     constexpr int kNTap = 9;                    // taps per wavefront: 3 rows x 3 dx at most
     __shared__ __attribute__((aligned(16))) uint16_t xht[kXh];
     __shared__ __attribute__((aligned(16))) uint16_t dyt[MT * 16 * kDy];
@@ -787,25 +789,41 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
         const int by = rest % nty, bz = rest / nty;
         const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
         __syncthreads();  // the previous tile's reads are done
-        // input halo, channels cc .. cc + 15, transposed
-        for (int c = threadIdx.x; c < kHP * 2; c += 256) {
-            const int h = c >> 1, e0 = 8 * (c & 1);
+        // input halo, channels cc .. cc + 15, transposed: a thread takes two
+        // neighbouring halo points (hx even) and 8 channels, and writes each
+        // channel's pair as one 4-byte word
+        for (int c = threadIdx.x; c < kHP; c += 256) {
+            const int h = (c >> 1) * 2, e0 = 8 * (c & 1);
             const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
-            const int gp = wrap(x0 - 1 + hx, nx) + nx * (wrap(y0 - 1 + hy, ny) + ny * wrap(z0 - 1 + hz, nz));
-            const uint4 v = *(const uint4 *)(x + gp * cin + cc + e0);
-            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+            const int gy = wrap(y0 - 1 + hy, ny), gz = wrap(z0 - 1 + hz, nz);
+            const int g0 = wrap(x0 - 1 + hx, nx) + nx * (gy + ny * gz);
+            const int g1 = wrap(x0 + hx, nx) + nx * (gy + ny * gz);
+            const uint4 v0 = *(const uint4 *)(x + g0 * cin + cc + e0);
+            const uint4 v1 = *(const uint4 *)(x + g1 * cin + cc + e0);
+            const uint32_t w0[4] = {v0.x, v0.y, v0.z, v0.w}, w1[4] = {v1.x, v1.y, v1.z, v1.w};
+            uint32_t *dst = (uint32_t *)(xht + e0 * kCh + (hz * kHY + hy) * kRow + hx);
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
-                xht[(e0 + e) * kCh + (hz * kHY + hy) * kRow + hx] = uint16_t(wd[e >> 1] >> (16 * (e & 1)));
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t a = (w0[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+                const uint32_t b = (w1[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+                dst[e * (kCh / 2)] = a | (b << 16);
+            }
         }
-        // output gradient of the tile's points, transposed
-        for (int c = threadIdx.x; c < 256 * MT * 2; c += 256) {
-            const int pl = c / (MT * 2), oc = c - pl * (MT * 2);
+        // output gradient of the tile's points, transposed: two neighbouring
+        // points (pl even) per thread, one 4-byte word per channel
+        for (int c = threadIdx.x; c < 128 * MT * 2; c += 256) {
+            const int pl = (c / (MT * 2)) * 2, oc = c - (c / (MT * 2)) * (MT * 2);
             const int gp = (x0 + (pl & 15)) + nx * ((y0 + ((pl >> 4) & 3)) + ny * (z0 + (pl >> 6)));
-            const uint4 v = *(const uint4 *)(dy + gp * cout + 8 * oc);
-            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+            const uint4 v0 = *(const uint4 *)(dy + gp * cout + 8 * oc);
+            const uint4 v1 = *(const uint4 *)(dy + (gp + 1) * cout + 8 * oc);
+            const uint32_t w0[4] = {v0.x, v0.y, v0.z, v0.w}, w1[4] = {v1.x, v1.y, v1.z, v1.w};
+            uint32_t *dst = (uint32_t *)(dyt + (8 * oc) * kDy + pl);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) dyt[(8 * oc + e) * kDy + pl] = uint16_t(wd[e >> 1] >> (16 * (e & 1)));
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t a = (w0[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+                const uint32_t b = (w1[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+                dst[e * (kDy / 2)] = a | (b << 16);
+            }
         }
         __syncthreads();
         if (do_bias) {
