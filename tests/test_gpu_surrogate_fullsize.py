@@ -113,3 +113,70 @@ def test_conv_weight_gradient_full_size(sur, n, cin, cout):
     P = n ** 3
     assert e <= 1e-5 * (1 + np.abs(rdw).max()) * np.sqrt(P) / 64
     assert eb <= 1e-5 * (1 + np.abs(rdb).max()) * np.sqrt(P) / 64
+
+
+def test_conv_reading_the_concat_in_place_full_size_sampled(sur):
+    """The decoder's first 128^3 convolution (32 upsampled channels of the
+    64^3 level + 16 skip channels -> 16) reading its concat in place, on
+    4096 sampled points against the definition over the concatenated input."""
+    import torch
+    n, cc, fc, cout = 128, 32, 16, 16
+    say(f"[sur-full] conv of the concat in place {n}^3 ({cc} up + {fc} skip) -> {cout}: 4096 points")
+    rng = np.random.default_rng(77)
+    xc = so.bf16_round(rng.standard_normal((n // 2, n // 2, n // 2, cc)).astype(np.float32))
+    xf = so.bf16_round(rng.standard_normal((n, n, n, fc)).astype(np.float32))
+    w = so.bf16_round((rng.standard_normal((27, cout, cc + fc)) * 0.1).astype(np.float32))
+    b = rng.standard_normal(cout).astype(np.float32)
+    wf = torch.empty((27, cout, cc + fc), dtype=torch.int16, device="cuda")
+    sur.sur_pack_weights(_f32(w), cc + fc, cout, wf, None)
+    y = torch.empty((n ** 3, cout), dtype=torch.float32, device="cuda")
+    sur.sur_conv3d_cat(_bits(xc.reshape(-1, cc)), cc, _bits(xf.reshape(-1, fc)), fc, wf, _f32(b),
+                       cout, (n, n, n), relu=1, y_f32=y)
+    pts = rng.integers(0, n, size=(4096, 3))
+    ref = np.zeros((len(pts), cout))
+    for t, (dx, dy, dz) in enumerate(so.TAPS):
+        zz, yy, xx = (pts[:, 0] + dz) % n, (pts[:, 1] + dy) % n, (pts[:, 2] + dx) % n
+        xin = np.concatenate([xc[zz // 2, yy // 2, xx // 2], xf[zz, yy, xx]], axis=1).astype(np.float64)
+        ref += xin @ w[t].astype(np.float64).T
+    ref = np.maximum(ref + b, 0.0)
+    got = y.cpu().numpy().reshape(n, n, n, cout)[pts[:, 0], pts[:, 1], pts[:, 2]]
+    e = np.abs(got - ref).max()
+    say(f"   max|dy| {e:.2e} (scale {np.abs(ref).max():.2f})")
+    assert e <= 1e-5 * (1 + np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n,cin,cout", [(64, 32, 32), (32, 48, 48)])
+def test_conv_with_pooling_full_size_sampled(sur, n, cin, cout):
+    """The encoders' second convolutions with their pooling in one pass (the
+    64^3 and 32^3 levels): the BF16 output on 4096 sampled points against
+    the definition, and the pooled output on 4096 sampled cells equal to the
+    mean of the cell's eight stored BF16 values (summed x, y, z in FP32)."""
+    import torch
+    say(f"[sur-full] conv + pooling {n}^3 {cin}->{cout}: 4096 points and cells")
+    rng = np.random.default_rng(5 * n + cin)
+    x = so.bf16_round(rng.standard_normal((n, n, n, cin)).astype(np.float32))
+    w = so.bf16_round((rng.standard_normal((27, cout, cin)) * 0.1).astype(np.float32))
+    b = rng.standard_normal(cout).astype(np.float32)
+    wf = torch.empty((27, cout, cin), dtype=torch.int16, device="cuda")
+    sur.sur_pack_weights(_f32(w), cin, cout, wf, None)
+    yb = torch.empty((n ** 3, cout), dtype=torch.int16, device="cuda")
+    yp = torch.empty((n ** 3 // 8, cout), dtype=torch.int16, device="cuda")
+    sur.sur_conv3d_pool(_bits(x.reshape(-1, cin)), cin, wf, _f32(b), cout, (n, n, n), relu=1,
+                        y_bf16=yb, y_pool=yp)
+    ybits = yb.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    yv = ybits.view(np.float32).reshape(n, n, n, cout)
+    pts = rng.integers(0, n, size=(4096, 3))
+    ref = np.maximum(_sampled_conv(x, w.astype(np.float64), b.astype(np.float64), pts, False), 0.0)
+    got = yv[pts[:, 0], pts[:, 1], pts[:, 2]]
+    e = np.abs(got - ref).max()
+    say(f"   max|dy| {e:.2e} (scale {np.abs(ref).max():.2f})")
+    assert e <= 2 ** -8 * np.abs(ref).max() + 1e-5 * (1 + np.abs(ref).max())
+    cells = rng.integers(0, n // 2, size=(4096, 3))
+    s = np.zeros((len(cells), cout), dtype=np.float32)
+    for k in range(8):
+        dx, dy, dz = k & 1, (k >> 1) & 1, k >> 2
+        s = s + yv[2 * cells[:, 0] + dz, 2 * cells[:, 1] + dy, 2 * cells[:, 2] + dx]
+    want = so.bf16_round(np.float32(0.125) * s)
+    pbits = yp.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    pv = pbits.view(np.float32).reshape(n // 2, n // 2, n // 2, cout)
+    assert np.array_equal(pv[cells[:, 0], cells[:, 1], cells[:, 2]], want)
