@@ -229,8 +229,8 @@ struct ConvGeom {
     int ltx, ltxy;  // log2 ntx, log2 (ntx nty)
 };
 
-// Origin of tile tl (x fastest over tiles).
-template <bool POW2>
+// Origin of tile tl (x fastest over tiles) of TZ planes in z.
+template <bool POW2, int TZ = kTZ>
 __device__ __forceinline__ void tile_origin(const ConvGeom &G, int tl, int &x0, int &y0, int &z0) {
     int bx, by, bz;
     if constexpr (POW2) {
@@ -245,7 +245,7 @@ __device__ __forceinline__ void tile_origin(const ConvGeom &G, int tl, int &x0, 
     }
     x0 = bx * kTX;
     y0 = by * kTY;
-    z0 = bz * kTZ;
+    z0 = bz * TZ;
 }
 
 // Point index of (x, y, z), each at most one period outside the grid.
@@ -391,18 +391,25 @@ constexpr int conv_min_waves() { return NT == 1 ? 4 : (WPF ? 2 : 1); }
 // by 1/8 and rounded, as the pooling pass over the stored tensor does. The
 // x pair is in the neighbouring lane, the y pair in the lane's next row and
 // the z pair in the next wavefront, which hands its values over in LDS.
-template <int NT, bool FLIP, bool POW2, bool CAT, bool WPF, bool POOL>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv_min_waves<NT, WPF>(), 8)))
+// WV = 8 (one output tile, large grids): blocks of eight wavefronts on
+// 16 x 4 x 8 point tiles, each wavefront as above on one plane; the halo
+// (18 x 6 x 10, 34.6 KB) is re-read 2.1 times instead of 2.5, and a block's
+// staging and barriers serve twice the points.
+template <int NT, bool FLIP, bool POW2, bool CAT, bool WPF, bool POOL, int WV = 4>
+__global__ void __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(conv_min_waves<NT, WPF>(), 8)))
 conv3d_tiled_kernel(
     const uint16_t *__restrict__ x, int cin, const uint16_t *__restrict__ xc, int cc,
     const uint16_t *__restrict__ w,
     const float *__restrict__ bias, int cout, ConvGeom G, int relu,
     const uint16_t *__restrict__ mask, uint16_t *__restrict__ yb, float *__restrict__ yf,
     uint16_t *__restrict__ yp) {
-    // LDS: the input halo (kHP points x 16 channels) and the chunk's weights
+    static_assert(WV == 4 || (WV == 8 && NT == 1 && !POOL), "eight wavefronts: one output tile, no pooling");
+    constexpr int NTH = 64 * WV, TZ = WV, HP = kHX * kHY * (TZ + 2);
+    constexpr int NPF = (2 * HP + NTH - 1) / NTH;  // halo pieces per thread
+    // LDS: the input halo (HP points x 16 channels) and the chunk's weights
     // (27 taps x 16 NT output channels x 16 channels), 32 B per row
     extern __shared__ uint4 lds[];
-    uint4 *tile = lds, *wl = lds + kHP * 2;
+    uint4 *tile = lds, *wl = lds + HP * 2;
     constexpr int S = FLIP ? -1 : 1;
     constexpr int NCO = 16 * NT;  // weight rows per tap in LDS
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -423,50 +430,50 @@ conv3d_tiled_kernel(
     int baseA3 = hb2 + 2 * S * second * D3 - 2 * step_bias(D3, S);
     int baseA0 = hb2 - 2 * step_bias(0, S);
     int baseB = 2 * (second * NCO + r) + half;
-    // this thread's halo pieces c = threadIdx.x + 256 k: point (packed) or -1
-    int hp[6];
+    // this thread's halo pieces c = threadIdx.x + NTH k: point (packed) or -1
+    int hp[NPF];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const int c = threadIdx.x + 256 * k, h = c >> 1;
-        hp[k] = c < kHP * 2 ? (h % kHX) | (((h / kHX) % kHY) << 8) | ((h / (kHX * kHY)) << 16) : -1;
+    for (int k = 0; k < NPF; ++k) {
+        const int c = threadIdx.x + NTH * k, h = c >> 1;
+        hp[k] = c < HP * 2 ? (h % kHX) | (((h / kHX) % kHY) << 8) | ((h / (kHX * kHY)) << 16) : -1;
     }
     const int part = threadIdx.x & 1;
     const int nmine = ntile > (int)blockIdx.x ? (ntile - 1 - (int)blockIdx.x) / (int)gridDim.x + 1 : 0;
-    uint4 pf[6];
+    uint4 pf[NPF];
     auto load_halo = [&](int k, int chunk) {
         int ox, oy, oz;
-        tile_origin<POW2>(G, (int)blockIdx.x + k * (int)gridDim.x, ox, oy, oz);
+        tile_origin<POW2, TZ>(G, (int)blockIdx.x + k * (int)gridDim.x, ox, oy, oz);
         if constexpr (CAT) {
             if (chunk * 16 < cc) {
 #pragma unroll
-                for (int j = 0; j < 6; ++j)
+                for (int j = 0; j < NPF; ++j)
                     pf[j] = halo_piece_up<POW2>(xc, cc, G, ox, oy, oz, chunk * 16, hp[j], part);
             } else {
 #pragma unroll
-                for (int j = 0; j < 6; ++j)
+                for (int j = 0; j < NPF; ++j)
                     pf[j] = halo_piece<POW2>(x, cin - cc, G, ox, oy, oz, chunk * 16 - cc, hp[j], part);
             }
         } else {
 #pragma unroll
-            for (int j = 0; j < 6; ++j) pf[j] = halo_piece<POW2>(x, cin, G, ox, oy, oz, chunk * 16, hp[j], part);
+            for (int j = 0; j < NPF; ++j) pf[j] = halo_piece<POW2>(x, cin, G, ox, oy, oz, chunk * 16, hp[j], part);
         }
     };
     // weight rows (t, o) of input chunk cc: w[t][cob + o][cc .. cc + 15]
     const int ls = ntiles == 2 ? 5 : 4;
     auto stage_weights = [&](int cc) {
-        for (int c = threadIdx.x; c < 27 * nco * 2; c += 256) {
+        for (int c = threadIdx.x; c < 27 * nco * 2; c += NTH) {
             const int row = c >> 1, t = row >> ls, o = row & (nco - 1);
             wl[2 * (t * NCO + o) + (c & 1)] = *(const uint4 *)(w + (t * cout + cob + o) * cin + cc + 8 * (c & 1));
         }
     };
-    constexpr int NPW = WPF ? (27 * NCO * 2 + 255) / 256 : 1;
+    constexpr int NPW = WPF ? (27 * NCO * 2 + NTH - 1) / NTH : 1;
     u4v pw[NPW];
     auto load_weights = [&](int cc) __attribute__((always_inline)) {
         unroll<0, NPW>([&](auto J) {
             constexpr int j = decltype(J)::value;
             // a thread past the last piece loads the last piece again (an
             // unconditional load keeps pw in registers); it is not stored
-            const int c = min((int)threadIdx.x + 256 * j, 27 * nco * 2 - 1);
+            const int c = min((int)threadIdx.x + NTH * j, 27 * nco * 2 - 1);
             const int row = c >> 1, t = row >> ls, o = row & (nco - 1);
             pw[j] = *(const u4v *)(w + (t * cout + cob + o) * cin + cc + 8 * (c & 1));
         });
@@ -474,7 +481,7 @@ conv3d_tiled_kernel(
     auto store_weights = [&]() __attribute__((always_inline)) {
         unroll<0, NPW>([&](auto J) {
             constexpr int j = decltype(J)::value;
-            const int c = threadIdx.x + 256 * j;
+            const int c = threadIdx.x + NTH * j;
             if (c < 27 * nco * 2) {
                 const int row = c >> 1, t = row >> ls, o = row & (nco - 1);
                 *(u4v *)&wl[2 * (t * NCO + o) + (c & 1)] = pw[j];
@@ -491,8 +498,8 @@ conv3d_tiled_kernel(
         for (int chunk = 0; chunk < nchunk; ++chunk) {
             __syncthreads();  // the previous item's reads are done
 #pragma unroll
-            for (int j = 0; j < 5; ++j) tile[threadIdx.x + 256 * j] = pf[j];
-            if (threadIdx.x + 1280 < kHP * 2) tile[threadIdx.x + 1280] = pf[5];
+            for (int j = 0; j < NPF; ++j)
+                if (NTH * (j + 1) <= HP * 2 || threadIdx.x + NTH * j < HP * 2) tile[threadIdx.x + NTH * j] = pf[j];
             if (nchunk > 1) {
                 if constexpr (WPF) store_weights();
                 else stage_weights(chunk * 16);
@@ -527,7 +534,7 @@ conv3d_tiled_kernel(
         // epilogue: lane (px, q) holds output channels 4q .. 4q + 3 of point
         // x0 + px of row mt of its plane, in register j of acc[mt][nt]
         int x0, y0, z0;
-        tile_origin<POW2>(G, (int)blockIdx.x + k * (int)gridDim.x, x0, y0, z0);
+        tile_origin<POW2, TZ>(G, (int)blockIdx.x + k * (int)gridDim.x, x0, y0, z0);
         float rv[POOL ? NT : 1][4][4];  // the stored BF16 values, for the pooling
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
@@ -646,7 +653,9 @@ conv3d_tiled_kernel(
 }
 
 // LDS bytes of conv3d_tiled_kernel with NT output tiles per block.
-size_t conv_tiled_lds(int nt) { return (size_t)(kHP * 2 + 27 * 16 * nt * 2) * sizeof(uint4); }
+size_t conv_tiled_lds(int nt, int wv = 4) {
+    return (size_t)(kHX * kHY * (wv + 2) * 2 + 27 * 16 * nt * 2) * sizeof(uint4);
+}
 
 // Weight gradient of one tap over one chunk of points:
 // dW[t][o][i] = sum_p dY[p][o] X[p + d_t][i], an M = cout, N = cin, K = points
@@ -1751,11 +1760,14 @@ int ilog2(int n) {
 // of four resident blocks, so a block's next item overlaps another's
 // epilogue), otherwise as many as are resident at once (three per CU, LDS
 // bound), which keeps the last round of a grid from running a third full.
+// Blocks of eight wavefronts: two per CU, as many as are resident at once
+// (register bound); a second round measured slower at every chunk count.
 // SUR_CONV_BLOCKS overrides it (tuning only; results do not depend on it).
-int conv_blocks(int nt, int nchunk, int cus) {
+int conv_blocks(int nt, int nchunk, int cus, int wv) {
     const char *v = std::getenv("SUR_CONV_BLOCKS");
     if (v && *v) return std::max(1, std::atoi(v));
     if (cus <= 0) return 2048;
+    if (wv == 8) return 2 * cus;
     return (nt == 1 && nchunk == 1 ? 8 : 3) * cus;
 }
 
@@ -1833,13 +1845,19 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
     const long P = (long)nx * ny * nz;
     // one N tile per block for 16 output channels (fewer registers), two otherwise
     const int nt = cout <= 16 ? 1 : kNT, nb = 16 * nt;
-    const long tiles = P / (kTX * kTY * kTZ);
     const long ncb = (cout + nb - 1) / nb;
     const int cus = device_cus();
-    const long nblk = std::max(1L, std::min(tiles, (long)conv_blocks(nt, cin / 16, cus) / ncb));
+    // eight wavefronts per block on 16 x 4 x 8 tiles: one output tile, no
+    // pooling, at least four such tiles per CU (SUR_CONV_WV=4 keeps four
+    // wavefronts; for comparisons only, both give the same bits)
+    const char *wvv = std::getenv("SUR_CONV_WV");
+    const int nwv = (nt == 1 && !y_pool && nz % 8 == 0 && cus > 0 &&
+                    P / (kTX * kTY * 8) >= 4L * cus && !(wvv && *wvv == '4')) ? 8 : 4;
+    const long tiles = P / (kTX * kTY * nwv);
+    const long nblk = std::max(1L, std::min(tiles, (long)conv_blocks(nt, cin / 16, cus, nwv) / ncb));
     const dim3 grid((unsigned)nblk, (unsigned)ncb);
-    const size_t lds = conv_tiled_lds(nt);
-    ConvGeom G{nx, ny, nz, nx / kTX, ny / kTY, nz / kTZ, 0, 0, 0, 0};
+    const size_t lds = conv_tiled_lds(nt, nwv);
+    ConvGeom G{nx, ny, nz, nx / kTX, ny / kTY, nz / nwv, 0, 0, 0, 0};
     const bool pow2 = pow2_ok(nx) && pow2_ok(ny) && pow2_ok(nz);
     if (pow2) {
         G.lx = ilog2(nx);
@@ -1868,7 +1886,18 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
         if (wpf) SUR_CONV_POW2(kNT, FL, CT, true, PL);                   \
         else SUR_CONV_POW2(kNT, FL, CT, false, PL);                      \
     } while (0)
-    if (xc) {
+#define SUR_CONV_WV8(FL, P2, CT)                                                                  \
+    hipLaunchKernelGGL((conv3d_tiled_kernel<1, FL, P2, CT, false, false, 8>), grid, dim3(512), lds, st, \
+                       xb, cin, xcb, cc, wb, bias, cout, G, relu, mb, yb, y_f32, yp)
+    if (nwv == 8) {
+        if (xc) {
+            if (pow2) SUR_CONV_WV8(false, true, true); else SUR_CONV_WV8(false, false, true);
+        } else if (flip) {
+            if (pow2) SUR_CONV_WV8(true, true, false); else SUR_CONV_WV8(true, false, false);
+        } else {
+            if (pow2) SUR_CONV_WV8(false, true, false); else SUR_CONV_WV8(false, false, false);
+        }
+    } else if (xc) {
         if (nt == 1) SUR_CONV_POW2(1, false, true, false, false);
         else SUR_CONV_NT2(false, true, false);
     } else if (y_pool && nt == kNT) {
@@ -1880,6 +1909,7 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
         if (flip) SUR_CONV_NT2(true, false, false);
         else SUR_CONV_NT2(false, false, false);
     }
+#undef SUR_CONV_WV8
 #undef SUR_CONV_NT2
 #undef SUR_CONV_POW2
 #undef SUR_CONV_LAUNCH

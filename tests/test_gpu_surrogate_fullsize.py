@@ -52,7 +52,7 @@ def _sampled_conv(x, w, b, pts, flip):
 
 
 @pytest.mark.parametrize("n,cin,cout,flip", [(128, 16, 16, 0), (128, 48, 16, 0), (128, 16, 48, 1),
-                                             (64, 80, 32, 0), (64, 32, 32, 1)])
+                                             (128, 48, 16, 1), (64, 80, 32, 0), (64, 32, 32, 1)])
 def test_conv_full_size_sampled(sur, n, cin, cout, flip):
     import torch
     say(f"[sur-full] conv {n}^3 {cin}->{cout} flip={flip}: 4096 sampled points")
@@ -180,3 +180,51 @@ def test_conv_with_pooling_full_size_sampled(sur, n, cin, cout):
     pbits = yp.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
     pv = pbits.view(np.float32).reshape(n // 2, n // 2, n // 2, cout)
     assert np.array_equal(pv[cells[:, 0], cells[:, 1], cells[:, 2]], want)
+
+
+@pytest.mark.parametrize("grid,cin,flip", [((96, 96, 64), 32, 0), ((80, 96, 128), 16, 1),
+                                           ((128, 64, 128), 48, 0)])
+def test_conv_eight_wavefront_tiles_sampled(sur, grid, cin, flip):
+    """Single-output-tile layers on large grids run eight wavefronts per
+    block on 16 x 4 x 8 point tiles (powers of two or not): 4096 sampled
+    points against the definition, and every output bit equal to the same
+    layer on four-wavefront 16 x 4 x 4 tiles (SUR_CONV_WV=4)."""
+    import os
+    import torch
+    nx, ny, nz = grid
+    cout, P = 16, nx * ny * nz
+    say(f"[sur-full] conv on 16x4x8 tiles {grid} {cin}->{cout} flip={flip}: 4096 points")
+    rng = np.random.default_rng(nx + 3 * ny + 5 * nz + cin + flip)
+    x = so.bf16_round(rng.standard_normal((nz, ny, nx, cin)).astype(np.float32))
+    w = so.bf16_round((rng.standard_normal((27, cout, cin)) * 0.1).astype(np.float32))
+    b = rng.standard_normal(cout).astype(np.float32)
+    mask = so.bf16_round(np.maximum(rng.standard_normal((nz, ny, nx, cout)), 0).astype(np.float32))
+    wf = torch.empty((27, cout, cin), dtype=torch.int16, device="cuda")
+    sur.sur_pack_weights(_f32(w), cin, cout, wf, None)
+    xb, mb = _bits(x.reshape(-1, cin)), _bits(mask.reshape(-1, cout))
+    outs = []
+    old = os.environ.get("SUR_CONV_WV")
+    try:
+        for wv in (None, "4"):
+            if wv is None:
+                os.environ.pop("SUR_CONV_WV", None)
+            else:
+                os.environ["SUR_CONV_WV"] = wv
+            y = torch.empty((P, cout), dtype=torch.float32, device="cuda")
+            yb = torch.empty((P, cout), dtype=torch.int16, device="cuda")
+            sur.sur_conv3d(xb, cin, wf, None if flip else _f32(b), cout, grid, flip=flip,
+                           relu=0 if flip else 1, mask=mb if flip else None, y_bf16=yb, y_f32=y)
+            outs.append((y.cpu().numpy(), yb.cpu().numpy()))
+    finally:
+        if old is None:
+            os.environ.pop("SUR_CONV_WV", None)
+        else:
+            os.environ["SUR_CONV_WV"] = old
+    pts = np.stack([rng.integers(0, nz, 4096), rng.integers(0, ny, 4096), rng.integers(0, nx, 4096)], 1)
+    ref = _sampled_conv(x, w.astype(np.float64), None if flip else b.astype(np.float64), pts, flip)
+    ref = ref * (mask[pts[:, 0], pts[:, 1], pts[:, 2]] > 0) if flip else np.maximum(ref, 0.0)
+    got = outs[0][0].reshape(nz, ny, nx, cout)[pts[:, 0], pts[:, 1], pts[:, 2]]
+    e = np.abs(got - ref).max()
+    say(f"   max|dy| {e:.2e} (scale {np.abs(ref).max():.2f})")
+    assert e <= 1e-5 * (1 + np.abs(ref).max())
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
