@@ -63,9 +63,11 @@ int sur_conv3d_cat(const void *xc, int32_t cc, const void *xf, int32_t fc, const
  * (flip = 0, no mask) into BF16 y_bf16 [P][cout], and y_pool
  * [P/8][cout] = sur_pool2 of y_bf16 (the mean of each 2 x 2 x 2 cell of
  * the stored BF16 values, summed in FP32 in x, y, z order, rounded to BF16),
- * bitwise, in one pass (two for cout = 16). Needs the tiled kernel (nx a multiple of 16, ny and
- * nz of 4, 16-byte aligned x and w) and 8-byte aligned outputs; otherwise
- * SUR_EINVAL (call sur_conv3d, then sur_pool2). */
+ * bitwise, in one pass (for cout = 16 only where nz is a multiple of 8 and
+ * the grid holds at least four 16 x 4 x 8 point tiles per compute unit;
+ * two passes otherwise). Needs the tiled kernel (nx a multiple of 16, ny
+ * and nz of 4, 16-byte aligned x and w) and 8-byte aligned outputs;
+ * otherwise SUR_EINVAL (call sur_conv3d, then sur_pool2). */
 int sur_conv3d_pool(const void *x, int32_t cin, const void *w, const float *bias, int32_t cout,
                     int32_t nx, int32_t ny, int32_t nz, int32_t relu, void *y_bf16, void *y_pool,
                     void *stream);

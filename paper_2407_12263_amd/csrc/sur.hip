@@ -227,6 +227,7 @@ struct ConvGeom {
     int ntx, nty, ntz;
     int lx, lxy;    // log2 nx, log2 (nx ny)
     int ltx, ltxy;  // log2 ntx, log2 (ntx nty)
+    int wres;       // every input chunk's weights staged in LDS once per kernel
 };
 
 // Origin of tile tl (x fastest over tiles) of TZ planes in z.
@@ -391,6 +392,8 @@ constexpr int conv_min_waves() { return NT == 1 ? 4 : (WPF ? 2 : 1); }
 // by 1/8 and rounded, as the pooling pass over the stored tensor does. The
 // x pair is in the neighbouring lane, the y pair in the lane's next row and
 // the z pair in the next wavefront, which hands its values over in LDS.
+// With one output tile (no registers to spare) every stored value goes
+// through LDS instead, and each thread sums one cell's channel pair.
 // WV = 8 (one output tile, large grids): blocks of eight wavefronts on
 // 16 x 4 x 8 point tiles, each wavefront as above on one plane; the halo
 // (18 x 6 x 10, 34.6 KB) is re-read 2.1 times instead of 2.5, and a block's
@@ -403,13 +406,17 @@ conv3d_tiled_kernel(
     const float *__restrict__ bias, int cout, ConvGeom G, int relu,
     const uint16_t *__restrict__ mask, uint16_t *__restrict__ yb, float *__restrict__ yf,
     uint16_t *__restrict__ yp) {
-    static_assert(WV == 4 || (WV == 8 && NT == 1 && !POOL), "eight wavefronts: one output tile, no pooling");
+    static_assert(WV == 4 || (WV == 8 && NT == 1), "eight wavefronts: one output tile");
     constexpr int NTH = 64 * WV, TZ = WV, HP = kHX * kHY * (TZ + 2);
     constexpr int NPF = (2 * HP + NTH - 1) / NTH;  // halo pieces per thread
-    // LDS: the input halo (HP points x 16 channels) and the chunk's weights
-    // (27 taps x 16 NT output channels x 16 channels), 32 B per row
+    constexpr bool POOL1 = POOL && NT == 1;          // pooling through LDS
+    constexpr int PXQ = POOL1 ? 16 * 4 * TZ * 2 : 0;  // its uint4: 32 B per point
+    // LDS: the input halo (HP points x 16 channels), the pooling's values
+    // and the chunk's weights (27 taps x 16 NT output channels x 16
+    // channels), 32 B per row
     extern __shared__ uint4 lds[];
-    uint4 *tile = lds, *wl = lds + HP * 2;
+    uint4 *tile = lds, *wl = lds + HP * 2 + PXQ;
+    uint2 *pxl = (uint2 *)(lds + HP * 2);  // point (x, y, z) at x + 16 (y + 4 z)
     constexpr int S = FLIP ? -1 : 1;
     constexpr int NCO = 16 * NT;  // weight rows per tap in LDS
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -460,12 +467,16 @@ conv3d_tiled_kernel(
     };
     // weight rows (t, o) of input chunk cc: w[t][cob + o][cc .. cc + 15]
     const int ls = ntiles == 2 ? 5 : 4;
-    auto stage_weights = [&](int cc) {
+    auto stage_weights = [&](int cc, int off) {
         for (int c = threadIdx.x; c < 27 * nco * 2; c += NTH) {
             const int row = c >> 1, t = row >> ls, o = row & (nco - 1);
-            wl[2 * (t * NCO + o) + (c & 1)] = *(const uint4 *)(w + (t * cout + cob + o) * cin + cc + 8 * (c & 1));
+            wl[off + 2 * (t * NCO + o) + (c & 1)] =
+                *(const uint4 *)(w + (t * cout + cob + o) * cin + cc + 8 * (c & 1));
         }
     };
+    // weights of every chunk resident (chunk c at c 27 NCO 2): staged once
+    const bool wres = nchunk > 1 && G.wres;
+    constexpr int WCH = 27 * NCO * 2;  // uint4 per chunk's weights
     constexpr int NPW = WPF ? (27 * NCO * 2 + NTH - 1) / NTH : 1;
     u4v pw[NPW];
     auto load_weights = [&](int cc) __attribute__((always_inline)) {
@@ -492,7 +503,8 @@ conv3d_tiled_kernel(
         load_halo(0, 0);
         if (WPF && nchunk > 1) load_weights(0);
     }
-    if (nchunk == 1) stage_weights(0);  // the same for every item
+    if (nchunk == 1 || wres)  // the same for every item
+        for (int c = 0; c < nchunk; ++c) stage_weights(c * 16, c * WCH);
     f4 acc[4][NT];
     for (int k = 0; k < nmine; ++k) {
         for (int chunk = 0; chunk < nchunk; ++chunk) {
@@ -500,9 +512,9 @@ conv3d_tiled_kernel(
 #pragma unroll
             for (int j = 0; j < NPF; ++j)
                 if (NTH * (j + 1) <= HP * 2 || threadIdx.x + NTH * j < HP * 2) tile[threadIdx.x + NTH * j] = pf[j];
-            if (nchunk > 1) {
+            if (nchunk > 1 && !wres) {
                 if constexpr (WPF) store_weights();
-                else stage_weights(chunk * 16);
+                else stage_weights(chunk * 16, 0);
             }
             __syncthreads();
             if (chunk + 1 < nchunk) {
@@ -524,18 +536,19 @@ conv3d_tiled_kernel(
             // offset) pair across the item loop
             if constexpr (WPF)
                 asm volatile("" : "+v"(baseA0), "+v"(baseA1), "+v"(baseA2), "+v"(baseA3), "+v"(baseB));
+            const int bB = wres ? baseB + chunk * WCH : baseB;
             if (NT == 1 || ntiles == NT)
-                conv_kloop<NT, NT, FLIP, NT == 1>(tile, wl, baseA0, baseA1, baseA2, baseA3, baseB,
+                conv_kloop<NT, NT, FLIP, NT == 1>(tile, wl, baseA0, baseA1, baseA2, baseA3, bB,
                                                  second, acc);
             else
-                conv_kloop<1, NT, FLIP, false>(tile, wl, baseA0, baseA1, baseA2, baseA3, baseB,
+                conv_kloop<1, NT, FLIP, false>(tile, wl, baseA0, baseA1, baseA2, baseA3, bB,
                                               second, acc);
         }
         // epilogue: lane (px, q) holds output channels 4q .. 4q + 3 of point
         // x0 + px of row mt of its plane, in register j of acc[mt][nt]
         int x0, y0, z0;
         tile_origin<POW2, TZ>(G, (int)blockIdx.x + k * (int)gridDim.x, x0, y0, z0);
-        float rv[POOL ? NT : 1][4][4];  // the stored BF16 values, for the pooling
+        float rv[POOL && !POOL1 ? NT : 1][4][4];  // the stored BF16 values, for the pooling
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             if (nt >= ntiles) break;
@@ -567,7 +580,9 @@ conv3d_tiled_kernel(
                     const uint32_t lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(fl2{v[0], v[1]}, bf2));
                     const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(fl2{v[2], v[3]}, bf2));
                     *(uint2 *)(yb + o) = uint2{lo, hi};
-                    if constexpr (POOL) {
+                    if constexpr (POOL1) {
+                        pxl[((wave * 4 + mt) * 16 + r) * 4 + q] = uint2{lo, hi};
+                    } else if constexpr (POOL) {
                         rv[nt][mt][0] = __uint_as_float(lo << 16);
                         rv[nt][mt][1] = __uint_as_float(lo & 0xffff0000u);
                         rv[nt][mt][2] = __uint_as_float(hi << 16);
@@ -577,7 +592,25 @@ conv3d_tiled_kernel(
                 if (yf) *(f4 *)(yf + o) = f4{v[0], v[1], v[2], v[3]};
             }
         }
-        if constexpr (POOL) {
+        if constexpr (POOL1) {
+            // thread: cell (cx, cy, cz) of the tile's 8 x 2 x (TZ / 2), channels
+            // 2 sub, 2 sub + 1; the eight values in the pooling pass's order
+            __syncthreads();
+            const int cl = threadIdx.x >> 3, sub = threadIdx.x & 7;
+            const int cx = cl & 7, cy = (cl >> 3) & 1, cz = cl >> 4;
+            const uint32_t *pw32 = (const uint32_t *)pxl;
+            float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int pt = (2 * cx + (k & 1)) + 16 * ((2 * cy + ((k >> 1) & 1)) + 4 * (2 * cz + (k >> 2)));
+                const uint32_t v2 = pw32[pt * 8 + sub];
+                s0 += __uint_as_float(v2 << 16);
+                s1 += __uint_as_float(v2 & 0xffff0000u);
+            }
+            const int X = (x0 >> 1) + cx, Y = (y0 >> 1) + cy, Z = (z0 >> 1) + cz;
+            const uint32_t qo = (uint32_t)(X + (G.nx >> 1) * (Y + (G.ny >> 1) * Z)) * (uint32_t)cout + cob + 2 * sub;
+            *(uint32_t *)(yp + qo) = (uint32_t)f2bf(0.125f * s0) | ((uint32_t)f2bf(0.125f * s1) << 16);
+        } else if constexpr (POOL) {
             // cell (x0 + r, y0 + 2 pr, z0 + w) .. + 1 of the even lanes r and
             // wavefronts w; value i = dx + 2 dy of plane dz = w & 1, channel j
             float *ex = (float *)tile;  // free once every wavefront is here
@@ -652,9 +685,12 @@ conv3d_tiled_kernel(
     }
 }
 
-// LDS bytes of conv3d_tiled_kernel with NT output tiles per block.
-size_t conv_tiled_lds(int nt, int wv = 4) {
-    return (size_t)(kHX * kHY * (wv + 2) * 2 + 27 * 16 * nt * 2) * sizeof(uint4);
+// LDS bytes of conv3d_tiled_kernel with NT output tiles per block, wv
+// wavefronts, the weights of nw input chunks resident and (pool1) the
+// pooling of one output tile.
+size_t conv_tiled_lds(int nt, int wv = 4, int nw = 1, bool pool1 = false) {
+    return (size_t)(kHX * kHY * (wv + 2) * 2 + (pool1 ? 16 * 4 * wv * 2 : 0) + 27 * 16 * nt * 2 * nw) *
+           sizeof(uint4);
 }
 
 // Weight gradient of one tap over one chunk of points:
@@ -1836,9 +1872,20 @@ int device_cus() {
     return cus;
 }
 
+// Wavefronts per block of conv3d_tiled_kernel: eight on 16 x 4 x 8 tiles
+// for one output tile and at least four such tiles per CU, else four
+// (SUR_CONV_WV=4 keeps four; for comparisons only, both give the same bits).
+int conv_waves(int cout, int nx, int ny, int nz, int cus) {
+    const char *v = std::getenv("SUR_CONV_WV");
+    const long P = (long)nx * ny * nz;
+    return (cout <= 16 && nz % 8 == 0 && cus > 0 && P / (kTX * kTY * 8) >= 4L * cus &&
+            !(v && *v == '4')) ? 8 : 4;
+}
+
 // Launches conv3d_tiled_kernel; xc != NULL selects the concat form (cc
 // channels of the upsampled coarse tensor first, then cin - cc of x);
-// y_pool != NULL the pooled output as well (forward form, BF16 output).
+// y_pool != NULL the pooled output as well (forward form, BF16 output; one
+// output tile only with eight wavefronts).
 void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const void *w,
                        const float *bias, int cout, int nx, int ny, int nz, bool flip, int relu,
                        const void *mask, void *y_bf16, float *y_f32, void *y_pool, hipStream_t st) {
@@ -1847,17 +1894,21 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
     const int nt = cout <= 16 ? 1 : kNT, nb = 16 * nt;
     const long ncb = (cout + nb - 1) / nb;
     const int cus = device_cus();
-    // eight wavefronts per block on 16 x 4 x 8 tiles: one output tile, no
-    // pooling, at least four such tiles per CU (SUR_CONV_WV=4 keeps four
-    // wavefronts; for comparisons only, both give the same bits)
-    const char *wvv = std::getenv("SUR_CONV_WV");
-    const int nwv = (nt == 1 && !y_pool && nz % 8 == 0 && cus > 0 &&
-                    P / (kTX * kTY * 8) >= 4L * cus && !(wvv && *wvv == '4')) ? 8 : 4;
+    const int nwv = conv_waves(cout, nx, ny, nz, cus);
     const long tiles = P / (kTX * kTY * nwv);
     const long nblk = std::max(1L, std::min(tiles, (long)conv_blocks(nt, cin / 16, cus, nwv) / ncb));
     const dim3 grid((unsigned)nblk, (unsigned)ncb);
-    const size_t lds = conv_tiled_lds(nt, nwv);
-    ConvGeom G{nx, ny, nz, nx / kTX, ny / kTY, nz / nwv, 0, 0, 0, 0};
+    // eight-wavefront blocks with a few input chunks keep every chunk's
+    // weights in LDS (at most 80 KB a block keeps two blocks per CU), so no
+    // item stages them again (SUR_CONV_WRES=0 turns it off; for comparisons
+    // only, both give the same bits)
+    const char *wrv = std::getenv("SUR_CONV_WRES");
+    const int nchunk = cin / 16;
+    const bool pool1 = y_pool && nt == 1;
+    const bool wres = nwv == 8 && nchunk > 1 && conv_tiled_lds(nt, nwv, nchunk, pool1) <= 80 * 1024 &&
+                      !(wrv && *wrv == '0');
+    const size_t lds = conv_tiled_lds(nt, nwv, wres ? nchunk : 1, pool1);
+    ConvGeom G{nx, ny, nz, nx / kTX, ny / kTY, nz / nwv, 0, 0, 0, 0, wres ? 1 : 0};
     const bool pow2 = pow2_ok(nx) && pow2_ok(ny) && pow2_ok(nz);
     if (pow2) {
         G.lx = ilog2(nx);
@@ -1886,16 +1937,18 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
         if (wpf) SUR_CONV_POW2(kNT, FL, CT, true, PL);                   \
         else SUR_CONV_POW2(kNT, FL, CT, false, PL);                      \
     } while (0)
-#define SUR_CONV_WV8(FL, P2, CT)                                                                  \
-    hipLaunchKernelGGL((conv3d_tiled_kernel<1, FL, P2, CT, false, false, 8>), grid, dim3(512), lds, st, \
+#define SUR_CONV_WV8(FL, P2, CT, PL)                                                           \
+    hipLaunchKernelGGL((conv3d_tiled_kernel<1, FL, P2, CT, false, PL, 8>), grid, dim3(512), lds, st, \
                        xb, cin, xcb, cc, wb, bias, cout, G, relu, mb, yb, y_f32, yp)
     if (nwv == 8) {
-        if (xc) {
-            if (pow2) SUR_CONV_WV8(false, true, true); else SUR_CONV_WV8(false, false, true);
+        if (pool1) {
+            if (pow2) SUR_CONV_WV8(false, true, false, true); else SUR_CONV_WV8(false, false, false, true);
+        } else if (xc) {
+            if (pow2) SUR_CONV_WV8(false, true, true, false); else SUR_CONV_WV8(false, false, true, false);
         } else if (flip) {
-            if (pow2) SUR_CONV_WV8(true, true, false); else SUR_CONV_WV8(true, false, false);
+            if (pow2) SUR_CONV_WV8(true, true, false, false); else SUR_CONV_WV8(true, false, false, false);
         } else {
-            if (pow2) SUR_CONV_WV8(false, true, false); else SUR_CONV_WV8(false, false, false);
+            if (pow2) SUR_CONV_WV8(false, true, false, false); else SUR_CONV_WV8(false, false, false, false);
         }
     } else if (xc) {
         if (nt == 1) SUR_CONV_POW2(1, false, true, false, false);
@@ -1960,9 +2013,9 @@ int sur_conv3d_pool(const void *x, int32_t cin, const void *w, const float *bias
         !dims_ok(nx, ny, nz) || !conv_tiled_ok(x, cin, w, cout, nx, ny, nz) ||
         ((uintptr_t)y_bf16 & 7) != 0 || ((uintptr_t)y_pool & 7) != 0)
         return SUR_EINVAL;
-    if (cout <= 16) {
-        // one output tile: its epilogue has no registers to spare for the
-        // pooling (it would run slower than the two passes), so pool after
+    if (cout <= 16 && conv_waves(cout, nx, ny, nz, device_cus()) == 4) {
+        // one output tile on four wavefronts: pooling in the epilogue would
+        // take LDS that a fourth block per CU needs, so pool after
         conv_tiled_launch(x, cin, nullptr, 0, w, bias, cout, nx, ny, nz, false, relu, nullptr,
                           y_bf16, nullptr, nullptr, (hipStream_t)stream);
         if (launched() != SUR_OK) return SUR_EDEVICE;

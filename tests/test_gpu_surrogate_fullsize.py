@@ -145,10 +145,11 @@ def test_conv_reading_the_concat_in_place_full_size_sampled(sur):
     assert e <= 1e-5 * (1 + np.abs(ref).max())
 
 
-@pytest.mark.parametrize("n,cin,cout", [(64, 32, 32), (32, 48, 48)])
+@pytest.mark.parametrize("n,cin,cout", [(128, 16, 16), (64, 32, 32), (32, 48, 48)])
 def test_conv_with_pooling_full_size_sampled(sur, n, cin, cout):
     """The encoders' second convolutions with their pooling in one pass (the
-    64^3 and 32^3 levels): the BF16 output on 4096 sampled points against
+    128^3 level on eight-wavefront blocks, pooled through LDS; the 64^3 and
+    32^3 levels with two output tiles): the BF16 output on 4096 sampled points against
     the definition, and the pooled output on 4096 sampled cells equal to the
     mean of the cell's eight stored BF16 values (summed x, y, z in FP32)."""
     import torch
