@@ -406,7 +406,7 @@ conv3d_tiled_kernel(
     const float *__restrict__ bias, int cout, ConvGeom G, int relu,
     const uint16_t *__restrict__ mask, uint16_t *__restrict__ yb, float *__restrict__ yf,
     uint16_t *__restrict__ yp) {
-    static_assert(WV == 4 || (WV == 8 && NT == 1), "eight wavefronts: one output tile");
+    static_assert(WV == 4 || (WV == 8 && (NT == 1 || (!POOL && !WPF))), "eight wavefronts");
     constexpr int NTH = 64 * WV, TZ = WV, HP = kHX * kHY * (TZ + 2);
     constexpr int NPF = (2 * HP + NTH - 1) / NTH;  // halo pieces per thread
     constexpr bool POOL1 = POOL && NT == 1;          // pooling through LDS
@@ -1796,14 +1796,15 @@ int ilog2(int n) {
 // of four resident blocks, so a block's next item overlaps another's
 // epilogue), otherwise as many as are resident at once (three per CU, LDS
 // bound), which keeps the last round of a grid from running a third full.
-// Blocks of eight wavefronts: two per CU, as many as are resident at once
-// (register bound); a second round measured slower at every chunk count.
+// Blocks of eight wavefronts: as many as are resident at once (register
+// bound: two per CU with one output tile, one with two); a second round of
+// one-tile blocks measured slower at every chunk count.
 // SUR_CONV_BLOCKS overrides it (tuning only; results do not depend on it).
 int conv_blocks(int nt, int nchunk, int cus, int wv) {
     const char *v = std::getenv("SUR_CONV_BLOCKS");
     if (v && *v) return std::max(1, std::atoi(v));
     if (cus <= 0) return 2048;
-    if (wv == 8) return 2 * cus;
+    if (wv == 8) return (nt == 1 ? 2 : 1) * cus;
     return (nt == 1 && nchunk == 1 ? 8 : 3) * cus;
 }
 
@@ -1873,13 +1874,16 @@ int device_cus() {
 }
 
 // Wavefronts per block of conv3d_tiled_kernel: eight on 16 x 4 x 8 tiles
-// for one output tile and at least four such tiles per CU, else four
+// for one output tile and at least four such tiles per CU; for two output
+// tiles (one block per CU) where the tiles make whole rounds of the CUs
+// and at most four input chunks (whose weights then stay in LDS); else four
 // (SUR_CONV_WV=4 keeps four; for comparisons only, both give the same bits).
-int conv_waves(int cout, int nx, int ny, int nz, int cus) {
+int conv_waves(int cin, int cout, int nx, int ny, int nz, int cus, bool pool) {
     const char *v = std::getenv("SUR_CONV_WV");
-    const long P = (long)nx * ny * nz;
-    return (cout <= 16 && nz % 8 == 0 && cus > 0 && P / (kTX * kTY * 8) >= 4L * cus &&
-            !(v && *v == '4')) ? 8 : 4;
+    const long P = (long)nx * ny * nz, tiles = P / (kTX * kTY * 8);
+    if ((v && *v == '4') || nz % 8 || cus <= 0) return 4;
+    if (cout <= 16) return tiles >= 4L * cus ? 8 : 4;
+    return !pool && cin <= 64 && tiles >= cus && tiles % cus == 0 ? 8 : 4;
 }
 
 // Launches conv3d_tiled_kernel; xc != NULL selects the concat form (cc
@@ -1894,7 +1898,7 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
     const int nt = cout <= 16 ? 1 : kNT, nb = 16 * nt;
     const long ncb = (cout + nb - 1) / nb;
     const int cus = device_cus();
-    const int nwv = conv_waves(cout, nx, ny, nz, cus);
+    const int nwv = conv_waves(cin, cout, nx, ny, nz, cus, y_pool != nullptr);
     const long tiles = P / (kTX * kTY * nwv);
     const long nblk = std::max(1L, std::min(tiles, (long)conv_blocks(nt, cin / 16, cus, nwv) / ncb));
     const dim3 grid((unsigned)nblk, (unsigned)ncb);
@@ -1905,7 +1909,7 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
     const char *wrv = std::getenv("SUR_CONV_WRES");
     const int nchunk = cin / 16;
     const bool pool1 = y_pool && nt == 1;
-    const bool wres = nwv == 8 && nchunk > 1 && conv_tiled_lds(nt, nwv, nchunk, pool1) <= 80 * 1024 &&
+    const bool wres = nwv == 8 && nchunk > 1 && conv_tiled_lds(nt, nwv, nchunk, pool1) <= (nt == 1 ? 80 : 160) * 1024 &&
                       !(wrv && *wrv == '0');
     const size_t lds = conv_tiled_lds(nt, nwv, wres ? nchunk : 1, pool1);
     ConvGeom G{nx, ny, nz, nx / kTX, ny / kTY, nz / nwv, 0, 0, 0, 0, wres ? 1 : 0};
@@ -1940,7 +1944,18 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
 #define SUR_CONV_WV8(FL, P2, CT, PL)                                                           \
     hipLaunchKernelGGL((conv3d_tiled_kernel<1, FL, P2, CT, false, PL, 8>), grid, dim3(512), lds, st, \
                        xb, cin, xcb, cc, wb, bias, cout, G, relu, mb, yb, y_f32, yp)
-    if (nwv == 8) {
+#define SUR_CONV_WV8N2(FL, P2, CT)                                                             \
+    hipLaunchKernelGGL((conv3d_tiled_kernel<kNT, FL, P2, CT, false, false, 8>), grid, dim3(512), lds, st, \
+                       xb, cin, xcb, cc, wb, bias, cout, G, relu, mb, yb, y_f32, yp)
+    if (nwv == 8 && nt == kNT) {
+        if (xc) {
+            if (pow2) SUR_CONV_WV8N2(false, true, true); else SUR_CONV_WV8N2(false, false, true);
+        } else if (flip) {
+            if (pow2) SUR_CONV_WV8N2(true, true, false); else SUR_CONV_WV8N2(true, false, false);
+        } else {
+            if (pow2) SUR_CONV_WV8N2(false, true, false); else SUR_CONV_WV8N2(false, false, false);
+        }
+    } else if (nwv == 8) {
         if (pool1) {
             if (pow2) SUR_CONV_WV8(false, true, false, true); else SUR_CONV_WV8(false, false, false, true);
         } else if (xc) {
@@ -1963,6 +1978,7 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
         else SUR_CONV_NT2(false, false, false);
     }
 #undef SUR_CONV_WV8
+#undef SUR_CONV_WV8N2
 #undef SUR_CONV_NT2
 #undef SUR_CONV_POW2
 #undef SUR_CONV_LAUNCH
@@ -2013,7 +2029,7 @@ int sur_conv3d_pool(const void *x, int32_t cin, const void *w, const float *bias
         !dims_ok(nx, ny, nz) || !conv_tiled_ok(x, cin, w, cout, nx, ny, nz) ||
         ((uintptr_t)y_bf16 & 7) != 0 || ((uintptr_t)y_pool & 7) != 0)
         return SUR_EINVAL;
-    if (cout <= 16 && conv_waves(cout, nx, ny, nz, device_cus()) == 4) {
+    if (cout <= 16 && conv_waves(cin, cout, nx, ny, nz, device_cus(), true) == 4) {
         // one output tile on four wavefronts: pooling in the epilogue would
         // take LDS that a fourth block per CU needs, so pool after
         conv_tiled_launch(x, cin, nullptr, 0, w, bias, cout, nx, ny, nz, false, relu, nullptr,

@@ -183,17 +183,20 @@ def test_conv_with_pooling_full_size_sampled(sur, n, cin, cout):
     assert np.array_equal(pv[cells[:, 0], cells[:, 1], cells[:, 2]], want)
 
 
-@pytest.mark.parametrize("grid,cin,flip", [((96, 96, 64), 32, 0), ((80, 96, 128), 16, 1),
-                                           ((128, 64, 128), 48, 0)])
-def test_conv_eight_wavefront_tiles_sampled(sur, grid, cin, flip):
-    """Single-output-tile layers on large grids run eight wavefronts per
-    block on 16 x 4 x 8 point tiles (powers of two or not): 4096 sampled
+@pytest.mark.parametrize("grid,cin,cout,flip", [((96, 96, 64), 32, 16, 0), ((80, 96, 128), 16, 16, 1),
+                                                ((128, 64, 128), 48, 16, 0), ((64, 64, 64), 32, 32, 0),
+                                                ((64, 64, 64), 64, 48, 1), ((128, 64, 64), 16, 32, 0)])
+def test_conv_eight_wavefront_tiles_sampled(sur, grid, cin, cout, flip):
+    """Layers on large grids run eight wavefronts per block on 16 x 4 x 8
+    point tiles (one output tile with at least four tiles per CU, powers of
+    two or not; two output tiles where the tiles make whole rounds of the
+    CUs, with up to four input chunks' weights resident): 4096 sampled
     points against the definition, and every output bit equal to the same
     layer on four-wavefront 16 x 4 x 4 tiles (SUR_CONV_WV=4)."""
     import os
     import torch
     nx, ny, nz = grid
-    cout, P = 16, nx * ny * nz
+    P = nx * ny * nz
     say(f"[sur-full] conv on 16x4x8 tiles {grid} {cin}->{cout} flip={flip}: 4096 points")
     rng = np.random.default_rng(nx + 3 * ny + 5 * nz + cin + flip)
     x = so.bf16_round(rng.standard_normal((nz, ny, nx, cin)).astype(np.float32))
