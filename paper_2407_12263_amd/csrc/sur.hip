@@ -189,11 +189,11 @@ __global__ void __launch_bounds__(256) conv3d_kernel(const uint16_t *__restrict_
 // z0 + w of the tile: four rows of 16 points, the four M tiles; a block
 // computes NT 16-channel N tiles (one for 16 output channels, run at four
 // wavefronts per SIMD; two otherwise). The K steps use the
-// 16x16x32 BF16 MFMA; one step covers two taps (lanes l / 16 = 0, 1: tap t,
-// 2, 3: tap t + 1) x 16 channels (8 per lane). A and B place the same (tap,
-// channel) in the same lane group and element, so the product does not
-// depend on how the hardware orders K within a step. The 14th step's second
-// tap does not exist and enters as zeros.
+// 16x16x32 BF16 MFMA; one step covers two taps (lanes l / 16 = 0, 1: the
+// step's first tap, 2, 3: its second) x 16 channels (8 per lane). A and B
+// place the same (tap, channel) in the same lane group and element, so the
+// product does not depend on how the hardware orders K within a step. The
+// 14th step's second tap does not exist and enters as zeros.
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 typedef float fl2 __attribute__((ext_vector_type(2)));
@@ -204,21 +204,39 @@ constexpr int kNT = 2;  // 16-channel output tiles per block at most (LDS <= 48.
 
 static_assert(kHP * 2 > 1280 && kHP * 2 <= 1536, "six 16-byte halo pieces per thread");
 
-// Halo offset of tap t (x fastest) and the offset step from tap t to t + 1
-// (0 for the last tap, which has no partner in its K step).
-__host__ __device__ constexpr int tap_off(int t) {
-    return (t % 3 - 1) + kHX * ((t / 3) % 3 - 1) + kHX * kHY * (t / 9 - 1);
+// The K steps' pairs of point offsets d = (dx, dy, dz): step s takes
+// slots 2s (lanes l / 16 = 0, 1) and 2s + 1 (lanes 2, 3):
+//   s = 3g + j, g = 0, 1, 2:  (g - 1, j - 1, -1) and (g - 1, j - 1, 0)
+//   s = 9 + j:                (-1, j - 1, 1)    and (0, j - 1, 1)
+//   s = 12:                   (1, -1, 1)        and (1, 0, 1)
+//   s = 13:                   (1, 1, 1)         and none (zeros)
+// In each of the first four groups of three steps the pair is the same but
+// for dy, so row mt of step j reads halo row mt + j: six fragment reads
+// serve the group's twelve products. The weight of slot sl is tap
+// slot_tap(sl) (t = (dx + 1) + 3 (dy + 1) + 9 (dz + 1)); the flipped
+// convolution, sum_t X[p - d_t] W[t], takes tap 26 - t for offset d_t.
+__host__ __device__ constexpr int slot_tap(int sl, bool flip) {
+    const int s = sl >> 1, h = sl & 1;
+    int dx = 1, dy = 1, dz = 1;
+    if (s < 9) {
+        dx = s / 3 - 1;
+        dy = s % 3 - 1;
+        dz = h - 1;
+    } else if (s < 12) {
+        dx = h - 1;
+        dy = s - 10;
+    } else if (s == 12) {
+        dy = h - 1;
+    }
+    const int t = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+    return flip ? 26 - t : t;
 }
-__host__ __device__ constexpr int pair_step(int t) { return t + 1 < 27 ? tap_off(t + 1) - tap_off(t) : 0; }
-// Over the K steps t = 0, 2, .., 26 whose pair step is d: the largest
-// -(s tap_off(t)), s = -1 for the flipped convolution. A lane base lowered
-// by it keeps every LDS offset of those steps a non-negative immediate.
-__host__ __device__ constexpr int step_bias(int d, int s) {
-    int k = -(1 << 20);
-    for (int t = 0; t < 27; t += 2)
-        if (pair_step(t) == d && -s * tap_off(t) > k) k = -s * tap_off(t);
-    return k;
+__host__ __device__ constexpr bool slots_cover_taps() {
+    int seen = 0;
+    for (int sl = 0; sl < 27; ++sl) seen |= 1 << slot_tap(sl, false);
+    return seen == (1 << 27) - 1;
 }
+static_assert(slots_cover_taps(), "the 27 slots hold every tap once");
 
 // Grid of the tiled convolution (host-computed): sizes, tile counts, and for
 // power-of-two sizes the shifts that replace divisions and the periodic wrap.
@@ -292,61 +310,77 @@ __device__ __forceinline__ uint4 halo_piece_up(const uint16_t *__restrict__ xc, 
 // The 14 K steps of one work item from LDS into the accumulators of the
 // first NTA of the block's NT output tiles (NTA is the number the block
 // actually has, so the loop carries no per-step test of it). baseA0..3: the
-// lane's A bases of the four step classes (pair step 0, 1, kHX - 2,
-// kHX kHY - 2 kHX - 2), baseB its weight base; every read adds an immediate.
-// With PIPE (blocks of one output tile) the loop is software-pipelined: the
-// fragments of step s + 1 are read before the MFMAs of step s are issued (the
-// scheduling barriers keep that order), so each wavefront has a whole step's
-// reads in flight while its MFMAs run. Two output tiles would need the
-// registers of a third wavefront per SIMD for it.
-template <int NTA, int NT, bool FLIP, bool PIPE>
+// lane's point bases of the four pair forms (second offset equal to the
+// first, one x, one y, one z further), baseB its weight base; every read
+// adds an immediate. Fragment buffers alternate between groups (F) and
+// steps (W). With PIPE (blocks of one output tile) the loop is
+// software-pipelined: the reads of step s + 1 are issued before the MFMAs of
+// step s (the scheduling barriers keep that order), so each wavefront has
+// the next step's reads in flight while its MFMAs run. Two output tiles
+// would need the registers of a third wavefront per SIMD for it.
+template <int NTA, int NT, bool PIPE>
 __device__ __forceinline__ void conv_kloop(const uint4 *tile, const uint4 *wl, int baseA0, int baseA1,
                                            int baseA2, int baseA3, int baseB, int second,
                                            f4 (&acc)[4][NT]) {
-    constexpr int S = FLIP ? -1 : 1;
     constexpr int NCO = 16 * NT;
-    constexpr int D1 = pair_step(0), D2 = pair_step(2), D3 = pair_step(8);
+    constexpr int PL = kHX * kHY;
     const uint4 z4 = uint4{0u, 0u, 0u, 0u};
-    bf8 a[2][4], b[2][NTA];
-    auto load = [&](auto T, int buf) {
-        constexpr int t = decltype(T)::value;
-        constexpr int d = pair_step(t);
-        const int base = d == D1 ? baseA1 : (d == D2 ? baseA2 : (d == D3 ? baseA3 : baseA0));
-        constexpr int imm = 2 * (S * tap_off(t) + step_bias(d, S));
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            uint4 v = tile[base + imm + 2 * kHX * mt];
-            if (t + 1 >= 27 && second) v = z4;
-            a[buf][mt] = __builtin_bit_cast(bf8, v);
+    bf8 F[2][6], W[2][NTA];
+    // fragment k of group g (0..3: three steps sharing halo rows, k the
+    // row; 4, 5: steps 12 and 13, k the output row)
+    auto loadF = [&](auto G, auto K) __attribute__((always_inline)) {
+        constexpr int g = decltype(G)::value, k = decltype(K)::value;
+        uint4 v;
+        if constexpr (g < 3) {
+            v = tile[baseA3 + 2 * (g + kHX * k)];
+        } else if constexpr (g == 3) {
+            v = tile[baseA1 + 2 * (kHX * k + 2 * PL)];
+        } else if constexpr (g == 4) {
+            v = tile[baseA2 + 2 * (2 + kHX * k + 2 * PL)];
+        } else {
+            v = tile[baseA0 + 2 * (2 + kHX * (k + 2) + 2 * PL)];
+            if (second) v = z4;
         }
+        F[g & 1][k] = __builtin_bit_cast(bf8, v);
+    };
+    // the reads step st needs that no earlier step made
+    auto loads = [&](auto Sx) __attribute__((always_inline)) {
+        constexpr int st = decltype(Sx)::value;
+        constexpr int g = st < 12 ? st / 3 : st - 8, j = st < 12 ? st % 3 : 0;
+        if constexpr (j == 0)
+            unroll<0, 4>([&](auto K) { loadF(std::integral_constant<int, g>{}, K); });
+        else
+            loadF(std::integral_constant<int, g>{}, std::integral_constant<int, j + 3>{});
 #pragma unroll
         for (int nt = 0; nt < NTA; ++nt) {
-            uint4 v = wl[baseB + 2 * (t * NCO + nt * 16)];
-            if (t + 1 >= 27 && second) v = z4;
-            b[buf][nt] = __builtin_bit_cast(bf8, v);
+            uint4 v = wl[baseB + 2 * (2 * st * NCO + nt * 16)];
+            if (st == 13 && second) v = z4;
+            W[st & 1][nt] = __builtin_bit_cast(bf8, v);
         }
     };
-    auto mfmas = [&](int buf) {
+    auto mfmas = [&](auto Sx) __attribute__((always_inline)) {
+        constexpr int st = decltype(Sx)::value;
+        constexpr int g = st < 12 ? st / 3 : st - 8, j = st < 12 ? st % 3 : 0;
 #pragma unroll
         for (int nt = 0; nt < NTA; ++nt)
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[buf][nt], a[buf][mt],
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[st & 1][nt], F[g & 1][mt + j],
                                                                        acc[mt][nt], 0, 0, 0);
     };
     if constexpr (PIPE) {
-        load(std::integral_constant<int, 0>{}, 0);
+        loads(std::integral_constant<int, 0>{});
         unroll<0, 14>([&](auto K) {
             constexpr int k = decltype(K)::value;
-            if constexpr (k + 1 < 14) load(std::integral_constant<int, 2 * (k + 1)>{}, (k + 1) & 1);
+            if constexpr (k + 1 < 14) loads(std::integral_constant<int, k + 1>{});
             __builtin_amdgcn_sched_barrier(0);
-            mfmas(k & 1);
+            mfmas(K);
             __builtin_amdgcn_sched_barrier(0);
         });
     } else {
         unroll<0, 14>([&](auto K) {
-            load(std::integral_constant<int, 2 * decltype(K)::value>{}, 0);
-            mfmas(0);
+            loads(K);
+            mfmas(K);
         });
     }
 }
@@ -417,7 +451,6 @@ conv3d_tiled_kernel(
     extern __shared__ uint4 lds[];
     uint4 *tile = lds, *wl = lds + HP * 2 + PXQ;
     uint2 *pxl = (uint2 *)(lds + HP * 2);  // point (x, y, z) at x + 16 (y + 4 z)
-    constexpr int S = FLIP ? -1 : 1;
     constexpr int NCO = 16 * NT;  // weight rows per tap in LDS
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, q = lane >> 4;
@@ -427,15 +460,13 @@ conv3d_tiled_kernel(
     const int cob = blockIdx.y * NCO;
     const int ntiles = NT == 1 ? 1 : min(NT, (cout - cob) >> 4);
     const int nco = ntiles * 16;
-    // halo index (uint4 units) of the lane's point in M tile 0 and its part
-    const int hb2 = 2 * ((r + 1) + kHX * (1 + kHY * (wave + 1))) + half;
-    // per step class of tap pairs: lane base of the A reads (see step_bias)
-    constexpr int D1 = pair_step(0), D2 = pair_step(2), D3 = pair_step(8);
-    static_assert(D1 == 1 && D2 == kHX - 2 && D3 == kHX * kHY - 2 * kHX - 2, "tap pair steps");
-    int baseA1 = hb2 + 2 * S * second * D1 - 2 * step_bias(D1, S);
-    int baseA2 = hb2 + 2 * S * second * D2 - 2 * step_bias(D2, S);
-    int baseA3 = hb2 + 2 * S * second * D3 - 2 * step_bias(D3, S);
-    int baseA0 = hb2 - 2 * step_bias(0, S);
+    // point bases (uint4 units) of the K steps' pair forms: halo point
+    // (r, 0, wave), part half, and the second tap one x, y or z further
+    const int c0 = 2 * (r + kHX * kHY * wave) + half;
+    int baseA0 = c0;
+    int baseA1 = c0 + 2 * second;
+    int baseA2 = c0 + 2 * second * kHX;
+    int baseA3 = c0 + 2 * second * kHX * kHY;
     int baseB = 2 * (second * NCO + r) + half;
     // this thread's halo pieces c = threadIdx.x + NTH k: point (packed) or -1
     int hp[NPF];
@@ -465,13 +496,13 @@ conv3d_tiled_kernel(
             for (int j = 0; j < NPF; ++j) pf[j] = halo_piece<POW2>(x, cin, G, ox, oy, oz, chunk * 16, hp[j], part);
         }
     };
-    // weight rows (t, o) of input chunk cc: w[t][cob + o][cc .. cc + 15]
+    // weight rows (slot sl, o) of input chunk cc: w[slot_tap(sl)][cob + o][cc .. cc + 15]
     const int ls = ntiles == 2 ? 5 : 4;
     auto stage_weights = [&](int cc, int off) {
         for (int c = threadIdx.x; c < 27 * nco * 2; c += NTH) {
-            const int row = c >> 1, t = row >> ls, o = row & (nco - 1);
-            wl[off + 2 * (t * NCO + o) + (c & 1)] =
-                *(const uint4 *)(w + (t * cout + cob + o) * cin + cc + 8 * (c & 1));
+            const int row = c >> 1, sl = row >> ls, o = row & (nco - 1);
+            wl[off + 2 * (sl * NCO + o) + (c & 1)] =
+                *(const uint4 *)(w + (slot_tap(sl, FLIP) * cout + cob + o) * cin + cc + 8 * (c & 1));
         }
     };
     // weights of every chunk resident (chunk c at c 27 NCO 2): staged once
@@ -485,8 +516,8 @@ conv3d_tiled_kernel(
             // a thread past the last piece loads the last piece again (an
             // unconditional load keeps pw in registers); it is not stored
             const int c = min((int)threadIdx.x + NTH * j, 27 * nco * 2 - 1);
-            const int row = c >> 1, t = row >> ls, o = row & (nco - 1);
-            pw[j] = *(const u4v *)(w + (t * cout + cob + o) * cin + cc + 8 * (c & 1));
+            const int row = c >> 1, sl = row >> ls, o = row & (nco - 1);
+            pw[j] = *(const u4v *)(w + (slot_tap(sl, FLIP) * cout + cob + o) * cin + cc + 8 * (c & 1));
         });
     };
     auto store_weights = [&]() __attribute__((always_inline)) {
@@ -494,8 +525,8 @@ conv3d_tiled_kernel(
             constexpr int j = decltype(J)::value;
             const int c = threadIdx.x + NTH * j;
             if (c < 27 * nco * 2) {
-                const int row = c >> 1, t = row >> ls, o = row & (nco - 1);
-                *(u4v *)&wl[2 * (t * NCO + o) + (c & 1)] = pw[j];
+                const int row = c >> 1, sl = row >> ls, o = row & (nco - 1);
+                *(u4v *)&wl[2 * (sl * NCO + o) + (c & 1)] = pw[j];
             }
         });
     };
@@ -538,11 +569,9 @@ conv3d_tiled_kernel(
                 asm volatile("" : "+v"(baseA0), "+v"(baseA1), "+v"(baseA2), "+v"(baseA3), "+v"(baseB));
             const int bB = wres ? baseB + chunk * WCH : baseB;
             if (NT == 1 || ntiles == NT)
-                conv_kloop<NT, NT, FLIP, NT == 1>(tile, wl, baseA0, baseA1, baseA2, baseA3, bB,
-                                                 second, acc);
+                conv_kloop<NT, NT, NT == 1>(tile, wl, baseA0, baseA1, baseA2, baseA3, bB, second, acc);
             else
-                conv_kloop<1, NT, FLIP, false>(tile, wl, baseA0, baseA1, baseA2, baseA3, bB,
-                                              second, acc);
+                conv_kloop<1, NT, false>(tile, wl, baseA0, baseA1, baseA2, baseA3, bB, second, acc);
         }
         // epilogue: lane (px, q) holds output channels 4q .. 4q + 3 of point
         // x0 + px of row mt of its plane, in register j of acc[mt][nt]
