@@ -413,12 +413,12 @@ __device__ __forceinline__ void conv_kloop(const uint4 *tile, const uint4 *wl, i
 // parent point, the others from x (cin - cc channels), so the concatenated
 // tensor is never written; the products and their order are those of the
 // convolution of the concatenated tensor.
-// With WPF (two output tiles, grids of fewer blocks than two per CU) the
-// next chunk's weights load into registers with its halo; those blocks run
-// at two wavefronts per SIMD, which costs nothing where there is at most one
-// block per CU. Otherwise each chunk stages its weights when it starts.
+// With WPF (grids of fewer blocks than two per CU) the next chunk's weights
+// load into registers with its halo; those blocks run at two or three
+// wavefronts per SIMD, which costs nothing where there are at most two
+// blocks per CU. Otherwise each chunk stages its weights when it starts.
 template <int NT, bool WPF>
-constexpr int conv_min_waves() { return NT == 1 ? 4 : (WPF ? 2 : 1); }
+constexpr int conv_min_waves() { return WPF ? 2 : (NT == 1 ? 4 : 1); }
 
 // With POOL the block also writes yp, the 2 x 2 x 2 average pooling of the
 // BF16 outputs it stores (a tile holds whole cells): the eight rounded
@@ -1917,19 +1917,33 @@ int conv_waves(int cin, int cout, int nx, int ny, int nz, int cus, bool pool) {
 
 // Launches conv3d_tiled_kernel; xc != NULL selects the concat form (cc
 // channels of the upsampled coarse tensor first, then cin - cc of x);
-// y_pool != NULL the pooled output as well (forward form, BF16 output; one
-// output tile only with eight wavefronts).
+// y_pool != NULL the pooled output as well (forward form, BF16 output; with
+// one output tile only on eight wavefronts or in the small-grid form).
 void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const void *w,
                        const float *bias, int cout, int nx, int ny, int nz, bool flip, int relu,
                        const void *mask, void *y_bf16, float *y_f32, void *y_pool, hipStream_t st) {
     const long P = (long)nx * ny * nz;
     // one N tile per block for 16 output channels (fewer registers), two otherwise
-    const int nt = cout <= 16 ? 1 : kNT, nb = 16 * nt;
-    const long ncb = (cout + nb - 1) / nb;
+    int nt = cout <= 16 ? 1 : kNT;
+    long ncb = (cout + 16 * nt - 1) / (16 * nt);
     const int cus = device_cus();
     const int nwv = conv_waves(cin, cout, nx, ny, nz, cus, y_pool != nullptr);
     const long tiles = P / (kTX * kTY * nwv);
-    const long nblk = std::max(1L, std::min(tiles, (long)conv_blocks(nt, cin / 16, cus, nwv) / ncb));
+    long nblk = std::max(1L, std::min(tiles, (long)conv_blocks(nt, cin / 16, cus, nwv) / ncb));
+    // grids of fewer two-tile blocks than two per CU (the 32^3 and 16^3
+    // levels, a block's one item sets the time): one output tile per block
+    // instead, with the next chunk's weights prefetched, so each block's
+    // chain of chunks runs half the MFMAs; as many blocks per output tile
+    // as the two-tile form (SUR_CONV_SPLITN=0 keeps two tiles; for
+    // comparisons only, both give the same bits)
+    const char *sn = std::getenv("SUR_CONV_SPLITN");
+    const bool splitn = nt == kNT && nwv == 4 && cin > 16 && cus > 0 && nblk * ncb < 2L * cus &&
+                        !(sn && *sn == '0');
+    if (splitn) {
+        nt = 1;
+        ncb = cout / 16;
+        nblk = std::max(1L, std::min(tiles, (long)conv_blocks(kNT, cin / 16, cus, nwv) / ncb));
+    }
     const dim3 grid((unsigned)nblk, (unsigned)ncb);
     // eight-wavefront blocks with a few input chunks keep every chunk's
     // weights in LDS (at most 80 KB a block keeps two blocks per CU), so no
@@ -1994,6 +2008,11 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
         } else {
             if (pow2) SUR_CONV_WV8(false, true, false, false); else SUR_CONV_WV8(false, false, false, false);
         }
+    } else if (splitn) {
+        if (pool1) SUR_CONV_POW2(1, false, false, true, true);
+        else if (xc) SUR_CONV_POW2(1, false, true, true, false);
+        else if (flip) SUR_CONV_POW2(1, true, false, true, false);
+        else SUR_CONV_POW2(1, false, false, true, false);
     } else if (xc) {
         if (nt == 1) SUR_CONV_POW2(1, false, true, false, false);
         else SUR_CONV_NT2(false, true, false);

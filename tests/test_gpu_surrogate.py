@@ -138,16 +138,23 @@ def test_conv_reading_the_concat_in_place(sur, cc, fc, cout, relu, grid):
     assert torch.equal(yf, yf2) and torch.equal(yb, yb2)
 
 
-@pytest.mark.parametrize("wpf", ["", "0"])
+# forms of the small grids' layers: one-tile blocks with the weights
+# prefetched (the default), two-tile blocks with and without the prefetch
+SMALL_FORMS = {"one-tile": {}, "two-tile": {"SUR_CONV_SPLITN": "0"},
+               "two-tile-staged": {"SUR_CONV_SPLITN": "0", "SUR_CONV_WPF": "0"}}
+
+
+@pytest.mark.parametrize("form", list(SMALL_FORMS))
 @pytest.mark.parametrize("grid", CAT_GRIDS + [(64, 16, 12)])
 @pytest.mark.parametrize("cin,cout", [(16, 16), (32, 32), (48, 48), (16, 64), (64, 16)])
-def test_conv_with_pooling_in_the_same_pass(sur, cin, cout, grid, wpf, monkeypatch):
+def test_conv_with_pooling_in_the_same_pass(sur, cin, cout, grid, form, monkeypatch):
     """sur_conv3d_pool = sur_conv3d then sur_pool2, bitwise, and the pooled
     output within BF16 rounding of the oracle's pool2 of the BF16 output;
-    with and without the weight prefetch of small grids (SUR_CONV_WPF)."""
+    in every form of the small grids' layers."""
     import torch
-    monkeypatch.setenv("SUR_CONV_WPF", wpf)
-    say(f"[sur] conv + pooling in one pass cin={cin} cout={cout} grid={grid} wpf={wpf!r}")
+    for k, v in SMALL_FORMS[form].items():
+        monkeypatch.setenv(k, v)
+    say(f"[sur] conv + pooling in one pass cin={cin} cout={cout} grid={grid} form={form}")
     rng = np.random.default_rng(cin * 7 + cout)
     nx, ny, nz = grid
     P = nx * ny * nz
@@ -168,6 +175,48 @@ def test_conv_with_pooling_in_the_same_pass(sur, cin, cout, grid, wpf, monkeypat
     ref = so.pool2(_from_bits(yb).reshape(nz, ny, nx, cout).astype(np.float64))
     got = _from_bits(yp).reshape(ref.shape)
     assert np.abs(got - ref).max() <= 2 ** -8 * (np.abs(ref).max() + 1e-30)
+
+
+@pytest.mark.parametrize("cin,cout,grid,flip", [(32, 48, (32, 32, 32), 0), (112, 48, (32, 32, 32), 0),
+                                                (48, 48, (32, 32, 32), 1), (64, 64, (16, 16, 16), 0),
+                                                (64, 48, (16, 16, 16), 1), (48, 32, (48, 16, 12), 1)])
+def test_conv_small_grid_forms_agree(sur, cin, cout, grid, flip, monkeypatch):
+    """The small grids' one-tile form gives the bits of the two-tile forms
+    (with and without the weight prefetch), forward and flipped with mask;
+    all within 1e-5 of the oracle's convolution."""
+    import torch
+    say(f"[sur] small-grid forms cin={cin} cout={cout} grid={grid} flip={flip}")
+    rng = np.random.default_rng(cin + 5 * cout + flip)
+    nx, ny, nz = grid
+    P = nx * ny * nz
+    x = so.bf16_round(rng.standard_normal((nz, ny, nx, cin)).astype(np.float32))
+    w = so.bf16_round((rng.standard_normal((27, cout, cin)) * 0.1).astype(np.float32))
+    b = rng.standard_normal(cout).astype(np.float32)
+    mask = so.bf16_round(np.maximum(rng.standard_normal((nz, ny, nx, cout)), 0).astype(np.float32))
+    wf = torch.empty((27, cout, cin), dtype=torch.int16, device="cuda")
+    sur.sur_pack_weights(_f32(w), cin, cout, wf, None)
+    xb, mb = _bits(x.reshape(-1, cin)), _bits(mask.reshape(-1, cout))
+    outs = {}
+    for form, env in SMALL_FORMS.items():
+        for k in ("SUR_CONV_SPLITN", "SUR_CONV_WPF"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        y = torch.empty((P, cout), dtype=torch.float32, device="cuda")
+        yb = torch.empty((P, cout), dtype=torch.int16, device="cuda")
+        sur.sur_conv3d(xb, cin, wf, None if flip else _f32(b), cout, grid, flip=flip,
+                       relu=0 if flip else 1, mask=mb if flip else None, y_bf16=yb, y_f32=y)
+        outs[form] = (y.cpu().numpy(), yb.cpu().numpy())
+    for form in SMALL_FORMS:
+        assert np.array_equal(outs[form][0], outs["one-tile"][0]), form
+        assert np.array_equal(outs[form][1], outs["one-tile"][1]), form
+    wt = w.astype(np.float64)
+    if flip:
+        ref = so.conv3d(x.astype(np.float64), wt, None, flip=True) * (mask > 0)
+    else:
+        ref = so.relu(so.conv3d(x.astype(np.float64), wt, b.astype(np.float64)))
+    got = outs["one-tile"][0].reshape(ref.shape)
+    assert np.abs(got - ref).max() <= 1e-5 * (1 + np.abs(ref).max())
 
 
 def test_conv_cat_rejects_grids_off_its_tile(sur):
