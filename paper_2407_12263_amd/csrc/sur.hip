@@ -1823,8 +1823,9 @@ int ilog2(int n) {
 // Persistent blocks of the tiled convolution (over all output-channel
 // blocks): eight per CU for one output tile and one input chunk (two rounds
 // of four resident blocks, so a block's next item overlaps another's
-// epilogue), otherwise as many as are resident at once (three per CU, LDS
-// bound), which keeps the last round of a grid from running a third full.
+// epilogue), otherwise as many as are resident at once (four per CU with
+// one output tile, register bound; three with two, LDS bound), which keeps
+// the last round of a grid from running a third full.
 // Blocks of eight wavefronts: as many as are resident at once (register
 // bound: two per CU with one output tile, one with two); a second round of
 // one-tile blocks measured slower at every chunk count.
@@ -1834,7 +1835,7 @@ int conv_blocks(int nt, int nchunk, int cus, int wv) {
     if (v && *v) return std::max(1, std::atoi(v));
     if (cus <= 0) return 2048;
     if (wv == 8) return (nt == 1 ? 2 : 1) * cus;
-    return (nt == 1 && nchunk == 1 ? 8 : 3) * cus;
+    return (nt == 1 ? (nchunk == 1 ? 8 : 4) : 3) * cus;
 }
 
 // The tiled weight gradient: lattice sizes multiples of the 16 x 4 x 4 tile,
