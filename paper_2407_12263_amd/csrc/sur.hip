@@ -440,11 +440,11 @@ conv3d_tiled_kernel(
     const float *__restrict__ bias, int cout, ConvGeom G, int relu,
     const uint16_t *__restrict__ mask, uint16_t *__restrict__ yb, float *__restrict__ yf,
     uint16_t *__restrict__ yp) {
-    static_assert(WV == 4 || (WV == 8 && (NT == 1 || (!POOL && !WPF))), "eight wavefronts");
+    static_assert(WV == 4 || (WV == 8 && (NT == 1 || !WPF)), "eight wavefronts");
     constexpr int NTH = 64 * WV, TZ = WV, HP = kHX * kHY * (TZ + 2);
     constexpr int NPF = (2 * HP + NTH - 1) / NTH;  // halo pieces per thread
-    constexpr bool POOL1 = POOL && NT == 1;          // pooling through LDS
-    constexpr int PXQ = POOL1 ? 16 * 4 * TZ * 2 : 0;  // its uint4: 32 B per point
+    constexpr bool POOL1 = POOL && (NT == 1 || WV == 8);  // pooling through LDS
+    constexpr int PXQ = POOL1 ? 16 * 4 * TZ * 2 * NT : 0;  // its uint4: 2 NCO B per point
     // LDS: the input halo (HP points x 16 channels), the pooling's values
     // and the chunk's weights (27 taps x 16 NT output channels x 16
     // channels), 32 B per row
@@ -610,7 +610,7 @@ conv3d_tiled_kernel(
                     const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(fl2{v[2], v[3]}, bf2));
                     *(uint2 *)(yb + o) = uint2{lo, hi};
                     if constexpr (POOL1) {
-                        pxl[((wave * 4 + mt) * 16 + r) * 4 + q] = uint2{lo, hi};
+                        pxl[((wave * 4 + mt) * 16 + r) * (NCO / 4) + nt * 4 + q] = uint2{lo, hi};
                     } else if constexpr (POOL) {
                         rv[nt][mt][0] = __uint_as_float(lo << 16);
                         rv[nt][mt][1] = __uint_as_float(lo & 0xffff0000u);
@@ -623,22 +623,29 @@ conv3d_tiled_kernel(
         }
         if constexpr (POOL1) {
             // thread: cell (cx, cy, cz) of the tile's 8 x 2 x (TZ / 2), channels
-            // 2 sub, 2 sub + 1; the eight values in the pooling pass's order
+            // 2 sub, 2 sub + 1 of each output tile; the eight values in the
+            // pooling pass's order
             __syncthreads();
-            const int cl = threadIdx.x >> 3, sub = threadIdx.x & 7;
+            const int cl = threadIdx.x >> 3;
             const int cx = cl & 7, cy = (cl >> 3) & 1, cz = cl >> 4;
             const uint32_t *pw32 = (const uint32_t *)pxl;
-            float s0 = 0.f, s1 = 0.f;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int pt = (2 * cx + (k & 1)) + 16 * ((2 * cy + ((k >> 1) & 1)) + 4 * (2 * cz + (k >> 2)));
-                const uint32_t v2 = pw32[pt * 8 + sub];
-                s0 += __uint_as_float(v2 << 16);
-                s1 += __uint_as_float(v2 & 0xffff0000u);
-            }
             const int X = (x0 >> 1) + cx, Y = (y0 >> 1) + cy, Z = (z0 >> 1) + cz;
-            const uint32_t qo = (uint32_t)(X + (G.nx >> 1) * (Y + (G.ny >> 1) * Z)) * (uint32_t)cout + cob + 2 * sub;
-            *(uint32_t *)(yp + qo) = (uint32_t)f2bf(0.125f * s0) | ((uint32_t)f2bf(0.125f * s1) << 16);
+            const uint32_t cell = (uint32_t)(X + (G.nx >> 1) * (Y + (G.ny >> 1) * Z)) * (uint32_t)cout + cob;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                if (nt >= ntiles) break;
+                const int sub = (threadIdx.x & 7) + 8 * nt;
+                float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int pt = (2 * cx + (k & 1)) + 16 * ((2 * cy + ((k >> 1) & 1)) + 4 * (2 * cz + (k >> 2)));
+                    const uint32_t v2 = pw32[pt * (NCO / 2) + sub];
+                    s0 += __uint_as_float(v2 << 16);
+                    s1 += __uint_as_float(v2 & 0xffff0000u);
+                }
+                *(uint32_t *)(yp + cell + 2 * sub) =
+                    (uint32_t)f2bf(0.125f * s0) | ((uint32_t)f2bf(0.125f * s1) << 16);
+            }
         } else if constexpr (POOL) {
             // cell (x0 + r, y0 + 2 pr, z0 + w) .. + 1 of the even lanes r and
             // wavefronts w; value i = dx + 2 dy of plane dz = w & 1, channel j
@@ -716,9 +723,9 @@ conv3d_tiled_kernel(
 
 // LDS bytes of conv3d_tiled_kernel with NT output tiles per block, wv
 // wavefronts, the weights of nw input chunks resident and (pool1) the
-// pooling of one output tile.
+// pooling through LDS.
 size_t conv_tiled_lds(int nt, int wv = 4, int nw = 1, bool pool1 = false) {
-    return (size_t)(kHX * kHY * (wv + 2) * 2 + (pool1 ? 16 * 4 * wv * 2 : 0) + 27 * 16 * nt * 2 * nw) *
+    return (size_t)(kHX * kHY * (wv + 2) * 2 + (pool1 ? 16 * 4 * wv * 2 * nt : 0) + 27 * 16 * nt * 2 * nw) *
            sizeof(uint4);
 }
 
@@ -1908,12 +1915,12 @@ int device_cus() {
 // tiles (one block per CU) where the tiles make whole rounds of the CUs
 // and at most four input chunks (whose weights then stay in LDS); else four
 // (SUR_CONV_WV=4 keeps four; for comparisons only, both give the same bits).
-int conv_waves(int cin, int cout, int nx, int ny, int nz, int cus, bool pool) {
+int conv_waves(int cin, int cout, int nx, int ny, int nz, int cus) {
     const char *v = std::getenv("SUR_CONV_WV");
     const long P = (long)nx * ny * nz, tiles = P / (kTX * kTY * 8);
     if ((v && *v == '4') || nz % 8 || cus <= 0) return 4;
     if (cout <= 16) return tiles >= 4L * cus ? 8 : 4;
-    return !pool && cin <= 64 && tiles >= cus && tiles % cus == 0 ? 8 : 4;
+    return cin <= 64 && tiles >= cus && tiles % cus == 0 ? 8 : 4;
 }
 
 // Launches conv3d_tiled_kernel; xc != NULL selects the concat form (cc
@@ -1928,7 +1935,7 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
     int nt = cout <= 16 ? 1 : kNT;
     long ncb = (cout + 16 * nt - 1) / (16 * nt);
     const int cus = device_cus();
-    const int nwv = conv_waves(cin, cout, nx, ny, nz, cus, y_pool != nullptr);
+    const int nwv = conv_waves(cin, cout, nx, ny, nz, cus);
     const long tiles = P / (kTX * kTY * nwv);
     long nblk = std::max(1L, std::min(tiles, (long)conv_blocks(nt, cin / 16, cus, nwv) / ncb));
     // grids of fewer two-tile blocks than two per CU (the 32^3 and 16^3
@@ -1952,7 +1959,7 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
     // only, both give the same bits)
     const char *wrv = std::getenv("SUR_CONV_WRES");
     const int nchunk = cin / 16;
-    const bool pool1 = y_pool && nt == 1;
+    const bool pool1 = y_pool && (nt == 1 || nwv == 8);
     const bool wres = nwv == 8 && nchunk > 1 && conv_tiled_lds(nt, nwv, nchunk, pool1) <= (nt == 1 ? 80 : 160) * 1024 &&
                       !(wrv && *wrv == '0');
     const size_t lds = conv_tiled_lds(nt, nwv, wres ? nchunk : 1, pool1);
@@ -1988,16 +1995,18 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
 #define SUR_CONV_WV8(FL, P2, CT, PL)                                                           \
     hipLaunchKernelGGL((conv3d_tiled_kernel<1, FL, P2, CT, false, PL, 8>), grid, dim3(512), lds, st, \
                        xb, cin, xcb, cc, wb, bias, cout, G, relu, mb, yb, y_f32, yp)
-#define SUR_CONV_WV8N2(FL, P2, CT)                                                             \
-    hipLaunchKernelGGL((conv3d_tiled_kernel<kNT, FL, P2, CT, false, false, 8>), grid, dim3(512), lds, st, \
+#define SUR_CONV_WV8N2(FL, P2, CT, PL)                                                         \
+    hipLaunchKernelGGL((conv3d_tiled_kernel<kNT, FL, P2, CT, false, PL, 8>), grid, dim3(512), lds, st, \
                        xb, cin, xcb, cc, wb, bias, cout, G, relu, mb, yb, y_f32, yp)
     if (nwv == 8 && nt == kNT) {
-        if (xc) {
-            if (pow2) SUR_CONV_WV8N2(false, true, true); else SUR_CONV_WV8N2(false, false, true);
+        if (pool1) {
+            if (pow2) SUR_CONV_WV8N2(false, true, false, true); else SUR_CONV_WV8N2(false, false, false, true);
+        } else if (xc) {
+            if (pow2) SUR_CONV_WV8N2(false, true, true, false); else SUR_CONV_WV8N2(false, false, true, false);
         } else if (flip) {
-            if (pow2) SUR_CONV_WV8N2(true, true, false); else SUR_CONV_WV8N2(true, false, false);
+            if (pow2) SUR_CONV_WV8N2(true, true, false, false); else SUR_CONV_WV8N2(true, false, false, false);
         } else {
-            if (pow2) SUR_CONV_WV8N2(false, true, false); else SUR_CONV_WV8N2(false, false, false);
+            if (pow2) SUR_CONV_WV8N2(false, true, false, false); else SUR_CONV_WV8N2(false, false, false, false);
         }
     } else if (nwv == 8) {
         if (pool1) {
@@ -2078,7 +2087,7 @@ int sur_conv3d_pool(const void *x, int32_t cin, const void *w, const float *bias
         !dims_ok(nx, ny, nz) || !conv_tiled_ok(x, cin, w, cout, nx, ny, nz) ||
         ((uintptr_t)y_bf16 & 7) != 0 || ((uintptr_t)y_pool & 7) != 0)
         return SUR_EINVAL;
-    if (cout <= 16 && conv_waves(cin, cout, nx, ny, nz, device_cus(), true) == 4) {
+    if (cout <= 16 && conv_waves(cin, cout, nx, ny, nz, device_cus()) == 4) {
         // one output tile on four wavefronts: pooling in the epilogue would
         // take LDS that a fourth block per CU needs, so pool after
         conv_tiled_launch(x, cin, nullptr, 0, w, bias, cout, nx, ny, nz, false, relu, nullptr,
