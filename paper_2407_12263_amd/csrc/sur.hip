@@ -536,6 +536,36 @@ conv3d_tiled_kernel(
     }
     if (nchunk == 1 || wres)  // the same for every item
         for (int c = 0; c < nchunk; ++c) stage_weights(c * 16, c * WCH);
+    // Loads in the epilogue would wait for the next item's halo, issued
+    // before them (loads complete in order): the bias is loaded once, and
+    // the data gradient's mask words before that halo (PREMASK; not in the
+    // four-wavefront one-tile form, whose 128 VGPRs have no room for them).
+    constexpr bool PREMASK = FLIP && (WV == 8 || NT > 1 || WPF);
+    float bvv[NT][4];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bvv[nt][j] = bias && nt < ntiles ? bias[cob + nt * 16 + 4 * q + j] : 0.f;
+    // output element of row mt of the lane's plane in the tile at (x0, y0, z0)
+    auto out_off = [&](int x0, int y0, int z0, int mt, int nt) -> uint32_t {
+        uint32_t p;
+        if constexpr (POW2)
+            p = (uint32_t)((x0 + r) | ((y0 + mt) << G.lx) | ((z0 + wave) << G.lxy));
+        else
+            p = (uint32_t)((x0 + r) + G.nx * ((y0 + mt) + G.ny * (z0 + wave)));
+        return p * (uint32_t)cout + (uint32_t)(cob + nt * 16 + 4 * q);
+    };
+    uint2 mrow[PREMASK ? NT : 1][4];
+    auto load_mask = [&](int k) {
+        int x0, y0, z0;
+        tile_origin<POW2, TZ>(G, (int)blockIdx.x + k * (int)gridDim.x, x0, y0, z0);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            if (nt >= ntiles) break;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) mrow[nt][mt] = *(const uint2 *)(mask + out_off(x0, y0, z0, mt, nt));
+        }
+    };
     f4 acc[4][NT];
     for (int k = 0; k < nmine; ++k) {
         for (int chunk = 0; chunk < nchunk; ++chunk) {
@@ -548,6 +578,8 @@ conv3d_tiled_kernel(
                 else stage_weights(chunk * 16, 0);
             }
             __syncthreads();
+            if constexpr (PREMASK)
+                if (mask && chunk + 1 == nchunk) load_mask(k);
             if (chunk + 1 < nchunk) {
                 load_halo(k, chunk + 1);
                 if (WPF) load_weights((chunk + 1) * 16);
@@ -581,25 +613,20 @@ conv3d_tiled_kernel(
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             if (nt >= ntiles) break;
-            const int co = cob + nt * 16 + 4 * q;
-            float bv[4] = {0.f, 0.f, 0.f, 0.f};
-            if (bias) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) bv[j] = bias[co + j];
-            }
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
-                const int p = grid_point<POW2>(G, x0 + r, y0 + mt, z0 + wave);
-                const uint32_t o = (uint32_t)p * (uint32_t)cout + co;
+                const uint32_t o = out_off(x0, y0, z0, mt, nt);
                 float v[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     v[j] = acc[mt][nt][j];
-                    if (bias) v[j] += bv[j];
+                    if (bias) v[j] += bvv[nt][j];
                     if (relu) v[j] = fmaxf(v[j], 0.f);
                 }
                 if (mask) {
-                    const uint2 m = *(const uint2 *)(mask + o);
+                    uint2 m;
+                    if constexpr (PREMASK) m = mrow[nt][mt];
+                    else m = *(const uint2 *)(mask + o);
                     const uint32_t mw[2] = {m.x, m.y};
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
