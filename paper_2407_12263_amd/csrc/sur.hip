@@ -610,44 +610,57 @@ conv3d_tiled_kernel(
         int x0, y0, z0;
         tile_origin<POW2, TZ>(G, (int)blockIdx.x + k * (int)gridDim.x, x0, y0, z0);
         float rv[POOL && !POOL1 ? NT : 1][4][4];  // the stored BF16 values, for the pooling
+        // the rows; MODE 1: bias, ReLU and BF16 output only (the forward's
+        // hidden layers), 2: bias and FP32 output only (its last layer), with
+        // no test of the other options per row; 0: any options
+        auto rows = [&](auto MODE) __attribute__((always_inline)) {
+            constexpr int MD = decltype(MODE)::value;
+            constexpr bool F = MD != 0;
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            if (nt >= ntiles) break;
+            for (int nt = 0; nt < NT; ++nt) {
+                if (nt >= ntiles) break;
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const uint32_t o = out_off(x0, y0, z0, mt, nt);
-                float v[4];
+                for (int mt = 0; mt < 4; ++mt) {
+                    const uint32_t o = out_off(x0, y0, z0, mt, nt);
+                    float v[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    v[j] = acc[mt][nt][j];
-                    if (bias) v[j] += bvv[nt][j];
-                    if (relu) v[j] = fmaxf(v[j], 0.f);
-                }
-                if (mask) {
-                    uint2 m;
-                    if constexpr (PREMASK) m = mrow[nt][mt];
-                    else m = *(const uint2 *)(mask + o);
-                    const uint32_t mw[2] = {m.x, m.y};
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (!(bf2f((uint16_t)(mw[j >> 1] >> (16 * (j & 1)))) > 0.f)) v[j] = 0.f;
-                }
-                if (yb) {
-                    const uint32_t lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(fl2{v[0], v[1]}, bf2));
-                    const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(fl2{v[2], v[3]}, bf2));
-                    *(uint2 *)(yb + o) = uint2{lo, hi};
-                    if constexpr (POOL1) {
-                        pxl[((wave * 4 + mt) * 16 + r) * (NCO / 4) + nt * 4 + q] = uint2{lo, hi};
-                    } else if constexpr (POOL) {
-                        rv[nt][mt][0] = __uint_as_float(lo << 16);
-                        rv[nt][mt][1] = __uint_as_float(lo & 0xffff0000u);
-                        rv[nt][mt][2] = __uint_as_float(hi << 16);
-                        rv[nt][mt][3] = __uint_as_float(hi & 0xffff0000u);
+                    for (int j = 0; j < 4; ++j) {
+                        v[j] = acc[mt][nt][j];
+                        if (F || bias) v[j] += bvv[nt][j];
+                        if (F ? MD == 1 : relu != 0) v[j] = fmaxf(v[j], 0.f);
                     }
+                    if (!F && mask) {
+                        uint2 m;
+                        if constexpr (PREMASK) m = mrow[nt][mt];
+                        else m = *(const uint2 *)(mask + o);
+                        const uint32_t mw[2] = {m.x, m.y};
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (!(bf2f((uint16_t)(mw[j >> 1] >> (16 * (j & 1)))) > 0.f)) v[j] = 0.f;
+                    }
+                    if (F ? MD == 1 : yb != nullptr) {
+                        const uint32_t lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(fl2{v[0], v[1]}, bf2));
+                        const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(fl2{v[2], v[3]}, bf2));
+                        *(uint2 *)(yb + o) = uint2{lo, hi};
+                        if constexpr (POOL1) {
+                            pxl[((wave * 4 + mt) * 16 + r) * (NCO / 4) + nt * 4 + q] = uint2{lo, hi};
+                        } else if constexpr (POOL) {
+                            rv[nt][mt][0] = __uint_as_float(lo << 16);
+                            rv[nt][mt][1] = __uint_as_float(lo & 0xffff0000u);
+                            rv[nt][mt][2] = __uint_as_float(hi << 16);
+                            rv[nt][mt][3] = __uint_as_float(hi & 0xffff0000u);
+                        }
+                    }
+                    if (F ? MD == 2 : yf != nullptr) *(f4 *)(yf + o) = f4{v[0], v[1], v[2], v[3]};
                 }
-                if (yf) *(f4 *)(yf + o) = f4{v[0], v[1], v[2], v[3]};
             }
-        }
+        };
+        if (bias && relu && !mask && yb && !yf)
+            rows(std::integral_constant<int, 1>{});
+        else if (bias && !relu && !mask && !yb && yf)
+            rows(std::integral_constant<int, 2>{});
+        else
+            rows(std::integral_constant<int, 0>{});
         if constexpr (POOL1) {
             // thread: cell (cx, cy, cz) of the tile's 8 x 2 x (TZ / 2), channels
             // 2 sub, 2 sub + 1 of each output tile; the eight values in the
