@@ -611,7 +611,8 @@ conv3d_tiled_kernel(
         tile_origin<POW2, TZ>(G, (int)blockIdx.x + k * (int)gridDim.x, x0, y0, z0);
         float rv[POOL && !POOL1 ? NT : 1][4][4];  // the stored BF16 values, for the pooling
         // the rows; MODE 1: bias, ReLU and BF16 output only (the forward's
-        // hidden layers), 2: bias and FP32 output only (its last layer), with
+        // hidden layers), 2: bias and FP32 output only (its last layer), 3
+        // and 4: mask and BF16 or FP32 output only (the data gradients), with
         // no test of the other options per row; 0: any options
         auto rows = [&](auto MODE) __attribute__((always_inline)) {
             constexpr int MD = decltype(MODE)::value;
@@ -626,10 +627,10 @@ conv3d_tiled_kernel(
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         v[j] = acc[mt][nt][j];
-                        if (F || bias) v[j] += bvv[nt][j];
+                        if (F ? MD <= 2 : bias != nullptr) v[j] += bvv[nt][j];
                         if (F ? MD == 1 : relu != 0) v[j] = fmaxf(v[j], 0.f);
                     }
-                    if (!F && mask) {
+                    if (F ? MD >= 3 : mask != nullptr) {
                         uint2 m;
                         if constexpr (PREMASK) m = mrow[nt][mt];
                         else m = *(const uint2 *)(mask + o);
@@ -638,7 +639,7 @@ conv3d_tiled_kernel(
                         for (int j = 0; j < 4; ++j)
                             if (!(bf2f((uint16_t)(mw[j >> 1] >> (16 * (j & 1)))) > 0.f)) v[j] = 0.f;
                     }
-                    if (F ? MD == 1 : yb != nullptr) {
+                    if (F ? (MD == 1 || MD == 3) : yb != nullptr) {
                         const uint32_t lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(fl2{v[0], v[1]}, bf2));
                         const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(fl2{v[2], v[3]}, bf2));
                         *(uint2 *)(yb + o) = uint2{lo, hi};
@@ -651,7 +652,7 @@ conv3d_tiled_kernel(
                             rv[nt][mt][3] = __uint_as_float(hi & 0xffff0000u);
                         }
                     }
-                    if (F ? MD == 2 : yf != nullptr) *(f4 *)(yf + o) = f4{v[0], v[1], v[2], v[3]};
+                    if (F ? (MD == 2 || MD == 4) : yf != nullptr) *(f4 *)(yf + o) = f4{v[0], v[1], v[2], v[3]};
                 }
             }
         };
@@ -659,6 +660,10 @@ conv3d_tiled_kernel(
             rows(std::integral_constant<int, 1>{});
         else if (bias && !relu && !mask && !yb && yf)
             rows(std::integral_constant<int, 2>{});
+        else if (PREMASK && !bias && !relu && mask && yb && !yf)
+            rows(std::integral_constant<int, 3>{});
+        else if (PREMASK && !bias && !relu && mask && !yb && yf)
+            rows(std::integral_constant<int, 4>{});
         else
             rows(std::integral_constant<int, 0>{});
         if constexpr (POOL1) {
