@@ -627,7 +627,7 @@ def surrogate_benchmark(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rma
                         test_seed: int = 1, horizon: int = 64, schedules=(7, 3, 1),
                         precision: str = "fp16", train_per_window: int = 9,
                         capacity: int = 300, lr: float = 3e-4, cycle: int = 8,
-                        log=print) -> dict:
+                        long_cycles=(16, 32), log=print) -> dict:
     """Emulsion workload: trains the U-Net on solver trajectories from
     ``train_seeds`` (``windows`` windows each) and runs the held-out
     ``test_seed`` for ``horizon`` windows with the plain solver and with each
@@ -637,7 +637,9 @@ def surrogate_benchmark(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rma
     without the network), the per-channel one-window prediction error on the
     held-out trajectory, and the error floor of the fine-grid reconstruction
     (an exact coarse change prolonged onto the fine grid) are reported
-    beside them."""
+    beside them. ``long_cycles`` adds one network window per cycle of that
+    many windows (fewer pushes onto the fine grid: lower error, less
+    speedup), with the network and the exact change."""
     import torch
     from . import inputs
     mk = lambda seed: inputs.emulsion(n=n, n_drops=n_drops, rmin=rmin, rmax=rmax, seed=seed)
@@ -706,23 +708,26 @@ def surrogate_benchmark(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rma
     zero = cp.new_state()
     exact = ExactChange(cp, hs, rscale, traj=hs.label[0][0])
     runs = {}
-    for ns in schedules:
-        for name, pred, lin in (("net", None, False), ("persistence", lambda s: zero, False),
-                                ("exact", exact, False)):
+    plan = [(ns, cycle, f"nsur{ns}", ("net", "persistence", "exact")) for ns in schedules]
+    plan += [(1, c, f"nsur1_cycle{c}", ("net", "exact")) for c in long_cycles]
+    preds = {"net": None, "persistence": lambda s: zero, "exact": exact}
+    for ns, cyc, tag, names_ in plan:
+        for name in names_:
+            pred, lin = preds[name], False
             solver.reset(*f0, 0)
-            st = accelerated_run(cp, net, rscale, horizon, nsur=ns, cycle=cycle,
-                                             limits=limits, predictor=pred, linear=lin,
-                                             judge_tol=0.5 if name != "persistence" else None)
+            st = accelerated_run(cp, net, rscale, horizon, nsur=ns, cycle=cyc, limits=limits,
+                                 predictor=pred, linear=lin,
+                                 judge_tol=0.5 if name != "persistence" else None)
             err = phi_error(solver, phi_ref)
             m = solver.diagnostics()["sum_phi"]
-            runs[f"nsur{ns}_{name}"] = dict(
+            runs[f"{tag}_{name}"] = dict(
                 seconds=st.seconds, speedup=t_plain / st.seconds, phi_l2_error=err,
                 mass_drift=(m - m_ref) / m_ref, surrogate_windows=st.sur_windows,
                 solver_windows=st.lbm_windows, fallbacks=st.fallbacks,
                 fallback_reasons=dict(st.fail_reasons), judged=st.judged,
                 judge_fail=st.judge_fail,
                 judge_err_mean=float(np.mean(st.judge_err)) if st.judge_err else None)
-            log(f"[surrogate] nsur={ns} {name}: {st.seconds * 1e3:.1f} ms, speedup "
+            log(f"[surrogate] {tag} {name}: {st.seconds * 1e3:.1f} ms, speedup "
                 f"{t_plain / st.seconds:.2f}, phi L2 error {err:.3e}, fallbacks {st.fallbacks}")
     out["runs"] = runs
 
