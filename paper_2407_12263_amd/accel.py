@@ -627,7 +627,7 @@ def surrogate_benchmark(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rma
                         test_seed: int = 1, horizon: int = 64, schedules=(7, 3, 1),
                         precision: str = "fp16", train_per_window: int = 9,
                         capacity: int = 300, lr: float = 3e-4, cycle: int = 8,
-                        long_cycles=(16, 32), log=print) -> dict:
+                        long_cycles=((1, 16), (1, 32), (2, 32), (3, 32)), log=print) -> dict:
     """Emulsion workload: trains the U-Net on solver trajectories from
     ``train_seeds`` (``windows`` windows each) and runs the held-out
     ``test_seed`` for ``horizon`` windows with the plain solver and with each
@@ -637,9 +637,9 @@ def surrogate_benchmark(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rma
     without the network), the per-channel one-window prediction error on the
     held-out trajectory, and the error floor of the fine-grid reconstruction
     (an exact coarse change prolonged onto the fine grid) are reported
-    beside them. ``long_cycles`` adds one network window per cycle of that
-    many windows (fewer pushes onto the fine grid: lower error, less
-    speedup), with the network and the exact change."""
+    beside them. ``long_cycles`` adds schedules of (network windows, cycle
+    length) with longer cycles (fewer pushes onto the fine grid: lower
+    error, less speedup), with the network and the exact change."""
     import torch
     from . import inputs
     mk = lambda seed: inputs.emulsion(n=n, n_drops=n_drops, rmin=rmin, rmax=rmax, seed=seed)
@@ -709,7 +709,7 @@ def surrogate_benchmark(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rma
     exact = ExactChange(cp, hs, rscale, traj=hs.label[0][0])
     runs = {}
     plan = [(ns, cycle, f"nsur{ns}", ("net", "persistence", "exact")) for ns in schedules]
-    plan += [(1, c, f"nsur1_cycle{c}", ("net", "exact")) for c in long_cycles]
+    plan += [(ns, c, f"nsur{ns}_cycle{c}", ("net", "exact")) for ns, c in long_cycles]
     preds = {"net": None, "persistence": lambda s: zero, "exact": exact}
     for ns, cyc, tag, names_ in plan:
         for name in names_:
