@@ -115,14 +115,16 @@ def test_conv_weight_gradient_full_size(sur, n, cin, cout):
     assert eb <= 1e-5 * (1 + np.abs(rdb).max()) * np.sqrt(P) / 64
 
 
-def test_conv_reading_the_concat_in_place_full_size_sampled(sur):
+@pytest.mark.parametrize("n,cc,fc,cout", [(128, 32, 16, 16), (64, 32, 32, 32)])
+def test_conv_reading_the_concat_in_place_full_size_sampled(sur, n, cc, fc, cout, monkeypatch):
     """The decoder's first 128^3 convolution (32 upsampled channels of the
-    64^3 level + 16 skip channels -> 16) reading its concat in place, on
-    4096 sampled points against the definition over the concatenated input."""
+    64^3 level + 16 skip channels -> 16) reading its concat in place, and a
+    64^3 one with two output tiles (both on eight-wavefront blocks), on 4096
+    sampled points against the definition over the concatenated input; the
+    output bits equal those of the four-wavefront form (SUR_CONV_WV=4)."""
     import torch
-    n, cc, fc, cout = 128, 32, 16, 16
     say(f"[sur-full] conv of the concat in place {n}^3 ({cc} up + {fc} skip) -> {cout}: 4096 points")
-    rng = np.random.default_rng(77)
+    rng = np.random.default_rng(77 + n + cout)
     xc = so.bf16_round(rng.standard_normal((n // 2, n // 2, n // 2, cc)).astype(np.float32))
     xf = so.bf16_round(rng.standard_normal((n, n, n, fc)).astype(np.float32))
     w = so.bf16_round((rng.standard_normal((27, cout, cc + fc)) * 0.1).astype(np.float32))
@@ -143,13 +145,20 @@ def test_conv_reading_the_concat_in_place_full_size_sampled(sur):
     e = np.abs(got - ref).max()
     say(f"   max|dy| {e:.2e} (scale {np.abs(ref).max():.2f})")
     assert e <= 1e-5 * (1 + np.abs(ref).max())
+    monkeypatch.setenv("SUR_CONV_WV", "4")
+    y4 = torch.empty_like(y)
+    sur.sur_conv3d_cat(_bits(xc.reshape(-1, cc)), cc, _bits(xf.reshape(-1, fc)), fc, wf, _f32(b),
+                       cout, (n, n, n), relu=1, y_f32=y4)
+    assert torch.equal(y, y4)
 
 
 @pytest.mark.parametrize("n,cin,cout", [(128, 16, 16), (64, 32, 32), (32, 48, 48)])
-def test_conv_with_pooling_full_size_sampled(sur, n, cin, cout):
+def test_conv_with_pooling_full_size_sampled(sur, n, cin, cout, monkeypatch):
     """The encoders' second convolutions with their pooling in one pass (the
-    128^3 level on eight-wavefront blocks, pooled through LDS; the 64^3 and
-    32^3 levels with two output tiles): the BF16 output on 4096 sampled points against
+    128^3 and 64^3 levels on eight-wavefront blocks, the 32^3 level on the
+    small grids' one-tile blocks, all pooled through LDS; the bits equal
+    those of the four-wavefront two-tile form, or of the two passes for 16
+    outputs): the BF16 output on 4096 sampled points against
     the definition, and the pooled output on 4096 sampled cells equal to the
     mean of the cell's eight stored BF16 values (summed x, y, z in FP32)."""
     import torch
@@ -181,6 +190,12 @@ def test_conv_with_pooling_full_size_sampled(sur, n, cin, cout):
     pbits = yp.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
     pv = pbits.view(np.float32).reshape(n // 2, n // 2, n // 2, cout)
     assert np.array_equal(pv[cells[:, 0], cells[:, 1], cells[:, 2]], want)
+    monkeypatch.setenv("SUR_CONV_WV", "4")
+    monkeypatch.setenv("SUR_CONV_SPLITN", "0")
+    yb4, yp4 = torch.empty_like(yb), torch.empty_like(yp)
+    sur.sur_conv3d_pool(_bits(x.reshape(-1, cin)), cin, wf, _f32(b), cout, (n, n, n), relu=1,
+                        y_bf16=yb4, y_pool=yp4)
+    assert torch.equal(yb, yb4) and torch.equal(yp, yp4)
 
 
 @pytest.mark.parametrize("grid,cin,cout,flip", [((96, 96, 64), 32, 16, 0), ((80, 96, 128), 16, 16, 1),
