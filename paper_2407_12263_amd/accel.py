@@ -627,7 +627,8 @@ def surrogate_benchmark(n: int = 256, n_drops: int = 200, rmin: float = 6.0, rma
                         test_seed: int = 1, horizon: int = 64, schedules=(7, 3, 1),
                         precision: str = "fp16", train_per_window: int = 9,
                         capacity: int = 300, lr: float = 3e-4, cycle: int = 8,
-                        long_cycles=((1, 16), (1, 32), (2, 32), (3, 32)), log=print) -> dict:
+                        long_cycles=((1, 16), (1, 32), (2, 32), (3, 32), (2, 64), (3, 64)),
+                        log=print) -> dict:
     """Emulsion workload: trains the U-Net on solver trajectories from
     ``train_seeds`` (``windows`` windows each) and runs the held-out
     ``test_seed`` for ``horizon`` windows with the plain solver and with each
