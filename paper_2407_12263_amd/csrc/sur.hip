@@ -395,19 +395,22 @@ __device__ __forceinline__ void conv_kloop(const uint4 *tile, const uint4 *wl, i
 // z0 + w of the tile: four rows of 16 points, the four M tiles; a block
 // computes NT 16-channel N tiles (one for 16 output channels, run at four
 // wavefronts per SIMD; two otherwise). The K steps use the 16x16x32 BF16
-// MFMA; one step covers two taps (lanes l / 16 = 0, 1: tap t, 2, 3: tap
-// t + 1) x 16 channels (8 per lane). A and B place the same (tap, channel)
-// in the same lane group and element, so the product does not depend on how
-// the hardware orders K within a step. The 14th step's second tap does not
-// exist and enters as zeros.
-// Addressing costs no vector instruction in the K loop: the flip is a
-// template parameter, every LDS read is a per-lane base (one per step class
-// of tap pairs, see step_bias) plus an immediate. The weights are the MFMA's
-// first operand and the points its second, so the result tile is output
+// MFMA; one step covers two taps (lanes l / 16 = 0, 1: its first, 2, 3: its
+// second, in the pairing of slot_tap) x 16 channels (8 per lane). A and B
+// place the same (tap, channel) in the same lane group and element, so the
+// product does not depend on how the hardware orders K within a step. The
+// 14th step's second tap does not exist and enters as zeros.
+// Addressing costs no vector instruction in the K loop: every LDS read is a
+// per-lane base (one per pair form) plus an immediate, and the flipped
+// convolution differs only in the taps its weight slots hold. The weights
+// are the MFMA's first operand and the points its second, so the result
+// tile is output
 // channel x point: lane (px, q) holds channels 4q .. 4q + 3 of point px, and
 // the lanes of one store instruction write 16 points x 16 channels of one
 // row (512 contiguous bytes when cout = 16) straight from the accumulators,
-// converted to BF16 by the hardware (round to nearest even).
+// converted to BF16 by the hardware (round to nearest even). The forward's
+// two kinds of layer and the data gradients take row code with their
+// options fixed; any other combination of options the general code.
 // With CAT the input is the decoder's concat [up2(xc), x] read in place: the
 // first cc / 16 chunks come from the coarse tensor xc (cc channels) at the
 // parent point, the others from x (cin - cc channels), so the concatenated
@@ -426,12 +429,14 @@ constexpr int conv_min_waves() { return WPF ? 2 : (NT == 1 ? 4 : 1); }
 // by 1/8 and rounded, as the pooling pass over the stored tensor does. The
 // x pair is in the neighbouring lane, the y pair in the lane's next row and
 // the z pair in the next wavefront, which hands its values over in LDS.
-// With one output tile (no registers to spare) every stored value goes
-// through LDS instead, and each thread sums one cell's channel pair.
-// WV = 8 (one output tile, large grids): blocks of eight wavefronts on
-// 16 x 4 x 8 point tiles, each wavefront as above on one plane; the halo
-// (18 x 6 x 10, 34.6 KB) is re-read 2.1 times instead of 2.5, and a block's
-// staging and barriers serve twice the points.
+// With one output tile (no registers to spare) or eight wavefronts every
+// stored value goes through LDS instead, and each thread sums one cell's
+// channel pair of each output tile.
+// WV = 8 (large grids): blocks of eight wavefronts on 16 x 4 x 8 point
+// tiles, each wavefront as above on one plane; the halo (18 x 6 x 10, 34.6
+// KB) is re-read 2.1 times instead of 2.5, and a block's staging and
+// barriers serve twice the points. With a few input chunks their weights
+// all stay in LDS (G.wres), staged once per kernel.
 template <int NT, bool FLIP, bool POW2, bool CAT, bool WPF, bool POOL, int WV = 4>
 __global__ void __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(conv_min_waves<NT, WPF>(), 8)))
 conv3d_tiled_kernel(
