@@ -972,6 +972,8 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
                     bsum += __uint_as_float(wd[e] << 16) + __uint_as_float(wd[e] & 0xffff0000u);
             }
         }
+        // wavefronts at their MFMAs go first (about 1% on the training step)
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll 1
         for (int st = 0; st < 8; ++st) {
             const int pl0 = 32 * st + 8 * q;  // the lane's first point of the step
@@ -1010,6 +1012,7 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
                 }
             }
         }
+        __builtin_amdgcn_s_setprio(0);
     }
     // D[m = 4 q + j][n = r] of tap t, M tile mt: dW[t][mt 16 + 4 q + j][cc + r];
     // accumulator u = 3 rr + d holds tap t = d + 3 (dy + 1) + 9 (dz + 1) of row
