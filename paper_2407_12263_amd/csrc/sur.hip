@@ -1970,14 +1970,15 @@ int device_cus() {
 // Wavefronts per block of conv3d_tiled_kernel: eight on 16 x 4 x 8 tiles
 // for one output tile and at least four such tiles per CU; for two output
 // tiles (one block per CU) where the tiles make whole rounds of the CUs
-// and at most four input chunks (whose weights then stay in LDS); else four
-// (SUR_CONV_WV=4 keeps four; for comparisons only, both give the same bits).
+// and at most eight input chunks (up to four keep their weights in LDS);
+// else four (SUR_CONV_WV=4 keeps four; for comparisons only, both give the
+// same bits).
 int conv_waves(int cin, int cout, int nx, int ny, int nz, int cus) {
     const char *v = std::getenv("SUR_CONV_WV");
     const long P = (long)nx * ny * nz, tiles = P / (kTX * kTY * 8);
     if ((v && *v == '4') || nz % 8 || cus <= 0) return 4;
     if (cout <= 16) return tiles >= 4L * cus ? 8 : 4;
-    return cin <= 64 && tiles >= cus && tiles % cus == 0 ? 8 : 4;
+    return cin <= 128 && tiles >= cus && tiles % cus == 0 ? 8 : 4;
 }
 
 // Launches conv3d_tiled_kernel; xc != NULL selects the concat form (cc

@@ -115,11 +115,12 @@ def test_conv_weight_gradient_full_size(sur, n, cin, cout):
     assert eb <= 1e-5 * (1 + np.abs(rdb).max()) * np.sqrt(P) / 64
 
 
-@pytest.mark.parametrize("n,cc,fc,cout", [(128, 32, 16, 16), (64, 32, 32, 32)])
+@pytest.mark.parametrize("n,cc,fc,cout", [(128, 32, 16, 16), (64, 32, 32, 32), (64, 48, 32, 32)])
 def test_conv_reading_the_concat_in_place_full_size_sampled(sur, n, cc, fc, cout, monkeypatch):
     """The decoder's first 128^3 convolution (32 upsampled channels of the
-    64^3 level + 16 skip channels -> 16) reading its concat in place, and a
-    64^3 one with two output tiles (both on eight-wavefront blocks), on 4096
+    64^3 level + 16 skip channels -> 16) reading its concat in place, and
+    64^3 ones with two output tiles (weights resident, or five chunks staged
+    per chunk; all on eight-wavefront blocks), on 4096
     sampled points against the definition over the concatenated input; the
     output bits equal those of the four-wavefront form (SUR_CONV_WV=4)."""
     import torch
