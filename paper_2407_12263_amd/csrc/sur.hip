@@ -246,16 +246,30 @@ struct ConvGeom {
     int lx, lxy;    // log2 nx, log2 (nx ny)
     int ltx, ltxy;  // log2 ntx, log2 (ntx nty)
     int wres;       // every input chunk's weights staged in LDS once per kernel
+    int lys;        // log2 of the tile rows of an XCD's slab, or -1 (x-fastest order)
 };
 
-// Origin of tile tl (x fastest over tiles) of TZ planes in z.
+// Origin of work item tl's tile of TZ planes in z. Work items are dealt to
+// the eight XCDs in turn (item tl on XCD tl % 8 when the grid's x size is a
+// multiple of 8). With G.lys >= 0 (power-of-two sizes, at least 8 tile rows)
+// XCD j takes the slab of tile rows j 2^lys .. (j + 1) 2^lys - 1 over all x
+// and z, item tl / 8 of it x fastest, then y, then z, so that the tiles an
+// XCD runs together are neighbours whose halos meet in its own L2; else the
+// tiles go x fastest, then y, then z. Either way a bijection of 0 .. T - 1.
 template <bool POW2, int TZ = kTZ>
 __device__ __forceinline__ void tile_origin(const ConvGeom &G, int tl, int &x0, int &y0, int &z0) {
     int bx, by, bz;
     if constexpr (POW2) {
-        bx = tl & (G.ntx - 1);
-        by = (tl >> G.ltx) & (G.nty - 1);
-        bz = tl >> G.ltxy;
+        if (G.lys >= 0) {
+            const int u = tl >> 3, r = u >> G.ltx;
+            bx = u & (G.ntx - 1);
+            by = ((tl & 7) << G.lys) | (r & ((1 << G.lys) - 1));
+            bz = r >> G.lys;
+        } else {
+            bx = tl & (G.ntx - 1);
+            by = (tl >> G.ltx) & (G.nty - 1);
+            bz = tl >> G.ltxy;
+        }
     } else {
         bx = tl % G.ntx;
         const int rest = tl / G.ntx;
@@ -873,9 +887,11 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const uint16_t *__restrict__
 
 // Weight gradient on the 16 x 4 x 4 point tiles of the forward kernel:
 // dW[t][o][i] = sum_p dY[p][o] X[p + d_t][i] as M = o, N = i, K = points
-// products on the 16x16x32 BF16 MFMA. A persistent block takes tiles
-// blockIdx.x, + gridDim.x, ... for the 16 input channels blockIdx.y; per tile
-// it stages in LDS the output gradient transposed, dYt[o][point], and the
+// products on the 16x16x32 BF16 MFMA. A persistent block takes work items
+// blockIdx.x, + gridDim.x, ... (tiles in the forward's XCD slabs where the
+// grid allows) for the 16 input channels blockIdx.y; the global reads of its
+// next tile are issued into registers before the current tile's MFMAs. Per
+// tile it stages in LDS the output gradient transposed, dYt[o][point], and the
 // input halo transposed, XhT[i][hz][hy][hx] (rows of 24, 16-byte aligned;
 // the planes of consecutive channels, and the rows dYt[o] of consecutive
 // output channels, start an odd multiple of 16 bytes apart modulo 256, so the
@@ -919,39 +935,86 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
     // channel t / 4 over the quarter t % 4 of each tile's points
     const bool do_bias = bpart != nullptr && blockIdx.y == 0 && threadIdx.x < MT * 64;
     float bsum = 0.f;
-    for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-        const int bx = tile % ntx, rest = tile / ntx;
-        const int by = rest % nty, bz = rest / nty;
-        const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
-        __syncthreads();  // the previous tile's reads are done
-        // input halo, channels cc .. cc + 15, transposed: a thread takes two
-        // neighbouring halo points (hx even) and 8 channels, and writes each
-        // channel's pair as one 4-byte word
-        for (int c = threadIdx.x; c < kHP; c += 256) {
-            const int h = (c >> 1) * 2, e0 = 8 * (c & 1);
-            const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
-            const int gy = wrap(y0 - 1 + hy, ny), gz = wrap(z0 - 1 + hz, nz);
-            const int g0 = wrap(x0 - 1 + hx, nx) + nx * (gy + ny * gz);
-            const int g1 = wrap(x0 + hx, nx) + nx * (gy + ny * gz);
-            const uint4 v0 = *(const uint4 *)(x + g0 * cin + cc + e0);
-            const uint4 v1 = *(const uint4 *)(x + g1 * cin + cc + e0);
-            const uint32_t w0[4] = {v0.x, v0.y, v0.z, v0.w}, w1[4] = {v1.x, v1.y, v1.z, v1.w};
-            uint32_t *dst = (uint32_t *)(xht + e0 * kCh + (hz * kHY + hy) * kRow + hx);
+    // the forward's XCD slabs of tile rows where the rows and the grid allow
+    // (tile % 8 is then the block's XCD for every input chunk, so the chunks
+    // of a tile and its neighbours read their halos through one L2)
+    const int nys = nty % 8 == 0 && gridDim.x % 8 == 0 ? nty / 8 : 0;
+    auto origin = [&](int tile, int &x0, int &y0, int &z0) {
+        int bx, by, bz;
+        if (nys) {
+            const int u = tile >> 3, rest = u / ntx;
+            bx = u - rest * ntx;
+            by = (tile & 7) * nys + rest % nys;
+            bz = rest / nys;
+        } else {
+            const int rest = tile / ntx;
+            bx = tile - rest * ntx;
+            by = rest % nty;
+            bz = rest / nty;
+        }
+        x0 = bx * kTX;
+        y0 = by * kTY;
+        z0 = bz * kTZ;
+    };
+    // a tile's global reads, held in registers from before the previous
+    // tile's MFMAs to its staging: input halo, a thread taking two
+    // neighbouring halo points (hx even) and 8 channels per piece; output
+    // gradient, two neighbouring points (pl even) and 8 channels per piece
+    constexpr int kXIt = (kHP + 255) / 256, kDIt = MT;
+    uint4 xv[kXIt][2], dv[kDIt][2];
+    auto fetch = [&](int tile) {
+        int x0, y0, z0;
+        origin(tile, x0, y0, z0);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const uint32_t a = (w0[e >> 1] >> (16 * (e & 1))) & 0xffffu;
-                const uint32_t b = (w1[e >> 1] >> (16 * (e & 1))) & 0xffffu;
-                dst[e * (kCh / 2)] = a | (b << 16);
+        for (int it = 0; it < kXIt; ++it) {
+            const int c = threadIdx.x + 256 * it;
+            if (c < kHP) {
+                const int h = (c >> 1) * 2, e0 = 8 * (c & 1);
+                const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
+                const int gy = wrap(y0 - 1 + hy, ny), gz = wrap(z0 - 1 + hz, nz);
+                const int g0 = wrap(x0 - 1 + hx, nx) + nx * (gy + ny * gz);
+                const int g1 = wrap(x0 + hx, nx) + nx * (gy + ny * gz);
+                xv[it][0] = *(const uint4 *)(x + g0 * cin + cc + e0);
+                xv[it][1] = *(const uint4 *)(x + g1 * cin + cc + e0);
             }
         }
-        // output gradient of the tile's points, transposed: two neighbouring
-        // points (pl even) per thread, one 4-byte word per channel
-        for (int c = threadIdx.x; c < 128 * MT * 2; c += 256) {
+#pragma unroll
+        for (int it = 0; it < kDIt; ++it) {
+            const int c = threadIdx.x + 256 * it;
             const int pl = (c / (MT * 2)) * 2, oc = c - (c / (MT * 2)) * (MT * 2);
             const int gp = (x0 + (pl & 15)) + nx * ((y0 + ((pl >> 4) & 3)) + ny * (z0 + (pl >> 6)));
-            const uint4 v0 = *(const uint4 *)(dy + gp * cout + 8 * oc);
-            const uint4 v1 = *(const uint4 *)(dy + (gp + 1) * cout + 8 * oc);
-            const uint32_t w0[4] = {v0.x, v0.y, v0.z, v0.w}, w1[4] = {v1.x, v1.y, v1.z, v1.w};
+            dv[it][0] = *(const uint4 *)(dy + gp * cout + 8 * oc);
+            dv[it][1] = *(const uint4 *)(dy + (gp + 1) * cout + 8 * oc);
+        }
+    };
+    if ((int)blockIdx.x < ntile) fetch(blockIdx.x);
+    for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        __syncthreads();  // the previous tile's reads are done
+        // both staged transposed, each channel's pair of points as one
+        // 4-byte word
+#pragma unroll
+        for (int it = 0; it < kXIt; ++it) {
+            const int c = threadIdx.x + 256 * it;
+            if (c < kHP) {
+                const int h = (c >> 1) * 2, e0 = 8 * (c & 1);
+                const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
+                const uint32_t w0[4] = {xv[it][0].x, xv[it][0].y, xv[it][0].z, xv[it][0].w};
+                const uint32_t w1[4] = {xv[it][1].x, xv[it][1].y, xv[it][1].z, xv[it][1].w};
+                uint32_t *dst = (uint32_t *)(xht + e0 * kCh + (hz * kHY + hy) * kRow + hx);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t a = (w0[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+                    const uint32_t b = (w1[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+                    dst[e * (kCh / 2)] = a | (b << 16);
+                }
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < kDIt; ++it) {
+            const int c = threadIdx.x + 256 * it;
+            const int pl = (c / (MT * 2)) * 2, oc = c - (c / (MT * 2)) * (MT * 2);
+            const uint32_t w0[4] = {dv[it][0].x, dv[it][0].y, dv[it][0].z, dv[it][0].w};
+            const uint32_t w1[4] = {dv[it][1].x, dv[it][1].y, dv[it][1].z, dv[it][1].w};
             uint32_t *dst = (uint32_t *)(dyt + (8 * oc) * kDy + pl);
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -961,6 +1024,8 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
             }
         }
         __syncthreads();
+        // the next tile's reads go out before this tile's MFMAs
+        if (tile + (int)gridDim.x < ntile) fetch(tile + (int)gridDim.x);
         if (do_bias) {
             const uint16_t *row = dyt + (threadIdx.x >> 2) * kDy + 64 * (threadIdx.x & 3);
 #pragma unroll
@@ -1911,10 +1976,12 @@ bool wgrad_tiled_ok(const void *x, int cin, const void *dy, int cout, int nx, in
 }
 
 // Persistent blocks of the tiled weight gradient per 16-channel input chunk:
-// about 1024 blocks in all, at most one per tile.
+// about 1024 blocks in all, at most one per tile, a multiple of 8 where
+// there are 8 or more (one run of blocks per XCD).
 long wgrad_tiled_blocks(int cin, long P) {
     const long tiles = P / (kTX * kTY * kTZ);
-    return std::max(1L, std::min(tiles, 1024L / (cin / 16)));
+    const long nb = std::max(1L, std::min(tiles, 1024L / (cin / 16)));
+    return nb >= 8 ? nb / 8 * 8 : nb;
 }
 
 
@@ -2021,13 +2088,17 @@ void conv_tiled_launch(const void *x, int cin, const void *xc, int cc, const voi
     const bool wres = nwv == 8 && nchunk > 1 && conv_tiled_lds(nt, nwv, nchunk, pool1) <= (nt == 1 ? 80 : 160) * 1024 &&
                       !(wrv && *wrv == '0');
     const size_t lds = conv_tiled_lds(nt, nwv, wres ? nchunk : 1, pool1);
-    ConvGeom G{nx, ny, nz, nx / kTX, ny / kTY, nz / nwv, 0, 0, 0, 0, wres ? 1 : 0};
+    ConvGeom G{nx, ny, nz, nx / kTX, ny / kTY, nz / nwv, 0, 0, 0, 0, wres ? 1 : 0, -1};
     const bool pow2 = pow2_ok(nx) && pow2_ok(ny) && pow2_ok(nz);
     if (pow2) {
         G.lx = ilog2(nx);
         G.lxy = ilog2(nx) + ilog2(ny);
         G.ltx = ilog2(G.ntx);
         G.ltxy = ilog2(G.ntx) + ilog2(G.nty);
+        // XCD slabs of tile rows (SUR_CONV_XCD=0 keeps the x-fastest order;
+        // for comparisons only, both give the same bits)
+        const char *xv = std::getenv("SUR_CONV_XCD");
+        if (G.nty >= 8 && nblk % 8 == 0 && !(xv && *xv == '0')) G.lys = ilog2(G.nty / 8);
     }
     const uint16_t *xb = (const uint16_t *)x, *xcb = (const uint16_t *)xc;
     const uint16_t *wb = (const uint16_t *)w, *mb = (const uint16_t *)mask;
