@@ -885,6 +885,76 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const uint16_t *__restrict__
     }
 }
 
+// Halves e of two 32-bit words as one word: the low halves (e = 0) or the
+// high halves (e = 1) of w0 and w1, w0's in the low half (one byte permute).
+__device__ __forceinline__ uint32_t pair_half(uint32_t w0, uint32_t w1, int e) {
+    return __builtin_amdgcn_perm(w1, w0, e ? 0x07060302u : 0x05040100u);
+}
+
+// Staged tiles of the tiled weight gradient: transposed input halo rows of
+// kWgRow elements, kWgCh elements per channel, and output-gradient rows of
+// kWgDy elements per channel.
+constexpr int kWgRow = 24;
+constexpr int kWgCh = kHZ * kHY * kWgRow + 8;
+constexpr int kWgDy = 256 + 8;
+
+// The eight K steps of one tile for wavefront wave with NR tap rows (dy, dz)
+// wave, wave + 4 (, wave + 8): arow and xlane are the lane's element offsets
+// in the staged output gradient and halo at step 0; step st takes the
+// tile's points 32 st .. 32 st + 31 (plane st / 2, rows 2 (st % 2) .. + 1),
+// a constant further on. Accumulator 3 rr + d takes the tap dx = d - 1 of
+// row rr. BIAS (a wavefront with two rows) also multiplies dY by ones into
+// accumulator 6, the bias gradient (each column holds the channel sums).
+template <int MT, int NR, bool BIAS>
+__device__ __forceinline__ void wgrad_steps(const uint16_t *__restrict__ dyt,
+                                            const uint16_t *__restrict__ xht, int arow, int xlane,
+                                            int wave, f4 (&acc)[9][MT]) {
+    static_assert(!BIAS || NR == 2, "the bias takes a free accumulator");
+    int xrow[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) {
+        const int rid = wave + 4 * rr, dyo = rid % 3 - 1, dz = rid / 3 - 1;
+        xrow[rr] = xlane + ((dz + 1) * kHY + dyo + 1) * kWgRow;
+    }
+    const bf8 ones = __builtin_bit_cast(bf8, uint4{0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u});
+#pragma unroll 1
+    for (int st = 0; st < 8; ++st) {
+        const int soff = ((st >> 1) * kHY + 2 * (st & 1)) * kWgRow;
+        bf8 a[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            a[mt] = __builtin_bit_cast(bf8, *(const uint4 *)(dyt + arow + mt * 16 * kWgDy + 32 * st));
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) {
+            // the three dx taps of a row start dx + 1 elements into the same
+            // two aligned 16-byte words
+            const uint16_t *row = xht + xrow[rr] + soff;
+            const uint4 w0 = *(const uint4 *)row;
+            const uint32_t w1x = *(const uint32_t *)(row + 8);
+            const uint4 bw[3] = {
+                w0,  // dx = -1
+                uint4{__builtin_amdgcn_alignbyte(w0.y, w0.x, 2),  // dx = 0: one element
+                      __builtin_amdgcn_alignbyte(w0.z, w0.y, 2),
+                      __builtin_amdgcn_alignbyte(w0.w, w0.z, 2),
+                      __builtin_amdgcn_alignbyte(w1x, w0.w, 2)},
+                uint4{w0.y, w0.z, w0.w, w1x}};  // dx = +1: two elements
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const bf8 b = __builtin_bit_cast(bf8, bw[d]);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[3 * rr + d][mt] =
+                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[3 * rr + d][mt], 0, 0, 0);
+            }
+        }
+        if constexpr (BIAS) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                acc[6][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], ones, acc[6][mt], 0, 0, 0);
+        }
+    }
+}
+
 // Weight gradient on the 16 x 4 x 4 point tiles of the forward kernel:
 // dW[t][o][i] = sum_p dY[p][o] X[p + d_t][i] as M = o, N = i, K = points
 // products on the 16x16x32 BF16 MFMA. A persistent block takes work items
@@ -905,17 +975,19 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const uint16_t *__restrict__
 // w, w + 4, w + 8 (9 or 6 taps: the three dx of a row share those two
 // words) and keeps their sums over all its tiles in registers; the block's
 // partial dW goes to part[block][t][o][i] and the partials are summed in
-// fixed order.
+// fixed order. One M tile keeps four wavefronts per SIMD (the LDS allows
+// four blocks per CU).
 template <int MT>
-__global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__restrict__ x, int cin,
-                                                          const uint16_t *__restrict__ dy, int cout,
-                                                          int nx, int ny, int nz,
-                                                          float *__restrict__ part,
-                                                          float *__restrict__ bpart) {
-    constexpr int kRow = 24;                    // hx row length in XhT
-    constexpr int kCh = kHZ * kHY * kRow + 8;   // XhT channel stride (1744 B)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT == 1 ? 4 : 1, 8)))
+wgrad_tiled_kernel(const uint16_t *__restrict__ x, int cin,
+                   const uint16_t *__restrict__ dy, int cout,
+                   int nx, int ny, int nz,
+                   float *__restrict__ part,
+                   float *__restrict__ bpart) {
+    constexpr int kRow = kWgRow;                // hx row length in XhT
+    constexpr int kCh = kWgCh;                  // XhT channel stride (1744 B)
     constexpr int kXh = 16 * kCh;               // XhT elements
-    constexpr int kDy = 256 + 8;                // dYt row stride (528 B)
+    constexpr int kDy = kWgDy;                  // dYt row stride (528 B)
     static_assert(kHX % 2 == 0 && kHP % 2 == 0 && kRow % 2 == 0 && kCh % 2 == 0 && kDy % 2 == 0,
                   "halo rows and strides hold whole pairs of points");
     constexpr int kNTap = 9;                    // taps per wavefront: 3 rows x 3 dx at most
@@ -931,10 +1003,11 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
     for (int u = 0; u < kNTap; ++u)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) acc[u][mt] = f4{0.f, 0.f, 0.f, 0.f};
-    // bias gradient (blocks of the first input chunk): thread t sums output
-    // channel t / 4 over the quarter t % 4 of each tile's points
-    const bool do_bias = bpart != nullptr && blockIdx.y == 0 && threadIdx.x < MT * 64;
-    float bsum = 0.f;
+    // bias gradient (blocks of the first input chunk): wavefront 3, which has
+    // two tap rows to wavefront 0's three, adds dY times ones on the MFMA
+    const bool do_bias = bpart != nullptr && blockIdx.y == 0;
+    // the lane's offsets in the staged dY and halo at the first K step
+    const int arow = r * kDy + 8 * q, xlane = r * kCh + (q >> 1) * kRow + 8 * (q & 1);
     // the forward's XCD slabs of tile rows where the rows and the grid allow
     // (tile % 8 is then the block's XCD for every input chunk, so the chunks
     // of a tile and its neighbours read their halos through one L2)
@@ -1002,11 +1075,7 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
                 const uint32_t w1[4] = {xv[it][1].x, xv[it][1].y, xv[it][1].z, xv[it][1].w};
                 uint32_t *dst = (uint32_t *)(xht + e0 * kCh + (hz * kHY + hy) * kRow + hx);
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const uint32_t a = (w0[e >> 1] >> (16 * (e & 1))) & 0xffffu;
-                    const uint32_t b = (w1[e >> 1] >> (16 * (e & 1))) & 0xffffu;
-                    dst[e * (kCh / 2)] = a | (b << 16);
-                }
+                for (int e = 0; e < 8; ++e) dst[e * (kCh / 2)] = pair_half(w0[e >> 1], w1[e >> 1], e & 1);
             }
         }
 #pragma unroll
@@ -1017,66 +1086,16 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
             const uint32_t w1[4] = {dv[it][1].x, dv[it][1].y, dv[it][1].z, dv[it][1].w};
             uint32_t *dst = (uint32_t *)(dyt + (8 * oc) * kDy + pl);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const uint32_t a = (w0[e >> 1] >> (16 * (e & 1))) & 0xffffu;
-                const uint32_t b = (w1[e >> 1] >> (16 * (e & 1))) & 0xffffu;
-                dst[e * (kDy / 2)] = a | (b << 16);
-            }
+            for (int e = 0; e < 8; ++e) dst[e * (kDy / 2)] = pair_half(w0[e >> 1], w1[e >> 1], e & 1);
         }
         __syncthreads();
         // the next tile's reads go out before this tile's MFMAs
         if (tile + (int)gridDim.x < ntile) fetch(tile + (int)gridDim.x);
-        if (do_bias) {
-            const uint16_t *row = dyt + (threadIdx.x >> 2) * kDy + 64 * (threadIdx.x & 3);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const uint4 v = *(const uint4 *)(row + 8 * k);
-                const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    bsum += __uint_as_float(wd[e] << 16) + __uint_as_float(wd[e] & 0xffff0000u);
-            }
-        }
         // wavefronts at their MFMAs go first (about 1% on the training step)
         __builtin_amdgcn_s_setprio(1);
-#pragma unroll 1
-        for (int st = 0; st < 8; ++st) {
-            const int pl0 = 32 * st + 8 * q;  // the lane's first point of the step
-            const int lx0 = pl0 & 15, ly = (pl0 >> 4) & 3, lz = pl0 >> 6;
-            bf8 a[MT];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                a[mt] = __builtin_bit_cast(bf8, *(const uint4 *)(dyt + (mt * 16 + r) * kDy + pl0));
-            // wavefront w takes the tap rows (dy, dz) w, w + 4, w + 8: the
-            // three dx taps of a row start dx + 1 elements into the same two
-            // aligned 16-byte words (lx0 is 0 or 8), read once per row
-#pragma unroll
-            for (int rr = 0; rr < 3; ++rr) {
-                const int rid = wave + 4 * rr;
-                if (rid < 9) {
-                    const int dyo = rid % 3 - 1, dz = rid / 3 - 1;
-                    const uint16_t *row =
-                        xht + r * kCh + ((lz + dz + 1) * kHY + ly + dyo + 1) * kRow + lx0;
-                    const uint4 w0 = *(const uint4 *)row;
-                    const uint4 w1 = *(const uint4 *)(row + 8);
-                    const uint4 bw[3] = {
-                        w0,  // dx = -1
-                        uint4{__builtin_amdgcn_alignbyte(w0.y, w0.x, 2),  // dx = 0: one element
-                              __builtin_amdgcn_alignbyte(w0.z, w0.y, 2),
-                              __builtin_amdgcn_alignbyte(w0.w, w0.z, 2),
-                              __builtin_amdgcn_alignbyte(w1.x, w0.w, 2)},
-                        uint4{w0.y, w0.z, w0.w, w1.x}};  // dx = +1: two elements
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        const bf8 b = __builtin_bit_cast(bf8, bw[d]);
-#pragma unroll
-                        for (int mt = 0; mt < MT; ++mt)
-                            acc[3 * rr + d][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                a[mt], b, acc[3 * rr + d][mt], 0, 0, 0);
-                    }
-                }
-            }
-        }
+        if (wave == 0) wgrad_steps<MT, 3, false>(dyt, xht, arow, xlane, 0, acc);
+        else if (wave < 3 || !do_bias) wgrad_steps<MT, 2, false>(dyt, xht, arow, xlane, wave, acc);
+        else wgrad_steps<MT, 2, true>(dyt, xht, arow, xlane, 3, acc);
         __builtin_amdgcn_s_setprio(0);
     }
     // D[m = 4 q + j][n = r] of tap t, M tile mt: dW[t][mt 16 + 4 q + j][cc + r];
@@ -1093,16 +1112,11 @@ __global__ void __launch_bounds__(256) wgrad_tiled_kernel(const uint16_t *__rest
             for (int j = 0; j < 4; ++j)
                 part[(((long)blockIdx.x * 27 + t) * cout + mt * 16 + 4 * q + j) * cin + cc + r] = acc[u][mt][j];
     }
-    if (bpart != nullptr && blockIdx.y == 0) {
-        // the four quarter sums of each channel, combined in order
-        __shared__ float bred[256];
-        __syncthreads();
-        bred[threadIdx.x] = do_bias ? bsum : 0.f;
-        __syncthreads();
-        if (threadIdx.x < MT * 16) {
-            const float* b4 = bred + 4 * threadIdx.x;
-            bpart[(long)blockIdx.x * cout + threadIdx.x] = ((b4[0] + b4[1]) + b4[2]) + b4[3];
-        }
+    if (do_bias && wave == 3 && r == 0) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bpart[(long)blockIdx.x * cout + mt * 16 + 4 * q + j] = acc[6][mt][j];
     }
 }
 
