@@ -1990,13 +1990,13 @@ bool wgrad_tiled_ok(const void *x, int cin, const void *dy, int cout, int nx, in
 }
 
 // Persistent blocks of the tiled weight gradient per 16-channel input chunk:
-// about 1024 blocks in all for one chunk and 512 for several (the chunk
+// about 768 blocks in all for one chunk and 512 for several (the chunk
 // blocks of a tile fetch the same halo lines; with fewer tiles in flight
 // per XCD those lines stay in its L2 across the blocks' drift), at most one
 // per tile, a multiple of 8 where there are 8 or more (one run per XCD).
 long wgrad_tiled_blocks(int cin, long P) {
     const long tiles = P / (kTX * kTY * kTZ);
-    const long nb = std::max(1L, std::min(tiles, (cin > 16 ? 512L : 1024L) / (cin / 16)));
+    const long nb = std::max(1L, std::min(tiles, (cin > 16 ? 512L : 768L) / (cin / 16)));
     return nb >= 8 ? nb / 8 * 8 : nb;
 }
 
