@@ -1033,7 +1033,21 @@ wgrad_tiled_kernel(const uint16_t *__restrict__ x, int cin,
     // tile's MFMAs to its staging: input halo, a thread taking two
     // neighbouring halo points (hx even) and 8 channels per piece; output
     // gradient, two neighbouring points (pl even) and 8 channels per piece
-    constexpr int kXIt = (kHP + 255) / 256, kDIt = MT;
+    // (lanes l and l + 32 of a wavefront take the two channel halves of one
+    // pair of points, so a half-wavefront's LDS stores of a channel fall on
+    // consecutive words within each halo row: a few bank conflicts where
+    // the rows wrap, where lanes l and l + 1 used to meet in every bank)
+    constexpr int kXPairs = kHP / 2, kXSlots = 2 * ((kXPairs + 31) / 32) * 32;
+    constexpr int kXIt = (kXSlots + 255) / 256, kDIt = MT;
+    auto xpiece = [](int c, int &h, int &e0) {
+        h = 2 * (((c >> 6) << 5) | (c & 31));
+        e0 = 8 * ((c >> 5) & 1);
+        return h < kHP;
+    };
+    auto dpiece = [](int c, int &pl, int &oc) {
+        pl = 2 * ((c / (64 * MT)) * 32 + (c & 31));
+        oc = (c >> 5) % (2 * MT);
+    };
     uint4 xv[kXIt][2], dv[kDIt][2];
     auto fetch = [&](int tile) {
         int x0, y0, z0;
@@ -1041,8 +1055,8 @@ wgrad_tiled_kernel(const uint16_t *__restrict__ x, int cin,
 #pragma unroll
         for (int it = 0; it < kXIt; ++it) {
             const int c = threadIdx.x + 256 * it;
-            if (c < kHP) {
-                const int h = (c >> 1) * 2, e0 = 8 * (c & 1);
+            int h, e0;
+            if (xpiece(c, h, e0)) {
                 const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
                 const int gy = wrap(y0 - 1 + hy, ny), gz = wrap(z0 - 1 + hz, nz);
                 const int g0 = wrap(x0 - 1 + hx, nx) + nx * (gy + ny * gz);
@@ -1054,7 +1068,8 @@ wgrad_tiled_kernel(const uint16_t *__restrict__ x, int cin,
 #pragma unroll
         for (int it = 0; it < kDIt; ++it) {
             const int c = threadIdx.x + 256 * it;
-            const int pl = (c / (MT * 2)) * 2, oc = c - (c / (MT * 2)) * (MT * 2);
+            int pl, oc;
+            dpiece(c, pl, oc);
             const int gp = (x0 + (pl & 15)) + nx * ((y0 + ((pl >> 4) & 3)) + ny * (z0 + (pl >> 6)));
             dv[it][0] = *(const uint4 *)(dy + gp * cout + 8 * oc);
             dv[it][1] = *(const uint4 *)(dy + (gp + 1) * cout + 8 * oc);
@@ -1068,8 +1083,8 @@ wgrad_tiled_kernel(const uint16_t *__restrict__ x, int cin,
 #pragma unroll
         for (int it = 0; it < kXIt; ++it) {
             const int c = threadIdx.x + 256 * it;
-            if (c < kHP) {
-                const int h = (c >> 1) * 2, e0 = 8 * (c & 1);
+            int h, e0;
+            if (xpiece(c, h, e0)) {
                 const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
                 const uint32_t w0[4] = {xv[it][0].x, xv[it][0].y, xv[it][0].z, xv[it][0].w};
                 const uint32_t w1[4] = {xv[it][1].x, xv[it][1].y, xv[it][1].z, xv[it][1].w};
@@ -1081,7 +1096,8 @@ wgrad_tiled_kernel(const uint16_t *__restrict__ x, int cin,
 #pragma unroll
         for (int it = 0; it < kDIt; ++it) {
             const int c = threadIdx.x + 256 * it;
-            const int pl = (c / (MT * 2)) * 2, oc = c - (c / (MT * 2)) * (MT * 2);
+            int pl, oc;
+            dpiece(c, pl, oc);
             const uint32_t w0[4] = {dv[it][0].x, dv[it][0].y, dv[it][0].z, dv[it][0].w};
             const uint32_t w1[4] = {dv[it][1].x, dv[it][1].y, dv[it][1].z, dv[it][1].w};
             uint32_t *dst = (uint32_t *)(dyt + (8 * oc) * kDy + pl);
