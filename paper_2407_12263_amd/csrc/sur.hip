@@ -1590,7 +1590,40 @@ __global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ pred
     __shared__ double red[4];
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     double l = 0.0;
-    if (p < P) {
+    if (vec4 == 2) {
+        // 16 stored channels: four lanes per point, lane j of a quad taking
+        // channels 4j .. 4j + 3, so a wavefront's 16-byte accesses cover 16
+        // consecutive points' rows; the block's 256 points in four rounds
+        // (the same arithmetic per channel as below)
+        const float inv = 1.0f / (float)((double)P * cu);
+        const int j = threadIdx.x & 3;
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const long pp = (long)blockIdx.x * blockDim.x + it * 64 + (threadIdx.x >> 2);
+            if (pp < P) {
+                float gg[4] = {0.f, 0.f, 0.f, 0.f};
+                if (4 * j < cu) {
+                    const float4 a = ((const float4 *)(pred + pp * 16))[j];
+                    const float4 b = ((const float4 *)(tgt + pp * 16))[j];
+                    const float pa[4] = {a.x, a.y, a.z, a.w}, tb[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int ch = 4 * j + k;
+                        if (ch < cu) {
+                            const float d = pa[k] - tb[k];
+                            l += (double)wch[ch] * d * d;
+                            gg[k] = 2.f * wch[ch] * d * inv;
+                        }
+                    }
+                }
+                if (grad) ((float4 *)(grad + pp * 16))[j] = float4{gg[0], gg[1], gg[2], gg[3]};
+                if (gradb)
+                    ((uint2 *)(gradb + pp * 16))[j] =
+                        uint2{uint32_t(f2bf(gg[0])) | (uint32_t(f2bf(gg[1])) << 16),
+                              uint32_t(f2bf(gg[2])) | (uint32_t(f2bf(gg[3])) << 16)};
+            }
+        }
+    } else if (p < P) {
         const float inv = 1.0f / (float)((double)P * cu);
         if (vec4) {
             // 16-byte accesses, four channels at a time (same arithmetic)
@@ -2558,8 +2591,11 @@ int sur_mse(const float *pred, const float *target, int32_t cu, int32_t cs, int6
         return SUR_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const long nb = grid1(P).x;
-    const int vec4 = cs % 4 == 0 && ((uintptr_t)pred & 15) == 0 && ((uintptr_t)target & 15) == 0 &&
-                     ((uintptr_t)grad & 15) == 0 && ((uintptr_t)grad_bf16 & 7) == 0;
+    // 1: 16-byte accesses per point; 2: the same for 16 stored channels,
+    // four lanes per point
+    int vec4 = cs % 4 == 0 && ((uintptr_t)pred & 15) == 0 && ((uintptr_t)target & 15) == 0 &&
+               ((uintptr_t)grad & 15) == 0 && ((uintptr_t)grad_bf16 & 7) == 0;
+    if (vec4 && cs == 16) vec4 = 2;
     hipLaunchKernelGGL(mse_kernel, dim3((unsigned)nb), dim3(256), 0, s, pred, target, cu, cs,
                        (long)P, wch, grad, (uint16_t *)grad_bf16, scratch, vec4);
     hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(1024), 0, s, (const double *)scratch, nb,
