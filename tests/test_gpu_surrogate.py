@@ -253,11 +253,14 @@ def test_unet_inference_forward_equals_training_forward(sur):
     assert torch.equal(a, b)
 
 
-# the first five grids are multiples of the 16 x 4 x 4 tile (the LDS-tiled
-# kernel, one to 24 tiles, every output-channel count), the rest are not
+# the first seven grids are multiples of the 16 x 4 x 4 tile (the LDS-tiled
+# kernel, one to 48 tiles, every output-channel count; the two with 8 tile
+# rows and a multiple of 8 blocks deal the tiles to the XCDs in slabs of
+# rows, one of them with 3 tiles in x), the rest are not
 @pytest.mark.parametrize("cin,cout,grid", [(16, 16, (16, 8, 12)), (112, 48, (32, 8, 8)),
                                            (48, 64, (16, 4, 4)), (80, 32, (16, 8, 4)),
-                                           (32, 16, (48, 4, 8)),
+                                           (32, 16, (48, 4, 8)), (16, 16, (48, 32, 8)),
+                                           (48, 16, (16, 64, 8)),
                                            (112, 48, (8, 8, 8)), (48, 64, (10, 6, 8)),
                                            (80, 32, (4, 4, 4))])
 def test_conv_weight_gradient(sur, cin, cout, grid):

@@ -199,6 +199,38 @@ def test_conv_with_pooling_full_size_sampled(sur, n, cin, cout, monkeypatch):
     assert torch.equal(yb, yb4) and torch.equal(yp, yp4)
 
 
+@pytest.mark.parametrize("grid,cin,cout,flip", [((128, 128, 128), 16, 16, 0), ((64, 64, 64), 32, 32, 1),
+                                                ((128, 64, 32), 48, 16, 0), ((64, 32, 64), 16, 48, 0)])
+def test_conv_xcd_slab_order_same_bits(sur, grid, cin, cout, flip, monkeypatch):
+    """On power-of-two grids with at least 8 tile rows the convolution deals
+    its tiles to the XCDs in slabs of tile rows; every output bit equals
+    that of the x-fastest order (SUR_CONV_XCD=0): both orders visit each
+    tile once."""
+    import torch
+    nx, ny, nz = grid
+    P = nx * ny * nz
+    say(f"[sur-full] conv tile order {grid} {cin}->{cout} flip={flip}")
+    rng = np.random.default_rng(nx + ny + nz + cin + cout + flip)
+    x = so.bf16_round(rng.standard_normal((P, cin)).astype(np.float32))
+    w = so.bf16_round((rng.standard_normal((27, cout, cin)) * 0.1).astype(np.float32))
+    b = rng.standard_normal(cout).astype(np.float32)
+    mask = so.bf16_round(np.maximum(rng.standard_normal((P, cout)), 0).astype(np.float32))
+    wf = torch.empty((27, cout, cin), dtype=torch.int16, device="cuda")
+    sur.sur_pack_weights(_f32(w), cin, cout, wf, None)
+    xb, mb = _bits(x), _bits(mask)
+    outs = []
+    for order in (None, "0"):
+        if order is not None:
+            monkeypatch.setenv("SUR_CONV_XCD", order)
+        y = torch.empty((P, cout), dtype=torch.float32, device="cuda")
+        yb = torch.empty((P, cout), dtype=torch.int16, device="cuda")
+        sur.sur_conv3d(xb, cin, wf, None if flip else _f32(b), cout, grid, flip=flip,
+                       relu=0 if flip else 1, mask=mb if flip else None, y_bf16=yb, y_f32=y)
+        torch.cuda.synchronize()
+        outs.append((y, yb))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
 @pytest.mark.parametrize("grid,cin,cout,flip", [((96, 96, 64), 32, 16, 0), ((80, 96, 128), 16, 16, 1),
                                                 ((128, 64, 128), 48, 16, 0), ((64, 64, 64), 32, 32, 0),
                                                 ((64, 64, 64), 64, 48, 1), ((128, 64, 64), 16, 32, 0)])
