@@ -1593,7 +1593,7 @@ __global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ pred
     if (vec4 == 2) {
         // 16 stored channels: four lanes per point, lane j of a quad taking
         // channels 4j .. 4j + 3, so a wavefront's 16-byte accesses cover 16
-        // consecutive points' rows; the block's 256 points in four rounds
+        // consecutive points' rows; the block's 256 points in four passes
         // (the same arithmetic per channel as below)
         const float inv = 1.0f / (float)((double)P * cu);
         const int j = threadIdx.x & 3;
